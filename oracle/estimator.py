@@ -1,0 +1,286 @@
+"""In-situ multipole 3PCF: kernel, fields and the three summation forms (float64).
+
+Conventions (cell units; the paper's passages in brackets):
+
+* grid: n^3 periodic nodes, cell a = box / n; density contrast delta on the
+  nodes [Sec. 3, periodic-box paragraph].
+* DFT: dhat(q) = sum_x delta_x exp(-2 pi i q.x / n), inverse with 1/n^3 and
+  the + sign, integer frequencies q_d in [-n/2, n/2), k = 2 pi q / box
+  [Sec. 2.1, Eq. trans-field-FT].
+* multipole window [Sec. 2.2, Eq. 3PCF-multipole-window, with the binning
+  window of the paragraph after Eq. nL-2fold]:
+      K_{lm,b}(q) = i^l jbar_{l,b}(|k|) conj(Y_lm(k_hat)),
+  set to zero on every Nyquist plane (any q_d = -n/2, which has no +n/2
+  partner); at q = 0 the direction is immaterial because jbar_{l>0}(0) = 0
+  and Y_00 is constant.
+* fields a_{lm,b} = ifftn(dhat K_{lm,b})  [Eq. SFC-3PCF-vertex].
+* nodal (grid) summation [Eqs. 3PCF-multipole-sum, SFC-3PCF with the
+  connection coefficients lumped onto the primary node]:
+      zeta_l[b1,b2] = (4 pi / n^3) sum_x delta_x sum_{m=-l}^{l} a_{lm,b1}(x) conj(a_{lm,b2}(x)).
+* grid-Gamma summation [Eqs. con-coeff, SFC-3PCF]:
+      zeta_l = (4 pi / n^3) sum_x delta_x sum_m sum_{s,t} Gamma_{s,t} a_{b1}(x+s) conj(a_{b2}(x+t)),
+  Gamma_{s,t} = prod_d gamma(s_d, t_d) from ``basis.gamma_1d``.
+* particle summation [Eq. DDD-sum-privertex and the particle sum at the end
+  of Sec. 2.2], primary vertex delta = n / nbar - 1 with n the catalogue:
+      zeta_l = 4 pi [ (1/W) sum_i w_i F_l(u_i) - Fbar_l ],
+      F_l(u) = sum_m atilde_{lm,b1}(u) conj(atilde_{lm,b2}(u)),
+  atilde the B3 interpolant of the field coefficients, Fbar_l the exact
+  volume mean of F_l (it carries the "-1" of the primary's contrast).
+
+The factor 4 pi is the product of the two sqrt(4 pi) of the paper's window;
+with it zeta(r1, r2, theta) = sum_l zeta_l P_l(cos theta) [Eq. triplet-counting].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import special, basis
+
+__all__ = ["Plan", "zeta_nodal", "zeta_gamma", "zeta_gamma_quadrature",
+           "zeta_particle", "fields", "volume_mean_pair"]
+
+FOUR_PI = 4.0 * np.pi
+
+
+class Plan:
+    """Grid, bins and the tabulated window functions for one configuration."""
+
+    def __init__(self, n: int, box: float, lmax: int, edges):
+        self.n = int(n)
+        self.box = float(box)
+        self.lmax = int(lmax)
+        self.edges = np.asarray(edges, dtype=np.float64)
+        self.nbins = self.edges.size - 1
+        q = np.fft.fftfreq(self.n, d=1.0 / self.n)                     # integers
+        self.q1 = q
+        qx, qy, qz = q[:, None, None], q[None, :, None], q[None, None, :]
+        q2 = (qx ** 2 + qy ** 2 + qz ** 2)
+        self.kf = 2.0 * np.pi / self.box
+        uniq, inv = np.unique(q2.ravel(), return_inverse=True)
+        self._q2_uniq = uniq
+        self._q2_inv = inv.reshape(q2.shape)
+        self.kmag_uniq = self.kf * np.sqrt(uniq)
+        half = -self.n // 2
+        self.nyquist = (qx == half) | (qy == half) | (qz == half)
+        qn = np.sqrt(q2)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            ct = np.where(qn > 0, qz / np.where(qn > 0, qn, 1.0), 1.0)
+        self.theta = np.arccos(np.clip(ct, -1.0, 1.0))
+        self.phi = np.arctan2(np.broadcast_to(qy, q2.shape), np.broadcast_to(qx, q2.shape))
+        self._jbar = {}
+
+    # -- window tables ---------------------------------------------------
+    def jbar_uniq(self, l: int) -> np.ndarray:
+        """jbar_{l,b} on the distinct |k| of the grid: [nbins, n_unique]."""
+        if l not in self._jbar:
+            self._jbar[l] = special.jbar(l, self.edges, self.kmag_uniq)
+        return self._jbar[l]
+
+    def jbar_grid(self, l: int, b: int) -> np.ndarray:
+        return self.jbar_uniq(l)[b][self._q2_inv]
+
+    def ylm_conj_grid(self, l: int, m: int) -> np.ndarray:
+        return np.conj(special.ylm(l, m, self.theta, self.phi))
+
+    def kernel(self, l: int, m: int, b: int, ylm_conj=None) -> np.ndarray:
+        """K_{lm,b}(q) on the full k-grid (complex128 [n, n, n])."""
+        yc = self.ylm_conj_grid(l, m) if ylm_conj is None else ylm_conj
+        k = (1j ** l) * self.jbar_grid(l, b) * yc
+        k[self.nyquist] = 0.0
+        return k
+
+    # -- helpers ----------------------------------------------------------
+    def ls(self, ls):
+        return list(range(self.lmax + 1)) if ls is None else [int(l) for l in ls]
+
+    def bins(self, bins):
+        return list(range(self.nbins)) if bins is None else [int(b) for b in bins]
+
+
+def fields(plan: Plan, dhat: np.ndarray, l: int, m: int, bins=None) -> np.ndarray:
+    """a_{lm,b}(x) = ifftn(dhat K_{lm,b}) for the requested bins: [nb, n, n, n] complex."""
+    yc = plan.ylm_conj_grid(l, m)
+    return np.stack([np.fft.ifftn(dhat * plan.kernel(l, m, b, yc)) for b in plan.bins(bins)])
+
+
+def _pair_sum(A: np.ndarray, weight: np.ndarray) -> np.ndarray:
+    """sum_x weight_x A_{b1}(x) conj(A_{b2}(x)) as an [nb, nb] complex matrix."""
+    nb = A.shape[0]
+    flat = A.reshape(nb, -1)
+    return (flat * weight.ravel()) @ flat.conj().T
+
+
+def zeta_nodal(plan: Plan, delta: np.ndarray, ls=None, bins=None) -> np.ndarray:
+    """Nodal grid summation; returns real zeta [len(ls), nb, nb].
+
+    The imaginary part, which cancels between m and -m, is checked to be at
+    rounding level before it is dropped.
+    """
+    delta = np.asarray(delta, dtype=np.float64)
+    dhat = np.fft.fftn(delta)
+    out = []
+    for l in plan.ls(ls):
+        z = 0.0
+        for m in range(-l, l + 1):
+            z = z + _pair_sum(fields(plan, dhat, l, m, bins), delta)
+        z = z * (FOUR_PI / plan.n ** 3)
+        _check_real(z)
+        out.append(z.real)
+    return np.array(out)
+
+
+def _check_real(z):
+    scale = max(np.abs(z).max(), 1e-300)
+    if np.abs(z.imag).max() > 1e-9 * scale:
+        raise AssertionError(f"zeta has an imaginary part {np.abs(z.imag).max():.3e} (scale {scale:.3e})")
+
+
+# ---------------------------------------------------------------------------
+# grid summation with connection coefficients
+# ---------------------------------------------------------------------------
+
+def _gamma_stencil_field(delta, gmat, shift):
+    """G_Delta(y) = sum_s delta(y - s) Gamma(s, s + Delta), Gamma = prod_d gamma (separable)."""
+    g = delta
+    for axis in range(3):
+        d = shift[axis]
+        acc = np.zeros_like(g)
+        for s in range(-3, 4):
+            t = s + d
+            if -3 <= t <= 3:
+                c = gmat[s + 3, t + 3]
+                if c != 0.0:
+                    acc = acc + c * np.roll(g, s, axis=axis)        # g(y - s)
+        g = acc
+    return g
+
+
+def zeta_gamma(plan: Plan, delta: np.ndarray, ls=None, bins=None) -> np.ndarray:
+    """Grid summation with the connection coefficients of B3 (Eq. SFC-3PCF).
+
+    The double sum over (s, t) is re-indexed by Delta = t - s:
+        sum_x delta_x sum_{s,t} Gamma(s,t) a(x+s) b*(x+t)
+      = sum_Delta sum_y G_Delta(y) a(y) b*(y + Delta),
+    with G_Delta(y) = sum_s delta(y - s) Gamma(s, s + Delta).
+    """
+    delta = np.asarray(delta, dtype=np.float64)
+    dhat = np.fft.fftn(delta)
+    gmat = basis.gamma_matrix()
+    shifts = [(dx, dy, dz) for dx in range(-3, 4) for dy in range(-3, 4) for dz in range(-3, 4)]
+    gfields = {sh: _gamma_stencil_field(delta, gmat, sh) for sh in shifts}
+    out = []
+    for l in plan.ls(ls):
+        z = 0.0
+        for m in range(-l, l + 1):
+            A = fields(plan, dhat, l, m, bins)
+            nb = A.shape[0]
+            flat = A.reshape(nb, -1)
+            for sh, G in gfields.items():
+                Bs = np.roll(A, shift=(-sh[0], -sh[1], -sh[2]), axis=(1, 2, 3)).reshape(nb, -1)
+                z = z + (flat * G.ravel()) @ Bs.conj().T
+        z = z * (FOUR_PI / plan.n ** 3)
+        _check_real(z)
+        out.append(z.real)
+    return np.array(out)
+
+
+def _node_interp_matrix(n: int, order: int = 5):
+    """Values of B3-interpolated data at Gauss-Legendre nodes of every cell (one axis).
+
+    Returns (M [order*n, n], weights [order*n]) with node j of cell c at
+    u = c + (xi_j + 1) / 2.
+    """
+    xi, wi = special.gauss_legendre(order)
+    u = (np.arange(n)[:, None] + 0.5 * (xi[None, :] + 1.0)).ravel()
+    M = np.zeros((u.size, n))
+    for l in range(n):
+        for wrap in (-n, 0, n):
+            M[:, l] += basis.b3(u - (l + wrap))
+    return M, np.tile(0.5 * wi, n)
+
+
+def zeta_gamma_quadrature(plan: Plan, delta: np.ndarray, ls=None, bins=None) -> np.ndarray:
+    """Grid-Gamma summation evaluated as the integral of three B3 interpolants.
+
+    sum_{x,s,t} delta_x Gamma(s,t) a(x+s) b*(x+t) = int delta_B(u) a_B(u) b_B*(u) d^3u,
+    with f_B(u) = sum_l f_l B3(u - l); the integrand is a degree-9 polynomial
+    per axis on each cell, which 5-point Gauss-Legendre integrates exactly.
+    """
+    n = plan.n
+    M, wq = _node_interp_matrix(n)
+
+    def interp(f):
+        g = np.tensordot(M, f, axes=(1, 0))                 # axis 0
+        g = np.tensordot(M, g, axes=(1, 1)).transpose(1, 0, 2)
+        g = np.tensordot(M, g, axes=(1, 2)).transpose(1, 2, 0)
+        return g
+
+    delta = np.asarray(delta, dtype=np.float64)
+    dhat = np.fft.fftn(delta)
+    W = wq[:, None, None] * wq[None, :, None] * wq[None, None, :]
+    wd = W * interp(delta)
+    out = []
+    for l in plan.ls(ls):
+        z = 0.0
+        for m in range(-l, l + 1):
+            A = fields(plan, dhat, l, m, bins)
+            At = np.stack([interp(a) for a in A])
+            z = z + _pair_sum(At, wd)
+        z = z * (FOUR_PI / n ** 3)
+        _check_real(z)
+        out.append(z.real)
+    return np.array(out)
+
+
+# ---------------------------------------------------------------------------
+# particle summation
+# ---------------------------------------------------------------------------
+
+def volume_mean_pair(plan: Plan, dhat: np.ndarray, l: int, bins=None) -> np.ndarray:
+    """Fbar_l[b1,b2] = (1/n^3) int sum_m atilde_{b1} conj(atilde_{b2}) d^3u.
+
+    By Parseval on the periodic interpolants (aliases folded into the
+    autocorrelation of B3) and the addition theorem
+    sum_m conj(Y_lm) Y_lm = (2l+1)/(4 pi):
+        Fbar_l = (2l+1) / (4 pi n^6) sum_q |dhat|^2 B7hat(q) jbar_{b1} jbar_{b2},
+    Nyquist planes excluded (the window vanishes there).
+    """
+    n = plan.n
+    th = 2.0 * np.pi * plan.q1 / n
+    b7 = basis.b7_hat(th)
+    b7g = b7[:, None, None] * b7[None, :, None] * b7[None, None, :]
+    p = np.abs(dhat) ** 2 * b7g
+    p[plan.nyquist] = 0.0
+    bl = plan.bins(bins)
+    J = np.stack([plan.jbar_grid(l, b).ravel() for b in bl])
+    return (2 * l + 1) / (FOUR_PI * float(n) ** 6) * ((J * p.ravel()) @ J.T)
+
+
+def zeta_particle(plan: Plan, pos, w, ls=None, bins=None, mode: str = "delta") -> np.ndarray:
+    """Particle summation over the catalogue (primary vertex on the particles).
+
+    mode "delta": secondaries from delta = n/nbar - 1 and primary n/nbar - 1
+                  (volume mean of F subtracted);
+    mode "ddd":   secondaries from n/nbar and primary n/nbar (plain triplet
+                  counting, the q = 0 mode kept, nothing subtracted).
+    """
+    n, box = plan.n, plan.box
+    w = np.ones(len(pos)) if w is None else np.asarray(w, dtype=np.float64)
+    W = w.sum()
+    eps = basis.deposit(pos, w, n, box)
+    rho = eps * (n ** 3 / W)
+    src = rho - 1.0 if mode == "delta" else rho
+    dhat = np.fft.fftn(src)
+    out = []
+    for l in plan.ls(ls):
+        z = 0.0
+        for m in range(-l, l + 1):
+            A = fields(plan, dhat, l, m, bins)
+            At = basis.gather(A, pos, n, box)                 # [nb, P]
+            z = z + (At * (w / W)) @ At.conj().T
+        _check_real(z)
+        z = z.real
+        if mode == "delta":
+            z = z - volume_mean_pair(plan, dhat, l, bins)
+        out.append(FOUR_PI * z)
+    return np.array(out)
