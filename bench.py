@@ -1,0 +1,198 @@
+"""Throughput of the in-situ multipole 3PCF path on one MI355X.
+
+One step = the whole path over one catalogue: deposit (B-spline scatter and
+contrast), forward DFT, the (l, m >= 0) loop of windowed inverse transforms
+with the nodal contraction (zeta_l for all l <= L and all bin pairs), and the
+hand-written adjoint (fields recomputed, adjoint transforms, gradient with
+respect to the grid and to every particle weight).
+
+Metric: zeta_l evaluations per second, one evaluation unit being one
+(grid cell, (l, m) with |m| <= l, radial bin): N^3 (L+1)^2 N_r units per step
+and mock, forward + adjoint.  Inputs are resident on the GPU before timing.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "zeta_l evals/s (N_g·(L+1)^2·Nr per s) fwd+adjoint, 256^3 L=10, vs FP64 form"
+HBM_PEAK_GBS = 8000.0
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic.txt")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def pass_bytes(name, n, nb, batch, real_bytes):
+    """Algorithmic HBM bytes of one launch of a pass (each element read or written once)."""
+    n3 = float(n) ** 3 * batch
+    c = 2 * real_bytes
+    return {
+        "filter_x": n3 * c + nb * n3 * c,                                  # dhat in, nb fields out
+        "y": 2.0 * nb * n3 * c,                                            # nb fields in and out
+        "z_nodal": nb * n3 * c + n3 * real_bytes,                          # nb fields + delta in
+        "z_adjoint": 2.0 * nb * n3 * c + n3 * real_bytes + 2 * n3 * real_bytes,  # fields in/out, delta, direct rmw
+        "adjoint_x": nb * n3 * c + 2.0 * n3 * c,                           # nb sources in, G rmw
+    }.get(name)
+
+
+def read_pmc(kernel_tag):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, if it matches the source."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2507_15209_amd", "csrc", "kernels.hip"), "rb").read()
+    src += open(os.path.join(ROOT, "paper_2507_15209_amd", "csrc", "fft_core.hpp"), "rb").read()
+    digest = hashlib.sha256(src).hexdigest()[:16]
+    for line in open(PMC_SUMMARY):
+        p = line.split()
+        if len(p) >= 4 and p[0] == "traffic" and p[1] == kernel_tag and p[2] == digest:
+            return float(p[3])
+    return None
+
+
+def cpu_baseline(wl, pos, w, nbins_sample=4, l_sample=0):
+    """The float64 oracle on a bounded sample of the same workload: the l = 0 multipole, first bins."""
+    from oracle import basis
+    from oracle import estimator as E
+    from oracle import adjoint as A
+    t0 = time.perf_counter()
+    eps = basis.deposit(pos, w, wl.n, wl.box)
+    delta = basis.density_contrast(eps, float(np.sum(w.astype(np.float64))))
+    plan = E.Plan(wl.n, wl.box, wl.lmax, wl.edges)
+    bins = list(range(nbins_sample))
+    lam = np.random.default_rng(7).standard_normal((1, nbins_sample, nbins_sample))
+    E.zeta_nodal(plan, delta, ls=[l_sample], bins=bins)
+    A.zeta_nodal_grad(plan, delta, lam, ls=[l_sample], bins=bins)
+    dt = time.perf_counter() - t0
+    units = float(wl.n) ** 3 * (2 * l_sample + 1) * nbins_sample
+    return {"value": units / dt, "unit": "zeta_l evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"deposit of the full catalogue + forward and gradient of zeta_{l_sample} over bins 0..{nbins_sample - 1} "
+                      f"({units:.3g} units in {dt:.1f} s, numpy float64, single-threaded FFTs)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="box2000_n256_l10")
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU path is a design "
+              "note only, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2507_15209_amd as mp3
+    from mockgen import WORKLOADS, workload_catalogue
+
+    wl = WORKLOADS[args.workload]
+    log("workload", wl.name, "n", wl.n, "L", wl.lmax, "bins", wl.nbins, "particles", wl.n_particles)
+    t0 = time.perf_counter()
+    pos, w = workload_catalogue(wl)
+    log(f"mock drawn in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    pt = torch.as_tensor(pos, device=dev)
+    wt = torch.as_tensor(w, device=dev)
+    lam = torch.as_tensor(np.random.default_rng(11).standard_normal((1, wl.lmax + 1, wl.nbins, wl.nbins)),
+                          device=dev)
+    units = float(wl.n) ** 3 * (wl.lmax + 1) ** 2 * wl.nbins
+
+    def run(precision, steps, warmup, profile):
+        t0 = time.perf_counter()
+        plan = mp3.Plan(wl.n, wl.box, wl.lmax, wl.edges, precision=precision, device=dev)
+        log(f"{precision} plan built in {time.perf_counter() - t0:.1f} s")
+
+        def step():
+            delta = plan.deposit(pt, wt)
+            plan.zeta(delta)
+            plan.zeta_backward(delta, lam, pt, wt)
+
+        for i in range(warmup):
+            step()
+            torch.cuda.synchronize()
+            log(f"{precision} warmup step {i + 1}/{warmup} done")
+        if profile:
+            plan.profile(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for i in range(steps):
+            step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        log(f"{precision}: {steps} steps in {dt:.3f} s")
+        prof = plan.profile_read() if profile else None
+        if profile:
+            plan.profile(False)
+        del plan
+        torch.cuda.empty_cache()
+        return dt / steps, prof
+
+    t_step, prof = run(args.precision, args.steps, args.warmup, True)
+    value = units / t_step
+    real_bytes = 4 if args.precision == "f32" else 8
+    passes = {k: v for k, v in prof.items() if v[1] > 0}
+    dom = max((k for k in passes if pass_bytes(k, wl.n, wl.nbins, 1, real_bytes) is not None),
+              key=lambda k: passes[k][0])
+    ms_tot, cnt = passes[dom]
+    avg_ms = ms_tot / cnt
+    abytes = pass_bytes(dom, wl.n, wl.nbins, 1, real_bytes)
+    achieved = abytes / (avg_ms * 1e-3) / 1e9
+    log("per-pass totals (ms, launches):", {k: (round(v[0], 2), v[1]) for k, v in passes.items()})
+    traffic = read_pmc(dom)
+
+    fp64 = None
+    if args.precision == "f32" and args.fp64_steps > 0:
+        t64, _ = run("f64", args.fp64_steps, 1, False)
+        fp64 = {"value": units / t64, "ms_per_step": t64 * 1e3, "ratio_f32_over_f64": t64 / t_step}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample")
+        cpu = cpu_baseline(wl, pos, w)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "zeta_l evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic seeded log-normal mock (stand-in for the N-body snapshot)",
+        "config": {"workload": wl.name, "form": "nodal grid summation, forward + adjoint incl. deposit and dJ/dw",
+                   "grid": wl.n, "box": wl.box, "lmax": wl.lmax, "nbins": wl.nbins,
+                   "n_particles": wl.n_particles, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": abytes},
+        "passes_ms": {k: {"total_ms": v[0] / args.steps, "launches": v[1] // args.steps} for k, v in passes.items()},
+        "fp64_form": fp64,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

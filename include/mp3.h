@@ -1,0 +1,180 @@
+/*
+ * mp3.h -- C ABI of the MI355X in-situ multipole 3PCF library.
+ *
+ * The library evaluates the multipole moments zeta_l(r1, r2) of the isotropic
+ * three-point correlation function of a periodic density field with the
+ * in-situ multipole algorithm of Ju, Feng, Huang, Sun & Zhu ("An Optimal
+ * In-Situ Multipole Algorithm for the Isotropic Three-Point Correlation
+ * Function"):
+ *
+ *   deposit      catalogue -> basis coefficients -> density contrast
+ *                (Sec. 2.1, multiresolution reconstruction; Sec. 3, workflow
+ *                step 2 and the periodic-box contrast delta = n/nbar - 1)
+ *   fields       a_{lm,b}(x) = IFFT[ FFT(delta) K_{lm,b} ],
+ *                K_{lm,b}(k) = i^l jbar_{l,b}(|k|) conj(Y_lm(k_hat))
+ *                (Sec. 2.2, Eqs. 3PCF-multipole-window and SFC-3PCF-vertex,
+ *                with the radial-bin window of the paragraph after Eq. nL-2fold)
+ *   zeta         zeta_l[b1,b2] = (4 pi / N^3) sum_x delta_x sum_{m=-l..l}
+ *                a_{lm,b1}(x) conj(a_{lm,b2}(x))   (Sec. 2.2,
+ *                Eqs. 3PCF-multipole-sum and SFC-3PCF, grid summation with
+ *                the connection coefficients lumped onto the primary node)
+ *   backward     gradient of J = sum_l <lambda_l, zeta_l> with respect to
+ *                the density grid and the particle weights (chain rule of
+ *                the above; the paper gives no gradient)
+ *
+ * Conventions shared by every entry point
+ *   - Grid: N^3 periodic nodes at x = l * a, a = box / N, row-major with the
+ *     x index slowest: element (ix, iy, iz) at (ix * N + iy) * N + iz.
+ *   - DFT: dhat(q) = sum_x delta_x exp(-2 pi i q.x / N); q_d in [-N/2, N/2)
+ *     stored at index q_d mod N; k = 2 pi q / box.  The window vanishes on
+ *     every Nyquist plane (any q_d = -N/2).
+ *   - Precision: a plan is MP3_F32 (fields, FFTs and filter in float32,
+ *     tables generated in float64, reductions in float64) or MP3_F64 (the
+ *     plain float64 form, same kernels).  "real" below means float for
+ *     MP3_F32 and double for MP3_F64; complex values are interleaved
+ *     (re, im) pairs of real.
+ *   - Bulk buffers are DEVICE pointers owned by the caller; the library never
+ *     frees caller memory and never allocates during a call.  It owns only
+ *     the plan (tables) allocated by mp3_plan_create.
+ *   - Every call is asynchronous on the given stream (a hipStream_t passed as
+ *     void*, NULL = default stream).  Argument errors are detected on the
+ *     host before any launch and return a negative status; a failed launch
+ *     returns MP3_EHIP.  mp3_last_error() gives a message for the last
+ *     failure of the calling thread.
+ *   - A plan may be used by one stream at a time.
+ */
+#ifndef MP3_H
+#define MP3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mp3_plan_s* mp3_plan_t;
+
+enum mp3_status {
+  MP3_OK = 0,
+  MP3_EINVAL = -1,        /* bad argument (NULL pointer, size, order, range)       */
+  MP3_ENOMEM = -2,        /* device or host allocation failed in mp3_plan_create   */
+  MP3_EHIP = -3,          /* a HIP runtime call or kernel launch failed            */
+  MP3_EUNSUPPORTED = -4,  /* valid request the library does not implement          */
+  MP3_EWORKSPACE = -5     /* workspace pointer NULL or smaller than required       */
+};
+
+enum mp3_precision { MP3_F32 = 0, MP3_F64 = 1 };
+
+enum mp3_summation {
+  MP3_SUM_NODAL = 0       /* grid summation on the nodes (connection coefficients
+                             lumped onto the primary node)                          */
+};
+
+typedef struct {
+  int32_t n;              /* grid points per side: 16, 32, 64, 128, 256 or 512       */
+  double box;             /* periodic box side (length units of the catalogue), > 0  */
+  int32_t lmax;           /* multipole truncation L, 0 <= L <= 20                    */
+  int32_t nbins;          /* radial bins Nr, 1 <= Nr <= 64                           */
+  const double* edges;    /* HOST array of nbins+1 strictly increasing edges >= 0,
+                             copied into the plan; bin b is [edges[b], edges[b+1])   */
+  int32_t precision;      /* enum mp3_precision                                     */
+  int32_t summation;      /* enum mp3_summation                                     */
+  int32_t batch;          /* mocks per call, >= 1                                   */
+} mp3_plan_desc;
+
+/* Build a plan: validates the description, generates the float64 tables (bin-
+ * averaged spherical Bessel functions on every |q|^2 of the grid, FFT twiddles)
+ * and uploads them.  *out is set only on success.  Blocking (host + device). */
+int mp3_plan_create(const mp3_plan_desc* desc, mp3_plan_t* out);
+
+/* Free a plan and its device tables.  NULL is accepted. */
+int mp3_plan_destroy(mp3_plan_t plan);
+
+/* Bytes of device workspace a call needs for catalogues of up to np_total
+ * particles in total over the batch (0 for field-level calls).  The same size
+ * serves every entry point.  The workspace is scratch: its content on entry is
+ * ignored and on exit undefined. */
+int mp3_workspace_size(mp3_plan_t plan, int64_t np_total, size_t* bytes);
+
+/* Deposit a batch of catalogues (Sec. 2.1, reconstruction on the basis; Sec. 3,
+ * density contrast):
+ *   eps_l = sum_i w_i prod_d B3(x_{i,d} N / box - l_d),  B3 the centred cubic
+ *   B-spline (support 4 cells per axis, periodic wrap),
+ *   delta_l = eps_l N^3 / W - 1,  W = sum_i w_i.
+ * pos     device float32 [np_total][3], positions in [0, box) (values outside
+ *         are wrapped periodically);
+ * w       device float32 [np_total] weights, or NULL for unit weights;
+ * np_off  HOST int64 [batch+1], strictly increasing prefix offsets with
+ *         np_off[0] = 0: mock j owns particles np_off[j] .. np_off[j+1]-1;
+ *         an empty mock (W = 0, contrast undefined) returns MP3_EINVAL;
+ * delta   device real [batch][N^3], written. */
+int mp3_deposit(mp3_plan_t plan, const float* pos, const float* w, const int64_t* np_off,
+                void* delta, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Fields of one multipole (Eq. SFC-3PCF-vertex with the binning window):
+ *   a_{lm,b} = ifftn( fftn(delta) K_{lm,b} ),  0 <= m <= l <= lmax
+ * (fields with m < 0 follow from a_{l,-m} = (-1)^m conj(a_{lm}) for real delta).
+ * delta  device real [batch][N^3];
+ * a_out  device complex [batch][nbins][N^3], written. */
+int mp3_multipole_fields(mp3_plan_t plan, const void* delta, int32_t l, int32_t m, void* a_out,
+                         void* workspace, size_t workspace_bytes, void* stream);
+
+/* Multipole moments by nodal grid summation (Eqs. 3PCF-multipole-sum, SFC-3PCF):
+ *   zeta_l[b1,b2] = (4 pi / N^3) sum_x delta_x sum_{m=-l}^{l} a_{lm,b1}(x) conj(a_{lm,b2}(x)),
+ * evaluated with m >= 0 only (m > 0 counted twice).  Real and symmetric.
+ * delta  device real [batch][N^3];
+ * zeta   device float64 [batch][lmax+1][nbins][nbins], overwritten. */
+int mp3_zeta(mp3_plan_t plan, const void* delta, double* zeta,
+             void* workspace, size_t workspace_bytes, void* stream);
+
+/* Gradient of J = sum_{j,l,b1,b2} dzeta[j][l][b1][b2] zeta_l^{(j)}[b1][b2].
+ * The fields are recomputed per (l, m); nothing is kept from mp3_zeta.
+ *   ddelta = dJ/ddelta                                          (device real [batch][N^3])
+ *   dw     = dJ/dw_i through delta = eps N^3 / W - 1 of mp3_deposit, i.e.
+ *            (N^3/W) [ sum_l B_i(l) g_l - N^-3 sum_l (1 + delta_l) g_l ], g = ddelta
+ *            (device real [np_total]); needs pos, w, np_off as given to mp3_deposit.
+ * ddelta must not be NULL.  dw may be NULL (then pos, w, np_off are ignored).
+ * dzeta  device float64 [batch][lmax+1][nbins][nbins]. */
+int mp3_zeta_backward(mp3_plan_t plan, const void* delta, const double* dzeta,
+                      void* ddelta, const float* pos, const float* w, const int64_t* np_off,
+                      void* dw, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Pass identifiers for per-pass timing. */
+enum mp3_pass {
+  MP3_PASS_DFT = 0,        /* forward 3-D DFT of delta; final DFT of the adjoint accumulator */
+  MP3_PASS_FILTER_X = 1,   /* window K_{lm,b} + x-transform, all bins (one launch per (l, m)) */
+  MP3_PASS_Y = 2,          /* y-transform of all bins                                          */
+  MP3_PASS_Z_NODAL = 3,    /* z-transform + nodal contraction                                  */
+  MP3_PASS_Z_ADJOINT = 4,  /* z-transform + adjoint sources + their z-transform                */
+  MP3_PASS_ADJOINT_X = 5,  /* x-transform of the adjoint sources, window, bin sum into G       */
+  MP3_PASS_DEPOSIT = 6,    /* B-spline scatter of the catalogue                                */
+  MP3_NPASS = 7
+};
+
+/* Per-pass timing for measurement: with enable != 0 every pass launch of
+ * later calls on this plan is bracketed by two HIP events on the call's
+ * stream.  Calling it resets the totals.  Diagnostic only; adds two event
+ * records per launch. */
+int mp3_profile(mp3_plan_t plan, int enable);
+
+/* Total milliseconds and number of launches of one pass since the last
+ * mp3_profile call.  Waits for the recorded events (synchronises the
+ * stream up to the last profiled launch). */
+int mp3_profile_read(mp3_plan_t plan, int pass, double* total_ms, int64_t* launches);
+
+/* Read back the plan's parameters (any out pointer may be NULL). */
+int mp3_plan_info(mp3_plan_t plan, int32_t* n, int32_t* lmax, int32_t* nbins,
+                  int32_t* precision, int32_t* batch);
+
+/* Human-readable name of a status code (static storage). */
+const char* mp3_status_string(int status);
+
+/* Message describing the last failure on the calling thread (thread-local,
+ * valid until the next library call on that thread). */
+const char* mp3_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MP3_H */

@@ -35,24 +35,29 @@ def zeta_nodal_objective(plan: Plan, delta, lam) -> float:
     return float(np.sum(np.asarray(lam) * zeta_nodal(plan, delta)))
 
 
-def zeta_nodal_grad(plan: Plan, delta, lam) -> np.ndarray:
-    """dJ/ddelta for the nodal form; lam has shape [lmax+1, nbins, nbins]."""
+def zeta_nodal_grad(plan: Plan, delta, lam, ls=None, bins=None) -> np.ndarray:
+    """dJ/ddelta for the nodal form.
+
+    lam has shape [lmax+1, nbins, nbins]; with ``ls`` / ``bins`` only those
+    multipoles and bins enter J (lam then indexed [len(ls), len(bins), len(bins)]).
+    """
     delta = np.asarray(delta, dtype=np.float64)
     lam = np.asarray(lam, dtype=np.float64)
     n = plan.n
     dhat = np.fft.fftn(delta)
     direct = np.zeros_like(delta)
     acc = np.zeros(delta.shape, dtype=np.complex128)
-    for l in range(plan.lmax + 1):
-        lam_l = lam[l]
+    bl = plan.bins(bins)
+    for li, l in enumerate(plan.ls(ls)):
+        lam_l = lam[li]
         lam_s = 0.5 * (lam_l + lam_l.T)
         for m in range(-l, l + 1):
-            A = fields(plan, dhat, l, m)                          # [nb, n, n, n]
+            A = fields(plan, dhat, l, m, bl)                      # [nb, n, n, n]
             direct += np.einsum("ij,ixyz,jxyz->xyz", lam_l, A, A.conj()).real
             C = delta[None] * np.einsum("ij,jxyz->ixyz", lam_s, A.conj())
             yc = plan.ylm_conj_grid(l, m)
-            for b in range(plan.nbins):
-                acc += plan.kernel(l, m, b, yc) * np.fft.ifftn(C[b])
+            for bi, b in enumerate(bl):
+                acc += plan.kernel(l, m, b, yc) * np.fft.ifftn(C[bi])
     grad = direct + 2.0 * np.fft.fftn(acc).real
     return grad * (FOUR_PI / n ** 3)
 

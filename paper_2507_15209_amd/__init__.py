@@ -1,0 +1,206 @@
+"""MI355X in-situ multipole 3PCF: Python binding of the HIP library.
+
+Every step of the estimator runs in the gfx950 kernels of ``libmp3.so``; this
+module only marshals torch device tensors (memory and the current stream) into
+the C ABI of ``include/mp3.h``.  There is no CPU fallback: without the built
+library or without a GPU the calls raise.
+
+    plan = Plan(n=256, box=2000.0, lmax=10, edges=np.linspace(20, 200, 21))
+    delta = plan.deposit(pos, w)                # [batch, n, n, n]
+    zeta = plan.zeta(delta)                     # [batch, lmax+1, nbins, nbins] float64
+    ddelta, dw = plan.zeta_backward(delta, dzeta, pos, w)
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+
+__all__ = ["Plan", "Zeta3PCF", "zeta_from_catalogue", "Mp3Error"]
+
+Mp3Error = _lib.Mp3Error
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Plan:
+    """A configuration of the estimator: grid, box, multipole order, radial bins.
+
+    precision "f32": fields, FFTs and window in float32 (tables generated in
+    float64, reductions in float64); "f64": the plain float64 form.
+    """
+
+    def __init__(self, n: int, box: float, lmax: int, edges, precision: str = "f32", batch: int = 1,
+                 device=None):
+        self.lib = _lib.load()
+        self.n, self.box, self.lmax, self.batch = int(n), float(box), int(lmax), int(batch)
+        self.edges = np.ascontiguousarray(edges, dtype=np.float64)
+        self.nbins = self.edges.size - 1
+        if precision not in ("f32", "f64"):
+            raise ValueError("precision must be 'f32' or 'f64'")
+        self.precision = precision
+        self.real_dtype = torch.float32 if precision == "f32" else torch.float64
+        self.complex_dtype = torch.complex64 if precision == "f32" else torch.complex128
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        desc = _lib.PlanDesc(self.n, self.box, self.lmax, self.nbins,
+                             self.edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             _lib.MP3_F32 if precision == "f32" else _lib.MP3_F64,
+                             _lib.MP3_SUM_NODAL, self.batch)
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(self.lib.mp3_plan_create(ctypes.byref(desc), ctypes.byref(handle)), "mp3_plan_create")
+        self._h = handle
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self.lib.mp3_plan_destroy(h)
+            self._h = None
+
+    # -- workspace -------------------------------------------------------
+    def workspace_bytes(self, np_total: int = 0) -> int:
+        out = ctypes.c_size_t()
+        _lib.check(self.lib.mp3_workspace_size(self._h, int(np_total), ctypes.byref(out)), "mp3_workspace_size")
+        return out.value
+
+    def _workspace(self, np_total: int = 0):
+        need = self.workspace_bytes(np_total)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def _offsets(self, np_off, np_total):
+        if np_off is None:
+            if self.batch != 1:
+                raise ValueError("np_off is required when batch > 1")
+            np_off = [0, np_total]
+        off = np.ascontiguousarray(np_off, dtype=np.int64)
+        if off.size != self.batch + 1:
+            raise ValueError("np_off must have batch + 1 entries")
+        return off
+
+    def _real(self, x, name):
+        if x.device != self.device or x.dtype != self.real_dtype or not x.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {self.real_dtype} tensor on {self.device}")
+        if x.numel() != self.batch * self.n ** 3:
+            raise ValueError(f"{name} must hold batch * n^3 values")
+        return x
+
+    def _catalogue(self, pos, w):
+        if pos.device != self.device or pos.dtype != torch.float32 or not pos.is_contiguous() or pos.dim() != 2 \
+                or pos.shape[1] != 3:
+            raise ValueError("pos must be a contiguous float32 [np, 3] tensor on the plan's device")
+        if w is not None and (w.device != self.device or w.dtype != torch.float32 or not w.is_contiguous()
+                              or w.numel() != pos.shape[0]):
+            raise ValueError("w must be a contiguous float32 [np] tensor on the plan's device")
+
+    # -- per-pass timing (HIP events around every pass launch) ---------------
+    def profile(self, enable: bool = True):
+        _lib.check(self.lib.mp3_profile(self._h, 1 if enable else 0), "mp3_profile")
+
+    def profile_read(self):
+        """{pass name: (total ms, launches)} since the last profile() call."""
+        out = {}
+        for i, name in enumerate(_lib.PASSES):
+            ms, cnt = ctypes.c_double(), ctypes.c_int64()
+            _lib.check(self.lib.mp3_profile_read(self._h, i, ctypes.byref(ms), ctypes.byref(cnt)), "mp3_profile_read")
+            out[name] = (ms.value, cnt.value)
+        return out
+
+    # -- entry points ------------------------------------------------------
+    def deposit(self, pos, w=None, np_off=None):
+        self._catalogue(pos, w)
+        off = self._offsets(np_off, pos.shape[0])
+        delta = torch.empty((self.batch, self.n, self.n, self.n), dtype=self.real_dtype, device=self.device)
+        ws = self._workspace(pos.shape[0])
+        st = self.lib.mp3_deposit(self._h, _ptr(pos), _ptr(w), off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  _ptr(delta), _ptr(ws), ws.numel(), _stream(self.device))
+        _lib.check(st, "mp3_deposit")
+        return delta
+
+    def multipole_fields(self, delta, l: int, m: int):
+        self._real(delta, "delta")
+        out = torch.empty((self.batch, self.nbins, self.n, self.n, self.n), dtype=self.complex_dtype,
+                          device=self.device)
+        ws = self._workspace()
+        st = self.lib.mp3_multipole_fields(self._h, _ptr(delta), int(l), int(m), _ptr(out), _ptr(ws), ws.numel(),
+                                           _stream(self.device))
+        _lib.check(st, "mp3_multipole_fields")
+        return out
+
+    def zeta(self, delta):
+        self._real(delta, "delta")
+        z = torch.empty((self.batch, self.lmax + 1, self.nbins, self.nbins), dtype=torch.float64, device=self.device)
+        ws = self._workspace()
+        st = self.lib.mp3_zeta(self._h, _ptr(delta), _ptr(z), _ptr(ws), ws.numel(), _stream(self.device))
+        _lib.check(st, "mp3_zeta")
+        return z
+
+    def zeta_backward(self, delta, dzeta, pos=None, w=None, np_off=None):
+        """Returns (dJ/ddelta, dJ/dw or None) for J = sum dzeta * zeta."""
+        self._real(delta, "delta")
+        dzeta = dzeta.to(device=self.device, dtype=torch.float64).contiguous()
+        if dzeta.numel() != self.batch * (self.lmax + 1) * self.nbins ** 2:
+            raise ValueError("dzeta must have shape [batch, lmax+1, nbins, nbins]")
+        ddelta = torch.empty_like(delta)
+        dw = None
+        offp = None
+        np_total = 0
+        if pos is not None:
+            self._catalogue(pos, w)
+            np_total = pos.shape[0]
+            off = self._offsets(np_off, np_total)
+            offp = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+            dw = torch.empty(np_total, dtype=self.real_dtype, device=self.device)
+        ws = self._workspace(np_total)
+        st = self.lib.mp3_zeta_backward(self._h, _ptr(delta), _ptr(dzeta), _ptr(ddelta), _ptr(pos), _ptr(w), offp,
+                                        _ptr(dw), _ptr(ws), ws.numel(), _stream(self.device))
+        _lib.check(st, "mp3_zeta_backward")
+        return ddelta, dw
+
+
+class Zeta3PCF(torch.autograd.Function):
+    """zeta = Zeta3PCF.apply(delta, plan); backward gives dJ/ddelta from the hand-written adjoint."""
+
+    @staticmethod
+    def forward(ctx, delta, plan):
+        ctx.plan = plan
+        ctx.save_for_backward(delta)
+        return plan.zeta(delta.contiguous())
+
+    @staticmethod
+    def backward(ctx, gz):
+        (delta,) = ctx.saved_tensors
+        ddelta, _ = ctx.plan.zeta_backward(delta.contiguous(), gz)
+        return ddelta, None
+
+
+class _CatalogueZeta(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, w, pos, plan, np_off):
+        delta = plan.deposit(pos, w, np_off)
+        ctx.plan, ctx.np_off = plan, np_off
+        ctx.save_for_backward(w, pos, delta)
+        return plan.zeta(delta)
+
+    @staticmethod
+    def backward(ctx, gz):
+        w, pos, delta = ctx.saved_tensors
+        _, dw = ctx.plan.zeta_backward(delta, gz, pos, w, ctx.np_off)
+        return dw, None, None, None
+
+
+def zeta_from_catalogue(plan: Plan, pos, w, np_off=None):
+    """zeta of a catalogue, differentiable with respect to the particle weights."""
+    return _CatalogueZeta.apply(w, pos, plan, np_off)

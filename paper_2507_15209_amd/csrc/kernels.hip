@@ -1,0 +1,924 @@
+// kernels.hip -- gfx950 kernels of the in-situ multipole 3PCF path.
+//
+// Data layout (per mock, per bin): complex fields of N^3 elements, index
+// (ix * N + iy) * N + iz, batches of fields contiguous.  The inverse 3-D
+// transform of each filtered field is done in three passes, one per axis:
+//
+//   pass x  (k_filter_x)   : k-space tile [qx column][16 or 8 contiguous qz] of
+//                            dhat read ONCE per (l, m); for every radial bin the
+//                            window K_{lm,b} is applied and the x-transform done;
+//                            writes field [x][qy][qz] per bin
+//   pass y  (k_fft_strided): y-transform in place           -> [x][y][qz]
+//   pass z  (k_zpass_*)    : per (x, y) pencil all bins are z-transformed into
+//                            LDS and consumed there: nodal contraction
+//                            (forward) or the adjoint source terms (backward)
+//
+// so a field element crosses HBM as: written by pass x, read+written by pass
+// y, read by pass z (32 bytes per complex64 element in the forward).
+#include "fft_core.hpp"
+#include "kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+namespace mp3 {
+
+// contiguous complex values per strided-pass row: 128 bytes
+template <typename T> constexpr int zc_of() { return 128 / (int)sizeof(c2<T>); }
+// columns-tiles per workgroup so that small lengths still fill >= 256 threads
+template <int N, typename T> constexpr int tiles_per_wg() {
+  constexpr int t = Fft<N>::TPC * zc_of<T>();
+  return t >= 256 ? 1 : 256 / t;
+}
+
+// pencils per workgroup of the contiguous pass: fill 256 threads within 32 KB of LDS
+template <int N, typename T> constexpr int contig_pencils() {
+  constexpr int byt = (N + N / 16) * (int)sizeof(c2<T>);
+  constexpr int p = Fft<N>::TPC >= 256 ? 1 : 256 / Fft<N>::TPC;
+  constexpr int cap = 32768 / byt;
+  return p < cap ? p : (cap < 1 ? 1 : cap);
+}
+
+template <int N, typename T> constexpr int strided_threads() { return Fft<N>::TPC * zc_of<T>() * tiles_per_wg<N, T>(); }
+
+__device__ __forceinline__ int sfreq(int i, int n) { return i < n / 2 ? i : i - n; }
+
+// i^l conj(Y_lm(q_hat)) * scale for m >= 0, in float64.
+// conj(Y_lm) = norm * Q_l^m(cos th) * (sin th e^{-i phi})^m with the reduced
+// associated Legendre polynomial Q_l^m = P_l^m / (1 - x^2)^{m/2}
+// (Condon-Shortley phase), which has no singularity at the poles.  At q = 0
+// the direction is taken along +z (only m = 0 survives; the radial window
+// then decides: jbar_{l>0}(0) = 0).
+__device__ double2 ylm_conj_il(int qx, int qy, int qz, int l, int m, double norm, double scale) {
+  const double q2 = (double)qx * qx + (double)qy * qy + (double)qz * qz;
+  double x = 1.0, sre = 0.0, sim = 0.0;
+  if (q2 > 0.0) {
+    const double inv = 1.0 / sqrt(q2);
+    x = qz * inv;
+    sre = qx * inv;
+    sim = -qy * inv;
+  }
+  double pmm = 1.0;
+  for (int k = 1; k <= m; ++k) pmm *= -(2.0 * k - 1.0);
+  double q = pmm;
+  if (l > m) {
+    double p0 = pmm, p1 = x * (2.0 * m + 1.0) * pmm;
+    for (int ll = m + 2; ll <= l; ++ll) {
+      const double p2 = ((2.0 * ll - 1.0) * x * p1 - (ll + m - 1.0) * p0) / (double)(ll - m);
+      p0 = p1;
+      p1 = p2;
+    }
+    q = p1;
+  }
+  double cr = 1.0, ci = 0.0;
+  for (int k = 0; k < m; ++k) {
+    const double t = cr * sre - ci * sim;
+    ci = cr * sim + ci * sre;
+    cr = t;
+  }
+  const double a = norm * q * scale;
+  double re = a * cr, im = a * ci;
+  double2 r;
+  switch (l & 3) {
+    case 0: r.x = re; r.y = im; break;
+    case 1: r.x = -im; r.y = re; break;
+    case 2: r.x = -re; r.y = -im; break;
+    default: r.x = im; r.y = -re; break;
+  }
+  return r;
+}
+
+// window factor at grid index (ix, iy, iz): i^l conj(Y) * scale with the
+// Nyquist planes set to zero; also returns |q|^2 for the radial table
+template <typename T>
+__device__ __forceinline__ c2<T> window_angular(int ix, int iy, int iz, int n, int l, int m, double norm,
+                                                double scale, int& q2) {
+  const int qx = sfreq(ix, n), qy = sfreq(iy, n), qz = sfreq(iz, n);
+  q2 = qx * qx + qy * qy + qz * qz;
+  const int h = -n / 2;
+  if (qx == h || qy == h || qz == h) return mk<T>((T)0, (T)0);
+  const double2 f = ylm_conj_il(qx, qy, qz, l, m, norm, scale);
+  return mk<T>((T)f.x, (T)f.y);
+}
+
+// ---------------------------------------------------------------------------
+// fills and small reductions
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_fill(T* p, long long count, T value) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = warpSize / 2; o > 0; o >>= 1) v += __shfl_down(v, o);
+  const int lane = threadIdx.x % warpSize, wid = threadIdx.x / warpSize;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < (int)(blockDim.x + warpSize - 1) / warpSize; ++i) t += sh[i];
+  }
+  __syncthreads();
+  return t;
+}
+
+// W[j] = sum of the weights of mock j (unit weights if w == nullptr)
+__global__ void k_weight_sum(const float* w, const long long* off, int batch, double* W) {
+  __shared__ double sh[32];
+  const int j = blockIdx.y;
+  const long long a = off[j], b = off[j + 1];
+  double s = 0.0;
+  for (long long i = a + blockIdx.x * (long long)blockDim.x + threadIdx.x; i < b; i += (long long)gridDim.x * blockDim.x)
+    s += w ? (double)w[i] : 1.0;
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0 && s != 0.0) atomicAdd(&W[j], s);
+}
+
+// S[j] = sum_x (1 + delta_x) g_x for mock j
+template <typename T>
+__global__ void k_dot_rho_g(const T* delta, const T* g, long long n3, double* S) {
+  __shared__ double sh[32];
+  const int j = blockIdx.y;
+  const T* d = delta + j * n3;
+  const T* gg = g + j * n3;
+  double s = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n3; i += (long long)gridDim.x * blockDim.x)
+    s += (1.0 + (double)d[i]) * (double)gg[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) atomicAdd(&S[j], s);
+}
+
+// ---------------------------------------------------------------------------
+// deposit: cubic B-spline, 4 taps per axis, periodic, float64 coordinates
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_mock(const long long* off, int batch, long long i) {
+  int lo = 0, hi = batch;  // off[lo] <= i < off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+struct Taps {
+  int base[3];
+  double wt[3][4];
+  bool ok;
+};
+
+__device__ __forceinline__ Taps make_taps(const float* p, int n, double sc) {
+  Taps t;
+  t.ok = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double u = (double)p[d] * sc;
+    if (!(u == u) || fabs(u) > 1e15) { t.ok = false; u = 0.0; }
+    u -= (double)n * floor(u / (double)n);          // periodic wrap into [0, n]
+    double fl = floor(u);
+    double f = u - fl;
+    int ib = (int)fl;
+    if (ib >= n) { ib -= n; }
+    t.base[d] = ib - 1;
+    const double g = 1.0 - f;
+    t.wt[d][0] = g * g * g / 6.0;
+    t.wt[d][1] = (4.0 - 6.0 * f * f + 3.0 * f * f * f) / 6.0;
+    t.wt[d][2] = (4.0 - 6.0 * g * g + 3.0 * g * g * g) / 6.0;
+    t.wt[d][3] = f * f * f / 6.0;
+  }
+  return t;
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+template <typename T>
+__global__ void k_deposit(const float* pos, const float* w, const long long* off, int batch, long long np_total,
+                          int n, double sc, T* eps) {
+  const long long n3 = (long long)n * n * n;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < np_total; i += (long long)gridDim.x * blockDim.x) {
+    const int mock = find_mock(off, batch, i);
+    Taps t = make_taps(pos + 3 * i, n, sc);
+    if (!t.ok) continue;
+    const double wi = w ? (double)w[i] : 1.0;
+    T* e = eps + mock * n3;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int ix = wrapi(t.base[0] + a, n);
+      const double wa = wi * t.wt[0][a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int iy = wrapi(t.base[1] + b, n);
+        const double wab = wa * t.wt[1][b];
+        const long long row = ((long long)ix * n + iy) * n;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int iz = wrapi(t.base[2] + c, n);
+          atomicAdd(&e[row + iz], (T)(wab * t.wt[2][c]));
+        }
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_normalise(T* eps, const double* W, long long n3) {
+  const int j = blockIdx.y;
+  const double f = (double)n3 / W[j];
+  T* e = eps + j * n3;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n3; i += (long long)gridDim.x * blockDim.x)
+    e[i] = (T)((double)e[i] * f - 1.0);
+}
+
+// dw_i = (N^3 / W) sum_taps B g - S / W
+template <typename T>
+__global__ void k_gather_dw(const float* pos, const long long* off, int batch, long long np_total, int n, double sc,
+                            const T* g, const double* W, const double* S, T* dw) {
+  const long long n3 = (long long)n * n * n;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < np_total; i += (long long)gridDim.x * blockDim.x) {
+    const int mock = find_mock(off, batch, i);
+    Taps t = make_taps(pos + 3 * i, n, sc);
+    double acc = 0.0;
+    if (t.ok) {
+      const T* gg = g + mock * n3;
+      for (int a = 0; a < 4; ++a) {
+        const int ix = wrapi(t.base[0] + a, n);
+        for (int b = 0; b < 4; ++b) {
+          const int iy = wrapi(t.base[1] + b, n);
+          const long long row = ((long long)ix * n + iy) * n;
+          const double wab = t.wt[0][a] * t.wt[1][b];
+          double s = 0.0;
+          for (int c = 0; c < 4; ++c) s += t.wt[2][c] * (double)gg[row + wrapi(t.base[2] + c, n)];
+          acc += wab * s;
+        }
+      }
+    }
+    const double Wj = W[mock];
+    dw[i] = (T)((double)n3 / Wj * acc - S[mock] / Wj);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FFT along a strided axis (x: astride = N^2, outer = N; y: astride = N, outer = N^2)
+// ---------------------------------------------------------------------------
+template <int N, typename T, int DIR, bool REAL_IN>
+__global__ void __launch_bounds__((strided_threads<N, T>())) k_fft_strided(const void* in, c2<T>* out, long long fstride_in,
+                                                       long long fstride_out, int astride, int outer, const c2<T>* tw) {
+  using F = Fft<N>;
+  constexpr int ZC = zc_of<T>();
+  constexpr int G = tiles_per_wg<N, T>();
+  constexpr int RMAX = F::RMAX;
+  __shared__ c2<T> lds[G * N * ZC];
+  const int tid = threadIdx.x;
+  const int cc = tid % ZC;
+  const int j = (tid / ZC) % F::TPC;
+  const int g = tid / (ZC * F::TPC);
+  const int tile = blockIdx.x * G + g;
+  constexpr int chunks = N / ZC;
+  const bool active = tile < N * chunks;
+  const int o = active ? tile / chunks : 0;
+  const int ch = active ? tile % chunks : 0;
+  const long long base = (long long)o * outer + ch * ZC + cc;
+  const long long f = blockIdx.y;
+  c2<T> v[RMAX];
+  if (active) {
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+      const long long idx = f * fstride_in + base + (long long)F::in_index(j, r) * astride;
+      if (REAL_IN) v[r] = mk<T>(static_cast<const T*>(in)[idx], (T)0);
+      else v[r] = static_cast<const c2<T>*>(in)[idx];
+    }
+  }
+  fft_column<N, DIR, T, false>(v, lds + g * N * ZC + cc, ZC, j, tw, active);
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < RMAX; ++e)
+      out[f * fstride_out + base + (long long)F::out_index(j, e) * astride] = v[e];
+  }
+}
+
+// FFT along the contiguous axis z, one pencil per TPC threads
+template <int N, typename T, int DIR>
+__global__ void __launch_bounds__((contig_pencils<N, T>() * Fft<N>::TPC)) k_fft_contig(const c2<T>* in, c2<T>* out, long long npencils, const c2<T>* tw) {
+  using F = Fft<N>;
+  constexpr int P = contig_pencils<N, T>();
+  constexpr int RS = N + N / 16;
+  constexpr int RMAX = F::RMAX;
+  __shared__ c2<T> lds[P * RS];
+  const int tid = threadIdx.x;
+  const int j = tid % F::TPC;
+  const int p = tid / F::TPC;
+  const long long pen = (long long)blockIdx.x * P + p;
+  const bool active = pen < npencils;
+  c2<T> v[RMAX];
+  if (active) {
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) v[r] = in[pen * N + F::in_index(j, r)];
+  }
+  fft_column<N, DIR, T, true>(v, lds + p * RS, 1, j, tw, active);
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < RMAX; ++e) out[pen * N + F::out_index(j, e)] = v[e];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass x of the forward: window K_{lm,b} on the k-space tile, all bins
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+__global__ void __launch_bounds__((strided_threads<N, T>())) k_filter_x(const c2<T>* dhat, c2<T>* fields, const T* jtab, int nq2, int nbins,
+                                                    int l, int m, double norm, double scale, const c2<T>* tw) {
+  using F = Fft<N>;
+  constexpr int ZC = zc_of<T>();
+  constexpr int G = tiles_per_wg<N, T>();
+  constexpr int RMAX = F::RMAX;
+  constexpr long long N3 = (long long)N * N * N;
+  __shared__ c2<T> lds[G * N * ZC];
+  const int tid = threadIdx.x;
+  const int cc = tid % ZC;
+  const int j = (tid / ZC) % F::TPC;
+  const int g = tid / (ZC * F::TPC);
+  const int tile = blockIdx.x * G + g;
+  constexpr int chunks = N / ZC;
+  const bool active = tile < N * chunks;
+  const int qy = active ? tile / chunks : 0;
+  const int qz = (active ? tile % chunks : 0) * ZC + cc;
+  const long long mock = blockIdx.y;
+  c2<T> v0[RMAX];
+  int q2[RMAX];
+  if (active) {
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+      const int qx = F::in_index(j, r);
+      const c2<T> d = dhat[mock * N3 + ((long long)qx * N + qy) * N + qz];
+      const c2<T> f = window_angular<T>(qx, qy, qz, N, l, m, norm, scale, q2[r]);
+      v0[r] = cmul<T>(d, f);
+    }
+  }
+  const T* jl = jtab + (long long)l * nq2 * nbins;
+  for (int b = 0; b < nbins; ++b) {
+    c2<T> v[RMAX];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) v[r] = active ? cscale<T>(v0[r], jl[(long long)q2[r] * nbins + b]) : mk<T>(0, 0);
+    fft_column<N, +1, T, false>(v, lds + g * N * ZC + cc, ZC, j, tw, active);
+    if (active) {
+      c2<T>* out = fields + (mock * nbins + b) * N3 + (long long)qy * N + qz;
+#pragma unroll
+      for (int e = 0; e < RMAX; ++e) out[(long long)F::out_index(j, e) * N * N] = v[e];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass z of the forward: z-transform of every bin of a pencil into LDS, then
+// the nodal contraction  P[b1,b2] += sum_z delta_z Re(a_b1 conj(a_b2))
+// in 4x4 register blocks (float32 per pencil, float64 across pencils).
+// ---------------------------------------------------------------------------
+struct PairBlocks {
+  int nblk, npb, zch;
+  __device__ void init(int nbins, int nthreads) {
+    nblk = (nbins + 3) / 4;
+    npb = nblk * (nblk + 1) / 2;
+    zch = nthreads / npb;
+    if (zch < 1) zch = 1;
+  }
+  __device__ void block_of(int beta, int& b1, int& b2) const {
+    int r = 0, rem = beta;
+    while (rem >= nblk - r) { rem -= nblk - r; ++r; }
+    b1 = r;
+    b2 = r + rem;
+  }
+};
+
+template <int N, typename T>
+__device__ __forceinline__ void transform_pencil_bins(const c2<T>* src, long long fstride, int nbins, c2<T>* A,
+                                                      const c2<T>* tw) {
+  using F = Fft<N>;
+  constexpr int RS = N + N / 16;
+  const int tid = threadIdx.x;
+  const int nbc = blockDim.x / F::TPC;
+  const int j = tid % F::TPC;
+  const int rounds = (nbins + nbc - 1) / nbc;
+  for (int rr = 0; rr < rounds; ++rr) {
+    const int b = rr * nbc + tid / F::TPC;
+    const bool active = b < nbins;
+    c2<T> v[F::RMAX];
+    if (active) {
+#pragma unroll
+      for (int r = 0; r < F::RMAX; ++r) v[r] = src[b * fstride + F::in_index(j, r)];
+    }
+    fft_column<N, +1, T, true>(v, A + (active ? b : 0) * RS, 1, j, tw, active);
+    if (active) {
+#pragma unroll
+      for (int e = 0; e < F::RMAX; ++e) A[b * RS + lds_pos<true>(F::out_index(j, e))] = v[e];
+    }
+  }
+}
+
+template <int N, typename T>
+__global__ void __launch_bounds__(512) k_zpass_nodal(const c2<T>* fields, const T* delta, double* partials, int nbins,
+                                                       int ppw, const c2<T>* tw) {
+  using F = Fft<N>;
+  constexpr int RS = N + N / 16;
+  constexpr long long N3 = (long long)N * N * N;
+  extern __shared__ __align__(16) char smem[];
+  c2<T>* A = reinterpret_cast<c2<T>*>(smem);
+  T* dl = reinterpret_cast<T*>(A + nbins * RS);
+  const int tid = threadIdx.x;
+  const long long mock = blockIdx.y;
+  PairBlocks pb;
+  pb.init(nbins, blockDim.x);
+  const int item = tid;
+  const bool has_item = item < pb.npb * pb.zch;
+  int bb1 = 0, bb2 = 0, zc = 0;
+  if (has_item) {
+    pb.block_of(item / pb.zch, bb1, bb2);
+    zc = item % pb.zch;
+  }
+  double acc[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+
+  const int p0 = blockIdx.x * ppw;
+  const int p1 = min(p0 + ppw, N * N);
+  for (int p = p0; p < p1; ++p) {
+    for (int z = tid; z < N; z += blockDim.x) dl[z] = delta[mock * N3 + (long long)p * N + z];
+    transform_pencil_bins<N, T>(fields + mock * nbins * N3 + (long long)p * N, N3, nbins, A, tw);
+    __syncthreads();
+    if (has_item) {
+      T a32[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) a32[i] = (T)0;
+      const int b1o = 4 * bb1, b2o = 4 * bb2;
+      for (int z = zc; z < N; z += pb.zch) {
+        const T d = dl[z];
+        const int zp = lds_pos<true>(z);
+        c2<T> x1[4], x2[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          x1[i] = (b1o + i < nbins) ? A[(b1o + i) * RS + zp] : mk<T>(0, 0);
+          x2[i] = (b2o + i < nbins) ? A[(b2o + i) * RS + zp] : mk<T>(0, 0);
+          x1[i] = cscale<T>(x1[i], d);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) a32[i * 4 + k] += x1[i].x * x2[k].x + x1[i].y * x2[k].y;
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[i] += (double)a32[i];
+    }
+    __syncthreads();
+  }
+  // reduce the z-chunks of every block through LDS, then write the symmetric partial
+  double* red = reinterpret_cast<double*>(smem);
+  if (has_item) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) red[item * 16 + i] = acc[i];
+  }
+  __syncthreads();
+  double* out = partials + ((long long)mock * gridDim.x + blockIdx.x) * nbins * nbins;
+  for (int t = tid; t < pb.npb * 16; t += blockDim.x) {
+    const int beta = t / 16, ik = t % 16;
+    double s = 0.0;
+    for (int c = 0; c < pb.zch; ++c) s += red[(beta * pb.zch + c) * 16 + ik];
+    int c1, c2b;
+    pb.block_of(beta, c1, c2b);
+    const int b1 = 4 * c1 + ik / 4, b2 = 4 * c2b + ik % 4;
+    // diagonal blocks hold both orders of a pair: keep b1 <= b2 and mirror,
+    // so the partial is exactly symmetric
+    if (b1 < nbins && b2 < nbins && b1 <= b2) {
+      out[b1 * nbins + b2] = s;
+      out[b2 * nbins + b1] = s;
+    }
+  }
+}
+
+// zeta[j][l][e] += scale * sum_w partials[j][w][e]
+__global__ void k_reduce_partials(const double* partials, int nwg, int nb2, double* zeta, int l, int lmax, double scale) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (e >= nb2) return;
+  const double* p = partials + (long long)j * nwg * nb2 + e;
+  double s = 0.0;
+  for (int w = 0; w < nwg; ++w) s += p[(long long)w * nb2];
+  zeta[((long long)j * (lmax + 1) + l) * nb2 + e] += scale * s;
+}
+
+// ---------------------------------------------------------------------------
+// backward pass z: recompute a_b on the pencil, form
+//   u_b = sum_b' lam_s[b,b'] conj(a_b'),  direct += wm Re(sum_b a_b u_b),
+//   c_b = delta u_b, and z-transform c_b (the adjoint's first axis).
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+__global__ void __launch_bounds__(512) k_zpass_adjoint(c2<T>* fields, const T* delta, const double* dzeta, T* direct,
+                                                         int nbins, int l, int lmax, T wm, int ppw, const c2<T>* tw) {
+  using F = Fft<N>;
+  constexpr int RS = N + N / 16;
+  constexpr long long N3 = (long long)N * N * N;
+  extern __shared__ __align__(16) char smem[];
+  c2<T>* A = reinterpret_cast<c2<T>*>(smem);
+  T* dl = reinterpret_cast<T*>(A + nbins * RS);
+  T* dirz = dl + N;
+  T* lam = dirz + N;
+  const int tid = threadIdx.x;
+  const long long mock = blockIdx.y;
+  const double* dz = dzeta + ((long long)mock * (lmax + 1) + l) * nbins * nbins;
+  for (int t = tid; t < nbins * nbins; t += blockDim.x) {
+    const int b = t / nbins, bp = t % nbins;
+    lam[t] = (T)(0.5 * (dz[b * nbins + bp] + dz[bp * nbins + b]));
+  }
+  const int zb = max(1, (int)blockDim.x / nbins);
+  const int j = tid % F::TPC;
+  const int nbc = blockDim.x / F::TPC;
+  const int p0 = blockIdx.x * ppw;
+  const int p1 = min(p0 + ppw, N * N);
+  for (int p = p0; p < p1; ++p) {
+    const long long poff = mock * N3 + (long long)p * N;
+    for (int z = tid; z < N; z += blockDim.x) {
+      dl[z] = delta[poff + z];
+      dirz[z] = (T)0;
+    }
+    c2<T>* fbase = fields + mock * nbins * N3 + (long long)p * N;
+    transform_pencil_bins<N, T>(fbase, N3, nbins, A, tw);
+    __syncthreads();
+    for (int z0 = 0; z0 < N; z0 += zb) {
+      const int z = z0 + tid / nbins;
+      const int b = tid % nbins;
+      const bool ok = (tid < zb * nbins) && (z < N);
+      c2<T> c = mk<T>(0, 0);
+      if (ok) {
+        const int zp = lds_pos<true>(z);
+        T ur = 0, ui = 0;
+        for (int bp = 0; bp < nbins; ++bp) {
+          const c2<T> a = A[bp * RS + zp];
+          const T lv = lam[b * nbins + bp];
+          ur += lv * a.x;
+          ui -= lv * a.y;
+        }
+        const c2<T> ab = A[b * RS + zp];
+        atomicAdd(&dirz[z], ab.x * ur - ab.y * ui);
+        c = mk<T>(dl[z] * ur, dl[z] * ui);
+      }
+      __syncthreads();
+      if (ok) A[b * RS + lds_pos<true>(z)] = c;
+      __syncthreads();
+    }
+    for (int z = tid; z < N; z += blockDim.x) direct[poff + z] += wm * dirz[z];
+    // adjoint z-transform of every c_b, read from LDS, written over the field
+    const int rounds = (nbins + nbc - 1) / nbc;
+    for (int rr = 0; rr < rounds; ++rr) {
+      const int b = rr * nbc + tid / F::TPC;
+      const bool active = b < nbins;
+      c2<T> v[F::RMAX];
+      if (active) {
+#pragma unroll
+        for (int r = 0; r < F::RMAX; ++r) v[r] = A[b * RS + lds_pos<true>(F::in_index(j, r))];
+      }
+      __syncthreads();
+      fft_column<N, +1, T, true>(v, A + (active ? b : 0) * RS, 1, j, tw, active);
+      if (active) {
+#pragma unroll
+        for (int e = 0; e < F::RMAX; ++e) fbase[b * N3 + F::out_index(j, e)] = v[e];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// backward pass x: x-transform of every adjoint source c_b, times the window,
+// summed over bins and accumulated into G(q) (one read-modify-write per (l, m))
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+__global__ void __launch_bounds__((strided_threads<N, T>())) k_adjoint_x(const c2<T>* fields, c2<T>* G, const T* jtab, int nq2, int nbins,
+                                                     int l, int m, double norm, double scale, const c2<T>* tw) {
+  using F = Fft<N>;
+  constexpr int ZC = zc_of<T>();
+  constexpr int GT = tiles_per_wg<N, T>();
+  constexpr int RMAX = F::RMAX;
+  constexpr long long N3 = (long long)N * N * N;
+  __shared__ c2<T> lds[GT * N * ZC];
+  const int tid = threadIdx.x;
+  const int cc = tid % ZC;
+  const int j = (tid / ZC) % F::TPC;
+  const int g = tid / (ZC * F::TPC);
+  const int tile = blockIdx.x * GT + g;
+  constexpr int chunks = N / ZC;
+  const bool active = tile < N * chunks;
+  const int qy = active ? tile / chunks : 0;
+  const int qz = (active ? tile % chunks : 0) * ZC + cc;
+  const long long mock = blockIdx.y;
+  c2<T> fac[RMAX], acc[RMAX];
+  int q2[RMAX];
+#pragma unroll
+  for (int e = 0; e < RMAX; ++e) {
+    acc[e] = mk<T>(0, 0);
+    fac[e] = active ? window_angular<T>(F::out_index(j, e), qy, qz, N, l, m, norm, scale, q2[e]) : mk<T>(0, 0);
+    if (!active) q2[e] = 0;
+  }
+  const T* jl = jtab + (long long)l * nq2 * nbins;
+  for (int b = 0; b < nbins; ++b) {
+    c2<T> v[RMAX];
+    if (active) {
+      const c2<T>* src = fields + (mock * nbins + b) * N3 + (long long)qy * N + qz;
+#pragma unroll
+      for (int r = 0; r < RMAX; ++r) v[r] = src[(long long)F::in_index(j, r) * N * N];
+    }
+    fft_column<N, +1, T, false>(v, lds + g * N * ZC + cc, ZC, j, tw, active);
+    if (active) {
+#pragma unroll
+      for (int e = 0; e < RMAX; ++e) {
+        const c2<T> k = cscale<T>(fac[e], jl[(long long)q2[e] * nbins + b]);
+        acc[e] = cadd<T>(acc[e], cmul<T>(v[e], k));
+      }
+    }
+  }
+  if (active) {
+    c2<T>* dst = G + mock * N3 + (long long)qy * N + qz;
+#pragma unroll
+    for (int e = 0; e < RMAX; ++e) {
+      c2<T>* p = dst + (long long)F::out_index(j, e) * N * N;
+      *p = cadd<T>(*p, acc[e]);
+    }
+  }
+}
+
+// ddelta = scale (direct + 2 Re Ghat)
+template <typename T>
+__global__ void k_grad_combine(const T* direct, const c2<T>* ghat, T* ddelta, long long count, double scale) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
+    ddelta[i] = (T)(scale * ((double)direct[i] + 2.0 * (double)ghat[i].x));
+}
+
+}  // namespace mp3
+
+// ===========================================================================
+// host launchers
+// ===========================================================================
+namespace mp3 {
+
+namespace {
+
+inline unsigned grid_for(long long count, int threads, unsigned cap = 65535u * 4) {
+  long long g = (count + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > (long long)cap) g = cap;
+  return (unsigned)g;
+}
+
+template <typename T> using CT = c2<T>;
+
+template <int N, typename T>
+hipError_t fft3d_t(int dir, bool real_in, const void* in, void* out, int nfields, const void* tw, hipStream_t st) {
+  constexpr int ZC = zc_of<T>();
+  constexpr int G = tiles_per_wg<N, T>();
+  constexpr int threads = Fft<N>::TPC * ZC * G;
+  constexpr long long N3 = (long long)N * N * N;
+  const dim3 gs((N * (N / ZC) + G - 1) / G, nfields);
+  CT<T>* o = static_cast<CT<T>*>(out);
+  const CT<T>* t = static_cast<const CT<T>*>(tw);
+  // x axis (stride N^2), tiles over (y, z-chunk)
+  if (dir < 0) {
+    if (real_in) k_fft_strided<N, T, -1, true><<<gs, threads, 0, st>>>(in, o, N3, N3, N * N, N, t);
+    else k_fft_strided<N, T, -1, false><<<gs, threads, 0, st>>>(in, o, N3, N3, N * N, N, t);
+    k_fft_strided<N, T, -1, false><<<gs, threads, 0, st>>>(o, o, N3, N3, N, N * N, t);
+  } else {
+    if (real_in) k_fft_strided<N, T, +1, true><<<gs, threads, 0, st>>>(in, o, N3, N3, N * N, N, t);
+    else k_fft_strided<N, T, +1, false><<<gs, threads, 0, st>>>(in, o, N3, N3, N * N, N, t);
+    k_fft_strided<N, T, +1, false><<<gs, threads, 0, st>>>(o, o, N3, N3, N, N * N, t);
+  }
+  constexpr int P = contig_pencils<N, T>();
+  const long long npen = (long long)nfields * N * N;
+  const unsigned gz = (unsigned)((npen + P - 1) / P);
+  if (dir < 0) k_fft_contig<N, T, -1><<<gz, P * Fft<N>::TPC, 0, st>>>(o, o, npen, t);
+  else k_fft_contig<N, T, +1><<<gz, P * Fft<N>::TPC, 0, st>>>(o, o, npen, t);
+  return hipGetLastError();
+}
+
+template <int N, typename T>
+hipError_t fft_y_t(int dir, void* buf, int nfields, const void* tw, hipStream_t st) {
+  constexpr int ZC = zc_of<T>();
+  constexpr int G = tiles_per_wg<N, T>();
+  constexpr int threads = Fft<N>::TPC * ZC * G;
+  constexpr long long N3 = (long long)N * N * N;
+  const dim3 gs((N * (N / ZC) + G - 1) / G, nfields);
+  CT<T>* o = static_cast<CT<T>*>(buf);
+  const CT<T>* t = static_cast<const CT<T>*>(tw);
+  if (dir < 0) k_fft_strided<N, T, -1, false><<<gs, threads, 0, st>>>(o, o, N3, N3, N, N * N, t);
+  else k_fft_strided<N, T, +1, false><<<gs, threads, 0, st>>>(o, o, N3, N3, N, N * N, t);
+  return hipGetLastError();
+}
+
+template <int N, typename T>
+hipError_t fft_z_t(int dir, const void* in, void* out, int nfields, const void* tw, hipStream_t st) {
+  constexpr int P = contig_pencils<N, T>();
+  const long long npen = (long long)nfields * N * N;
+  const unsigned gz = (unsigned)((npen + P - 1) / P);
+  const CT<T>* i = static_cast<const CT<T>*>(in);
+  CT<T>* o = static_cast<CT<T>*>(out);
+  const CT<T>* t = static_cast<const CT<T>*>(tw);
+  if (dir < 0) k_fft_contig<N, T, -1><<<gz, P * Fft<N>::TPC, 0, st>>>(i, o, npen, t);
+  else k_fft_contig<N, T, +1><<<gz, P * Fft<N>::TPC, 0, st>>>(i, o, npen, t);
+  return hipGetLastError();
+}
+
+template <int N, typename T>
+hipError_t filter_x_t(const FilterArgs& a, hipStream_t st) {
+  constexpr int ZC = zc_of<T>();
+  constexpr int G = tiles_per_wg<N, T>();
+  constexpr int threads = Fft<N>::TPC * ZC * G;
+  const dim3 gs((N * (N / ZC) + G - 1) / G, a.batch);
+  k_filter_x<N, T><<<gs, threads, 0, st>>>(static_cast<const CT<T>*>(a.src), static_cast<CT<T>*>(a.dst),
+                                          static_cast<const T*>(a.jtab), a.nq2, a.nbins, a.l, a.m, a.norm, a.scale,
+                                          static_cast<const CT<T>*>(a.tw));
+  return hipGetLastError();
+}
+
+template <int N, typename T>
+hipError_t adjoint_x_t(const FilterArgs& a, hipStream_t st) {
+  constexpr int ZC = zc_of<T>();
+  constexpr int G = tiles_per_wg<N, T>();
+  constexpr int threads = Fft<N>::TPC * ZC * G;
+  const dim3 gs((N * (N / ZC) + G - 1) / G, a.batch);
+  k_adjoint_x<N, T><<<gs, threads, 0, st>>>(static_cast<const CT<T>*>(a.src), static_cast<CT<T>*>(a.dst),
+                                           static_cast<const T*>(a.jtab), a.nq2, a.nbins, a.l, a.m, a.norm, a.scale,
+                                           static_cast<const CT<T>*>(a.tw));
+  return hipGetLastError();
+}
+
+template <int N> inline int zpass_threads(int nbins) {
+  constexpr int TPC = Fft<N>::TPC;
+  int nbc = nbins;
+  const int lo = TPC >= 64 ? 1 : 64 / TPC;
+  const int hi = 512 / TPC;
+  if (nbc < lo) nbc = lo;
+  if (nbc > hi) nbc = hi;
+  return nbc * TPC;
+}
+
+template <int N, typename T> inline size_t zpass_nodal_lds(int nbins, int threads) {
+  constexpr int RS = N + N / 16;
+  size_t a = (size_t)nbins * RS * sizeof(CT<T>) + (size_t)N * sizeof(T);
+  size_t r = (size_t)threads * 16 * sizeof(double);
+  return a > r ? a : r;
+}
+
+template <int N, typename T> inline size_t zpass_adjoint_lds(int nbins) {
+  constexpr int RS = N + N / 16;
+  return (size_t)nbins * RS * sizeof(CT<T>) + 2 * (size_t)N * sizeof(T) + (size_t)nbins * nbins * sizeof(T);
+}
+
+template <typename K> hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int N, typename T>
+hipError_t zpass_nodal_t(const ZpassArgs& a, hipStream_t st) {
+  const int threads = zpass_threads<N>(a.nbins);
+  const size_t lds = zpass_nodal_lds<N, T>(a.nbins, threads);
+  hipError_t e = allow_lds(k_zpass_nodal<N, T>, lds);
+  if (e != hipSuccess) return e;
+  const dim3 gs(a.nwg, a.batch);
+  k_zpass_nodal<N, T><<<gs, threads, lds, st>>>(static_cast<const CT<T>*>(a.fields), static_cast<const T*>(a.delta),
+                                               a.partials, a.nbins, a.ppw, static_cast<const CT<T>*>(a.tw));
+  return hipGetLastError();
+}
+
+template <int N, typename T>
+hipError_t zpass_adjoint_t(const ZpassArgs& a, hipStream_t st) {
+  const int threads = zpass_threads<N>(a.nbins);
+  const size_t lds = zpass_adjoint_lds<N, T>(a.nbins);
+  hipError_t e = allow_lds(k_zpass_adjoint<N, T>, lds);
+  if (e != hipSuccess) return e;
+  const dim3 gs(a.nwg, a.batch);
+  k_zpass_adjoint<N, T><<<gs, threads, lds, st>>>(static_cast<CT<T>*>(const_cast<void*>(a.fields)),
+                                                 static_cast<const T*>(a.delta), a.dzeta, static_cast<T*>(a.direct),
+                                                 a.nbins, a.l, a.lmax, (T)a.wm, a.ppw, static_cast<const CT<T>*>(a.tw));
+  return hipGetLastError();
+}
+
+template <int N, typename T> size_t zpass_lds_need_t(int nbins) {
+  const size_t a = zpass_nodal_lds<N, T>(nbins, zpass_threads<N>(nbins));
+  const size_t b = zpass_adjoint_lds<N, T>(nbins);
+  return a > b ? a : b;
+}
+
+// dispatch over the grid length and the precision
+#define MP3_DISPATCH(fn, n, prec, ...)                                                              \
+  do {                                                                                              \
+    switch (n) {                                                                                    \
+      case 16: return prec ? fn<16, double>(__VA_ARGS__) : fn<16, float>(__VA_ARGS__);              \
+      case 32: return prec ? fn<32, double>(__VA_ARGS__) : fn<32, float>(__VA_ARGS__);              \
+      case 64: return prec ? fn<64, double>(__VA_ARGS__) : fn<64, float>(__VA_ARGS__);              \
+      case 128: return prec ? fn<128, double>(__VA_ARGS__) : fn<128, float>(__VA_ARGS__);           \
+      case 256: return prec ? fn<256, double>(__VA_ARGS__) : fn<256, float>(__VA_ARGS__);           \
+      case 512: return prec ? fn<512, double>(__VA_ARGS__) : fn<512, float>(__VA_ARGS__);           \
+      default: return hipErrorInvalidValue;                                                         \
+    }                                                                                               \
+  } while (0)
+
+}  // namespace
+
+hipError_t launch_fft3d(int n, int prec, int dir, bool real_in, const void* in, void* out, int nfields, const void* tw,
+                        hipStream_t st) {
+  MP3_DISPATCH(fft3d_t, n, prec, dir, real_in, in, out, nfields, tw, st);
+}
+
+hipError_t launch_fft_y(int n, int prec, int dir, void* buf, int nfields, const void* tw, hipStream_t st) {
+  MP3_DISPATCH(fft_y_t, n, prec, dir, buf, nfields, tw, st);
+}
+
+hipError_t launch_fft_z(int n, int prec, int dir, const void* in, void* out, int nfields, const void* tw, hipStream_t st) {
+  MP3_DISPATCH(fft_z_t, n, prec, dir, in, out, nfields, tw, st);
+}
+
+hipError_t launch_filter_x(int n, int prec, const FilterArgs& a, hipStream_t st) { MP3_DISPATCH(filter_x_t, n, prec, a, st); }
+hipError_t launch_adjoint_x(int n, int prec, const FilterArgs& a, hipStream_t st) { MP3_DISPATCH(adjoint_x_t, n, prec, a, st); }
+hipError_t launch_zpass_nodal(int n, int prec, const ZpassArgs& a, hipStream_t st) { MP3_DISPATCH(zpass_nodal_t, n, prec, a, st); }
+hipError_t launch_zpass_adjoint(int n, int prec, const ZpassArgs& a, hipStream_t st) { MP3_DISPATCH(zpass_adjoint_t, n, prec, a, st); }
+
+size_t zpass_lds_need(int n, int prec, int nbins) {
+  switch (n) {
+    case 16: return prec ? zpass_lds_need_t<16, double>(nbins) : zpass_lds_need_t<16, float>(nbins);
+    case 32: return prec ? zpass_lds_need_t<32, double>(nbins) : zpass_lds_need_t<32, float>(nbins);
+    case 64: return prec ? zpass_lds_need_t<64, double>(nbins) : zpass_lds_need_t<64, float>(nbins);
+    case 128: return prec ? zpass_lds_need_t<128, double>(nbins) : zpass_lds_need_t<128, float>(nbins);
+    case 256: return prec ? zpass_lds_need_t<256, double>(nbins) : zpass_lds_need_t<256, float>(nbins);
+    case 512: return prec ? zpass_lds_need_t<512, double>(nbins) : zpass_lds_need_t<512, float>(nbins);
+    default: return (size_t)-1;
+  }
+}
+
+hipError_t launch_fill(int prec, void* p, long long count, double value, hipStream_t st) {
+  const unsigned g = grid_for(count, 256, 8192);
+  if (prec) k_fill<double><<<g, 256, 0, st>>>(static_cast<double*>(p), count, value);
+  else k_fill<float><<<g, 256, 0, st>>>(static_cast<float*>(p), count, (float)value);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, long long count, double value, hipStream_t st) {
+  const unsigned g = grid_for(count, 256, 8192);
+  k_fill<double><<<g, 256, 0, st>>>(p, count, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const double* partials, int nwg, int nb2, double* zeta, int l, int lmax, double scale,
+                                  int batch, hipStream_t st) {
+  const dim3 gs((nb2 + 255) / 256, batch);
+  k_reduce_partials<<<gs, 256, 0, st>>>(partials, nwg, nb2, zeta, l, lmax, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_weight_sum(const float* w, const long long* off, int batch, long long np_max, double* W, hipStream_t st) {
+  const dim3 gs(grid_for(np_max, 256, 1024), batch);
+  k_weight_sum<<<gs, 256, 0, st>>>(w, off, batch, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_deposit(int prec, const float* pos, const float* w, const long long* off, int batch, long long np_total,
+                          int n, double sc, void* eps, hipStream_t st) {
+  const unsigned g = grid_for(np_total, 256, 16384);
+  if (prec) k_deposit<double><<<g, 256, 0, st>>>(pos, w, off, batch, np_total, n, sc, static_cast<double*>(eps));
+  else k_deposit<float><<<g, 256, 0, st>>>(pos, w, off, batch, np_total, n, sc, static_cast<float*>(eps));
+  return hipGetLastError();
+}
+
+hipError_t launch_normalise(int prec, void* eps, const double* W, long long n3, int batch, hipStream_t st) {
+  const dim3 gs(grid_for(n3, 256, 4096), batch);
+  if (prec) k_normalise<double><<<gs, 256, 0, st>>>(static_cast<double*>(eps), W, n3);
+  else k_normalise<float><<<gs, 256, 0, st>>>(static_cast<float*>(eps), W, n3);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_combine(int prec, const void* direct, const void* ghat, void* ddelta, long long count, double scale,
+                               hipStream_t st) {
+  const unsigned g = grid_for(count, 256, 16384);
+  if (prec)
+    k_grad_combine<double><<<g, 256, 0, st>>>(static_cast<const double*>(direct), static_cast<const double2*>(ghat),
+                                              static_cast<double*>(ddelta), count, scale);
+  else
+    k_grad_combine<float><<<g, 256, 0, st>>>(static_cast<const float*>(direct), static_cast<const float2*>(ghat),
+                                             static_cast<float*>(ddelta), count, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot_rho_g(int prec, const void* delta, const void* g, long long n3, double* S, int batch, hipStream_t st) {
+  const dim3 gs(grid_for(n3, 256, 1024), batch);
+  if (prec) k_dot_rho_g<double><<<gs, 256, 0, st>>>(static_cast<const double*>(delta), static_cast<const double*>(g), n3, S);
+  else k_dot_rho_g<float><<<gs, 256, 0, st>>>(static_cast<const float*>(delta), static_cast<const float*>(g), n3, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_dw(int prec, const float* pos, const long long* off, int batch, long long np_total, int n,
+                            double sc, const void* g, const double* W, const double* S, void* dw, hipStream_t st) {
+  const unsigned gr = grid_for(np_total, 256, 16384);
+  if (prec)
+    k_gather_dw<double><<<gr, 256, 0, st>>>(pos, off, batch, np_total, n, sc, static_cast<const double*>(g), W, S,
+                                            static_cast<double*>(dw));
+  else
+    k_gather_dw<float><<<gr, 256, 0, st>>>(pos, off, batch, np_total, n, sc, static_cast<const float*>(g), W, S,
+                                           static_cast<float*>(dw));
+  return hipGetLastError();
+}
+
+}  // namespace mp3

@@ -1,0 +1,52 @@
+// kernels.hpp -- host entry points of the device kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+
+namespace mp3 {
+
+struct FilterArgs {
+  const void* src;   // k_filter_x: dhat [batch][N^3]; k_adjoint_x: sources [batch][nbins][N^3]
+  void* dst;         // k_filter_x: fields [batch][nbins][N^3]; k_adjoint_x: accumulator G [batch][N^3]
+  const void* jtab;  // [lmax+1][nq2][nbins] radial window
+  const void* tw;    // twiddles exp(-2 pi i t / N)
+  int nq2, nbins, l, m, batch;
+  double norm;       // Y_lm normalisation
+  double scale;      // extra real factor (1/N^3, times the m weight in the adjoint)
+};
+
+struct ZpassArgs {
+  const void* fields;   // [batch][nbins][N^3], layout [x][y][qz]
+  const void* delta;    // [batch][N^3]
+  double* partials;     // forward: [batch][nwg][nbins^2]
+  const double* dzeta;  // backward: [batch][lmax+1][nbins^2]
+  void* direct;         // backward: [batch][N^3] explicit-primary gradient accumulator
+  const void* tw;
+  int nbins, nwg, ppw, batch, l, lmax;
+  double wm;            // m weight (1 for m = 0, 2 otherwise)
+};
+
+hipError_t launch_fft3d(int n, int prec, int dir, bool real_in, const void* in, void* out, int nfields, const void* tw,
+                        hipStream_t st);
+hipError_t launch_fft_y(int n, int prec, int dir, void* buf, int nfields, const void* tw, hipStream_t st);
+hipError_t launch_fft_z(int n, int prec, int dir, const void* in, void* out, int nfields, const void* tw, hipStream_t st);
+hipError_t launch_filter_x(int n, int prec, const FilterArgs& a, hipStream_t st);
+hipError_t launch_adjoint_x(int n, int prec, const FilterArgs& a, hipStream_t st);
+hipError_t launch_zpass_nodal(int n, int prec, const ZpassArgs& a, hipStream_t st);
+hipError_t launch_zpass_adjoint(int n, int prec, const ZpassArgs& a, hipStream_t st);
+size_t zpass_lds_need(int n, int prec, int nbins);
+hipError_t launch_fill(int prec, void* p, long long count, double value, hipStream_t st);
+hipError_t launch_fill_f64(double* p, long long count, double value, hipStream_t st);
+hipError_t launch_reduce_partials(const double* partials, int nwg, int nb2, double* zeta, int l, int lmax, double scale,
+                                  int batch, hipStream_t st);
+hipError_t launch_weight_sum(const float* w, const long long* off, int batch, long long np_max, double* W, hipStream_t st);
+hipError_t launch_deposit(int prec, const float* pos, const float* w, const long long* off, int batch, long long np_total,
+                          int n, double sc, void* eps, hipStream_t st);
+hipError_t launch_normalise(int prec, void* eps, const double* W, long long n3, int batch, hipStream_t st);
+hipError_t launch_grad_combine(int prec, const void* direct, const void* ghat, void* ddelta, long long count, double scale,
+                               hipStream_t st);
+hipError_t launch_dot_rho_g(int prec, const void* delta, const void* g, long long n3, double* S, int batch, hipStream_t st);
+hipError_t launch_gather_dw(int prec, const float* pos, const long long* off, int batch, long long np_total, int n,
+                            double sc, const void* g, const double* W, const double* S, void* dw, hipStream_t st);
+
+}  // namespace mp3

@@ -1,0 +1,462 @@
+// mp3_api.cpp -- the C ABI declared in include/mp3.h: plan, validation,
+// workspace layout and the per-(l, m) launch sequence.
+#include "mp3.h"
+
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "tables.hpp"
+
+struct mp3_plan_s {
+  int n = 0, lmax = 0, nbins = 0, prec = 0, summation = 0, batch = 1;
+  double box = 0.0;
+  std::vector<double> edges;
+  int nq2 = 0;
+  void* jtab = nullptr;  // [lmax+1][nq2][nbins] real
+  void* tw = nullptr;    // [n] complex
+  size_t elt = 4, celt = 8;
+  int device = 0;
+  // optional per-pass HIP event timing
+  bool profile = false;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+  struct Rec { int pass; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  double prof_ms[MP3_NPASS] = {0};
+  long long prof_n[MP3_NPASS] = {0};
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(MP3_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define MP3_HIP(call, where)                       \
+  do {                                             \
+    hipError_t e_ = (call);                        \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+constexpr double kFourPi = 12.566370614359172953850573533118011536788677597500;
+constexpr size_t kLdsLimit = 160 * 1024;
+constexpr int kTargetWorkgroups = 4096;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t off, W, S, dhat, fields, partials, G, direct, total;
+  int nwg, ppw;
+};
+
+Layout layout(const mp3_plan_s* p) {
+  Layout L{};
+  const size_t n3 = (size_t)p->n * p->n * p->n;
+  const size_t B = (size_t)p->batch;
+  const long long pencils = (long long)p->n * p->n;
+  long long nwg = kTargetWorkgroups / p->batch;
+  if (nwg < 1) nwg = 1;
+  if (nwg > pencils) nwg = pencils;
+  L.ppw = (int)((pencils + nwg - 1) / nwg);
+  L.nwg = (int)((pencils + L.ppw - 1) / L.ppw);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align256(o + bytes);
+    return r;
+  };
+  L.off = take((B + 1) * sizeof(long long));
+  L.W = take(B * sizeof(double));
+  L.S = take(B * sizeof(double));
+  L.dhat = take(B * n3 * p->celt);
+  L.fields = take(B * (size_t)p->nbins * n3 * p->celt);
+  L.partials = take(B * (size_t)L.nwg * p->nbins * p->nbins * sizeof(double));
+  L.G = take(B * n3 * p->celt);
+  L.direct = take(B * n3 * p->elt);
+  L.total = o;
+  return L;
+}
+
+bool pow2_supported(int n) { return n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512; }
+
+int check_plan(const mp3_plan_s* p) {
+  if (!p) return fail(MP3_EINVAL, "plan is NULL");
+  return MP3_OK;
+}
+
+int check_ws(const mp3_plan_s* p, void* ws, size_t wsb, size_t need) {
+  (void)p;
+  if (!ws) return fail(MP3_EWORKSPACE, "workspace is NULL");
+  if (wsb < need)
+    return fail(MP3_EWORKSPACE, "workspace too small: " + std::to_string(wsb) + " < " + std::to_string(need) + " bytes");
+  return MP3_OK;
+}
+
+int check_offsets(const mp3_plan_s* p, const int64_t* np_off, long long* np_total, long long* np_max) {
+  if (!np_off) return fail(MP3_EINVAL, "np_off is NULL");
+  if (np_off[0] != 0) return fail(MP3_EINVAL, "np_off[0] must be 0");
+  long long mx = 0;
+  for (int j = 0; j < p->batch; ++j) {
+    const long long c = np_off[j + 1] - np_off[j];
+    if (c <= 0) return fail(MP3_EINVAL, "mock " + std::to_string(j) + " has no particles (np_off must increase strictly)");
+    if (c > mx) mx = c;
+  }
+  *np_total = np_off[p->batch];
+  *np_max = mx;
+  return MP3_OK;
+}
+
+char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
+
+hipEvent_t next_event(mp3_plan_s* p) {
+  if (p->pool_used == p->pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    p->pool.push_back(e);
+  }
+  return p->pool[p->pool_used++];
+}
+
+// Launch f() on stream st; with profiling on, bracket it by two events
+// attributed to the given pass.
+template <typename Fn>
+hipError_t timed(const mp3_plan_s* cp, int pass, hipStream_t st, Fn f) {
+  mp3_plan_s* p = const_cast<mp3_plan_s*>(cp);
+  if (!p->profile) return f();
+  hipEvent_t a = next_event(p), b = next_event(p);
+  if (!a || !b) return f();
+  hipEventRecord(a, st);
+  hipError_t e = f();
+  hipEventRecord(b, st);
+  p->recs.push_back({pass, a, b});
+  return e;
+}
+
+void collect_profile(mp3_plan_s* p) {
+  for (auto& r : p->recs) {
+    hipEventSynchronize(r.b);
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      p->prof_ms[r.pass] += ms;
+      p->prof_n[r.pass] += 1;
+    }
+  }
+  p->recs.clear();
+  p->pool_used = 0;
+}
+
+int upload_offsets(const mp3_plan_s* p, const int64_t* np_off, void* ws, const Layout& L, hipStream_t st) {
+  MP3_HIP(hipMemcpyAsync(at(ws, L.off), np_off, (p->batch + 1) * sizeof(long long), hipMemcpyHostToDevice, st),
+          "copy np_off");
+  return MP3_OK;
+}
+
+// delta -> dhat (forward DFT, unnormalised)
+int forward_dft(const mp3_plan_s* p, const void* delta, void* ws, const Layout& L, hipStream_t st) {
+  MP3_HIP(timed(p, MP3_PASS_DFT, st, [&] { return mp3::launch_fft3d(p->n, p->prec, -1, true, delta, at(ws, L.dhat), p->batch, p->tw, st); }), "forward FFT");
+  return MP3_OK;
+}
+
+mp3::FilterArgs filter_args(const mp3_plan_s* p, const void* src, void* dst, int l, int m, double scale) {
+  mp3::FilterArgs a;
+  a.src = src;
+  a.dst = dst;
+  a.jtab = p->jtab;
+  a.tw = p->tw;
+  a.nq2 = p->nq2;
+  a.nbins = p->nbins;
+  a.l = l;
+  a.m = m;
+  a.batch = p->batch;
+  a.norm = mp3::ylm_norm(l, m);
+  a.scale = scale;
+  return a;
+}
+
+// fields of (l, m) after the x and y passes: layout [batch][nbins][x][y][qz]
+int fields_xy(const mp3_plan_s* p, void* ws, const Layout& L, void* dst, int l, int m, hipStream_t st) {
+  const double n3 = (double)p->n * p->n * p->n;
+  mp3::FilterArgs a = filter_args(p, at(ws, L.dhat), dst, l, m, 1.0 / n3);
+  MP3_HIP(timed(p, MP3_PASS_FILTER_X, st, [&] { return mp3::launch_filter_x(p->n, p->prec, a, st); }), "filter pass");
+  MP3_HIP(timed(p, MP3_PASS_Y, st, [&] { return mp3::launch_fft_y(p->n, p->prec, +1, dst, p->batch * p->nbins, p->tw, st); }), "y pass");
+  return MP3_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mp3_status_string(int s) {
+  switch (s) {
+    case MP3_OK: return "MP3_OK";
+    case MP3_EINVAL: return "MP3_EINVAL";
+    case MP3_ENOMEM: return "MP3_ENOMEM";
+    case MP3_EHIP: return "MP3_EHIP";
+    case MP3_EUNSUPPORTED: return "MP3_EUNSUPPORTED";
+    case MP3_EWORKSPACE: return "MP3_EWORKSPACE";
+    default: return "MP3_UNKNOWN";
+  }
+}
+
+const char* mp3_last_error(void) { return g_last_error.c_str(); }
+
+int mp3_plan_create(const mp3_plan_desc* d, mp3_plan_t* out) {
+  if (!d || !out) return fail(MP3_EINVAL, "desc and out must not be NULL");
+  if (!pow2_supported(d->n)) return fail(MP3_EUNSUPPORTED, "n must be one of 16, 32, 64, 128, 256, 512");
+  if (!(d->box > 0.0) || !std::isfinite(d->box)) return fail(MP3_EINVAL, "box must be positive and finite");
+  if (d->lmax < 0 || d->lmax > 20) return fail(MP3_EINVAL, "lmax must be in [0, 20]");
+  if (d->nbins < 1 || d->nbins > 64) return fail(MP3_EINVAL, "nbins must be in [1, 64]");
+  if (!d->edges) return fail(MP3_EINVAL, "edges is NULL");
+  for (int b = 0; b <= d->nbins; ++b) {
+    if (!std::isfinite(d->edges[b]) || d->edges[b] < 0.0) return fail(MP3_EINVAL, "edges must be finite and >= 0");
+    if (b > 0 && !(d->edges[b] > d->edges[b - 1])) return fail(MP3_EINVAL, "edges must increase strictly");
+  }
+  if (d->precision != MP3_F32 && d->precision != MP3_F64) return fail(MP3_EINVAL, "precision must be MP3_F32 or MP3_F64");
+  if (d->summation != MP3_SUM_NODAL) return fail(MP3_EUNSUPPORTED, "summation form not supported");
+  if (d->batch < 1) return fail(MP3_EINVAL, "batch must be >= 1");
+  if (mp3::zpass_lds_need(d->n, d->precision, d->nbins) > kLdsLimit)
+    return fail(MP3_EUNSUPPORTED, "n * nbins too large for the z pass's LDS at this precision");
+
+  mp3_plan_s* p = new (std::nothrow) mp3_plan_s;
+  if (!p) return fail(MP3_ENOMEM, "host allocation failed");
+  p->n = d->n;
+  p->box = d->box;
+  p->lmax = d->lmax;
+  p->nbins = d->nbins;
+  p->prec = d->precision;
+  p->summation = d->summation;
+  p->batch = d->batch;
+  p->edges.assign(d->edges, d->edges + d->nbins + 1);
+  p->nq2 = mp3::nq2_count(p->n);
+  p->elt = p->prec ? sizeof(double) : sizeof(float);
+  p->celt = 2 * p->elt;
+  hipGetDevice(&p->device);
+
+  std::vector<double> jt;
+  mp3::jbar_table(p->n, p->box, p->lmax, p->edges, jt);
+  std::vector<double> twr, twi;
+  mp3::twiddles(p->n, twr, twi);
+  std::vector<char> hj(jt.size() * p->elt), ht((size_t)p->n * p->celt);
+  for (size_t i = 0; i < jt.size(); ++i) {
+    if (p->prec) reinterpret_cast<double*>(hj.data())[i] = jt[i];
+    else reinterpret_cast<float*>(hj.data())[i] = (float)jt[i];
+  }
+  for (int i = 0; i < p->n; ++i) {
+    if (p->prec) {
+      reinterpret_cast<double*>(ht.data())[2 * i] = twr[i];
+      reinterpret_cast<double*>(ht.data())[2 * i + 1] = twi[i];
+    } else {
+      reinterpret_cast<float*>(ht.data())[2 * i] = (float)twr[i];
+      reinterpret_cast<float*>(ht.data())[2 * i + 1] = (float)twi[i];
+    }
+  }
+  if (hipMalloc(&p->jtab, hj.size()) != hipSuccess || hipMalloc(&p->tw, ht.size()) != hipSuccess) {
+    if (p->jtab) hipFree(p->jtab);
+    if (p->tw) hipFree(p->tw);
+    delete p;
+    (void)hipGetLastError();
+    return fail(MP3_ENOMEM, "device allocation of the plan tables failed");
+  }
+  hipError_t e1 = hipMemcpy(p->jtab, hj.data(), hj.size(), hipMemcpyHostToDevice);
+  hipError_t e2 = hipMemcpy(p->tw, ht.data(), ht.size(), hipMemcpyHostToDevice);
+  if (e1 != hipSuccess || e2 != hipSuccess) {
+    hipFree(p->jtab);
+    hipFree(p->tw);
+    delete p;
+    return hip_fail(e1 != hipSuccess ? e1 : e2, "upload plan tables");
+  }
+  *out = p;
+  return MP3_OK;
+}
+
+int mp3_profile(mp3_plan_t p, int enable) {
+  if (int s = check_plan(p)) return s;
+  collect_profile(p);
+  for (int i = 0; i < MP3_NPASS; ++i) {
+    p->prof_ms[i] = 0.0;
+    p->prof_n[i] = 0;
+  }
+  p->profile = enable != 0;
+  return MP3_OK;
+}
+
+int mp3_profile_read(mp3_plan_t p, int pass, double* total_ms, int64_t* launches) {
+  if (int s = check_plan(p)) return s;
+  if (pass < 0 || pass >= MP3_NPASS) return fail(MP3_EINVAL, "pass id out of range");
+  collect_profile(p);
+  if (total_ms) *total_ms = p->prof_ms[pass];
+  if (launches) *launches = p->prof_n[pass];
+  return MP3_OK;
+}
+
+int mp3_plan_destroy(mp3_plan_t p) {
+  if (!p) return MP3_OK;
+  collect_profile(p);
+  for (hipEvent_t e : p->pool) hipEventDestroy(e);
+  if (p->jtab) hipFree(p->jtab);
+  if (p->tw) hipFree(p->tw);
+  delete p;
+  return MP3_OK;
+}
+
+int mp3_plan_info(mp3_plan_t p, int32_t* n, int32_t* lmax, int32_t* nbins, int32_t* precision, int32_t* batch) {
+  if (int s = check_plan(p)) return s;
+  if (n) *n = p->n;
+  if (lmax) *lmax = p->lmax;
+  if (nbins) *nbins = p->nbins;
+  if (precision) *precision = p->prec;
+  if (batch) *batch = p->batch;
+  return MP3_OK;
+}
+
+int mp3_workspace_size(mp3_plan_t p, int64_t np_total, size_t* bytes) {
+  if (int s = check_plan(p)) return s;
+  if (!bytes) return fail(MP3_EINVAL, "bytes is NULL");
+  if (np_total < 0) return fail(MP3_EINVAL, "np_total must be >= 0");
+  *bytes = layout(p).total;
+  return MP3_OK;
+}
+
+int mp3_deposit(mp3_plan_t p, const float* pos, const float* w, const int64_t* np_off, void* delta, void* ws,
+                size_t wsb, void* stream) {
+  if (int s = check_plan(p)) return s;
+  long long np_total = 0, np_max = 0;
+  if (int s = check_offsets(p, np_off, &np_total, &np_max)) return s;
+  if (!pos) return fail(MP3_EINVAL, "pos is NULL");
+  if (!delta) return fail(MP3_EINVAL, "delta is NULL");
+  const Layout L = layout(p);
+  if (int s = check_ws(p, ws, wsb, L.total)) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const long long n3 = (long long)p->n * p->n * p->n;
+  if (int s = upload_offsets(p, np_off, ws, L, st)) return s;
+  const long long* off = reinterpret_cast<const long long*>(at(ws, L.off));
+  double* W = reinterpret_cast<double*>(at(ws, L.W));
+  MP3_HIP(mp3::launch_fill_f64(W, p->batch, 0.0, st), "zero W");
+  MP3_HIP(mp3::launch_weight_sum(w, off, p->batch, np_max, W, st), "weight sum");
+  MP3_HIP(mp3::launch_fill(p->prec, delta, n3 * p->batch, 0.0, st), "zero grid");
+  MP3_HIP(timed(p, MP3_PASS_DEPOSIT, st, [&] { return mp3::launch_deposit(p->prec, pos, w, off, p->batch, np_total, p->n, (double)p->n / p->box, delta, st); }), "deposit");
+  MP3_HIP(mp3::launch_normalise(p->prec, delta, W, n3, p->batch, st), "normalise");
+  return MP3_OK;
+}
+
+int mp3_multipole_fields(mp3_plan_t p, const void* delta, int32_t l, int32_t m, void* a_out, void* ws, size_t wsb,
+                         void* stream) {
+  if (int s = check_plan(p)) return s;
+  if (!delta || !a_out) return fail(MP3_EINVAL, "delta and a_out must not be NULL");
+  if (l < 0 || l > p->lmax || m < 0 || m > l) return fail(MP3_EINVAL, "need 0 <= m <= l <= lmax");
+  const Layout L = layout(p);
+  if (int s = check_ws(p, ws, wsb, L.total)) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int s = forward_dft(p, delta, ws, L, st)) return s;
+  if (int s = fields_xy(p, ws, L, a_out, l, m, st)) return s;
+  MP3_HIP(mp3::launch_fft_z(p->n, p->prec, +1, a_out, a_out, p->batch * p->nbins, p->tw, st), "z pass");
+  return MP3_OK;
+}
+
+int mp3_zeta(mp3_plan_t p, const void* delta, double* zeta, void* ws, size_t wsb, void* stream) {
+  if (int s = check_plan(p)) return s;
+  if (!delta || !zeta) return fail(MP3_EINVAL, "delta and zeta must not be NULL");
+  const Layout L = layout(p);
+  if (int s = check_ws(p, ws, wsb, L.total)) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int nb2 = p->nbins * p->nbins;
+  const double n3 = (double)p->n * p->n * p->n;
+  if (int s = forward_dft(p, delta, ws, L, st)) return s;
+  MP3_HIP(mp3::launch_fill_f64(zeta, (long long)p->batch * (p->lmax + 1) * nb2, 0.0, st), "zero zeta");
+  void* F = at(ws, L.fields);
+  double* partials = reinterpret_cast<double*>(at(ws, L.partials));
+  for (int l = 0; l <= p->lmax; ++l) {
+    for (int m = 0; m <= l; ++m) {
+      if (int s = fields_xy(p, ws, L, F, l, m, st)) return s;
+      mp3::ZpassArgs z{};
+      z.fields = F;
+      z.delta = delta;
+      z.partials = partials;
+      z.tw = p->tw;
+      z.nbins = p->nbins;
+      z.nwg = L.nwg;
+      z.ppw = L.ppw;
+      z.batch = p->batch;
+      z.l = l;
+      z.lmax = p->lmax;
+      MP3_HIP(timed(p, MP3_PASS_Z_NODAL, st, [&] { return mp3::launch_zpass_nodal(p->n, p->prec, z, st); }), "z pass (contraction)");
+      const double wm = m == 0 ? 1.0 : 2.0;
+      MP3_HIP(mp3::launch_reduce_partials(partials, L.nwg, nb2, zeta, l, p->lmax, wm * kFourPi / n3, p->batch, st),
+              "reduce");
+    }
+  }
+  return MP3_OK;
+}
+
+int mp3_zeta_backward(mp3_plan_t p, const void* delta, const double* dzeta, void* ddelta, const float* pos,
+                      const float* w, const int64_t* np_off, void* dw, void* ws, size_t wsb, void* stream) {
+  if (int s = check_plan(p)) return s;
+  if (!delta || !dzeta || !ddelta) return fail(MP3_EINVAL, "delta, dzeta and ddelta must not be NULL");
+  long long np_total = 0, np_max = 0;
+  if (dw) {
+    if (int s = check_offsets(p, np_off, &np_total, &np_max)) return s;
+    if (!pos) return fail(MP3_EINVAL, "pos is NULL while dw is requested");
+  }
+  const Layout L = layout(p);
+  if (int s = check_ws(p, ws, wsb, L.total)) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const long long n3 = (long long)p->n * p->n * p->n;
+  if (int s = forward_dft(p, delta, ws, L, st)) return s;
+  void* F = at(ws, L.fields);
+  void* G = at(ws, L.G);
+  void* direct = at(ws, L.direct);
+  MP3_HIP(mp3::launch_fill(p->prec, G, 2 * n3 * p->batch, 0.0, st), "zero G");
+  MP3_HIP(mp3::launch_fill(p->prec, direct, n3 * p->batch, 0.0, st), "zero direct");
+  for (int l = 0; l <= p->lmax; ++l) {
+    for (int m = 0; m <= l; ++m) {
+      const double wm = m == 0 ? 1.0 : 2.0;
+      if (int s = fields_xy(p, ws, L, F, l, m, st)) return s;
+      mp3::ZpassArgs z{};
+      z.fields = F;
+      z.delta = delta;
+      z.dzeta = dzeta;
+      z.direct = direct;
+      z.tw = p->tw;
+      z.nbins = p->nbins;
+      z.nwg = L.nwg;
+      z.ppw = L.ppw;
+      z.batch = p->batch;
+      z.l = l;
+      z.lmax = p->lmax;
+      z.wm = wm;
+      MP3_HIP(timed(p, MP3_PASS_Z_ADJOINT, st, [&] { return mp3::launch_zpass_adjoint(p->n, p->prec, z, st); }), "z pass (adjoint)");
+      MP3_HIP(timed(p, MP3_PASS_Y, st, [&] { return mp3::launch_fft_y(p->n, p->prec, +1, F, p->batch * p->nbins, p->tw, st); }), "adjoint y pass");
+      mp3::FilterArgs a = filter_args(p, F, G, l, m, wm / (double)n3);
+      MP3_HIP(timed(p, MP3_PASS_ADJOINT_X, st, [&] { return mp3::launch_adjoint_x(p->n, p->prec, a, st); }), "adjoint x pass");
+    }
+  }
+  MP3_HIP(timed(p, MP3_PASS_DFT, st, [&] { return mp3::launch_fft3d(p->n, p->prec, -1, false, G, G, p->batch, p->tw, st); }), "adjoint final FFT");
+  MP3_HIP(mp3::launch_grad_combine(p->prec, direct, G, ddelta, n3 * p->batch, kFourPi / (double)n3, st), "combine");
+  if (dw) {
+    if (int s = upload_offsets(p, np_off, ws, L, st)) return s;
+    const long long* off = reinterpret_cast<const long long*>(at(ws, L.off));
+    double* W = reinterpret_cast<double*>(at(ws, L.W));
+    double* S = reinterpret_cast<double*>(at(ws, L.S));
+    MP3_HIP(mp3::launch_fill_f64(W, p->batch, 0.0, st), "zero W");
+    MP3_HIP(mp3::launch_fill_f64(S, p->batch, 0.0, st), "zero S");
+    MP3_HIP(mp3::launch_weight_sum(w, off, p->batch, np_max, W, st), "weight sum");
+    MP3_HIP(mp3::launch_dot_rho_g(p->prec, delta, ddelta, n3, S, p->batch, st), "dot");
+    MP3_HIP(mp3::launch_gather_dw(p->prec, pos, off, p->batch, np_total, p->n, (double)p->n / p->box, ddelta, W, S, dw, st),
+            "gather dw");
+  }
+  return MP3_OK;
+}
+
+}  // extern "C"

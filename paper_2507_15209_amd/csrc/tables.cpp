@@ -1,0 +1,148 @@
+// tables.cpp -- float64 window tables generated at plan creation (host side).
+//
+// * Gauss-Legendre nodes by Newton iteration on P_n (three-term recurrence).
+// * Spherical Bessel functions j_0..j_L: upward recurrence from j_0, j_1 when
+//   x > L (stable there), Miller's downward recurrence normalised to j_0 when
+//   x <= L, exact values at x = 0.
+// * Bin-averaged j_l (the radial binning window applied to the secondary
+//   vertices of the multipole window, Sec. 2.2 around Eq. 3PCF-multipole-window):
+//     jbar_{l,b}(k) = 3 / (r_{b+1}^3 - r_b^3) int_{r_b}^{r_{b+1}} r^2 j_l(k r) dr,
+//   64-point Gauss-Legendre per bin, tabulated for every integer |q|^2 of the
+//   grid, k = (2 pi / box) sqrt(|q|^2).
+// * FFT twiddles exp(-2 pi i t / N).
+// * Normalisation of Y_lm: sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!).
+#include "tables.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <thread>
+#include <vector>
+
+namespace mp3 {
+
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      // p1 = P_n(z), p0 = P_{n-1}(z)
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+void sph_bessel_all(int L, double x, double* out) {
+  if (x == 0.0) {
+    out[0] = 1.0;
+    for (int l = 1; l <= L; ++l) out[l] = 0.0;
+    return;
+  }
+  const double s = std::sin(x), c = std::cos(x);
+  const double j0 = s / x;
+  if (L == 0) {
+    out[0] = j0;
+    return;
+  }
+  if (x > (double)L) {
+    out[0] = j0;
+    out[1] = s / (x * x) - c / x;
+    for (int l = 1; l < L; ++l) out[l + 1] = (2.0 * l + 1.0) / x * out[l] - out[l - 1];
+    return;
+  }
+  // Miller: start well above max(L, x) with (0, tiny) and recur downward.
+  const int lstart = L + 40 + (int)x;
+  double jp1 = 0.0, jl = 1e-280;
+  std::vector<double> tmp(L + 1);
+  double scale_acc = 1.0;
+  for (int l = lstart; l >= 1; --l) {
+    double jm1 = (2.0 * l + 1.0) / x * jl - jp1;
+    jp1 = jl;
+    jl = jm1;
+    if (l - 1 <= L) tmp[l - 1] = jl;
+    if (std::fabs(jl) > 1e250) {  // rescale to stay in range
+      jl *= 1e-250;
+      jp1 *= 1e-250;
+      for (int k = l - 1; k <= L; ++k) tmp[k] *= 1e-250;
+    }
+  }
+  (void)scale_acc;
+  const double norm = j0 / tmp[0];
+  for (int l = 0; l <= L; ++l) out[l] = tmp[l] * norm;
+}
+
+void jbar_table(int n, double box, int lmax, const std::vector<double>& edges, std::vector<double>& out) {
+  const int nbins = (int)edges.size() - 1;
+  const int nq2 = nq2_count(n);
+  out.assign((size_t)(lmax + 1) * nq2 * nbins, 0.0);
+  std::vector<double> xg, wg;
+  gauss_legendre(64, xg, wg);
+  const double kf = 2.0 * M_PI / box;
+  unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  auto work = [&](int tid) {
+    std::vector<double> jl(lmax + 1);
+    std::vector<double> acc((size_t)(lmax + 1));
+    for (int s = tid; s < nq2; s += (int)nthreads) {
+      const double k = kf * std::sqrt((double)s);
+      for (int b = 0; b < nbins; ++b) {
+        const double r1 = edges[b], r2 = edges[b + 1];
+        const double half = 0.5 * (r2 - r1), mid = 0.5 * (r2 + r1);
+        std::fill(acc.begin(), acc.end(), 0.0);
+        for (size_t g = 0; g < xg.size(); ++g) {
+          const double r = mid + half * xg[g];
+          sph_bessel_all(lmax, k * r, jl.data());
+          const double wr = half * wg[g] * r * r;
+          for (int l = 0; l <= lmax; ++l) acc[l] += wr * jl[l];
+        }
+        const double vol = 3.0 / (r2 * r2 * r2 - r1 * r1 * r1);
+        for (int l = 0; l <= lmax; ++l) out[((size_t)l * nq2 + s) * nbins + b] = acc[l] * vol;
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nthreads; ++t) th.emplace_back(work, (int)t);
+  for (auto& t : th) t.join();
+}
+
+void twiddles(int n, std::vector<double>& re, std::vector<double>& im) {
+  re.resize(n);
+  im.resize(n);
+  for (int t = 0; t < n; ++t) {
+    // exact values at the quarter points keep the table symmetric
+    const double a = -2.0 * M_PI * (double)t / (double)n;
+    re[t] = std::cos(a);
+    im[t] = std::sin(a);
+    if (4 * t == n) { re[t] = 0.0; im[t] = -1.0; }
+    if (2 * t == n) { re[t] = -1.0; im[t] = 0.0; }
+    if (4 * t == 3 * n) { re[t] = 0.0; im[t] = 1.0; }
+  }
+}
+
+double ylm_norm(int l, int m) {
+  // sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!) by a running product
+  double r = 1.0;
+  for (int k = l - m + 1; k <= l + m; ++k) r /= (double)k;
+  return std::sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * r);
+}
+
+}  // namespace mp3

@@ -1,0 +1,17 @@
+// tables.hpp -- host-side float64 table generation (see tables.cpp).
+#pragma once
+#include <vector>
+
+namespace mp3 {
+
+// number of distinct integer |q|^2 values tabulated: 0 .. 3 (N/2)^2
+inline int nq2_count(int n) { return 3 * (n / 2) * (n / 2) + 1; }
+
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+void sph_bessel_all(int L, double x, double* out);
+// [lmax+1][nq2][nbins]
+void jbar_table(int n, double box, int lmax, const std::vector<double>& edges, std::vector<double>& out);
+void twiddles(int n, std::vector<double>& re, std::vector<double>& im);
+double ylm_norm(int l, int m);
+
+}  // namespace mp3

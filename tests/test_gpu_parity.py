@@ -1,0 +1,232 @@
+"""GPU parity: the HIP path through the C ABI against the CPU float64 oracle.
+
+Bars: the float64 form within 1e-10 relative, the float32 form within 1e-4
+per multipole (see tests/_common.per_l_errors).  Inputs are seeded mocks and
+random fields from ``mockgen``; expected values come only from ``oracle``.
+"""
+import numpy as np
+import pytest
+
+from mockgen import random_field, lognormal_catalogue, WORKLOADS, workload_catalogue, batch_sizes
+from oracle import basis
+from oracle import estimator as E
+from oracle import adjoint as A
+from tests._common import assert_zeta_close, per_l_errors
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-10, "f32": 1e-4}
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def mp3():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_15209_amd as m
+    return m
+
+
+def _dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n,l,m,nb", [(16, 0, 0, 3), (16, 3, 2, 5), (32, 4, 4, 6), (64, 2, 1, 2), (128, 5, 3, 1)])
+def test_multipole_fields(mp3, prec, n, l, m, nb):
+    _say("fields", prec, n, l, m, nb)
+    box = 10.0 * n
+    edges = np.linspace(0.1 * box, 0.35 * box, nb + 1)
+    delta = random_field(n, 100 + n + l)
+    plan = mp3.Plan(n, box, max(l, 1), edges, precision=prec)
+    rd = torch.float64 if prec == "f64" else torch.float32
+    a = plan.multipole_fields(_dev(delta[None], rd), l, m).cpu().numpy()[0]
+    oplan = E.Plan(n, box, max(l, 1), edges)
+    ref = E.fields(oplan, np.fft.fftn(delta), l, m)
+    err = np.linalg.norm(a - ref) / np.linalg.norm(ref)
+    assert err < (1e-12 if prec == "f64" else 2e-6), err
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_deposit(mp3, prec):
+    _say("deposit", prec)
+    n, box = 32, 250.0
+    pos, w = lognormal_catalogue(n, box, 20000, 4.0, 1001, 1002, 1003, (0.5, 1.5))
+    plan = mp3.Plan(n, box, 1, [10.0, 20.0], precision=prec)
+    d = plan.deposit(_dev(pos, torch.float32), _dev(w, torch.float32)).cpu().numpy()[0]
+    ref = basis.density_contrast(basis.deposit(pos, w, n, box), float(np.sum(w.astype(np.float64))))
+    err = np.abs(d - ref).max() / np.abs(ref).max()
+    assert err < (1e-13 if prec == "f64" else 1e-6), err
+
+
+def test_deposit_wraps_edge_positions(mp3):
+    """Positions on the seam, at 0 and just below box, and outside [0, box) wrap periodically."""
+    _say("deposit seam")
+    n, box = 16, 100.0
+    pos = np.array([[0.0, 0.0, 0.0], [np.nextafter(np.float32(box), np.float32(0)), 50.0, 99.9],
+                    [6.25, 6.25, 6.25], [-3.0, 103.0, 250.0]], dtype=np.float32)
+    plan = mp3.Plan(n, box, 0, [10.0, 20.0], precision="f64")
+    d = plan.deposit(_dev(pos, torch.float32)).cpu().numpy()[0]
+    wrapped = np.mod(pos.astype(np.float64), box).astype(np.float32)
+    ref = basis.density_contrast(basis.deposit(wrapped, None, n, box), 4.0)
+    assert np.abs(d - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n,lmax,nb", [(16, 3, 4), (32, 4, 6), (64, 2, 5), (32, 6, 1)])
+def test_zeta_random_field(mp3, prec, n, lmax, nb):
+    _say("zeta random", prec, n, lmax, nb)
+    box = 8.0 * n
+    edges = np.linspace(0.05 * box, 0.4 * box, nb + 1)
+    delta = random_field(n, 7 + n + nb)
+    plan = mp3.Plan(n, box, lmax, edges, precision=prec)
+    rd = torch.float64 if prec == "f64" else torch.float32
+    z = plan.zeta(_dev(delta[None], rd)).cpu().numpy()[0]
+    ref = E.zeta_nodal(E.Plan(n, box, lmax, edges), delta)
+    e = assert_zeta_close(z, ref, TOL[prec])
+    print("per-l errors", e)
+    assert np.abs(z - z.transpose(0, 2, 1)).max() <= 1e-12 * np.abs(z).max()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_zeta_small_workload(mp3, prec):
+    """Box 250, 32^3, L = 4, 6 bins, 2000-particle log-normal mock: deposit + nodal zeta."""
+    wl = WORKLOADS["box250_n32_l4"]
+    _say("zeta workload", wl.name, prec)
+    pos, w = workload_catalogue(wl)
+    plan = mp3.Plan(wl.n, wl.box, wl.lmax, wl.edges, precision=prec)
+    delta = plan.deposit(_dev(pos, torch.float32), _dev(w, torch.float32))
+    z = plan.zeta(delta).cpu().numpy()[0]
+    dref = basis.density_contrast(basis.deposit(pos, w, wl.n, wl.box), float(len(w)))
+    ref = E.zeta_nodal(E.Plan(wl.n, wl.box, wl.lmax, wl.edges), dref)
+    e = assert_zeta_close(z, ref, TOL[prec])
+    print("per-l errors", e)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_zeta_batch_uneven(mp3, prec):
+    """Three mocks of uneven size in one call equal three separate oracle evaluations."""
+    _say("batch", prec)
+    n, box, lmax = 32, 500.0, 3
+    edges = np.linspace(30.0, 150.0, 5)
+    cats = [lognormal_catalogue(n, box, npart, 8.0, 5000 + 10 * j + 1, 5000 + 10 * j + 2)
+            for j, npart in enumerate((3000, 11000, 500))]
+    pos = np.concatenate([c[0] for c in cats])
+    w = np.concatenate([c[1] for c in cats])
+    off = np.cumsum([0] + [len(c[1]) for c in cats])
+    plan = mp3.Plan(n, box, lmax, edges, precision=prec, batch=3)
+    delta = plan.deposit(_dev(pos, torch.float32), _dev(w, torch.float32), off)
+    z = plan.zeta(delta).cpu().numpy()
+    op = E.Plan(n, box, lmax, edges)
+    for j, (p, ww) in enumerate(cats):
+        ref = E.zeta_nodal(op, basis.density_contrast(basis.deposit(p, ww, n, box), float(len(ww))))
+        assert_zeta_close(z[j], ref, TOL[prec])
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n,lmax,nb", [(16, 2, 3), (32, 3, 5)])
+def test_backward_delta_and_weights(mp3, prec, n, lmax, nb):
+    _say("backward", prec, n, lmax, nb)
+    box = 10.0 * n
+    edges = np.linspace(0.08 * box, 0.35 * box, nb + 1)
+    pos, w = lognormal_catalogue(n, box, 4000, 0.05 * box, 61, 62, 63, (0.5, 1.5))
+    lam = np.random.default_rng(64).standard_normal((lmax + 1, nb, nb))
+    plan = mp3.Plan(n, box, lmax, edges, precision=prec)
+    pt, wt = _dev(pos, torch.float32), _dev(w, torch.float32)
+    delta = plan.deposit(pt, wt)
+    dd, dw = plan.zeta_backward(delta, _dev(lam[None], torch.float64), pt, wt)
+    dref = basis.density_contrast(basis.deposit(pos, w, n, box), float(np.sum(w.astype(np.float64))))
+    op = E.Plan(n, box, lmax, edges)
+    gref = A.zeta_nodal_grad(op, dref, lam)
+    wref = A.deposit_weight_grad(pos, w, n, box, gref)
+    tol = 1e-10 if prec == "f64" else 1e-4
+    eg = np.linalg.norm(dd.cpu().numpy()[0] - gref) / np.linalg.norm(gref)
+    ew = np.linalg.norm(dw.cpu().numpy() - wref) / np.linalg.norm(wref)
+    print("grad errors", eg, ew)
+    assert eg < tol and ew < tol
+
+
+def test_backward_batch_autograd(mp3):
+    """torch.autograd through Zeta3PCF on a batch of two fields equals the oracle gradient."""
+    _say("autograd batch")
+    n, box, lmax = 16, 160.0, 2
+    edges = np.linspace(15.0, 55.0, 4)
+    d = np.stack([random_field(n, 71), random_field(n, 72)])
+    lam = np.random.default_rng(73).standard_normal((2, lmax + 1, 3, 3))
+    plan = mp3.Plan(n, box, lmax, edges, precision="f64", batch=2)
+    x = _dev(d, torch.float64).requires_grad_(True)
+    z = mp3.Zeta3PCF.apply(x, plan)
+    (z * _dev(lam, torch.float64)).sum().backward()
+    op = E.Plan(n, box, lmax, edges)
+    for j in range(2):
+        ref = A.zeta_nodal_grad(op, d[j], lam[j])
+        assert np.linalg.norm(x.grad[j].cpu().numpy() - ref) < 1e-10 * np.linalg.norm(ref)
+
+
+def test_weight_gradient_finite_difference_f64(mp3):
+    """Central differences of J(w) along seeded unit directions on the float64 GPU form."""
+    _say("fd weights")
+    n, box, lmax = 16, 160.0, 2
+    edges = np.linspace(15.0, 55.0, 4)
+    pos, w = lognormal_catalogue(n, box, 3000, 8.0, 81, 82, 83, (0.5, 1.5))
+    plan = mp3.Plan(n, box, lmax, edges, precision="f64")
+    lam = np.random.default_rng(84).standard_normal((1, lmax + 1, 3, 3))
+    lt = _dev(lam, torch.float64)
+    pt = _dev(pos, torch.float32)
+    w64 = w.astype(np.float64)
+
+    def J(wv):
+        wt = _dev(wv.astype(np.float32), torch.float32)
+        return float((plan.zeta(plan.deposit(pt, wt)) * lt).sum())
+
+    wt = _dev(w, torch.float32)
+    _, dw = plan.zeta_backward(plan.deposit(pt, wt), lt, pt, wt)
+    rng = np.random.default_rng(85)
+    v = rng.standard_normal(w.shape)
+    v /= np.linalg.norm(v)
+    h = 1e-3
+    # weights are float32 on the device: use the rounded perturbation actually applied
+    wp = (w64 + h * v).astype(np.float32).astype(np.float64)
+    wm = (w64 - h * v).astype(np.float32).astype(np.float64)
+    fd = (J(wp) - J(wm))
+    an = float(np.dot(dw.cpu().numpy(), wp - wm))
+    assert abs(fd - an) < 1e-5 * abs(an)
+
+
+def test_zeta_f32_matches_f64_form(mp3):
+    """Float32 form against the float64 GPU form on a 128^3 log-normal mock (L = 8, 12 bins)."""
+    wl = WORKLOADS["batch64_n128_l8"]
+    _say("f32 vs f64", wl.name)
+    pos, w = workload_catalogue(wl, 0)
+    res = {}
+    for prec in ("f32", "f64"):
+        plan = mp3.Plan(wl.n, wl.box, wl.lmax, wl.edges, precision=prec)
+        res[prec] = plan.zeta(plan.deposit(_dev(pos, torch.float32), _dev(w, torch.float32))).cpu().numpy()[0]
+        del plan
+        torch.cuda.empty_cache()
+    assert_zeta_close(res["f32"], res["f64"], 1e-4)
+
+
+def test_invalid_arguments_raise(mp3):
+    _say("invalid args")
+    plan = mp3.Plan(16, 100.0, 2, [10.0, 20.0, 30.0])
+    d = torch.zeros((1, 16, 16, 16), dtype=torch.float32, device="cuda")
+    with pytest.raises(mp3.Mp3Error):
+        plan.multipole_fields(d, 3, 0)
+    with pytest.raises(mp3.Mp3Error):
+        plan.multipole_fields(d, 1, 2)
+    pos = torch.zeros((4, 3), dtype=torch.float32, device="cuda")
+    b2 = mp3.Plan(16, 100.0, 1, [10.0, 20.0], batch=2)
+    with pytest.raises(mp3.Mp3Error):
+        b2.deposit(pos, None, [0, 4, 4])       # empty second mock
+    import ctypes
+    from paper_2507_15209_amd import _lib
+    z = torch.empty((1, 3, 2, 2), dtype=torch.float64, device="cuda")
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    st = plan.lib.mp3_zeta(plan._h, ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(z.data_ptr()),
+                           ctypes.c_void_p(ws.data_ptr()), 16, None)
+    assert st == _lib.MP3_EWORKSPACE
