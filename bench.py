@@ -40,11 +40,11 @@ def pass_bytes(name, n, nb, batch, real_bytes):
     n3 = float(n) ** 3 * batch
     c = 2 * real_bytes
     return {
-        "filter_x": n3 * c + nb * n3 * c,                                  # dhat in, nb fields out
-        "y": 2.0 * nb * n3 * c,                                            # nb fields in and out
+        "filter": n3 * c + nb * n3 * c,                                    # dhat in, nb fields out
+        "x": 2.0 * nb * n3 * c,                                            # nb fields in and out
         "z_nodal": nb * n3 * c + n3 * real_bytes,                          # nb fields + delta in
         "z_adjoint": 2.0 * nb * n3 * c + n3 * real_bytes + 2 * n3 * real_bytes,  # fields in/out, delta, direct rmw
-        "adjoint_x": nb * n3 * c + 2.0 * n3 * c,                           # nb sources in, G rmw
+        "adjoint": nb * n3 * c + 2.0 * n3 * c,                             # nb sources in, G rmw
     }.get(name)
 
 

@@ -143,11 +143,11 @@ int mp3_zeta_backward(mp3_plan_t plan, const void* delta, const double* dzeta,
 /* Pass identifiers for per-pass timing. */
 enum mp3_pass {
   MP3_PASS_DFT = 0,        /* forward 3-D DFT of delta; final DFT of the adjoint accumulator */
-  MP3_PASS_FILTER_X = 1,   /* window K_{lm,b} + x-transform, all bins (one launch per (l, m)) */
-  MP3_PASS_Y = 2,          /* y-transform of all bins                                          */
+  MP3_PASS_FILTER = 1,     /* window K_{lm,b} + y-transform, all bins (one launch per (l, m)) */
+  MP3_PASS_X = 2,          /* x-transform of all bins                                          */
   MP3_PASS_Z_NODAL = 3,    /* z-transform + nodal contraction                                  */
   MP3_PASS_Z_ADJOINT = 4,  /* z-transform + adjoint sources + their z-transform                */
-  MP3_PASS_ADJOINT_X = 5,  /* x-transform of the adjoint sources, window, bin sum into G       */
+  MP3_PASS_ADJOINT = 5,    /* y-transform of the adjoint sources, window, bin sum into G       */
   MP3_PASS_DEPOSIT = 6,    /* B-spline scatter of the catalogue                                */
   MP3_NPASS = 7
 };

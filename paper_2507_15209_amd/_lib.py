@@ -23,7 +23,7 @@ EXPORTS = (
     "mp3_multipole_fields", "mp3_zeta", "mp3_zeta_backward", "mp3_plan_info",
     "mp3_status_string", "mp3_last_error", "mp3_profile", "mp3_profile_read",
 )
-PASSES = ("dft", "filter_x", "y", "z_nodal", "z_adjoint", "adjoint_x", "deposit")
+PASSES = ("dft", "filter", "x", "z_nodal", "z_adjoint", "adjoint", "deposit")
 
 
 class PlanDesc(ctypes.Structure):

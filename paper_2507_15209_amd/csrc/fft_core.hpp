@@ -5,6 +5,7 @@
 // between radix stages (one LDS round trip per stage boundary).  Radix
 // sequences per length:
 //     16: {16}   32: {8,4}   64: {8,8}   128: {16,8}   256: {16,16}   512: {8,8,8}
+// and a low-register variant with radix <= 8 (see FftPlan).
 // The first stage always has radix RMAX, so a thread's first-stage inputs are
 // the strided elements j + r * (N / RMAX), r < RMAX, which is also the
 // coalesced order for global loads.  After the last stage, register e of
@@ -121,19 +122,27 @@ template <int R, int DIR, typename T> __device__ __forceinline__ void dft(c2<T>*
 // ---------------------------------------------------------------------------
 // per-length radix plans
 // ---------------------------------------------------------------------------
-template <int N> struct FftPlan;
-template <> struct FftPlan<16>  { static constexpr int RMAX = 16, S = 1; static constexpr int R[3] = {16, 1, 1}; };
-template <> struct FftPlan<32>  { static constexpr int RMAX = 8,  S = 2; static constexpr int R[3] = {8, 4, 1}; };
-template <> struct FftPlan<64>  { static constexpr int RMAX = 8,  S = 2; static constexpr int R[3] = {8, 8, 1}; };
-template <> struct FftPlan<128> { static constexpr int RMAX = 16, S = 2; static constexpr int R[3] = {16, 8, 1}; };
-template <> struct FftPlan<256> { static constexpr int RMAX = 16, S = 2; static constexpr int R[3] = {16, 16, 1}; };
-template <> struct FftPlan<512> { static constexpr int RMAX = 8,  S = 3; static constexpr int R[3] = {8, 8, 8}; };
+// Radix plans.  Variant V = 0 favours few stages (radix 16), V = 1 keeps at
+// most 8 values per thread (fewer registers, one more LDS exchange).
+template <int N, int V> struct FftPlan;
+template <> struct FftPlan<16, 0>  { static constexpr int RMAX = 16, S = 1; static constexpr int R[3] = {16, 1, 1}; };
+template <> struct FftPlan<32, 0>  { static constexpr int RMAX = 8,  S = 2; static constexpr int R[3] = {8, 4, 1}; };
+template <> struct FftPlan<64, 0>  { static constexpr int RMAX = 8,  S = 2; static constexpr int R[3] = {8, 8, 1}; };
+template <> struct FftPlan<128, 0> { static constexpr int RMAX = 16, S = 2; static constexpr int R[3] = {16, 8, 1}; };
+template <> struct FftPlan<256, 0> { static constexpr int RMAX = 16, S = 2; static constexpr int R[3] = {16, 16, 1}; };
+template <> struct FftPlan<512, 0> { static constexpr int RMAX = 8,  S = 3; static constexpr int R[3] = {8, 8, 8}; };
+template <> struct FftPlan<16, 1>  { static constexpr int RMAX = 4,  S = 2; static constexpr int R[3] = {4, 4, 1}; };
+template <> struct FftPlan<32, 1>  { static constexpr int RMAX = 8,  S = 2; static constexpr int R[3] = {8, 4, 1}; };
+template <> struct FftPlan<64, 1>  { static constexpr int RMAX = 8,  S = 2; static constexpr int R[3] = {8, 8, 1}; };
+template <> struct FftPlan<128, 1> { static constexpr int RMAX = 8,  S = 3; static constexpr int R[3] = {8, 4, 4}; };
+template <> struct FftPlan<256, 1> { static constexpr int RMAX = 8,  S = 3; static constexpr int R[3] = {8, 8, 4}; };
+template <> struct FftPlan<512, 1> { static constexpr int RMAX = 8,  S = 3; static constexpr int R[3] = {8, 8, 8}; };
 
-template <int N> struct Fft {
-  static constexpr int RMAX = FftPlan<N>::RMAX;
-  static constexpr int S = FftPlan<N>::S;
+template <int N, int V = 0> struct Fft {
+  static constexpr int RMAX = FftPlan<N, V>::RMAX;
+  static constexpr int S = FftPlan<N, V>::S;
   static constexpr int TPC = N / RMAX;                 // threads per column
-  static constexpr int RLAST = FftPlan<N>::R[S - 1];
+  static constexpr int RLAST = FftPlan<N, V>::R[S - 1];
   static constexpr int NSLAST = N / RLAST;
   // output index held in register e of thread j after the last stage
   __device__ __forceinline__ static int out_index(int j, int e) {
@@ -150,12 +159,12 @@ template <bool PAD> __device__ __forceinline__ int lds_pos(int i) { return PAD ?
 // One radix stage (compile-time stage index S_IDX, Ns = product of earlier
 // radices): twiddle, butterflies, and -- unless it is the last stage -- the
 // LDS exchange that gathers the next stage's inputs.
-template <int N, int S_IDX, int DIR, typename T, bool PAD>
+template <int N, int S_IDX, int DIR, typename T, bool PAD, int V>
 __device__ __forceinline__ void fft_stage(c2<T>* v, c2<T>* col, int ld, int j, const c2<T>* tw, bool active, int Ns) {
-  using F = Fft<N>;
+  using F = Fft<N, V>;
   constexpr int RMAX = F::RMAX;
   constexpr int TPC = F::TPC;
-  constexpr int R = FftPlan<N>::R[S_IDX];
+  constexpr int R = FftPlan<N, V>::R[S_IDX];
   constexpr int BPT = RMAX / R;
   if constexpr (S_IDX > 0) {
     if (active) {
@@ -181,7 +190,7 @@ __device__ __forceinline__ void fft_stage(c2<T>* v, c2<T>* col, int ld, int j, c
       }
     }
     __syncthreads();
-    constexpr int Rn = FftPlan<N>::R[S_IDX + 1];
+    constexpr int Rn = FftPlan<N, V>::R[S_IDX + 1];
     constexpr int BPTn = RMAX / Rn;
     if (active) {
 #pragma unroll
@@ -192,7 +201,7 @@ __device__ __forceinline__ void fft_stage(c2<T>* v, c2<T>* col, int ld, int j, c
       }
     }
     __syncthreads();
-    fft_stage<N, S_IDX + 1, DIR, T, PAD>(v, col, ld, j, tw, active, Ns * R);
+    fft_stage<N, S_IDX + 1, DIR, T, PAD, V>(v, col, ld, j, tw, active, Ns * R);
   }
 }
 
@@ -202,9 +211,9 @@ __device__ __forceinline__ void fft_stage(c2<T>* v, c2<T>* col, int ld, int j, c
 // Every thread of the workgroup must call this the same number of times
 // (it contains __syncthreads when N has more than one stage); threads without
 // a column pass active = false.
-template <int N, int DIR, typename T, bool PAD>
+template <int N, int DIR, typename T, bool PAD, int V = 0>
 __device__ __forceinline__ void fft_column(c2<T>* v, c2<T>* col, int ld, int j, const c2<T>* tw, bool active) {
-  fft_stage<N, 0, DIR, T, PAD>(v, col, ld, j, tw, active, 1);
+  fft_stage<N, 0, DIR, T, PAD, V>(v, col, ld, j, tw, active, 1);
 }
 
 }  // namespace mp3

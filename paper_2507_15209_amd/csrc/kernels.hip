@@ -4,17 +4,19 @@
 // (ix * N + iy) * N + iz, batches of fields contiguous.  The inverse 3-D
 // transform of each filtered field is done in three passes, one per axis:
 //
-//   pass x  (k_filter_x)   : k-space tile [qx column][16 or 8 contiguous qz] of
-//                            dhat read ONCE per (l, m); for every radial bin the
-//                            window K_{lm,b} is applied and the x-transform done;
-//                            writes field [x][qy][qz] per bin
-//   pass y  (k_fft_strided): y-transform in place           -> [x][y][qz]
+//   pass y  (k_filter_y)   : k-space tile [qy column][16 or 8 contiguous qz] of
+//                            dhat at fixed qx, read ONCE per (l, m); for every
+//                            radial bin the window K_{lm,b} is applied and the
+//                            y-transform done; writes field [qx][y][qz] per bin
+//   pass x  (k_fft_strided): x-transform in place           -> [x][y][qz]
 //   pass z  (k_zpass_*)    : per (x, y) pencil all bins are z-transformed into
 //                            LDS and consumed there: nodal contraction
 //                            (forward) or the adjoint source terms (backward)
 //
-// so a field element crosses HBM as: written by pass x, read+written by pass
-// y, read by pass z (32 bytes per complex64 element in the forward).
+// so a field element crosses HBM as: written by pass y, read+written by pass
+// x, read by pass z (32 bytes per complex64 element in the forward).  The
+// bin-looping kernels run along y, whose columns lie in one contiguous x-slab;
+// the 512 KB-strided x axis is left to the one-field-per-tile plain pass.
 #include "fft_core.hpp"
 #include "kernels.hpp"
 
@@ -25,8 +27,8 @@ namespace mp3 {
 // contiguous complex values per strided-pass row: 128 bytes
 template <typename T> constexpr int zc_of() { return 128 / (int)sizeof(c2<T>); }
 // columns-tiles per workgroup so that small lengths still fill >= 256 threads
-template <int N, typename T> constexpr int tiles_per_wg() {
-  constexpr int t = Fft<N>::TPC * zc_of<T>();
+template <int N, typename T, int V = 0> constexpr int tiles_per_wg() {
+  constexpr int t = Fft<N, V>::TPC * zc_of<T>();
   return t >= 256 ? 1 : 256 / t;
 }
 
@@ -38,7 +40,12 @@ template <int N, typename T> constexpr int contig_pencils() {
   return p < cap ? p : (cap < 1 ? 1 : cap);
 }
 
-template <int N, typename T> constexpr int strided_threads() { return Fft<N>::TPC * zc_of<T>() * tiles_per_wg<N, T>(); }
+template <int N, typename T, int V = 0> constexpr int strided_threads() {
+  return Fft<N, V>::TPC * zc_of<T>() * tiles_per_wg<N, T, V>();
+}
+// the multi-bin kernels (window pass, adjoint x pass, z passes) use the
+// low-register FFT plan
+constexpr int VB = 1;
 
 __device__ __forceinline__ int sfreq(int i, int n) { return i < n / 2 ? i : i - n; }
 
@@ -98,6 +105,19 @@ __device__ __forceinline__ c2<T> window_angular(int ix, int iy, int iz, int n, i
   if (qx == h || qy == h || qz == h) return mk<T>((T)0, (T)0);
   const double2 f = ylm_conj_il(qx, qy, qz, l, m, norm, scale);
   return mk<T>((T)f.x, (T)f.y);
+}
+
+// four consecutive radial-window values (the table's bin axis is padded to a
+// multiple of four and 16-byte aligned per |q|^2 row)
+template <typename T> __device__ __forceinline__ void load_quad(const T* p, T* o);
+template <> __device__ __forceinline__ void load_quad<float>(const float* p, float* o) {
+  const float4 q = *reinterpret_cast<const float4*>(p);
+  o[0] = q.x; o[1] = q.y; o[2] = q.z; o[3] = q.w;
+}
+template <> __device__ __forceinline__ void load_quad<double>(const double* p, double* o) {
+  const double2 a = reinterpret_cast<const double2*>(p)[0];
+  const double2 b = reinterpret_cast<const double2*>(p)[1];
+  o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
 }
 
 // ---------------------------------------------------------------------------
@@ -321,14 +341,17 @@ __global__ void __launch_bounds__((contig_pencils<N, T>() * Fft<N>::TPC)) k_fft_
 }
 
 // ---------------------------------------------------------------------------
-// pass x of the forward: window K_{lm,b} on the k-space tile, all bins
+// first pass of the forward: window K_{lm,b} on the k-space tile, all bins,
+// transform along y
 // ---------------------------------------------------------------------------
 template <int N, typename T>
-__global__ void __launch_bounds__((strided_threads<N, T>())) k_filter_x(const c2<T>* dhat, c2<T>* fields, const T* jtab, int nq2, int nbins,
-                                                    int l, int m, double norm, double scale, const c2<T>* tw) {
-  using F = Fft<N>;
+__global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_filter_y(const c2<T>* dhat, c2<T>* fields,
+                                                                         const T* jtab, int nq2, int nbins, int nbp,
+                                                                         int l, int m, double norm, double scale,
+                                                                         const c2<T>* tw) {
+  using F = Fft<N, VB>;
   constexpr int ZC = zc_of<T>();
-  constexpr int G = tiles_per_wg<N, T>();
+  constexpr int G = tiles_per_wg<N, T, VB>();
   constexpr int RMAX = F::RMAX;
   constexpr long long N3 = (long long)N * N * N;
   __shared__ c2<T> lds[G * N * ZC];
@@ -339,31 +362,50 @@ __global__ void __launch_bounds__((strided_threads<N, T>())) k_filter_x(const c2
   const int tile = blockIdx.x * G + g;
   constexpr int chunks = N / ZC;
   const bool active = tile < N * chunks;
-  const int qy = active ? tile / chunks : 0;
+  const int qx = active ? tile / chunks : 0;
   const int qz = (active ? tile % chunks : 0) * ZC + cc;
   const long long mock = blockIdx.y;
   c2<T> v0[RMAX];
   int q2[RMAX];
-  if (active) {
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r) {
-      const int qx = F::in_index(j, r);
-      const c2<T> d = dhat[mock * N3 + ((long long)qx * N + qy) * N + qz];
-      const c2<T> f = window_angular<T>(qx, qy, qz, N, l, m, norm, scale, q2[r]);
-      v0[r] = cmul<T>(d, f);
-    }
+  for (int r = 0; r < RMAX; ++r) {
+    const int qy = F::in_index(j, r);
+    const c2<T> d = active ? dhat[mock * N3 + ((long long)qx * N + qy) * N + qz] : mk<T>(0, 0);
+    const c2<T> f = window_angular<T>(qx, qy, qz, N, l, m, norm, scale, q2[r]);
+    v0[r] = cmul<T>(d, f);
   }
-  const T* jl = jtab + (long long)l * nq2 * nbins;
-  for (int b = 0; b < nbins; ++b) {
-    c2<T> v[RMAX];
+  // radial window of this thread's elements, four bins per load, one quad ahead
+  const T* jl = jtab + (long long)l * nq2 * nbp;
+  T jq[RMAX][4];
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r) v[r] = active ? cscale<T>(v0[r], jl[(long long)q2[r] * nbins + b]) : mk<T>(0, 0);
-    fft_column<N, +1, T, false>(v, lds + g * N * ZC + cc, ZC, j, tw, active);
-    if (active) {
-      c2<T>* out = fields + (mock * nbins + b) * N3 + (long long)qy * N + qz;
+  for (int r = 0; r < RMAX; ++r) load_quad<T>(jl + (long long)q2[r] * nbp, jq[r]);
+  c2<T>* fbase = fields + mock * nbins * N3 + (long long)qx * N * N + qz;
+  for (int bq = 0; bq < nbins; bq += 4) {
+    T jn[RMAX][4];
+    if (bq + 4 < nbins) {
 #pragma unroll
-      for (int e = 0; e < RMAX; ++e) out[(long long)F::out_index(j, e) * N * N] = v[e];
+      for (int r = 0; r < RMAX; ++r) load_quad<T>(jl + (long long)q2[r] * nbp + bq + 4, jn[r]);
     }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (bq + k < nbins) {
+        c2<T> v[RMAX];
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) v[r] = cscale<T>(v0[r], jq[r][k]);
+        int jj = j;
+        asm volatile("" : "+v"(jj));
+        fft_column<N, +1, T, false, VB>(v, lds + g * N * ZC + cc, ZC, jj, tw, active);
+        if (active) {
+          c2<T>* out = fbase + (bq + k) * N3;
+#pragma unroll
+          for (int e = 0; e < RMAX; ++e) out[F::out_index(jj, e) * N] = v[e];
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) jq[r][k] = jn[r][k];
   }
 }
 
@@ -388,35 +430,87 @@ struct PairBlocks {
   }
 };
 
+// Bins of a pencil are transformed in rounds of nbc = blockDim / TPC columns.
+template <int N>
+__device__ __forceinline__ int pencil_rounds(int nbins) {
+  const int nbc = blockDim.x / Fft<N, VB>::TPC;
+  return (nbins + nbc - 1) / nbc;
+}
+
+// Load round rr of a pencil: thread (bin b = rr * nbc + tid / TPC, j) loads its
+// column's first-stage elements.
+template <int N, typename T>
+__device__ __forceinline__ void load_pencil_round(const c2<T>* src, long long fstride, int nbins, int rr,
+                                                  c2<T>* v) {
+  using F = Fft<N, VB>;
+  const int nbc = blockDim.x / F::TPC;
+  const int b = rr * nbc + threadIdx.x / F::TPC;
+  const int j = threadIdx.x % F::TPC;
+  if (b < nbins) {
+#pragma unroll
+    for (int r = 0; r < F::RMAX; ++r) v[r] = src[b * fstride + F::in_index(j, r)];
+  }
+}
+
+// Up to two rounds are prefetched into registers (vpre) ahead of use.
+template <int N, typename T>
+__device__ __forceinline__ void prefetch_pencil(const c2<T>* src, long long fstride, int nbins,
+                                                c2<T> (*vpre)[Fft<N, VB>::RMAX]) {
+  const int rounds = pencil_rounds<N>(nbins);
+  load_pencil_round<N, T>(src, fstride, nbins, 0, vpre[0]);
+  if (rounds > 1) load_pencil_round<N, T>(src, fstride, nbins, 1, vpre[1]);
+}
+
+// the z-pass workgroup has at least N threads (zpass_threads), so thread
+// z = tid owns one value of a real pencil (DPRE = 1)
+constexpr int DPRE = 1;
+template <int N, typename T>
+__device__ __forceinline__ void prefetch_delta(const T* src, T* d) {
+#pragma unroll
+  for (int k = 0; k < DPRE; ++k) {
+    const int z = threadIdx.x + k * blockDim.x;
+    d[k] = z < N ? src[z] : (T)0;
+  }
+}
+
+// z-transform one round of bins of a pencil into LDS rows A[b] (padded).
+template <int N, typename T>
+__device__ __forceinline__ void transform_round(int nbins, int rr, c2<T>* v, c2<T>* A, const c2<T>* tw) {
+  using F = Fft<N, VB>;
+  constexpr int RS = N + N / 16;
+  const int nbc = blockDim.x / F::TPC;
+  int j = threadIdx.x % F::TPC;
+  // keep per-thread LDS index arithmetic inside the pencil loop: hoisting it
+  // out of the loop would pin dozens of registers for the whole kernel
+  asm volatile("" : "+v"(j));
+  const int b = rr * nbc + threadIdx.x / F::TPC;
+  const bool active = b < nbins;
+  fft_column<N, +1, T, true, VB>(v, A + (active ? b : 0) * RS, 1, j, tw, active);
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < F::RMAX; ++e) A[b * RS + lds_pos<true>(F::out_index(j, e))] = v[e];
+  }
+}
+
+// z-transform every bin of one pencil into LDS rows A[b]; rounds 0 and 1
+// come from the prefetched registers.
 template <int N, typename T>
 __device__ __forceinline__ void transform_pencil_bins(const c2<T>* src, long long fstride, int nbins, c2<T>* A,
-                                                      const c2<T>* tw) {
-  using F = Fft<N>;
-  constexpr int RS = N + N / 16;
-  const int tid = threadIdx.x;
-  const int nbc = blockDim.x / F::TPC;
-  const int j = tid % F::TPC;
-  const int rounds = (nbins + nbc - 1) / nbc;
-  for (int rr = 0; rr < rounds; ++rr) {
-    const int b = rr * nbc + tid / F::TPC;
-    const bool active = b < nbins;
-    c2<T> v[F::RMAX];
-    if (active) {
-#pragma unroll
-      for (int r = 0; r < F::RMAX; ++r) v[r] = src[b * fstride + F::in_index(j, r)];
-    }
-    fft_column<N, +1, T, true>(v, A + (active ? b : 0) * RS, 1, j, tw, active);
-    if (active) {
-#pragma unroll
-      for (int e = 0; e < F::RMAX; ++e) A[b * RS + lds_pos<true>(F::out_index(j, e))] = v[e];
-    }
+                                                      const c2<T>* tw, c2<T> (*vpre)[Fft<N, VB>::RMAX]) {
+  const int rounds = pencil_rounds<N>(nbins);
+  transform_round<N, T>(nbins, 0, vpre[0], A, tw);
+  if (rounds > 1) transform_round<N, T>(nbins, 1, vpre[1], A, tw);
+  for (int rr = 2; rr < rounds; ++rr) {
+    c2<T> v[Fft<N, VB>::RMAX];
+    load_pencil_round<N, T>(src, fstride, nbins, rr, v);
+    transform_round<N, T>(nbins, rr, v, A, tw);
   }
 }
 
 template <int N, typename T>
 __global__ void __launch_bounds__(512) k_zpass_nodal(const c2<T>* fields, const T* delta, double* partials, int nbins,
-                                                       int ppw, const c2<T>* tw) {
-  using F = Fft<N>;
+                                                      int ppw, const c2<T>* tw) {
+  using F = Fft<N, VB>;
   constexpr int RS = N + N / 16;
   constexpr long long N3 = (long long)N * N * N;
   extern __shared__ __align__(16) char smem[];
@@ -433,20 +527,35 @@ __global__ void __launch_bounds__(512) k_zpass_nodal(const c2<T>* fields, const 
     pb.block_of(item / pb.zch, bb1, bb2);
     zc = item % pb.zch;
   }
-  double acc[16];
+  // partial sums in the working precision over this workgroup's pencils;
+  // float64 across workgroups (k_reduce_partials)
+  T acc[16];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+  for (int i = 0; i < 16; ++i) acc[i] = (T)0;
 
   const int p0 = blockIdx.x * ppw;
   const int p1 = min(p0 + ppw, N * N);
+  const c2<T>* fmock = fields + mock * nbins * N3;
+  c2<T> vpre[2][F::RMAX];
+  T dpre[DPRE];
+  const T* dmock = delta + mock * N3;
+  if (p0 < p1) {
+    prefetch_pencil<N, T>(fmock + (long long)p0 * N, N3, nbins, vpre);
+    prefetch_delta<N, T>(dmock + (long long)p0 * N, dpre);
+  }
   for (int p = p0; p < p1; ++p) {
-    for (int z = tid; z < N; z += blockDim.x) dl[z] = delta[mock * N3 + (long long)p * N + z];
-    transform_pencil_bins<N, T>(fields + mock * nbins * N3 + (long long)p * N, N3, nbins, A, tw);
-    __syncthreads();
-    if (has_item) {
-      T a32[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) a32[i] = (T)0;
+    for (int k = 0; k < DPRE; ++k) {
+      const int z = tid + k * blockDim.x;
+      if (z < N) dl[z] = dpre[k];
+    }
+    transform_pencil_bins<N, T>(fmock + (long long)p * N, N3, nbins, A, tw, vpre);
+    __syncthreads();
+    if (p + 1 < p1) {
+      prefetch_pencil<N, T>(fmock + (long long)(p + 1) * N, N3, nbins, vpre);
+      prefetch_delta<N, T>(dmock + (long long)(p + 1) * N, dpre);
+    }
+    if (has_item) {
       const int b1o = 4 * bb1, b2o = 4 * bb2;
       for (int z = zc; z < N; z += pb.zch) {
         const T d = dl[z];
@@ -461,10 +570,8 @@ __global__ void __launch_bounds__(512) k_zpass_nodal(const c2<T>* fields, const 
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int k = 0; k < 4; ++k) a32[i * 4 + k] += x1[i].x * x2[k].x + x1[i].y * x2[k].y;
+          for (int k = 0; k < 4; ++k) acc[i * 4 + k] += x1[i].x * x2[k].x + x1[i].y * x2[k].y;
       }
-#pragma unroll
-      for (int i = 0; i < 16; ++i) acc[i] += (double)a32[i];
     }
     __syncthreads();
   }
@@ -472,7 +579,7 @@ __global__ void __launch_bounds__(512) k_zpass_nodal(const c2<T>* fields, const 
   double* red = reinterpret_cast<double*>(smem);
   if (has_item) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) red[item * 16 + i] = acc[i];
+    for (int i = 0; i < 16; ++i) red[item * 16 + i] = (double)acc[i];
   }
   __syncthreads();
   double* out = partials + ((long long)mock * gridDim.x + blockIdx.x) * nbins * nbins;
@@ -492,80 +599,104 @@ __global__ void __launch_bounds__(512) k_zpass_nodal(const c2<T>* fields, const 
   }
 }
 
-// zeta[j][l][e] += scale * sum_w partials[j][w][e]
+// zeta[j][l][e] += scale * sum_w partials[j][w][e]; one block per (e, j),
+// fixed summation order (deterministic)
 __global__ void k_reduce_partials(const double* partials, int nwg, int nb2, double* zeta, int l, int lmax, double scale) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double sh[32];
+  const int e = blockIdx.x;
   const int j = blockIdx.y;
-  if (e >= nb2) return;
   const double* p = partials + (long long)j * nwg * nb2 + e;
   double s = 0.0;
-  for (int w = 0; w < nwg; ++w) s += p[(long long)w * nb2];
-  zeta[((long long)j * (lmax + 1) + l) * nb2 + e] += scale * s;
+  for (int w = threadIdx.x; w < nwg; w += blockDim.x) s += p[(long long)w * nb2];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) zeta[((long long)j * (lmax + 1) + l) * nb2 + e] += scale * s;
 }
 
 // ---------------------------------------------------------------------------
-// backward pass z: recompute a_b on the pencil, form
+// backward pass z: recompute a_b on the pencil, then per z (one thread owns a
+// z column, so no atomics and no read/write hazards)
 //   u_b = sum_b' lam_s[b,b'] conj(a_b'),  direct += wm Re(sum_b a_b u_b),
-//   c_b = delta u_b, and z-transform c_b (the adjoint's first axis).
+//   c_b = delta u_b,
+// and z-transform every c_b (the adjoint's first axis), written over the field.
+// lam_s is read with wave-uniform indices (scalar loads).
 // ---------------------------------------------------------------------------
-template <int N, typename T>
-__global__ void __launch_bounds__(512) k_zpass_adjoint(c2<T>* fields, const T* delta, const double* dzeta, T* direct,
-                                                         int nbins, int l, int lmax, T wm, int ppw, const c2<T>* tw) {
-  using F = Fft<N>;
+template <int N, typename T, int MAXNB>
+__global__ void __launch_bounds__(512) k_zpass_adjoint(c2<T>* fields, const T* delta, const T* __restrict__ lam_s,
+                                                        T* direct, int nbins, T wm, int ppw, const c2<T>* tw) {
+  using F = Fft<N, VB>;
   constexpr int RS = N + N / 16;
   constexpr long long N3 = (long long)N * N * N;
   extern __shared__ __align__(16) char smem[];
   c2<T>* A = reinterpret_cast<c2<T>*>(smem);
-  T* dl = reinterpret_cast<T*>(A + nbins * RS);
-  T* dirz = dl + N;
-  T* lam = dirz + N;
   const int tid = threadIdx.x;
   const long long mock = blockIdx.y;
-  const double* dz = dzeta + ((long long)mock * (lmax + 1) + l) * nbins * nbins;
-  for (int t = tid; t < nbins * nbins; t += blockDim.x) {
-    const int b = t / nbins, bp = t % nbins;
-    lam[t] = (T)(0.5 * (dz[b * nbins + bp] + dz[bp * nbins + b]));
-  }
-  const int zb = max(1, (int)blockDim.x / nbins);
-  const int j = tid % F::TPC;
+  const T* lam = lam_s + mock * nbins * nbins;
   const int nbc = blockDim.x / F::TPC;
   const int p0 = blockIdx.x * ppw;
   const int p1 = min(p0 + ppw, N * N);
+  c2<T>* fmock = fields + mock * nbins * N3;
+  const T* dmock = delta + mock * N3;
+  T* rmock = direct + mock * N3;
+  c2<T> vpre[2][F::RMAX];
+  T dpre[DPRE], rpre[DPRE];
+  if (p0 < p1) {
+    prefetch_pencil<N, T>(fmock + (long long)p0 * N, N3, nbins, vpre);
+    prefetch_delta<N, T>(dmock + (long long)p0 * N, dpre);
+    prefetch_delta<N, T>(rmock + (long long)p0 * N, rpre);
+  }
   for (int p = p0; p < p1; ++p) {
-    const long long poff = mock * N3 + (long long)p * N;
-    for (int z = tid; z < N; z += blockDim.x) {
-      dl[z] = delta[poff + z];
-      dirz[z] = (T)0;
-    }
-    c2<T>* fbase = fields + mock * nbins * N3 + (long long)p * N;
-    transform_pencil_bins<N, T>(fbase, N3, nbins, A, tw);
+    c2<T>* fbase = fmock + (long long)p * N;
+    transform_pencil_bins<N, T>(fbase, N3, nbins, A, tw, vpre);
     __syncthreads();
-    for (int z0 = 0; z0 < N; z0 += zb) {
-      const int z = z0 + tid / nbins;
-      const int b = tid % nbins;
-      const bool ok = (tid < zb * nbins) && (z < N);
-      c2<T> c = mk<T>(0, 0);
-      if (ok) {
-        const int zp = lds_pos<true>(z);
-        T ur = 0, ui = 0;
-        for (int bp = 0; bp < nbins; ++bp) {
-          const c2<T> a = A[bp * RS + zp];
-          const T lv = lam[b * nbins + bp];
-          ur += lv * a.x;
-          ui -= lv * a.y;
-        }
-        const c2<T> ab = A[b * RS + zp];
-        atomicAdd(&dirz[z], ab.x * ur - ab.y * ui);
-        c = mk<T>(dl[z] * ur, dl[z] * ui);
-      }
-      __syncthreads();
-      if (ok) A[b * RS + lds_pos<true>(z)] = c;
-      __syncthreads();
+    T dcur[DPRE], rcur[DPRE];
+#pragma unroll
+    for (int k = 0; k < DPRE; ++k) {
+      dcur[k] = dpre[k];
+      rcur[k] = rpre[k];
     }
-    for (int z = tid; z < N; z += blockDim.x) direct[poff + z] += wm * dirz[z];
+    if (p + 1 < p1) {
+      prefetch_pencil<N, T>(fbase + N, N3, nbins, vpre);
+      prefetch_delta<N, T>(dmock + (long long)(p + 1) * N, dpre);
+      prefetch_delta<N, T>(rmock + (long long)(p + 1) * N, rpre);
+    }
+#pragma unroll
+    for (int k = 0; k < DPRE; ++k) {
+      const int z = tid + k * blockDim.x;
+      if (z >= N) continue;
+      const int zp = lds_pos<true>(z);
+      c2<T> u[MAXNB];
+#pragma unroll
+      for (int b = 0; b < MAXNB; ++b) u[b] = mk<T>(0, 0);
+      for (int bp = 0; bp < nbins; ++bp) {
+        const c2<T> a = A[bp * RS + zp];
+        const T* lrow = lam + bp * nbins;          // lam_s is symmetric: row bp = column bp
+#pragma unroll
+        for (int b = 0; b < MAXNB; ++b) {
+          if (b < nbins) {
+            const T lv = lrow[b];
+            u[b].x += lv * a.x;
+            u[b].y -= lv * a.y;
+          }
+        }
+      }
+      const T d = dcur[k];
+      T dir = 0;
+#pragma unroll
+      for (int b = 0; b < MAXNB; ++b) {
+        if (b < nbins) {
+          const c2<T> a = A[b * RS + zp];
+          dir += a.x * u[b].x - a.y * u[b].y;
+          A[b * RS + zp] = mk<T>(d * u[b].x, d * u[b].y);
+        }
+      }
+      rmock[(long long)p * N + z] = rcur[k] + wm * dir;
+    }
+    __syncthreads();
     // adjoint z-transform of every c_b, read from LDS, written over the field
     const int rounds = (nbins + nbc - 1) / nbc;
     for (int rr = 0; rr < rounds; ++rr) {
+      int j = tid % F::TPC;
+      asm volatile("" : "+v"(j));
       const int b = rr * nbc + tid / F::TPC;
       const bool active = b < nbins;
       c2<T> v[F::RMAX];
@@ -574,7 +705,7 @@ __global__ void __launch_bounds__(512) k_zpass_adjoint(c2<T>* fields, const T* d
         for (int r = 0; r < F::RMAX; ++r) v[r] = A[b * RS + lds_pos<true>(F::in_index(j, r))];
       }
       __syncthreads();
-      fft_column<N, +1, T, true>(v, A + (active ? b : 0) * RS, 1, j, tw, active);
+      fft_column<N, +1, T, true, VB>(v, A + (active ? b : 0) * RS, 1, j, tw, active);
       if (active) {
 #pragma unroll
         for (int e = 0; e < F::RMAX; ++e) fbase[b * N3 + F::out_index(j, e)] = v[e];
@@ -584,16 +715,29 @@ __global__ void __launch_bounds__(512) k_zpass_adjoint(c2<T>* fields, const T* d
   }
 }
 
+// lam_s[j][b][b'] = (dzeta[j][l][b][b'] + dzeta[j][l][b'][b]) / 2 for one l
+template <typename T>
+__global__ void k_lam_sym(const double* dzeta, T* lam_s, int nbins, int l, int lmax) {
+  const int j = blockIdx.y;
+  const double* dz = dzeta + ((long long)j * (lmax + 1) + l) * nbins * nbins;
+  for (int t = threadIdx.x; t < nbins * nbins; t += blockDim.x) {
+    const int b = t / nbins, bp = t % nbins;
+    lam_s[(long long)j * nbins * nbins + t] = (T)(0.5 * (dz[b * nbins + bp] + dz[bp * nbins + b]));
+  }
+}
+
 // ---------------------------------------------------------------------------
-// backward pass x: x-transform of every adjoint source c_b, times the window,
+// last adjoint pass: y-transform of every adjoint source c_b, times the window,
 // summed over bins and accumulated into G(q) (one read-modify-write per (l, m))
 // ---------------------------------------------------------------------------
 template <int N, typename T>
-__global__ void __launch_bounds__((strided_threads<N, T>())) k_adjoint_x(const c2<T>* fields, c2<T>* G, const T* jtab, int nq2, int nbins,
-                                                     int l, int m, double norm, double scale, const c2<T>* tw) {
-  using F = Fft<N>;
+__global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_adjoint_y(const c2<T>* fields, c2<T>* G,
+                                                                          const T* jtab, int nq2, int nbins, int nbp,
+                                                                          int l, int m, double norm, double scale,
+                                                                          const c2<T>* tw) {
+  using F = Fft<N, VB>;
   constexpr int ZC = zc_of<T>();
-  constexpr int GT = tiles_per_wg<N, T>();
+  constexpr int GT = tiles_per_wg<N, T, VB>();
   constexpr int RMAX = F::RMAX;
   constexpr long long N3 = (long long)N * N * N;
   __shared__ c2<T> lds[GT * N * ZC];
@@ -604,7 +748,7 @@ __global__ void __launch_bounds__((strided_threads<N, T>())) k_adjoint_x(const c
   const int tile = blockIdx.x * GT + g;
   constexpr int chunks = N / ZC;
   const bool active = tile < N * chunks;
-  const int qy = active ? tile / chunks : 0;
+  const int qx = active ? tile / chunks : 0;
   const int qz = (active ? tile % chunks : 0) * ZC + cc;
   const long long mock = blockIdx.y;
   c2<T> fac[RMAX], acc[RMAX];
@@ -612,31 +756,44 @@ __global__ void __launch_bounds__((strided_threads<N, T>())) k_adjoint_x(const c
 #pragma unroll
   for (int e = 0; e < RMAX; ++e) {
     acc[e] = mk<T>(0, 0);
-    fac[e] = active ? window_angular<T>(F::out_index(j, e), qy, qz, N, l, m, norm, scale, q2[e]) : mk<T>(0, 0);
-    if (!active) q2[e] = 0;
+    fac[e] = window_angular<T>(qx, F::out_index(j, e), qz, N, l, m, norm, scale, q2[e]);
   }
-  const T* jl = jtab + (long long)l * nq2 * nbins;
-  for (int b = 0; b < nbins; ++b) {
-    c2<T> v[RMAX];
-    if (active) {
-      const c2<T>* src = fields + (mock * nbins + b) * N3 + (long long)qy * N + qz;
+  const T* jl = jtab + (long long)l * nq2 * nbp;
+  const c2<T>* src = fields + mock * nbins * N3 + (long long)qx * N * N + qz;
+  // next bin's column, one bin ahead
+  c2<T> vn[RMAX];
+  if (active) {
 #pragma unroll
-      for (int r = 0; r < RMAX; ++r) v[r] = src[(long long)F::in_index(j, r) * N * N];
-    }
-    fft_column<N, +1, T, false>(v, lds + g * N * ZC + cc, ZC, j, tw, active);
-    if (active) {
+    for (int r = 0; r < RMAX; ++r) vn[r] = src[F::in_index(j, r) * N];
+  }
+  for (int bq = 0; bq < nbins; bq += 4) {
+    T jq[RMAX][4];
 #pragma unroll
-      for (int e = 0; e < RMAX; ++e) {
-        const c2<T> k = cscale<T>(fac[e], jl[(long long)q2[e] * nbins + b]);
-        acc[e] = cadd<T>(acc[e], cmul<T>(v[e], k));
+    for (int e = 0; e < RMAX; ++e) load_quad<T>(jl + (long long)q2[e] * nbp + bq, jq[e]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int b = bq + k;
+      if (b < nbins) {
+        c2<T> v[RMAX];
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) v[r] = vn[r];
+        if (b + 1 < nbins && active) {
+#pragma unroll
+          for (int r = 0; r < RMAX; ++r) vn[r] = src[(b + 1) * N3 + F::in_index(j, r) * N];
+        }
+        int jj = j;
+        asm volatile("" : "+v"(jj));
+        fft_column<N, +1, T, false, VB>(v, lds + g * N * ZC + cc, ZC, jj, tw, active);
+#pragma unroll
+        for (int e = 0; e < RMAX; ++e) acc[e] = cadd<T>(acc[e], cmul<T>(v[e], cscale<T>(fac[e], jq[e][k])));
       }
     }
   }
   if (active) {
-    c2<T>* dst = G + mock * N3 + (long long)qy * N + qz;
+    c2<T>* dst = G + mock * N3 + (long long)qx * N * N + qz;
 #pragma unroll
     for (int e = 0; e < RMAX; ++e) {
-      c2<T>* p = dst + (long long)F::out_index(j, e) * N * N;
+      c2<T>* p = dst + F::out_index(j, e) * N;
       *p = cadd<T>(*p, acc[e]);
     }
   }
@@ -695,6 +852,20 @@ hipError_t fft3d_t(int dir, bool real_in, const void* in, void* out, int nfields
 }
 
 template <int N, typename T>
+hipError_t fft_x_t(int dir, void* buf, int nfields, const void* tw, hipStream_t st) {
+  constexpr int ZC = zc_of<T>();
+  constexpr int G = tiles_per_wg<N, T>();
+  constexpr int threads = Fft<N>::TPC * ZC * G;
+  constexpr long long N3 = (long long)N * N * N;
+  const dim3 gs((N * (N / ZC) + G - 1) / G, nfields);
+  CT<T>* o = static_cast<CT<T>*>(buf);
+  const CT<T>* t = static_cast<const CT<T>*>(tw);
+  if (dir < 0) k_fft_strided<N, T, -1, false><<<gs, threads, 0, st>>>(o, o, N3, N3, N * N, N, t);
+  else k_fft_strided<N, T, +1, false><<<gs, threads, 0, st>>>(o, o, N3, N3, N * N, N, t);
+  return hipGetLastError();
+}
+
+template <int N, typename T>
 hipError_t fft_y_t(int dir, void* buf, int nfields, const void* tw, hipStream_t st) {
   constexpr int ZC = zc_of<T>();
   constexpr int G = tiles_per_wg<N, T>();
@@ -722,36 +893,40 @@ hipError_t fft_z_t(int dir, const void* in, void* out, int nfields, const void* 
 }
 
 template <int N, typename T>
-hipError_t filter_x_t(const FilterArgs& a, hipStream_t st) {
+hipError_t filter_y_t(const FilterArgs& a, hipStream_t st) {
   constexpr int ZC = zc_of<T>();
-  constexpr int G = tiles_per_wg<N, T>();
-  constexpr int threads = Fft<N>::TPC * ZC * G;
+  constexpr int G = tiles_per_wg<N, T, VB>();
+  constexpr int threads = Fft<N, VB>::TPC * ZC * G;
   const dim3 gs((N * (N / ZC) + G - 1) / G, a.batch);
-  k_filter_x<N, T><<<gs, threads, 0, st>>>(static_cast<const CT<T>*>(a.src), static_cast<CT<T>*>(a.dst),
-                                          static_cast<const T*>(a.jtab), a.nq2, a.nbins, a.l, a.m, a.norm, a.scale,
-                                          static_cast<const CT<T>*>(a.tw));
+  k_filter_y<N, T><<<gs, threads, 0, st>>>(static_cast<const CT<T>*>(a.src), static_cast<CT<T>*>(a.dst),
+                                          static_cast<const T*>(a.jtab), a.nq2, a.nbins, a.nbp, a.l, a.m, a.norm,
+                                          a.scale, static_cast<const CT<T>*>(a.tw));
   return hipGetLastError();
 }
 
 template <int N, typename T>
-hipError_t adjoint_x_t(const FilterArgs& a, hipStream_t st) {
+hipError_t adjoint_y_t(const FilterArgs& a, hipStream_t st) {
   constexpr int ZC = zc_of<T>();
-  constexpr int G = tiles_per_wg<N, T>();
-  constexpr int threads = Fft<N>::TPC * ZC * G;
+  constexpr int G = tiles_per_wg<N, T, VB>();
+  constexpr int threads = Fft<N, VB>::TPC * ZC * G;
   const dim3 gs((N * (N / ZC) + G - 1) / G, a.batch);
-  k_adjoint_x<N, T><<<gs, threads, 0, st>>>(static_cast<const CT<T>*>(a.src), static_cast<CT<T>*>(a.dst),
-                                           static_cast<const T*>(a.jtab), a.nq2, a.nbins, a.l, a.m, a.norm, a.scale,
-                                           static_cast<const CT<T>*>(a.tw));
+  k_adjoint_y<N, T><<<gs, threads, 0, st>>>(static_cast<const CT<T>*>(a.src), static_cast<CT<T>*>(a.dst),
+                                           static_cast<const T*>(a.jtab), a.nq2, a.nbins, a.nbp, a.l, a.m, a.norm,
+                                           a.scale, static_cast<const CT<T>*>(a.tw));
   return hipGetLastError();
 }
 
+// z-pass workgroup: nbc columns (bins) per round, rounds balanced, <= 512 threads
 template <int N> inline int zpass_threads(int nbins) {
-  constexpr int TPC = Fft<N>::TPC;
-  int nbc = nbins;
-  const int lo = TPC >= 64 ? 1 : 64 / TPC;
+  constexpr int TPC = Fft<N, VB>::TPC;
   const int hi = 512 / TPC;
+  const int rounds = (nbins + hi - 1) / hi;
+  int nbc = (nbins + rounds - 1) / rounds;
+  int lo = TPC >= 64 ? 1 : 64 / TPC;
+  const int lo_delta = (N / DPRE + TPC - 1) / TPC;   // at least N / DPRE threads
+  if (lo < lo_delta) lo = lo_delta;
+  if (lo > hi) lo = hi;
   if (nbc < lo) nbc = lo;
-  if (nbc > hi) nbc = hi;
   return nbc * TPC;
 }
 
@@ -764,7 +939,7 @@ template <int N, typename T> inline size_t zpass_nodal_lds(int nbins, int thread
 
 template <int N, typename T> inline size_t zpass_adjoint_lds(int nbins) {
   constexpr int RS = N + N / 16;
-  return (size_t)nbins * RS * sizeof(CT<T>) + 2 * (size_t)N * sizeof(T) + (size_t)nbins * nbins * sizeof(T);
+  return (size_t)nbins * RS * sizeof(CT<T>);
 }
 
 template <typename K> hipError_t allow_lds(K kernel, size_t bytes) {
@@ -784,17 +959,30 @@ hipError_t zpass_nodal_t(const ZpassArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int N, typename T>
-hipError_t zpass_adjoint_t(const ZpassArgs& a, hipStream_t st) {
+template <int N, typename T, int MAXNB>
+hipError_t zpass_adjoint_nb(const ZpassArgs& a, hipStream_t st) {
   const int threads = zpass_threads<N>(a.nbins);
   const size_t lds = zpass_adjoint_lds<N, T>(a.nbins);
-  hipError_t e = allow_lds(k_zpass_adjoint<N, T>, lds);
+  hipError_t e = allow_lds(k_zpass_adjoint<N, T, MAXNB>, lds);
   if (e != hipSuccess) return e;
   const dim3 gs(a.nwg, a.batch);
-  k_zpass_adjoint<N, T><<<gs, threads, lds, st>>>(static_cast<CT<T>*>(const_cast<void*>(a.fields)),
-                                                 static_cast<const T*>(a.delta), a.dzeta, static_cast<T*>(a.direct),
-                                                 a.nbins, a.l, a.lmax, (T)a.wm, a.ppw, static_cast<const CT<T>*>(a.tw));
+  k_zpass_adjoint<N, T, MAXNB><<<gs, threads, lds, st>>>(static_cast<CT<T>*>(const_cast<void*>(a.fields)),
+                                                        static_cast<const T*>(a.delta), static_cast<const T*>(a.lam),
+                                                        static_cast<T*>(a.direct), a.nbins, (T)a.wm, a.ppw,
+                                                        static_cast<const CT<T>*>(a.tw));
   return hipGetLastError();
+}
+
+template <int N, typename T>
+hipError_t zpass_adjoint_t(const ZpassArgs& a, hipStream_t st) {
+  if (a.nbins <= 8) return zpass_adjoint_nb<N, T, 8>(a, st);
+  if (a.nbins <= 12) return zpass_adjoint_nb<N, T, 12>(a, st);
+  if (a.nbins <= 16) return zpass_adjoint_nb<N, T, 16>(a, st);
+  if (a.nbins <= 20) return zpass_adjoint_nb<N, T, 20>(a, st);
+  if (a.nbins <= 24) return zpass_adjoint_nb<N, T, 24>(a, st);
+  if (a.nbins <= 32) return zpass_adjoint_nb<N, T, 32>(a, st);
+  if (a.nbins <= 48) return zpass_adjoint_nb<N, T, 48>(a, st);
+  return zpass_adjoint_nb<N, T, 64>(a, st);
 }
 
 template <int N, typename T> size_t zpass_lds_need_t(int nbins) {
@@ -824,6 +1012,10 @@ hipError_t launch_fft3d(int n, int prec, int dir, bool real_in, const void* in, 
   MP3_DISPATCH(fft3d_t, n, prec, dir, real_in, in, out, nfields, tw, st);
 }
 
+hipError_t launch_fft_x(int n, int prec, int dir, void* buf, int nfields, const void* tw, hipStream_t st) {
+  MP3_DISPATCH(fft_x_t, n, prec, dir, buf, nfields, tw, st);
+}
+
 hipError_t launch_fft_y(int n, int prec, int dir, void* buf, int nfields, const void* tw, hipStream_t st) {
   MP3_DISPATCH(fft_y_t, n, prec, dir, buf, nfields, tw, st);
 }
@@ -832,8 +1024,8 @@ hipError_t launch_fft_z(int n, int prec, int dir, const void* in, void* out, int
   MP3_DISPATCH(fft_z_t, n, prec, dir, in, out, nfields, tw, st);
 }
 
-hipError_t launch_filter_x(int n, int prec, const FilterArgs& a, hipStream_t st) { MP3_DISPATCH(filter_x_t, n, prec, a, st); }
-hipError_t launch_adjoint_x(int n, int prec, const FilterArgs& a, hipStream_t st) { MP3_DISPATCH(adjoint_x_t, n, prec, a, st); }
+hipError_t launch_filter_y(int n, int prec, const FilterArgs& a, hipStream_t st) { MP3_DISPATCH(filter_y_t, n, prec, a, st); }
+hipError_t launch_adjoint_y(int n, int prec, const FilterArgs& a, hipStream_t st) { MP3_DISPATCH(adjoint_y_t, n, prec, a, st); }
 hipError_t launch_zpass_nodal(int n, int prec, const ZpassArgs& a, hipStream_t st) { MP3_DISPATCH(zpass_nodal_t, n, prec, a, st); }
 hipError_t launch_zpass_adjoint(int n, int prec, const ZpassArgs& a, hipStream_t st) { MP3_DISPATCH(zpass_adjoint_t, n, prec, a, st); }
 
@@ -862,9 +1054,17 @@ hipError_t launch_fill_f64(double* p, long long count, double value, hipStream_t
   return hipGetLastError();
 }
 
+hipError_t launch_lam_sym(int prec, const double* dzeta, void* lam_s, int nbins, int l, int lmax, int batch,
+                          hipStream_t st) {
+  const dim3 gs(1, batch);
+  if (prec) k_lam_sym<double><<<gs, 256, 0, st>>>(dzeta, static_cast<double*>(lam_s), nbins, l, lmax);
+  else k_lam_sym<float><<<gs, 256, 0, st>>>(dzeta, static_cast<float*>(lam_s), nbins, l, lmax);
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce_partials(const double* partials, int nwg, int nb2, double* zeta, int l, int lmax, double scale,
                                   int batch, hipStream_t st) {
-  const dim3 gs((nb2 + 255) / 256, batch);
+  const dim3 gs(nb2, batch);
   k_reduce_partials<<<gs, 256, 0, st>>>(partials, nwg, nb2, zeta, l, lmax, scale);
   return hipGetLastError();
 }

@@ -6,11 +6,11 @@
 namespace mp3 {
 
 struct FilterArgs {
-  const void* src;   // k_filter_x: dhat [batch][N^3]; k_adjoint_x: sources [batch][nbins][N^3]
-  void* dst;         // k_filter_x: fields [batch][nbins][N^3]; k_adjoint_x: accumulator G [batch][N^3]
-  const void* jtab;  // [lmax+1][nq2][nbins] radial window
+  const void* src;   // k_filter_y: dhat [batch][N^3]; k_adjoint_y: sources [batch][nbins][N^3]
+  void* dst;         // k_filter_y: fields [batch][nbins][N^3]; k_adjoint_y: accumulator G [batch][N^3]
+  const void* jtab;  // [lmax+1][nq2][nbp] radial window, bin axis padded to nbp = 4 ceil(nbins / 4)
   const void* tw;    // twiddles exp(-2 pi i t / N)
-  int nq2, nbins, l, m, batch;
+  int nq2, nbins, nbp, l, m, batch;
   double norm;       // Y_lm normalisation
   double scale;      // extra real factor (1/N^3, times the m weight in the adjoint)
 };
@@ -21,6 +21,7 @@ struct ZpassArgs {
   double* partials;     // forward: [batch][nwg][nbins^2]
   const double* dzeta;  // backward: [batch][lmax+1][nbins^2]
   void* direct;         // backward: [batch][N^3] explicit-primary gradient accumulator
+  const void* lam;      // backward: symmetrised dzeta of this l, [batch][nbins^2] real
   const void* tw;
   int nbins, nwg, ppw, batch, l, lmax;
   double wm;            // m weight (1 for m = 0, 2 otherwise)
@@ -28,15 +29,18 @@ struct ZpassArgs {
 
 hipError_t launch_fft3d(int n, int prec, int dir, bool real_in, const void* in, void* out, int nfields, const void* tw,
                         hipStream_t st);
+hipError_t launch_fft_x(int n, int prec, int dir, void* buf, int nfields, const void* tw, hipStream_t st);
 hipError_t launch_fft_y(int n, int prec, int dir, void* buf, int nfields, const void* tw, hipStream_t st);
 hipError_t launch_fft_z(int n, int prec, int dir, const void* in, void* out, int nfields, const void* tw, hipStream_t st);
-hipError_t launch_filter_x(int n, int prec, const FilterArgs& a, hipStream_t st);
-hipError_t launch_adjoint_x(int n, int prec, const FilterArgs& a, hipStream_t st);
+hipError_t launch_filter_y(int n, int prec, const FilterArgs& a, hipStream_t st);
+hipError_t launch_adjoint_y(int n, int prec, const FilterArgs& a, hipStream_t st);
 hipError_t launch_zpass_nodal(int n, int prec, const ZpassArgs& a, hipStream_t st);
 hipError_t launch_zpass_adjoint(int n, int prec, const ZpassArgs& a, hipStream_t st);
 size_t zpass_lds_need(int n, int prec, int nbins);
 hipError_t launch_fill(int prec, void* p, long long count, double value, hipStream_t st);
 hipError_t launch_fill_f64(double* p, long long count, double value, hipStream_t st);
+hipError_t launch_lam_sym(int prec, const double* dzeta, void* lam_s, int nbins, int l, int lmax, int batch,
+                          hipStream_t st);
 hipError_t launch_reduce_partials(const double* partials, int nwg, int nb2, double* zeta, int l, int lmax, double scale,
                                   int batch, hipStream_t st);
 hipError_t launch_weight_sum(const float* w, const long long* off, int batch, long long np_max, double* W, hipStream_t st);

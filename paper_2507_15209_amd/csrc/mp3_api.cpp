@@ -16,8 +16,8 @@ struct mp3_plan_s {
   int n = 0, lmax = 0, nbins = 0, prec = 0, summation = 0, batch = 1;
   double box = 0.0;
   std::vector<double> edges;
-  int nq2 = 0;
-  void* jtab = nullptr;  // [lmax+1][nq2][nbins] real
+  int nq2 = 0, nbp = 0;
+  void* jtab = nullptr;  // [lmax+1][nq2][nbp] real, bin axis zero-padded to a multiple of 4
   void* tw = nullptr;    // [n] complex
   size_t elt = 4, celt = 8;
   int device = 0;
@@ -57,7 +57,7 @@ constexpr int kTargetWorkgroups = 4096;
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t off, W, S, dhat, fields, partials, G, direct, total;
+  size_t off, W, S, dhat, fields, partials, G, direct, lam, total;
   int nwg, ppw;
 };
 
@@ -85,6 +85,7 @@ Layout layout(const mp3_plan_s* p) {
   L.partials = take(B * (size_t)L.nwg * p->nbins * p->nbins * sizeof(double));
   L.G = take(B * n3 * p->celt);
   L.direct = take(B * n3 * p->elt);
+  L.lam = take(B * (size_t)p->nbins * p->nbins * p->elt);
   L.total = o;
   return L;
 }
@@ -176,6 +177,7 @@ mp3::FilterArgs filter_args(const mp3_plan_s* p, const void* src, void* dst, int
   a.jtab = p->jtab;
   a.tw = p->tw;
   a.nq2 = p->nq2;
+  a.nbp = p->nbp;
   a.nbins = p->nbins;
   a.l = l;
   a.m = m;
@@ -185,12 +187,12 @@ mp3::FilterArgs filter_args(const mp3_plan_s* p, const void* src, void* dst, int
   return a;
 }
 
-// fields of (l, m) after the x and y passes: layout [batch][nbins][x][y][qz]
+// fields of (l, m) after the y and x passes: layout [batch][nbins][x][y][qz]
 int fields_xy(const mp3_plan_s* p, void* ws, const Layout& L, void* dst, int l, int m, hipStream_t st) {
   const double n3 = (double)p->n * p->n * p->n;
   mp3::FilterArgs a = filter_args(p, at(ws, L.dhat), dst, l, m, 1.0 / n3);
-  MP3_HIP(timed(p, MP3_PASS_FILTER_X, st, [&] { return mp3::launch_filter_x(p->n, p->prec, a, st); }), "filter pass");
-  MP3_HIP(timed(p, MP3_PASS_Y, st, [&] { return mp3::launch_fft_y(p->n, p->prec, +1, dst, p->batch * p->nbins, p->tw, st); }), "y pass");
+  MP3_HIP(timed(p, MP3_PASS_FILTER, st, [&] { return mp3::launch_filter_y(p->n, p->prec, a, st); }), "window pass");
+  MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, dst, p->batch * p->nbins, p->tw, st); }), "x pass");
   return MP3_OK;
 }
 
@@ -240,6 +242,7 @@ int mp3_plan_create(const mp3_plan_desc* d, mp3_plan_t* out) {
   p->batch = d->batch;
   p->edges.assign(d->edges, d->edges + d->nbins + 1);
   p->nq2 = mp3::nq2_count(p->n);
+  p->nbp = (p->nbins + 3) / 4 * 4;
   p->elt = p->prec ? sizeof(double) : sizeof(float);
   p->celt = 2 * p->elt;
   hipGetDevice(&p->device);
@@ -248,10 +251,15 @@ int mp3_plan_create(const mp3_plan_desc* d, mp3_plan_t* out) {
   mp3::jbar_table(p->n, p->box, p->lmax, p->edges, jt);
   std::vector<double> twr, twi;
   mp3::twiddles(p->n, twr, twi);
-  std::vector<char> hj(jt.size() * p->elt), ht((size_t)p->n * p->celt);
-  for (size_t i = 0; i < jt.size(); ++i) {
-    if (p->prec) reinterpret_cast<double*>(hj.data())[i] = jt[i];
-    else reinterpret_cast<float*>(hj.data())[i] = (float)jt[i];
+  const size_t rows = (size_t)(p->lmax + 1) * p->nq2;
+  std::vector<char> hj(rows * p->nbp * p->elt, 0), ht((size_t)p->n * p->celt);
+  for (size_t rw = 0; rw < rows; ++rw) {
+    for (int b = 0; b < p->nbins; ++b) {
+      const double v = jt[rw * p->nbins + b];
+      const size_t i = rw * p->nbp + b;
+      if (p->prec) reinterpret_cast<double*>(hj.data())[i] = v;
+      else reinterpret_cast<float*>(hj.data())[i] = (float)v;
+    }
   }
   for (int i = 0; i < p->n; ++i) {
     if (p->prec) {
@@ -422,11 +430,14 @@ int mp3_zeta_backward(mp3_plan_t p, const void* delta, const double* dzeta, void
   for (int l = 0; l <= p->lmax; ++l) {
     for (int m = 0; m <= l; ++m) {
       const double wm = m == 0 ? 1.0 : 2.0;
+      if (m == 0)
+        MP3_HIP(mp3::launch_lam_sym(p->prec, dzeta, at(ws, L.lam), p->nbins, l, p->lmax, p->batch, st), "lambda");
       if (int s = fields_xy(p, ws, L, F, l, m, st)) return s;
       mp3::ZpassArgs z{};
       z.fields = F;
       z.delta = delta;
       z.dzeta = dzeta;
+      z.lam = at(ws, L.lam);
       z.direct = direct;
       z.tw = p->tw;
       z.nbins = p->nbins;
@@ -437,9 +448,9 @@ int mp3_zeta_backward(mp3_plan_t p, const void* delta, const double* dzeta, void
       z.lmax = p->lmax;
       z.wm = wm;
       MP3_HIP(timed(p, MP3_PASS_Z_ADJOINT, st, [&] { return mp3::launch_zpass_adjoint(p->n, p->prec, z, st); }), "z pass (adjoint)");
-      MP3_HIP(timed(p, MP3_PASS_Y, st, [&] { return mp3::launch_fft_y(p->n, p->prec, +1, F, p->batch * p->nbins, p->tw, st); }), "adjoint y pass");
+      MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, F, p->batch * p->nbins, p->tw, st); }), "adjoint x pass");
       mp3::FilterArgs a = filter_args(p, F, G, l, m, wm / (double)n3);
-      MP3_HIP(timed(p, MP3_PASS_ADJOINT_X, st, [&] { return mp3::launch_adjoint_x(p->n, p->prec, a, st); }), "adjoint x pass");
+      MP3_HIP(timed(p, MP3_PASS_ADJOINT, st, [&] { return mp3::launch_adjoint_y(p->n, p->prec, a, st); }), "adjoint window pass");
     }
   }
   MP3_HIP(timed(p, MP3_PASS_DFT, st, [&] { return mp3::launch_fft3d(p->n, p->prec, -1, false, G, G, p->batch, p->tw, st); }), "adjoint final FFT");
