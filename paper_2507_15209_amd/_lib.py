@@ -54,11 +54,14 @@ def _status_name(s: int) -> str:
     return _lib.mp3_status_string(s).decode()
 
 
-def load(path: str = LIB_PATH) -> ctypes.CDLL:
-    """Load libmp3.so; raises if it has not been built (there is no fallback path)."""
+def load(path: str | None = None) -> ctypes.CDLL:
+    """Load libmp3.so; raises if it has not been built (there is no fallback path).
+
+    MP3_LIBRARY may name another build of the same library (A/B timing)."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or os.environ.get("MP3_LIBRARY") or LIB_PATH
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it first (python -m paper_2507_15209_amd.build)")
     lib = ctypes.CDLL(path)

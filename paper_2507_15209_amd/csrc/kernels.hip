@@ -22,6 +22,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace mp3 {
 
 // contiguous complex values per strided-pass row: 128 bytes
@@ -32,9 +34,13 @@ template <int N, typename T, int V = 0> constexpr int tiles_per_wg() {
   return t >= 256 ? 1 : 256 / t;
 }
 
+// LDS row stride (in complex elements) of a padded pencil: N plus one pad per
+// 16 elements plus one, odd so that consecutive rows start in different banks
+template <int N> constexpr int zrow() { return N + N / 16 + 1; }
+
 // pencils per workgroup of the contiguous pass: fill 256 threads within 32 KB of LDS
 template <int N, typename T> constexpr int contig_pencils() {
-  constexpr int byt = (N + N / 16) * (int)sizeof(c2<T>);
+  constexpr int byt = zrow<N>() * (int)sizeof(c2<T>);
   constexpr int p = Fft<N>::TPC >= 256 ? 1 : 256 / Fft<N>::TPC;
   constexpr int cap = 32768 / byt;
   return p < cap ? p : (cap < 1 ? 1 : cap);
@@ -43,9 +49,11 @@ template <int N, typename T> constexpr int contig_pencils() {
 template <int N, typename T, int V = 0> constexpr int strided_threads() {
   return Fft<N, V>::TPC * zc_of<T>() * tiles_per_wg<N, T, V>();
 }
-// the multi-bin kernels (window pass, adjoint x pass, z passes) use the
-// low-register FFT plan
+// plan variants by kernel (measured): radix 8 for the window passes and the
+// nodal z pass, radix 16 for the adjoint z pass
 constexpr int VB = 1;
+constexpr int VZN = 1;   // nodal z pass
+constexpr int VZA = 0;   // adjoint z pass
 
 __device__ __forceinline__ int sfreq(int i, int n) { return i < n / 2 ? i : i - n; }
 
@@ -118,6 +126,12 @@ template <> __device__ __forceinline__ void load_quad<double>(const double* p, d
   const double2 a = reinterpret_cast<const double2*>(p)[0];
   const double2 b = reinterpret_cast<const double2*>(p)[1];
   o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+}
+
+// copy the N twiddles to LDS (the multi-bin kernels reuse them for every bin)
+template <int N, typename T>
+__device__ __forceinline__ void stage_twiddles(const c2<T>* tw, c2<T>* tws) {
+  for (int i = threadIdx.x; i < N; i += blockDim.x) tws[i] = tw[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -320,7 +334,7 @@ template <int N, typename T, int DIR>
 __global__ void __launch_bounds__((contig_pencils<N, T>() * Fft<N>::TPC)) k_fft_contig(const c2<T>* in, c2<T>* out, long long npencils, const c2<T>* tw) {
   using F = Fft<N>;
   constexpr int P = contig_pencils<N, T>();
-  constexpr int RS = N + N / 16;
+  constexpr int RS = zrow<N>();
   constexpr int RMAX = F::RMAX;
   __shared__ c2<T> lds[P * RS];
   const int tid = threadIdx.x;
@@ -355,6 +369,7 @@ __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_filter_y(cons
   constexpr int RMAX = F::RMAX;
   constexpr long long N3 = (long long)N * N * N;
   __shared__ c2<T> lds[G * N * ZC];
+  __shared__ c2<T> tws[N];
   const int tid = threadIdx.x;
   const int cc = tid % ZC;
   const int j = (tid / ZC) % F::TPC;
@@ -365,6 +380,8 @@ __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_filter_y(cons
   const int qx = active ? tile / chunks : 0;
   const int qz = (active ? tile % chunks : 0) * ZC + cc;
   const long long mock = blockIdx.y;
+  stage_twiddles<N, T>(tw, tws);
+  __syncthreads();
   c2<T> v0[RMAX];
   int q2[RMAX];
 #pragma unroll
@@ -394,7 +411,7 @@ __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_filter_y(cons
         for (int r = 0; r < RMAX; ++r) v[r] = cscale<T>(v0[r], jq[r][k]);
         int jj = j;
         asm volatile("" : "+v"(jj));
-        fft_column<N, +1, T, false, VB>(v, lds + g * N * ZC + cc, ZC, jj, tw, active);
+        fft_column<N, +1, T, false, VB>(v, lds + g * N * ZC + cc, ZC, jj, tws, active);
         if (active) {
           c2<T>* out = fbase + (bq + k) * N3;
 #pragma unroll
@@ -431,18 +448,18 @@ struct PairBlocks {
 };
 
 // Bins of a pencil are transformed in rounds of nbc = blockDim / TPC columns.
-template <int N>
+template <int N, int V>
 __device__ __forceinline__ int pencil_rounds(int nbins) {
-  const int nbc = blockDim.x / Fft<N, VB>::TPC;
+  const int nbc = blockDim.x / Fft<N, V>::TPC;
   return (nbins + nbc - 1) / nbc;
 }
 
 // Load round rr of a pencil: thread (bin b = rr * nbc + tid / TPC, j) loads its
 // column's first-stage elements.
-template <int N, typename T>
+template <int N, typename T, int V>
 __device__ __forceinline__ void load_pencil_round(const c2<T>* src, long long fstride, int nbins, int rr,
                                                   c2<T>* v) {
-  using F = Fft<N, VB>;
+  using F = Fft<N, V>;
   const int nbc = blockDim.x / F::TPC;
   const int b = rr * nbc + threadIdx.x / F::TPC;
   const int j = threadIdx.x % F::TPC;
@@ -452,13 +469,18 @@ __device__ __forceinline__ void load_pencil_round(const c2<T>* src, long long fs
   }
 }
 
-// Up to two rounds are prefetched into registers (vpre) ahead of use.
-template <int N, typename T>
+// Rounds prefetched into registers ahead of use: one with radix-16 columns
+// (16 values per thread), two with radix-8 columns.
+template <int N, int V> constexpr int prefetch_rounds() { return Fft<N, V>::RMAX >= 16 ? 1 : 2; }
+
+template <int N, typename T, int V>
 __device__ __forceinline__ void prefetch_pencil(const c2<T>* src, long long fstride, int nbins,
-                                                c2<T> (*vpre)[Fft<N, VB>::RMAX]) {
-  const int rounds = pencil_rounds<N>(nbins);
-  load_pencil_round<N, T>(src, fstride, nbins, 0, vpre[0]);
-  if (rounds > 1) load_pencil_round<N, T>(src, fstride, nbins, 1, vpre[1]);
+                                                c2<T> (*vpre)[Fft<N, V>::RMAX]) {
+  const int rounds = pencil_rounds<N, V>(nbins);
+  load_pencil_round<N, T, V>(src, fstride, nbins, 0, vpre[0]);
+  if constexpr (prefetch_rounds<N, V>() > 1) {
+    if (rounds > 1) load_pencil_round<N, T, V>(src, fstride, nbins, 1, vpre[1]);
+  }
 }
 
 // the z-pass workgroup has at least N threads (zpass_threads), so thread
@@ -474,10 +496,10 @@ __device__ __forceinline__ void prefetch_delta(const T* src, T* d) {
 }
 
 // z-transform one round of bins of a pencil into LDS rows A[b] (padded).
-template <int N, typename T>
+template <int N, typename T, int V>
 __device__ __forceinline__ void transform_round(int nbins, int rr, c2<T>* v, c2<T>* A, const c2<T>* tw) {
-  using F = Fft<N, VB>;
-  constexpr int RS = N + N / 16;
+  using F = Fft<N, V>;
+  constexpr int RS = zrow<N>();
   const int nbc = blockDim.x / F::TPC;
   int j = threadIdx.x % F::TPC;
   // keep per-thread LDS index arithmetic inside the pencil loop: hoisting it
@@ -485,7 +507,7 @@ __device__ __forceinline__ void transform_round(int nbins, int rr, c2<T>* v, c2<
   asm volatile("" : "+v"(j));
   const int b = rr * nbc + threadIdx.x / F::TPC;
   const bool active = b < nbins;
-  fft_column<N, +1, T, true, VB>(v, A + (active ? b : 0) * RS, 1, j, tw, active);
+  fft_column<N, +1, T, true, V>(v, A + (active ? b : 0) * RS, 1, j, tw, active);
   if (active) {
 #pragma unroll
     for (int e = 0; e < F::RMAX; ++e) A[b * RS + lds_pos<true>(F::out_index(j, e))] = v[e];
@@ -494,34 +516,75 @@ __device__ __forceinline__ void transform_round(int nbins, int rr, c2<T>* v, c2<
 
 // z-transform every bin of one pencil into LDS rows A[b]; rounds 0 and 1
 // come from the prefetched registers.
-template <int N, typename T>
+template <int N, typename T, int V>
 __device__ __forceinline__ void transform_pencil_bins(const c2<T>* src, long long fstride, int nbins, c2<T>* A,
-                                                      const c2<T>* tw, c2<T> (*vpre)[Fft<N, VB>::RMAX]) {
-  const int rounds = pencil_rounds<N>(nbins);
-  transform_round<N, T>(nbins, 0, vpre[0], A, tw);
-  if (rounds > 1) transform_round<N, T>(nbins, 1, vpre[1], A, tw);
-  for (int rr = 2; rr < rounds; ++rr) {
-    c2<T> v[Fft<N, VB>::RMAX];
-    load_pencil_round<N, T>(src, fstride, nbins, rr, v);
-    transform_round<N, T>(nbins, rr, v, A, tw);
+                                                      const c2<T>* tw, c2<T> (*vpre)[Fft<N, V>::RMAX]) {
+  constexpr int PR = prefetch_rounds<N, V>();
+  const int rounds = pencil_rounds<N, V>(nbins);
+  transform_round<N, T, V>(nbins, 0, vpre[0], A, tw);
+  if constexpr (PR > 1) {
+    if (rounds > 1) transform_round<N, T, V>(nbins, 1, vpre[1], A, tw);
+  }
+  for (int rr = PR; rr < rounds; ++rr) {
+    c2<T> v[Fft<N, V>::RMAX];
+    load_pencil_round<N, T, V>(src, fstride, nbins, rr, v);
+    transform_round<N, T, V>(nbins, rr, v, A, tw);
   }
 }
 
-template <int N, typename T>
-__global__ void __launch_bounds__(512) k_zpass_nodal(const c2<T>* fields, const T* delta, double* partials, int nbins,
+typedef float mp3_f4 __attribute__((ext_vector_type(4)));
+
+// Nodal contraction on the matrix cores (float32, nbins <= 32): per pair of z,
+// one v_mfma_f32_16x16x4f32 per upper-triangular 16x16 block of (b1, b2),
+// k = (z, re/im):  A[b1][k] = delta_z c_k(a_b1(z)),  B[k][b2] = c_k(a_b2(z)).
+// Lane l supplies A[l%16][l/16] and B[l/16][l%16]; D register i of lane l is
+// C[4 (l/16) + i][l%16].
+struct MfmaAcc {
+  mp3_f4 c00, c01, c11;
+};
+
+__device__ __forceinline__ void mfma_contract_pencil(const float2* A, const float* dl, int nbins, int RS, int N,
+                                                     MfmaAcc& acc) {
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  const int zz = kq >> 1, comp = kq & 1;
+  const bool two = nbins > 16;
+  const bool ok0 = col < nbins, ok1 = 16 + col < nbins;
+  const float* r0 = reinterpret_cast<const float*>(A + col * RS) + comp;
+  const float* r1 = reinterpret_cast<const float*>(A + (16 + col) * RS) + comp;
+  for (int zp = w; zp < N / 2; zp += nw) {
+    const int z = 2 * zp + zz;
+    const int off = 2 * lds_pos<true>(z);
+    const float d = dl[z];
+    const float v0 = ok0 ? r0[off] : 0.f;
+    acc.c00 = __builtin_amdgcn_mfma_f32_16x16x4f32(d * v0, v0, acc.c00, 0, 0, 0);
+    if (two) {
+      const float v1 = ok1 ? r1[off] : 0.f;
+      acc.c01 = __builtin_amdgcn_mfma_f32_16x16x4f32(d * v0, v1, acc.c01, 0, 0, 0);
+      acc.c11 = __builtin_amdgcn_mfma_f32_16x16x4f32(d * v1, v1, acc.c11, 0, 0, 0);
+    }
+  }
+}
+
+template <int N, typename T, bool MF>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MF ? 4 : 1))) k_zpass_nodal(const c2<T>* fields, const T* delta, double* partials, int nbins,
                                                       int ppw, const c2<T>* tw) {
-  using F = Fft<N, VB>;
-  constexpr int RS = N + N / 16;
+  using F = Fft<N, VZN>;
+  constexpr int RS = zrow<N>();
   constexpr long long N3 = (long long)N * N * N;
   extern __shared__ __align__(16) char smem[];
   c2<T>* A = reinterpret_cast<c2<T>*>(smem);
-  T* dl = reinterpret_cast<T*>(A + nbins * RS);
+  c2<T>* tws = A + nbins * RS;
+  T* dl = reinterpret_cast<T*>(tws + N);
   const int tid = threadIdx.x;
   const long long mock = blockIdx.y;
+  stage_twiddles<N, T>(tw, tws);
   PairBlocks pb;
   pb.init(nbins, blockDim.x);
   const int item = tid;
-  const bool has_item = item < pb.npb * pb.zch;
+  const bool has_item = !MF && item < pb.npb * pb.zch;
   int bb1 = 0, bb2 = 0, zc = 0;
   if (has_item) {
     pb.block_of(item / pb.zch, bb1, bb2);
@@ -529,33 +592,47 @@ __global__ void __launch_bounds__(512) k_zpass_nodal(const c2<T>* fields, const 
   }
   // partial sums in the working precision over this workgroup's pencils;
   // float64 across workgroups (k_reduce_partials)
-  T acc[16];
+  T acc[MF ? 1 : 16];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) acc[i] = (T)0;
+  for (int i = 0; i < (MF ? 1 : 16); ++i) acc[i] = (T)0;
+  MfmaAcc macc;
+  macc.c00 = mp3_f4{0.f, 0.f, 0.f, 0.f};
+  macc.c01 = macc.c00;
+  macc.c11 = macc.c00;
 
   const int p0 = blockIdx.x * ppw;
   const int p1 = min(p0 + ppw, N * N);
   const c2<T>* fmock = fields + mock * nbins * N3;
-  c2<T> vpre[2][F::RMAX];
+  c2<T> vpre[prefetch_rounds<N, VZN>()][F::RMAX];
   T dpre[DPRE];
   const T* dmock = delta + mock * N3;
   if (p0 < p1) {
-    prefetch_pencil<N, T>(fmock + (long long)p0 * N, N3, nbins, vpre);
+    prefetch_pencil<N, T, VZN>(fmock + (long long)p0 * N, N3, nbins, vpre);
     prefetch_delta<N, T>(dmock + (long long)p0 * N, dpre);
   }
   for (int p = p0; p < p1; ++p) {
+    // this pencil's data moves to vcur; the next pencil's loads are issued
+    // before the transform so they stay in flight for the whole iteration
+    c2<T> vcur[prefetch_rounds<N, VZN>()][F::RMAX];
+#pragma unroll
+    for (int q = 0; q < prefetch_rounds<N, VZN>(); ++q)
+#pragma unroll
+      for (int r = 0; r < F::RMAX; ++r) vcur[q][r] = vpre[q][r];
 #pragma unroll
     for (int k = 0; k < DPRE; ++k) {
       const int z = tid + k * blockDim.x;
       if (z < N) dl[z] = dpre[k];
     }
-    transform_pencil_bins<N, T>(fmock + (long long)p * N, N3, nbins, A, tw, vpre);
-    __syncthreads();
     if (p + 1 < p1) {
-      prefetch_pencil<N, T>(fmock + (long long)(p + 1) * N, N3, nbins, vpre);
+      prefetch_pencil<N, T, VZN>(fmock + (long long)(p + 1) * N, N3, nbins, vpre);
       prefetch_delta<N, T>(dmock + (long long)(p + 1) * N, dpre);
     }
-    if (has_item) {
+    __syncthreads();
+    transform_pencil_bins<N, T, VZN>(fmock + (long long)p * N, N3, nbins, A, tws, vcur);
+    __syncthreads();
+    if constexpr (MF) {
+      mfma_contract_pencil(reinterpret_cast<const float2*>(A), reinterpret_cast<const float*>(dl), nbins, RS, N, macc);
+    } else if (has_item) {
       const int b1o = 4 * bb1, b2o = 4 * bb2;
       for (int z = zc; z < N; z += pb.zch) {
         const T d = dl[z];
@@ -575,26 +652,49 @@ __global__ void __launch_bounds__(512) k_zpass_nodal(const c2<T>* fields, const 
     }
     __syncthreads();
   }
-  // reduce the z-chunks of every block through LDS, then write the symmetric partial
-  double* red = reinterpret_cast<double*>(smem);
-  if (has_item) {
-#pragma unroll
-    for (int i = 0; i < 16; ++i) red[item * 16 + i] = (double)acc[i];
-  }
-  __syncthreads();
   double* out = partials + ((long long)mock * gridDim.x + blockIdx.x) * nbins * nbins;
-  for (int t = tid; t < pb.npb * 16; t += blockDim.x) {
-    const int beta = t / 16, ik = t % 16;
-    double s = 0.0;
-    for (int c = 0; c < pb.zch; ++c) s += red[(beta * pb.zch + c) * 16 + ik];
-    int c1, c2b;
-    pb.block_of(beta, c1, c2b);
-    const int b1 = 4 * c1 + ik / 4, b2 = 4 * c2b + ik % 4;
-    // diagonal blocks hold both orders of a pair: keep b1 <= b2 and mirror,
-    // so the partial is exactly symmetric
-    if (b1 < nbins && b2 < nbins && b1 <= b2) {
-      out[b1 * nbins + b2] = s;
-      out[b2 * nbins + b1] = s;
+  double* red = reinterpret_cast<double*>(smem);
+  if constexpr (MF) {
+    // red[w][blk][row][col], blk 0 = (0,0), 1 = (0,1), 2 = (1,1)
+    const int lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = 4 * (lane >> 4) + i, col = lane & 15;
+      red[((w * 3 + 0) * 16 + row) * 16 + col] = (double)macc.c00[i];
+      red[((w * 3 + 1) * 16 + row) * 16 + col] = (double)macc.c01[i];
+      red[((w * 3 + 2) * 16 + row) * 16 + col] = (double)macc.c11[i];
+    }
+    __syncthreads();
+    for (int t = tid; t < 3 * 256; t += blockDim.x) {
+      const int blk = t / 256, row = (t / 16) % 16, col = t % 16;
+      double sacc = 0.0;
+      for (int ww = 0; ww < nw; ++ww) sacc += red[((ww * 3 + blk) * 16 + row) * 16 + col];
+      const int b1 = row + (blk == 2 ? 16 : 0), b2 = col + (blk >= 1 ? 16 : 0);
+      if (b1 < nbins && b2 < nbins && b1 <= b2) {
+        out[b1 * nbins + b2] = sacc;
+        out[b2 * nbins + b1] = sacc;
+      }
+    }
+  } else {
+    // reduce the z-chunks of every block through LDS, then write the symmetric partial
+    if (has_item) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) red[item * 16 + i] = (double)acc[i];
+    }
+    __syncthreads();
+    for (int t = tid; t < pb.npb * 16; t += blockDim.x) {
+      const int beta = t / 16, ik = t % 16;
+      double sacc = 0.0;
+      for (int c = 0; c < pb.zch; ++c) sacc += red[(beta * pb.zch + c) * 16 + ik];
+      int c1, c2b;
+      pb.block_of(beta, c1, c2b);
+      const int b1 = 4 * c1 + ik / 4, b2 = 4 * c2b + ik % 4;
+      // diagonal blocks hold both orders of a pair: keep b1 <= b2 and mirror,
+      // so the partial is exactly symmetric
+      if (b1 < nbins && b2 < nbins && b1 <= b2) {
+        out[b1 * nbins + b2] = sacc;
+        out[b2 * nbins + b1] = sacc;
+      }
     }
   }
 }
@@ -623,31 +723,44 @@ __global__ void k_reduce_partials(const double* partials, int nwg, int nb2, doub
 template <int N, typename T, int MAXNB>
 __global__ void __launch_bounds__(512) k_zpass_adjoint(c2<T>* fields, const T* delta, const T* __restrict__ lam_s,
                                                         T* direct, int nbins, T wm, int ppw, const c2<T>* tw) {
-  using F = Fft<N, VB>;
-  constexpr int RS = N + N / 16;
+  using F = Fft<N, VZA>;
+  constexpr int RS = zrow<N>();
+  constexpr int NBP = (MAXNB + 3) / 4 * 4;
   constexpr long long N3 = (long long)N * N * N;
   extern __shared__ __align__(16) char smem[];
   c2<T>* A = reinterpret_cast<c2<T>*>(smem);
+  c2<T>* tws = A + nbins * RS;
+  T* lam = reinterpret_cast<T*>(tws + N);             // [nbins][NBP], zero padded
   const int tid = threadIdx.x;
   const long long mock = blockIdx.y;
-  const T* lam = lam_s + mock * nbins * nbins;
+  stage_twiddles<N, T>(tw, tws);
+  for (int t = tid; t < nbins * NBP; t += blockDim.x) {
+    const int bp = t / NBP, b = t % NBP;
+    lam[t] = b < nbins ? lam_s[mock * nbins * nbins + bp * nbins + b] : (T)0;
+  }
+  __syncthreads();
   const int nbc = blockDim.x / F::TPC;
   const int p0 = blockIdx.x * ppw;
   const int p1 = min(p0 + ppw, N * N);
   c2<T>* fmock = fields + mock * nbins * N3;
   const T* dmock = delta + mock * N3;
   T* rmock = direct + mock * N3;
-  c2<T> vpre[2][F::RMAX];
+  c2<T> vpre[prefetch_rounds<N, VZA>()][F::RMAX];
   T dpre[DPRE], rpre[DPRE];
   if (p0 < p1) {
-    prefetch_pencil<N, T>(fmock + (long long)p0 * N, N3, nbins, vpre);
+    prefetch_pencil<N, T, VZA>(fmock + (long long)p0 * N, N3, nbins, vpre);
     prefetch_delta<N, T>(dmock + (long long)p0 * N, dpre);
     prefetch_delta<N, T>(rmock + (long long)p0 * N, rpre);
   }
   for (int p = p0; p < p1; ++p) {
     c2<T>* fbase = fmock + (long long)p * N;
-    transform_pencil_bins<N, T>(fbase, N3, nbins, A, tw, vpre);
-    __syncthreads();
+    // this pencil's data moves to vcur; the next pencil's loads are issued
+    // before the transform so they stay in flight for the whole iteration
+    c2<T> vcur[prefetch_rounds<N, VZA>()][F::RMAX];
+#pragma unroll
+    for (int q = 0; q < prefetch_rounds<N, VZA>(); ++q)
+#pragma unroll
+      for (int r = 0; r < F::RMAX; ++r) vcur[q][r] = vpre[q][r];
     T dcur[DPRE], rcur[DPRE];
 #pragma unroll
     for (int k = 0; k < DPRE; ++k) {
@@ -655,10 +768,12 @@ __global__ void __launch_bounds__(512) k_zpass_adjoint(c2<T>* fields, const T* d
       rcur[k] = rpre[k];
     }
     if (p + 1 < p1) {
-      prefetch_pencil<N, T>(fbase + N, N3, nbins, vpre);
+      prefetch_pencil<N, T, VZA>(fbase + N, N3, nbins, vpre);
       prefetch_delta<N, T>(dmock + (long long)(p + 1) * N, dpre);
       prefetch_delta<N, T>(rmock + (long long)(p + 1) * N, rpre);
     }
+    transform_pencil_bins<N, T, VZA>(fbase, N3, nbins, A, tws, vcur);
+    __syncthreads();
 #pragma unroll
     for (int k = 0; k < DPRE; ++k) {
       const int z = tid + k * blockDim.x;
@@ -669,13 +784,17 @@ __global__ void __launch_bounds__(512) k_zpass_adjoint(c2<T>* fields, const T* d
       for (int b = 0; b < MAXNB; ++b) u[b] = mk<T>(0, 0);
       for (int bp = 0; bp < nbins; ++bp) {
         const c2<T> a = A[bp * RS + zp];
-        const T* lrow = lam + bp * nbins;          // lam_s is symmetric: row bp = column bp
+        const T* lrow = lam + bp * NBP;            // lam_s is symmetric: row bp = column bp
 #pragma unroll
-        for (int b = 0; b < MAXNB; ++b) {
-          if (b < nbins) {
-            const T lv = lrow[b];
-            u[b].x += lv * a.x;
-            u[b].y -= lv * a.y;
+        for (int bq = 0; bq < NBP; bq += 4) {
+          T lq[4];
+          load_quad<T>(lrow + bq, lq);             // LDS broadcast
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            if (bq + k < MAXNB) {
+              u[bq + k].x += lq[k] * a.x;
+              u[bq + k].y -= lq[k] * a.y;
+            }
           }
         }
       }
@@ -705,7 +824,7 @@ __global__ void __launch_bounds__(512) k_zpass_adjoint(c2<T>* fields, const T* d
         for (int r = 0; r < F::RMAX; ++r) v[r] = A[b * RS + lds_pos<true>(F::in_index(j, r))];
       }
       __syncthreads();
-      fft_column<N, +1, T, true, VB>(v, A + (active ? b : 0) * RS, 1, j, tw, active);
+      fft_column<N, +1, T, true, VZA>(v, A + (active ? b : 0) * RS, 1, j, tws, active);
       if (active) {
 #pragma unroll
         for (int e = 0; e < F::RMAX; ++e) fbase[b * N3 + F::out_index(j, e)] = v[e];
@@ -741,6 +860,9 @@ __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_adjoint_y(con
   constexpr int RMAX = F::RMAX;
   constexpr long long N3 = (long long)N * N * N;
   __shared__ c2<T> lds[GT * N * ZC];
+  __shared__ c2<T> tws[N];
+  stage_twiddles<N, T>(tw, tws);
+  __syncthreads();
   const int tid = threadIdx.x;
   const int cc = tid % ZC;
   const int j = (tid / ZC) % F::TPC;
@@ -783,7 +905,7 @@ __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_adjoint_y(con
         }
         int jj = j;
         asm volatile("" : "+v"(jj));
-        fft_column<N, +1, T, false, VB>(v, lds + g * N * ZC + cc, ZC, jj, tw, active);
+        fft_column<N, +1, T, false, VB>(v, lds + g * N * ZC + cc, ZC, jj, tws, active);
 #pragma unroll
         for (int e = 0; e < RMAX; ++e) acc[e] = cadd<T>(acc[e], cmul<T>(v[e], cscale<T>(fac[e], jq[e][k])));
       }
@@ -917,8 +1039,8 @@ hipError_t adjoint_y_t(const FilterArgs& a, hipStream_t st) {
 }
 
 // z-pass workgroup: nbc columns (bins) per round, rounds balanced, <= 512 threads
-template <int N> inline int zpass_threads(int nbins) {
-  constexpr int TPC = Fft<N, VB>::TPC;
+template <int N, int V> inline int zpass_threads(int nbins) {
+  constexpr int TPC = Fft<N, V>::TPC;
   const int hi = 512 / TPC;
   const int rounds = (nbins + hi - 1) / hi;
   int nbc = (nbins + rounds - 1) / rounds;
@@ -931,15 +1053,20 @@ template <int N> inline int zpass_threads(int nbins) {
 }
 
 template <int N, typename T> inline size_t zpass_nodal_lds(int nbins, int threads) {
-  constexpr int RS = N + N / 16;
-  size_t a = (size_t)nbins * RS * sizeof(CT<T>) + (size_t)N * sizeof(T);
+  constexpr int RS = zrow<N>();
+  size_t a = (size_t)nbins * RS * sizeof(CT<T>) + (size_t)N * sizeof(CT<T>) + (size_t)N * sizeof(T);
   size_t r = (size_t)threads * 16 * sizeof(double);
   return a > r ? a : r;
 }
 
 template <int N, typename T> inline size_t zpass_adjoint_lds(int nbins) {
-  constexpr int RS = N + N / 16;
-  return (size_t)nbins * RS * sizeof(CT<T>);
+  constexpr int RS = zrow<N>();
+  const size_t nbp = (size_t)(nbins + 3) / 4 * 4;
+  // nbp here is the padded stride of the largest MAXNB that serves nbins
+  const size_t maxnb = nbins <= 8 ? 8 : nbins <= 12 ? 12 : nbins <= 16 ? 16 : nbins <= 20 ? 20 : nbins <= 24 ? 24
+                       : nbins <= 32 ? 32 : nbins <= 48 ? 48 : 64;
+  (void)nbp;
+  return (size_t)nbins * RS * sizeof(CT<T>) + (size_t)N * sizeof(CT<T>) + (size_t)nbins * maxnb * sizeof(T);
 }
 
 template <typename K> hipError_t allow_lds(K kernel, size_t bytes) {
@@ -947,21 +1074,32 @@ template <typename K> hipError_t allow_lds(K kernel, size_t bytes) {
   return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int N, typename T>
-hipError_t zpass_nodal_t(const ZpassArgs& a, hipStream_t st) {
-  const int threads = zpass_threads<N>(a.nbins);
-  const size_t lds = zpass_nodal_lds<N, T>(a.nbins, threads);
-  hipError_t e = allow_lds(k_zpass_nodal<N, T>, lds);
+template <int N, typename T, bool MF>
+hipError_t zpass_nodal_mf(const ZpassArgs& a, hipStream_t st) {
+  const int threads = zpass_threads<N, VZN>(a.nbins);
+  size_t lds = zpass_nodal_lds<N, T>(a.nbins, threads);
+  const size_t red = (size_t)(threads / 64) * 3 * 256 * sizeof(double);
+  if (lds < red) lds = red;
+  hipError_t e = allow_lds(k_zpass_nodal<N, T, MF>, lds);
   if (e != hipSuccess) return e;
   const dim3 gs(a.nwg, a.batch);
-  k_zpass_nodal<N, T><<<gs, threads, lds, st>>>(static_cast<const CT<T>*>(a.fields), static_cast<const T*>(a.delta),
-                                               a.partials, a.nbins, a.ppw, static_cast<const CT<T>*>(a.tw));
+  k_zpass_nodal<N, T, MF><<<gs, threads, lds, st>>>(static_cast<const CT<T>*>(a.fields), static_cast<const T*>(a.delta),
+                                                   a.partials, a.nbins, a.ppw, static_cast<const CT<T>*>(a.tw));
   return hipGetLastError();
+}
+
+// float32 with at most 32 bins contracts on the matrix cores
+template <int N, typename T>
+hipError_t zpass_nodal_t(const ZpassArgs& a, hipStream_t st) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (a.nbins <= 32 && zpass_threads<N, VZN>(a.nbins) % 64 == 0) return zpass_nodal_mf<N, T, true>(a, st);
+  }
+  return zpass_nodal_mf<N, T, false>(a, st);
 }
 
 template <int N, typename T, int MAXNB>
 hipError_t zpass_adjoint_nb(const ZpassArgs& a, hipStream_t st) {
-  const int threads = zpass_threads<N>(a.nbins);
+  const int threads = zpass_threads<N, VZA>(a.nbins);
   const size_t lds = zpass_adjoint_lds<N, T>(a.nbins);
   hipError_t e = allow_lds(k_zpass_adjoint<N, T, MAXNB>, lds);
   if (e != hipSuccess) return e;
@@ -986,7 +1124,7 @@ hipError_t zpass_adjoint_t(const ZpassArgs& a, hipStream_t st) {
 }
 
 template <int N, typename T> size_t zpass_lds_need_t(int nbins) {
-  const size_t a = zpass_nodal_lds<N, T>(nbins, zpass_threads<N>(nbins));
+  const size_t a = zpass_nodal_lds<N, T>(nbins, zpass_threads<N, VZN>(nbins));
   const size_t b = zpass_adjoint_lds<N, T>(nbins);
   return a > b ? a : b;
 }
