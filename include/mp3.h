@@ -67,8 +67,9 @@ enum mp3_status {
 enum mp3_precision { MP3_F32 = 0, MP3_F64 = 1 };
 
 enum mp3_summation {
-  MP3_SUM_NODAL = 0       /* grid summation on the nodes (connection coefficients
+  MP3_SUM_NODAL = 0,      /* grid summation on the nodes (connection coefficients
                              lumped onto the primary node)                          */
+  MP3_SUM_PARTICLE = 2    /* particle summation: primary vertex on the catalogue    */
 };
 
 typedef struct {
@@ -120,15 +121,32 @@ int mp3_deposit(mp3_plan_t plan, const float* pos, const float* w, const int64_t
 int mp3_multipole_fields(mp3_plan_t plan, const void* delta, int32_t l, int32_t m, void* a_out,
                          void* workspace, size_t workspace_bytes, void* stream);
 
-/* Multipole moments by nodal grid summation (Eqs. 3PCF-multipole-sum, SFC-3PCF):
- *   zeta_l[b1,b2] = (4 pi / N^3) sum_x delta_x sum_{m=-l}^{l} a_{lm,b1}(x) conj(a_{lm,b2}(x)),
- * evaluated with m >= 0 only (m > 0 counted twice).  Real and symmetric.
+/* Multipole moments of one batch.
+ *
+ * MP3_SUM_NODAL (Eqs. 3PCF-multipole-sum and SFC-3PCF, grid summation with the
+ * connection coefficients lumped onto the primary node):
+ *   zeta_l[b1,b2] = (4 pi / N^3) sum_x delta_x sum_{m=-l}^{l} a_{lm,b1}(x) conj(a_{lm,b2}(x)).
+ *   pos, w and np_off are ignored (may be NULL).
+ *
+ * MP3_SUM_PARTICLE (Sec. 2.2, the particle sum after Eq. DDD-sum-privertex; the
+ * primary vertex is the catalogue's contrast n/nbar - 1):
+ *   zeta_l[b1,b2] = 4 pi [ (1/W) sum_i w_i F_l(x_i) - Fbar_l ],
+ *   F_l(x) = sum_{m=-l}^{l} atilde_{lm,b1}(x) conj(atilde_{lm,b2}(x)),
+ *   atilde the cubic B-spline interpolant of the fields at the particle, Fbar_l
+ *   the exact volume mean of F_l:
+ *   Fbar_l = (2l+1)/(4 pi N^6) sum_q |dhat(q)|^2 B7hat(q) jbar_{l,b1} jbar_{l,b2},
+ *   B7hat the DFT of the B-spline autocorrelation samples.  pos, w (NULL =
+ *   unit) and np_off as for mp3_deposit (delta must be their deposit).
+ *   At most 2^31 - 1 particles in total.
+ *
+ * Both forms sum m >= 0 only (m > 0 counted twice).  Result real and symmetric.
  * delta  device real [batch][N^3];
  * zeta   device float64 [batch][lmax+1][nbins][nbins], overwritten. */
-int mp3_zeta(mp3_plan_t plan, const void* delta, double* zeta,
-             void* workspace, size_t workspace_bytes, void* stream);
+int mp3_zeta(mp3_plan_t plan, const void* delta, const float* pos, const float* w, const int64_t* np_off,
+             double* zeta, void* workspace, size_t workspace_bytes, void* stream);
 
-/* Gradient of J = sum_{j,l,b1,b2} dzeta[j][l][b1][b2] zeta_l^{(j)}[b1][b2].
+/* Gradient of J = sum_{j,l,b1,b2} dzeta[j][l][b1][b2] zeta_l^{(j)}[b1][b2] for the
+ * nodal form (other forms return MP3_EUNSUPPORTED).
  * The fields are recomputed per (l, m); nothing is kept from mp3_zeta.
  *   ddelta = dJ/ddelta                                          (device real [batch][N^3])
  *   dw     = dJ/dw_i through delta = eps N^3 / W - 1 of mp3_deposit, i.e.
@@ -149,7 +167,9 @@ enum mp3_pass {
   MP3_PASS_Z_ADJOINT = 4,  /* z-transform + adjoint sources + their z-transform                */
   MP3_PASS_ADJOINT = 5,    /* y-transform of the adjoint sources, window, bin sum into G       */
   MP3_PASS_DEPOSIT = 6,    /* B-spline scatter of the catalogue                                */
-  MP3_NPASS = 7
+  MP3_PASS_Z_STORE = 7,    /* z-transform, fields stored bin-interleaved (particle form)       */
+  MP3_PASS_GATHER = 8,     /* B-spline gather at the particles + contraction                   */
+  MP3_NPASS = 9
 };
 
 /* Per-pass timing for measurement: with enable != 0 every pass launch of

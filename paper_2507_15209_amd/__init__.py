@@ -37,10 +37,14 @@ class Plan:
 
     precision "f32": fields, FFTs and window in float32 (tables generated in
     float64, reductions in float64); "f64": the plain float64 form.
+    summation "nodal": grid summation on the nodes; "particle": primary vertex
+    on the catalogue (zeta() then needs pos, w, np_off).
     """
 
+    SUMMATIONS = {"nodal": _lib.MP3_SUM_NODAL, "particle": _lib.MP3_SUM_PARTICLE}
+
     def __init__(self, n: int, box: float, lmax: int, edges, precision: str = "f32", batch: int = 1,
-                 device=None):
+                 device=None, summation: str = "nodal"):
         self.lib = _lib.load()
         self.n, self.box, self.lmax, self.batch = int(n), float(box), int(lmax), int(batch)
         self.edges = np.ascontiguousarray(edges, dtype=np.float64)
@@ -48,13 +52,16 @@ class Plan:
         if precision not in ("f32", "f64"):
             raise ValueError("precision must be 'f32' or 'f64'")
         self.precision = precision
+        if summation not in self.SUMMATIONS:
+            raise ValueError(f"summation must be one of {sorted(self.SUMMATIONS)}")
+        self.summation = summation
         self.real_dtype = torch.float32 if precision == "f32" else torch.float64
         self.complex_dtype = torch.complex64 if precision == "f32" else torch.complex128
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         desc = _lib.PlanDesc(self.n, self.box, self.lmax, self.nbins,
                              self.edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                              _lib.MP3_F32 if precision == "f32" else _lib.MP3_F64,
-                             _lib.MP3_SUM_NODAL, self.batch)
+                             self.SUMMATIONS[summation], self.batch)
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _lib.check(self.lib.mp3_plan_create(ctypes.byref(desc), ctypes.byref(handle)), "mp3_plan_create")
@@ -139,11 +146,23 @@ class Plan:
         _lib.check(st, "mp3_multipole_fields")
         return out
 
-    def zeta(self, delta):
+    def zeta(self, delta, pos=None, w=None, np_off=None):
+        """zeta_l [batch, lmax+1, nbins, nbins] float64; the particle form needs the catalogue."""
         self._real(delta, "delta")
+        offp = None
+        np_total = 0
+        if self.summation == "particle":
+            if pos is None:
+                raise ValueError("particle summation needs pos (and w, np_off)")
+            self._catalogue(pos, w)
+            np_total = pos.shape[0]
+            off = self._offsets(np_off, np_total)
+            offp = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
         z = torch.empty((self.batch, self.lmax + 1, self.nbins, self.nbins), dtype=torch.float64, device=self.device)
-        ws = self._workspace()
-        st = self.lib.mp3_zeta(self._h, _ptr(delta), _ptr(z), _ptr(ws), ws.numel(), _stream(self.device))
+        ws = self._workspace(np_total)
+        st = self.lib.mp3_zeta(self._h, _ptr(delta), _ptr(pos if offp is not None else None),
+                               _ptr(w if offp is not None else None), offp, _ptr(z), _ptr(ws), ws.numel(),
+                               _stream(self.device))
         _lib.check(st, "mp3_zeta")
         return z
 

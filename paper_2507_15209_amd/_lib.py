@@ -16,6 +16,7 @@ MP3_EWORKSPACE = -5
 MP3_F32 = 0
 MP3_F64 = 1
 MP3_SUM_NODAL = 0
+MP3_SUM_PARTICLE = 2
 
 # every entry point of include/mp3.h
 EXPORTS = (
@@ -23,7 +24,7 @@ EXPORTS = (
     "mp3_multipole_fields", "mp3_zeta", "mp3_zeta_backward", "mp3_plan_info",
     "mp3_status_string", "mp3_last_error", "mp3_profile", "mp3_profile_read",
 )
-PASSES = ("dft", "filter", "x", "z_nodal", "z_adjoint", "adjoint", "deposit")
+PASSES = ("dft", "filter", "x", "z_nodal", "z_adjoint", "adjoint", "deposit", "z_store", "gather")
 
 
 class PlanDesc(ctypes.Structure):
@@ -71,7 +72,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.mp3_workspace_size.argtypes = [vp, i64, ctypes.POINTER(sz)]
     lib.mp3_deposit.argtypes = [vp, vp, vp, ctypes.POINTER(i64), vp, vp, sz, vp]
     lib.mp3_multipole_fields.argtypes = [vp, vp, i32, i32, vp, vp, sz, vp]
-    lib.mp3_zeta.argtypes = [vp, vp, vp, vp, sz, vp]
+    lib.mp3_zeta.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i64), vp, vp, sz, vp]
     lib.mp3_zeta_backward.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(i64), vp, vp, sz, vp]
     lib.mp3_plan_info.argtypes = [vp] + [ctypes.POINTER(i32)] * 5
     lib.mp3_profile.argtypes = [vp, ctypes.c_int]

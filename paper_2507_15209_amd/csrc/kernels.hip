@@ -568,9 +568,112 @@ __device__ __forceinline__ void mfma_contract_pencil(const float2* A, const floa
   }
 }
 
+// Per-workgroup accumulator of  P[b1,b2] = sum_k w_k Re(a_b1(k) conj(a_b2(k)))
+// over LDS rows A[b * RS + lds_pos(k)], either on the matrix cores (MF) or in
+// 4x4 register blocks on the vector ALUs.  Partial sums stay in the working
+// precision over the workgroup's slices and are written as float64.
+template <typename T, bool MF>
+struct Contractor {
+  PairBlocks pb;
+  int bb1 = 0, bb2 = 0, zc = 0;
+  bool has_item = false;
+  T acc[MF ? 1 : 16];
+  MfmaAcc macc;
+
+  __device__ void init(int nbins) {
+    pb.init(nbins, blockDim.x);
+    has_item = !MF && (int)threadIdx.x < pb.npb * pb.zch;
+    if (has_item) {
+      pb.block_of(threadIdx.x / pb.zch, bb1, bb2);
+      zc = threadIdx.x % pb.zch;
+    }
+#pragma unroll
+    for (int i = 0; i < (MF ? 1 : 16); ++i) acc[i] = (T)0;
+    macc.c00 = mp3_f4{0.f, 0.f, 0.f, 0.f};
+    macc.c01 = macc.c00;
+    macc.c11 = macc.c00;
+  }
+
+  // K positions (even), weights w[k] in LDS
+  __device__ void add(const c2<T>* A, const T* w, int nbins, int RS, int K) {
+    if constexpr (MF) {
+      mfma_contract_pencil(reinterpret_cast<const float2*>(A), reinterpret_cast<const float*>(w), nbins, RS, K, macc);
+    } else if (has_item) {
+      const int b1o = 4 * bb1, b2o = 4 * bb2;
+      for (int z = zc; z < K; z += pb.zch) {
+        const T d = w[z];
+        const int zp = lds_pos<true>(z);
+        c2<T> x1[4], x2[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          x1[i] = (b1o + i < nbins) ? A[(b1o + i) * RS + zp] : mk<T>(0, 0);
+          x2[i] = (b2o + i < nbins) ? A[(b2o + i) * RS + zp] : mk<T>(0, 0);
+          x1[i] = cscale<T>(x1[i], d);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) acc[i * 4 + k] += x1[i].x * x2[k].x + x1[i].y * x2[k].y;
+      }
+    }
+  }
+
+  // LDS bytes finish() needs as scratch
+  static __host__ __device__ size_t scratch_bytes(int threads) {
+    return MF ? (size_t)(threads / 64) * 3 * 256 * sizeof(double) : (size_t)threads * 16 * sizeof(double);
+  }
+
+  // workgroup reduction through LDS scratch red, symmetric partial to out[nbins^2]
+  __device__ void finish(double* red, double* out, int nbins) {
+    const int tid = threadIdx.x;
+    if constexpr (MF) {
+      // red[w][blk][row][col], blk 0 = (0,0), 1 = (0,1), 2 = (1,1)
+      const int lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 4 * (lane >> 4) + i, col = lane & 15;
+        red[((w * 3 + 0) * 16 + row) * 16 + col] = (double)macc.c00[i];
+        red[((w * 3 + 1) * 16 + row) * 16 + col] = (double)macc.c01[i];
+        red[((w * 3 + 2) * 16 + row) * 16 + col] = (double)macc.c11[i];
+      }
+      __syncthreads();
+      for (int t = tid; t < 3 * 256; t += blockDim.x) {
+        const int blk = t / 256, row = (t / 16) % 16, col = t % 16;
+        double sacc = 0.0;
+        for (int ww = 0; ww < nw; ++ww) sacc += red[((ww * 3 + blk) * 16 + row) * 16 + col];
+        const int b1 = row + (blk == 2 ? 16 : 0), b2 = col + (blk >= 1 ? 16 : 0);
+        if (b1 < nbins && b2 < nbins && b1 <= b2) {
+          out[b1 * nbins + b2] = sacc;
+          out[b2 * nbins + b1] = sacc;
+        }
+      }
+    } else {
+      if (has_item) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) red[tid * 16 + i] = (double)acc[i];
+      }
+      __syncthreads();
+      for (int t = tid; t < pb.npb * 16; t += blockDim.x) {
+        const int beta = t / 16, ik = t % 16;
+        double sacc = 0.0;
+        for (int c = 0; c < pb.zch; ++c) sacc += red[(beta * pb.zch + c) * 16 + ik];
+        int c1, c2b;
+        pb.block_of(beta, c1, c2b);
+        const int b1 = 4 * c1 + ik / 4, b2 = 4 * c2b + ik % 4;
+        // diagonal blocks hold both orders of a pair: keep b1 <= b2 and mirror,
+        // so the partial is exactly symmetric
+        if (b1 < nbins && b2 < nbins && b1 <= b2) {
+          out[b1 * nbins + b2] = sacc;
+          out[b2 * nbins + b1] = sacc;
+        }
+      }
+    }
+  }
+};
+
 template <int N, typename T, bool MF>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MF ? 4 : 1))) k_zpass_nodal(const c2<T>* fields, const T* delta, double* partials, int nbins,
-                                                      int ppw, const c2<T>* tw) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MF ? 4 : 1))) k_zpass_nodal(
+    const c2<T>* fields, const T* delta, double* partials, int nbins, int ppw, const c2<T>* tw) {
   using F = Fft<N, VZN>;
   constexpr int RS = zrow<N>();
   constexpr long long N3 = (long long)N * N * N;
@@ -581,25 +684,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MF ? 4
   const int tid = threadIdx.x;
   const long long mock = blockIdx.y;
   stage_twiddles<N, T>(tw, tws);
-  PairBlocks pb;
-  pb.init(nbins, blockDim.x);
-  const int item = tid;
-  const bool has_item = !MF && item < pb.npb * pb.zch;
-  int bb1 = 0, bb2 = 0, zc = 0;
-  if (has_item) {
-    pb.block_of(item / pb.zch, bb1, bb2);
-    zc = item % pb.zch;
-  }
-  // partial sums in the working precision over this workgroup's pencils;
-  // float64 across workgroups (k_reduce_partials)
-  T acc[MF ? 1 : 16];
-#pragma unroll
-  for (int i = 0; i < (MF ? 1 : 16); ++i) acc[i] = (T)0;
-  MfmaAcc macc;
-  macc.c00 = mp3_f4{0.f, 0.f, 0.f, 0.f};
-  macc.c01 = macc.c00;
-  macc.c11 = macc.c00;
-
+  Contractor<T, MF> ctr;
+  ctr.init(nbins);
   const int p0 = blockIdx.x * ppw;
   const int p1 = min(p0 + ppw, N * N);
   const c2<T>* fmock = fields + mock * nbins * N3;
@@ -630,73 +716,224 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MF ? 4
     __syncthreads();
     transform_pencil_bins<N, T, VZN>(fmock + (long long)p * N, N3, nbins, A, tws, vcur);
     __syncthreads();
-    if constexpr (MF) {
-      mfma_contract_pencil(reinterpret_cast<const float2*>(A), reinterpret_cast<const float*>(dl), nbins, RS, N, macc);
-    } else if (has_item) {
-      const int b1o = 4 * bb1, b2o = 4 * bb2;
-      for (int z = zc; z < N; z += pb.zch) {
-        const T d = dl[z];
-        const int zp = lds_pos<true>(z);
-        c2<T> x1[4], x2[4];
+    ctr.add(A, dl, nbins, RS, N);
+    __syncthreads();
+  }
+  ctr.finish(reinterpret_cast<double*>(smem), partials + ((long long)mock * gridDim.x + blockIdx.x) * nbins * nbins,
+             nbins);
+}
+
+// ---------------------------------------------------------------------------
+// particle summation
+// ---------------------------------------------------------------------------
+// z pass that stores the fields bin-interleaved, out[mock][cell][b], so that a
+// B-spline tap reads all bins of a node contiguously
+template <int N, typename T>
+__global__ void __launch_bounds__(512) k_zpass_store(const c2<T>* fields, c2<T>* out, int nbins, int ppw,
+                                                      const c2<T>* tw) {
+  using F = Fft<N, VZN>;
+  constexpr int RS = zrow<N>();
+  constexpr long long N3 = (long long)N * N * N;
+  extern __shared__ __align__(16) char smem[];
+  c2<T>* A = reinterpret_cast<c2<T>*>(smem);
+  c2<T>* tws = A + nbins * RS;
+  const long long mock = blockIdx.y;
+  stage_twiddles<N, T>(tw, tws);
+  const int p0 = blockIdx.x * ppw;
+  const int p1 = min(p0 + ppw, N * N);
+  const c2<T>* fmock = fields + mock * nbins * N3;
+  c2<T>* omock = out + mock * nbins * N3;
+  c2<T> vpre[prefetch_rounds<N, VZN>()][F::RMAX];
+  if (p0 < p1) prefetch_pencil<N, T, VZN>(fmock + (long long)p0 * N, N3, nbins, vpre);
+  for (int p = p0; p < p1; ++p) {
+    c2<T> vcur[prefetch_rounds<N, VZN>()][F::RMAX];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          x1[i] = (b1o + i < nbins) ? A[(b1o + i) * RS + zp] : mk<T>(0, 0);
-          x2[i] = (b2o + i < nbins) ? A[(b2o + i) * RS + zp] : mk<T>(0, 0);
-          x1[i] = cscale<T>(x1[i], d);
+    for (int q = 0; q < prefetch_rounds<N, VZN>(); ++q)
+#pragma unroll
+      for (int r = 0; r < F::RMAX; ++r) vcur[q][r] = vpre[q][r];
+    if (p + 1 < p1) prefetch_pencil<N, T, VZN>(fmock + (long long)(p + 1) * N, N3, nbins, vpre);
+    __syncthreads();
+    transform_pencil_bins<N, T, VZN>(fmock + (long long)p * N, N3, nbins, A, tws, vcur);
+    __syncthreads();
+    c2<T>* dst = omock + (long long)p * N * nbins;
+    for (int idx = threadIdx.x; idx < N * nbins; idx += blockDim.x) {
+      const int z = idx / nbins, b = idx - z * nbins;
+      dst[idx] = A[b * RS + lds_pos<true>(z)];
+    }
+  }
+}
+
+// particles per 4^3-cell tile (sort key), tile id mock * NT + (tx * NTd + ty) * NTd + tz
+__device__ __forceinline__ int tile_of(const float* p, int n, double sc, int ntd) {
+  int t = 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double u = (double)p[d] * sc;
+    if (!(u == u) || fabs(u) > 1e15) u = 0.0;
+    u -= (double)n * floor(u / (double)n);
+    int c = (int)floor(u);
+    if (c >= n) c -= n;
+    if (c < 0) c = 0;
+    t = t * ntd + (c >> 2);
+  }
+  return t;
+}
+
+__global__ void k_tile_count(const float* pos, const long long* off, int batch, long long np_total, int n, double sc,
+                             int* counts) {
+  const int ntd = n / 4;
+  const long long nt = (long long)ntd * ntd * ntd;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < np_total; i += (long long)gridDim.x * blockDim.x) {
+    const int mock = find_mock(off, batch, i);
+    atomicAdd(&counts[mock * nt + tile_of(pos + 3 * i, n, sc, ntd)], 1);
+  }
+}
+
+// exclusive scan of counts[0..m) into offs (and a copy into cursor), one block
+__global__ void k_scan_counts(const int* counts, int* offs, int* cursor, long long m) {
+  __shared__ long long part[1024];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const long long seg = (m + nt - 1) / nt;
+  const long long a = tid * seg, b = min(m, a + seg);
+  long long s = 0;
+  for (long long i = a; i < b; ++i) s += counts[i];
+  part[tid] = s;
+  __syncthreads();
+  if (tid == 0) {
+    long long run = 0;
+    for (int t = 0; t < nt; ++t) {
+      const long long v = part[t];
+      part[t] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  long long run = part[tid];
+  for (long long i = a; i < b; ++i) {
+    offs[i] = (int)run;
+    cursor[i] = (int)run;
+    run += counts[i];
+  }
+}
+
+__global__ void k_tile_scatter(const float* pos, const long long* off, int batch, long long np_total, int n, double sc,
+                               int* cursor, int* perm) {
+  const int ntd = n / 4;
+  const long long nt = (long long)ntd * ntd * ntd;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < np_total; i += (long long)gridDim.x * blockDim.x) {
+    const int mock = find_mock(off, batch, i);
+    const int slot = atomicAdd(&cursor[mock * nt + tile_of(pos + 3 * i, n, sc, ntd)], 1);
+    perm[slot] = (int)i;
+  }
+}
+
+// Gather the B-spline interpolants of the (bin-interleaved) fields at the
+// particles, one lane per (particle, bin), into LDS rows, then contract with
+// the weights w_i / W.  Particles are visited in tile order (perm).
+template <typename T, bool MF>
+__global__ void __launch_bounds__(256) k_gather_contract(const c2<T>* fields, const float* pos, const float* w,
+                                                          const int* perm, const long long* off, const double* W,
+                                                          int n, double sc, int nbins, double* partials) {
+  constexpr int K = 256;                                // particles per contraction slice
+  constexpr int RS = K + K / 16 + 1;
+  extern __shared__ __align__(16) char smem[];
+  c2<T>* A = reinterpret_cast<c2<T>*>(smem);
+  T* wk = reinterpret_cast<T*>(A + nbins * RS);
+  const long long mock = blockIdx.y;
+  const long long n3 = (long long)n * n * n;
+  const long long a0 = off[mock], a1 = off[mock + 1];
+  const long long per = (a1 - a0 + gridDim.x - 1) / gridDim.x;
+  const long long s0 = a0 + per * blockIdx.x, s1 = min(a1, s0 + per);
+  const double invW = 1.0 / W[mock];
+  const int lpp = nbins <= 32 ? 32 : 64;                // lanes per particle
+  const int ppp = blockDim.x / lpp;                     // particles per pass
+  const int b = threadIdx.x % lpp;
+  const c2<T>* fm = fields + mock * n3 * nbins;
+  Contractor<T, MF> ctr;
+  ctr.init(nbins);
+  for (long long c0 = s0; c0 < s1; c0 += K) {
+    for (int k0 = 0; k0 < K; k0 += ppp) {
+      const int k = k0 + threadIdx.x / lpp;
+      const long long si = c0 + k;
+      c2<T> acc = mk<T>(0, 0);
+      T wgt = 0;
+      if (si < s1) {
+        const int i = perm[si];
+        Taps t = make_taps(pos + 3 * (long long)i, n, sc);
+        if (t.ok && b < nbins) {
+          for (int ax = 0; ax < 4; ++ax) {
+            const int ix = wrapi(t.base[0] + ax, n);
+            for (int ay = 0; ay < 4; ++ay) {
+              const int iy = wrapi(t.base[1] + ay, n);
+              const T wxy = (T)(t.wt[0][ax] * t.wt[1][ay]);
+              const c2<T>* row = fm + ((long long)ix * n + iy) * n * nbins + b;
+#pragma unroll
+              for (int az = 0; az < 4; ++az) {
+                const int iz = wrapi(t.base[2] + az, n);
+                const c2<T> v = row[(long long)iz * nbins];
+                const T wt = wxy * (T)t.wt[2][az];
+                acc.x += wt * v.x;
+                acc.y += wt * v.y;
+              }
+            }
+          }
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int k = 0; k < 4; ++k) acc[i * 4 + k] += x1[i].x * x2[k].x + x1[i].y * x2[k].y;
+        wgt = (T)((w ? (double)w[i] : 1.0) * invW);
       }
+      if (b < nbins) A[b * RS + lds_pos<true>(k)] = acc;
+      if (b == 0) wk[k] = wgt;
     }
+    __syncthreads();
+    ctr.add(A, wk, nbins, RS, K);
     __syncthreads();
   }
-  double* out = partials + ((long long)mock * gridDim.x + blockIdx.x) * nbins * nbins;
-  double* red = reinterpret_cast<double*>(smem);
-  if constexpr (MF) {
-    // red[w][blk][row][col], blk 0 = (0,0), 1 = (0,1), 2 = (1,1)
-    const int lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+  ctr.finish(reinterpret_cast<double*>(smem), partials + ((long long)mock * gridDim.x + blockIdx.x) * nbins * nbins,
+             nbins);
+}
+
+// P[mock][s] += |dhat(q)|^2 B7hat(q) over q with |q|^2 = s, Nyquist planes excluded.
+// B7hat(theta) = sum_s B7(s) e^{-i theta s} with the cubic B-spline
+// autocorrelation samples B7(0) = 2416/5040, B7(1) = 1191/5040, B7(2) = 120/5040,
+// B7(3) = 1/5040.
+template <typename T>
+__global__ void k_power_hist(const c2<T>* dhat, int n, int nq2, double* P) {
+  const long long n3 = (long long)n * n * n;
+  const int mock = blockIdx.y;
+  const c2<T>* d = dhat + mock * n3;
+  double* pm = P + (long long)mock * nq2;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n3; i += (long long)gridDim.x * blockDim.x) {
+    const int ix = (int)(i / ((long long)n * n)), iy = (int)((i / n) % n), iz = (int)(i % n);
+    const int qx = sfreq(ix, n), qy = sfreq(iy, n), qz = sfreq(iz, n);
+    const int h = -n / 2;
+    if (qx == h || qy == h || qz == h) continue;
+    const double tp = 2.0 * 3.14159265358979323846 / n;
+    double b7 = 1.0;
+    const int qs[3] = {qx, qy, qz};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int row = 4 * (lane >> 4) + i, col = lane & 15;
-      red[((w * 3 + 0) * 16 + row) * 16 + col] = (double)macc.c00[i];
-      red[((w * 3 + 1) * 16 + row) * 16 + col] = (double)macc.c01[i];
-      red[((w * 3 + 2) * 16 + row) * 16 + col] = (double)macc.c11[i];
+    for (int a = 0; a < 3; ++a) {
+      const double th = tp * qs[a];
+      b7 *= (2416.0 + 2382.0 * cos(th) + 240.0 * cos(2.0 * th) + 2.0 * cos(3.0 * th)) / 5040.0;
     }
-    __syncthreads();
-    for (int t = tid; t < 3 * 256; t += blockDim.x) {
-      const int blk = t / 256, row = (t / 16) % 16, col = t % 16;
-      double sacc = 0.0;
-      for (int ww = 0; ww < nw; ++ww) sacc += red[((ww * 3 + blk) * 16 + row) * 16 + col];
-      const int b1 = row + (blk == 2 ? 16 : 0), b2 = col + (blk >= 1 ? 16 : 0);
-      if (b1 < nbins && b2 < nbins && b1 <= b2) {
-        out[b1 * nbins + b2] = sacc;
-        out[b2 * nbins + b1] = sacc;
-      }
-    }
-  } else {
-    // reduce the z-chunks of every block through LDS, then write the symmetric partial
-    if (has_item) {
-#pragma unroll
-      for (int i = 0; i < 16; ++i) red[item * 16 + i] = (double)acc[i];
-    }
-    __syncthreads();
-    for (int t = tid; t < pb.npb * 16; t += blockDim.x) {
-      const int beta = t / 16, ik = t % 16;
-      double sacc = 0.0;
-      for (int c = 0; c < pb.zch; ++c) sacc += red[(beta * pb.zch + c) * 16 + ik];
-      int c1, c2b;
-      pb.block_of(beta, c1, c2b);
-      const int b1 = 4 * c1 + ik / 4, b2 = 4 * c2b + ik % 4;
-      // diagonal blocks hold both orders of a pair: keep b1 <= b2 and mirror,
-      // so the partial is exactly symmetric
-      if (b1 < nbins && b2 < nbins && b1 <= b2) {
-        out[b1 * nbins + b2] = sacc;
-        out[b2 * nbins + b1] = sacc;
-      }
-    }
+    const c2<T> v = d[i];
+    const double p2 = (double)v.x * v.x + (double)v.y * v.y;
+    atomicAdd(&pm[qx * qx + qy * qy + qz * qz], p2 * b7);
   }
+}
+
+// zeta[mock][l][b1][b2] -= (2l+1)/N^6 sum_s P[s] jbar_{l,b1}(s) jbar_{l,b2}(s)
+// (4 pi times the volume mean of F_l); one block per (b1 b2, mock)
+template <typename T>
+__global__ void k_fbar_subtract(const double* P, const T* jtab, int nq2, int nbp, int nbins, int l, int lmax,
+                                double n6, double* zeta) {
+  __shared__ double sh[32];
+  const int e = blockIdx.x, mock = blockIdx.y;
+  const int b1 = e / nbins, b2 = e % nbins;
+  const double* pm = P + (long long)mock * nq2;
+  const T* jl = jtab + (long long)l * nq2 * nbp;
+  double s = 0.0;
+  for (int q = threadIdx.x; q < nq2; q += blockDim.x) s += pm[q] * (double)jl[(long long)q * nbp + b1] * (double)jl[(long long)q * nbp + b2];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) zeta[((long long)mock * (lmax + 1) + l) * nbins * nbins + e] -= (2.0 * l + 1.0) / n6 * s;
 }
 
 // zeta[j][l][e] += scale * sum_w partials[j][w][e]; one block per (e, j),
@@ -1078,13 +1315,25 @@ template <int N, typename T, bool MF>
 hipError_t zpass_nodal_mf(const ZpassArgs& a, hipStream_t st) {
   const int threads = zpass_threads<N, VZN>(a.nbins);
   size_t lds = zpass_nodal_lds<N, T>(a.nbins, threads);
-  const size_t red = (size_t)(threads / 64) * 3 * 256 * sizeof(double);
+  const size_t red = Contractor<T, MF>::scratch_bytes(threads);
   if (lds < red) lds = red;
   hipError_t e = allow_lds(k_zpass_nodal<N, T, MF>, lds);
   if (e != hipSuccess) return e;
   const dim3 gs(a.nwg, a.batch);
   k_zpass_nodal<N, T, MF><<<gs, threads, lds, st>>>(static_cast<const CT<T>*>(a.fields), static_cast<const T*>(a.delta),
                                                    a.partials, a.nbins, a.ppw, static_cast<const CT<T>*>(a.tw));
+  return hipGetLastError();
+}
+
+template <int N, typename T>
+hipError_t zpass_store_t(const ZpassArgs& a, void* out, hipStream_t st) {
+  const int threads = zpass_threads<N, VZN>(a.nbins);
+  const size_t lds = (size_t)a.nbins * zrow<N>() * sizeof(CT<T>) + (size_t)N * sizeof(CT<T>);
+  hipError_t e = allow_lds(k_zpass_store<N, T>, lds);
+  if (e != hipSuccess) return e;
+  const dim3 gs(a.nwg, a.batch);
+  k_zpass_store<N, T><<<gs, threads, lds, st>>>(static_cast<const CT<T>*>(a.fields), static_cast<CT<T>*>(out), a.nbins,
+                                               a.ppw, static_cast<const CT<T>*>(a.tw));
   return hipGetLastError();
 }
 
@@ -1165,6 +1414,9 @@ hipError_t launch_fft_z(int n, int prec, int dir, const void* in, void* out, int
 hipError_t launch_filter_y(int n, int prec, const FilterArgs& a, hipStream_t st) { MP3_DISPATCH(filter_y_t, n, prec, a, st); }
 hipError_t launch_adjoint_y(int n, int prec, const FilterArgs& a, hipStream_t st) { MP3_DISPATCH(adjoint_y_t, n, prec, a, st); }
 hipError_t launch_zpass_nodal(int n, int prec, const ZpassArgs& a, hipStream_t st) { MP3_DISPATCH(zpass_nodal_t, n, prec, a, st); }
+hipError_t launch_zpass_store(int n, int prec, const ZpassArgs& a, void* out, hipStream_t st) {
+  MP3_DISPATCH(zpass_store_t, n, prec, a, out, st);
+}
 hipError_t launch_zpass_adjoint(int n, int prec, const ZpassArgs& a, hipStream_t st) { MP3_DISPATCH(zpass_adjoint_t, n, prec, a, st); }
 
 size_t zpass_lds_need(int n, int prec, int nbins) {
@@ -1256,6 +1508,56 @@ hipError_t launch_gather_dw(int prec, const float* pos, const long long* off, in
   else
     k_gather_dw<float><<<gr, 256, 0, st>>>(pos, off, batch, np_total, n, sc, static_cast<const float*>(g), W, S,
                                            static_cast<float*>(dw));
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_sort(const float* pos, const long long* off, int batch, long long np_total, int n, double sc,
+                            int* counts, int* offs, int* cursor, int* perm, hipStream_t st) {
+  const long long nt = (long long)(n / 4) * (n / 4) * (n / 4) * batch;
+  k_fill<int><<<grid_for(nt, 256, 8192), 256, 0, st>>>(counts, nt, 0);
+  const unsigned g = grid_for(np_total, 256, 16384);
+  k_tile_count<<<g, 256, 0, st>>>(pos, off, batch, np_total, n, sc, counts);
+  k_scan_counts<<<1, 1024, 0, st>>>(counts, offs, cursor, nt);
+  k_tile_scatter<<<g, 256, 0, st>>>(pos, off, batch, np_total, n, sc, cursor, perm);
+  return hipGetLastError();
+}
+
+template <typename T, bool MF>
+hipError_t gather_contract_t(const GatherArgs& a, hipStream_t st) {
+  constexpr int K = 256;
+  const size_t rs = K + K / 16 + 1;
+  size_t lds = (size_t)a.nbins * rs * sizeof(CT<T>) + K * sizeof(T);
+  const size_t red = Contractor<T, MF>::scratch_bytes(256);
+  if (lds < red) lds = red;
+  hipError_t e = allow_lds(k_gather_contract<T, MF>, lds);
+  if (e != hipSuccess) return e;
+  const dim3 gs(a.nwg, a.batch);
+  k_gather_contract<T, MF><<<gs, 256, lds, st>>>(static_cast<const CT<T>*>(a.fields), a.pos, a.w, a.perm, a.off, a.W,
+                                                a.n, a.sc, a.nbins, a.partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_contract(int prec, const GatherArgs& a, hipStream_t st) {
+  if (prec) return gather_contract_t<double, false>(a, st);
+  if (a.nbins <= 32) return gather_contract_t<float, true>(a, st);
+  return gather_contract_t<float, false>(a, st);
+}
+
+hipError_t launch_power_hist(int prec, const void* dhat, int n, int nq2, double* P, int batch, hipStream_t st) {
+  const long long n3 = (long long)n * n * n;
+  const dim3 gs(grid_for(n3, 256, 8192), batch);
+  if (prec) k_power_hist<double><<<gs, 256, 0, st>>>(static_cast<const double2*>(dhat), n, nq2, P);
+  else k_power_hist<float><<<gs, 256, 0, st>>>(static_cast<const float2*>(dhat), n, nq2, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_fbar_subtract(int prec, const double* P, const void* jtab, int nq2, int nbp, int nbins, int l, int lmax,
+                                double n6, double* zeta, int batch, hipStream_t st) {
+  const dim3 gs(nbins * nbins, batch);
+  if (prec)
+    k_fbar_subtract<double><<<gs, 256, 0, st>>>(P, static_cast<const double*>(jtab), nq2, nbp, nbins, l, lmax, n6, zeta);
+  else
+    k_fbar_subtract<float><<<gs, 256, 0, st>>>(P, static_cast<const float*>(jtab), nq2, nbp, nbins, l, lmax, n6, zeta);
   return hipGetLastError();
 }
 

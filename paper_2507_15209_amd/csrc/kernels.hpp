@@ -27,6 +27,25 @@ struct ZpassArgs {
   double wm;            // m weight (1 for m = 0, 2 otherwise)
 };
 
+struct GatherArgs {
+  const void* fields;     // bin-interleaved fields [batch][N^3][nbins]
+  const float* pos;       // [np_total][3]
+  const float* w;         // [np_total] or NULL
+  const int* perm;        // particle order (tile-sorted), [np_total]
+  const long long* off;   // device [batch+1]
+  const double* W;        // device [batch] weight sums
+  double* partials;       // [batch][nwg][nbins^2]
+  int n, nbins, nwg, batch;
+  double sc;              // N / box
+};
+
+hipError_t launch_zpass_store(int n, int prec, const ZpassArgs& a, void* out, hipStream_t st);
+hipError_t launch_tile_sort(const float* pos, const long long* off, int batch, long long np_total, int n, double sc,
+                            int* counts, int* offs, int* cursor, int* perm, hipStream_t st);
+hipError_t launch_gather_contract(int prec, const GatherArgs& a, hipStream_t st);
+hipError_t launch_power_hist(int prec, const void* dhat, int n, int nq2, double* P, int batch, hipStream_t st);
+hipError_t launch_fbar_subtract(int prec, const double* P, const void* jtab, int nq2, int nbp, int nbins, int l, int lmax,
+                                double n6, double* zeta, int batch, hipStream_t st);
 hipError_t launch_fft3d(int n, int prec, int dir, bool real_in, const void* in, void* out, int nfields, const void* tw,
                         hipStream_t st);
 hipError_t launch_fft_x(int n, int prec, int dir, void* buf, int nfields, const void* tw, hipStream_t st);

@@ -57,20 +57,37 @@ constexpr int kTargetWorkgroups = 4096;
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t off, W, S, dhat, fields, partials, G, direct, lam, total;
+  size_t off, W, S, dhat, fields, partials, G, direct, lam, fields_i, perm, counts, offs, cursor, power, total;
   int nwg, ppw;
 };
 
-Layout layout(const mp3_plan_s* p) {
+constexpr int kGatherSlice = 256;
+
+// workgroups per mock of the particle gather: at least four slices each
+int gather_wgs(const mp3_plan_s* p, long long np_max) {
+  long long g = (np_max + 4LL * kGatherSlice - 1) / (4LL * kGatherSlice);
+  long long cap = kTargetWorkgroups / p->batch;
+  if (cap < 1) cap = 1;
+  if (g > cap) g = cap;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+Layout layout(const mp3_plan_s* p, long long np_total = 0) {
   Layout L{};
   const size_t n3 = (size_t)p->n * p->n * p->n;
   const size_t B = (size_t)p->batch;
+  const size_t nb2 = (size_t)p->nbins * p->nbins;
   const long long pencils = (long long)p->n * p->n;
   long long nwg = kTargetWorkgroups / p->batch;
   if (nwg < 1) nwg = 1;
   if (nwg > pencils) nwg = pencils;
   L.ppw = (int)((pencils + nwg - 1) / nwg);
   L.nwg = (int)((pencils + L.ppw - 1) / L.ppw);
+  // partial sums: one per workgroup of the z pass or of the particle gather
+  size_t pw = (size_t)L.nwg;
+  const size_t gw = (size_t)(kTargetWorkgroups / p->batch > 1 ? kTargetWorkgroups / p->batch : 1);
+  if (p->summation == MP3_SUM_PARTICLE && gw > pw) pw = gw;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t r = o;
@@ -82,10 +99,19 @@ Layout layout(const mp3_plan_s* p) {
   L.S = take(B * sizeof(double));
   L.dhat = take(B * n3 * p->celt);
   L.fields = take(B * (size_t)p->nbins * n3 * p->celt);
-  L.partials = take(B * (size_t)L.nwg * p->nbins * p->nbins * sizeof(double));
+  L.partials = take(B * pw * nb2 * sizeof(double));
   L.G = take(B * n3 * p->celt);
   L.direct = take(B * n3 * p->elt);
-  L.lam = take(B * (size_t)p->nbins * p->nbins * p->elt);
+  L.lam = take(B * nb2 * p->elt);
+  if (p->summation == MP3_SUM_PARTICLE) {
+    const size_t nt = (size_t)(p->n / 4) * (p->n / 4) * (p->n / 4) * B + 1;
+    L.fields_i = take(B * (size_t)p->nbins * n3 * p->celt);
+    L.perm = take((size_t)(np_total > 0 ? np_total : 1) * sizeof(int));
+    L.counts = take(nt * sizeof(int));
+    L.offs = take(nt * sizeof(int));
+    L.cursor = take(nt * sizeof(int));
+    L.power = take(B * (size_t)mp3::nq2_count(p->n) * sizeof(double));
+  }
   L.total = o;
   return L;
 }
@@ -226,7 +252,8 @@ int mp3_plan_create(const mp3_plan_desc* d, mp3_plan_t* out) {
     if (b > 0 && !(d->edges[b] > d->edges[b - 1])) return fail(MP3_EINVAL, "edges must increase strictly");
   }
   if (d->precision != MP3_F32 && d->precision != MP3_F64) return fail(MP3_EINVAL, "precision must be MP3_F32 or MP3_F64");
-  if (d->summation != MP3_SUM_NODAL) return fail(MP3_EUNSUPPORTED, "summation form not supported");
+  if (d->summation != MP3_SUM_NODAL && d->summation != MP3_SUM_PARTICLE)
+    return fail(MP3_EUNSUPPORTED, "summation form not supported");
   if (d->batch < 1) return fail(MP3_EINVAL, "batch must be >= 1");
   if (mp3::zpass_lds_need(d->n, d->precision, d->nbins) > kLdsLimit)
     return fail(MP3_EUNSUPPORTED, "n * nbins too large for the z pass's LDS at this precision");
@@ -333,7 +360,7 @@ int mp3_workspace_size(mp3_plan_t p, int64_t np_total, size_t* bytes) {
   if (int s = check_plan(p)) return s;
   if (!bytes) return fail(MP3_EINVAL, "bytes is NULL");
   if (np_total < 0) return fail(MP3_EINVAL, "np_total must be >= 0");
-  *bytes = layout(p).total;
+  *bytes = layout(p, np_total).total;
   return MP3_OK;
 }
 
@@ -344,7 +371,7 @@ int mp3_deposit(mp3_plan_t p, const float* pos, const float* w, const int64_t* n
   if (int s = check_offsets(p, np_off, &np_total, &np_max)) return s;
   if (!pos) return fail(MP3_EINVAL, "pos is NULL");
   if (!delta) return fail(MP3_EINVAL, "delta is NULL");
-  const Layout L = layout(p);
+  const Layout L = layout(p, np_total);
   if (int s = check_ws(p, ws, wsb, L.total)) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const long long n3 = (long long)p->n * p->n * p->n;
@@ -373,16 +400,11 @@ int mp3_multipole_fields(mp3_plan_t p, const void* delta, int32_t l, int32_t m, 
   return MP3_OK;
 }
 
-int mp3_zeta(mp3_plan_t p, const void* delta, double* zeta, void* ws, size_t wsb, void* stream) {
-  if (int s = check_plan(p)) return s;
-  if (!delta || !zeta) return fail(MP3_EINVAL, "delta and zeta must not be NULL");
-  const Layout L = layout(p);
-  if (int s = check_ws(p, ws, wsb, L.total)) return s;
-  hipStream_t st = static_cast<hipStream_t>(stream);
+namespace {
+
+int zeta_nodal(mp3_plan_t p, const void* delta, double* zeta, void* ws, const Layout& L, hipStream_t st) {
   const int nb2 = p->nbins * p->nbins;
   const double n3 = (double)p->n * p->n * p->n;
-  if (int s = forward_dft(p, delta, ws, L, st)) return s;
-  MP3_HIP(mp3::launch_fill_f64(zeta, (long long)p->batch * (p->lmax + 1) * nb2, 0.0, st), "zero zeta");
   void* F = at(ws, L.fields);
   double* partials = reinterpret_cast<double*>(at(ws, L.partials));
   for (int l = 0; l <= p->lmax; ++l) {
@@ -408,16 +430,95 @@ int mp3_zeta(mp3_plan_t p, const void* delta, double* zeta, void* ws, size_t wsb
   return MP3_OK;
 }
 
+// particle summation: zeta_l = 4 pi [ (1/W) sum_i w_i F_l(x_i) - Fbar_l ]
+int zeta_particle(mp3_plan_t p, const float* pos, const float* w, const int64_t* np_off, long long np_total,
+                  long long np_max, double* zeta, void* ws, const Layout& L, hipStream_t st) {
+  const int nb2 = p->nbins * p->nbins;
+  const double n3 = (double)p->n * p->n * p->n;
+  const double sc = (double)p->n / p->box;
+  if (int s = upload_offsets(p, np_off, ws, L, st)) return s;
+  const long long* off = reinterpret_cast<const long long*>(at(ws, L.off));
+  double* W = reinterpret_cast<double*>(at(ws, L.W));
+  MP3_HIP(mp3::launch_fill_f64(W, p->batch, 0.0, st), "zero W");
+  MP3_HIP(mp3::launch_weight_sum(w, off, p->batch, np_max, W, st), "weight sum");
+  int* perm = reinterpret_cast<int*>(at(ws, L.perm));
+  MP3_HIP(mp3::launch_tile_sort(pos, off, p->batch, np_total, p->n, sc, reinterpret_cast<int*>(at(ws, L.counts)),
+                                reinterpret_cast<int*>(at(ws, L.offs)), reinterpret_cast<int*>(at(ws, L.cursor)), perm, st),
+          "tile sort");
+  double* P = reinterpret_cast<double*>(at(ws, L.power));
+  const int nq2 = mp3::nq2_count(p->n);
+  MP3_HIP(mp3::launch_fill_f64(P, (long long)p->batch * nq2, 0.0, st), "zero power");
+  MP3_HIP(mp3::launch_power_hist(p->prec, at(ws, L.dhat), p->n, nq2, P, p->batch, st), "power histogram");
+  void* F = at(ws, L.fields);
+  void* Fi = at(ws, L.fields_i);
+  double* partials = reinterpret_cast<double*>(at(ws, L.partials));
+  const int gwg = gather_wgs(p, np_max);
+  for (int l = 0; l <= p->lmax; ++l) {
+    for (int m = 0; m <= l; ++m) {
+      if (int s = fields_xy(p, ws, L, F, l, m, st)) return s;
+      mp3::ZpassArgs z{};
+      z.fields = F;
+      z.tw = p->tw;
+      z.nbins = p->nbins;
+      z.nwg = L.nwg;
+      z.ppw = L.ppw;
+      z.batch = p->batch;
+      MP3_HIP(timed(p, MP3_PASS_Z_STORE, st, [&] { return mp3::launch_zpass_store(p->n, p->prec, z, Fi, st); }), "z pass (store)");
+      mp3::GatherArgs g{};
+      g.fields = Fi;
+      g.pos = pos;
+      g.w = w;
+      g.perm = perm;
+      g.off = off;
+      g.W = W;
+      g.partials = partials;
+      g.n = p->n;
+      g.nbins = p->nbins;
+      g.nwg = gwg;
+      g.batch = p->batch;
+      g.sc = sc;
+      MP3_HIP(timed(p, MP3_PASS_GATHER, st, [&] { return mp3::launch_gather_contract(p->prec, g, st); }), "gather");
+      const double wm = m == 0 ? 1.0 : 2.0;
+      MP3_HIP(mp3::launch_reduce_partials(partials, gwg, nb2, zeta, l, p->lmax, wm * kFourPi, p->batch, st), "reduce");
+    }
+    MP3_HIP(mp3::launch_fbar_subtract(p->prec, P, p->jtab, nq2, p->nbp, p->nbins, l, p->lmax, n3 * n3, zeta, p->batch, st),
+            "volume mean");
+  }
+  return MP3_OK;
+}
+
+}  // namespace
+
+int mp3_zeta(mp3_plan_t p, const void* delta, const float* pos, const float* w, const int64_t* np_off, double* zeta,
+             void* ws, size_t wsb, void* stream) {
+  if (int s = check_plan(p)) return s;
+  if (!delta || !zeta) return fail(MP3_EINVAL, "delta and zeta must not be NULL");
+  long long np_total = 0, np_max = 0;
+  if (p->summation == MP3_SUM_PARTICLE) {
+    if (int s = check_offsets(p, np_off, &np_total, &np_max)) return s;
+    if (!pos) return fail(MP3_EINVAL, "pos is NULL (particle summation needs the catalogue)");
+    if (np_total >= (1LL << 31)) return fail(MP3_EUNSUPPORTED, "more than 2^31 - 1 particles");
+  }
+  const Layout L = layout(p, np_total);
+  if (int s = check_ws(p, ws, wsb, L.total)) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int s = forward_dft(p, delta, ws, L, st)) return s;
+  MP3_HIP(mp3::launch_fill_f64(zeta, (long long)p->batch * (p->lmax + 1) * p->nbins * p->nbins, 0.0, st), "zero zeta");
+  if (p->summation == MP3_SUM_PARTICLE) return zeta_particle(p, pos, w, np_off, np_total, np_max, zeta, ws, L, st);
+  return zeta_nodal(p, delta, zeta, ws, L, st);
+}
+
 int mp3_zeta_backward(mp3_plan_t p, const void* delta, const double* dzeta, void* ddelta, const float* pos,
                       const float* w, const int64_t* np_off, void* dw, void* ws, size_t wsb, void* stream) {
   if (int s = check_plan(p)) return s;
   if (!delta || !dzeta || !ddelta) return fail(MP3_EINVAL, "delta, dzeta and ddelta must not be NULL");
+  if (p->summation != MP3_SUM_NODAL) return fail(MP3_EUNSUPPORTED, "the adjoint is implemented for the nodal form");
   long long np_total = 0, np_max = 0;
   if (dw) {
     if (int s = check_offsets(p, np_off, &np_total, &np_max)) return s;
     if (!pos) return fail(MP3_EINVAL, "pos is NULL while dw is requested");
   }
-  const Layout L = layout(p);
+  const Layout L = layout(p, np_total);
   if (int s = check_ws(p, ws, wsb, L.total)) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const long long n3 = (long long)p->n * p->n * p->n;

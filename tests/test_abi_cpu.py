@@ -63,7 +63,7 @@ def test_null_arguments_are_rejected():
     lib = _lib.load()
     h = ctypes.c_void_p()
     assert lib.mp3_plan_create(None, ctypes.byref(h)) == _lib.MP3_EINVAL
-    assert lib.mp3_zeta(None, None, None, None, 0, None) == _lib.MP3_EINVAL
+    assert lib.mp3_zeta(None, None, None, None, None, None, None, 0, None) == _lib.MP3_EINVAL
     sz = ctypes.c_size_t()
     assert lib.mp3_workspace_size(None, 0, ctypes.byref(sz)) == _lib.MP3_EINVAL
     assert lib.mp3_plan_destroy(None) == _lib.MP3_OK
