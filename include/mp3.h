@@ -69,6 +69,8 @@ enum mp3_precision { MP3_F32 = 0, MP3_F64 = 1 };
 enum mp3_summation {
   MP3_SUM_NODAL = 0,      /* grid summation on the nodes (connection coefficients
                              lumped onto the primary node)                          */
+  MP3_SUM_GRID_GAMMA = 1, /* grid summation with the B-spline connection
+                             coefficients (Eqs. con-coeff, SFC-3PCF)                 */
   MP3_SUM_PARTICLE = 2    /* particle summation: primary vertex on the catalogue    */
 };
 
@@ -128,6 +130,13 @@ int mp3_multipole_fields(mp3_plan_t plan, const void* delta, int32_t l, int32_t 
  *   zeta_l[b1,b2] = (4 pi / N^3) sum_x delta_x sum_{m=-l}^{l} a_{lm,b1}(x) conj(a_{lm,b2}(x)).
  *   pos, w and np_off are ignored (may be NULL).
  *
+ * MP3_SUM_GRID_GAMMA (Eqs. con-coeff, SFC-3PCF, 3PCF-multipole-sum):
+ *   zeta_l[b1,b2] = (4 pi / N^3) sum_x delta_x sum_m sum_{s,t} Gamma_{s,t}
+ *                   a_{lm,b1}(x+s) conj(a_{lm,b2}(x+t)),
+ *   Gamma_{s,t} = prod_d int B3(u) B3(u - s_d) B3(u - t_d) du, evaluated exactly
+ *   as the integral of the three B-spline interpolants (5-point Gauss-Legendre
+ *   per cell and axis).  pos, w, np_off ignored.
+ *
  * MP3_SUM_PARTICLE (Sec. 2.2, the particle sum after Eq. DDD-sum-privertex; the
  * primary vertex is the catalogue's contrast n/nbar - 1):
  *   zeta_l[b1,b2] = 4 pi [ (1/W) sum_i w_i F_l(x_i) - Fbar_l ],
@@ -169,7 +178,8 @@ enum mp3_pass {
   MP3_PASS_DEPOSIT = 6,    /* B-spline scatter of the catalogue                                */
   MP3_PASS_Z_STORE = 7,    /* z-transform, fields stored bin-interleaved (particle form)       */
   MP3_PASS_GATHER = 8,     /* B-spline gather at the particles + contraction                   */
-  MP3_NPASS = 9
+  MP3_PASS_GAMMA = 9,      /* grid-Gamma quadrature contraction                                */
+  MP3_NPASS = 10
 };
 
 /* Per-pass timing for measurement: with enable != 0 every pass launch of

@@ -37,11 +37,12 @@ class Plan:
 
     precision "f32": fields, FFTs and window in float32 (tables generated in
     float64, reductions in float64); "f64": the plain float64 form.
-    summation "nodal": grid summation on the nodes; "particle": primary vertex
-    on the catalogue (zeta() then needs pos, w, np_off).
+    summation "nodal": grid summation on the nodes; "gamma": grid summation
+    with the B-spline connection coefficients; "particle": primary vertex on
+    the catalogue (zeta() then needs pos, w, np_off).
     """
 
-    SUMMATIONS = {"nodal": _lib.MP3_SUM_NODAL, "particle": _lib.MP3_SUM_PARTICLE}
+    SUMMATIONS = {"nodal": _lib.MP3_SUM_NODAL, "gamma": _lib.MP3_SUM_GRID_GAMMA, "particle": _lib.MP3_SUM_PARTICLE}
 
     def __init__(self, n: int, box: float, lmax: int, edges, precision: str = "f32", batch: int = 1,
                  device=None, summation: str = "nodal"):

@@ -17,6 +17,7 @@ MP3_F32 = 0
 MP3_F64 = 1
 MP3_SUM_NODAL = 0
 MP3_SUM_PARTICLE = 2
+MP3_SUM_GRID_GAMMA = 1
 
 # every entry point of include/mp3.h
 EXPORTS = (
@@ -24,7 +25,7 @@ EXPORTS = (
     "mp3_multipole_fields", "mp3_zeta", "mp3_zeta_backward", "mp3_plan_info",
     "mp3_status_string", "mp3_last_error", "mp3_profile", "mp3_profile_read",
 )
-PASSES = ("dft", "filter", "x", "z_nodal", "z_adjoint", "adjoint", "deposit", "z_store", "gather")
+PASSES = ("dft", "filter", "x", "z_nodal", "z_adjoint", "adjoint", "deposit", "z_store", "gather", "gamma")
 
 
 class PlanDesc(ctypes.Structure):

@@ -891,6 +891,173 @@ __global__ void __launch_bounds__(256) k_gather_contract(const c2<T>* fields, co
              nbins);
 }
 
+// ---------------------------------------------------------------------------
+// grid summation with connection coefficients
+// ---------------------------------------------------------------------------
+// sum_x delta_x sum_{s,t} Gamma(s,t) a(x+s) conj(b(x+t)) equals the integral of
+// the three cubic B-spline interpolants, a degree-9 polynomial per axis on each
+// cell, integrated exactly by 5-point Gauss-Legendre.  A workgroup takes a
+// tile of 4^3 cells, holds the 7^3 coefficients it touches (all bins) in LDS
+// and, per x node, interpolates along x, y (half of the y nodes at a time)
+// and z into LDS rows A[b][node] with weights w_node delta_B(node), which the
+// contraction consumes.  Interpolation weights M[s][t] = B3(xi_s + 1 - t) and
+// node weights are set on the host.
+struct GammaQuad {
+  float m[5][4];     // B3 weight of tap t at node s (node xi_s in the unit cell)
+  float wq[5];       // Gauss-Legendre weights on [0, 1]
+  double md[5][4];
+  double wqd[5];
+};
+
+template <typename T> __device__ __forceinline__ T gq_m(const GammaQuad& q, int s, int t);
+template <> __device__ __forceinline__ float gq_m<float>(const GammaQuad& q, int s, int t) { return q.m[s][t]; }
+template <> __device__ __forceinline__ double gq_m<double>(const GammaQuad& q, int s, int t) { return q.md[s][t]; }
+template <typename T> __device__ __forceinline__ T gq_w(const GammaQuad& q, int s);
+template <> __device__ __forceinline__ float gq_w<float>(const GammaQuad& q, int s) { return q.wq[s]; }
+template <> __device__ __forceinline__ double gq_w<double>(const GammaQuad& q, int s) { return q.wqd[s]; }
+
+constexpr int GT = 4;              // cells per tile edge
+constexpr int GC = GT + 3;         // coefficients per tile edge
+constexpr int GN = 5 * GT;         // quadrature nodes per tile edge
+constexpr int GYH = GN / 2;        // y nodes per half
+constexpr int GK = GYH * GN;       // nodes per contraction slice (200)
+constexpr int GRS = GK + GK / 16 + 1;
+
+template <typename T>
+struct GammaLds {
+  // byte offsets into dynamic LDS for nbins bins
+  size_t C, D, P, Pd, Q, Qd, A, W, total;
+  __host__ __device__ GammaLds(int nbins) {
+    size_t o = 0;
+    auto take = [&](size_t b) { size_t r = o; o = (o + b + 15) & ~(size_t)15; return r; };
+    C = take((size_t)GC * GC * GC * nbins * sizeof(c2<T>));
+    D = take((size_t)GC * GC * GC * sizeof(T));
+    P = take((size_t)GC * GC * nbins * sizeof(c2<T>));
+    Pd = take((size_t)GC * GC * sizeof(T));
+    Q = take((size_t)GYH * GC * nbins * sizeof(c2<T>));
+    Qd = take((size_t)GYH * GC * sizeof(T));
+    A = take((size_t)nbins * GRS * sizeof(c2<T>));
+    W = take((size_t)GK * sizeof(T));
+    total = o;
+  }
+};
+
+template <typename T, bool MF>
+__global__ void __launch_bounds__(512) k_gamma_contract(const c2<T>* fields, const T* delta, int n, int nbins,
+                                                         GammaQuad gq, double* partials) {
+  extern __shared__ __align__(16) char smem[];
+  const GammaLds<T> L(nbins);
+  c2<T>* C = reinterpret_cast<c2<T>*>(smem + L.C);
+  T* D = reinterpret_cast<T*>(smem + L.D);
+  c2<T>* P = reinterpret_cast<c2<T>*>(smem + L.P);
+  T* Pd = reinterpret_cast<T*>(smem + L.Pd);
+  c2<T>* Q = reinterpret_cast<c2<T>*>(smem + L.Q);
+  T* Qd = reinterpret_cast<T*>(smem + L.Qd);
+  c2<T>* A = reinterpret_cast<c2<T>*>(smem + L.A);
+  T* W = reinterpret_cast<T*>(smem + L.W);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const long long mock = blockIdx.y;
+  const long long n3 = (long long)n * n * n;
+  const c2<T>* fm = fields + mock * n3 * nbins;
+  const T* dm = delta + mock * n3;
+  const int td = n / GT;
+  const long long ntiles = (long long)td * td * td;
+  Contractor<T, MF> ctr;
+  ctr.init(nbins);
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int tx = (int)(tile / ((long long)td * td)), ty = (int)((tile / td) % td), tz = (int)(tile % td);
+    const int x0 = tx * GT - 1, y0 = ty * GT - 1, z0 = tz * GT - 1;     // first coefficient (periodic)
+    __syncthreads();
+    for (int e = tid; e < GC * GC * GC * nbins; e += nt) {
+      const int b = e % nbins, c = e / nbins;
+      const int i = c / (GC * GC), j = (c / GC) % GC, k = c % GC;
+      const long long cell = ((long long)wrapi(x0 + i, n) * n + wrapi(y0 + j, n)) * n + wrapi(z0 + k, n);
+      C[e] = fm[cell * nbins + b];
+    }
+    for (int c = tid; c < GC * GC * GC; c += nt) {
+      const int i = c / (GC * GC), j = (c / GC) % GC, k = c % GC;
+      D[c] = dm[((long long)wrapi(x0 + i, n) * n + wrapi(y0 + j, n)) * n + wrapi(z0 + k, n)];
+    }
+    for (int xn = 0; xn < GN; ++xn) {
+      const int cx = xn / 5, sx = xn % 5;
+      __syncthreads();
+      // x interpolation: P[j][k][b], Pd[j][k]
+      for (int e = tid; e < GC * GC * nbins; e += nt) {
+        const int b = e % nbins, jk = e / nbins;
+        c2<T> acc = mk<T>(0, 0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const c2<T> v = C[((cx + t) * GC * GC + jk) * nbins + b];
+          const T m = gq_m<T>(gq, sx, t);
+          acc.x += m * v.x;
+          acc.y += m * v.y;
+        }
+        P[e] = acc;
+      }
+      for (int jk = tid; jk < GC * GC; jk += nt) {
+        T acc = 0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc += gq_m<T>(gq, sx, t) * D[(cx + t) * GC * GC + jk];
+        Pd[jk] = acc;
+      }
+      for (int half = 0; half < 2; ++half) {
+        __syncthreads();
+        // y interpolation for this half of the y nodes: Q[yh][k][b], Qd[yh][k]
+        for (int e = tid; e < GYH * GC * nbins; e += nt) {
+          const int b = e % nbins, yk = e / nbins;
+          const int yh = yk / GC, k = yk % GC;
+          const int yn = half * GYH + yh, cy = yn / 5, sy = yn % 5;
+          c2<T> acc = mk<T>(0, 0);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const c2<T> v = P[((cy + t) * GC + k) * nbins + b];
+            const T m = gq_m<T>(gq, sy, t);
+            acc.x += m * v.x;
+            acc.y += m * v.y;
+          }
+          Q[e] = acc;
+        }
+        for (int yk = tid; yk < GYH * GC; yk += nt) {
+          const int yh = yk / GC, k = yk % GC;
+          const int yn = half * GYH + yh, cy = yn / 5, sy = yn % 5;
+          T acc = 0;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc += gq_m<T>(gq, sy, t) * Pd[(cy + t) * GC + k];
+          Qd[yk] = acc;
+        }
+        __syncthreads();
+        // z interpolation into the contraction rows; weights w_x w_y w_z delta_B
+        for (int e = tid; e < GK * nbins; e += nt) {
+          const int b = e % nbins, node = e / nbins;
+          const int yh = node / GN, zn = node % GN, cz = zn / 5, sz = zn % 5;
+          c2<T> acc = mk<T>(0, 0);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const c2<T> v = Q[(yh * GC + cz + t) * nbins + b];
+            const T m = gq_m<T>(gq, sz, t);
+            acc.x += m * v.x;
+            acc.y += m * v.y;
+          }
+          A[b * GRS + lds_pos<true>(node)] = acc;
+        }
+        for (int node = tid; node < GK; node += nt) {
+          const int yh = node / GN, zn = node % GN, cz = zn / 5, sz = zn % 5;
+          const int sy = (half * GYH + yh) % 5;
+          T acc = 0;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc += gq_m<T>(gq, sz, t) * Qd[yh * GC + cz + t];
+          W[node] = acc * gq_w<T>(gq, sx) * gq_w<T>(gq, sy) * gq_w<T>(gq, sz);
+        }
+        __syncthreads();
+        ctr.add(A, W, nbins, GRS, GK);
+      }
+    }
+  }
+  __syncthreads();
+  ctr.finish(reinterpret_cast<double*>(smem), partials + ((long long)mock * gridDim.x + blockIdx.x) * nbins * nbins,
+             nbins);
+}
+
 // P[mock][s] += |dhat(q)|^2 B7hat(q) over q with |q|^2 = s, Nyquist planes excluded.
 // B7hat(theta) = sum_s B7(s) e^{-i theta s} with the cubic B-spline
 // autocorrelation samples B7(0) = 2416/5040, B7(1) = 1191/5040, B7(2) = 120/5040,
@@ -1559,6 +1726,42 @@ hipError_t launch_fbar_subtract(int prec, const double* P, const void* jtab, int
   else
     k_fbar_subtract<float><<<gs, 256, 0, st>>>(P, static_cast<const float*>(jtab), nq2, nbp, nbins, l, lmax, n6, zeta);
   return hipGetLastError();
+}
+
+template <typename T, bool MF>
+hipError_t gamma_contract_t(const void* fields, const void* delta, int n, int nbins, const GammaQuad& gq,
+                            double* partials, int nwg, int batch, hipStream_t st) {
+  const int threads = 512;
+  size_t lds = GammaLds<T>(nbins).total;
+  const size_t red = Contractor<T, MF>::scratch_bytes(threads);
+  if (lds < red) lds = red;
+  hipError_t e = allow_lds(k_gamma_contract<T, MF>, lds);
+  if (e != hipSuccess) return e;
+  const dim3 gs(nwg, batch);
+  k_gamma_contract<T, MF><<<gs, threads, lds, st>>>(static_cast<const CT<T>*>(fields), static_cast<const T*>(delta), n,
+                                                   nbins, gq, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_gamma_contract(int prec, const void* fields, const void* delta, int n, int nbins,
+                                 const double (*m)[4], const double* wq, double* partials, int nwg, int batch,
+                                 hipStream_t st) {
+  GammaQuad gq;
+  for (int s = 0; s < 5; ++s) {
+    for (int t = 0; t < 4; ++t) {
+      gq.m[s][t] = (float)m[s][t];
+      gq.md[s][t] = m[s][t];
+    }
+    gq.wq[s] = (float)wq[s];
+    gq.wqd[s] = wq[s];
+  }
+  if (prec) return gamma_contract_t<double, false>(fields, delta, n, nbins, gq, partials, nwg, batch, st);
+  if (nbins <= 32) return gamma_contract_t<float, true>(fields, delta, n, nbins, gq, partials, nwg, batch, st);
+  return gamma_contract_t<float, false>(fields, delta, n, nbins, gq, partials, nwg, batch, st);
+}
+
+size_t gamma_lds_need(int prec, int nbins) {
+  return prec ? GammaLds<double>(nbins).total : GammaLds<float>(nbins).total;
 }
 
 }  // namespace mp3

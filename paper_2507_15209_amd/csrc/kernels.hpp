@@ -39,6 +39,12 @@ struct GatherArgs {
   double sc;              // N / box
 };
 
+// grid summation with connection coefficients (5-point Gauss-Legendre per cell);
+// m[s][t] = B3(xi_s + 1 - t), wq[s] node weights on [0, 1]
+hipError_t launch_gamma_contract(int prec, const void* fields, const void* delta, int n, int nbins,
+                                 const double (*m)[4], const double* wq, double* partials, int nwg, int batch,
+                                 hipStream_t st);
+size_t gamma_lds_need(int prec, int nbins);
 hipError_t launch_zpass_store(int n, int prec, const ZpassArgs& a, void* out, hipStream_t st);
 hipError_t launch_tile_sort(const float* pos, const long long* off, int batch, long long np_total, int n, double sc,
                             int* counts, int* offs, int* cursor, int* perm, hipStream_t st);

@@ -21,6 +21,8 @@ struct mp3_plan_s {
   void* tw = nullptr;    // [n] complex
   size_t elt = 4, celt = 8;
   int device = 0;
+  double gm[5][4] = {{0}};   // grid-Gamma quadrature: B3 tap weights at the nodes
+  double gw[5] = {0};        // and node weights
   // optional per-pass HIP event timing
   bool profile = false;
   std::vector<hipEvent_t> pool;
@@ -87,7 +89,7 @@ Layout layout(const mp3_plan_s* p, long long np_total = 0) {
   // partial sums: one per workgroup of the z pass or of the particle gather
   size_t pw = (size_t)L.nwg;
   const size_t gw = (size_t)(kTargetWorkgroups / p->batch > 1 ? kTargetWorkgroups / p->batch : 1);
-  if (p->summation == MP3_SUM_PARTICLE && gw > pw) pw = gw;
+  if (p->summation != MP3_SUM_NODAL && gw > pw) pw = gw;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t r = o;
@@ -103,9 +105,9 @@ Layout layout(const mp3_plan_s* p, long long np_total = 0) {
   L.G = take(B * n3 * p->celt);
   L.direct = take(B * n3 * p->elt);
   L.lam = take(B * nb2 * p->elt);
+  if (p->summation != MP3_SUM_NODAL) L.fields_i = take(B * (size_t)p->nbins * n3 * p->celt);
   if (p->summation == MP3_SUM_PARTICLE) {
     const size_t nt = (size_t)(p->n / 4) * (p->n / 4) * (p->n / 4) * B + 1;
-    L.fields_i = take(B * (size_t)p->nbins * n3 * p->celt);
     L.perm = take((size_t)(np_total > 0 ? np_total : 1) * sizeof(int));
     L.counts = take(nt * sizeof(int));
     L.offs = take(nt * sizeof(int));
@@ -252,8 +254,10 @@ int mp3_plan_create(const mp3_plan_desc* d, mp3_plan_t* out) {
     if (b > 0 && !(d->edges[b] > d->edges[b - 1])) return fail(MP3_EINVAL, "edges must increase strictly");
   }
   if (d->precision != MP3_F32 && d->precision != MP3_F64) return fail(MP3_EINVAL, "precision must be MP3_F32 or MP3_F64");
-  if (d->summation != MP3_SUM_NODAL && d->summation != MP3_SUM_PARTICLE)
+  if (d->summation != MP3_SUM_NODAL && d->summation != MP3_SUM_PARTICLE && d->summation != MP3_SUM_GRID_GAMMA)
     return fail(MP3_EUNSUPPORTED, "summation form not supported");
+  if (d->summation == MP3_SUM_GRID_GAMMA && mp3::gamma_lds_need(d->precision, d->nbins) > kLdsLimit)
+    return fail(MP3_EUNSUPPORTED, "nbins too large for the grid-Gamma tile's LDS at this precision");
   if (d->batch < 1) return fail(MP3_EINVAL, "batch must be >= 1");
   if (mp3::zpass_lds_need(d->n, d->precision, d->nbins) > kLdsLimit)
     return fail(MP3_EUNSUPPORTED, "n * nbins too large for the z pass's LDS at this precision");
@@ -270,6 +274,7 @@ int mp3_plan_create(const mp3_plan_desc* d, mp3_plan_t* out) {
   p->edges.assign(d->edges, d->edges + d->nbins + 1);
   p->nq2 = mp3::nq2_count(p->n);
   p->nbp = (p->nbins + 3) / 4 * 4;
+  mp3::gamma_quadrature(p->gm, p->gw);
   p->elt = p->prec ? sizeof(double) : sizeof(float);
   p->celt = 2 * p->elt;
   hipGetDevice(&p->device);
@@ -487,6 +492,42 @@ int zeta_particle(mp3_plan_t p, const float* pos, const float* w, const int64_t*
   return MP3_OK;
 }
 
+// grid summation with connection coefficients:
+// zeta_l = (4 pi / N^3) int delta_B sum_m atilde_b1 conj(atilde_b2) d^3u
+int zeta_gamma(mp3_plan_t p, const void* delta, double* zeta, void* ws, const Layout& L, hipStream_t st) {
+  const int nb2 = p->nbins * p->nbins;
+  const double n3 = (double)p->n * p->n * p->n;
+  void* F = at(ws, L.fields);
+  void* Fi = at(ws, L.fields_i);
+  double* partials = reinterpret_cast<double*>(at(ws, L.partials));
+  const long long tiles = (long long)(p->n / 4) * (p->n / 4) * (p->n / 4);
+  long long gwg = kTargetWorkgroups / p->batch;
+  if (gwg < 1) gwg = 1;
+  if (gwg > tiles) gwg = tiles;
+  for (int l = 0; l <= p->lmax; ++l) {
+    for (int m = 0; m <= l; ++m) {
+      if (int s = fields_xy(p, ws, L, F, l, m, st)) return s;
+      mp3::ZpassArgs z{};
+      z.fields = F;
+      z.tw = p->tw;
+      z.nbins = p->nbins;
+      z.nwg = L.nwg;
+      z.ppw = L.ppw;
+      z.batch = p->batch;
+      MP3_HIP(timed(p, MP3_PASS_Z_STORE, st, [&] { return mp3::launch_zpass_store(p->n, p->prec, z, Fi, st); }), "z pass (store)");
+      MP3_HIP(timed(p, MP3_PASS_GAMMA, st, [&] {
+                return mp3::launch_gamma_contract(p->prec, Fi, delta, p->n, p->nbins, p->gm, p->gw, partials, (int)gwg,
+                                                  p->batch, st);
+              }),
+              "grid-Gamma contraction");
+      const double wm = m == 0 ? 1.0 : 2.0;
+      MP3_HIP(mp3::launch_reduce_partials(partials, (int)gwg, nb2, zeta, l, p->lmax, wm * kFourPi / n3, p->batch, st),
+              "reduce");
+    }
+  }
+  return MP3_OK;
+}
+
 }  // namespace
 
 int mp3_zeta(mp3_plan_t p, const void* delta, const float* pos, const float* w, const int64_t* np_off, double* zeta,
@@ -505,6 +546,7 @@ int mp3_zeta(mp3_plan_t p, const void* delta, const float* pos, const float* w, 
   if (int s = forward_dft(p, delta, ws, L, st)) return s;
   MP3_HIP(mp3::launch_fill_f64(zeta, (long long)p->batch * (p->lmax + 1) * p->nbins * p->nbins, 0.0, st), "zero zeta");
   if (p->summation == MP3_SUM_PARTICLE) return zeta_particle(p, pos, w, np_off, np_total, np_max, zeta, ws, L, st);
+  if (p->summation == MP3_SUM_GRID_GAMMA) return zeta_gamma(p, delta, zeta, ws, L, st);
   return zeta_nodal(p, delta, zeta, ws, L, st);
 }
 

@@ -138,6 +138,23 @@ void twiddles(int n, std::vector<double>& re, std::vector<double>& im) {
   }
 }
 
+double bspline3(double u) {
+  const double a = std::fabs(u);
+  if (a < 1.0) return (4.0 - 6.0 * a * a + 3.0 * a * a * a) / 6.0;
+  if (a < 2.0) return (2.0 - a) * (2.0 - a) * (2.0 - a) / 6.0;
+  return 0.0;
+}
+
+void gamma_quadrature(double m[5][4], double wq[5]) {
+  std::vector<double> x, w;
+  gauss_legendre(5, x, w);
+  for (int s = 0; s < 5; ++s) {
+    const double xi = 0.5 * (x[s] + 1.0);
+    wq[s] = 0.5 * w[s];
+    for (int t = 0; t < 4; ++t) m[s][t] = bspline3(xi + 1.0 - t);
+  }
+}
+
 double ylm_norm(int l, int m) {
   // sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!) by a running product
   double r = 1.0;

@@ -13,5 +13,9 @@ void sph_bessel_all(int L, double x, double* out);
 void jbar_table(int n, double box, int lmax, const std::vector<double>& edges, std::vector<double>& out);
 void twiddles(int n, std::vector<double>& re, std::vector<double>& im);
 double ylm_norm(int l, int m);
+// centred cubic B-spline
+double bspline3(double u);
+// 5-point Gauss-Legendre nodes xi_s on [0, 1]: m[s][t] = B3(xi_s + 1 - t), weights wq[s]
+void gamma_quadrature(double m[5][4], double wq[5]);
 
 }  // namespace mp3

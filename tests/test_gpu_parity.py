@@ -271,3 +271,34 @@ def test_zeta_particle_batch_uneven(mp3):
     op = E.Plan(n, box, lmax, edges)
     for j, (p_, w_) in enumerate(cats):
         assert_zeta_close(z[j], E.zeta_particle(op, p_, w_), 1e-4)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n,lmax,nb", [(16, 2, 3), (32, 3, 5)])
+def test_zeta_gamma_random_field(mp3, prec, n, lmax, nb):
+    """Grid summation with connection coefficients against the oracle's Delta-stencil form."""
+    _say("gamma", prec, n, lmax, nb)
+    box = 8.0 * n
+    edges = np.linspace(0.06 * box, 0.35 * box, nb + 1)
+    delta = random_field(n, 50 + n)
+    plan = mp3.Plan(n, box, lmax, edges, precision=prec, summation="gamma")
+    rd = torch.float64 if prec == "f64" else torch.float32
+    z = plan.zeta(_dev(delta[None], rd)).cpu().numpy()[0]
+    ref = E.zeta_gamma_quadrature(E.Plan(n, box, lmax, edges), delta)
+    e = assert_zeta_close(z, ref, TOL[prec])
+    print("per-l errors", e)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_zeta_gamma_small_workload(mp3, prec):
+    """Box 250, 32^3, L = 4, 6 bins, 2000-particle mock: the grid-Gamma form of the small workload."""
+    wl = WORKLOADS["box250_n32_l4"]
+    _say("gamma workload", prec)
+    pos, w = workload_catalogue(wl)
+    plan = mp3.Plan(wl.n, wl.box, wl.lmax, wl.edges, precision=prec, summation="gamma")
+    delta = plan.deposit(_dev(pos, torch.float32), _dev(w, torch.float32))
+    z = plan.zeta(delta).cpu().numpy()[0]
+    dref = basis.density_contrast(basis.deposit(pos, w, wl.n, wl.box), float(len(w)))
+    ref = E.zeta_gamma_quadrature(E.Plan(wl.n, wl.box, wl.lmax, wl.edges), dref)
+    e = assert_zeta_close(z, ref, TOL[prec])
+    print("per-l errors", e)
