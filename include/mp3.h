@@ -193,6 +193,36 @@ int mp3_profile(mp3_plan_t plan, int enable);
  * stream up to the last profiled launch). */
 int mp3_profile_read(mp3_plan_t plan, int pass, double* total_ms, int64_t* launches);
 
+/* Launch-shape knobs of a plan.  They change how the work is cut into
+ * workgroups and which FFT radix plan a pass uses, never what is computed
+ * (results agree to rounding order).  Defaults are the values measured best
+ * for the 256^3, L = 10, 20-bin nodal workload on MI355X; the autotuner of
+ * the Python package searches them per (n, nbins, lmax, form, precision,
+ * batch, device) and caches the winners. */
+enum mp3_tune_knob {
+  MP3_TUNE_ZPASS_WGS = 0,     /* workgroups of the z passes per call, split over the batch;
+                                 64 .. 65536, default 4096                                       */
+  MP3_TUNE_CONTRACT_WGS = 1,  /* workgroups of the particle gather and the grid-Gamma
+                                 contraction per call; 64 .. 65536, default 4096                 */
+  MP3_TUNE_FFT_X_PLAN = 2,    /* radix plan of the strided x pass: 0 = largest radix first
+                                 (16 at n = 256), 1 = radix-8 stages; default 0                  */
+  MP3_TUNE_DEPOSIT_TILE = 3,  /* side of the deposit's LDS tile in cells: 4, 8 or 16;
+                                 default 8                                                       */
+  MP3_TUNE_DEPOSIT_WGS = 4,   /* workgroups of the persistent deposit; 64 .. 65536, default 2048
+                                 (never more than there are tiles)                               */
+  MP3_NTUNE = 5
+};
+
+/* Set a knob.  Out-of-range values return MP3_EINVAL and leave the knob as
+ * it was.  The workspace size depends on MP3_TUNE_ZPASS_WGS,
+ * MP3_TUNE_CONTRACT_WGS and MP3_TUNE_DEPOSIT_TILE: query mp3_workspace_size
+ * again after changing them.  Not to be called while work of the plan is in
+ * flight on another thread. */
+int mp3_tune_set(mp3_plan_t plan, int knob, int32_t value);
+
+/* Read a knob's current value into *value. */
+int mp3_tune_get(mp3_plan_t plan, int knob, int32_t* value);
+
 /* Read back the plan's parameters (any out pointer may be NULL). */
 int mp3_plan_info(mp3_plan_t plan, int32_t* n, int32_t* lmax, int32_t* nbins,
                   int32_t* precision, int32_t* batch);

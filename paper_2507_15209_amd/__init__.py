@@ -126,6 +126,19 @@ class Plan:
             out[name] = (ms.value, cnt.value)
         return out
 
+    # -- launch-shape knobs -------------------------------------------------
+    def tune_set(self, knob: str, value: int):
+        _lib.check(self.lib.mp3_tune_set(self._h, _lib.TUNE_KNOBS.index(knob), int(value)), "mp3_tune_set")
+
+    def tune_get(self, knob: str) -> int:
+        v = ctypes.c_int32()
+        _lib.check(self.lib.mp3_tune_get(self._h, _lib.TUNE_KNOBS.index(knob), ctypes.byref(v)), "mp3_tune_get")
+        return v.value
+
+    def tuning(self) -> dict:
+        """All knobs as {name: value}."""
+        return {k: self.tune_get(k) for k in _lib.TUNE_KNOBS}
+
     # -- entry points ------------------------------------------------------
     def deposit(self, pos, w=None, np_off=None):
         self._catalogue(pos, w)

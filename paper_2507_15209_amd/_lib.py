@@ -18,12 +18,15 @@ MP3_F64 = 1
 MP3_SUM_NODAL = 0
 MP3_SUM_PARTICLE = 2
 MP3_SUM_GRID_GAMMA = 1
+# launch-shape knobs (enum mp3_tune_knob)
+TUNE_KNOBS = ("zpass_wgs", "contract_wgs", "fft_x_plan", "deposit_tile", "deposit_wgs")
 
 # every entry point of include/mp3.h
 EXPORTS = (
     "mp3_plan_create", "mp3_plan_destroy", "mp3_workspace_size", "mp3_deposit",
     "mp3_multipole_fields", "mp3_zeta", "mp3_zeta_backward", "mp3_plan_info",
     "mp3_status_string", "mp3_last_error", "mp3_profile", "mp3_profile_read",
+    "mp3_tune_set", "mp3_tune_get",
 )
 PASSES = ("dft", "filter", "x", "z_nodal", "z_adjoint", "adjoint", "deposit", "z_store", "gather", "gamma")
 
@@ -78,6 +81,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.mp3_plan_info.argtypes = [vp] + [ctypes.POINTER(i32)] * 5
     lib.mp3_profile.argtypes = [vp, ctypes.c_int]
     lib.mp3_profile_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    lib.mp3_tune_set.argtypes = [vp, ctypes.c_int, i32]
+    lib.mp3_tune_get.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i32)]
     lib.mp3_status_string.argtypes = [ctypes.c_int]
     lib.mp3_status_string.restype = ctypes.c_char_p
     lib.mp3_last_error.argtypes = []

@@ -1,0 +1,144 @@
+"""Autotuner of the plan's launch-shape knobs.
+
+The knobs (``mp3_tune_knob`` in include/mp3.h) change how the work is cut
+into workgroups and which radix plan the strided x pass uses, never the
+arithmetic.  The tuner times the plan's own calls on the device with events
+on the current stream, descends one knob at a time over a short candidate
+list, keeps the fastest value, and stores the winners in a JSON cache keyed
+by (device, n, nbins, lmax, form, precision, batch) so that a later plan of
+the same configuration starts from them.
+"""
+from __future__ import annotations
+
+import json
+import os
+import tempfile
+
+import torch
+
+from . import _lib
+
+__all__ = ["CANDIDATES", "cache_key", "cache_path", "load_tuning", "save_tuning", "autotune"]
+
+CANDIDATES = {
+    "deposit_tile": (4, 8, 16),
+    "deposit_wgs": (256, 512, 1024, 2048, 4096, 8192),
+    "fft_x_plan": (0, 1),
+    "zpass_wgs": (1024, 2048, 4096, 8192, 16384),
+    "contract_wgs": (1024, 2048, 4096, 8192, 16384),
+}
+
+
+def cache_path(path: str | None = None) -> str:
+    if path:
+        return path
+    env = os.environ.get("MP3_TUNE_CACHE")
+    if env:
+        return env
+    return os.path.join(os.path.expanduser("~"), ".cache", "mp3", "tuning.json")
+
+
+def cache_key(plan) -> str:
+    name = torch.cuda.get_device_name(plan.device) if torch.cuda.is_available() else "nodevice"
+    return (f"{name}|n={plan.n}|nbins={plan.nbins}|lmax={plan.lmax}|{plan.summation}|{plan.precision}"
+            f"|batch={plan.batch}")
+
+
+def _read(path: str) -> dict:
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def load_tuning(plan, path: str | None = None) -> bool:
+    """Apply cached knobs to the plan; False if the cache has none for it."""
+    entry = _read(cache_path(path)).get(cache_key(plan))
+    if not isinstance(entry, dict):
+        return False
+    for k, v in entry.get("knobs", {}).items():
+        if k in _lib.TUNE_KNOBS:
+            plan.tune_set(k, int(v))
+    return True
+
+
+def save_tuning(plan, timings: dict | None = None, path: str | None = None) -> str:
+    """Write the plan's current knobs (and the measured times) into the cache."""
+    path = cache_path(path)
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    data = _read(path)
+    data[cache_key(plan)] = {"knobs": plan.tuning(), "ms": timings or {}}
+    fd, tmp = tempfile.mkstemp(dir=os.path.dirname(path) or ".", suffix=".tmp")
+    with os.fdopen(fd, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+    return path
+
+
+def _time_ms(fn, reps: int) -> float:
+    """Best of ``reps`` timed calls after one untimed call, events on the current stream."""
+    fn()
+    best = float("inf")
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    return best
+
+
+def _descend(plan, knob: str, fn, reps: int, log) -> float:
+    best_v, best_t = plan.tune_get(knob), float("inf")
+    for v in CANDIDATES[knob]:
+        plan.tune_set(knob, v)
+        t = _time_ms(fn, reps)
+        if log:
+            log(f"autotune {knob}={v}: {t:.3f} ms")
+        if t < best_t:
+            best_v, best_t = v, t
+    plan.tune_set(knob, best_v)
+    return best_t
+
+
+def autotune(plan, delta, pos=None, w=None, np_off=None, dzeta=None, backward: bool = True,
+             reps: int = 2, cache: str | None = None, force: bool = False, log=None) -> dict:
+    """Tune ``plan`` on representative inputs and return its knobs.
+
+    delta: a density contrast of the plan's shape (the forward's input).
+    pos, w, np_off: a catalogue; needed by the particle form and for the
+    deposit knobs (skipped without it).  dzeta: the backward's seed (nodal
+    form only; random if None).  With a cache entry for this configuration
+    and ``force`` False the cached knobs are applied and nothing is timed.
+    """
+    if not force and load_tuning(plan, cache):
+        return plan.tuning()
+    with torch.cuda.device(plan.device):
+        times = {}
+        if pos is not None:
+            dep = lambda: plan.deposit(pos, w, np_off)
+            for k in ("deposit_tile", "deposit_wgs"):
+                times[k] = _descend(plan, k, dep, reps, log)
+        cat = (pos, w, np_off) if plan.summation == "particle" else (None, None, None)
+        do_bwd = backward and plan.summation == "nodal"
+        if do_bwd and dzeta is None:
+            g = torch.Generator(device=plan.device).manual_seed(0)
+            dzeta = torch.randn((plan.batch, plan.lmax + 1, plan.nbins, plan.nbins), dtype=torch.float64,
+                                device=plan.device, generator=g)
+
+        def path():
+            plan.zeta(delta, *cat)
+            if do_bwd:
+                plan.zeta_backward(delta, dzeta)
+
+        knobs = ["fft_x_plan", "zpass_wgs"]
+        if plan.summation != "nodal":
+            knobs.append("contract_wgs")
+        for k in knobs:
+            times[k] = _descend(plan, k, path, reps, log)
+    save_tuning(plan, times, cache)
+    return plan.tuning()

@@ -225,35 +225,6 @@ __device__ __forceinline__ Taps make_taps(const float* p, int n, double sc) {
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 template <typename T>
-__global__ void k_deposit(const float* pos, const float* w, const long long* off, int batch, long long np_total,
-                          int n, double sc, T* eps) {
-  const long long n3 = (long long)n * n * n;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < np_total; i += (long long)gridDim.x * blockDim.x) {
-    const int mock = find_mock(off, batch, i);
-    Taps t = make_taps(pos + 3 * i, n, sc);
-    if (!t.ok) continue;
-    const double wi = w ? (double)w[i] : 1.0;
-    T* e = eps + mock * n3;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int ix = wrapi(t.base[0] + a, n);
-      const double wa = wi * t.wt[0][a];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int iy = wrapi(t.base[1] + b, n);
-        const double wab = wa * t.wt[1][b];
-        const long long row = ((long long)ix * n + iy) * n;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int iz = wrapi(t.base[2] + c, n);
-          atomicAdd(&e[row + iz], (T)(wab * t.wt[2][c]));
-        }
-      }
-    }
-  }
-}
-
-template <typename T>
 __global__ void k_normalise(T* eps, const double* W, long long n3) {
   const int j = blockIdx.y;
   const double f = (double)n3 / W[j];
@@ -293,12 +264,12 @@ __global__ void k_gather_dw(const float* pos, const long long* off, int batch, l
 // ---------------------------------------------------------------------------
 // FFT along a strided axis (x: astride = N^2, outer = N; y: astride = N, outer = N^2)
 // ---------------------------------------------------------------------------
-template <int N, typename T, int DIR, bool REAL_IN>
-__global__ void __launch_bounds__((strided_threads<N, T>())) k_fft_strided(const void* in, c2<T>* out, long long fstride_in,
+template <int N, typename T, int DIR, bool REAL_IN, int V = 0>
+__global__ void __launch_bounds__((strided_threads<N, T, V>())) k_fft_strided(const void* in, c2<T>* out, long long fstride_in,
                                                        long long fstride_out, int astride, int outer, const c2<T>* tw) {
-  using F = Fft<N>;
+  using F = Fft<N, V>;
   constexpr int ZC = zc_of<T>();
-  constexpr int G = tiles_per_wg<N, T>();
+  constexpr int G = tiles_per_wg<N, T, V>();
   constexpr int RMAX = F::RMAX;
   __shared__ c2<T> lds[G * N * ZC];
   const int tid = threadIdx.x;
@@ -321,7 +292,7 @@ __global__ void __launch_bounds__((strided_threads<N, T>())) k_fft_strided(const
       else v[r] = static_cast<const c2<T>*>(in)[idx];
     }
   }
-  fft_column<N, DIR, T, false>(v, lds + g * N * ZC + cc, ZC, j, tw, active);
+  fft_column<N, DIR, T, false, V>(v, lds + g * N * ZC + cc, ZC, j, tw, active);
   if (active) {
 #pragma unroll
     for (int e = 0; e < RMAX; ++e)
@@ -763,8 +734,8 @@ __global__ void __launch_bounds__(512) k_zpass_store(const c2<T>* fields, c2<T>*
   }
 }
 
-// particles per 4^3-cell tile (sort key), tile id mock * NT + (tx * NTd + ty) * NTd + tz
-__device__ __forceinline__ int tile_of(const float* p, int n, double sc, int ntd) {
+// particles per (2^shift)^3-cell tile (sort key), tile id mock * NT + (tx * NTd + ty) * NTd + tz
+__device__ __forceinline__ int tile_of(const float* p, int n, double sc, int ntd, int shift) {
   int t = 0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -774,18 +745,18 @@ __device__ __forceinline__ int tile_of(const float* p, int n, double sc, int ntd
     int c = (int)floor(u);
     if (c >= n) c -= n;
     if (c < 0) c = 0;
-    t = t * ntd + (c >> 2);
+    t = t * ntd + (c >> shift);
   }
   return t;
 }
 
 __global__ void k_tile_count(const float* pos, const long long* off, int batch, long long np_total, int n, double sc,
-                             int* counts) {
-  const int ntd = n / 4;
+                             int shift, int* counts) {
+  const int ntd = n >> shift;
   const long long nt = (long long)ntd * ntd * ntd;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < np_total; i += (long long)gridDim.x * blockDim.x) {
     const int mock = find_mock(off, batch, i);
-    atomicAdd(&counts[mock * nt + tile_of(pos + 3 * i, n, sc, ntd)], 1);
+    atomicAdd(&counts[mock * nt + tile_of(pos + 3 * i, n, sc, ntd, shift)], 1);
   }
 }
 
@@ -817,12 +788,12 @@ __global__ void k_scan_counts(const int* counts, int* offs, int* cursor, long lo
 }
 
 __global__ void k_tile_scatter(const float* pos, const long long* off, int batch, long long np_total, int n, double sc,
-                               int* cursor, int* perm) {
-  const int ntd = n / 4;
+                               int shift, int* cursor, int* perm) {
+  const int ntd = n >> shift;
   const long long nt = (long long)ntd * ntd * ntd;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < np_total; i += (long long)gridDim.x * blockDim.x) {
     const int mock = find_mock(off, batch, i);
-    const int slot = atomicAdd(&cursor[mock * nt + tile_of(pos + 3 * i, n, sc, ntd)], 1);
+    const int slot = atomicAdd(&cursor[mock * nt + tile_of(pos + 3 * i, n, sc, ntd, shift)], 1);
     perm[slot] = (int)i;
   }
 }
@@ -1377,18 +1348,23 @@ hipError_t fft3d_t(int dir, bool real_in, const void* in, void* out, int nfields
   return hipGetLastError();
 }
 
-template <int N, typename T>
-hipError_t fft_x_t(int dir, void* buf, int nfields, const void* tw, hipStream_t st) {
+template <int N, typename T, int V>
+hipError_t fft_x_v(int dir, void* buf, int nfields, const void* tw, hipStream_t st) {
   constexpr int ZC = zc_of<T>();
-  constexpr int G = tiles_per_wg<N, T>();
-  constexpr int threads = Fft<N>::TPC * ZC * G;
+  constexpr int G = tiles_per_wg<N, T, V>();
+  constexpr int threads = Fft<N, V>::TPC * ZC * G;
   constexpr long long N3 = (long long)N * N * N;
   const dim3 gs((N * (N / ZC) + G - 1) / G, nfields);
   CT<T>* o = static_cast<CT<T>*>(buf);
   const CT<T>* t = static_cast<const CT<T>*>(tw);
-  if (dir < 0) k_fft_strided<N, T, -1, false><<<gs, threads, 0, st>>>(o, o, N3, N3, N * N, N, t);
-  else k_fft_strided<N, T, +1, false><<<gs, threads, 0, st>>>(o, o, N3, N3, N * N, N, t);
+  if (dir < 0) k_fft_strided<N, T, -1, false, V><<<gs, threads, 0, st>>>(o, o, N3, N3, N * N, N, t);
+  else k_fft_strided<N, T, +1, false, V><<<gs, threads, 0, st>>>(o, o, N3, N3, N * N, N, t);
   return hipGetLastError();
+}
+
+template <int N, typename T>
+hipError_t fft_x_t(int dir, void* buf, int nfields, const void* tw, int variant, hipStream_t st) {
+  return variant ? fft_x_v<N, T, 1>(dir, buf, nfields, tw, st) : fft_x_v<N, T, 0>(dir, buf, nfields, tw, st);
 }
 
 template <int N, typename T>
@@ -1566,8 +1542,8 @@ hipError_t launch_fft3d(int n, int prec, int dir, bool real_in, const void* in, 
   MP3_DISPATCH(fft3d_t, n, prec, dir, real_in, in, out, nfields, tw, st);
 }
 
-hipError_t launch_fft_x(int n, int prec, int dir, void* buf, int nfields, const void* tw, hipStream_t st) {
-  MP3_DISPATCH(fft_x_t, n, prec, dir, buf, nfields, tw, st);
+hipError_t launch_fft_x(int n, int prec, int dir, void* buf, int nfields, const void* tw, int variant, hipStream_t st) {
+  MP3_DISPATCH(fft_x_t, n, prec, dir, buf, nfields, tw, variant, st);
 }
 
 hipError_t launch_fft_y(int n, int prec, int dir, void* buf, int nfields, const void* tw, hipStream_t st) {
@@ -1632,13 +1608,6 @@ hipError_t launch_weight_sum(const float* w, const long long* off, int batch, lo
   return hipGetLastError();
 }
 
-hipError_t launch_deposit(int prec, const float* pos, const float* w, const long long* off, int batch, long long np_total,
-                          int n, double sc, void* eps, hipStream_t st) {
-  const unsigned g = grid_for(np_total, 256, 16384);
-  if (prec) k_deposit<double><<<g, 256, 0, st>>>(pos, w, off, batch, np_total, n, sc, static_cast<double*>(eps));
-  else k_deposit<float><<<g, 256, 0, st>>>(pos, w, off, batch, np_total, n, sc, static_cast<float*>(eps));
-  return hipGetLastError();
-}
 
 hipError_t launch_normalise(int prec, void* eps, const double* W, long long n3, int batch, hipStream_t st) {
   const dim3 gs(grid_for(n3, 256, 4096), batch);
@@ -1679,14 +1648,97 @@ hipError_t launch_gather_dw(int prec, const float* pos, const long long* off, in
 }
 
 hipError_t launch_tile_sort(const float* pos, const long long* off, int batch, long long np_total, int n, double sc,
-                            int* counts, int* offs, int* cursor, int* perm, hipStream_t st) {
-  const long long nt = (long long)(n / 4) * (n / 4) * (n / 4) * batch;
-  k_fill<int><<<grid_for(nt, 256, 8192), 256, 0, st>>>(counts, nt, 0);
+                            int shift, int* counts, int* offs, int* cursor, int* perm, hipStream_t st) {
+  const long long ntd = n >> shift;
+  const long long nt = ntd * ntd * ntd * batch;
+  k_fill<int><<<grid_for(nt + 1, 256, 8192), 256, 0, st>>>(counts, nt + 1, 0);
   const unsigned g = grid_for(np_total, 256, 16384);
-  k_tile_count<<<g, 256, 0, st>>>(pos, off, batch, np_total, n, sc, counts);
-  k_scan_counts<<<1, 1024, 0, st>>>(counts, offs, cursor, nt);
-  k_tile_scatter<<<g, 256, 0, st>>>(pos, off, batch, np_total, n, sc, cursor, perm);
+  k_tile_count<<<g, 256, 0, st>>>(pos, off, batch, np_total, n, sc, shift, counts);
+  k_scan_counts<<<1, 1024, 0, st>>>(counts, offs, cursor, nt + 1);
+  k_tile_scatter<<<g, 256, 0, st>>>(pos, off, batch, np_total, n, sc, shift, cursor, perm);
   return hipGetLastError();
+}
+
+// Tiled deposit: a persistent grid takes TS^3-cell tiles (of every mock) from
+// an atomic work counter, accumulates the tile's particles into an LDS block
+// of (TS + 3)^3 nodes (the tile plus the B-spline halo) and flushes it with
+// one global atomic per touched node.  Every workgroup leaves when the
+// counter passes the number of tiles.  The particles of a tile were sorted
+// there by the same cell arithmetic as make_taps, so their taps stay inside
+// the block.
+template <typename T, int TS>
+__global__ void __launch_bounds__(256) k_deposit_tiled(const float* pos, const float* w, const int* perm,
+                                                       const int* toff, int ntiles_total, int* counter, int n,
+                                                       double sc, T* eps) {
+  constexpr int TB = TS + 3;
+  __shared__ T acc[TB * TB * TB];
+  __shared__ int item_sh;
+  const int ntd = n / TS;
+  const int nt = ntd * ntd * ntd;
+  const long long n3 = (long long)n * n * n;
+  for (;;) {
+    if (threadIdx.x == 0) item_sh = atomicAdd(counter, 1);
+    __syncthreads();
+    const int item = item_sh;
+    __syncthreads();                               // item_sh is rewritten by the next take
+    if (item >= ntiles_total) break;
+    const int a = toff[item], b = toff[item + 1];
+    if (a == b) continue;                          // empty tile: nothing to add
+    const int mock = item / nt, t = item % nt;
+    const int tx = t / (ntd * ntd), ty = (t / ntd) % ntd, tz = t % ntd;
+    const int ox = tx * TS - 1, oy = ty * TS - 1, oz = tz * TS - 1;   // node of local index 0
+    for (int c = threadIdx.x; c < TB * TB * TB; c += blockDim.x) acc[c] = (T)0;
+    __syncthreads();
+    for (int k = a + threadIdx.x; k < b; k += blockDim.x) {
+      const int i = perm[k];
+      Taps tp = make_taps(pos + 3 * (long long)i, n, sc);
+      if (!tp.ok) continue;
+      const double wi = w ? (double)w[i] : 1.0;
+      const int lx = tp.base[0] - ox, ly = tp.base[1] - oy, lz = tp.base[2] - oz;   // in [0, TS)
+#pragma unroll
+      for (int ax = 0; ax < 4; ++ax) {
+        const double wa = wi * tp.wt[0][ax];
+#pragma unroll
+        for (int ay = 0; ay < 4; ++ay) {
+          const double wab = wa * tp.wt[1][ay];
+          T* row = acc + ((lx + ax) * TB + (ly + ay)) * TB + lz;
+#pragma unroll
+          for (int az = 0; az < 4; ++az) atomicAdd(&row[az], (T)(wab * tp.wt[2][az]));
+        }
+      }
+    }
+    __syncthreads();
+    T* em = eps + (long long)mock * n3;
+    for (int c = threadIdx.x; c < TB * TB * TB; c += blockDim.x) {
+      const T v = acc[c];
+      if (v != (T)0) {
+        const int i = c / (TB * TB), j = (c / TB) % TB, k = c % TB;
+        atomicAdd(&em[((long long)wrapi(ox + i, n) * n + wrapi(oy + j, n)) * n + wrapi(oz + k, n)], v);
+      }
+    }
+    __syncthreads();                               // acc is cleared by the next tile
+  }
+}
+
+template <typename T>
+hipError_t deposit_tiled_t(int tside, const float* pos, const float* w, const int* perm, const int* toff,
+                           int ntiles_total, unsigned g, int* counter, int n, double sc, T* eps, hipStream_t st) {
+  switch (tside) {
+    case 4: k_deposit_tiled<T, 4><<<g, 256, 0, st>>>(pos, w, perm, toff, ntiles_total, counter, n, sc, eps); break;
+    case 8: k_deposit_tiled<T, 8><<<g, 256, 0, st>>>(pos, w, perm, toff, ntiles_total, counter, n, sc, eps); break;
+    case 16: k_deposit_tiled<T, 16><<<g, 256, 0, st>>>(pos, w, perm, toff, ntiles_total, counter, n, sc, eps); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_deposit_tiled(int prec, int tside, const float* pos, const float* w, const int* perm, const int* toff,
+                                int ntiles_total, int wgs, int* counter, int n, double sc, void* eps, hipStream_t st) {
+  if (ntiles_total <= 0 || wgs <= 0 || tside <= 0 || n % tside != 0) return hipErrorInvalidValue;
+  k_fill<int><<<1, 64, 0, st>>>(counter, 1, 0);
+  const unsigned g = (unsigned)(ntiles_total < wgs ? ntiles_total : wgs);
+  if (prec) return deposit_tiled_t<double>(tside, pos, w, perm, toff, ntiles_total, g, counter, n, sc, static_cast<double*>(eps), st);
+  return deposit_tiled_t<float>(tside, pos, w, perm, toff, ntiles_total, g, counter, n, sc, static_cast<float*>(eps), st);
 }
 
 template <typename T, bool MF>

@@ -46,15 +46,21 @@ hipError_t launch_gamma_contract(int prec, const void* fields, const void* delta
                                  hipStream_t st);
 size_t gamma_lds_need(int prec, int nbins);
 hipError_t launch_zpass_store(int n, int prec, const ZpassArgs& a, void* out, hipStream_t st);
+// counting sort of the particles by (2^shift)^3-cell tile of their mock; offs
+// gets batch * (n >> shift)^3 + 1 exclusive tile offsets
 hipError_t launch_tile_sort(const float* pos, const long long* off, int batch, long long np_total, int n, double sc,
-                            int* counts, int* offs, int* cursor, int* perm, hipStream_t st);
+                            int shift, int* counts, int* offs, int* cursor, int* perm, hipStream_t st);
+// persistent tiled deposit over tiles of side tside (4, 8, 16) with at most
+// wgs workgroups; toff from launch_tile_sort with shift log2(tside)
+hipError_t launch_deposit_tiled(int prec, int tside, const float* pos, const float* w, const int* perm, const int* toff,
+                                int ntiles_total, int wgs, int* counter, int n, double sc, void* eps, hipStream_t st);
 hipError_t launch_gather_contract(int prec, const GatherArgs& a, hipStream_t st);
 hipError_t launch_power_hist(int prec, const void* dhat, int n, int nq2, double* P, int batch, hipStream_t st);
 hipError_t launch_fbar_subtract(int prec, const double* P, const void* jtab, int nq2, int nbp, int nbins, int l, int lmax,
                                 double n6, double* zeta, int batch, hipStream_t st);
 hipError_t launch_fft3d(int n, int prec, int dir, bool real_in, const void* in, void* out, int nfields, const void* tw,
                         hipStream_t st);
-hipError_t launch_fft_x(int n, int prec, int dir, void* buf, int nfields, const void* tw, hipStream_t st);
+hipError_t launch_fft_x(int n, int prec, int dir, void* buf, int nfields, const void* tw, int variant, hipStream_t st);
 hipError_t launch_fft_y(int n, int prec, int dir, void* buf, int nfields, const void* tw, hipStream_t st);
 hipError_t launch_fft_z(int n, int prec, int dir, const void* in, void* out, int nfields, const void* tw, hipStream_t st);
 hipError_t launch_filter_y(int n, int prec, const FilterArgs& a, hipStream_t st);
@@ -69,8 +75,6 @@ hipError_t launch_lam_sym(int prec, const double* dzeta, void* lam_s, int nbins,
 hipError_t launch_reduce_partials(const double* partials, int nwg, int nb2, double* zeta, int l, int lmax, double scale,
                                   int batch, hipStream_t st);
 hipError_t launch_weight_sum(const float* w, const long long* off, int batch, long long np_max, double* W, hipStream_t st);
-hipError_t launch_deposit(int prec, const float* pos, const float* w, const long long* off, int batch, long long np_total,
-                          int n, double sc, void* eps, hipStream_t st);
 hipError_t launch_normalise(int prec, void* eps, const double* W, long long n3, int batch, hipStream_t st);
 hipError_t launch_grad_combine(int prec, const void* direct, const void* ghat, void* ddelta, long long count, double scale,
                                hipStream_t st);

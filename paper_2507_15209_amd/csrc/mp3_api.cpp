@@ -23,6 +23,7 @@ struct mp3_plan_s {
   int device = 0;
   double gm[5][4] = {{0}};   // grid-Gamma quadrature: B3 tap weights at the nodes
   double gw[5] = {0};        // and node weights
+  int tune[MP3_NTUNE] = {4096, 4096, 0, 8, 2048};   // launch-shape knobs (mp3_tune_knob)
   // optional per-pass HIP event timing
   bool profile = false;
   std::vector<hipEvent_t> pool;
@@ -54,12 +55,12 @@ int hip_fail(hipError_t e, const char* where) {
 
 constexpr double kFourPi = 12.566370614359172953850573533118011536788677597500;
 constexpr size_t kLdsLimit = 160 * 1024;
-constexpr int kTargetWorkgroups = 4096;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t off, W, S, dhat, fields, partials, G, direct, lam, fields_i, perm, counts, offs, cursor, power, total;
+  size_t off, W, S, dhat, fields, partials, G, direct, lam, fields_i, perm, counts, offs, cursor, power;
+  size_t dperm, dcounts, doffs, dcursor, dcounter, total;
   int nwg, ppw;
 };
 
@@ -68,12 +69,25 @@ constexpr int kGatherSlice = 256;
 // workgroups per mock of the particle gather: at least four slices each
 int gather_wgs(const mp3_plan_s* p, long long np_max) {
   long long g = (np_max + 4LL * kGatherSlice - 1) / (4LL * kGatherSlice);
-  long long cap = kTargetWorkgroups / p->batch;
+  long long cap = p->tune[MP3_TUNE_CONTRACT_WGS] / p->batch;
   if (cap < 1) cap = 1;
   if (g > cap) g = cap;
   if (g < 1) g = 1;
   return (int)g;
 }
+
+// workgroups per mock of the grid-Gamma contraction and the gather partials
+size_t contract_wgs(const mp3_plan_s* p) {
+  const int g = p->tune[MP3_TUNE_CONTRACT_WGS] / p->batch;
+  return (size_t)(g > 1 ? g : 1);
+}
+
+size_t deposit_tiles(const mp3_plan_s* p) {
+  const size_t t = (size_t)(p->n / p->tune[MP3_TUNE_DEPOSIT_TILE]);
+  return t * t * t * (size_t)p->batch;
+}
+
+int tile_shift(int side) { return side == 4 ? 2 : (side == 8 ? 3 : 4); }
 
 Layout layout(const mp3_plan_s* p, long long np_total = 0) {
   Layout L{};
@@ -81,14 +95,14 @@ Layout layout(const mp3_plan_s* p, long long np_total = 0) {
   const size_t B = (size_t)p->batch;
   const size_t nb2 = (size_t)p->nbins * p->nbins;
   const long long pencils = (long long)p->n * p->n;
-  long long nwg = kTargetWorkgroups / p->batch;
+  long long nwg = p->tune[MP3_TUNE_ZPASS_WGS] / p->batch;
   if (nwg < 1) nwg = 1;
   if (nwg > pencils) nwg = pencils;
   L.ppw = (int)((pencils + nwg - 1) / nwg);
   L.nwg = (int)((pencils + L.ppw - 1) / L.ppw);
   // partial sums: one per workgroup of the z pass or of the particle gather
   size_t pw = (size_t)L.nwg;
-  const size_t gw = (size_t)(kTargetWorkgroups / p->batch > 1 ? kTargetWorkgroups / p->batch : 1);
+  const size_t gw = contract_wgs(p);
   if (p->summation != MP3_SUM_NODAL && gw > pw) pw = gw;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -114,6 +128,14 @@ Layout layout(const mp3_plan_s* p, long long np_total = 0) {
     L.cursor = take(nt * sizeof(int));
     L.power = take(B * (size_t)mp3::nq2_count(p->n) * sizeof(double));
   }
+  // tiled deposit, last so that the offsets above do not depend on the
+  // number of particles of the nodal and grid forms
+  const size_t ntd = deposit_tiles(p) + 1;
+  L.dperm = take((size_t)(np_total > 0 ? np_total : 1) * sizeof(int));
+  L.dcounts = take(ntd * sizeof(int));
+  L.doffs = take(ntd * sizeof(int));
+  L.dcursor = take(ntd * sizeof(int));
+  L.dcounter = take(sizeof(int));
   L.total = o;
   return L;
 }
@@ -220,7 +242,7 @@ int fields_xy(const mp3_plan_s* p, void* ws, const Layout& L, void* dst, int l, 
   const double n3 = (double)p->n * p->n * p->n;
   mp3::FilterArgs a = filter_args(p, at(ws, L.dhat), dst, l, m, 1.0 / n3);
   MP3_HIP(timed(p, MP3_PASS_FILTER, st, [&] { return mp3::launch_filter_y(p->n, p->prec, a, st); }), "window pass");
-  MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, dst, p->batch * p->nbins, p->tw, st); }), "x pass");
+  MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, dst, p->batch * p->nbins, p->tw, p->tune[MP3_TUNE_FFT_X_PLAN], st); }), "x pass");
   return MP3_OK;
 }
 
@@ -351,6 +373,35 @@ int mp3_plan_destroy(mp3_plan_t p) {
   return MP3_OK;
 }
 
+int mp3_tune_set(mp3_plan_t p, int knob, int32_t value) {
+  if (int s = check_plan(p)) return s;
+  switch (knob) {
+    case MP3_TUNE_ZPASS_WGS:
+    case MP3_TUNE_CONTRACT_WGS:
+    case MP3_TUNE_DEPOSIT_WGS:
+      if (value < 64 || value > 65536) return fail(MP3_EINVAL, "workgroup count must lie in 64 .. 65536");
+      break;
+    case MP3_TUNE_FFT_X_PLAN:
+      if (value != 0 && value != 1) return fail(MP3_EINVAL, "x-pass radix plan must be 0 or 1");
+      break;
+    case MP3_TUNE_DEPOSIT_TILE:
+      if (value != 4 && value != 8 && value != 16) return fail(MP3_EINVAL, "deposit tile side must be 4, 8 or 16");
+      break;
+    default:
+      return fail(MP3_EINVAL, "unknown tuning knob");
+  }
+  p->tune[knob] = value;
+  return MP3_OK;
+}
+
+int mp3_tune_get(mp3_plan_t p, int knob, int32_t* value) {
+  if (int s = check_plan(p)) return s;
+  if (knob < 0 || knob >= MP3_NTUNE) return fail(MP3_EINVAL, "unknown tuning knob");
+  if (!value) return fail(MP3_EINVAL, "value must not be NULL");
+  *value = p->tune[knob];
+  return MP3_OK;
+}
+
 int mp3_plan_info(mp3_plan_t p, int32_t* n, int32_t* lmax, int32_t* nbins, int32_t* precision, int32_t* batch) {
   if (int s = check_plan(p)) return s;
   if (n) *n = p->n;
@@ -386,7 +437,21 @@ int mp3_deposit(mp3_plan_t p, const float* pos, const float* w, const int64_t* n
   MP3_HIP(mp3::launch_fill_f64(W, p->batch, 0.0, st), "zero W");
   MP3_HIP(mp3::launch_weight_sum(w, off, p->batch, np_max, W, st), "weight sum");
   MP3_HIP(mp3::launch_fill(p->prec, delta, n3 * p->batch, 0.0, st), "zero grid");
-  MP3_HIP(timed(p, MP3_PASS_DEPOSIT, st, [&] { return mp3::launch_deposit(p->prec, pos, w, off, p->batch, np_total, p->n, (double)p->n / p->box, delta, st); }), "deposit");
+  if (np_total >= (1LL << 31)) return fail(MP3_EUNSUPPORTED, "more than 2^31 - 1 particles");
+  const double sc = (double)p->n / p->box;
+  int* dperm = reinterpret_cast<int*>(at(ws, L.dperm));
+  int* doffs = reinterpret_cast<int*>(at(ws, L.doffs));
+  const int ntiles = (int)deposit_tiles(p);
+  const int tside = p->tune[MP3_TUNE_DEPOSIT_TILE];
+  MP3_HIP(timed(p, MP3_PASS_DEPOSIT, st, [&] {
+            hipError_t e = mp3::launch_tile_sort(pos, off, p->batch, np_total, p->n, sc, tile_shift(tside),
+                                                 reinterpret_cast<int*>(at(ws, L.dcounts)), doffs,
+                                                 reinterpret_cast<int*>(at(ws, L.dcursor)), dperm, st);
+            if (e != hipSuccess) return e;
+            return mp3::launch_deposit_tiled(p->prec, tside, pos, w, dperm, doffs, ntiles, p->tune[MP3_TUNE_DEPOSIT_WGS],
+                                             reinterpret_cast<int*>(at(ws, L.dcounter)), p->n, sc, delta, st);
+          }),
+          "deposit");
   MP3_HIP(mp3::launch_normalise(p->prec, delta, W, n3, p->batch, st), "normalise");
   return MP3_OK;
 }
@@ -447,7 +512,7 @@ int zeta_particle(mp3_plan_t p, const float* pos, const float* w, const int64_t*
   MP3_HIP(mp3::launch_fill_f64(W, p->batch, 0.0, st), "zero W");
   MP3_HIP(mp3::launch_weight_sum(w, off, p->batch, np_max, W, st), "weight sum");
   int* perm = reinterpret_cast<int*>(at(ws, L.perm));
-  MP3_HIP(mp3::launch_tile_sort(pos, off, p->batch, np_total, p->n, sc, reinterpret_cast<int*>(at(ws, L.counts)),
+  MP3_HIP(mp3::launch_tile_sort(pos, off, p->batch, np_total, p->n, sc, 2, reinterpret_cast<int*>(at(ws, L.counts)),
                                 reinterpret_cast<int*>(at(ws, L.offs)), reinterpret_cast<int*>(at(ws, L.cursor)), perm, st),
           "tile sort");
   double* P = reinterpret_cast<double*>(at(ws, L.power));
@@ -501,7 +566,7 @@ int zeta_gamma(mp3_plan_t p, const void* delta, double* zeta, void* ws, const La
   void* Fi = at(ws, L.fields_i);
   double* partials = reinterpret_cast<double*>(at(ws, L.partials));
   const long long tiles = (long long)(p->n / 4) * (p->n / 4) * (p->n / 4);
-  long long gwg = kTargetWorkgroups / p->batch;
+  long long gwg = (long long)contract_wgs(p);
   if (gwg < 1) gwg = 1;
   if (gwg > tiles) gwg = tiles;
   for (int l = 0; l <= p->lmax; ++l) {
@@ -591,7 +656,7 @@ int mp3_zeta_backward(mp3_plan_t p, const void* delta, const double* dzeta, void
       z.lmax = p->lmax;
       z.wm = wm;
       MP3_HIP(timed(p, MP3_PASS_Z_ADJOINT, st, [&] { return mp3::launch_zpass_adjoint(p->n, p->prec, z, st); }), "z pass (adjoint)");
-      MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, F, p->batch * p->nbins, p->tw, st); }), "adjoint x pass");
+      MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, F, p->batch * p->nbins, p->tw, p->tune[MP3_TUNE_FFT_X_PLAN], st); }), "adjoint x pass");
       mp3::FilterArgs a = filter_args(p, F, G, l, m, wm / (double)n3);
       MP3_HIP(timed(p, MP3_PASS_ADJOINT, st, [&] { return mp3::launch_adjoint_y(p->n, p->prec, a, st); }), "adjoint window pass");
     }

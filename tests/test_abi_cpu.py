@@ -68,3 +68,14 @@ def test_null_arguments_are_rejected():
     assert lib.mp3_workspace_size(None, 0, ctypes.byref(sz)) == _lib.MP3_EINVAL
     assert lib.mp3_plan_destroy(None) == _lib.MP3_OK
     assert lib.mp3_status_string(-5) == b"MP3_EWORKSPACE"
+
+
+def test_tuning_knobs_reject_null_plan_and_bad_knobs():
+    ensure_library()
+    from paper_2507_15209_amd import _lib
+    lib = _lib.load()
+    v = ctypes.c_int32(-7)
+    assert lib.mp3_tune_set(None, 0, 4096) == _lib.MP3_EINVAL
+    assert lib.mp3_tune_get(None, 0, ctypes.byref(v)) == _lib.MP3_EINVAL
+    assert v.value == -7
+    assert len(_lib.TUNE_KNOBS) == 5

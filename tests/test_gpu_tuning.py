@@ -1,0 +1,142 @@
+"""GPU: the launch-shape knobs and the autotuner leave the results unchanged.
+
+Every knob value is checked against the float64 oracle (deposit 1e-13,
+zeta 1e-10 relative per multipole) or, for the backward, against the
+default knobs' output of the same float64 path at 1e-12.
+"""
+import numpy as np
+import pytest
+
+from mockgen import random_field, lognormal_catalogue, batch_sizes
+from oracle import basis
+from oracle import estimator as E
+from tests._common import assert_zeta_close
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def mp3():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_15209_amd as m
+    return m
+
+
+def _dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+@pytest.mark.parametrize("n", [16, 32, 64])
+@pytest.mark.parametrize("tile", [4, 8, 16])
+@pytest.mark.parametrize("wgs", [64, 2048])
+def test_deposit_tiles(mp3, n, tile, wgs):
+    _say("deposit tile", n, tile, wgs)
+    box = 8.0 * n
+    pos, w = lognormal_catalogue(n, box, 30000, 2.0, 2001 + n, 2002, 2003, (0.5, 1.5))
+    plan = mp3.Plan(n, box, 1, [10.0, 20.0], precision="f64")
+    plan.tune_set("deposit_tile", tile)
+    plan.tune_set("deposit_wgs", wgs)
+    d = plan.deposit(_dev(pos, torch.float32), _dev(w, torch.float32)).cpu().numpy()[0]
+    ref = basis.density_contrast(basis.deposit(pos, w, n, box), float(np.sum(w.astype(np.float64))))
+    assert np.abs(d - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("tile", [4, 16])
+def test_deposit_tiles_batch_uneven(mp3, tile):
+    _say("deposit tile batch", tile)
+    n, box, batch = 32, 250.0, 5
+    sizes = [int(s) for s in batch_sizes(batch, 77, 300, 9000)]
+    cats = [lognormal_catalogue(n, box, s, 3.0, 3001 + j, 3101 + j, 3201 + j, (0.5, 1.5)) for j, s in enumerate(sizes)]
+    pos = np.concatenate([c[0] for c in cats])
+    w = np.concatenate([c[1] for c in cats])
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    plan = mp3.Plan(n, box, 1, [10.0, 20.0], precision="f64", batch=batch)
+    plan.tune_set("deposit_tile", tile)
+    d = plan.deposit(_dev(pos, torch.float32), _dev(w, torch.float32), off).cpu().numpy()
+    for j, (p, ww) in enumerate(cats):
+        ref = basis.density_contrast(basis.deposit(p, ww, n, box), float(np.sum(ww.astype(np.float64))))
+        assert np.abs(d[j] - ref).max() <= 1e-13 * np.abs(ref).max(), j
+
+
+@pytest.mark.parametrize("knob,value", [("zpass_wgs", 64), ("zpass_wgs", 16384), ("fft_x_plan", 1)])
+def test_knobs_keep_nodal_zeta_and_gradient(mp3, knob, value):
+    _say("nodal knob", knob, value)
+    n, box, lmax = 32, 320.0, 4
+    edges = np.linspace(30.0, 110.0, 7)
+    delta = random_field(n, 4001)
+    dd = _dev(delta[None], torch.float64)
+    lam = _dev(np.random.default_rng(4002).standard_normal((1, lmax + 1, 6, 6)), torch.float64)
+    base = mp3.Plan(n, box, lmax, edges, precision="f64")
+    g0, _ = base.zeta_backward(dd, lam)
+    plan = mp3.Plan(n, box, lmax, edges, precision="f64")
+    plan.tune_set(knob, value)
+    assert plan.tune_get(knob) == value
+    z = plan.zeta(dd).cpu().numpy()[0]
+    ref = E.zeta_nodal(E.Plan(n, box, lmax, edges), delta)
+    assert_zeta_close(z, ref, 1e-10)
+    g1, _ = plan.zeta_backward(dd, lam)
+    g0, g1 = g0.cpu().numpy(), g1.cpu().numpy()
+    assert np.abs(g1 - g0).max() <= 1e-12 * np.abs(g0).max()
+
+
+@pytest.mark.parametrize("summation", ["gamma", "particle"])
+@pytest.mark.parametrize("value", [64, 16384])
+def test_contract_workgroups_keep_zeta(mp3, summation, value):
+    _say("contract knob", summation, value)
+    n, box, lmax = 16, 160.0, 3
+    edges = np.linspace(15.0, 55.0, 5)
+    oplan = E.Plan(n, box, lmax, edges)
+    plan = mp3.Plan(n, box, lmax, edges, precision="f64", summation=summation)
+    plan.tune_set("contract_wgs", value)
+    if summation == "gamma":
+        delta = random_field(n, 5001)
+        z = plan.zeta(_dev(delta[None], torch.float64)).cpu().numpy()[0]
+        ref = E.zeta_gamma(oplan, delta)
+    else:
+        pos, w = lognormal_catalogue(n, box, 5000, 2.0, 5002, 5003, 5004, (0.5, 1.5))
+        pt, wt = _dev(pos, torch.float32), _dev(w, torch.float32)
+        delta = plan.deposit(pt, wt)
+        z = plan.zeta(delta, pt, wt).cpu().numpy()[0]
+        ref = E.zeta_particle(oplan, pos, w)
+    assert_zeta_close(z, ref, 1e-10)
+
+
+def test_tune_set_rejects_out_of_range(mp3):
+    _say("tune invalid")
+    plan = mp3.Plan(16, 160.0, 1, [10.0, 20.0])
+    for knob, bad in [("zpass_wgs", 10), ("zpass_wgs", 1 << 20), ("contract_wgs", 0), ("fft_x_plan", 2),
+                      ("deposit_tile", 5), ("deposit_tile", 32), ("deposit_wgs", 63)]:
+        before = plan.tune_get(knob)
+        with pytest.raises(mp3.Mp3Error):
+            plan.tune_set(knob, bad)
+        assert plan.tune_get(knob) == before
+
+
+def test_autotune_caches_and_keeps_results(mp3, tmp_path):
+    _say("autotune")
+    from paper_2507_15209_amd import autotune as at
+    n, box, lmax = 32, 320.0, 3
+    edges = np.linspace(30.0, 110.0, 5)
+    pos, w = lognormal_catalogue(n, box, 20000, 3.0, 6001, 6002, 6003, (0.5, 1.5))
+    pt, wt = _dev(pos, torch.float32), _dev(w, torch.float32)
+    cache = str(tmp_path / "tuning.json")
+    plan = mp3.Plan(n, box, lmax, edges, precision="f64")
+    delta = plan.deposit(pt, wt)
+    knobs = at.autotune(plan, delta, pt, wt, cache=cache, reps=1)
+    assert set(knobs) == set(at.CANDIDATES)
+    for k, v in knobs.items():
+        assert v in at.CANDIDATES[k]
+    other = mp3.Plan(n, box, lmax, edges, precision="f64")
+    assert at.load_tuning(other, cache)
+    assert other.tuning() == knobs
+    d2 = other.deposit(pt, wt)
+    z = other.zeta(d2).cpu().numpy()[0]
+    ref_delta = basis.density_contrast(basis.deposit(pos, w, n, box), float(np.sum(w.astype(np.float64))))
+    assert np.abs(d2.cpu().numpy()[0] - ref_delta).max() <= 1e-13 * np.abs(ref_delta).max()
+    assert_zeta_close(z, E.zeta_nodal(E.Plan(n, box, lmax, edges), ref_delta), 1e-10)
