@@ -52,15 +52,119 @@ def read_pmc(kernel_tag):
     """HBM traffic per launch from the committed rocprofv3 counter summary, if it matches the source."""
     if not os.path.exists(PMC_SUMMARY):
         return None
-    import hashlib
-    src = open(os.path.join(ROOT, "paper_2507_15209_amd", "csrc", "kernels.hip"), "rb").read()
-    src += open(os.path.join(ROOT, "paper_2507_15209_amd", "csrc", "fft_core.hpp"), "rb").read()
-    digest = hashlib.sha256(src).hexdigest()[:16]
+    digest = _source_digest()
     for line in open(PMC_SUMMARY):
         p = line.split()
         if len(p) >= 4 and p[0] == "traffic" and p[1] == kernel_tag and p[2] == digest:
             return float(p[3])
     return None
+
+
+COPY_BYTES = 1 << 30
+
+
+def pmc_probe(wl, precision):
+    """One step of the path and a plain 1 GiB device copy, for hardware-counter runs.
+
+    The copy reads and writes COPY_BYTES each; what FETCH_SIZE / WRITE_SIZE
+    report for it calibrates the counters against known traffic."""
+    import torch
+    import paper_2507_15209_amd as mp3
+    from mockgen import workload_catalogue
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copy done")
+    pos, w = workload_catalogue(wl)
+    pt, wt = torch.as_tensor(pos, device=dev), torch.as_tensor(w, device=dev)
+    lam = torch.as_tensor(np.random.default_rng(11).standard_normal((1, wl.lmax + 1, wl.nbins, wl.nbins)), device=dev)
+    plan = mp3.Plan(wl.n, wl.box, wl.lmax, wl.edges, precision=precision, device=dev)
+    delta = plan.deposit(pt, wt)
+    plan.zeta(delta)
+    torch.cuda.synchronize()
+    log("forward done")
+    plan.zeta_backward(delta, lam, pt, wt)
+    torch.cuda.synchronize()
+    log("backward done")
+
+
+def _csv_rows(root, suffix):
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(root, "**", "*" + suffix), recursive=True)):
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def _source_digest():
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2507_15209_amd", "csrc", "kernels.hip"), "rb").read()
+    src += open(os.path.join(ROOT, "paper_2507_15209_amd", "csrc", "fft_core.hpp"), "rb").read()
+    return hashlib.sha256(src).hexdigest()[:16]
+
+
+# kernels whose traffic is summarised: pass name -> (kernel-name prefix, grid filter on fields per launch)
+PMC_KERNELS = {"x": "k_fft_strided", "filter": "k_filter_y", "z_nodal": "k_zpass_nodal",
+               "z_adjoint": "k_zpass_adjoint", "adjoint": "k_adjoint_y"}
+
+
+def pmc_summarize(fetch_dir, write_dir, wl, precision):
+    """Per-launch HBM bytes of the path's kernels from two rocprofv3 --pmc runs of --pmc-probe."""
+    n, nb = wl.n, wl.nbins
+    real_bytes = 4 if precision == "f32" else 8
+    out = [f"# HBM traffic per launch from rocprofv3 counters, workload {wl.name} ({precision})",
+           f"# source digest {_source_digest()} (kernels.hip + fft_core.hpp); a changed kernel voids these lines",
+           "# columns: traffic <pass> <digest> <bytes per launch> | fetch_bytes write_bytes algorithmic_bytes launches"]
+    per = {}
+    for cname, root in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = [r for r in _csv_rows(root, "counter_collection.csv") if r.get("Counter_Name") == cname]
+        if not rows:
+            raise SystemExit(f"no {cname} rows under {root}")
+        copy = [float(r["Counter_Value"]) for r in rows if "copy" in r["Kernel_Name"].lower()]
+        if not copy:
+            names = sorted({r["Kernel_Name"][:80] for r in rows})
+            raise SystemExit(f"no copy kernel among the {cname} rows: {names}")
+        big = sorted(v for v in copy if v >= 0.5 * max(copy))
+        kib = big[len(big) // 2]
+        factor = kib * 1024.0 / COPY_BYTES
+        out.append(f"# {cname}: plain 1 GiB device copy counts {kib:.0f} KiB -> factor {factor:.4f} "
+                   f"(counter bytes per true byte)")
+        for tag, prefix in PMC_KERNELS.items():
+            sel = [r for r in rows if prefix in r["Kernel_Name"]]
+            if tag == "x" and sel:
+                # the x pass transforms all bins in one launch: the largest grid of the strided kernel
+                gmax = max(int(r.get("Grid_Size") or 0) for r in sel)
+                sel = [r for r in sel if int(r.get("Grid_Size") or 0) == gmax]
+            vals = [float(r["Counter_Value"]) for r in sel]
+            if vals:
+                per.setdefault(tag, {})[cname] = (sum(vals) / len(vals) * 1024.0 / factor, len(vals))
+    dig = _source_digest()
+    for tag, d in per.items():
+        if "FETCH_SIZE" in d and "WRITE_SIZE" in d:
+            f, cnt = d["FETCH_SIZE"]
+            w_, _ = d["WRITE_SIZE"]
+            alg = pass_bytes(tag, n, nb, 1, real_bytes)
+            out.append(f"traffic {tag} {dig} {f + w_:.6g} | {f:.6g} {w_:.6g} {alg:.6g} {cnt}")
+    print("\n".join(out))
+
+
+def stats_summarize(root, top=20):
+    """Markdown table of a rocprofv3 --kernel-trace --stats run (kernel_stats.csv)."""
+    rows = _csv_rows(root, "kernel_stats.csv")
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    print("| kernel | calls | total ms | avg ms | min ms | max ms | % |")
+    print("|---|---|---|---|---|---|---|")
+    for r in rows[:top]:
+        name = r["Name"]
+        name = name if len(name) < 90 else name[:87] + "..."
+        print(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['AverageNs']) / 1e6:.4f} "
+              f"| {float(r['MinNs']) / 1e6:.4f} | {float(r['MaxNs']) / 1e6:.4f} | {float(r['Percentage']):.2f} |")
 
 
 def cpu_baseline(wl, pos, w, nbins_sample=4, l_sample=0):
@@ -92,17 +196,32 @@ def main():
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-probe", action="store_true", help="one step plus a 1 GiB copy, for counter runs")
+    ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print the per-launch traffic summary of two rocprofv3 --pmc runs of --pmc-probe")
+    ap.add_argument("--stats-summarize", metavar="DIR", help="print a table of a rocprofv3 --stats run")
     args = ap.parse_args()
+    if args.stats_summarize:
+        stats_summarize(args.stats_summarize)
+        return
+    if args.pmc_summarize:
+        from mockgen import WORKLOADS
+        pmc_summarize(args.pmc_summarize[0], args.pmc_summarize[1], WORKLOADS[args.workload], args.precision)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU path is a design "
               "note only, see DESIGN.md", file=sys.stderr)
         sys.exit(2)
 
+    from mockgen import WORKLOADS, workload_catalogue
+    wl = WORKLOADS[args.workload]
+    if args.pmc_probe:
+        pmc_probe(wl, args.precision)
+        return
+
     import torch
     import paper_2507_15209_amd as mp3
-    from mockgen import WORKLOADS, workload_catalogue
 
-    wl = WORKLOADS[args.workload]
     log("workload", wl.name, "n", wl.n, "L", wl.lmax, "bins", wl.nbins, "particles", wl.n_particles)
     t0 = time.perf_counter()
     pos, w = workload_catalogue(wl)
