@@ -155,13 +155,21 @@ int mp3_zeta(mp3_plan_t plan, const void* delta, const float* pos, const float* 
              double* zeta, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Gradient of J = sum_{j,l,b1,b2} dzeta[j][l][b1][b2] zeta_l^{(j)}[b1][b2] for the
- * nodal form (other forms return MP3_EUNSUPPORTED).
+ * nodal and particle forms (the grid-Gamma form returns MP3_EUNSUPPORTED); the
+ * paper gives no gradient, this is the chain rule of mp3_zeta and mp3_deposit.
  * The fields are recomputed per (l, m); nothing is kept from mp3_zeta.
  *   ddelta = dJ/ddelta                                          (device real [batch][N^3])
- *   dw     = dJ/dw_i through delta = eps N^3 / W - 1 of mp3_deposit, i.e.
- *            (N^3/W) [ sum_l B_i(l) g_l - N^-3 sum_l (1 + delta_l) g_l ], g = ddelta
- *            (device real [np_total]); needs pos, w, np_off as given to mp3_deposit.
- * ddelta must not be NULL.  dw may be NULL (then pos, w, np_off are ignored).
+ *            For the particle form this is the dependence through the
+ *            secondary vertices (the fields and the volume mean), the
+ *            primary's weights held fixed.
+ *   dw     = dJ/dw_i (device real [np_total]): through delta = eps N^3 / W - 1
+ *            of mp3_deposit, (N^3/W) [ sum_l B_i(l) g_l - N^-3 sum_l (1 + delta_l) g_l ]
+ *            with g = ddelta, plus for the particle form the primary vertex's
+ *            4 pi [ F_J(u_i) / W - sum_j w_j F_J(u_j) / W^2 ],
+ *            F_J = sum_{l,m,b1,b2} dzeta_l[b1][b2] atilde_{b1} conj(atilde_{b2}).
+ *            Needs pos, w, np_off as given to mp3_deposit.
+ * ddelta must not be NULL.  dw may be NULL: then the nodal form ignores pos,
+ * w and np_off; the particle form always needs them.
  * dzeta  device float64 [batch][lmax+1][nbins][nbins]. */
 int mp3_zeta_backward(mp3_plan_t plan, const void* delta, const double* dzeta,
                       void* ddelta, const float* pos, const float* w, const int64_t* np_off,
@@ -179,7 +187,8 @@ enum mp3_pass {
   MP3_PASS_Z_STORE = 7,    /* z-transform, fields stored bin-interleaved (particle form)       */
   MP3_PASS_GATHER = 8,     /* B-spline gather at the particles + contraction                   */
   MP3_PASS_GAMMA = 9,      /* grid-Gamma quadrature contraction                                */
-  MP3_NPASS = 10
+  MP3_PASS_SCATTER = 10,   /* adjoint sources scattered from the particles onto the grid      */
+  MP3_NPASS = 11
 };
 
 /* Per-pass timing for measurement: with enable != 0 every pass launch of

@@ -14,6 +14,22 @@ with m over -l..l: the first term is the explicit dependence on the primary
 vertex, the second the transpose of the filter-and-transform map applied to
 the secondary vertices.
 
+Particle form (primary on the catalogue, volume mean subtracted).  With
+atilde = gather(a) at the particles, F_J(u) = sum_{l,m} sum_{b1,b2}
+lam_l[b1,b2] atilde_{b1}(u) conj(atilde_{b2}(u)) and
+H(q) = B7hat(q) sum_l (2l+1) sum_{b1,b2} lam_l[b1,b2] jbar_{b1} jbar_{b2}
+(zero on the Nyquist planes), the dependence on delta at fixed primary
+weights is
+
+  dJ/ddelta = (4 pi / n^3) 2 Re fftn( sum_{l,m,b} K_{lm,b} ifftn(c_{lm,b}) )
+              - (2 / n^3) Re ifftn(H dhat),
+  c_{lm,b} = n^3 scatter_i[ (w_i / W) sum_{b'} lam^s_l[b,b'] conj(atilde_{lm,b'}(u_i)) ],
+
+the scatter being the transpose of the gather (the deposit's stencil).  The
+weights enter through delta (deposit, below) and through the primary:
+
+  dJ/dw_i += 4 pi [ F_J(u_i) / W - sum_j w_j F_J(u_j) / W^2 ].
+
 Deposit.  delta_l = eps_l n^3 / W - 1 with eps_l = sum_i w_i B_i(l) and
 W = sum_i w_i, so for a grid gradient g = dJ/ddelta,
 
@@ -26,7 +42,8 @@ import numpy as np
 from . import basis
 from .estimator import Plan, fields, FOUR_PI
 
-__all__ = ["zeta_nodal_grad", "deposit_weight_grad", "zeta_nodal_objective"]
+__all__ = ["zeta_nodal_grad", "deposit_weight_grad", "zeta_nodal_objective",
+           "zeta_particle_objective", "zeta_particle_grad"]
 
 
 def zeta_nodal_objective(plan: Plan, delta, lam) -> float:
@@ -70,3 +87,54 @@ def deposit_weight_grad(pos, w, n: int, box: float, g) -> np.ndarray:
     g = np.asarray(g, dtype=np.float64)
     interp = basis.gather(g, pos, n, box)
     return (n ** 3 / W) * interp - (n ** 3 / W ** 2) * float(np.sum(eps * g))
+
+
+def zeta_particle_objective(plan: Plan, pos, w, lam) -> float:
+    """J = sum_l <lam_l, zeta_l> for the particle form (used by finite differences)."""
+    from .estimator import zeta_particle
+    return float(np.sum(np.asarray(lam) * zeta_particle(plan, pos, w)))
+
+
+def _scatter(vals, pos, n: int, box: float) -> np.ndarray:
+    """Transpose of basis.gather for complex per-particle values: sum_i v_i B(u_i - l)."""
+    return (basis.deposit(pos, vals.real, n, box) + 1j * basis.deposit(pos, vals.imag, n, box))
+
+
+def zeta_particle_grad(plan: Plan, pos, w, lam, ls=None, bins=None):
+    """(dJ/ddelta at fixed primary weights, dJ/dw) for the particle form.
+
+    lam has shape [lmax+1, nbins, nbins], or [len(ls), len(bins), len(bins)]
+    with ``ls`` / ``bins``.
+    """
+    from .estimator import fields
+    n, box = plan.n, plan.box
+    w = np.ones(len(pos)) if w is None else np.asarray(w, dtype=np.float64)
+    W = w.sum()
+    lam = np.asarray(lam, dtype=np.float64)
+    delta = basis.density_contrast(basis.deposit(pos, w, n, box), W)
+    dhat = np.fft.fftn(delta)
+    acc = np.zeros(delta.shape, dtype=np.complex128)
+    FJ = np.zeros(len(pos))
+    bl = plan.bins(bins)
+    th = 2.0 * np.pi * plan.q1 / n
+    b7 = basis.b7_hat(th)
+    H = np.zeros(delta.shape)
+    for li, l in enumerate(plan.ls(ls)):
+        lam_l = lam[li]
+        lam_s = 0.5 * (lam_l + lam_l.T)
+        J = np.stack([plan.jbar_grid(l, b) for b in bl])               # [nb, n, n, n]
+        H += (2 * l + 1) * np.einsum("ij,ixyz,jxyz->xyz", lam_l, J, J)
+        for m in range(-l, l + 1):
+            A = fields(plan, dhat, l, m, bl)
+            At = basis.gather(A, pos, n, box)                          # [nb, P]
+            FJ += np.einsum("ij,ip,jp->p", lam_l, At, At.conj()).real
+            S = (w / W)[None, :] * (lam_s @ At.conj())
+            yc = plan.ylm_conj_grid(l, m)
+            for bi, b in enumerate(bl):
+                c = float(n) ** 3 * _scatter(S[bi], pos, n, box)
+                acc += plan.kernel(l, m, b, yc) * np.fft.ifftn(c)
+    H *= b7[:, None, None] * b7[None, :, None] * b7[None, None, :]
+    H[plan.nyquist] = 0.0
+    g = (FOUR_PI / n ** 3) * 2.0 * np.fft.fftn(acc).real - (2.0 / n ** 3) * np.fft.ifftn(H * dhat).real
+    dw = deposit_weight_grad(pos, w, n, box, g) + FOUR_PI * (FJ / W - float(np.dot(w, FJ)) / W ** 2)
+    return g, dw

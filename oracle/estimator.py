@@ -256,20 +256,27 @@ def volume_mean_pair(plan: Plan, dhat: np.ndarray, l: int, bins=None) -> np.ndar
     return (2 * l + 1) / (FOUR_PI * float(n) ** 6) * ((J * p.ravel()) @ J.T)
 
 
-def zeta_particle(plan: Plan, pos, w, ls=None, bins=None, mode: str = "delta") -> np.ndarray:
+def zeta_particle(plan: Plan, pos, w, ls=None, bins=None, mode: str = "delta", delta=None) -> np.ndarray:
     """Particle summation over the catalogue (primary vertex on the particles).
 
     mode "delta": secondaries from delta = n/nbar - 1 and primary n/nbar - 1
                   (volume mean of F subtracted);
     mode "ddd":   secondaries from n/nbar and primary n/nbar (plain triplet
                   counting, the q = 0 mode kept, nothing subtracted).
+    ``delta`` (mode "delta" only) replaces the deposit of the catalogue as the
+    secondaries' grid, the primary staying on the weighted particles.
     """
     n, box = plan.n, plan.box
     w = np.ones(len(pos)) if w is None else np.asarray(w, dtype=np.float64)
     W = w.sum()
-    eps = basis.deposit(pos, w, n, box)
-    rho = eps * (n ** 3 / W)
-    src = rho - 1.0 if mode == "delta" else rho
+    if delta is not None:
+        if mode != "delta":
+            raise ValueError("an explicit delta needs mode 'delta'")
+        src = np.asarray(delta, dtype=np.float64)
+    else:
+        eps = basis.deposit(pos, w, n, box)
+        rho = eps * (n ** 3 / W)
+        src = rho - 1.0 if mode == "delta" else rho
     dhat = np.fft.fftn(src)
     out = []
     for l in plan.ls(ls):

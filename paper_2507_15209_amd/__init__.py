@@ -181,7 +181,7 @@ class Plan:
         return z
 
     def zeta_backward(self, delta, dzeta, pos=None, w=None, np_off=None):
-        """Returns (dJ/ddelta, dJ/dw or None) for J = sum dzeta * zeta."""
+        """Returns (dJ/ddelta, dJ/dw or None) for J = sum dzeta * zeta (nodal and particle forms)."""
         self._real(delta, "delta")
         dzeta = dzeta.to(device=self.device, dtype=torch.float64).contiguous()
         if dzeta.numel() != self.batch * (self.lmax + 1) * self.nbins ** 2:
@@ -190,6 +190,8 @@ class Plan:
         dw = None
         offp = None
         np_total = 0
+        if self.summation == "particle" and pos is None:
+            raise ValueError("the particle form's backward needs pos (and w, np_off)")
         if pos is not None:
             self._catalogue(pos, w)
             np_total = pos.shape[0]
@@ -225,6 +227,8 @@ class _CatalogueZeta(torch.autograd.Function):
         delta = plan.deposit(pos, w, np_off)
         ctx.plan, ctx.np_off = plan, np_off
         ctx.save_for_backward(w, pos, delta)
+        if plan.summation == "particle":
+            return plan.zeta(delta, pos, w, np_off)
         return plan.zeta(delta)
 
     @staticmethod

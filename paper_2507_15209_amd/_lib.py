@@ -28,7 +28,8 @@ EXPORTS = (
     "mp3_status_string", "mp3_last_error", "mp3_profile", "mp3_profile_read",
     "mp3_tune_set", "mp3_tune_get",
 )
-PASSES = ("dft", "filter", "x", "z_nodal", "z_adjoint", "adjoint", "deposit", "z_store", "gather", "gamma")
+PASSES = ("dft", "filter", "x", "z_nodal", "z_adjoint", "adjoint", "deposit", "z_store", "gather", "gamma",
+          "scatter")
 
 
 class PlanDesc(ctypes.Structure):

@@ -157,13 +157,14 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 // W[j] = sum of the weights of mock j (unit weights if w == nullptr)
-__global__ void k_weight_sum(const float* w, const long long* off, int batch, double* W) {
+// (times f[i] when f is given)
+__global__ void k_weight_sum(const float* w, const double* f, const long long* off, int batch, double* W) {
   __shared__ double sh[32];
   const int j = blockIdx.y;
   const long long a = off[j], b = off[j + 1];
   double s = 0.0;
   for (long long i = a + blockIdx.x * (long long)blockDim.x + threadIdx.x; i < b; i += (long long)gridDim.x * blockDim.x)
-    s += w ? (double)w[i] : 1.0;
+    s += (w ? (double)w[i] : 1.0) * (f ? f[i] : 1.0);
   s = block_sum(s, sh);
   if (threadIdx.x == 0 && s != 0.0) atomicAdd(&W[j], s);
 }
@@ -1303,6 +1304,226 @@ __global__ void k_grad_combine(const T* direct, const c2<T>* ghat, T* ddelta, lo
     ddelta[i] = (T)(scale * ((double)direct[i] + 2.0 * (double)ghat[i].x));
 }
 
+// ---------------------------------------------------------------------------
+// adjoint of the particle summation
+// ---------------------------------------------------------------------------
+// Per particle (tile order): gather atilde_b(u_i) for every bin, form
+//   v_b = sum_b' lam_s[b][b'] conj(atilde_b'),
+// add wm sum_b Re(atilde_b v_b) to F_J(u_i) (the primary vertex's share of J)
+// and store the adjoint source s_b(i) = N^3 (w_i / W) v_b at the particle's
+// sorted slot.  One lane per (particle, bin), 32 or 64 lanes per particle.
+template <typename T>
+__global__ void __launch_bounds__(256) k_gather_source(const c2<T>* fields, const float* pos, const float* w,
+                                                        const int* perm, const long long* off, const double* W,
+                                                        const T* lam_s, int n, double sc, int nbins, T wm,
+                                                        double* FJ, c2<T>* src) {
+  extern __shared__ __align__(16) char smem[];
+  c2<T>* at = reinterpret_cast<c2<T>*>(smem);                     // [particles per pass][nbins]
+  const int lpp = nbins <= 32 ? 32 : 64;
+  const int ppp = blockDim.x / lpp;
+  T* lam = reinterpret_cast<T*>(at + ppp * nbins);               // [nbins][nbins]
+  const long long mock = blockIdx.y;
+  const int nb2 = nbins * nbins;
+  for (int t = threadIdx.x; t < nb2; t += blockDim.x) lam[t] = lam_s[mock * nb2 + t];
+  const long long n3 = (long long)n * n * n;
+  const long long a0 = off[mock], a1 = off[mock + 1];
+  const long long per = (a1 - a0 + gridDim.x - 1) / gridDim.x;
+  const long long s0 = a0 + per * blockIdx.x, s1 = min(a1, s0 + per);
+  const double fw = (double)n3 / W[mock];
+  const int b = threadIdx.x % lpp, g = threadIdx.x / lpp;
+  const c2<T>* fm = fields + mock * n3 * nbins;
+  for (long long c0 = s0; c0 < s1; c0 += ppp) {
+    const long long si = c0 + g;
+    const bool has = si < s1;
+    const int i = has ? perm[si] : 0;
+    c2<T> acc = mk<T>(0, 0);
+    if (has && b < nbins) {
+      Taps t = make_taps(pos + 3 * (long long)i, n, sc);
+      if (t.ok) {
+        for (int ax = 0; ax < 4; ++ax) {
+          const int ix = wrapi(t.base[0] + ax, n);
+          for (int ay = 0; ay < 4; ++ay) {
+            const int iy = wrapi(t.base[1] + ay, n);
+            const T wxy = (T)(t.wt[0][ax] * t.wt[1][ay]);
+            const c2<T>* row = fm + ((long long)ix * n + iy) * n * nbins + b;
+#pragma unroll
+            for (int az = 0; az < 4; ++az) {
+              const c2<T> v = row[(long long)wrapi(t.base[2] + az, n) * nbins];
+              const T wt = wxy * (T)t.wt[2][az];
+              acc.x += wt * v.x;
+              acc.y += wt * v.y;
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();                                   // the previous pass's reads of at[] are done
+    if (b < nbins) at[g * nbins + b] = acc;
+    __syncthreads();
+    T fj = 0;
+    if (has && b < nbins) {
+      c2<T> v = mk<T>(0, 0);
+      for (int bp = 0; bp < nbins; ++bp) {
+        const c2<T> a = at[g * nbins + bp];
+        const T lv = lam[b * nbins + bp];
+        v.x += lv * a.x;
+        v.y -= lv * a.y;
+      }
+      fj = acc.x * v.x - acc.y * v.y;
+      const T f = (T)(fw * (w ? (double)w[i] : 1.0));
+      src[si * nbins + b] = mk<T>(f * v.x, f * v.y);
+    }
+    for (int o = lpp / 2; o > 0; o >>= 1) fj += __shfl_xor(fj, o, lpp);
+    if (has && b == 0) FJ[i] += (double)wm * (double)fj;
+  }
+}
+
+// Adjoint source on the grid, c_b(x) = sum_i B3(u_i - x) s_b(i).  A workgroup
+// owns an 8^3-node tile and BC bins; it visits the particles of the 4^3-cell
+// sort tiles whose stencils can reach the tile (cells x0 - 4 .. x0 + 11 per
+// axis), accumulates the taps that land inside in LDS and writes the tile
+// once: every node has exactly one owner, so there are no global atomics and
+// empty tiles are written as zeros.
+template <typename T, int BC>
+__global__ void __launch_bounds__(256) k_scatter_source(const float* pos, const int* perm, const int* toff,
+                                                         const c2<T>* src, int n, double sc, int nbins, int nchunk,
+                                                         c2<T>* out) {
+  constexpr int TO = 8;
+  constexpr int NODES = TO * TO * TO;
+  __shared__ T acc[NODES * BC * 2];
+  const int no = n / TO;
+  const int ot = blockIdx.x;
+  const int oxi = ot / (no * no), oyi = (ot / no) % no, ozi = ot % no;
+  const int o0[3] = {oxi * TO, oyi * TO, ozi * TO};
+  const int mock = blockIdx.y / nchunk, b0 = (blockIdx.y % nchunk) * BC;
+  const int nbc = min(BC, nbins - b0);
+  for (int t = threadIdx.x; t < NODES * BC * 2; t += blockDim.x) acc[t] = (T)0;
+  __syncthreads();
+  const int ntd = n / 4;
+  const long long ns = (long long)ntd * ntd * ntd;
+  const int ppp = blockDim.x / BC;
+  const int g = threadIdx.x / BC, bb = threadIdx.x % BC;
+  for (int c = 0; c < 64; ++c) {
+    const int sx = wrapi(2 * oxi - 1 + c / 16, ntd), sy = wrapi(2 * oyi - 1 + (c / 4) % 4, ntd);
+    const int sz = wrapi(2 * ozi - 1 + c % 4, ntd);
+    const long long tile = mock * ns + ((long long)sx * ntd + sy) * ntd + sz;
+    const int a = toff[tile], e = toff[tile + 1];
+    for (int k = a + g; k < e; k += ppp) {
+      const int i = perm[k];
+      Taps t = make_taps(pos + 3 * (long long)i, n, sc);
+      if (!t.ok || bb >= nbc) continue;
+      int loc[3][4];
+      int hit = 1;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        int any = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          int r = (t.base[d] + q - o0[d]) % n;
+          if (r < 0) r += n;
+          loc[d][q] = r < TO ? r : -1;
+          any |= r < TO;
+        }
+        hit &= any;
+      }
+      if (!hit) continue;
+      const c2<T> sv = src[(long long)k * nbins + b0 + bb];
+#pragma unroll
+      for (int ax = 0; ax < 4; ++ax) {
+        if (loc[0][ax] < 0) continue;
+#pragma unroll
+        for (int ay = 0; ay < 4; ++ay) {
+          if (loc[1][ay] < 0) continue;
+          const double wxy = t.wt[0][ax] * t.wt[1][ay];
+#pragma unroll
+          for (int az = 0; az < 4; ++az) {
+            if (loc[2][az] < 0) continue;
+            const T wt = (T)(wxy * t.wt[2][az]);
+            const int node = (loc[0][ax] * TO + loc[1][ay]) * TO + loc[2][az];
+            atomicAdd(&acc[(node * BC + bb) * 2], wt * sv.x);
+            atomicAdd(&acc[(node * BC + bb) * 2 + 1], wt * sv.y);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const long long n3 = (long long)n * n * n;
+  for (int t = threadIdx.x; t < nbc * NODES; t += blockDim.x) {
+    const int bq = t / NODES, node = t % NODES;
+    const int i = node / (TO * TO), j = (node / TO) % TO, k = node % TO;
+    out[((long long)mock * nbins + b0 + bq) * n3 + ((long long)(o0[0] + i) * n + o0[1] + j) * n + o0[2] + k] =
+        mk<T>(acc[(node * BC + bq) * 2], acc[(node * BC + bq) * 2 + 1]);
+  }
+}
+
+// h[mock][s] = sum_l (2l+1) sum_{b1,b2} dzeta[mock][l][b1][b2] jbar_{l,b1}(s) jbar_{l,b2}(s):
+// the weight of |dhat(q)|^2 B7hat(q) in sum_l <dzeta_l, 4 pi Fbar_l>
+template <typename T>
+__global__ void k_fbar_weight(const double* dzeta, const T* jtab, int nq2, int nbp, int nbins, int lmax, double* h) {
+  const int mock = blockIdx.y;
+  const int nb2 = nbins * nbins;
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < nq2; s += gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int l = 0; l <= lmax; ++l) {
+      const T* jl = jtab + ((long long)l * nq2 + s) * nbp;
+      const double* dz = dzeta + ((long long)mock * (lmax + 1) + l) * nb2;
+      double al = 0.0;
+      for (int b1 = 0; b1 < nbins; ++b1) {
+        double r = 0.0;
+        for (int b2 = 0; b2 < nbins; ++b2) r += dz[b1 * nbins + b2] * (double)jl[b2];
+        al += (double)jl[b1] * r;
+      }
+      acc += (2.0 * l + 1.0) * al;
+    }
+    h[(long long)mock * nq2 + s] = acc;
+  }
+}
+
+// G(q) += scale B7hat(q) h(|q|^2) conj(dhat(q)), Nyquist planes excluded: the
+// volume-mean term of the particle form's gradient, added in k-space before
+// the final transform
+template <typename T>
+__global__ void k_fbar_adjoint(const c2<T>* dhat, const double* h, int n, int nq2, double scale, c2<T>* G) {
+  const long long n3 = (long long)n * n * n;
+  const int mock = blockIdx.y;
+  const c2<T>* d = dhat + mock * n3;
+  c2<T>* gm = G + mock * n3;
+  const double* hm = h + (long long)mock * nq2;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n3; i += (long long)gridDim.x * blockDim.x) {
+    const int ix = (int)(i / ((long long)n * n)), iy = (int)((i / n) % n), iz = (int)(i % n);
+    const int qx = sfreq(ix, n), qy = sfreq(iy, n), qz = sfreq(iz, n);
+    const int hh = -n / 2;
+    if (qx == hh || qy == hh || qz == hh) continue;
+    const double tp = 2.0 * 3.14159265358979323846 / n;
+    double b7 = 1.0;
+    const int qs[3] = {qx, qy, qz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double th = tp * qs[a];
+      b7 *= (2416.0 + 2382.0 * cos(th) + 240.0 * cos(2.0 * th) + 2.0 * cos(3.0 * th)) / 5040.0;
+    }
+    const double f = scale * b7 * hm[qx * qx + qy * qy + qz * qz];
+    const c2<T> v = d[i];
+    c2<T> o = gm[i];
+    o.x = (T)((double)o.x + f * (double)v.x);
+    o.y = (T)((double)o.y - f * (double)v.y);
+    gm[i] = o;
+  }
+}
+
+// dw_i += 4 pi [ F_J(u_i) / W - sum_j w_j F_J(u_j) / W^2 ]: the primary vertex's weights
+template <typename T>
+__global__ void k_primary_dw(const long long* off, int batch, long long np_total, const double* FJ, const double* W,
+                             const double* SF, T* dw) {
+  const double fp = 12.566370614359172953850573533118011536788677597500;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < np_total; i += (long long)gridDim.x * blockDim.x) {
+    const int mock = find_mock(off, batch, i);
+    const double Wj = W[mock];
+    dw[i] = (T)((double)dw[i] + fp * (FJ[i] / Wj - SF[mock] / (Wj * Wj)));
+  }
+}
+
 }  // namespace mp3
 
 // ===========================================================================
@@ -1604,9 +1825,17 @@ hipError_t launch_reduce_partials(const double* partials, int nwg, int nb2, doub
 
 hipError_t launch_weight_sum(const float* w, const long long* off, int batch, long long np_max, double* W, hipStream_t st) {
   const dim3 gs(grid_for(np_max, 256, 1024), batch);
-  k_weight_sum<<<gs, 256, 0, st>>>(w, off, batch, W);
+  k_weight_sum<<<gs, 256, 0, st>>>(w, nullptr, off, batch, W);
   return hipGetLastError();
 }
+
+hipError_t launch_weighted_sum(const float* w, const double* f, const long long* off, int batch, long long np_max,
+                               double* out, hipStream_t st) {
+  const dim3 gs(grid_for(np_max, 256, 1024), batch);
+  k_weight_sum<<<gs, 256, 0, st>>>(w, f, off, batch, out);
+  return hipGetLastError();
+}
+
 
 
 hipError_t launch_normalise(int prec, void* eps, const double* W, long long n3, int batch, hipStream_t st) {
@@ -1814,6 +2043,74 @@ hipError_t launch_gamma_contract(int prec, const void* fields, const void* delta
 
 size_t gamma_lds_need(int prec, int nbins) {
   return prec ? GammaLds<double>(nbins).total : GammaLds<float>(nbins).total;
+}
+
+hipError_t launch_gather_source(int prec, const void* fields, const float* pos, const float* w, const int* perm,
+                                const long long* off, const double* W, const void* lam_s, int n, double sc, int nbins,
+                                double wm, int nwg, int batch, double* FJ, void* src, hipStream_t st) {
+  const int lpp = nbins <= 32 ? 32 : 64;
+  const int ppp = 256 / lpp;
+  const size_t elt = prec ? sizeof(double) : sizeof(float);
+  const size_t lds = (size_t)ppp * nbins * 2 * elt + (size_t)nbins * nbins * elt;
+  const dim3 gs(nwg, batch);
+  if (prec) {
+    hipError_t e = allow_lds(k_gather_source<double>, lds);
+    if (e != hipSuccess) return e;
+    k_gather_source<double><<<gs, 256, lds, st>>>(static_cast<const double2*>(fields), pos, w, perm, off, W,
+                                                  static_cast<const double*>(lam_s), n, sc, nbins, wm, FJ,
+                                                  static_cast<double2*>(src));
+  } else {
+    hipError_t e = allow_lds(k_gather_source<float>, lds);
+    if (e != hipSuccess) return e;
+    k_gather_source<float><<<gs, 256, lds, st>>>(static_cast<const float2*>(fields), pos, w, perm, off, W,
+                                                 static_cast<const float*>(lam_s), n, sc, nbins, (float)wm, FJ,
+                                                 static_cast<float2*>(src));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_source(int prec, const float* pos, const int* perm, const int* toff, const void* src, int n,
+                                 double sc, int nbins, int batch, void* out, hipStream_t st) {
+  const int no = n / 8;
+  if (prec) {
+    constexpr int BC = 4;
+    const int nchunk = (nbins + BC - 1) / BC;
+    const dim3 gs(no * no * no, batch * nchunk);
+    k_scatter_source<double, BC><<<gs, 256, 0, st>>>(pos, perm, toff, static_cast<const double2*>(src), n, sc, nbins,
+                                                     nchunk, static_cast<double2*>(out));
+  } else {
+    constexpr int BC = 8;
+    const int nchunk = (nbins + BC - 1) / BC;
+    const dim3 gs(no * no * no, batch * nchunk);
+    k_scatter_source<float, BC><<<gs, 256, 0, st>>>(pos, perm, toff, static_cast<const float2*>(src), n, sc, nbins,
+                                                    nchunk, static_cast<float2*>(out));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fbar_adjoint(int prec, const double* dzeta, const void* jtab, int nq2, int nbp, int nbins, int lmax,
+                               const void* dhat, int n, double scale, double* h, void* G, int batch, hipStream_t st) {
+  const dim3 gh(grid_for(nq2, 256, 1024), batch);
+  const long long n3 = (long long)n * n * n;
+  const dim3 gs(grid_for(n3, 256, 8192), batch);
+  if (prec) {
+    k_fbar_weight<double><<<gh, 256, 0, st>>>(dzeta, static_cast<const double*>(jtab), nq2, nbp, nbins, lmax, h);
+    k_fbar_adjoint<double><<<gs, 256, 0, st>>>(static_cast<const double2*>(dhat), h, n, nq2, scale,
+                                               static_cast<double2*>(G));
+  } else {
+    k_fbar_weight<float><<<gh, 256, 0, st>>>(dzeta, static_cast<const float*>(jtab), nq2, nbp, nbins, lmax, h);
+    k_fbar_adjoint<float><<<gs, 256, 0, st>>>(static_cast<const float2*>(dhat), h, n, nq2, scale,
+                                              static_cast<float2*>(G));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_primary_dw(int prec, const long long* off, int batch, long long np_total, const double* FJ,
+                             const double* W, const double* SF, void* dw, hipStream_t st) {
+  const unsigned gr = grid_for(np_total, 256, 16384);
+  if (prec) k_primary_dw<double><<<gr, 256, 0, st>>>(off, batch, np_total, FJ, W, SF, static_cast<double*>(dw));
+  else k_primary_dw<float><<<gr, 256, 0, st>>>(off, batch, np_total, FJ, W, SF, static_cast<float*>(dw));
+  return hipGetLastError();
 }
 
 }  // namespace mp3

@@ -75,6 +75,21 @@ hipError_t launch_lam_sym(int prec, const double* dzeta, void* lam_s, int nbins,
 hipError_t launch_reduce_partials(const double* partials, int nwg, int nb2, double* zeta, int l, int lmax, double scale,
                                   int batch, hipStream_t st);
 hipError_t launch_weight_sum(const float* w, const long long* off, int batch, long long np_max, double* W, hipStream_t st);
+// out[j] = sum over mock j of w_i f_i (w NULL = unit weights)
+hipError_t launch_weighted_sum(const float* w, const double* f, const long long* off, int batch, long long np_max,
+                               double* out, hipStream_t st);
+// particle-form adjoint: per-particle sources and F_J, their scatter onto the
+// grid ([batch][nbins][N^3], every node written), the volume-mean term into G
+// and the primary vertex's share of dJ/dw
+hipError_t launch_gather_source(int prec, const void* fields, const float* pos, const float* w, const int* perm,
+                                const long long* off, const double* W, const void* lam_s, int n, double sc, int nbins,
+                                double wm, int nwg, int batch, double* FJ, void* src, hipStream_t st);
+hipError_t launch_scatter_source(int prec, const float* pos, const int* perm, const int* toff, const void* src, int n,
+                                 double sc, int nbins, int batch, void* out, hipStream_t st);
+hipError_t launch_fbar_adjoint(int prec, const double* dzeta, const void* jtab, int nq2, int nbp, int nbins, int lmax,
+                               const void* dhat, int n, double scale, double* h, void* G, int batch, hipStream_t st);
+hipError_t launch_primary_dw(int prec, const long long* off, int batch, long long np_total, const double* FJ,
+                             const double* W, const double* SF, void* dw, hipStream_t st);
 hipError_t launch_normalise(int prec, void* eps, const double* W, long long n3, int batch, hipStream_t st);
 hipError_t launch_grad_combine(int prec, const void* direct, const void* ghat, void* ddelta, long long count, double scale,
                                hipStream_t st);

@@ -60,6 +60,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
   size_t off, W, S, dhat, fields, partials, G, direct, lam, fields_i, perm, counts, offs, cursor, power;
+  size_t src, fj, hq, SF;
   size_t dperm, dcounts, doffs, dcursor, dcounter, total;
   int nwg, ppw;
 };
@@ -127,6 +128,13 @@ Layout layout(const mp3_plan_s* p, long long np_total = 0) {
     L.offs = take(nt * sizeof(int));
     L.cursor = take(nt * sizeof(int));
     L.power = take(B * (size_t)mp3::nq2_count(p->n) * sizeof(double));
+    // adjoint: per-particle sources (sorted order, all bins), F_J, the
+    // volume-mean weights per |q|^2 and sum_i w_i F_J(u_i)
+    const size_t npt = (size_t)(np_total > 0 ? np_total : 1);
+    L.src = take(npt * (size_t)p->nbins * p->celt);
+    L.fj = take(npt * sizeof(double));
+    L.hq = take(B * (size_t)mp3::nq2_count(p->n) * sizeof(double));
+    L.SF = take(B * sizeof(double));
   }
   // tiled deposit, last so that the offsets above do not depend on the
   // number of particles of the nodal and grid forms
@@ -615,11 +623,103 @@ int mp3_zeta(mp3_plan_t p, const void* delta, const float* pos, const float* w, 
   return zeta_nodal(p, delta, zeta, ws, L, st);
 }
 
+namespace {
+
+// Adjoint of the particle summation (chain rule of zeta_particle):
+//   dJ/ddelta = (4 pi / N^3) 2 Re fftn( sum_{l,m,b} wm K_b ifftn(c_b) - H conj(dhat) / (4 pi N^3) ),
+//   c_b = N^3 scatter_i[ (w_i / W) sum_b' lam_s[b][b'] conj(atilde_b'(u_i)) ],
+//   H(q) = B7hat(q) sum_l (2l+1) sum_{b1,b2} lam_l[b1][b2] jbar_{l,b1} jbar_{l,b2},
+// and dJ/dw adds the primary vertex's 4 pi [F_J(u_i) / W - sum_j w_j F_J(u_j) / W^2]
+// to the deposit's chain rule.
+int backward_particle(mp3_plan_t p, const void* delta, const double* dzeta, void* ddelta, const float* pos,
+                      const float* w, const int64_t* np_off, void* dw, void* ws, size_t wsb, void* stream) {
+  long long np_total = 0, np_max = 0;
+  if (int s = check_offsets(p, np_off, &np_total, &np_max)) return s;
+  if (!pos) return fail(MP3_EINVAL, "pos is NULL (the particle form's adjoint needs the catalogue)");
+  if (np_total >= (1LL << 31)) return fail(MP3_EUNSUPPORTED, "more than 2^31 - 1 particles");
+  const Layout L = layout(p, np_total);
+  if (int s = check_ws(p, ws, wsb, L.total)) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const long long n3 = (long long)p->n * p->n * p->n;
+  const double sc = (double)p->n / p->box;
+  if (int s = forward_dft(p, delta, ws, L, st)) return s;
+  if (int s = upload_offsets(p, np_off, ws, L, st)) return s;
+  const long long* off = reinterpret_cast<const long long*>(at(ws, L.off));
+  double* W = reinterpret_cast<double*>(at(ws, L.W));
+  MP3_HIP(mp3::launch_fill_f64(W, p->batch, 0.0, st), "zero W");
+  MP3_HIP(mp3::launch_weight_sum(w, off, p->batch, np_max, W, st), "weight sum");
+  int* perm = reinterpret_cast<int*>(at(ws, L.perm));
+  const int* toff = reinterpret_cast<const int*>(at(ws, L.offs));
+  MP3_HIP(mp3::launch_tile_sort(pos, off, p->batch, np_total, p->n, sc, 2, reinterpret_cast<int*>(at(ws, L.counts)),
+                                reinterpret_cast<int*>(at(ws, L.offs)), reinterpret_cast<int*>(at(ws, L.cursor)), perm, st),
+          "tile sort");
+  void* F = at(ws, L.fields);
+  void* Fi = at(ws, L.fields_i);
+  void* G = at(ws, L.G);
+  void* direct = at(ws, L.direct);
+  void* src = at(ws, L.src);
+  double* FJ = reinterpret_cast<double*>(at(ws, L.fj));
+  MP3_HIP(mp3::launch_fill(p->prec, G, 2 * n3 * p->batch, 0.0, st), "zero G");
+  MP3_HIP(mp3::launch_fill(p->prec, direct, n3 * p->batch, 0.0, st), "zero direct");
+  MP3_HIP(mp3::launch_fill_f64(FJ, np_total, 0.0, st), "zero F_J");
+  const int gwg = gather_wgs(p, np_max);
+  for (int l = 0; l <= p->lmax; ++l) {
+    MP3_HIP(mp3::launch_lam_sym(p->prec, dzeta, at(ws, L.lam), p->nbins, l, p->lmax, p->batch, st), "lambda");
+    for (int m = 0; m <= l; ++m) {
+      const double wm = m == 0 ? 1.0 : 2.0;
+      if (int s = fields_xy(p, ws, L, F, l, m, st)) return s;
+      mp3::ZpassArgs z{};
+      z.fields = F;
+      z.tw = p->tw;
+      z.nbins = p->nbins;
+      z.nwg = L.nwg;
+      z.ppw = L.ppw;
+      z.batch = p->batch;
+      MP3_HIP(timed(p, MP3_PASS_Z_STORE, st, [&] { return mp3::launch_zpass_store(p->n, p->prec, z, Fi, st); }), "z pass (store)");
+      MP3_HIP(timed(p, MP3_PASS_GATHER, st, [&] {
+                return mp3::launch_gather_source(p->prec, Fi, pos, w, perm, off, W, at(ws, L.lam), p->n, sc, p->nbins, wm,
+                                                 gwg, p->batch, FJ, src, st);
+              }),
+              "gather (adjoint sources)");
+      MP3_HIP(timed(p, MP3_PASS_SCATTER, st, [&] {
+                return mp3::launch_scatter_source(p->prec, pos, perm, toff, src, p->n, sc, p->nbins, p->batch, F, st);
+              }),
+              "scatter (adjoint sources)");
+      MP3_HIP(timed(p, MP3_PASS_Z_ADJOINT, st, [&] { return mp3::launch_fft_z(p->n, p->prec, +1, F, F, p->batch * p->nbins, p->tw, st); }),
+              "adjoint z pass");
+      MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, F, p->batch * p->nbins, p->tw, p->tune[MP3_TUNE_FFT_X_PLAN], st); }),
+              "adjoint x pass");
+      mp3::FilterArgs a = filter_args(p, F, G, l, m, wm / (double)n3);
+      MP3_HIP(timed(p, MP3_PASS_ADJOINT, st, [&] { return mp3::launch_adjoint_y(p->n, p->prec, a, st); }), "adjoint window pass");
+    }
+  }
+  MP3_HIP(mp3::launch_fbar_adjoint(p->prec, dzeta, p->jtab, p->nq2, p->nbp, p->nbins, p->lmax, at(ws, L.dhat), p->n,
+                                   -1.0 / (kFourPi * (double)n3), reinterpret_cast<double*>(at(ws, L.hq)), G, p->batch, st),
+          "volume-mean adjoint");
+  MP3_HIP(timed(p, MP3_PASS_DFT, st, [&] { return mp3::launch_fft3d(p->n, p->prec, -1, false, G, G, p->batch, p->tw, st); }), "adjoint final FFT");
+  MP3_HIP(mp3::launch_grad_combine(p->prec, direct, G, ddelta, n3 * p->batch, kFourPi / (double)n3, st), "combine");
+  if (dw) {
+    double* S = reinterpret_cast<double*>(at(ws, L.S));
+    double* SF = reinterpret_cast<double*>(at(ws, L.SF));
+    MP3_HIP(mp3::launch_fill_f64(S, p->batch, 0.0, st), "zero S");
+    MP3_HIP(mp3::launch_fill_f64(SF, p->batch, 0.0, st), "zero SF");
+    MP3_HIP(mp3::launch_dot_rho_g(p->prec, delta, ddelta, n3, S, p->batch, st), "dot");
+    MP3_HIP(mp3::launch_gather_dw(p->prec, pos, off, p->batch, np_total, p->n, sc, ddelta, W, S, dw, st), "gather dw");
+    MP3_HIP(mp3::launch_weighted_sum(w, FJ, off, p->batch, np_max, SF, st), "sum w F_J");
+    MP3_HIP(mp3::launch_primary_dw(p->prec, off, p->batch, np_total, FJ, W, SF, dw, st), "primary dw");
+  }
+  return MP3_OK;
+}
+
+}  // namespace
+
 int mp3_zeta_backward(mp3_plan_t p, const void* delta, const double* dzeta, void* ddelta, const float* pos,
                       const float* w, const int64_t* np_off, void* dw, void* ws, size_t wsb, void* stream) {
   if (int s = check_plan(p)) return s;
   if (!delta || !dzeta || !ddelta) return fail(MP3_EINVAL, "delta, dzeta and ddelta must not be NULL");
-  if (p->summation != MP3_SUM_NODAL) return fail(MP3_EUNSUPPORTED, "the adjoint is implemented for the nodal form");
+  if (p->summation == MP3_SUM_GRID_GAMMA)
+    return fail(MP3_EUNSUPPORTED, "the adjoint is implemented for the nodal and particle forms");
+  if (p->summation == MP3_SUM_PARTICLE) return backward_particle(p, delta, dzeta, ddelta, pos, w, np_off, dw, ws, wsb, stream);
   long long np_total = 0, np_max = 0;
   if (dw) {
     if (int s = check_offsets(p, np_off, &np_total, &np_max)) return s;

@@ -1,0 +1,168 @@
+"""GPU parity at the full workload sizes, in the launch configuration the bench times.
+
+At these sizes the float64 oracle takes minutes to tens of minutes, so its
+sampled results are stored by tests/golden/make_fullsize.py (oracle and
+mockgen only) in tests/golden/fullsize_*.json.  Each test compares
+  * the stored oracle sample (a few (l, bin) sub-blocks of zeta, the density
+    contrast and the gradients at seeded nodes or particles): float64 GPU form
+    at 1e-10 and float32 at 1e-4, per multipole for zeta (A17 reading) and
+    relative to the largest magnitude for the samples, and
+  * every multipole of the float32 path against the float64 GPU form (a
+    property that holds at any size) at 1e-4 per multipole.
+Progress lines name the case before each step.
+"""
+import json
+import os
+import time
+
+import numpy as np
+import pytest
+
+from mockgen import WORKLOADS, workload_catalogue
+from tests._common import ROOT, assert_zeta_close
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def _say(*a):
+    print("[fullsize]", time.strftime("%H:%M:%S"), *a, flush=True)
+
+
+def _golden(name):
+    return json.load(open(os.path.join(GOLDEN, f"fullsize_{name}.json")))
+
+
+@pytest.fixture(scope="module")
+def mp3():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_15209_amd as m
+    return m
+
+
+def _dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def _sub(z, ls, bins):
+    return np.asarray(z)[np.ix_(ls, bins, bins)]
+
+
+def _samples_close(got, ref, scale, tol):
+    err = np.abs(np.asarray(got, np.float64) - np.asarray(ref, np.float64)).max() / scale
+    assert err <= tol, err
+    return err
+
+
+def _embed_lam(g, wl, batch=1, per_mock=None):
+    lam = np.zeros((batch, wl.lmax + 1, wl.nbins, wl.nbins))
+    for j in range(batch):
+        src = g["lam"] if per_mock is None else per_mock[j]
+        for li, l in enumerate(g["ls"]):
+            lam[j, l][np.ix_(g["bins"], g["bins"])] = np.asarray(src[li])
+    return lam
+
+
+def test_nodal_256_forward_and_gradient(mp3):
+    """box 2000, 256^3, L = 10, 20 bins, 8e6 particles: the bench's workload and launch shapes."""
+    g = _golden("nodal_256")
+    wl = WORKLOADS[g["workload"]]
+    ls, bins, nodes = g["ls"], g["bins"], np.asarray(g["nodes"])
+    _say("nodal 256: mock")
+    pos, w = workload_catalogue(wl)
+    pt, wt = _dev(pos, torch.float32), _dev(w, torch.float32)
+    lam = _dev(_embed_lam(g, wl), torch.float64)
+    res = {}
+    for prec in ("f32", "f64"):
+        _say("nodal 256: GPU", prec)
+        plan = mp3.Plan(wl.n, wl.box, wl.lmax, wl.edges, precision=prec)
+        d = plan.deposit(pt, wt)
+        z = plan.zeta(d).cpu().numpy()[0]
+        gr, _ = plan.zeta_backward(d, lam)
+        res[prec] = (d.cpu().numpy()[0].ravel()[nodes], z, gr.cpu().numpy()[0].ravel()[nodes])
+        del plan, d, gr
+        torch.cuda.empty_cache()
+    e = assert_zeta_close(res["f32"][1], res["f64"][1], 1e-4)
+    _say("f32 vs f64 per l", np.array2string(e, precision=2))
+    z64 = res["f64"][1]
+    assert np.abs(z64 - z64.transpose(0, 2, 1)).max() <= 1e-12 * np.abs(z64).max()
+    for prec, tol in (("f64", 1e-10), ("f32", 1e-4)):
+        dsm, z, gsm = res[prec]
+        _samples_close(dsm, g["delta"], g["delta_max"], 1e-12 if prec == "f64" else 1e-6)
+        assert_zeta_close(_sub(z, ls, bins), g["zeta"], tol)
+        _samples_close(gsm, g["grad"], g["grad_max"], tol)
+
+
+@pytest.mark.parametrize("name", ["particle_512", "particle_128"])
+def test_particle_fullsize(mp3, name):
+    """512^3 / 5e7 weighted particles (the target workload) and 128^3 / 1e6 particles, particle summation."""
+    g = _golden(name)
+    wl = WORKLOADS[g["workload"]]
+    ls, bins, nodes = g["ls"], g["bins"], np.asarray(g["nodes"])
+    _say(name, "mock")
+    pos, w = workload_catalogue(wl)
+    pt, wt = _dev(pos, torch.float32), _dev(w, torch.float32)
+    res = {}
+    for prec in ("f32", "f64"):
+        _say(name, "GPU", prec)
+        plan = mp3.Plan(wl.n, wl.box, wl.lmax, wl.edges, precision=prec, summation="particle")
+        d = plan.deposit(pt, wt)
+        res[prec] = (d.cpu().numpy()[0].ravel()[nodes], plan.zeta(d, pt, wt).cpu().numpy()[0])
+        del plan, d
+        torch.cuda.empty_cache()
+    e = assert_zeta_close(res["f32"][1], res["f64"][1], 1e-4)
+    _say("f32 vs f64 per l", np.array2string(e, precision=2))
+    for prec, tol in (("f64", 1e-10), ("f32", 1e-4)):
+        dsm, z = res[prec]
+        _samples_close(dsm, g["delta"], g["delta_max"], 1e-12 if prec == "f64" else 1e-6)
+        assert_zeta_close(_sub(z, ls, bins), g["zeta"], tol)
+
+
+def test_gamma_256(mp3):
+    """box 2000, 256^3, L = 10, 20 bins, 8e6 particles, grid summation with connection coefficients."""
+    g = _golden("gamma_256")
+    wl = WORKLOADS[g["workload"]]
+    ls, bins = g["ls"], g["bins"]
+    _say("gamma 256: mock")
+    pos, w = workload_catalogue(wl)
+    pt, wt = _dev(pos, torch.float32), _dev(w, torch.float32)
+    out = {}
+    for prec in ("f32", "f64"):
+        _say("gamma 256: GPU", prec)
+        plan = mp3.Plan(wl.n, wl.box, wl.lmax, wl.edges, precision=prec, summation="gamma")
+        out[prec] = plan.zeta(plan.deposit(pt, wt)).cpu().numpy()[0]
+        del plan
+        torch.cuda.empty_cache()
+    e = assert_zeta_close(out["f32"], out["f64"], 1e-4)
+    _say("f32 vs f64 per l", np.array2string(e, precision=2))
+    assert_zeta_close(_sub(out["f64"], ls, bins), g["zeta"], 1e-10)
+    assert_zeta_close(_sub(out["f32"], ls, bins), g["zeta"], 1e-4)
+
+
+def test_batch64_forward_and_weight_gradient(mp3):
+    """64 mocks of 2e5..1e6 particles, 128^3, L = 8, 12 bins, float32, one call per step."""
+    g = _golden("batch64")
+    wl = WORKLOADS[g["workload"]]
+    ls, bins, sizes = g["ls"], g["bins"], g["sizes"]
+    _say("batch64: mocks")
+    cats = [workload_catalogue(wl, j, sizes[j]) for j in range(64)]
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    pt = _dev(np.concatenate([c[0] for c in cats]), torch.float32)
+    wt = _dev(np.concatenate([c[1] for c in cats]), torch.float32)
+    zero = [[[0.0] * len(bins)] * len(bins)] * len(ls)
+    per_mock = [g["mocks"][str(j)]["lam"] if str(j) in g["mocks"] else zero for j in range(64)]
+    lam = _dev(_embed_lam(g, wl, 64, per_mock), torch.float64)
+    _say("batch64: GPU f32 forward + backward")
+    plan = mp3.Plan(wl.n, wl.box, wl.lmax, wl.edges, precision="f32", batch=64)
+    delta = plan.deposit(pt, wt, off)
+    z = plan.zeta(delta).cpu().numpy()
+    _, dw = plan.zeta_backward(delta, lam, pt, wt, off)
+    dw = dw.cpu().numpy()
+    for key, ref in g["mocks"].items():
+        j = int(key)
+        assert_zeta_close(_sub(z[j], ls, bins), ref["zeta"], 1e-4)
+        got = dw[off[j]:off[j + 1]][np.asarray(ref["particles"])]
+        _samples_close(got, ref["dw"], ref["dw_max"], 1e-4)

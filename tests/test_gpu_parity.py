@@ -233,8 +233,11 @@ def test_invalid_arguments_raise(mp3):
     pp = mp3.Plan(16, 100.0, 1, [10.0, 20.0], summation="particle")
     with pytest.raises(ValueError):
         pp.zeta(d)                                # catalogue missing
+    with pytest.raises(ValueError):
+        pp.zeta_backward(d, torch.zeros((1, 2, 1, 1), dtype=torch.float64, device="cuda"))   # catalogue missing
+    pg = mp3.Plan(16, 100.0, 1, [10.0, 20.0], summation="gamma")
     with pytest.raises(mp3.Mp3Error):
-        pp.zeta_backward(d, torch.zeros((1, 2, 1, 1), dtype=torch.float64, device="cuda"))
+        pg.zeta_backward(d, torch.zeros((1, 2, 1, 1), dtype=torch.float64, device="cuda"))   # no grid-Gamma adjoint
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -302,3 +305,49 @@ def test_zeta_gamma_small_workload(mp3, prec):
     ref = E.zeta_gamma_quadrature(E.Plan(wl.n, wl.box, wl.lmax, wl.edges), dref)
     e = assert_zeta_close(z, ref, TOL[prec])
     print("per-l errors", e)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n,lmax,nb,npart", [(16, 2, 3, 3000), (32, 3, 5, 20000)])
+def test_backward_particle(mp3, prec, n, lmax, nb, npart):
+    """Particle-form gradient (dJ/ddelta at fixed primary weights, dJ/dw) against the oracle's."""
+    _say("backward particle", prec, n, lmax, nb, npart)
+    box = 8.0 * n
+    edges = np.linspace(0.06 * box, 0.35 * box, nb + 1)
+    pos, w = lognormal_catalogue(n, box, npart, 0.04 * box, 190 + n, 191 + n, 192 + n, (0.5, 1.5))
+    lam = np.random.default_rng(193 + n).standard_normal((1, lmax + 1, nb, nb))
+    plan = mp3.Plan(n, box, lmax, edges, precision=prec, summation="particle")
+    pt, wt = _dev(pos, torch.float32), _dev(w, torch.float32)
+    delta = plan.deposit(pt, wt)
+    g, dw = plan.zeta_backward(delta, _dev(lam, torch.float64), pt, wt)
+    g, dw = g.cpu().numpy()[0], dw.cpu().numpy()
+    gref, dwref = A.zeta_particle_grad(E.Plan(n, box, lmax, edges), pos, w, lam[0])
+    eg = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    ew = np.linalg.norm(dw - dwref) / np.linalg.norm(dwref)
+    print("grad errors", eg, ew)
+    tol = TOL[prec]
+    assert eg <= tol and ew <= tol, (eg, ew)
+
+
+def test_backward_particle_batch_autograd(mp3):
+    """Two uneven catalogues, particle form, float32, through zeta_from_catalogue's autograd."""
+    _say("backward particle batch")
+    n, box, lmax = 32, 320.0, 2
+    edges = np.linspace(20.0, 100.0, 5)
+    cats = [lognormal_catalogue(n, box, npart, 12.0, 400 + j, 410 + j, 420 + j, (0.5, 1.5))
+            for j, npart in enumerate((9000, 4000))]
+    pos = np.concatenate([c[0] for c in cats])
+    w = np.concatenate([c[1] for c in cats])
+    off = np.cumsum([0] + [len(c[1]) for c in cats])
+    lam = np.random.default_rng(430).standard_normal((2, lmax + 1, 4, 4))
+    plan = mp3.Plan(n, box, lmax, edges, precision="f32", batch=2, summation="particle")
+    pt = _dev(pos, torch.float32)
+    wt = _dev(w, torch.float32).requires_grad_(True)
+    z = mp3.zeta_from_catalogue(plan, pt, wt, off)
+    (z * _dev(lam, torch.float64)).sum().backward()
+    dw = wt.grad.cpu().numpy()
+    op = E.Plan(n, box, lmax, edges)
+    for j, (p_, w_) in enumerate(cats):
+        _, dwref = A.zeta_particle_grad(op, p_, w_, lam[j])
+        got = dw[off[j]:off[j + 1]]
+        assert np.linalg.norm(got - dwref) <= 1e-4 * np.linalg.norm(dwref), j

@@ -76,3 +76,53 @@ def test_fft_filter_dot_products():
     lhs = np.sum(np.fft.ifftn(K * np.fft.fftn(x)) * c)
     rhs = np.sum(x * np.fft.fftn(K * np.fft.ifftn(c)))
     assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+
+
+def _particle_case():
+    n, box = 8, 80.0
+    pos, w = lognormal_catalogue(n, box, 1500, 12.0, 31, 32, 33, (0.5, 1.5))
+    plan = E.Plan(n, box, 2, np.array([8.0, 16.0, 24.0, 32.0]))
+    lam = np.random.default_rng(34).standard_normal((plan.lmax + 1, plan.nbins, plan.nbins))
+    return plan, pos, w.astype(np.float64), lam
+
+
+def test_particle_grad_delta_matches_finite_differences():
+    """dJ/ddelta of the particle form (primary weights fixed) against central differences."""
+    plan, pos, w, lam = _particle_case()
+    g, _ = A.zeta_particle_grad(plan, pos, w, lam)
+    delta = basis.density_contrast(basis.deposit(pos, w, plan.n, plan.box), w.sum())
+    rng = np.random.default_rng(35)
+    for _ in range(3):
+        v = rng.standard_normal(delta.shape)
+        v /= np.sqrt(np.mean(v * v))
+        h = 1e-4
+        jp = np.sum(lam * E.zeta_particle(plan, pos, w, delta=delta + h * v))
+        jm = np.sum(lam * E.zeta_particle(plan, pos, w, delta=delta - h * v))
+        fd = (jp - jm) / (2 * h)
+        assert abs(fd - np.sum(g * v)) < 1e-7 * abs(fd)
+
+
+def test_particle_grad_weights_matches_finite_differences():
+    """dJ/dw of the particle form (through the deposit and the primary) against central differences."""
+    plan, pos, w, lam = _particle_case()
+    _, dw = A.zeta_particle_grad(plan, pos, w, lam)
+    rng = np.random.default_rng(36)
+    for _ in range(3):
+        v = rng.standard_normal(w.shape)
+        v /= np.linalg.norm(v)
+        h = 1e-4
+        fd = (A.zeta_particle_objective(plan, pos, w + h * v, lam)
+              - A.zeta_particle_objective(plan, pos, w - h * v, lam)) / (2 * h)
+        assert abs(fd - np.dot(dw, v)) < 1e-7 * abs(fd)
+
+
+def test_particle_grad_subset_equals_masked_full():
+    """Restricting to some (l, bins) equals the full gradient with lam zero elsewhere."""
+    plan, pos, w, lam = _particle_case()
+    ls, bins = [0, 2], [0, 2]
+    masked = np.zeros_like(lam)
+    masked[np.ix_(ls, bins, bins)] = lam[np.ix_(ls, bins, bins)]
+    g_full, dw_full = A.zeta_particle_grad(plan, pos, w, masked)
+    g_sub, dw_sub = A.zeta_particle_grad(plan, pos, w, lam[np.ix_(ls, bins, bins)], ls=ls, bins=bins)
+    assert np.abs(g_full - g_sub).max() <= 1e-12 * np.abs(g_full).max()
+    assert np.abs(dw_full - dw_sub).max() <= 1e-12 * np.abs(dw_full).max()
