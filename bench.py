@@ -154,6 +154,27 @@ def pmc_summarize(fetch_dir, write_dir, wl, precision):
     print("\n".join(out))
 
 
+def pmc_table(root):
+    """Markdown table of per-dispatch counter averages by kernel from rocprofv3 --pmc runs under root."""
+    rows = _csv_rows(root, "counter_collection.csv")
+    agg = {}
+    for r in rows:
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        d = agg.setdefault(name, {})
+        v = d.setdefault(r["Counter_Name"], [0.0, 0])
+        v[0] += float(r["Counter_Value"])
+        v[1] += 1
+    counters = sorted({c for d in agg.values() for c in d})
+    print("| kernel | " + " | ".join(counters) + " |")
+    print("|---" * (len(counters) + 1) + "|")
+    for name in sorted(agg):
+        cells = []
+        for c in counters:
+            v = agg[name].get(c)
+            cells.append(f"{v[0] / v[1]:.4g}" if v else "")
+        print(f"| `{name[:70]}` | " + " | ".join(cells) + " |")
+
+
 def stats_summarize(root, top=20):
     """Markdown table of a rocprofv3 --kernel-trace --stats run (kernel_stats.csv)."""
     rows = _csv_rows(root, "kernel_stats.csv")
@@ -200,9 +221,13 @@ def main():
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print the per-launch traffic summary of two rocprofv3 --pmc runs of --pmc-probe")
     ap.add_argument("--stats-summarize", metavar="DIR", help="print a table of a rocprofv3 --stats run")
+    ap.add_argument("--pmc-table", metavar="DIR", help="print per-kernel averages of rocprofv3 --pmc runs")
     args = ap.parse_args()
     if args.stats_summarize:
         stats_summarize(args.stats_summarize)
+        return
+    if args.pmc_table:
+        pmc_table(args.pmc_table)
         return
     if args.pmc_summarize:
         from mockgen import WORKLOADS

@@ -64,7 +64,12 @@ enum mp3_status {
   MP3_EWORKSPACE = -5     /* workspace pointer NULL or smaller than required       */
 };
 
-enum mp3_precision { MP3_F32 = 0, MP3_F64 = 1 };
+/* MP3_F32_BF16X3 is MP3_F32 whose contractions on the matrix cores (nodal,
+ * grid-Gamma and particle forms with at most 32 bins) take BF16-split inputs:
+ * each float32 operand x is carried as hi = bf16(x), lo = bf16(x - hi) and each
+ * product as hi*hi + hi*lo + lo*hi, accumulated in float32 (relative error of
+ * about 2^-16 per product against 2^-24).  Everything else is as MP3_F32. */
+enum mp3_precision { MP3_F32 = 0, MP3_F64 = 1, MP3_F32_BF16X3 = 2 };
 
 enum mp3_summation {
   MP3_SUM_NODAL = 0,      /* grid summation on the nodes (connection coefficients

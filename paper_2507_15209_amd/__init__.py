@@ -36,12 +36,14 @@ class Plan:
     """A configuration of the estimator: grid, box, multipole order, radial bins.
 
     precision "f32": fields, FFTs and window in float32 (tables generated in
-    float64, reductions in float64); "f64": the plain float64 form.
+    float64, reductions in float64); "f64": the plain float64 form; "bf16x3":
+    "f32" with BF16-split inputs to the matrix-core contractions.
     summation "nodal": grid summation on the nodes; "gamma": grid summation
     with the B-spline connection coefficients; "particle": primary vertex on
     the catalogue (zeta() then needs pos, w, np_off).
     """
 
+    PRECISIONS = {"f32": _lib.MP3_F32, "f64": _lib.MP3_F64, "bf16x3": _lib.MP3_F32_BF16X3}
     SUMMATIONS = {"nodal": _lib.MP3_SUM_NODAL, "gamma": _lib.MP3_SUM_GRID_GAMMA, "particle": _lib.MP3_SUM_PARTICLE}
 
     def __init__(self, n: int, box: float, lmax: int, edges, precision: str = "f32", batch: int = 1,
@@ -50,18 +52,18 @@ class Plan:
         self.n, self.box, self.lmax, self.batch = int(n), float(box), int(lmax), int(batch)
         self.edges = np.ascontiguousarray(edges, dtype=np.float64)
         self.nbins = self.edges.size - 1
-        if precision not in ("f32", "f64"):
-            raise ValueError("precision must be 'f32' or 'f64'")
+        if precision not in self.PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(self.PRECISIONS)}")
         self.precision = precision
         if summation not in self.SUMMATIONS:
             raise ValueError(f"summation must be one of {sorted(self.SUMMATIONS)}")
         self.summation = summation
-        self.real_dtype = torch.float32 if precision == "f32" else torch.float64
-        self.complex_dtype = torch.complex64 if precision == "f32" else torch.complex128
+        self.real_dtype = torch.float64 if precision == "f64" else torch.float32
+        self.complex_dtype = torch.complex128 if precision == "f64" else torch.complex64
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         desc = _lib.PlanDesc(self.n, self.box, self.lmax, self.nbins,
                              self.edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                             _lib.MP3_F32 if precision == "f32" else _lib.MP3_F64,
+                             self.PRECISIONS[precision],
                              self.SUMMATIONS[summation], self.batch)
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):

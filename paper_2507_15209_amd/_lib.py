@@ -15,6 +15,7 @@ MP3_EUNSUPPORTED = -4
 MP3_EWORKSPACE = -5
 MP3_F32 = 0
 MP3_F64 = 1
+MP3_F32_BF16X3 = 2
 MP3_SUM_NODAL = 0
 MP3_SUM_PARTICLE = 2
 MP3_SUM_GRID_GAMMA = 1

@@ -540,11 +540,79 @@ __device__ __forceinline__ void mfma_contract_pencil(const float2* A, const floa
   }
 }
 
+// BF16-split variant: every float operand x is carried as hi = bf16(x) and
+// lo = bf16(x - hi) and each product as hi*hi + hi*lo + lo*hi on the bf16
+// matrix cores (v_mfma_f32_16x16x16bf16_1k, k = 8 z values x (re, im) per
+// instruction), accumulating in float32.  The dropped lo*lo term and the
+// rounding of lo leave a relative error of about 2^-16 per product.
+typedef short mp3_s4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  const unsigned u = __float_as_uint(x);
+  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_float(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+__device__ __forceinline__ void bf16_split4(const float* x, mp3_s4& hi, mp3_s4& lo) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const unsigned short h = bf16_rne(x[i]);
+    hi[i] = (short)h;
+    lo[i] = (short)bf16_rne(x[i] - bf16_to_float(h));
+  }
+}
+
+__device__ __forceinline__ mp3_f4 mfma3(const mp3_s4& ah, const mp3_s4& al, const mp3_s4& bh, const mp3_s4& bl,
+                                        mp3_f4 c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, c, 0, 0, 0);
+  return c;
+}
+
+// K must be a multiple of 8.  Lane l supplies A[l%16][4 (l/16) + j] and
+// B[4 (l/16) + j][l%16], j = 0..3: k = 2 (z - z0) + comp over z = z0 + 2 (l/16) + {0, 1}.
+__device__ __forceinline__ void mfma_contract_bf16x3(const float2* A, const float* dl, int nbins, int RS, int K,
+                                                     MfmaAcc& acc) {
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  const bool two = nbins > 16;
+  const bool ok0 = col < nbins, ok1 = 16 + col < nbins;
+  const float2* r0 = A + col * RS;
+  const float2* r1 = A + (16 + col) * RS;
+  for (int zc = w; zc < K / 8; zc += nw) {
+    const int z = 8 * zc + 2 * kq;
+    const int p0 = lds_pos<true>(z), p1 = lds_pos<true>(z + 1);
+    const float d0 = dl[z], d1 = dl[z + 1];
+    float2 u0 = ok0 ? r0[p0] : make_float2(0.f, 0.f);
+    float2 u1 = ok0 ? r0[p1] : make_float2(0.f, 0.f);
+    float xa[4] = {d0 * u0.x, d0 * u0.y, d1 * u1.x, d1 * u1.y};
+    float xb[4] = {u0.x, u0.y, u1.x, u1.y};
+    mp3_s4 ah, al, bh, bl;
+    bf16_split4(xa, ah, al);
+    bf16_split4(xb, bh, bl);
+    acc.c00 = mfma3(ah, al, bh, bl, acc.c00);
+    if (two) {
+      u0 = ok1 ? r1[p0] : make_float2(0.f, 0.f);
+      u1 = ok1 ? r1[p1] : make_float2(0.f, 0.f);
+      float ya[4] = {d0 * u0.x, d0 * u0.y, d1 * u1.x, d1 * u1.y};
+      float yb[4] = {u0.x, u0.y, u1.x, u1.y};
+      mp3_s4 ch, cl, dh, dlo;
+      bf16_split4(ya, ch, cl);
+      bf16_split4(yb, dh, dlo);
+      acc.c01 = mfma3(ah, al, dh, dlo, acc.c01);
+      acc.c11 = mfma3(ch, cl, dh, dlo, acc.c11);
+    }
+  }
+}
+
 // Per-workgroup accumulator of  P[b1,b2] = sum_k w_k Re(a_b1(k) conj(a_b2(k)))
 // over LDS rows A[b * RS + lds_pos(k)], either on the matrix cores (MF) or in
 // 4x4 register blocks on the vector ALUs.  Partial sums stay in the working
 // precision over the workgroup's slices and are written as float64.
-template <typename T, bool MF>
+template <typename T, bool MF, bool SPLIT = false>
 struct Contractor {
   PairBlocks pb;
   int bb1 = 0, bb2 = 0, zc = 0;
@@ -568,7 +636,9 @@ struct Contractor {
 
   // K positions (even), weights w[k] in LDS
   __device__ void add(const c2<T>* A, const T* w, int nbins, int RS, int K) {
-    if constexpr (MF) {
+    if constexpr (MF && SPLIT) {
+      mfma_contract_bf16x3(reinterpret_cast<const float2*>(A), reinterpret_cast<const float*>(w), nbins, RS, K, macc);
+    } else if constexpr (MF) {
       mfma_contract_pencil(reinterpret_cast<const float2*>(A), reinterpret_cast<const float*>(w), nbins, RS, K, macc);
     } else if (has_item) {
       const int b1o = 4 * bb1, b2o = 4 * bb2;
@@ -643,7 +713,7 @@ struct Contractor {
   }
 };
 
-template <int N, typename T, bool MF>
+template <int N, typename T, bool MF, bool SPLIT = false>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MF ? 4 : 1))) k_zpass_nodal(
     const c2<T>* fields, const T* delta, double* partials, int nbins, int ppw, const c2<T>* tw) {
   using F = Fft<N, VZN>;
@@ -656,7 +726,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MF ? 4
   const int tid = threadIdx.x;
   const long long mock = blockIdx.y;
   stage_twiddles<N, T>(tw, tws);
-  Contractor<T, MF> ctr;
+  Contractor<T, MF, SPLIT> ctr;
   ctr.init(nbins);
   const int p0 = blockIdx.x * ppw;
   const int p1 = min(p0 + ppw, N * N);
@@ -802,7 +872,7 @@ __global__ void k_tile_scatter(const float* pos, const long long* off, int batch
 // Gather the B-spline interpolants of the (bin-interleaved) fields at the
 // particles, one lane per (particle, bin), into LDS rows, then contract with
 // the weights w_i / W.  Particles are visited in tile order (perm).
-template <typename T, bool MF>
+template <typename T, bool MF, bool SPLIT = false>
 __global__ void __launch_bounds__(256) k_gather_contract(const c2<T>* fields, const float* pos, const float* w,
                                                           const int* perm, const long long* off, const double* W,
                                                           int n, double sc, int nbins, double* partials) {
@@ -821,7 +891,7 @@ __global__ void __launch_bounds__(256) k_gather_contract(const c2<T>* fields, co
   const int ppp = blockDim.x / lpp;                     // particles per pass
   const int b = threadIdx.x % lpp;
   const c2<T>* fm = fields + mock * n3 * nbins;
-  Contractor<T, MF> ctr;
+  Contractor<T, MF, SPLIT> ctr;
   ctr.init(nbins);
   for (long long c0 = s0; c0 < s1; c0 += K) {
     for (int k0 = 0; k0 < K; k0 += ppp) {
@@ -914,7 +984,7 @@ struct GammaLds {
   }
 };
 
-template <typename T, bool MF>
+template <typename T, bool MF, bool SPLIT = false>
 __global__ void __launch_bounds__(512) k_gamma_contract(const c2<T>* fields, const T* delta, int n, int nbins,
                                                          GammaQuad gq, double* partials) {
   extern __shared__ __align__(16) char smem[];
@@ -934,7 +1004,7 @@ __global__ void __launch_bounds__(512) k_gamma_contract(const c2<T>* fields, con
   const T* dm = delta + mock * n3;
   const int td = n / GT;
   const long long ntiles = (long long)td * td * td;
-  Contractor<T, MF> ctr;
+  Contractor<T, MF, SPLIT> ctr;
   ctr.init(nbins);
   for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int tx = (int)(tile / ((long long)td * td)), ty = (int)((tile / td) % td), tz = (int)(tile % td);
@@ -1675,17 +1745,18 @@ template <typename K> hipError_t allow_lds(K kernel, size_t bytes) {
   return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int N, typename T, bool MF>
+template <int N, typename T, bool MF, bool SPLIT = false>
 hipError_t zpass_nodal_mf(const ZpassArgs& a, hipStream_t st) {
   const int threads = zpass_threads<N, VZN>(a.nbins);
   size_t lds = zpass_nodal_lds<N, T>(a.nbins, threads);
-  const size_t red = Contractor<T, MF>::scratch_bytes(threads);
+  const size_t red = Contractor<T, MF, SPLIT>::scratch_bytes(threads);
   if (lds < red) lds = red;
-  hipError_t e = allow_lds(k_zpass_nodal<N, T, MF>, lds);
+  hipError_t e = allow_lds(k_zpass_nodal<N, T, MF, SPLIT>, lds);
   if (e != hipSuccess) return e;
   const dim3 gs(a.nwg, a.batch);
-  k_zpass_nodal<N, T, MF><<<gs, threads, lds, st>>>(static_cast<const CT<T>*>(a.fields), static_cast<const T*>(a.delta),
-                                                   a.partials, a.nbins, a.ppw, static_cast<const CT<T>*>(a.tw));
+  k_zpass_nodal<N, T, MF, SPLIT><<<gs, threads, lds, st>>>(static_cast<const CT<T>*>(a.fields),
+                                                          static_cast<const T*>(a.delta), a.partials, a.nbins, a.ppw,
+                                                          static_cast<const CT<T>*>(a.tw));
   return hipGetLastError();
 }
 
@@ -1701,11 +1772,13 @@ hipError_t zpass_store_t(const ZpassArgs& a, void* out, hipStream_t st) {
   return hipGetLastError();
 }
 
-// float32 with at most 32 bins contracts on the matrix cores
+// float32 with at most 32 bins contracts on the matrix cores (float32 or
+// BF16-split inputs); otherwise on the vector ALUs
 template <int N, typename T>
 hipError_t zpass_nodal_t(const ZpassArgs& a, hipStream_t st) {
   if constexpr (std::is_same<T, float>::value) {
-    if (a.nbins <= 32 && zpass_threads<N, VZN>(a.nbins) % 64 == 0) return zpass_nodal_mf<N, T, true>(a, st);
+    if (a.nbins <= 32 && zpass_threads<N, VZN>(a.nbins) % 64 == 0)
+      return a.split ? zpass_nodal_mf<N, T, true, true>(a, st) : zpass_nodal_mf<N, T, true>(a, st);
   }
   return zpass_nodal_mf<N, T, false>(a, st);
 }
@@ -1970,24 +2043,24 @@ hipError_t launch_deposit_tiled(int prec, int tside, const float* pos, const flo
   return deposit_tiled_t<float>(tside, pos, w, perm, toff, ntiles_total, g, counter, n, sc, static_cast<float*>(eps), st);
 }
 
-template <typename T, bool MF>
+template <typename T, bool MF, bool SPLIT = false>
 hipError_t gather_contract_t(const GatherArgs& a, hipStream_t st) {
   constexpr int K = 256;
   const size_t rs = K + K / 16 + 1;
   size_t lds = (size_t)a.nbins * rs * sizeof(CT<T>) + K * sizeof(T);
-  const size_t red = Contractor<T, MF>::scratch_bytes(256);
+  const size_t red = Contractor<T, MF, SPLIT>::scratch_bytes(256);
   if (lds < red) lds = red;
-  hipError_t e = allow_lds(k_gather_contract<T, MF>, lds);
+  hipError_t e = allow_lds(k_gather_contract<T, MF, SPLIT>, lds);
   if (e != hipSuccess) return e;
   const dim3 gs(a.nwg, a.batch);
-  k_gather_contract<T, MF><<<gs, 256, lds, st>>>(static_cast<const CT<T>*>(a.fields), a.pos, a.w, a.perm, a.off, a.W,
-                                                a.n, a.sc, a.nbins, a.partials);
+  k_gather_contract<T, MF, SPLIT><<<gs, 256, lds, st>>>(static_cast<const CT<T>*>(a.fields), a.pos, a.w, a.perm, a.off,
+                                                       a.W, a.n, a.sc, a.nbins, a.partials);
   return hipGetLastError();
 }
 
 hipError_t launch_gather_contract(int prec, const GatherArgs& a, hipStream_t st) {
   if (prec) return gather_contract_t<double, false>(a, st);
-  if (a.nbins <= 32) return gather_contract_t<float, true>(a, st);
+  if (a.nbins <= 32) return a.split ? gather_contract_t<float, true, true>(a, st) : gather_contract_t<float, true>(a, st);
   return gather_contract_t<float, false>(a, st);
 }
 
@@ -2009,22 +2082,22 @@ hipError_t launch_fbar_subtract(int prec, const double* P, const void* jtab, int
   return hipGetLastError();
 }
 
-template <typename T, bool MF>
+template <typename T, bool MF, bool SPLIT = false>
 hipError_t gamma_contract_t(const void* fields, const void* delta, int n, int nbins, const GammaQuad& gq,
                             double* partials, int nwg, int batch, hipStream_t st) {
   const int threads = 512;
   size_t lds = GammaLds<T>(nbins).total;
-  const size_t red = Contractor<T, MF>::scratch_bytes(threads);
+  const size_t red = Contractor<T, MF, SPLIT>::scratch_bytes(threads);
   if (lds < red) lds = red;
-  hipError_t e = allow_lds(k_gamma_contract<T, MF>, lds);
+  hipError_t e = allow_lds(k_gamma_contract<T, MF, SPLIT>, lds);
   if (e != hipSuccess) return e;
   const dim3 gs(nwg, batch);
-  k_gamma_contract<T, MF><<<gs, threads, lds, st>>>(static_cast<const CT<T>*>(fields), static_cast<const T*>(delta), n,
-                                                   nbins, gq, partials);
+  k_gamma_contract<T, MF, SPLIT><<<gs, threads, lds, st>>>(static_cast<const CT<T>*>(fields),
+                                                          static_cast<const T*>(delta), n, nbins, gq, partials);
   return hipGetLastError();
 }
 
-hipError_t launch_gamma_contract(int prec, const void* fields, const void* delta, int n, int nbins,
+hipError_t launch_gamma_contract(int prec, bool split, const void* fields, const void* delta, int n, int nbins,
                                  const double (*m)[4], const double* wq, double* partials, int nwg, int batch,
                                  hipStream_t st) {
   GammaQuad gq;
@@ -2037,7 +2110,10 @@ hipError_t launch_gamma_contract(int prec, const void* fields, const void* delta
     gq.wqd[s] = wq[s];
   }
   if (prec) return gamma_contract_t<double, false>(fields, delta, n, nbins, gq, partials, nwg, batch, st);
-  if (nbins <= 32) return gamma_contract_t<float, true>(fields, delta, n, nbins, gq, partials, nwg, batch, st);
+  if (nbins <= 32) {
+    if (split) return gamma_contract_t<float, true, true>(fields, delta, n, nbins, gq, partials, nwg, batch, st);
+    return gamma_contract_t<float, true>(fields, delta, n, nbins, gq, partials, nwg, batch, st);
+  }
   return gamma_contract_t<float, false>(fields, delta, n, nbins, gq, partials, nwg, batch, st);
 }
 

@@ -25,6 +25,7 @@ struct ZpassArgs {
   const void* tw;
   int nbins, nwg, ppw, batch, l, lmax;
   double wm;            // m weight (1 for m = 0, 2 otherwise)
+  bool split;           // float32 contraction with BF16-split inputs on the matrix cores
 };
 
 struct GatherArgs {
@@ -37,11 +38,12 @@ struct GatherArgs {
   double* partials;       // [batch][nwg][nbins^2]
   int n, nbins, nwg, batch;
   double sc;              // N / box
+  bool split;             // float32 contraction with BF16-split inputs on the matrix cores
 };
 
 // grid summation with connection coefficients (5-point Gauss-Legendre per cell);
 // m[s][t] = B3(xi_s + 1 - t), wq[s] node weights on [0, 1]
-hipError_t launch_gamma_contract(int prec, const void* fields, const void* delta, int n, int nbins,
+hipError_t launch_gamma_contract(int prec, bool split, const void* fields, const void* delta, int n, int nbins,
                                  const double (*m)[4], const double* wq, double* partials, int nwg, int batch,
                                  hipStream_t st);
 size_t gamma_lds_need(int prec, int nbins);

@@ -14,6 +14,7 @@
 
 struct mp3_plan_s {
   int n = 0, lmax = 0, nbins = 0, prec = 0, summation = 0, batch = 1;
+  bool split = false;    // MP3_F32_BF16X3: float32 with BF16-split contraction inputs
   double box = 0.0;
   std::vector<double> edges;
   int nq2 = 0, nbp = 0;
@@ -283,13 +284,15 @@ int mp3_plan_create(const mp3_plan_desc* d, mp3_plan_t* out) {
     if (!std::isfinite(d->edges[b]) || d->edges[b] < 0.0) return fail(MP3_EINVAL, "edges must be finite and >= 0");
     if (b > 0 && !(d->edges[b] > d->edges[b - 1])) return fail(MP3_EINVAL, "edges must increase strictly");
   }
-  if (d->precision != MP3_F32 && d->precision != MP3_F64) return fail(MP3_EINVAL, "precision must be MP3_F32 or MP3_F64");
+  if (d->precision != MP3_F32 && d->precision != MP3_F64 && d->precision != MP3_F32_BF16X3)
+    return fail(MP3_EINVAL, "precision must be MP3_F32, MP3_F64 or MP3_F32_BF16X3");
+  const int storage = d->precision == MP3_F64 ? 1 : 0;
   if (d->summation != MP3_SUM_NODAL && d->summation != MP3_SUM_PARTICLE && d->summation != MP3_SUM_GRID_GAMMA)
     return fail(MP3_EUNSUPPORTED, "summation form not supported");
-  if (d->summation == MP3_SUM_GRID_GAMMA && mp3::gamma_lds_need(d->precision, d->nbins) > kLdsLimit)
+  if (d->summation == MP3_SUM_GRID_GAMMA && mp3::gamma_lds_need(storage, d->nbins) > kLdsLimit)
     return fail(MP3_EUNSUPPORTED, "nbins too large for the grid-Gamma tile's LDS at this precision");
   if (d->batch < 1) return fail(MP3_EINVAL, "batch must be >= 1");
-  if (mp3::zpass_lds_need(d->n, d->precision, d->nbins) > kLdsLimit)
+  if (mp3::zpass_lds_need(d->n, storage, d->nbins) > kLdsLimit)
     return fail(MP3_EUNSUPPORTED, "n * nbins too large for the z pass's LDS at this precision");
 
   mp3_plan_s* p = new (std::nothrow) mp3_plan_s;
@@ -298,7 +301,8 @@ int mp3_plan_create(const mp3_plan_desc* d, mp3_plan_t* out) {
   p->box = d->box;
   p->lmax = d->lmax;
   p->nbins = d->nbins;
-  p->prec = d->precision;
+  p->prec = storage;
+  p->split = d->precision == MP3_F32_BF16X3;
   p->summation = d->summation;
   p->batch = d->batch;
   p->edges.assign(d->edges, d->edges + d->nbins + 1);
@@ -415,7 +419,7 @@ int mp3_plan_info(mp3_plan_t p, int32_t* n, int32_t* lmax, int32_t* nbins, int32
   if (n) *n = p->n;
   if (lmax) *lmax = p->lmax;
   if (nbins) *nbins = p->nbins;
-  if (precision) *precision = p->prec;
+  if (precision) *precision = p->split ? MP3_F32_BF16X3 : p->prec;
   if (batch) *batch = p->batch;
   return MP3_OK;
 }
@@ -499,6 +503,7 @@ int zeta_nodal(mp3_plan_t p, const void* delta, double* zeta, void* ws, const La
       z.batch = p->batch;
       z.l = l;
       z.lmax = p->lmax;
+      z.split = p->split;
       MP3_HIP(timed(p, MP3_PASS_Z_NODAL, st, [&] { return mp3::launch_zpass_nodal(p->n, p->prec, z, st); }), "z pass (contraction)");
       const double wm = m == 0 ? 1.0 : 2.0;
       MP3_HIP(mp3::launch_reduce_partials(partials, L.nwg, nb2, zeta, l, p->lmax, wm * kFourPi / n3, p->batch, st),
@@ -555,6 +560,7 @@ int zeta_particle(mp3_plan_t p, const float* pos, const float* w, const int64_t*
       g.nwg = gwg;
       g.batch = p->batch;
       g.sc = sc;
+      g.split = p->split;
       MP3_HIP(timed(p, MP3_PASS_GATHER, st, [&] { return mp3::launch_gather_contract(p->prec, g, st); }), "gather");
       const double wm = m == 0 ? 1.0 : 2.0;
       MP3_HIP(mp3::launch_reduce_partials(partials, gwg, nb2, zeta, l, p->lmax, wm * kFourPi, p->batch, st), "reduce");
@@ -589,7 +595,7 @@ int zeta_gamma(mp3_plan_t p, const void* delta, double* zeta, void* ws, const La
       z.batch = p->batch;
       MP3_HIP(timed(p, MP3_PASS_Z_STORE, st, [&] { return mp3::launch_zpass_store(p->n, p->prec, z, Fi, st); }), "z pass (store)");
       MP3_HIP(timed(p, MP3_PASS_GAMMA, st, [&] {
-                return mp3::launch_gamma_contract(p->prec, Fi, delta, p->n, p->nbins, p->gm, p->gw, partials, (int)gwg,
+                return mp3::launch_gamma_contract(p->prec, p->split, Fi, delta, p->n, p->nbins, p->gm, p->gw, partials, (int)gwg,
                                                   p->batch, st);
               }),
               "grid-Gamma contraction");

@@ -43,7 +43,7 @@ def _desc(**kw):
 @pytest.mark.parametrize("kw,code", [
     (dict(n=48), -4), (dict(n=1024), -4), (dict(box=0.0), -1), (dict(box=float("nan")), -1),
     (dict(lmax=-1), -1), (dict(lmax=21), -1), (dict(nbins=0), -1), (dict(nbins=65), -1),
-    (dict(edges=[10.0, 5.0, 20.0]), -1), (dict(edges=[-1.0, 5.0]), -1), (dict(precision=2), -1),
+    (dict(edges=[10.0, 5.0, 20.0]), -1), (dict(edges=[-1.0, 5.0]), -1), (dict(precision=3), -1),
     (dict(summation=3), -4), (dict(batch=0), -1),
 ])
 def test_plan_create_rejects_bad_descriptions(kw, code):

@@ -130,7 +130,7 @@ def test_gamma_256(mp3):
     pos, w = workload_catalogue(wl)
     pt, wt = _dev(pos, torch.float32), _dev(w, torch.float32)
     out = {}
-    for prec in ("f32", "f64"):
+    for prec in ("f32", "f64", "bf16x3"):
         _say("gamma 256: GPU", prec)
         plan = mp3.Plan(wl.n, wl.box, wl.lmax, wl.edges, precision=prec, summation="gamma")
         out[prec] = plan.zeta(plan.deposit(pt, wt)).cpu().numpy()[0]
@@ -138,6 +138,8 @@ def test_gamma_256(mp3):
         torch.cuda.empty_cache()
     e = assert_zeta_close(out["f32"], out["f64"], 1e-4)
     _say("f32 vs f64 per l", np.array2string(e, precision=2))
+    e = assert_zeta_close(out["bf16x3"], out["f64"], 1e-4)
+    _say("bf16x3 vs f64 per l", np.array2string(e, precision=2))
     assert_zeta_close(_sub(out["f64"], ls, bins), g["zeta"], 1e-10)
     assert_zeta_close(_sub(out["f32"], ls, bins), g["zeta"], 1e-4)
 

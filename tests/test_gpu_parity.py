@@ -351,3 +351,40 @@ def test_backward_particle_batch_autograd(mp3):
         _, dwref = A.zeta_particle_grad(op, p_, w_, lam[j])
         got = dw[off[j]:off[j + 1]]
         assert np.linalg.norm(got - dwref) <= 1e-4 * np.linalg.norm(dwref), j
+
+
+# BF16-split contraction inputs: each product carries a relative error of about
+# 2^-16 instead of 2^-24, random over the summed products; the float32 bar
+# still holds (measured per-l errors 2e-7 .. 6e-6 on these cases)
+TOL_BF16X3 = 1e-4
+
+
+@pytest.mark.parametrize("summation,n,lmax,nb", [("nodal", 32, 4, 6), ("nodal", 32, 3, 20), ("gamma", 16, 2, 3),
+                                                  ("gamma", 32, 3, 20), ("particle", 32, 3, 5)])
+def test_zeta_bf16x3(mp3, summation, n, lmax, nb):
+    """float32 fields with BF16-split inputs to the matrix-core contraction, against the oracle."""
+    _say("bf16x3", summation, n, lmax, nb)
+    box = 8.0 * n
+    edges = np.linspace(0.06 * box, 0.35 * box, nb + 1)
+    op = E.Plan(n, box, lmax, edges)
+    out = {}
+    for prec in ("bf16x3", "f32"):
+        plan = mp3.Plan(n, box, lmax, edges, precision=prec, summation=summation)
+        if summation == "particle":
+            pos, w = lognormal_catalogue(n, box, 20000, 0.04 * box, 500 + n, 501 + n, 502 + n, (0.5, 1.5))
+            pt, wt = _dev(pos, torch.float32), _dev(w, torch.float32)
+            out[prec] = plan.zeta(plan.deposit(pt, wt), pt, wt).cpu().numpy()[0]
+        else:
+            delta = random_field(n, 510 + n + nb)
+            out[prec] = plan.zeta(_dev(delta[None], torch.float32)).cpu().numpy()[0]
+    if summation == "particle":
+        ref = E.zeta_particle(op, pos, w)
+    elif summation == "gamma":
+        ref = E.zeta_gamma(op, delta)
+    else:
+        ref = E.zeta_nodal(op, delta)
+    e16 = assert_zeta_close(out["bf16x3"], ref, TOL_BF16X3)
+    e32 = assert_zeta_close(out["f32"], ref, 1e-4)
+    print("per-l errors bf16x3", e16, "f32", e32)
+    z = out["bf16x3"]
+    assert np.abs(z - z.transpose(0, 2, 1)).max() <= 1e-12 * np.abs(z).max()
