@@ -188,6 +188,54 @@ def stats_summarize(root, top=20):
               f"| {float(r['MinNs']) / 1e6:.4f} | {float(r['MaxNs']) / 1e6:.4f} | {float(r['Percentage']):.2f} |")
 
 
+# secondary measurements: (workload, summation, precision, with adjoint)
+FORMS = {
+    "gamma_256_f32": ("box2000_n256_l10", "gamma", "f32", False),
+    "gamma_256_bf16x3": ("box2000_n256_l10", "gamma", "bf16x3", False),
+    "particle_512_f32": ("box3000_n512_l10", "particle", "f32", True),
+}
+
+
+def measure_form(name, steps=1, warmup=1):
+    """Throughput of one form on its workload: deposit + zeta (+ zeta_backward with dJ/dw)."""
+    import torch
+    import paper_2507_15209_amd as mp3
+    from mockgen import WORKLOADS, workload_catalogue
+    wname, summation, precision, backward = FORMS[name]
+    wl = WORKLOADS[wname]
+    dev = torch.device("cuda", 0)
+    t0 = time.perf_counter()
+    pos, w = workload_catalogue(wl)
+    log(f"{name}: mock drawn in {time.perf_counter() - t0:.1f} s")
+    pt, wt = torch.as_tensor(pos, device=dev), torch.as_tensor(w, device=dev)
+    del pos, w
+    lam = torch.as_tensor(np.random.default_rng(12).standard_normal((1, wl.lmax + 1, wl.nbins, wl.nbins)), device=dev)
+    plan = mp3.Plan(wl.n, wl.box, wl.lmax, wl.edges, precision=precision, device=dev, summation=summation)
+    cat = (pt, wt) if summation == "particle" else ()
+
+    def step():
+        delta = plan.deposit(pt, wt)
+        plan.zeta(delta, *cat)
+        if backward:
+            plan.zeta_backward(delta, lam, pt, wt)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t1) / steps
+    log(f"{name}: {dt * 1e3:.1f} ms per step")
+    del plan, pt, wt
+    torch.cuda.empty_cache()
+    units = float(wl.n) ** 3 * (wl.lmax + 1) ** 2 * wl.nbins
+    return {"workload": wl.name, "summation": summation, "precision": precision,
+            "pass": "deposit + forward" + (" + adjoint with dJ/dw" if backward else ""),
+            "value": units / dt, "unit": "zeta_l evals/s", "ms_per_step": dt * 1e3, "steps": steps}
+
+
 def cpu_baseline(wl, pos, w, nbins_sample=4, l_sample=0):
     """The float64 oracle on a bounded sample of the same workload: the l = 0 multipole, first bins."""
     from oracle import basis
@@ -217,6 +265,8 @@ def main():
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default=",".join(FORMS),
+                    help="secondary measurements after the headline (comma list of %s, or none)" % ", ".join(FORMS))
     ap.add_argument("--pmc-probe", action="store_true", help="one step plus a 1 GiB copy, for counter runs")
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print the per-launch traffic summary of two rocprofv3 --pmc runs of --pmc-probe")
@@ -307,6 +357,10 @@ def main():
         t64, _ = run("f64", args.fp64_steps, 1, False)
         fp64 = {"value": units / t64, "ms_per_step": t64 * 1e3, "ratio_f32_over_f64": t64 / t_step}
 
+    forms = {}
+    for name in [f for f in args.forms.split(",") if f and f != "none"]:
+        forms[name] = measure_form(name)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
@@ -333,6 +387,7 @@ def main():
                      "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": abytes},
         "passes_ms": {k: {"total_ms": v[0] / args.steps, "launches": v[1] // args.steps} for k, v in passes.items()},
         "fp64_form": fp64,
+        "forms": forms,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -198,8 +198,19 @@ __device__ __forceinline__ int find_mock(const long long* off, int batch, long l
 struct Taps {
   int base[3];
   double wt[3][4];
+  double f[3];     // fractional position in the cell
   bool ok;
 };
+
+// weight of tap a (0..3) at fractional position f: the same expressions as make_taps
+__device__ __forceinline__ double b3_tap(double f, int a) {
+  const double g = 1.0 - f;
+  const double w0 = g * g * g / 6.0;
+  const double w1 = (4.0 - 6.0 * f * f + 3.0 * f * f * f) / 6.0;
+  const double w2 = (4.0 - 6.0 * g * g + 3.0 * g * g * g) / 6.0;
+  const double w3 = f * f * f / 6.0;
+  return a == 0 ? w0 : (a == 1 ? w1 : (a == 2 ? w2 : w3));
+}
 
 __device__ __forceinline__ Taps make_taps(const float* p, int n, double sc) {
   Taps t;
@@ -214,6 +225,7 @@ __device__ __forceinline__ Taps make_taps(const float* p, int n, double sc) {
     int ib = (int)fl;
     if (ib >= n) { ib -= n; }
     t.base[d] = ib - 1;
+    t.f[d] = f;
     const double g = 1.0 - f;
     t.wt[d][0] = g * g * g / 6.0;
     t.wt[d][1] = (4.0 - 6.0 * f * f + 3.0 * f * f * f) / 6.0;
@@ -1448,82 +1460,209 @@ __global__ void __launch_bounds__(256) k_gather_source(const c2<T>* fields, cons
   }
 }
 
-// Adjoint source on the grid, c_b(x) = sum_i B3(u_i - x) s_b(i).  A workgroup
-// owns an 8^3-node tile and BC bins; it visits the particles of the 4^3-cell
-// sort tiles whose stencils can reach the tile (cells x0 - 4 .. x0 + 11 per
-// axis), accumulates the taps that land inside in LDS and writes the tile
-// once: every node has exactly one owner, so there are no global atomics and
-// empty tiles are written as zeros.
-template <typename T, int BC>
+// Adjoint source on the grid, c_b(x) = sum_i B3(u_i - x) s_b(i), by pulling:
+// a workgroup owns an 8^3-node tile and BC bins, and every thread owns two of
+// its nodes with BC complex accumulators in registers (no atomics on values).
+// Candidates are the particles of the 4^3-cell sort tiles covering cells
+// x0 - 4 .. x0 + 11 per axis, taken 256 at a time through a prefix sum over
+// the 64 tiles' counts.  The ones whose stencil reaches the tile (first tap
+// at local offset -3 .. 7 per axis) are staged in LDS with their tap weights
+// and sources, bucketed by first-tap cell (11^3 buckets, counting sort), and
+// each node then visits the 4^3 buckets that can reach it.  Batches of up to
+// SCQ particles keep the LDS bounded in dense regions.  Every node has one
+// owner: the tile is written once, empty tiles as zeros.
+__device__ __forceinline__ int tap_offset(int base, int o, int n) {
+  int r = (base - o) % n;
+  return r < 0 ? r + n : r;
+}
+
+constexpr int SCT = 8;                    // owner tile side (nodes)
+constexpr int SCB = (SCT + 3) * (SCT + 3) * (SCT + 3);   // first-tap buckets
+template <typename T> constexpr int scatter_bc() { return sizeof(T) == 4 ? 8 : 4; }
+template <typename T> constexpr int scatter_q() { return sizeof(T) == 4 ? 256 : 256; }
+
+template <typename T>
+struct ScatterLds {
+  size_t key, wt, sv, cnt, ord, total;
+  __host__ __device__ ScatterLds() {
+    constexpr int Q = scatter_q<T>(), BC = scatter_bc<T>();
+    size_t o = 0;
+    auto take = [&](size_t b) { size_t r = o; o = (o + b + 15) & ~(size_t)15; return r; };
+    key = take((size_t)Q * sizeof(int));
+    wt = take((size_t)Q * 12 * sizeof(T));
+    sv = take((size_t)Q * BC * sizeof(c2<T>));
+    cnt = take((size_t)(SCB + 1) * sizeof(int));
+    ord = take((size_t)Q * sizeof(int));
+    total = o;
+  }
+};
+
+template <typename T>
 __global__ void __launch_bounds__(256) k_scatter_source(const float* pos, const int* perm, const int* toff,
                                                          const c2<T>* src, int n, double sc, int nbins, int nchunk,
                                                          c2<T>* out) {
-  constexpr int TO = 8;
+  constexpr int TO = SCT, TB = SCT + 3;
   constexpr int NODES = TO * TO * TO;
-  __shared__ T acc[NODES * BC * 2];
+  constexpr int BC = scatter_bc<T>(), Q = scatter_q<T>();
+  extern __shared__ __align__(16) char smem[];
+  const ScatterLds<T> L;
+  int* qkey = reinterpret_cast<int*>(smem + L.key);          // bucket of each staged particle
+  T* qwt = reinterpret_cast<T*>(smem + L.wt);                // [q][3][4] tap weights
+  c2<T>* qsv = reinterpret_cast<c2<T>*>(smem + L.sv);        // [q][BC] sources
+  int* cnt = reinterpret_cast<int*>(smem + L.cnt);           // bucket counts, then starts
+  int* ord = reinterpret_cast<int*>(smem + L.ord);           // staged particles in bucket order
+  __shared__ int pre[65];
+  __shared__ int cbase[64];
+  __shared__ int qn;
+  __shared__ int wsum[4];
+  const int tid = threadIdx.x;
   const int no = n / TO;
   const int ot = blockIdx.x;
   const int oxi = ot / (no * no), oyi = (ot / no) % no, ozi = ot % no;
   const int o0[3] = {oxi * TO, oyi * TO, ozi * TO};
   const int mock = blockIdx.y / nchunk, b0 = (blockIdx.y % nchunk) * BC;
   const int nbc = min(BC, nbins - b0);
-  for (int t = threadIdx.x; t < NODES * BC * 2; t += blockDim.x) acc[t] = (T)0;
-  __syncthreads();
   const int ntd = n / 4;
   const long long ns = (long long)ntd * ntd * ntd;
-  const int ppp = blockDim.x / BC;
-  const int g = threadIdx.x / BC, bb = threadIdx.x % BC;
-  for (int c = 0; c < 64; ++c) {
-    const int sx = wrapi(2 * oxi - 1 + c / 16, ntd), sy = wrapi(2 * oyi - 1 + (c / 4) % 4, ntd);
-    const int sz = wrapi(2 * ozi - 1 + c % 4, ntd);
+  if (tid < 64) {
+    const int sx = wrapi(2 * oxi - 1 + tid / 16, ntd), sy = wrapi(2 * oyi - 1 + (tid / 4) % 4, ntd);
+    const int sz = wrapi(2 * ozi - 1 + tid % 4, ntd);
     const long long tile = mock * ns + ((long long)sx * ntd + sy) * ntd + sz;
-    const int a = toff[tile], e = toff[tile + 1];
-    for (int k = a + g; k < e; k += ppp) {
-      const int i = perm[k];
-      Taps t = make_taps(pos + 3 * (long long)i, n, sc);
-      if (!t.ok || bb >= nbc) continue;
-      int loc[3][4];
-      int hit = 1;
+    const int a = toff[tile];
+    cbase[tid] = a;
+    pre[tid + 1] = toff[tile + 1] - a;
+  }
+  if (tid == 0) qn = 0;
+  __syncthreads();
+  if (tid == 0) {
+    pre[0] = 0;
+    for (int c = 1; c <= 64; ++c) pre[c] += pre[c - 1];
+  }
+  __syncthreads();
+  const int total = pre[64];
+  // owned nodes: tid and tid + 256
+  c2<T> acc[2][BC];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int bb = 0; bb < BC; ++bb) acc[h][bb] = mk<T>(0, 0);
+  for (int t0 = 0; t0 <= total; t0 += blockDim.x) {
+    // stage this pass's candidates that reach the tile
+    const int t = t0 + tid;
+    if (t < total) {
+      int lo = 0, hi = 64;                      // pre[lo] <= t < pre[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= t) lo = mid; else hi = mid;
+      }
+      const int k = cbase[lo] + (t - pre[lo]);
+      Taps tp = make_taps(pos + 3 * (long long)perm[k], n, sc);
+      int rl[3];
+      bool reach = tp.ok;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        int any = 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          int r = (t.base[d] + q - o0[d]) % n;
-          if (r < 0) r += n;
-          loc[d][q] = r < TO ? r : -1;
-          any |= r < TO;
-        }
-        hit &= any;
+        const int r = tap_offset(tp.base[d], o0[d], n);
+        rl[d] = r < TO ? r : r - n;             // -3 .. 7 when the stencil reaches the tile
+        reach = reach && (r < TO || r >= n - 3);
       }
-      if (!hit) continue;
-      const c2<T> sv = src[(long long)k * nbins + b0 + bb];
+      if (reach) {
+        const int q = atomicAdd(&qn, 1);
+        qkey[q] = ((rl[0] + 3) * TB + (rl[1] + 3)) * TB + (rl[2] + 3);
 #pragma unroll
-      for (int ax = 0; ax < 4; ++ax) {
-        if (loc[0][ax] < 0) continue;
+        for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int ay = 0; ay < 4; ++ay) {
-          if (loc[1][ay] < 0) continue;
-          const double wxy = t.wt[0][ax] * t.wt[1][ay];
+          for (int a = 0; a < 4; ++a) qwt[(q * 3 + d) * 4 + a] = (T)tp.wt[d][a];
+        const c2<T>* sp = src + (long long)k * nbins + b0;
 #pragma unroll
-          for (int az = 0; az < 4; ++az) {
-            if (loc[2][az] < 0) continue;
-            const T wt = (T)(wxy * t.wt[2][az]);
-            const int node = (loc[0][ax] * TO + loc[1][ay]) * TO + loc[2][az];
-            atomicAdd(&acc[(node * BC + bb) * 2], wt * sv.x);
-            atomicAdd(&acc[(node * BC + bb) * 2 + 1], wt * sv.y);
+        for (int bb = 0; bb < BC; ++bb) qsv[q * BC + bb] = bb < nbc ? sp[bb] : mk<T>(0, 0);
+      }
+    }
+    __syncthreads();
+    const int nq = qn;
+    __syncthreads();                              // every thread has read qn before it changes
+    // pull when the next pass might overflow the stage, and at the end
+    if (nq > Q - (int)blockDim.x || t0 + (int)blockDim.x > total) {
+      for (int c = tid; c <= SCB; c += blockDim.x) cnt[c] = 0;
+      __syncthreads();
+      for (int q = tid; q < nq; q += blockDim.x) atomicAdd(&cnt[qkey[q] + 1], 1);
+      __syncthreads();
+      // exclusive starts: cnt[c] = first slot of bucket c (c = 0 .. SCB)
+      {
+        constexpr int PER = (SCB + 1 + 255) / 256;
+        int loc[PER];
+        int run = 0;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+          const int c = tid * PER + e;
+          loc[e] = c <= SCB ? cnt[c] : 0;
+          run += loc[e];
+        }
+        // block-wide exclusive scan of the per-thread sums
+        int incl = run;
+        for (int o = 1; o < 64; o <<= 1) {
+          const int v = __shfl_up(incl, o, 64);
+          if ((tid & 63) >= o) incl += v;
+        }
+        if ((tid & 63) == 63) wsum[tid >> 6] = incl;
+        __syncthreads();
+        int woff = 0;
+        for (int w = 0; w < (tid >> 6); ++w) woff += wsum[w];
+        int ex = woff + incl - run;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+          const int c = tid * PER + e;
+          ex += loc[e];
+          if (c <= SCB) cnt[c] = ex;              // sum of the counts of buckets 0 .. c - 1
+        }
+      }
+      __syncthreads();
+      // cnt[c] is now the start of bucket c (counts were stored at c + 1)
+      for (int q = tid; q < nq; q += blockDim.x) {
+        const int slot = atomicAdd(&cnt[qkey[q]], 1);
+        ord[slot] = q;
+      }
+      __syncthreads();
+      // after the fill cnt[c] is the end of bucket c = start of bucket c + 1;
+      // bucket c spans [c == 0 ? 0 : cnt[c - 1], cnt[c])
+      // the 4 buckets (z taps c = 0..3) of one (a, b) row are consecutive keys,
+      // so their particles form one contiguous range of ord
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int node = tid + h * 256;
+        const int i = node / (TO * TO), j = (node / TO) % TO, kz = node % TO;
+        for (int a = 0; a < 4; ++a) {
+          for (int b = 0; b < 4; ++b) {
+            const int rowc = ((i - a + 3) * TB + (j - b + 3)) * TB + 3 + kz;   // key of tap c = 0
+            const int k0 = rowc - 3;
+            const int e0 = k0 == 0 ? 0 : cnt[k0 - 1], e1 = cnt[rowc];
+            for (int e = e0; e < e1; ++e) {
+              const int q = ord[e];
+              const int c = rowc - qkey[q];
+              const T w = qwt[(q * 3 + 0) * 4 + a] * qwt[(q * 3 + 1) * 4 + b] * qwt[(q * 3 + 2) * 4 + c];
+#pragma unroll
+              for (int bb = 0; bb < BC; ++bb) {
+                const c2<T> v = qsv[q * BC + bb];
+                acc[h][bb].x += w * v.x;
+                acc[h][bb].y += w * v.y;
+              }
+            }
           }
         }
       }
+      __syncthreads();
+      if (tid == 0) qn = 0;
+      __syncthreads();
     }
   }
-  __syncthreads();
   const long long n3 = (long long)n * n * n;
-  for (int t = threadIdx.x; t < nbc * NODES; t += blockDim.x) {
-    const int bq = t / NODES, node = t % NODES;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int node = tid + h * 256;
     const int i = node / (TO * TO), j = (node / TO) % TO, k = node % TO;
-    out[((long long)mock * nbins + b0 + bq) * n3 + ((long long)(o0[0] + i) * n + o0[1] + j) * n + o0[2] + k] =
-        mk<T>(acc[(node * BC + bq) * 2], acc[(node * BC + bq) * 2 + 1]);
+    const long long cell = ((long long)(o0[0] + i) * n + o0[1] + j) * n + o0[2] + k;
+#pragma unroll
+    for (int bb = 0; bb < BC; ++bb)
+      if (bb < nbc) out[((long long)mock * nbins + b0 + bb) * n3 + cell] = acc[h][bb];
   }
 }
 
@@ -2147,19 +2286,23 @@ hipError_t launch_gather_source(int prec, const void* fields, const float* pos, 
 
 hipError_t launch_scatter_source(int prec, const float* pos, const int* perm, const int* toff, const void* src, int n,
                                  double sc, int nbins, int batch, void* out, hipStream_t st) {
-  const int no = n / 8;
+  const int no = n / SCT;
   if (prec) {
-    constexpr int BC = 4;
-    const int nchunk = (nbins + BC - 1) / BC;
+    const int nchunk = (nbins + scatter_bc<double>() - 1) / scatter_bc<double>();
+    const size_t lds = ScatterLds<double>().total;
+    hipError_t e = allow_lds(k_scatter_source<double>, lds);
+    if (e != hipSuccess) return e;
     const dim3 gs(no * no * no, batch * nchunk);
-    k_scatter_source<double, BC><<<gs, 256, 0, st>>>(pos, perm, toff, static_cast<const double2*>(src), n, sc, nbins,
-                                                     nchunk, static_cast<double2*>(out));
+    k_scatter_source<double><<<gs, 256, lds, st>>>(pos, perm, toff, static_cast<const double2*>(src), n, sc, nbins,
+                                                   nchunk, static_cast<double2*>(out));
   } else {
-    constexpr int BC = 8;
-    const int nchunk = (nbins + BC - 1) / BC;
+    const int nchunk = (nbins + scatter_bc<float>() - 1) / scatter_bc<float>();
+    const size_t lds = ScatterLds<float>().total;
+    hipError_t e = allow_lds(k_scatter_source<float>, lds);
+    if (e != hipSuccess) return e;
     const dim3 gs(no * no * no, batch * nchunk);
-    k_scatter_source<float, BC><<<gs, 256, 0, st>>>(pos, perm, toff, static_cast<const float2*>(src), n, sc, nbins,
-                                                    nchunk, static_cast<float2*>(out));
+    k_scatter_source<float><<<gs, 256, lds, st>>>(pos, perm, toff, static_cast<const float2*>(src), n, sc, nbins,
+                                                  nchunk, static_cast<float2*>(out));
   }
   return hipGetLastError();
 }
