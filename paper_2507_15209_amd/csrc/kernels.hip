@@ -552,6 +552,47 @@ __device__ __forceinline__ void mfma_contract_pencil(const float2* A, const floa
   }
 }
 
+// 17..20 bins: the 15 upper-triangle 4x4 blocks (g1 <= g2 of 5 bin groups)
+// of P on v_mfma_f32_4x4x1f32, 16 independent 4x4 outer products per
+// instruction, one instruction per k = (z, re/im): a third of the matrix-core
+// cycles of three 16x16 blocks.  K must be even.  Lane l supplies A[4 g1 + l%4][k] of block
+// beta = l/4 and B[k][4 g2 + l%4]; D register i of lane l is block l/4, row i,
+// column l%4.  Block 15 is idle.
+__device__ __forceinline__ void pair_group(int beta, int& g1, int& g2) {
+  // beta = 0..14 over (g1, g2), 0 <= g1 <= g2 < 5, row-major
+  int r = 0, rem = beta;
+  while (rem >= 5 - r) { rem -= 5 - r; ++r; }
+  g1 = r;
+  g2 = r + rem;
+}
+
+__device__ __forceinline__ void mfma_contract_4x4(const float2* A, const float* dl, int nbins, int RS, int K,
+                                                  MfmaAcc& acc) {
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int beta = lane >> 2, i = lane & 3;
+  int g1 = 0, g2 = 0;
+  if (beta < 15) pair_group(beta, g1, g2);
+  const int ba = 4 * g1 + i, bb = 4 * g2 + i;
+  const bool oka = beta < 15 && ba < nbins, okb = beta < 15 && bb < nbins;
+  const float2* ra = A + (oka ? ba : 0) * RS;
+  const float2* rb = A + (okb ? bb : 0) * RS;
+  // three accumulators in rotation keep dependent matrix-core issues apart
+  for (int z = 2 * w; z < K; z += 2 * nw) {
+    const int zp0 = lds_pos<true>(z), zp1 = lds_pos<true>(z + 1);
+    const float d0 = dl[z], d1 = dl[z + 1];
+    const float2 u0 = oka ? ra[zp0] : make_float2(0.f, 0.f);
+    const float2 v0 = okb ? rb[zp0] : make_float2(0.f, 0.f);
+    const float2 u1 = oka ? ra[zp1] : make_float2(0.f, 0.f);
+    const float2 v1 = okb ? rb[zp1] : make_float2(0.f, 0.f);
+    acc.c00 = __builtin_amdgcn_mfma_f32_4x4x1f32(d0 * u0.x, v0.x, acc.c00, 0, 0, 0);
+    acc.c01 = __builtin_amdgcn_mfma_f32_4x4x1f32(d0 * u0.y, v0.y, acc.c01, 0, 0, 0);
+    acc.c11 = __builtin_amdgcn_mfma_f32_4x4x1f32(d1 * u1.x, v1.x, acc.c11, 0, 0, 0);
+    acc.c00 = __builtin_amdgcn_mfma_f32_4x4x1f32(d1 * u1.y, v1.y, acc.c00, 0, 0, 0);
+  }
+}
+
 // BF16-split variant: every float operand x is carried as hi = bf16(x) and
 // lo = bf16(x - hi) and each product as hi*hi + hi*lo + lo*hi on the bf16
 // matrix cores (v_mfma_f32_16x16x16bf16_1k, k = 8 z values x (re, im) per
@@ -624,8 +665,10 @@ __device__ __forceinline__ void mfma_contract_bf16x3(const float2* A, const floa
 // over LDS rows A[b * RS + lds_pos(k)], either on the matrix cores (MF) or in
 // 4x4 register blocks on the vector ALUs.  Partial sums stay in the working
 // precision over the workgroup's slices and are written as float64.
-template <typename T, bool MF, bool SPLIT = false>
+// QUAD: 4x4 blocks on the matrix cores (float32 inputs, 17..20 bins)
+template <typename T, bool MF, bool SPLIT = false, bool QUAD = false>
 struct Contractor {
+  static __host__ __device__ bool quad(int) { return QUAD; }
   PairBlocks pb;
   int bb1 = 0, bb2 = 0, zc = 0;
   bool has_item = false;
@@ -650,6 +693,8 @@ struct Contractor {
   __device__ void add(const c2<T>* A, const T* w, int nbins, int RS, int K) {
     if constexpr (MF && SPLIT) {
       mfma_contract_bf16x3(reinterpret_cast<const float2*>(A), reinterpret_cast<const float*>(w), nbins, RS, K, macc);
+    } else if constexpr (MF && QUAD) {
+      mfma_contract_4x4(reinterpret_cast<const float2*>(A), reinterpret_cast<const float*>(w), nbins, RS, K, macc);
     } else if constexpr (MF) {
       mfma_contract_pencil(reinterpret_cast<const float2*>(A), reinterpret_cast<const float*>(w), nbins, RS, K, macc);
     } else if (has_item) {
@@ -680,7 +725,28 @@ struct Contractor {
   // workgroup reduction through LDS scratch red, symmetric partial to out[nbins^2]
   __device__ void finish(double* red, double* out, int nbins) {
     const int tid = threadIdx.x;
-    if constexpr (MF) {
+    if constexpr (MF && QUAD) {
+      // red[w][beta][row][col] for the 15 (g1, g2) 4x4 blocks
+      const int lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        red[(w * 16 + (lane >> 2)) * 16 + i * 4 + (lane & 3)] =
+            (double)macc.c00[i] + (double)macc.c01[i] + (double)macc.c11[i];
+      __syncthreads();
+      for (int t = tid; t < 15 * 16; t += blockDim.x) {
+        const int beta = t / 16, row = (t / 4) % 4, col = t % 4;
+        double sacc = 0.0;
+        for (int ww = 0; ww < nw; ++ww) sacc += red[(ww * 16 + beta) * 16 + row * 4 + col];
+        int g1, g2;
+        pair_group(beta, g1, g2);
+        const int b1 = 4 * g1 + row, b2 = 4 * g2 + col;
+        // diagonal blocks hold both orders of a pair: keep b1 <= b2 and mirror
+        if (b1 < nbins && b2 < nbins && b1 <= b2) {
+          out[b1 * nbins + b2] = sacc;
+          out[b2 * nbins + b1] = sacc;
+        }
+      }
+    } else if constexpr (MF) {
       // red[w][blk][row][col], blk 0 = (0,0), 1 = (0,1), 2 = (1,1)
       const int lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
 #pragma unroll
@@ -725,7 +791,7 @@ struct Contractor {
   }
 };
 
-template <int N, typename T, bool MF, bool SPLIT = false>
+template <int N, typename T, bool MF, bool SPLIT = false, bool QUAD = false>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MF ? 4 : 1))) k_zpass_nodal(
     const c2<T>* fields, const T* delta, double* partials, int nbins, int ppw, const c2<T>* tw) {
   using F = Fft<N, VZN>;
@@ -738,7 +804,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MF ? 4
   const int tid = threadIdx.x;
   const long long mock = blockIdx.y;
   stage_twiddles<N, T>(tw, tws);
-  Contractor<T, MF, SPLIT> ctr;
+  Contractor<T, MF, SPLIT, QUAD> ctr;
   ctr.init(nbins);
   const int p0 = blockIdx.x * ppw;
   const int p1 = min(p0 + ppw, N * N);
@@ -884,7 +950,7 @@ __global__ void k_tile_scatter(const float* pos, const long long* off, int batch
 // Gather the B-spline interpolants of the (bin-interleaved) fields at the
 // particles, one lane per (particle, bin), into LDS rows, then contract with
 // the weights w_i / W.  Particles are visited in tile order (perm).
-template <typename T, bool MF, bool SPLIT = false>
+template <typename T, bool MF, bool SPLIT = false, bool QUAD = false>
 __global__ void __launch_bounds__(256) k_gather_contract(const c2<T>* fields, const float* pos, const float* w,
                                                           const int* perm, const long long* off, const double* W,
                                                           int n, double sc, int nbins, double* partials) {
@@ -903,7 +969,7 @@ __global__ void __launch_bounds__(256) k_gather_contract(const c2<T>* fields, co
   const int ppp = blockDim.x / lpp;                     // particles per pass
   const int b = threadIdx.x % lpp;
   const c2<T>* fm = fields + mock * n3 * nbins;
-  Contractor<T, MF, SPLIT> ctr;
+  Contractor<T, MF, SPLIT, QUAD> ctr;
   ctr.init(nbins);
   for (long long c0 = s0; c0 < s1; c0 += K) {
     for (int k0 = 0; k0 < K; k0 += ppp) {
@@ -996,7 +1062,7 @@ struct GammaLds {
   }
 };
 
-template <typename T, bool MF, bool SPLIT = false>
+template <typename T, bool MF, bool SPLIT = false, bool QUAD = false>
 __global__ void __launch_bounds__(512) k_gamma_contract(const c2<T>* fields, const T* delta, int n, int nbins,
                                                          GammaQuad gq, double* partials) {
   extern __shared__ __align__(16) char smem[];
@@ -1016,7 +1082,7 @@ __global__ void __launch_bounds__(512) k_gamma_contract(const c2<T>* fields, con
   const T* dm = delta + mock * n3;
   const int td = n / GT;
   const long long ntiles = (long long)td * td * td;
-  Contractor<T, MF, SPLIT> ctr;
+  Contractor<T, MF, SPLIT, QUAD> ctr;
   ctr.init(nbins);
   for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int tx = (int)(tile / ((long long)td * td)), ty = (int)((tile / td) % td), tz = (int)(tile % td);
@@ -1884,18 +1950,18 @@ template <typename K> hipError_t allow_lds(K kernel, size_t bytes) {
   return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int N, typename T, bool MF, bool SPLIT = false>
+template <int N, typename T, bool MF, bool SPLIT = false, bool QUAD = false>
 hipError_t zpass_nodal_mf(const ZpassArgs& a, hipStream_t st) {
   const int threads = zpass_threads<N, VZN>(a.nbins);
   size_t lds = zpass_nodal_lds<N, T>(a.nbins, threads);
-  const size_t red = Contractor<T, MF, SPLIT>::scratch_bytes(threads);
+  const size_t red = Contractor<T, MF, SPLIT, QUAD>::scratch_bytes(threads);
   if (lds < red) lds = red;
-  hipError_t e = allow_lds(k_zpass_nodal<N, T, MF, SPLIT>, lds);
+  hipError_t e = allow_lds(k_zpass_nodal<N, T, MF, SPLIT, QUAD>, lds);
   if (e != hipSuccess) return e;
   const dim3 gs(a.nwg, a.batch);
-  k_zpass_nodal<N, T, MF, SPLIT><<<gs, threads, lds, st>>>(static_cast<const CT<T>*>(a.fields),
-                                                          static_cast<const T*>(a.delta), a.partials, a.nbins, a.ppw,
-                                                          static_cast<const CT<T>*>(a.tw));
+  k_zpass_nodal<N, T, MF, SPLIT, QUAD><<<gs, threads, lds, st>>>(static_cast<const CT<T>*>(a.fields),
+                                                                static_cast<const T*>(a.delta), a.partials, a.nbins,
+                                                                a.ppw, static_cast<const CT<T>*>(a.tw));
   return hipGetLastError();
 }
 
@@ -1916,8 +1982,11 @@ hipError_t zpass_store_t(const ZpassArgs& a, void* out, hipStream_t st) {
 template <int N, typename T>
 hipError_t zpass_nodal_t(const ZpassArgs& a, hipStream_t st) {
   if constexpr (std::is_same<T, float>::value) {
-    if (a.nbins <= 32 && zpass_threads<N, VZN>(a.nbins) % 64 == 0)
-      return a.split ? zpass_nodal_mf<N, T, true, true>(a, st) : zpass_nodal_mf<N, T, true>(a, st);
+    if (a.nbins <= 32 && zpass_threads<N, VZN>(a.nbins) % 64 == 0) {
+      if (a.split) return zpass_nodal_mf<N, T, true, true>(a, st);
+      if (a.nbins > 16 && a.nbins <= 20) return zpass_nodal_mf<N, T, true, false, true>(a, st);
+      return zpass_nodal_mf<N, T, true>(a, st);
+    }
   }
   return zpass_nodal_mf<N, T, false>(a, st);
 }
@@ -2182,24 +2251,28 @@ hipError_t launch_deposit_tiled(int prec, int tside, const float* pos, const flo
   return deposit_tiled_t<float>(tside, pos, w, perm, toff, ntiles_total, g, counter, n, sc, static_cast<float*>(eps), st);
 }
 
-template <typename T, bool MF, bool SPLIT = false>
+template <typename T, bool MF, bool SPLIT = false, bool QUAD = false>
 hipError_t gather_contract_t(const GatherArgs& a, hipStream_t st) {
   constexpr int K = 256;
   const size_t rs = K + K / 16 + 1;
   size_t lds = (size_t)a.nbins * rs * sizeof(CT<T>) + K * sizeof(T);
-  const size_t red = Contractor<T, MF, SPLIT>::scratch_bytes(256);
+  const size_t red = Contractor<T, MF, SPLIT, QUAD>::scratch_bytes(256);
   if (lds < red) lds = red;
-  hipError_t e = allow_lds(k_gather_contract<T, MF, SPLIT>, lds);
+  hipError_t e = allow_lds(k_gather_contract<T, MF, SPLIT, QUAD>, lds);
   if (e != hipSuccess) return e;
   const dim3 gs(a.nwg, a.batch);
-  k_gather_contract<T, MF, SPLIT><<<gs, 256, lds, st>>>(static_cast<const CT<T>*>(a.fields), a.pos, a.w, a.perm, a.off,
-                                                       a.W, a.n, a.sc, a.nbins, a.partials);
+  k_gather_contract<T, MF, SPLIT, QUAD><<<gs, 256, lds, st>>>(static_cast<const CT<T>*>(a.fields), a.pos, a.w, a.perm,
+                                                             a.off, a.W, a.n, a.sc, a.nbins, a.partials);
   return hipGetLastError();
 }
 
 hipError_t launch_gather_contract(int prec, const GatherArgs& a, hipStream_t st) {
   if (prec) return gather_contract_t<double, false>(a, st);
-  if (a.nbins <= 32) return a.split ? gather_contract_t<float, true, true>(a, st) : gather_contract_t<float, true>(a, st);
+  if (a.nbins <= 32) {
+    if (a.split) return gather_contract_t<float, true, true>(a, st);
+    if (a.nbins > 16 && a.nbins <= 20) return gather_contract_t<float, true, false, true>(a, st);
+    return gather_contract_t<float, true>(a, st);
+  }
   return gather_contract_t<float, false>(a, st);
 }
 
@@ -2221,18 +2294,18 @@ hipError_t launch_fbar_subtract(int prec, const double* P, const void* jtab, int
   return hipGetLastError();
 }
 
-template <typename T, bool MF, bool SPLIT = false>
+template <typename T, bool MF, bool SPLIT = false, bool QUAD = false>
 hipError_t gamma_contract_t(const void* fields, const void* delta, int n, int nbins, const GammaQuad& gq,
                             double* partials, int nwg, int batch, hipStream_t st) {
   const int threads = 512;
   size_t lds = GammaLds<T>(nbins).total;
-  const size_t red = Contractor<T, MF, SPLIT>::scratch_bytes(threads);
+  const size_t red = Contractor<T, MF, SPLIT, QUAD>::scratch_bytes(threads);
   if (lds < red) lds = red;
-  hipError_t e = allow_lds(k_gamma_contract<T, MF, SPLIT>, lds);
+  hipError_t e = allow_lds(k_gamma_contract<T, MF, SPLIT, QUAD>, lds);
   if (e != hipSuccess) return e;
   const dim3 gs(nwg, batch);
-  k_gamma_contract<T, MF, SPLIT><<<gs, threads, lds, st>>>(static_cast<const CT<T>*>(fields),
-                                                          static_cast<const T*>(delta), n, nbins, gq, partials);
+  k_gamma_contract<T, MF, SPLIT, QUAD><<<gs, threads, lds, st>>>(static_cast<const CT<T>*>(fields),
+                                                                static_cast<const T*>(delta), n, nbins, gq, partials);
   return hipGetLastError();
 }
 
@@ -2251,6 +2324,8 @@ hipError_t launch_gamma_contract(int prec, bool split, const void* fields, const
   if (prec) return gamma_contract_t<double, false>(fields, delta, n, nbins, gq, partials, nwg, batch, st);
   if (nbins <= 32) {
     if (split) return gamma_contract_t<float, true, true>(fields, delta, n, nbins, gq, partials, nwg, batch, st);
+    if (nbins > 16 && nbins <= 20)
+      return gamma_contract_t<float, true, false, true>(fields, delta, n, nbins, gq, partials, nwg, batch, st);
     return gamma_contract_t<float, true>(fields, delta, n, nbins, gq, partials, nwg, batch, st);
   }
   return gamma_contract_t<float, false>(fields, delta, n, nbins, gq, partials, nwg, batch, st);

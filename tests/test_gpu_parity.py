@@ -388,3 +388,25 @@ def test_zeta_bf16x3(mp3, summation, n, lmax, nb):
     print("per-l errors bf16x3", e16, "f32", e32)
     z = out["bf16x3"]
     assert np.abs(z - z.transpose(0, 2, 1)).max() <= 1e-12 * np.abs(z).max()
+
+
+@pytest.mark.parametrize("summation", ["nodal", "particle", "gamma"])
+def test_zeta_20_bins_matrix_cores(mp3, summation):
+    """17..20 bins take the 4x4-block matrix-core contraction (nodal z pass, gather and grid-Gamma)."""
+    _say("20 bins", summation)
+    n, box, lmax, nb = (128, 1024.0, 2, 20) if summation != "gamma" else (32, 256.0, 2, 18)
+    edges = np.linspace(0.05 * box, 0.3 * box, nb + 1)
+    op = E.Plan(n, box, lmax, edges)
+    plan = mp3.Plan(n, box, lmax, edges, precision="f32", summation=summation)
+    if summation == "particle":
+        pos, w = lognormal_catalogue(n, box, 30000, 0.03 * box, 600, 601, 602, (0.5, 1.5))
+        pt, wt = _dev(pos, torch.float32), _dev(w, torch.float32)
+        z = plan.zeta(plan.deposit(pt, wt), pt, wt).cpu().numpy()[0]
+        ref = E.zeta_particle(op, pos, w)
+    else:
+        delta = random_field(n, 603)
+        z = plan.zeta(_dev(delta[None], torch.float32)).cpu().numpy()[0]
+        ref = E.zeta_gamma(op, delta) if summation == "gamma" else E.zeta_nodal(op, delta)
+    e = assert_zeta_close(z, ref, 1e-4)
+    print("per-l errors", e)
+    assert np.abs(z - z.transpose(0, 2, 1)).max() <= 1e-12 * np.abs(z).max()
