@@ -193,7 +193,14 @@ FORMS = {
     "gamma_256_f32": ("box2000_n256_l10", "gamma", "f32", False),
     "gamma_256_bf16x3": ("box2000_n256_l10", "gamma", "bf16x3", False),
     "particle_512_f32": ("box3000_n512_l10", "particle", "f32", True),
+    # the remaining configurations (not run by default)
+    "gamma_32_f64": ("box250_n32_l4", "gamma", "f64", False),
+    "nodal_32_f64": ("box250_n32_l4", "nodal", "f64", True),
+    "particle_128_f32": ("box1000_n128_l10", "particle", "f32", True),
+    "particle_128_f64": ("box1000_n128_l10", "particle", "f64", True),
+    "batch64_f32": ("batch64_n128_l8", "nodal", "f32", True),
 }
+DEFAULT_FORMS = ("gamma_256_f32", "gamma_256_bf16x3", "particle_512_f32")
 
 
 def measure_form(name, steps=1, warmup=1):
@@ -201,23 +208,36 @@ def measure_form(name, steps=1, warmup=1):
     import torch
     import paper_2507_15209_amd as mp3
     from mockgen import WORKLOADS, workload_catalogue
+    from mockgen import batch_sizes
     wname, summation, precision, backward = FORMS[name]
     wl = WORKLOADS[wname]
     dev = torch.device("cuda", 0)
     t0 = time.perf_counter()
-    pos, w = workload_catalogue(wl)
+    if wname.startswith("batch"):
+        sizes = [int(x) for x in batch_sizes()]
+        cats = [workload_catalogue(wl, j, sizes[j]) for j in range(len(sizes))]
+        pos = np.concatenate([c[0] for c in cats])
+        w = np.concatenate([c[1] for c in cats])
+        off = np.concatenate([[0], np.cumsum(sizes)])
+        del cats
+    else:
+        pos, w = workload_catalogue(wl)
+        off = None
+    batch = 1 if off is None else len(off) - 1
     log(f"{name}: mock drawn in {time.perf_counter() - t0:.1f} s")
     pt, wt = torch.as_tensor(pos, device=dev), torch.as_tensor(w, device=dev)
     del pos, w
-    lam = torch.as_tensor(np.random.default_rng(12).standard_normal((1, wl.lmax + 1, wl.nbins, wl.nbins)), device=dev)
-    plan = mp3.Plan(wl.n, wl.box, wl.lmax, wl.edges, precision=precision, device=dev, summation=summation)
-    cat = (pt, wt) if summation == "particle" else ()
+    lam = torch.as_tensor(np.random.default_rng(12).standard_normal((batch, wl.lmax + 1, wl.nbins, wl.nbins)),
+                          device=dev)
+    plan = mp3.Plan(wl.n, wl.box, wl.lmax, wl.edges, precision=precision, device=dev, summation=summation,
+                    batch=batch)
+    cat = (pt, wt, off) if summation == "particle" else ()
 
     def step():
-        delta = plan.deposit(pt, wt)
+        delta = plan.deposit(pt, wt, off)
         plan.zeta(delta, *cat)
         if backward:
-            plan.zeta_backward(delta, lam, pt, wt)
+            plan.zeta_backward(delta, lam, pt, wt, off)
 
     for _ in range(warmup):
         step()
@@ -230,8 +250,8 @@ def measure_form(name, steps=1, warmup=1):
     log(f"{name}: {dt * 1e3:.1f} ms per step")
     del plan, pt, wt
     torch.cuda.empty_cache()
-    units = float(wl.n) ** 3 * (wl.lmax + 1) ** 2 * wl.nbins
-    return {"workload": wl.name, "summation": summation, "precision": precision,
+    units = float(wl.n) ** 3 * (wl.lmax + 1) ** 2 * wl.nbins * batch
+    return {"workload": wl.name, "summation": summation, "precision": precision, "batch": batch,
             "pass": "deposit + forward" + (" + adjoint with dJ/dw" if backward else ""),
             "value": units / dt, "unit": "zeta_l evals/s", "ms_per_step": dt * 1e3, "steps": steps}
 
@@ -265,8 +285,8 @@ def main():
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default=",".join(FORMS),
-                    help="secondary measurements after the headline (comma list of %s, or none)" % ", ".join(FORMS))
+    ap.add_argument("--forms", default=",".join(DEFAULT_FORMS),
+                    help="secondary measurements after the headline (comma list of %s, all, or none)" % ", ".join(FORMS))
     ap.add_argument("--pmc-probe", action="store_true", help="one step plus a 1 GiB copy, for counter runs")
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print the per-launch traffic summary of two rocprofv3 --pmc runs of --pmc-probe")
@@ -358,7 +378,8 @@ def main():
         fp64 = {"value": units / t64, "ms_per_step": t64 * 1e3, "ratio_f32_over_f64": t64 / t_step}
 
     forms = {}
-    for name in [f for f in args.forms.split(",") if f and f != "none"]:
+    names = list(FORMS) if args.forms == "all" else [f for f in args.forms.split(",") if f and f != "none"]
+    for name in names:
         forms[name] = measure_form(name)
 
     cpu = None

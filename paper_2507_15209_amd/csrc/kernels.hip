@@ -847,10 +847,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MF ? 4
 // particle summation
 // ---------------------------------------------------------------------------
 // z pass that stores the fields bin-interleaved, out[mock][cell][b], so that a
-// B-spline tap reads all bins of a node contiguously
+// B-spline tap reads all bins of a node contiguously.  One launch handles bins
+// b0 .. b0 + nbins - 1 of nbt (the pencil of those bins is held in LDS).
 template <int N, typename T>
-__global__ void __launch_bounds__(512) k_zpass_store(const c2<T>* fields, c2<T>* out, int nbins, int ppw,
-                                                      const c2<T>* tw) {
+__global__ void __launch_bounds__(512) k_zpass_store(const c2<T>* fields, c2<T>* out, int nbins, int nbt, int b0,
+                                                      int ppw, const c2<T>* tw) {
   using F = Fft<N, VZN>;
   constexpr int RS = zrow<N>();
   constexpr long long N3 = (long long)N * N * N;
@@ -861,8 +862,8 @@ __global__ void __launch_bounds__(512) k_zpass_store(const c2<T>* fields, c2<T>*
   stage_twiddles<N, T>(tw, tws);
   const int p0 = blockIdx.x * ppw;
   const int p1 = min(p0 + ppw, N * N);
-  const c2<T>* fmock = fields + mock * nbins * N3;
-  c2<T>* omock = out + mock * nbins * N3;
+  const c2<T>* fmock = fields + (mock * nbt + b0) * N3;
+  c2<T>* omock = out + mock * nbt * N3;
   c2<T> vpre[prefetch_rounds<N, VZN>()][F::RMAX];
   if (p0 < p1) prefetch_pencil<N, T, VZN>(fmock + (long long)p0 * N, N3, nbins, vpre);
   for (int p = p0; p < p1; ++p) {
@@ -875,10 +876,10 @@ __global__ void __launch_bounds__(512) k_zpass_store(const c2<T>* fields, c2<T>*
     __syncthreads();
     transform_pencil_bins<N, T, VZN>(fmock + (long long)p * N, N3, nbins, A, tws, vcur);
     __syncthreads();
-    c2<T>* dst = omock + (long long)p * N * nbins;
+    c2<T>* dst = omock + (long long)p * N * nbt + b0;
     for (int idx = threadIdx.x; idx < N * nbins; idx += blockDim.x) {
       const int z = idx / nbins, b = idx - z * nbins;
-      dst[idx] = A[b * RS + lds_pos<true>(z)];
+      dst[(long long)z * nbt + b] = A[b * RS + lds_pos<true>(z)];
     }
   }
 }
@@ -1965,16 +1966,30 @@ hipError_t zpass_nodal_mf(const ZpassArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// bins per launch of the store pass: as many as the LDS holds
+template <int N, typename T> inline int zpass_store_bins(int nbins) {
+  const size_t per = (size_t)zrow<N>() * sizeof(CT<T>);
+  const size_t room = (size_t)160 * 1024 - (size_t)N * sizeof(CT<T>);
+  const int cb = (int)(room / per);
+  return nbins < cb ? nbins : cb;
+}
+
 template <int N, typename T>
 hipError_t zpass_store_t(const ZpassArgs& a, void* out, hipStream_t st) {
-  const int threads = zpass_threads<N, VZN>(a.nbins);
-  const size_t lds = (size_t)a.nbins * zrow<N>() * sizeof(CT<T>) + (size_t)N * sizeof(CT<T>);
-  hipError_t e = allow_lds(k_zpass_store<N, T>, lds);
-  if (e != hipSuccess) return e;
-  const dim3 gs(a.nwg, a.batch);
-  k_zpass_store<N, T><<<gs, threads, lds, st>>>(static_cast<const CT<T>*>(a.fields), static_cast<CT<T>*>(out), a.nbins,
-                                               a.ppw, static_cast<const CT<T>*>(a.tw));
-  return hipGetLastError();
+  const int cb = zpass_store_bins<N, T>(a.nbins);
+  for (int b0 = 0; b0 < a.nbins; b0 += cb) {
+    const int nb = a.nbins - b0 < cb ? a.nbins - b0 : cb;
+    const int threads = zpass_threads<N, VZN>(nb);
+    const size_t lds = (size_t)nb * zrow<N>() * sizeof(CT<T>) + (size_t)N * sizeof(CT<T>);
+    hipError_t e = allow_lds(k_zpass_store<N, T>, lds);
+    if (e != hipSuccess) return e;
+    const dim3 gs(a.nwg, a.batch);
+    k_zpass_store<N, T><<<gs, threads, lds, st>>>(static_cast<const CT<T>*>(a.fields), static_cast<CT<T>*>(out), nb,
+                                                 a.nbins, b0, a.ppw, static_cast<const CT<T>*>(a.tw));
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // float32 with at most 32 bins contracts on the matrix cores (float32 or

@@ -292,8 +292,10 @@ int mp3_plan_create(const mp3_plan_desc* d, mp3_plan_t* out) {
   if (d->summation == MP3_SUM_GRID_GAMMA && mp3::gamma_lds_need(storage, d->nbins) > kLdsLimit)
     return fail(MP3_EUNSUPPORTED, "nbins too large for the grid-Gamma tile's LDS at this precision");
   if (d->batch < 1) return fail(MP3_EINVAL, "batch must be >= 1");
-  if (mp3::zpass_lds_need(d->n, storage, d->nbins) > kLdsLimit)
-    return fail(MP3_EUNSUPPORTED, "n * nbins too large for the z pass's LDS at this precision");
+  // the nodal z passes hold every bin of a pencil in LDS (the other forms'
+  // store pass takes the bins in chunks)
+  if (d->summation == MP3_SUM_NODAL && mp3::zpass_lds_need(d->n, storage, d->nbins) > kLdsLimit)
+    return fail(MP3_EUNSUPPORTED, "n * nbins too large for the nodal z pass's LDS at this precision");
 
   mp3_plan_s* p = new (std::nothrow) mp3_plan_s;
   if (!p) return fail(MP3_ENOMEM, "host allocation failed");
