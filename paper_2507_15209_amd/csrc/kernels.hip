@@ -948,13 +948,64 @@ __global__ void k_tile_scatter(const float* pos, const long long* off, int batch
   }
 }
 
+// Per-particle stencil records in sorted order, computed once per call by
+// make_taps: the cell (floor of x n / box per axis, packed 10 bits each; -1
+// for a position that is not finite) and the 12 tap weights in the working
+// precision.  The gathers and the scatter read these instead of re-deriving
+// the stencil in float64 for every lane and (l, m).
+__device__ __forceinline__ int pack_cell(const Taps& t) {
+  return t.ok ? ((t.base[0] + 1) | ((t.base[1] + 1) << 10) | ((t.base[2] + 1) << 20)) : -1;
+}
+
+template <typename T>
+__global__ void k_tap_records(const float* pos, const int* perm, long long np_total, int n, double sc, int* tcell,
+                              T* twt) {
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < np_total; k += (long long)gridDim.x * blockDim.x) {
+    const Taps t = make_taps(pos + 3 * (long long)perm[k], n, sc);
+    tcell[k] = pack_cell(t);
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) twt[k * 12 + d * 4 + a] = (T)t.wt[d][a];
+  }
+}
+
+// sum over the 64 taps of record k of w_tap * f[node][b] (bin-interleaved
+// fields of one mock, nbins per node)
+template <typename T>
+__device__ __forceinline__ c2<T> gather_record(const c2<T>* fm, int cell, const T* wt, int n, int nbins, int b) {
+  c2<T> acc = mk<T>(0, 0);
+  const int cx = cell & 1023, cy = (cell >> 10) & 1023, cz = cell >> 20;
+  int iz[4];
+#pragma unroll
+  for (int az = 0; az < 4; ++az) iz[az] = wrapi(cz - 1 + az, n);
+#pragma unroll
+  for (int ax = 0; ax < 4; ++ax) {
+    const int ix = wrapi(cx - 1 + ax, n);
+#pragma unroll
+    for (int ay = 0; ay < 4; ++ay) {
+      const int iy = wrapi(cy - 1 + ay, n);
+      const T wxy = wt[ax] * wt[4 + ay];
+      const int row = (ix * n + iy) * n;
+#pragma unroll
+      for (int az = 0; az < 4; ++az) {
+        const c2<T> v = fm[(long long)(row + iz[az]) * nbins + b];
+        const T w = wxy * wt[8 + az];
+        acc.x += w * v.x;
+        acc.y += w * v.y;
+      }
+    }
+  }
+  return acc;
+}
+
 // Gather the B-spline interpolants of the (bin-interleaved) fields at the
 // particles, one lane per (particle, bin), into LDS rows, then contract with
 // the weights w_i / W.  Particles are visited in tile order (perm).
 template <typename T, bool MF, bool SPLIT = false, bool QUAD = false>
-__global__ void __launch_bounds__(256) k_gather_contract(const c2<T>* fields, const float* pos, const float* w,
-                                                          const int* perm, const long long* off, const double* W,
-                                                          int n, double sc, int nbins, double* partials) {
+__global__ void __launch_bounds__(256) k_gather_contract(const c2<T>* fields, const int* tcell, const T* twt,
+                                                          const float* w, const int* perm, const long long* off,
+                                                          const double* W, int n, int nbins, double* partials) {
   constexpr int K = 256;                                // particles per contraction slice
   constexpr int RS = K + K / 16 + 1;
   extern __shared__ __align__(16) char smem[];
@@ -980,25 +1031,8 @@ __global__ void __launch_bounds__(256) k_gather_contract(const c2<T>* fields, co
       T wgt = 0;
       if (si < s1) {
         const int i = perm[si];
-        Taps t = make_taps(pos + 3 * (long long)i, n, sc);
-        if (t.ok && b < nbins) {
-          for (int ax = 0; ax < 4; ++ax) {
-            const int ix = wrapi(t.base[0] + ax, n);
-            for (int ay = 0; ay < 4; ++ay) {
-              const int iy = wrapi(t.base[1] + ay, n);
-              const T wxy = (T)(t.wt[0][ax] * t.wt[1][ay]);
-              const c2<T>* row = fm + ((long long)ix * n + iy) * n * nbins + b;
-#pragma unroll
-              for (int az = 0; az < 4; ++az) {
-                const int iz = wrapi(t.base[2] + az, n);
-                const c2<T> v = row[(long long)iz * nbins];
-                const T wt = wxy * (T)t.wt[2][az];
-                acc.x += wt * v.x;
-                acc.y += wt * v.y;
-              }
-            }
-          }
-        }
+        const int cell = tcell[si];
+        if (cell >= 0 && b < nbins) acc = gather_record<T>(fm, cell, twt + si * 12, n, nbins, b);
         wgt = (T)((w ? (double)w[i] : 1.0) * invW);
       }
       if (b < nbins) A[b * RS + lds_pos<true>(k)] = acc;
@@ -1462,9 +1496,9 @@ __global__ void k_grad_combine(const T* direct, const c2<T>* ghat, T* ddelta, lo
 // and store the adjoint source s_b(i) = N^3 (w_i / W) v_b at the particle's
 // sorted slot.  One lane per (particle, bin), 32 or 64 lanes per particle.
 template <typename T>
-__global__ void __launch_bounds__(256) k_gather_source(const c2<T>* fields, const float* pos, const float* w,
-                                                        const int* perm, const long long* off, const double* W,
-                                                        const T* lam_s, int n, double sc, int nbins, T wm,
+__global__ void __launch_bounds__(256) k_gather_source(const c2<T>* fields, const int* tcell, const T* twt,
+                                                        const float* w, const int* perm, const long long* off,
+                                                        const double* W, const T* lam_s, int n, int nbins, T wm,
                                                         double* FJ, c2<T>* src) {
   extern __shared__ __align__(16) char smem[];
   c2<T>* at = reinterpret_cast<c2<T>*>(smem);                     // [particles per pass][nbins]
@@ -1487,24 +1521,8 @@ __global__ void __launch_bounds__(256) k_gather_source(const c2<T>* fields, cons
     const int i = has ? perm[si] : 0;
     c2<T> acc = mk<T>(0, 0);
     if (has && b < nbins) {
-      Taps t = make_taps(pos + 3 * (long long)i, n, sc);
-      if (t.ok) {
-        for (int ax = 0; ax < 4; ++ax) {
-          const int ix = wrapi(t.base[0] + ax, n);
-          for (int ay = 0; ay < 4; ++ay) {
-            const int iy = wrapi(t.base[1] + ay, n);
-            const T wxy = (T)(t.wt[0][ax] * t.wt[1][ay]);
-            const c2<T>* row = fm + ((long long)ix * n + iy) * n * nbins + b;
-#pragma unroll
-            for (int az = 0; az < 4; ++az) {
-              const c2<T> v = row[(long long)wrapi(t.base[2] + az, n) * nbins];
-              const T wt = wxy * (T)t.wt[2][az];
-              acc.x += wt * v.x;
-              acc.y += wt * v.y;
-            }
-          }
-        }
-      }
+      const int cell = tcell[si];
+      if (cell >= 0) acc = gather_record<T>(fm, cell, twt + si * 12, n, nbins, b);
     }
     __syncthreads();                                   // the previous pass's reads of at[] are done
     if (b < nbins) at[g * nbins + b] = acc;
@@ -1565,9 +1583,8 @@ struct ScatterLds {
 };
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_scatter_source(const float* pos, const int* perm, const int* toff,
-                                                         const c2<T>* src, int n, double sc, int nbins, int nchunk,
-                                                         c2<T>* out) {
+__global__ void __launch_bounds__(256) k_scatter_source(const int* tcell, const T* twt, const int* toff,
+                                                         const c2<T>* src, int n, int nbins, int nchunk, c2<T>* out) {
   constexpr int TO = SCT, TB = SCT + 3;
   constexpr int NODES = TO * TO * TO;
   constexpr int BC = scatter_bc<T>(), Q = scatter_q<T>();
@@ -1623,22 +1640,22 @@ __global__ void __launch_bounds__(256) k_scatter_source(const float* pos, const 
         if (pre[mid] <= t) lo = mid; else hi = mid;
       }
       const int k = cbase[lo] + (t - pre[lo]);
-      Taps tp = make_taps(pos + 3 * (long long)perm[k], n, sc);
+      const int cell = tcell[k];
+      const int cb[3] = {(cell & 1023) - 1, ((cell >> 10) & 1023) - 1, (cell >> 20) - 1};   // first tap per axis
       int rl[3];
-      bool reach = tp.ok;
+      bool reach = cell >= 0;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const int r = tap_offset(tp.base[d], o0[d], n);
+        const int r = tap_offset(cb[d], o0[d], n);
         rl[d] = r < TO ? r : r - n;             // -3 .. 7 when the stencil reaches the tile
         reach = reach && (r < TO || r >= n - 3);
       }
       if (reach) {
         const int q = atomicAdd(&qn, 1);
         qkey[q] = ((rl[0] + 3) * TB + (rl[1] + 3)) * TB + (rl[2] + 3);
+        const T* wr = twt + (long long)k * 12;
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
-#pragma unroll
-          for (int a = 0; a < 4; ++a) qwt[(q * 3 + d) * 4 + a] = (T)tp.wt[d][a];
+        for (int e = 0; e < 12; ++e) qwt[q * 12 + e] = wr[e];
         const c2<T>* sp = src + (long long)k * nbins + b0;
 #pragma unroll
         for (int bb = 0; bb < BC; ++bb) qsv[q * BC + bb] = bb < nbc ? sp[bb] : mk<T>(0, 0);
@@ -2276,8 +2293,9 @@ hipError_t gather_contract_t(const GatherArgs& a, hipStream_t st) {
   hipError_t e = allow_lds(k_gather_contract<T, MF, SPLIT, QUAD>, lds);
   if (e != hipSuccess) return e;
   const dim3 gs(a.nwg, a.batch);
-  k_gather_contract<T, MF, SPLIT, QUAD><<<gs, 256, lds, st>>>(static_cast<const CT<T>*>(a.fields), a.pos, a.w, a.perm,
-                                                             a.off, a.W, a.n, a.sc, a.nbins, a.partials);
+  k_gather_contract<T, MF, SPLIT, QUAD><<<gs, 256, lds, st>>>(static_cast<const CT<T>*>(a.fields), a.tcell,
+                                                             static_cast<const T*>(a.twt), a.w, a.perm, a.off, a.W,
+                                                             a.n, a.nbins, a.partials);
   return hipGetLastError();
 }
 
@@ -2350,9 +2368,9 @@ size_t gamma_lds_need(int prec, int nbins) {
   return prec ? GammaLds<double>(nbins).total : GammaLds<float>(nbins).total;
 }
 
-hipError_t launch_gather_source(int prec, const void* fields, const float* pos, const float* w, const int* perm,
-                                const long long* off, const double* W, const void* lam_s, int n, double sc, int nbins,
-                                double wm, int nwg, int batch, double* FJ, void* src, hipStream_t st) {
+hipError_t launch_gather_source(int prec, const void* fields, const int* tcell, const void* twt, const float* w,
+                                const int* perm, const long long* off, const double* W, const void* lam_s, int n,
+                                int nbins, double wm, int nwg, int batch, double* FJ, void* src, hipStream_t st) {
   const int lpp = nbins <= 32 ? 32 : 64;
   const int ppp = 256 / lpp;
   const size_t elt = prec ? sizeof(double) : sizeof(float);
@@ -2361,21 +2379,23 @@ hipError_t launch_gather_source(int prec, const void* fields, const float* pos, 
   if (prec) {
     hipError_t e = allow_lds(k_gather_source<double>, lds);
     if (e != hipSuccess) return e;
-    k_gather_source<double><<<gs, 256, lds, st>>>(static_cast<const double2*>(fields), pos, w, perm, off, W,
-                                                  static_cast<const double*>(lam_s), n, sc, nbins, wm, FJ,
+    k_gather_source<double><<<gs, 256, lds, st>>>(static_cast<const double2*>(fields), tcell,
+                                                  static_cast<const double*>(twt), w, perm, off, W,
+                                                  static_cast<const double*>(lam_s), n, nbins, wm, FJ,
                                                   static_cast<double2*>(src));
   } else {
     hipError_t e = allow_lds(k_gather_source<float>, lds);
     if (e != hipSuccess) return e;
-    k_gather_source<float><<<gs, 256, lds, st>>>(static_cast<const float2*>(fields), pos, w, perm, off, W,
-                                                 static_cast<const float*>(lam_s), n, sc, nbins, (float)wm, FJ,
+    k_gather_source<float><<<gs, 256, lds, st>>>(static_cast<const float2*>(fields), tcell,
+                                                 static_cast<const float*>(twt), w, perm, off, W,
+                                                 static_cast<const float*>(lam_s), n, nbins, (float)wm, FJ,
                                                  static_cast<float2*>(src));
   }
   return hipGetLastError();
 }
 
-hipError_t launch_scatter_source(int prec, const float* pos, const int* perm, const int* toff, const void* src, int n,
-                                 double sc, int nbins, int batch, void* out, hipStream_t st) {
+hipError_t launch_scatter_source(int prec, const int* tcell, const void* twt, const int* toff, const void* src, int n,
+                                 int nbins, int batch, void* out, hipStream_t st) {
   const int no = n / SCT;
   if (prec) {
     const int nchunk = (nbins + scatter_bc<double>() - 1) / scatter_bc<double>();
@@ -2383,17 +2403,27 @@ hipError_t launch_scatter_source(int prec, const float* pos, const int* perm, co
     hipError_t e = allow_lds(k_scatter_source<double>, lds);
     if (e != hipSuccess) return e;
     const dim3 gs(no * no * no, batch * nchunk);
-    k_scatter_source<double><<<gs, 256, lds, st>>>(pos, perm, toff, static_cast<const double2*>(src), n, sc, nbins,
-                                                   nchunk, static_cast<double2*>(out));
+    k_scatter_source<double><<<gs, 256, lds, st>>>(tcell, static_cast<const double*>(twt), toff,
+                                                   static_cast<const double2*>(src), n, nbins, nchunk,
+                                                   static_cast<double2*>(out));
   } else {
     const int nchunk = (nbins + scatter_bc<float>() - 1) / scatter_bc<float>();
     const size_t lds = ScatterLds<float>().total;
     hipError_t e = allow_lds(k_scatter_source<float>, lds);
     if (e != hipSuccess) return e;
     const dim3 gs(no * no * no, batch * nchunk);
-    k_scatter_source<float><<<gs, 256, lds, st>>>(pos, perm, toff, static_cast<const float2*>(src), n, sc, nbins,
-                                                  nchunk, static_cast<float2*>(out));
+    k_scatter_source<float><<<gs, 256, lds, st>>>(tcell, static_cast<const float*>(twt), toff,
+                                                  static_cast<const float2*>(src), n, nbins, nchunk,
+                                                  static_cast<float2*>(out));
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_tap_records(int prec, const float* pos, const int* perm, long long np_total, int n, double sc,
+                              int* tcell, void* twt, hipStream_t st) {
+  const unsigned g = grid_for(np_total, 256, 16384);
+  if (prec) k_tap_records<double><<<g, 256, 0, st>>>(pos, perm, np_total, n, sc, tcell, static_cast<double*>(twt));
+  else k_tap_records<float><<<g, 256, 0, st>>>(pos, perm, np_total, n, sc, tcell, static_cast<float*>(twt));
   return hipGetLastError();
 }
 

@@ -30,6 +30,8 @@ struct ZpassArgs {
 
 struct GatherArgs {
   const void* fields;     // bin-interleaved fields [batch][N^3][nbins]
+  const int* tcell;       // stencil records in sorted order (launch_tap_records)
+  const void* twt;
   const float* pos;       // [np_total][3]
   const float* w;         // [np_total] or NULL
   const int* perm;        // particle order (tile-sorted), [np_total]
@@ -83,11 +85,15 @@ hipError_t launch_weighted_sum(const float* w, const double* f, const long long*
 // particle-form adjoint: per-particle sources and F_J, their scatter onto the
 // grid ([batch][nbins][N^3], every node written), the volume-mean term into G
 // and the primary vertex's share of dJ/dw
-hipError_t launch_gather_source(int prec, const void* fields, const float* pos, const float* w, const int* perm,
-                                const long long* off, const double* W, const void* lam_s, int n, double sc, int nbins,
-                                double wm, int nwg, int batch, double* FJ, void* src, hipStream_t st);
-hipError_t launch_scatter_source(int prec, const float* pos, const int* perm, const int* toff, const void* src, int n,
-                                 double sc, int nbins, int batch, void* out, hipStream_t st);
+hipError_t launch_gather_source(int prec, const void* fields, const int* tcell, const void* twt, const float* w,
+                                const int* perm, const long long* off, const double* W, const void* lam_s, int n,
+                                int nbins, double wm, int nwg, int batch, double* FJ, void* src, hipStream_t st);
+hipError_t launch_scatter_source(int prec, const int* tcell, const void* twt, const int* toff, const void* src, int n,
+                                 int nbins, int batch, void* out, hipStream_t st);
+// per-particle stencil records in sorted order: packed cell (-1 if not
+// finite) and 12 tap weights in the working precision
+hipError_t launch_tap_records(int prec, const float* pos, const int* perm, long long np_total, int n, double sc,
+                              int* tcell, void* twt, hipStream_t st);
 hipError_t launch_fbar_adjoint(int prec, const double* dzeta, const void* jtab, int nq2, int nbp, int nbins, int lmax,
                                const void* dhat, int n, double scale, double* h, void* G, int batch, hipStream_t st);
 hipError_t launch_primary_dw(int prec, const long long* off, int batch, long long np_total, const double* FJ,

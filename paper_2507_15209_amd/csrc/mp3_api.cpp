@@ -61,7 +61,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
   size_t off, W, S, dhat, fields, partials, G, direct, lam, fields_i, perm, counts, offs, cursor, power;
-  size_t src, fj, hq, SF;
+  size_t src, fj, hq, SF, tcell, twt;
   size_t dperm, dcounts, doffs, dcursor, dcounter, total;
   int nwg, ppw;
 };
@@ -136,6 +136,8 @@ Layout layout(const mp3_plan_s* p, long long np_total = 0) {
     L.fj = take(npt * sizeof(double));
     L.hq = take(B * (size_t)mp3::nq2_count(p->n) * sizeof(double));
     L.SF = take(B * sizeof(double));
+    L.tcell = take(npt * sizeof(int));
+    L.twt = take(npt * 12 * p->elt);
   }
   // tiled deposit, last so that the offsets above do not depend on the
   // number of particles of the nodal and grid forms
@@ -530,6 +532,9 @@ int zeta_particle(mp3_plan_t p, const float* pos, const float* w, const int64_t*
   MP3_HIP(mp3::launch_tile_sort(pos, off, p->batch, np_total, p->n, sc, 2, reinterpret_cast<int*>(at(ws, L.counts)),
                                 reinterpret_cast<int*>(at(ws, L.offs)), reinterpret_cast<int*>(at(ws, L.cursor)), perm, st),
           "tile sort");
+  int* tcell = reinterpret_cast<int*>(at(ws, L.tcell));
+  void* twt = at(ws, L.twt);
+  MP3_HIP(mp3::launch_tap_records(p->prec, pos, perm, np_total, p->n, sc, tcell, twt, st), "stencil records");
   double* P = reinterpret_cast<double*>(at(ws, L.power));
   const int nq2 = mp3::nq2_count(p->n);
   MP3_HIP(mp3::launch_fill_f64(P, (long long)p->batch * nq2, 0.0, st), "zero power");
@@ -551,6 +556,8 @@ int zeta_particle(mp3_plan_t p, const float* pos, const float* w, const int64_t*
       MP3_HIP(timed(p, MP3_PASS_Z_STORE, st, [&] { return mp3::launch_zpass_store(p->n, p->prec, z, Fi, st); }), "z pass (store)");
       mp3::GatherArgs g{};
       g.fields = Fi;
+      g.tcell = tcell;
+      g.twt = twt;
       g.pos = pos;
       g.w = w;
       g.perm = perm;
@@ -661,6 +668,9 @@ int backward_particle(mp3_plan_t p, const void* delta, const double* dzeta, void
   MP3_HIP(mp3::launch_tile_sort(pos, off, p->batch, np_total, p->n, sc, 2, reinterpret_cast<int*>(at(ws, L.counts)),
                                 reinterpret_cast<int*>(at(ws, L.offs)), reinterpret_cast<int*>(at(ws, L.cursor)), perm, st),
           "tile sort");
+  int* tcell = reinterpret_cast<int*>(at(ws, L.tcell));
+  void* twt = at(ws, L.twt);
+  MP3_HIP(mp3::launch_tap_records(p->prec, pos, perm, np_total, p->n, sc, tcell, twt, st), "stencil records");
   void* F = at(ws, L.fields);
   void* Fi = at(ws, L.fields_i);
   void* G = at(ws, L.G);
@@ -685,12 +695,12 @@ int backward_particle(mp3_plan_t p, const void* delta, const double* dzeta, void
       z.batch = p->batch;
       MP3_HIP(timed(p, MP3_PASS_Z_STORE, st, [&] { return mp3::launch_zpass_store(p->n, p->prec, z, Fi, st); }), "z pass (store)");
       MP3_HIP(timed(p, MP3_PASS_GATHER, st, [&] {
-                return mp3::launch_gather_source(p->prec, Fi, pos, w, perm, off, W, at(ws, L.lam), p->n, sc, p->nbins, wm,
-                                                 gwg, p->batch, FJ, src, st);
+                return mp3::launch_gather_source(p->prec, Fi, tcell, twt, w, perm, off, W, at(ws, L.lam), p->n, p->nbins,
+                                                 wm, gwg, p->batch, FJ, src, st);
               }),
               "gather (adjoint sources)");
       MP3_HIP(timed(p, MP3_PASS_SCATTER, st, [&] {
-                return mp3::launch_scatter_source(p->prec, pos, perm, toff, src, p->n, sc, p->nbins, p->batch, F, st);
+                return mp3::launch_scatter_source(p->prec, tcell, twt, toff, src, p->n, p->nbins, p->batch, F, st);
               }),
               "scatter (adjoint sources)");
       MP3_HIP(timed(p, MP3_PASS_Z_ADJOINT, st, [&] { return mp3::launch_fft_z(p->n, p->prec, +1, F, F, p->batch * p->nbins, p->tw, st); }),
