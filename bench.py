@@ -194,7 +194,8 @@ FORMS = {
     "gamma_256_bf16x3": ("box2000_n256_l10", "gamma", "bf16x3", False),
     "particle_512_f32": ("box3000_n512_l10", "particle", "f32", True),
     # the remaining configurations (not run by default)
-    "gamma_32_f64": ("box250_n32_l4", "gamma", "f64", False),
+    "gamma_256_f32_adj": ("box2000_n256_l10", "gamma", "f32", True),
+    "gamma_32_f64": ("box250_n32_l4", "gamma", "f64", True),
     "nodal_32_f64": ("box250_n32_l4", "nodal", "f64", True),
     "particle_128_f32": ("box1000_n128_l10", "particle", "f32", True),
     "particle_128_f64": ("box1000_n128_l10", "particle", "f64", True),

@@ -159,9 +159,11 @@ int mp3_multipole_fields(mp3_plan_t plan, const void* delta, int32_t l, int32_t 
 int mp3_zeta(mp3_plan_t plan, const void* delta, const float* pos, const float* w, const int64_t* np_off,
              double* zeta, void* workspace, size_t workspace_bytes, void* stream);
 
-/* Gradient of J = sum_{j,l,b1,b2} dzeta[j][l][b1][b2] zeta_l^{(j)}[b1][b2] for the
- * nodal and particle forms (the grid-Gamma form returns MP3_EUNSUPPORTED); the
- * paper gives no gradient, this is the chain rule of mp3_zeta and mp3_deposit.
+/* Gradient of J = sum_{j,l,b1,b2} dzeta[j][l][b1][b2] zeta_l^{(j)}[b1][b2] for
+ * every form; the paper gives no gradient, this is the chain rule of mp3_zeta
+ * and mp3_deposit.  The grid-Gamma form's adjoint tile holds 7^3 coefficients
+ * of every bin twice in LDS: float32 up to 20 bins, float64 up to 9 bins
+ * (MP3_EUNSUPPORTED beyond).
  * The fields are recomputed per (l, m); nothing is kept from mp3_zeta.
  *   ddelta = dJ/ddelta                                          (device real [batch][N^3])
  *            For the particle form this is the dependence through the

@@ -30,6 +30,19 @@ weights enter through delta (deposit, below) and through the primary:
 
   dJ/dw_i += 4 pi [ F_J(u_i) / W - sum_j w_j F_J(u_j) / W^2 ].
 
+Grid summation with connection coefficients.  zeta_l is the bilinear form
+sum lam a_{b1}^T M conj(a_{b2}) with the symmetric operator
+M(x, y) = sum_w delta_w Gamma(x - w, y - w); with G_Delta(x) =
+sum_s delta(x - s) Gamma(s, s + Delta) (the stencil fields of
+estimator.zeta_gamma),
+
+  dJ/ddelta_x = (4 pi / n^3) [ Re sum_{l,m} sum_{s,t} Gamma(s,t) sum_{b1,b2} lam[b1,b2] a_{b1}(x+s) conj(a_{b2}(x+t))
+                               + 2 Re fftn( sum_{l,m,b} K_{lm,b} ifftn(c_{lm,b}) )(x) ],
+  c_{lm,b}(x) = sum_Delta G_Delta(x) V_b(x + Delta),  V_b = sum_{b'} lam^s[b,b'] conj(a_{b'}):
+
+the nodal formula with every pointwise product replaced by its Gamma
+stencil (the nodal form is Gamma(s,t) = delta_{s0} delta_{t0}).
+
 Deposit.  delta_l = eps_l n^3 / W - 1 with eps_l = sum_i w_i B_i(l) and
 W = sum_i w_i, so for a grid gradient g = dJ/ddelta,
 
@@ -43,7 +56,7 @@ from . import basis
 from .estimator import Plan, fields, FOUR_PI
 
 __all__ = ["zeta_nodal_grad", "deposit_weight_grad", "zeta_nodal_objective",
-           "zeta_particle_objective", "zeta_particle_grad"]
+           "zeta_particle_objective", "zeta_particle_grad", "zeta_gamma_objective", "zeta_gamma_grad"]
 
 
 def zeta_nodal_objective(plan: Plan, delta, lam) -> float:
@@ -138,3 +151,46 @@ def zeta_particle_grad(plan: Plan, pos, w, lam, ls=None, bins=None):
     g = (FOUR_PI / n ** 3) * 2.0 * np.fft.fftn(acc).real - (2.0 / n ** 3) * np.fft.ifftn(H * dhat).real
     dw = deposit_weight_grad(pos, w, n, box, g) + FOUR_PI * (FJ / W - float(np.dot(w, FJ)) / W ** 2)
     return g, dw
+
+
+def zeta_gamma_objective(plan: Plan, delta, lam) -> float:
+    """J = sum_l <lam_l, zeta_l> for the grid-Gamma form (used by finite differences)."""
+    from .estimator import zeta_gamma
+    return float(np.sum(np.asarray(lam) * zeta_gamma(plan, delta)))
+
+
+def zeta_gamma_grad(plan: Plan, delta, lam, ls=None, bins=None) -> np.ndarray:
+    """dJ/ddelta for the grid summation with connection coefficients.
+
+    lam has shape [lmax+1, nbins, nbins], or [len(ls), len(bins), len(bins)]
+    with ``ls`` / ``bins``.
+    """
+    from .estimator import _gamma_stencil_field
+    delta = np.asarray(delta, dtype=np.float64)
+    lam = np.asarray(lam, dtype=np.float64)
+    n = plan.n
+    dhat = np.fft.fftn(delta)
+    gmat = basis.gamma_matrix()
+    shifts = [(dx, dy, dz) for dx in range(-3, 4) for dy in range(-3, 4) for dz in range(-3, 4)]
+    gfields = {sh: _gamma_stencil_field(delta, gmat, sh) for sh in shifts}
+    direct = np.zeros(delta.shape, dtype=np.complex128)
+    acc = np.zeros(delta.shape, dtype=np.complex128)
+    bl = plan.bins(bins)
+    for li, l in enumerate(plan.ls(ls)):
+        lam_l = lam[li]
+        lam_s = 0.5 * (lam_l + lam_l.T)
+        for m in range(-l, l + 1):
+            A = fields(plan, dhat, l, m, bl)                                 # [nb, n, n, n]
+            V = np.einsum("ij,jxyz->ixyz", lam_s, A.conj())
+            C = np.zeros_like(A)
+            for sh, G in gfields.items():
+                rolled = (-sh[0], -sh[1], -sh[2])
+                Ash = np.roll(A, shift=rolled, axis=(1, 2, 3))              # a(x + Delta)
+                Q = np.einsum("ij,ixyz,jxyz->xyz", lam_l, A, Ash.conj())     # sum lam a_b1(y) conj(a_b2(y + Delta))
+                direct += _gamma_stencil_field(Q, gmat, (-sh[0], -sh[1], -sh[2]))
+                C += G[None] * np.roll(V, shift=rolled, axis=(1, 2, 3))      # G_Delta(x) V_b(x + Delta)
+            yc = plan.ylm_conj_grid(l, m)
+            for bi, b in enumerate(bl):
+                acc += plan.kernel(l, m, b, yc) * np.fft.ifftn(C[bi])
+    grad = direct.real + 2.0 * np.fft.fftn(acc).real
+    return grad * (FOUR_PI / n ** 3)

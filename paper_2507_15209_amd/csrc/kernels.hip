@@ -1750,6 +1750,303 @@ __global__ void __launch_bounds__(256) k_scatter_source(const int* tcell, const 
   }
 }
 
+// ---------------------------------------------------------------------------
+// adjoint of the grid summation with connection coefficients
+// ---------------------------------------------------------------------------
+// zeta is the exact 5-point Gauss-Legendre quadrature over every cell of
+// delta_B(u) sum lam atilde_{b1}(u) conj(atilde_{b2}(u)), so for one (l, m)
+//   c_b(x)    = sum_q B3(u_q - x) w_q delta_B(u_q) v_b(u_q),   v_b = sum_b' lam_s[b][b'] conj(atilde_b'),
+//   direct(x) += wm sum_q B3(u_q - x) w_q F(u_q),               F = sum_b Re(atilde_b v_b):
+// the transposes of the three interpolations of k_gamma_contract applied to
+// the node sources.  A workgroup takes a 4^3-cell tile as the forward does,
+// per x node and per y cell (5 y nodes x 20 z nodes) interpolates the fields
+// to the nodes, forms v and F there, and folds the sources back through the
+// transposed z, y and x interpolations into a 7^3-coefficient LDS accumulator,
+// which it adds to c and direct with global atomics (neighbouring tiles
+// overlap by three coefficients per axis).
+constexpr int AGY = 5;                      // y nodes per adjoint slice (one y cell)
+constexpr int AGK = AGY * GN;               // nodes per slice (100)
+constexpr int AGRS = AGK + AGK / 16 + 1;
+constexpr int AGH = 10;                     // bins per half in the per-node step
+
+template <typename T>
+struct GammaAdjLds {
+  size_t C, D, Ct, Dt, P, Pd, Pt, Pdt, Q, Qd, Qt, Qdt, A, W, Wq, Fh, lam, total;
+  __host__ __device__ GammaAdjLds(int nbins) {
+    size_t o = 0;
+    auto take = [&](size_t b) { size_t r = o; o = (o + b + 15) & ~(size_t)15; return r; };
+    const size_t c = sizeof(c2<T>), r = sizeof(T);
+    C = take((size_t)GC * GC * GC * nbins * c);
+    D = take((size_t)GC * GC * GC * r);
+    Ct = take((size_t)GC * GC * GC * nbins * c);
+    Dt = take((size_t)GC * GC * GC * r);
+    P = take((size_t)GC * GC * nbins * c);
+    Pd = take((size_t)GC * GC * r);
+    Pt = take((size_t)GC * GC * nbins * c);
+    Pdt = take((size_t)GC * GC * r);
+    Q = take((size_t)AGY * GC * nbins * c);
+    Qd = take((size_t)AGY * GC * r);
+    Qt = take((size_t)AGY * GC * nbins * c);
+    Qdt = take((size_t)AGY * GC * r);
+    A = take((size_t)nbins * AGRS * c);
+    W = take((size_t)AGK * r);
+    Wq = take((size_t)AGK * r);
+    Fh = take((size_t)2 * AGK * r);
+    lam = take((size_t)nbins * nbins * r);
+    total = o;
+  }
+};
+
+template <typename T>
+__global__ void __launch_bounds__(512) k_gamma_adjoint(const c2<T>* fields, const T* delta, const T* lam_s, int n,
+                                                        int nbins, GammaQuad gq, T wm, c2<T>* cout, T* direct) {
+  extern __shared__ __align__(16) char smem[];
+  const GammaAdjLds<T> L(nbins);
+  c2<T>* C = reinterpret_cast<c2<T>*>(smem + L.C);
+  T* D = reinterpret_cast<T*>(smem + L.D);
+  c2<T>* Ct = reinterpret_cast<c2<T>*>(smem + L.Ct);
+  T* Dt = reinterpret_cast<T*>(smem + L.Dt);
+  c2<T>* P = reinterpret_cast<c2<T>*>(smem + L.P);
+  T* Pd = reinterpret_cast<T*>(smem + L.Pd);
+  c2<T>* Pt = reinterpret_cast<c2<T>*>(smem + L.Pt);
+  T* Pdt = reinterpret_cast<T*>(smem + L.Pdt);
+  c2<T>* Q = reinterpret_cast<c2<T>*>(smem + L.Q);
+  T* Qd = reinterpret_cast<T*>(smem + L.Qd);
+  c2<T>* Qt = reinterpret_cast<c2<T>*>(smem + L.Qt);
+  T* Qdt = reinterpret_cast<T*>(smem + L.Qdt);
+  c2<T>* A = reinterpret_cast<c2<T>*>(smem + L.A);
+  T* W = reinterpret_cast<T*>(smem + L.W);
+  T* Wq = reinterpret_cast<T*>(smem + L.Wq);
+  T* Fh = reinterpret_cast<T*>(smem + L.Fh);
+  T* lam = reinterpret_cast<T*>(smem + L.lam);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const long long mock = blockIdx.y;
+  const long long n3 = (long long)n * n * n;
+  const c2<T>* fm = fields + mock * n3 * nbins;
+  const T* dm = delta + mock * n3;
+  c2<T>* cm = cout + mock * nbins * n3;
+  T* rm = direct + mock * n3;
+  const int nb2 = nbins * nbins;
+  for (int t = tid; t < nb2; t += nt) lam[t] = lam_s[mock * nb2 + t];
+  const int td = n / GT;
+  const long long ntiles = (long long)td * td * td;
+  constexpr int NC = GC * GC * GC;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int tx = (int)(tile / ((long long)td * td)), ty = (int)((tile / td) % td), tz = (int)(tile % td);
+    const int x0 = tx * GT - 1, y0 = ty * GT - 1, z0 = tz * GT - 1;     // first coefficient (periodic)
+    __syncthreads();
+    for (int e = tid; e < NC * nbins; e += nt) {
+      const int b = e % nbins, c = e / nbins;
+      const int i = c / (GC * GC), j = (c / GC) % GC, k = c % GC;
+      const long long cell = ((long long)wrapi(x0 + i, n) * n + wrapi(y0 + j, n)) * n + wrapi(z0 + k, n);
+      C[e] = fm[cell * nbins + b];
+      Ct[e] = mk<T>(0, 0);
+    }
+    for (int c = tid; c < NC; c += nt) {
+      const int i = c / (GC * GC), j = (c / GC) % GC, k = c % GC;
+      D[c] = dm[((long long)wrapi(x0 + i, n) * n + wrapi(y0 + j, n)) * n + wrapi(z0 + k, n)];
+      Dt[c] = (T)0;
+    }
+    for (int xn = 0; xn < GN; ++xn) {
+      const int cx = xn / 5, sx = xn % 5;
+      __syncthreads();
+      // x interpolation: P[j][k][b], Pd[j][k]; clear the transposed accumulators
+      for (int e = tid; e < GC * GC * nbins; e += nt) {
+        const int b = e % nbins, jk = e / nbins;
+        c2<T> acc = mk<T>(0, 0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const c2<T> v = C[((cx + t) * GC * GC + jk) * nbins + b];
+          const T m = gq_m<T>(gq, sx, t);
+          acc.x += m * v.x;
+          acc.y += m * v.y;
+        }
+        P[e] = acc;
+        Pt[e] = mk<T>(0, 0);
+      }
+      for (int jk = tid; jk < GC * GC; jk += nt) {
+        T acc = 0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc += gq_m<T>(gq, sx, t) * D[(cx + t) * GC * GC + jk];
+        Pd[jk] = acc;
+        Pdt[jk] = (T)0;
+      }
+      for (int cy = 0; cy < GT; ++cy) {
+        __syncthreads();
+        // y interpolation for the 5 y nodes of cell cy: Q[yh][k][b], Qd[yh][k]
+        for (int e = tid; e < AGY * GC * nbins; e += nt) {
+          const int b = e % nbins, yk = e / nbins;
+          const int yh = yk / GC, k = yk % GC;
+          c2<T> acc = mk<T>(0, 0);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const c2<T> v = P[((cy + t) * GC + k) * nbins + b];
+            const T m = gq_m<T>(gq, yh, t);
+            acc.x += m * v.x;
+            acc.y += m * v.y;
+          }
+          Q[e] = acc;
+        }
+        for (int yk = tid; yk < AGY * GC; yk += nt) {
+          const int yh = yk / GC, k = yk % GC;
+          T acc = 0;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc += gq_m<T>(gq, yh, t) * Pd[(cy + t) * GC + k];
+          Qd[yk] = acc;
+        }
+        __syncthreads();
+        // z interpolation to the nodes: A[b][node], node = yh * GN + zn; weights
+        for (int e = tid; e < AGK * nbins; e += nt) {
+          const int b = e % nbins, node = e / nbins;
+          const int yh = node / GN, zn = node % GN, cz = zn / 5, sz = zn % 5;
+          c2<T> acc = mk<T>(0, 0);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const c2<T> v = Q[(yh * GC + cz + t) * nbins + b];
+            const T m = gq_m<T>(gq, sz, t);
+            acc.x += m * v.x;
+            acc.y += m * v.y;
+          }
+          A[b * AGRS + lds_pos<true>(node)] = acc;
+        }
+        for (int node = tid; node < AGK; node += nt) {
+          const int yh = node / GN, zn = node % GN, cz = zn / 5, sz = zn % 5;
+          T acc = 0;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc += gq_m<T>(gq, sz, t) * Qd[yh * GC + cz + t];
+          const T wq = gq_w<T>(gq, sx) * gq_w<T>(gq, yh) * gq_w<T>(gq, sz);
+          W[node] = acc * wq;                  // w_q delta_B(u_q)
+          Wq[node] = wq;
+        }
+        __syncthreads();
+        // per node and half of the bins: v_b = sum_b' lam_s[b][b'] conj(a_b'), F
+        c2<T> vh[AGH];
+        const bool vthread = tid < 2 * AGK;
+        const int vnode = tid >> 1, vh0 = (tid & 1) * AGH;
+        if (vthread) {
+          const int zp = lds_pos<true>(vnode);
+          T f = 0;
+#pragma unroll
+          for (int i = 0; i < AGH; ++i) {
+            const int b = vh0 + i;
+            c2<T> v = mk<T>(0, 0);
+            if (b < nbins) {
+              for (int bp = 0; bp < nbins; ++bp) {
+                const c2<T> a = A[bp * AGRS + zp];
+                const T lv = lam[b * nbins + bp];
+                v.x += lv * a.x;
+                v.y -= lv * a.y;
+              }
+              const c2<T> a = A[b * AGRS + zp];
+              f += a.x * v.x - a.y * v.y;
+            }
+            vh[i] = v;
+          }
+          Fh[tid] = f;
+        }
+        __syncthreads();
+        // node sources: S_b = w_q delta_B v_b over A; direct source w_q F into Fh[2 node]
+        if (vthread) {
+          const int zp = lds_pos<true>(vnode);
+          const T wv = W[vnode];
+#pragma unroll
+          for (int i = 0; i < AGH; ++i) {
+            const int b = vh0 + i;
+            if (b < nbins) A[b * AGRS + zp] = mk<T>(wv * vh[i].x, wv * vh[i].y);
+          }
+        }
+        __syncthreads();
+        if (tid < AGK) Fh[2 * tid] = Wq[tid] * (Fh[2 * tid] + Fh[2 * tid + 1]);
+        __syncthreads();
+        // transposed z: Qt[yh][kz][b] = sum_{tz, sz} M[sz][tz] S_b(yh, 5 (kz - tz) + sz)
+        for (int e = tid; e < AGY * GC * nbins; e += nt) {
+          const int b = e % nbins, yk = e / nbins;
+          const int yh = yk / GC, kz = yk % GC;
+          c2<T> acc = mk<T>(0, 0);
+#pragma unroll
+          for (int tz = 0; tz < 4; ++tz) {
+            const int cz = kz - tz;
+            if (cz < 0 || cz >= GT) continue;
+#pragma unroll
+            for (int sz = 0; sz < 5; ++sz) {
+              const c2<T> v = A[b * AGRS + lds_pos<true>(yh * GN + 5 * cz + sz)];
+              const T m = gq_m<T>(gq, sz, tz);
+              acc.x += m * v.x;
+              acc.y += m * v.y;
+            }
+          }
+          Qt[e] = acc;
+        }
+        for (int yk = tid; yk < AGY * GC; yk += nt) {
+          const int yh = yk / GC, kz = yk % GC;
+          T acc = 0;
+#pragma unroll
+          for (int tz = 0; tz < 4; ++tz) {
+            const int cz = kz - tz;
+            if (cz < 0 || cz >= GT) continue;
+#pragma unroll
+            for (int sz = 0; sz < 5; ++sz) acc += gq_m<T>(gq, sz, tz) * Fh[2 * (yh * GN + 5 * cz + sz)];
+          }
+          Qdt[yk] = acc;
+        }
+        __syncthreads();
+        // transposed y: Pt[cy + ty][kz][b] += sum_yh M[yh][ty] Qt[yh][kz][b]
+        for (int e = tid; e < 4 * GC * nbins; e += nt) {
+          const int b = e % nbins, tk = e / nbins;
+          const int tyy = tk / GC, kz = tk % GC;
+          c2<T> acc = mk<T>(0, 0);
+#pragma unroll
+          for (int yh = 0; yh < AGY; ++yh) {
+            const c2<T> v = Qt[(yh * GC + kz) * nbins + b];
+            const T m = gq_m<T>(gq, yh, tyy);
+            acc.x += m * v.x;
+            acc.y += m * v.y;
+          }
+          c2<T>& o = Pt[((cy + tyy) * GC + kz) * nbins + b];
+          o.x += acc.x;
+          o.y += acc.y;
+        }
+        for (int tk = tid; tk < 4 * GC; tk += nt) {
+          const int tyy = tk / GC, kz = tk % GC;
+          T acc = 0;
+#pragma unroll
+          for (int yh = 0; yh < AGY; ++yh) acc += gq_m<T>(gq, yh, tyy) * Qdt[yh * GC + kz];
+          Pdt[(cy + tyy) * GC + kz] += acc;
+        }
+      }
+      __syncthreads();
+      // transposed x: Ct[cx + tx][j][k][b] += M[sx][tx] Pt[j][k][b]
+      for (int e = tid; e < 4 * GC * GC * nbins; e += nt) {
+        const int b = e % nbins, r = e / nbins;
+        const int txx = r / (GC * GC), jk = r % (GC * GC);
+        const c2<T> v = Pt[jk * nbins + b];
+        const T m = gq_m<T>(gq, sx, txx);
+        c2<T>& o = Ct[((cx + txx) * GC * GC + jk) * nbins + b];
+        o.x += m * v.x;
+        o.y += m * v.y;
+      }
+      for (int r = tid; r < 4 * GC * GC; r += nt) {
+        const int txx = r / (GC * GC), jk = r % (GC * GC);
+        Dt[(cx + txx) * GC * GC + jk] += gq_m<T>(gq, sx, txx) * Pdt[jk];
+      }
+    }
+    __syncthreads();
+    // fold the tile into the grid (neighbouring tiles share coefficients)
+    for (int e = tid; e < NC * nbins; e += nt) {
+      const int b = e % nbins, c = e / nbins;
+      const int i = c / (GC * GC), j = (c / GC) % GC, k = c % GC;
+      const long long cell = ((long long)wrapi(x0 + i, n) * n + wrapi(y0 + j, n)) * n + wrapi(z0 + k, n);
+      c2<T>* o = cm + (long long)b * n3 + cell;
+      atomicAdd(&o->x, Ct[e].x);
+      atomicAdd(&o->y, Ct[e].y);
+    }
+    for (int c = tid; c < NC; c += nt) {
+      const int i = c / (GC * GC), j = (c / GC) % GC, k = c % GC;
+      atomicAdd(&rm[((long long)wrapi(x0 + i, n) * n + wrapi(y0 + j, n)) * n + wrapi(z0 + k, n)], wm * Dt[c]);
+    }
+  }
+}
+
 // h[mock][s] = sum_l (2l+1) sum_{b1,b2} dzeta[mock][l][b1][b2] jbar_{l,b1}(s) jbar_{l,b2}(s):
 // the weight of |dhat(q)|^2 B7hat(q) in sum_l <dzeta_l, 4 pi Fbar_l>
 template <typename T>
@@ -2450,6 +2747,43 @@ hipError_t launch_primary_dw(int prec, const long long* off, int batch, long lon
   if (prec) k_primary_dw<double><<<gr, 256, 0, st>>>(off, batch, np_total, FJ, W, SF, static_cast<double*>(dw));
   else k_primary_dw<float><<<gr, 256, 0, st>>>(off, batch, np_total, FJ, W, SF, static_cast<float*>(dw));
   return hipGetLastError();
+}
+
+hipError_t launch_gamma_adjoint(int prec, const void* fields, const void* delta, const void* lam_s, int n, int nbins,
+                                const double (*m)[4], const double* wq, double wm, int nwg, int batch, void* cout,
+                                void* direct, hipStream_t st) {
+  GammaQuad gq;
+  for (int s = 0; s < 5; ++s) {
+    for (int t = 0; t < 4; ++t) {
+      gq.m[s][t] = (float)m[s][t];
+      gq.md[s][t] = m[s][t];
+    }
+    gq.wq[s] = (float)wq[s];
+    gq.wqd[s] = wq[s];
+  }
+  const dim3 gs(nwg, batch);
+  if (nbins > 2 * AGH) return hipErrorInvalidValue;
+  if (prec) {
+    const size_t lds = GammaAdjLds<double>(nbins).total;
+    hipError_t e = allow_lds(k_gamma_adjoint<double>, lds);
+    if (e != hipSuccess) return e;
+    k_gamma_adjoint<double><<<gs, 512, lds, st>>>(static_cast<const double2*>(fields), static_cast<const double*>(delta),
+                                                  static_cast<const double*>(lam_s), n, nbins, gq, wm,
+                                                  static_cast<double2*>(cout), static_cast<double*>(direct));
+  } else {
+    const size_t lds = GammaAdjLds<float>(nbins).total;
+    hipError_t e = allow_lds(k_gamma_adjoint<float>, lds);
+    if (e != hipSuccess) return e;
+    k_gamma_adjoint<float><<<gs, 512, lds, st>>>(static_cast<const float2*>(fields), static_cast<const float*>(delta),
+                                                 static_cast<const float*>(lam_s), n, nbins, gq, (float)wm,
+                                                 static_cast<float2*>(cout), static_cast<float*>(direct));
+  }
+  return hipGetLastError();
+}
+
+size_t gamma_adjoint_lds_need(int prec, int nbins) {
+  if (nbins > 2 * AGH) return (size_t)1 << 40;
+  return prec ? GammaAdjLds<double>(nbins).total : GammaAdjLds<float>(nbins).total;
 }
 
 }  // namespace mp3

@@ -729,15 +729,86 @@ int backward_particle(mp3_plan_t p, const void* delta, const double* dzeta, void
   return MP3_OK;
 }
 
+// Adjoint of the grid summation with connection coefficients: the nodal
+// adjoint with the primary's weight delta_x and the pointwise products
+// replaced by the quadrature of the B-spline reconstructions (k_gamma_adjoint
+// produces c_b and the direct term per (l, m)); the same adjoint transforms
+// and deposit chain rule follow.
+int backward_gamma(mp3_plan_t p, const void* delta, const double* dzeta, void* ddelta, const float* pos,
+                   const float* w, const int64_t* np_off, void* dw, void* ws, size_t wsb, void* stream) {
+  if (mp3::gamma_adjoint_lds_need(p->prec, p->nbins) > kLdsLimit)
+    return fail(MP3_EUNSUPPORTED, "nbins too large for the grid-Gamma adjoint tile's LDS at this precision");
+  long long np_total = 0, np_max = 0;
+  if (dw) {
+    if (int s = check_offsets(p, np_off, &np_total, &np_max)) return s;
+    if (!pos) return fail(MP3_EINVAL, "pos is NULL while dw is requested");
+  }
+  const Layout L = layout(p, np_total);
+  if (int s = check_ws(p, ws, wsb, L.total)) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const long long n3 = (long long)p->n * p->n * p->n;
+  if (int s = forward_dft(p, delta, ws, L, st)) return s;
+  void* F = at(ws, L.fields);
+  void* Fi = at(ws, L.fields_i);
+  void* G = at(ws, L.G);
+  void* direct = at(ws, L.direct);
+  MP3_HIP(mp3::launch_fill(p->prec, G, 2 * n3 * p->batch, 0.0, st), "zero G");
+  MP3_HIP(mp3::launch_fill(p->prec, direct, n3 * p->batch, 0.0, st), "zero direct");
+  const long long tiles = (long long)(p->n / 4) * (p->n / 4) * (p->n / 4);
+  long long gwg = (long long)contract_wgs(p);
+  if (gwg > tiles) gwg = tiles;
+  for (int l = 0; l <= p->lmax; ++l) {
+    MP3_HIP(mp3::launch_lam_sym(p->prec, dzeta, at(ws, L.lam), p->nbins, l, p->lmax, p->batch, st), "lambda");
+    for (int m = 0; m <= l; ++m) {
+      const double wm = m == 0 ? 1.0 : 2.0;
+      if (int s = fields_xy(p, ws, L, F, l, m, st)) return s;
+      mp3::ZpassArgs z{};
+      z.fields = F;
+      z.tw = p->tw;
+      z.nbins = p->nbins;
+      z.nwg = L.nwg;
+      z.ppw = L.ppw;
+      z.batch = p->batch;
+      MP3_HIP(timed(p, MP3_PASS_Z_STORE, st, [&] { return mp3::launch_zpass_store(p->n, p->prec, z, Fi, st); }), "z pass (store)");
+      MP3_HIP(mp3::launch_fill(p->prec, F, 2 * n3 * p->batch * p->nbins, 0.0, st), "zero sources");
+      MP3_HIP(timed(p, MP3_PASS_GAMMA, st, [&] {
+                return mp3::launch_gamma_adjoint(p->prec, Fi, delta, at(ws, L.lam), p->n, p->nbins, p->gm, p->gw, wm,
+                                                 (int)gwg, p->batch, F, direct, st);
+              }),
+              "grid-Gamma adjoint");
+      MP3_HIP(timed(p, MP3_PASS_Z_ADJOINT, st, [&] { return mp3::launch_fft_z(p->n, p->prec, +1, F, F, p->batch * p->nbins, p->tw, st); }),
+              "adjoint z pass");
+      MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, F, p->batch * p->nbins, p->tw, p->tune[MP3_TUNE_FFT_X_PLAN], st); }),
+              "adjoint x pass");
+      mp3::FilterArgs a = filter_args(p, F, G, l, m, wm / (double)n3);
+      MP3_HIP(timed(p, MP3_PASS_ADJOINT, st, [&] { return mp3::launch_adjoint_y(p->n, p->prec, a, st); }), "adjoint window pass");
+    }
+  }
+  MP3_HIP(timed(p, MP3_PASS_DFT, st, [&] { return mp3::launch_fft3d(p->n, p->prec, -1, false, G, G, p->batch, p->tw, st); }), "adjoint final FFT");
+  MP3_HIP(mp3::launch_grad_combine(p->prec, direct, G, ddelta, n3 * p->batch, kFourPi / (double)n3, st), "combine");
+  if (dw) {
+    if (int s = upload_offsets(p, np_off, ws, L, st)) return s;
+    const long long* off = reinterpret_cast<const long long*>(at(ws, L.off));
+    double* W = reinterpret_cast<double*>(at(ws, L.W));
+    double* S = reinterpret_cast<double*>(at(ws, L.S));
+    MP3_HIP(mp3::launch_fill_f64(W, p->batch, 0.0, st), "zero W");
+    MP3_HIP(mp3::launch_fill_f64(S, p->batch, 0.0, st), "zero S");
+    MP3_HIP(mp3::launch_weight_sum(w, off, p->batch, np_max, W, st), "weight sum");
+    MP3_HIP(mp3::launch_dot_rho_g(p->prec, delta, ddelta, n3, S, p->batch, st), "dot");
+    MP3_HIP(mp3::launch_gather_dw(p->prec, pos, off, p->batch, np_total, p->n, (double)p->n / p->box, ddelta, W, S, dw, st),
+            "gather dw");
+  }
+  return MP3_OK;
+}
+
 }  // namespace
 
 int mp3_zeta_backward(mp3_plan_t p, const void* delta, const double* dzeta, void* ddelta, const float* pos,
                       const float* w, const int64_t* np_off, void* dw, void* ws, size_t wsb, void* stream) {
   if (int s = check_plan(p)) return s;
   if (!delta || !dzeta || !ddelta) return fail(MP3_EINVAL, "delta, dzeta and ddelta must not be NULL");
-  if (p->summation == MP3_SUM_GRID_GAMMA)
-    return fail(MP3_EUNSUPPORTED, "the adjoint is implemented for the nodal and particle forms");
   if (p->summation == MP3_SUM_PARTICLE) return backward_particle(p, delta, dzeta, ddelta, pos, w, np_off, dw, ws, wsb, stream);
+  if (p->summation == MP3_SUM_GRID_GAMMA) return backward_gamma(p, delta, dzeta, ddelta, pos, w, np_off, dw, ws, wsb, stream);
   long long np_total = 0, np_max = 0;
   if (dw) {
     if (int s = check_offsets(p, np_off, &np_total, &np_max)) return s;

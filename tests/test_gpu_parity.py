@@ -235,9 +235,10 @@ def test_invalid_arguments_raise(mp3):
         pp.zeta(d)                                # catalogue missing
     with pytest.raises(ValueError):
         pp.zeta_backward(d, torch.zeros((1, 2, 1, 1), dtype=torch.float64, device="cuda"))   # catalogue missing
-    pg = mp3.Plan(16, 100.0, 1, [10.0, 20.0], summation="gamma")
+    pg = mp3.Plan(16, 100.0, 1, np.linspace(10.0, 40.0, 13), precision="f64", summation="gamma")
+    dd = torch.zeros((1, 16, 16, 16), dtype=torch.float64, device="cuda")
     with pytest.raises(mp3.Mp3Error):
-        pg.zeta_backward(d, torch.zeros((1, 2, 1, 1), dtype=torch.float64, device="cuda"))   # no grid-Gamma adjoint
+        pg.zeta_backward(dd, torch.zeros((1, 2, 12, 12), dtype=torch.float64, device="cuda"))   # adjoint tile LDS
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -410,3 +411,45 @@ def test_zeta_20_bins_matrix_cores(mp3, summation):
     e = assert_zeta_close(z, ref, 1e-4)
     print("per-l errors", e)
     assert np.abs(z - z.transpose(0, 2, 1)).max() <= 1e-12 * np.abs(z).max()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n,lmax,nb", [(16, 2, 3), (16, 3, 6), (32, 2, 4)])
+def test_backward_gamma(mp3, prec, n, lmax, nb):
+    """Grid-Gamma gradient (dJ/ddelta and dJ/dw through the deposit) against the oracle's."""
+    _say("backward gamma", prec, n, lmax, nb)
+    box = 8.0 * n
+    edges = np.linspace(0.06 * box, 0.35 * box, nb + 1)
+    pos, w = lognormal_catalogue(n, box, 6000, 0.04 * box, 700 + n, 701 + n, 702 + n, (0.5, 1.5))
+    lam = np.random.default_rng(703 + n + nb).standard_normal((1, lmax + 1, nb, nb))
+    plan = mp3.Plan(n, box, lmax, edges, precision=prec, summation="gamma")
+    pt, wt = _dev(pos, torch.float32), _dev(w, torch.float32)
+    delta = plan.deposit(pt, wt)
+    g, dw = plan.zeta_backward(delta, _dev(lam, torch.float64), pt, wt)
+    g, dw = g.cpu().numpy()[0], dw.cpu().numpy()
+    dref = basis.density_contrast(basis.deposit(pos, w, n, box), float(np.sum(w.astype(np.float64))))
+    gref = A.zeta_gamma_grad(E.Plan(n, box, lmax, edges), dref, lam[0])
+    dwref = A.deposit_weight_grad(pos, w, n, box, gref)
+    eg = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    ew = np.linalg.norm(dw - dwref) / np.linalg.norm(dwref)
+    print("grad errors", eg, ew)
+    assert eg <= TOL[prec] and ew <= TOL[prec], (eg, ew)
+
+
+def test_backward_gamma_20_bins_autograd(mp3):
+    """20 bins (the largest float32 adjoint tile) through the autograd wrapper of the catalogue."""
+    _say("backward gamma 20 bins")
+    n, box, lmax, nb = 16, 160.0, 1, 20
+    edges = np.linspace(10.0, 60.0, nb + 1)
+    pos, w = lognormal_catalogue(n, box, 4000, 6.0, 710, 711, 712, (0.5, 1.5))
+    lam = np.random.default_rng(713).standard_normal((1, lmax + 1, nb, nb))
+    plan = mp3.Plan(n, box, lmax, edges, precision="f32", summation="gamma")
+    pt = _dev(pos, torch.float32)
+    wt = _dev(w, torch.float32).requires_grad_(True)
+    z = mp3.zeta_from_catalogue(plan, pt, wt)
+    (z * _dev(lam, torch.float64)).sum().backward()
+    dref = basis.density_contrast(basis.deposit(pos, w, n, box), float(np.sum(w.astype(np.float64))))
+    gref = A.zeta_gamma_grad(E.Plan(n, box, lmax, edges), dref, lam[0])
+    dwref = A.deposit_weight_grad(pos, w, n, box, gref)
+    got = wt.grad.cpu().numpy()
+    assert np.linalg.norm(got - dwref) <= 1e-4 * np.linalg.norm(dwref)

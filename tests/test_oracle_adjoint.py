@@ -126,3 +126,39 @@ def test_particle_grad_subset_equals_masked_full():
     g_sub, dw_sub = A.zeta_particle_grad(plan, pos, w, lam[np.ix_(ls, bins, bins)], ls=ls, bins=bins)
     assert np.abs(g_full - g_sub).max() <= 1e-12 * np.abs(g_full).max()
     assert np.abs(dw_full - dw_sub).max() <= 1e-12 * np.abs(dw_full).max()
+
+
+def test_gamma_grad_matches_finite_differences():
+    """dJ/ddelta of the grid summation with connection coefficients against central differences."""
+    n = 8
+    delta = random_field(n, 41)
+    plan = E.Plan(n, 100.0, 2, np.linspace(5.0, 40.0, 4))
+    lam = np.random.default_rng(42).standard_normal((plan.lmax + 1, plan.nbins, plan.nbins))
+    g = A.zeta_gamma_grad(plan, delta, lam)
+    rng = np.random.default_rng(43)
+    for _ in range(3):
+        v = rng.standard_normal(delta.shape)
+        v /= np.sqrt(np.mean(v * v))
+        h = 1e-4
+        fd = (A.zeta_gamma_objective(plan, delta + h * v, lam)
+              - A.zeta_gamma_objective(plan, delta - h * v, lam)) / (2 * h)
+        assert abs(fd - np.sum(g * v)) < 1e-7 * abs(fd)
+
+
+def test_gamma_grad_with_point_stencil_is_nodal():
+    """With Gamma(s,t) replaced by delta_{s0} delta_{t0} the gradient is the nodal one (structure check)."""
+    from oracle import basis as B
+    n = 8
+    delta = random_field(n, 44)
+    plan = E.Plan(n, 100.0, 1, np.linspace(5.0, 40.0, 3))
+    lam = np.random.default_rng(45).standard_normal((plan.lmax + 1, plan.nbins, plan.nbins))
+    point = np.zeros((7, 7))
+    point[3, 3] = 1.0
+    orig = B.gamma_matrix
+    try:
+        B.gamma_matrix = lambda: point
+        g = A.zeta_gamma_grad(plan, delta, lam)
+    finally:
+        B.gamma_matrix = orig
+    gn = A.zeta_nodal_grad(plan, delta, lam)
+    assert np.abs(g - gn).max() <= 1e-12 * np.abs(gn).max()
