@@ -1767,7 +1767,8 @@ __global__ void __launch_bounds__(256) k_scatter_source(const int* tcell, const 
 constexpr int AGY = 5;                      // y nodes per adjoint slice (one y cell)
 constexpr int AGK = AGY * GN;               // nodes per slice (100)
 constexpr int AGRS = AGK + AGK / 16 + 1;
-constexpr int AGH = 10;                     // bins per half in the per-node step
+constexpr int AGH = 4;                      // bins per thread in the per-node step
+constexpr int AGP = 5;                      // threads per node in that step (AGP * AGH >= bins)
 
 template <typename T>
 struct GammaAdjLds {
@@ -1791,7 +1792,7 @@ struct GammaAdjLds {
     A = take((size_t)nbins * AGRS * c);
     W = take((size_t)AGK * r);
     Wq = take((size_t)AGK * r);
-    Fh = take((size_t)2 * AGK * r);
+    Fh = take((size_t)AGP * AGK * r);
     lam = take((size_t)nbins * nbins * r);
     total = o;
   }
@@ -1919,23 +1920,30 @@ __global__ void __launch_bounds__(512) k_gamma_adjoint(const c2<T>* fields, cons
           Wq[node] = wq;
         }
         __syncthreads();
-        // per node and half of the bins: v_b = sum_b' lam_s[b][b'] conj(a_b'), F
+        // per node and AGH bins: v_b = sum_b' lam_s[b][b'] conj(a_b'), F; the
+        // node's field values are read from LDS once into registers
         c2<T> vh[AGH];
-        const bool vthread = tid < 2 * AGK;
-        const int vnode = tid >> 1, vh0 = (tid & 1) * AGH;
+        const bool vthread = tid < AGP * AGK;
+        const int vnode = tid / AGP, vh0 = (tid % AGP) * AGH;
         if (vthread) {
           const int zp = lds_pos<true>(vnode);
+          c2<T> av[AGP * AGH];
+#pragma unroll
+          for (int bp = 0; bp < AGP * AGH; ++bp) av[bp] = bp < nbins ? A[bp * AGRS + zp] : mk<T>(0, 0);
           T f = 0;
 #pragma unroll
           for (int i = 0; i < AGH; ++i) {
             const int b = vh0 + i;
             c2<T> v = mk<T>(0, 0);
             if (b < nbins) {
-              for (int bp = 0; bp < nbins; ++bp) {
-                const c2<T> a = A[bp * AGRS + zp];
-                const T lv = lam[b * nbins + bp];
-                v.x += lv * a.x;
-                v.y -= lv * a.y;
+              const T* lrow = lam + b * nbins;
+#pragma unroll
+              for (int bp = 0; bp < AGP * AGH; ++bp) {
+                if (bp < nbins) {
+                  const T lv = lrow[bp];
+                  v.x += lv * av[bp].x;
+                  v.y -= lv * av[bp].y;
+                }
               }
               const c2<T> a = A[b * AGRS + zp];
               f += a.x * v.x - a.y * v.y;
@@ -1945,7 +1953,7 @@ __global__ void __launch_bounds__(512) k_gamma_adjoint(const c2<T>* fields, cons
           Fh[tid] = f;
         }
         __syncthreads();
-        // node sources: S_b = w_q delta_B v_b over A; direct source w_q F into Fh[2 node]
+        // node sources: S_b = w_q delta_B v_b over A; direct source w_q F into Fh[AGP node]
         if (vthread) {
           const int zp = lds_pos<true>(vnode);
           const T wv = W[vnode];
@@ -1956,7 +1964,12 @@ __global__ void __launch_bounds__(512) k_gamma_adjoint(const c2<T>* fields, cons
           }
         }
         __syncthreads();
-        if (tid < AGK) Fh[2 * tid] = Wq[tid] * (Fh[2 * tid] + Fh[2 * tid + 1]);
+        if (tid < AGK) {
+          T f = 0;
+#pragma unroll
+          for (int q = 0; q < AGP; ++q) f += Fh[AGP * tid + q];
+          Fh[AGP * tid] = Wq[tid] * f;
+        }
         __syncthreads();
         // transposed z: Qt[yh][kz][b] = sum_{tz, sz} M[sz][tz] S_b(yh, 5 (kz - tz) + sz)
         for (int e = tid; e < AGY * GC * nbins; e += nt) {
@@ -1985,7 +1998,7 @@ __global__ void __launch_bounds__(512) k_gamma_adjoint(const c2<T>* fields, cons
             const int cz = kz - tz;
             if (cz < 0 || cz >= GT) continue;
 #pragma unroll
-            for (int sz = 0; sz < 5; ++sz) acc += gq_m<T>(gq, sz, tz) * Fh[2 * (yh * GN + 5 * cz + sz)];
+            for (int sz = 0; sz < 5; ++sz) acc += gq_m<T>(gq, sz, tz) * Fh[AGP * (yh * GN + 5 * cz + sz)];
           }
           Qdt[yk] = acc;
         }
@@ -2762,7 +2775,7 @@ hipError_t launch_gamma_adjoint(int prec, const void* fields, const void* delta,
     gq.wqd[s] = wq[s];
   }
   const dim3 gs(nwg, batch);
-  if (nbins > 2 * AGH) return hipErrorInvalidValue;
+  if (nbins > AGP * AGH) return hipErrorInvalidValue;
   if (prec) {
     const size_t lds = GammaAdjLds<double>(nbins).total;
     hipError_t e = allow_lds(k_gamma_adjoint<double>, lds);
@@ -2782,7 +2795,7 @@ hipError_t launch_gamma_adjoint(int prec, const void* fields, const void* delta,
 }
 
 size_t gamma_adjoint_lds_need(int prec, int nbins) {
-  if (nbins > 2 * AGH) return (size_t)1 << 40;
+  if (nbins > AGP * AGH) return (size_t)1 << 40;
   return prec ? GammaAdjLds<double>(nbins).total : GammaAdjLds<float>(nbins).total;
 }
 

@@ -90,6 +90,20 @@ def case_gamma_256():
     return dict(workload=wl.name, ls=ls, bins=bins, zeta=z.tolist())
 
 
+def case_gamma_256_grad():
+    wl = WORKLOADS["box2000_n256_l10"]
+    ls, bins = [0], [0, 19]
+    pos, w = workload_catalogue(wl)
+    say("gamma_256_grad deposit")
+    delta = contrast(pos, w, wl.n, wl.box)
+    idx = node_sample(wl.n, 8104)
+    lam = nodal_lam(len(ls), len(bins), 8105)
+    say("gamma_256_grad gradient")
+    g = A.zeta_gamma_grad(E.Plan(wl.n, wl.box, wl.lmax, wl.edges), delta, lam, ls=ls, bins=bins)
+    return dict(workload=wl.name, ls=ls, bins=bins, lam=lam.tolist(), nodes=idx.tolist(),
+                grad=g.ravel()[idx].tolist(), grad_max=float(np.abs(g).max()))
+
+
 def case_batch64():
     wl = WORKLOADS["batch64_n128_l8"]
     ls, bins = [0, 8], [0, 11]
@@ -115,6 +129,7 @@ CASES = {
     "particle_512": lambda: case_particle("box3000_n512_l10", [0], [0, 19]),
     "particle_128": lambda: case_particle("box1000_n128_l10", [0, 2, 10], [0, 7, 14]),
     "gamma_256": case_gamma_256,
+    "gamma_256_grad": case_gamma_256_grad,
     "batch64": case_batch64,
 }
 
