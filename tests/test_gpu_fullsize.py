@@ -154,6 +154,26 @@ def test_gamma_256(mp3):
     assert np.abs(z - z.transpose(0, 2, 1)).max() <= 1e-12 * np.abs(z).max()
 
 
+def test_gamma_256_gradient(mp3):
+    """box 2000, 256^3, L = 10, 20 bins: the grid-Gamma adjoint (float32) at the oracle's sampled nodes."""
+    g = _golden("gamma_256_grad")
+    wl = WORKLOADS[g["workload"]]
+    nodes = np.asarray(g["nodes"])
+    _say("gamma 256 gradient: mock")
+    pos, w = workload_catalogue(wl)
+    pt, wt = _dev(pos, torch.float32), _dev(w, torch.float32)
+    # only l = 0 enters J, so a plan with lmax = 0 has the same gradient (and 1/66 of the work)
+    assert g["ls"] == [0]
+    lam = np.zeros((1, 1, wl.nbins, wl.nbins))
+    lam[0, 0][np.ix_(g["bins"], g["bins"])] = np.asarray(g["lam"][0])
+    lam = _dev(lam, torch.float64)
+    _say("gamma 256 gradient: GPU f32")
+    plan = mp3.Plan(wl.n, wl.box, 0, wl.edges, precision="f32", summation="gamma")
+    gr, _ = plan.zeta_backward(plan.deposit(pt, wt), lam)
+    e = _samples_close(gr.cpu().numpy()[0].ravel()[nodes], g["grad"], g["grad_max"], 1e-4)
+    _say("gamma 256 gradient: max sampled error / max |grad|", e)
+
+
 def test_batch64_forward_and_weight_gradient(mp3):
     """64 mocks of 2e5..1e6 particles, 128^3, L = 8, 12 bins, float32, one call per step."""
     g = _golden("batch64")
