@@ -129,8 +129,10 @@ def zeta_nodal(plan: Plan, delta: np.ndarray, ls=None, bins=None) -> np.ndarray:
     return np.array(out)
 
 
-def _check_real(z):
-    scale = max(np.abs(z).max(), 1e-300)
+def _check_real(z, floor: float = 0.0):
+    """The m-sum must be real up to rounding; ``floor`` is the size of the summed
+    terms for sums that cancel exactly (then |z| itself is rounding noise)."""
+    scale = max(np.abs(z).max(), floor, 1e-300)
     if np.abs(z.imag).max() > 1e-9 * scale:
         raise AssertionError(f"zeta has an imaginary part {np.abs(z.imag).max():.3e} (scale {scale:.3e})")
 
@@ -281,11 +283,13 @@ def zeta_particle(plan: Plan, pos, w, ls=None, bins=None, mode: str = "delta", d
     out = []
     for l in plan.ls(ls):
         z = 0.0
+        floor = 0.0
         for m in range(-l, l + 1):
             A = fields(plan, dhat, l, m, bins)
             At = basis.gather(A, pos, n, box)                 # [nb, P]
             z = z + (At * (w / W)) @ At.conj().T
-        _check_real(z)
+            floor += float(np.abs(A).max()) ** 2
+        _check_real(z, floor)
         z = z.real
         if mode == "delta":
             z = z - volume_mean_pair(plan, dhat, l, bins)

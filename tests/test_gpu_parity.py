@@ -453,3 +453,53 @@ def test_backward_gamma_20_bins_autograd(mp3):
     dwref = A.deposit_weight_grad(pos, w, n, box, gref)
     got = wt.grad.cpu().numpy()
     assert np.linalg.norm(got - dwref) <= 1e-4 * np.linalg.norm(dwref)
+
+
+def test_extreme_orders_and_bins(mp3):
+    """The largest multipole order (L = 20) and the largest bin count (64, vector-ALU contraction and adjoint)."""
+    _say("extremes")
+    n, box = 16, 160.0
+    delta = random_field(n, 800)
+    # L = 20, 2 bins, float64
+    edges = np.array([20.0, 40.0, 60.0])
+    plan = mp3.Plan(n, box, 20, edges, precision="f64")
+    z = plan.zeta(_dev(delta[None], torch.float64)).cpu().numpy()[0]
+    assert_zeta_close(z, E.zeta_nodal(E.Plan(n, box, 20, edges), delta), 1e-10)
+    # 64 bins, L = 1, float32 forward and gradient
+    edges = np.linspace(5.0, 70.0, 65)
+    op = E.Plan(n, box, 1, edges)
+    plan = mp3.Plan(n, box, 1, edges, precision="f32")
+    d = _dev(delta[None], torch.float32)
+    z = plan.zeta(d).cpu().numpy()[0]
+    assert_zeta_close(z, E.zeta_nodal(op, delta), 1e-4)
+    lam = np.random.default_rng(801).standard_normal((1, 2, 64, 64))
+    g, _ = plan.zeta_backward(d, _dev(lam, torch.float64))
+    gref = A.zeta_nodal_grad(op, delta, lam[0])
+    assert np.linalg.norm(g.cpu().numpy()[0] - gref) <= 1e-4 * np.linalg.norm(gref)
+
+
+@pytest.mark.parametrize("summation", ["nodal", "gamma", "particle"])
+def test_degenerate_inputs(mp3, summation):
+    """A zero contrast gives zeta = 0 and a zero gradient; a one-particle catalogue deposits exactly."""
+    _say("degenerate", summation)
+    n, box, lmax = 16, 160.0, 2
+    edges = np.linspace(15.0, 55.0, 4)
+    plan = mp3.Plan(n, box, lmax, edges, precision="f64", summation=summation)
+    lam = _dev(np.ones((1, lmax + 1, 3, 3)), torch.float64)
+    # one particle at a node: delta = B3 stencil * n^3 - 1, exactly
+    pos = np.array([[50.0, 70.0, 90.0]], dtype=np.float32)
+    pt = _dev(pos, torch.float32)
+    d = plan.deposit(pt)
+    ref = basis.density_contrast(basis.deposit(pos, None, n, box), 1.0)
+    assert np.abs(d.cpu().numpy()[0] - ref).max() <= 1e-12 * np.abs(ref).max()
+    if summation == "particle":
+        # a lone particle at a node: by the blob's cubic symmetry F_l(u) = 0 for l = 1, 2,
+        # so zeta_{l>0} is minus the volume mean alone
+        z = plan.zeta(d, pt).cpu().numpy()[0]
+        assert_zeta_close(z, E.zeta_particle(E.Plan(n, box, lmax, edges), pos, None), 1e-10)
+        return
+    zero = torch.zeros((1, n, n, n), dtype=torch.float64, device="cuda")
+    z = plan.zeta(zero).cpu().numpy()
+    assert np.all(z == 0.0)
+    g, _ = plan.zeta_backward(zero, lam)
+    assert torch.count_nonzero(g).item() == 0
