@@ -1097,8 +1097,10 @@ struct GammaLds {
   }
 };
 
+// 1024 threads: the per-node phases are short, and one workgroup fills the
+// CU's LDS, so the waves of that one workgroup are what hides LDS latency
 template <typename T, bool MF, bool SPLIT = false, bool QUAD = false>
-__global__ void __launch_bounds__(512) k_gamma_contract(const c2<T>* fields, const T* delta, int n, int nbins,
+__global__ void __launch_bounds__(1024) k_gamma_contract(const c2<T>* fields, const T* delta, int n, int nbins,
                                                          GammaQuad gq, double* partials) {
   extern __shared__ __align__(16) char smem[];
   const GammaLds<T> L(nbins);
@@ -1798,8 +1800,10 @@ struct GammaAdjLds {
   }
 };
 
+// float: 1024 threads, for the same reason as k_gamma_contract; double needs
+// more than the 128 registers a 1024-thread workgroup leaves each lane
 template <typename T>
-__global__ void __launch_bounds__(512) k_gamma_adjoint(const c2<T>* fields, const T* delta, const T* lam_s, int n,
+__global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) k_gamma_adjoint(const c2<T>* fields, const T* delta, const T* lam_s, int n,
                                                         int nbins, GammaQuad gq, T wm, c2<T>* cout, T* direct) {
   extern __shared__ __align__(16) char smem[];
   const GammaAdjLds<T> L(nbins);
@@ -2640,7 +2644,7 @@ hipError_t launch_fbar_subtract(int prec, const double* P, const void* jtab, int
 template <typename T, bool MF, bool SPLIT = false, bool QUAD = false>
 hipError_t gamma_contract_t(const void* fields, const void* delta, int n, int nbins, const GammaQuad& gq,
                             double* partials, int nwg, int batch, hipStream_t st) {
-  const int threads = 512;
+  const int threads = 1024;
   size_t lds = GammaLds<T>(nbins).total;
   const size_t red = Contractor<T, MF, SPLIT, QUAD>::scratch_bytes(threads);
   if (lds < red) lds = red;
@@ -2787,7 +2791,7 @@ hipError_t launch_gamma_adjoint(int prec, const void* fields, const void* delta,
     const size_t lds = GammaAdjLds<float>(nbins).total;
     hipError_t e = allow_lds(k_gamma_adjoint<float>, lds);
     if (e != hipSuccess) return e;
-    k_gamma_adjoint<float><<<gs, 512, lds, st>>>(static_cast<const float2*>(fields), static_cast<const float*>(delta),
+    k_gamma_adjoint<float><<<gs, 1024, lds, st>>>(static_cast<const float2*>(fields), static_cast<const float*>(delta),
                                                  static_cast<const float*>(lam_s), n, nbins, gq, (float)wm,
                                                  static_cast<float2*>(cout), static_cast<float*>(direct));
   }
