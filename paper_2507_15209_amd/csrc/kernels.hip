@@ -49,6 +49,22 @@ template <int N, typename T> constexpr int contig_pencils() {
 template <int N, typename T, int V = 0> constexpr int strided_threads() {
   return Fft<N, V>::TPC * zc_of<T>() * tiles_per_wg<N, T, V>();
 }
+// rows of the plain strided transforms (x pass, y and 3-D transforms): 256
+// contiguous bytes, which HBM serves measurably faster than 128 in the
+// in-place x pass, capped by N, 1024 threads and 64 KB of static LDS
+template <int N, typename T, int V = 0> constexpr int zcx_of() {
+  int z = 256 / (int)sizeof(c2<T>);
+  if (z > N) z = N;
+  while (z > 1 && (z * Fft<N, V>::TPC > 1024 || (long long)z * N * (long long)sizeof(c2<T>) > 65536)) z /= 2;
+  return z;
+}
+template <int N, typename T, int V = 0> constexpr int tiles_x() {
+  constexpr int t = Fft<N, V>::TPC * zcx_of<N, T, V>();
+  return t >= 256 ? 1 : 256 / t;
+}
+template <int N, typename T, int V = 0> constexpr int strided_threads_x() {
+  return Fft<N, V>::TPC * zcx_of<N, T, V>() * tiles_x<N, T, V>();
+}
 // plan variants by kernel (measured): radix 8 for the window passes and the
 // nodal z pass, radix 16 for the adjoint z pass
 constexpr int VB = 1;
@@ -278,11 +294,11 @@ __global__ void k_gather_dw(const float* pos, const long long* off, int batch, l
 // FFT along a strided axis (x: astride = N^2, outer = N; y: astride = N, outer = N^2)
 // ---------------------------------------------------------------------------
 template <int N, typename T, int DIR, bool REAL_IN, int V = 0>
-__global__ void __launch_bounds__((strided_threads<N, T, V>())) k_fft_strided(const void* in, c2<T>* out, long long fstride_in,
+__global__ void __launch_bounds__((strided_threads_x<N, T, V>())) k_fft_strided(const void* in, c2<T>* out, long long fstride_in,
                                                        long long fstride_out, int astride, int outer, const c2<T>* tw) {
   using F = Fft<N, V>;
-  constexpr int ZC = zc_of<T>();
-  constexpr int G = tiles_per_wg<N, T, V>();
+  constexpr int ZC = zcx_of<N, T, V>();
+  constexpr int G = tiles_x<N, T, V>();
   constexpr int RMAX = F::RMAX;
   __shared__ c2<T> lds[G * N * ZC];
   const int tid = threadIdx.x;
@@ -2151,8 +2167,8 @@ template <typename T> using CT = c2<T>;
 
 template <int N, typename T>
 hipError_t fft3d_t(int dir, bool real_in, const void* in, void* out, int nfields, const void* tw, hipStream_t st) {
-  constexpr int ZC = zc_of<T>();
-  constexpr int G = tiles_per_wg<N, T>();
+  constexpr int ZC = zcx_of<N, T>();
+  constexpr int G = tiles_x<N, T>();
   constexpr int threads = Fft<N>::TPC * ZC * G;
   constexpr long long N3 = (long long)N * N * N;
   const dim3 gs((N * (N / ZC) + G - 1) / G, nfields);
@@ -2178,8 +2194,8 @@ hipError_t fft3d_t(int dir, bool real_in, const void* in, void* out, int nfields
 
 template <int N, typename T, int V>
 hipError_t fft_x_v(int dir, void* buf, int nfields, const void* tw, hipStream_t st) {
-  constexpr int ZC = zc_of<T>();
-  constexpr int G = tiles_per_wg<N, T, V>();
+  constexpr int ZC = zcx_of<N, T, V>();
+  constexpr int G = tiles_x<N, T, V>();
   constexpr int threads = Fft<N, V>::TPC * ZC * G;
   constexpr long long N3 = (long long)N * N * N;
   const dim3 gs((N * (N / ZC) + G - 1) / G, nfields);
@@ -2197,8 +2213,8 @@ hipError_t fft_x_t(int dir, void* buf, int nfields, const void* tw, int variant,
 
 template <int N, typename T>
 hipError_t fft_y_t(int dir, void* buf, int nfields, const void* tw, hipStream_t st) {
-  constexpr int ZC = zc_of<T>();
-  constexpr int G = tiles_per_wg<N, T>();
+  constexpr int ZC = zcx_of<N, T>();
+  constexpr int G = tiles_x<N, T>();
   constexpr int threads = Fft<N>::TPC * ZC * G;
   constexpr long long N3 = (long long)N * N * N;
   const dim3 gs((N * (N / ZC) + G - 1) / G, nfields);
