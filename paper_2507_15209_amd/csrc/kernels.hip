@@ -66,10 +66,11 @@ template <int N, typename T, int V = 0> constexpr int strided_threads_x() {
   return Fft<N, V>::TPC * zcx_of<N, T, V>() * tiles_x<N, T, V>();
 }
 // plan variants by kernel (measured): radix 8 for the window passes and the
-// nodal z pass, radix 16 for the adjoint z pass
+// nodal z pass; the adjoint z pass takes radix 16 in float32 and radix 8 in
+// float64 (radix 16 spills there)
 constexpr int VB = 1;
 constexpr int VZN = 1;   // nodal z pass
-constexpr int VZA = 0;   // adjoint z pass
+template <typename T> constexpr int VZA = std::is_same<T, double>::value ? 1 : 0;   // adjoint z pass
 
 __device__ __forceinline__ int sfreq(int i, int n) { return i < n / 2 ? i : i - n; }
 
@@ -79,7 +80,7 @@ __device__ __forceinline__ int sfreq(int i, int n) { return i < n / 2 ? i : i - 
 // (Condon-Shortley phase), which has no singularity at the poles.  At q = 0
 // the direction is taken along +z (only m = 0 survives; the radial window
 // then decides: jbar_{l>0}(0) = 0).
-__device__ double2 ylm_conj_il(int qx, int qy, int qz, int l, int m, double norm, double scale) {
+__device__ double2 ylm_conj_il(int qx, int qy, int qz, int l, int m, double norm, double scale, const YlmRec& yr) {
   const double q2 = (double)qx * qx + (double)qy * qy + (double)qz * qz;
   double x = 1.0, sre = 0.0, sim = 0.0;
   if (q2 > 0.0) {
@@ -88,13 +89,12 @@ __device__ double2 ylm_conj_il(int qx, int qy, int qz, int l, int m, double norm
     sre = qx * inv;
     sim = -qy * inv;
   }
-  double pmm = 1.0;
-  for (int k = 1; k <= m; ++k) pmm *= -(2.0 * k - 1.0);
+  const double pmm = yr.pmm;
   double q = pmm;
   if (l > m) {
     double p0 = pmm, p1 = x * (2.0 * m + 1.0) * pmm;
     for (int ll = m + 2; ll <= l; ++ll) {
-      const double p2 = ((2.0 * ll - 1.0) * x * p1 - (ll + m - 1.0) * p0) / (double)(ll - m);
+      const double p2 = yr.c1[ll] * x * p1 - yr.c2[ll] * p0;
       p0 = p1;
       p1 = p2;
     }
@@ -122,12 +122,12 @@ __device__ double2 ylm_conj_il(int qx, int qy, int qz, int l, int m, double norm
 // Nyquist planes set to zero; also returns |q|^2 for the radial table
 template <typename T>
 __device__ __forceinline__ c2<T> window_angular(int ix, int iy, int iz, int n, int l, int m, double norm,
-                                                double scale, int& q2) {
+                                                double scale, const YlmRec& yr, int& q2) {
   const int qx = sfreq(ix, n), qy = sfreq(iy, n), qz = sfreq(iz, n);
   q2 = qx * qx + qy * qy + qz * qz;
   const int h = -n / 2;
   if (qx == h || qy == h || qz == h) return mk<T>((T)0, (T)0);
-  const double2 f = ylm_conj_il(qx, qy, qz, l, m, norm, scale);
+  const double2 f = ylm_conj_il(qx, qy, qz, l, m, norm, scale, yr);
   return mk<T>((T)f.x, (T)f.y);
 }
 
@@ -362,7 +362,7 @@ template <int N, typename T>
 __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_filter_y(const c2<T>* dhat, c2<T>* fields,
                                                                          const T* jtab, int nq2, int nbins, int nbp,
                                                                          int l, int m, double norm, double scale,
-                                                                         const c2<T>* tw) {
+                                                                         const c2<T>* tw, YlmRec yr) {
   using F = Fft<N, VB>;
   constexpr int ZC = zc_of<T>();
   constexpr int G = tiles_per_wg<N, T, VB>();
@@ -388,7 +388,7 @@ __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_filter_y(cons
   for (int r = 0; r < RMAX; ++r) {
     const int qy = F::in_index(j, r);
     const c2<T> d = active ? dhat[mock * N3 + ((long long)qx * N + qy) * N + qz] : mk<T>(0, 0);
-    const c2<T> f = window_angular<T>(qx, qy, qz, N, l, m, norm, scale, q2[r]);
+    const c2<T> f = window_angular<T>(qx, qy, qz, N, l, m, norm, scale, yr, q2[r]);
     v0[r] = cmul<T>(d, f);
   }
   // radial window of this thread's elements, four bins per load, one quad ahead
@@ -1300,7 +1300,7 @@ __global__ void k_reduce_partials(const double* partials, int nwg, int nb2, doub
 template <int N, typename T, int MAXNB>
 __global__ void __launch_bounds__(512) k_zpass_adjoint(c2<T>* fields, const T* delta, const T* __restrict__ lam_s,
                                                         T* direct, int nbins, T wm, int ppw, const c2<T>* tw) {
-  using F = Fft<N, VZA>;
+  using F = Fft<N, VZA<T>>;
   constexpr int RS = zrow<N>();
   constexpr int NBP = (MAXNB + 3) / 4 * 4;
   constexpr long long N3 = (long long)N * N * N;
@@ -1322,10 +1322,10 @@ __global__ void __launch_bounds__(512) k_zpass_adjoint(c2<T>* fields, const T* d
   c2<T>* fmock = fields + mock * nbins * N3;
   const T* dmock = delta + mock * N3;
   T* rmock = direct + mock * N3;
-  c2<T> vpre[prefetch_rounds<N, VZA>()][F::RMAX];
+  c2<T> vpre[prefetch_rounds<N, VZA<T>>()][F::RMAX];
   T dpre[DPRE], rpre[DPRE];
   if (p0 < p1) {
-    prefetch_pencil<N, T, VZA>(fmock + (long long)p0 * N, N3, nbins, vpre);
+    prefetch_pencil<N, T, VZA<T>>(fmock + (long long)p0 * N, N3, nbins, vpre);
     prefetch_delta<N, T>(dmock + (long long)p0 * N, dpre);
     prefetch_delta<N, T>(rmock + (long long)p0 * N, rpre);
   }
@@ -1333,9 +1333,9 @@ __global__ void __launch_bounds__(512) k_zpass_adjoint(c2<T>* fields, const T* d
     c2<T>* fbase = fmock + (long long)p * N;
     // this pencil's data moves to vcur; the next pencil's loads are issued
     // before the transform so they stay in flight for the whole iteration
-    c2<T> vcur[prefetch_rounds<N, VZA>()][F::RMAX];
+    c2<T> vcur[prefetch_rounds<N, VZA<T>>()][F::RMAX];
 #pragma unroll
-    for (int q = 0; q < prefetch_rounds<N, VZA>(); ++q)
+    for (int q = 0; q < prefetch_rounds<N, VZA<T>>(); ++q)
 #pragma unroll
       for (int r = 0; r < F::RMAX; ++r) vcur[q][r] = vpre[q][r];
     T dcur[DPRE], rcur[DPRE];
@@ -1345,11 +1345,11 @@ __global__ void __launch_bounds__(512) k_zpass_adjoint(c2<T>* fields, const T* d
       rcur[k] = rpre[k];
     }
     if (p + 1 < p1) {
-      prefetch_pencil<N, T, VZA>(fbase + N, N3, nbins, vpre);
+      prefetch_pencil<N, T, VZA<T>>(fbase + N, N3, nbins, vpre);
       prefetch_delta<N, T>(dmock + (long long)(p + 1) * N, dpre);
       prefetch_delta<N, T>(rmock + (long long)(p + 1) * N, rpre);
     }
-    transform_pencil_bins<N, T, VZA>(fbase, N3, nbins, A, tws, vcur);
+    transform_pencil_bins<N, T, VZA<T>>(fbase, N3, nbins, A, tws, vcur);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < DPRE; ++k) {
@@ -1401,7 +1401,7 @@ __global__ void __launch_bounds__(512) k_zpass_adjoint(c2<T>* fields, const T* d
         for (int r = 0; r < F::RMAX; ++r) v[r] = A[b * RS + lds_pos<true>(F::in_index(j, r))];
       }
       __syncthreads();
-      fft_column<N, +1, T, true, VZA>(v, A + (active ? b : 0) * RS, 1, j, tws, active);
+      fft_column<N, +1, T, true, VZA<T>>(v, A + (active ? b : 0) * RS, 1, j, tws, active);
       if (active) {
 #pragma unroll
         for (int e = 0; e < F::RMAX; ++e) fbase[b * N3 + F::out_index(j, e)] = v[e];
@@ -1430,7 +1430,7 @@ template <int N, typename T>
 __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_adjoint_y(const c2<T>* fields, c2<T>* G,
                                                                           const T* jtab, int nq2, int nbins, int nbp,
                                                                           int l, int m, double norm, double scale,
-                                                                          const c2<T>* tw) {
+                                                                          const c2<T>* tw, YlmRec yr) {
   using F = Fft<N, VB>;
   constexpr int ZC = zc_of<T>();
   constexpr int GT = tiles_per_wg<N, T, VB>();
@@ -1455,7 +1455,7 @@ __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_adjoint_y(con
 #pragma unroll
   for (int e = 0; e < RMAX; ++e) {
     acc[e] = mk<T>(0, 0);
-    fac[e] = window_angular<T>(qx, F::out_index(j, e), qz, N, l, m, norm, scale, q2[e]);
+    fac[e] = window_angular<T>(qx, F::out_index(j, e), qz, N, l, m, norm, scale, yr, q2[e]);
   }
   const T* jl = jtab + (long long)l * nq2 * nbp;
   const c2<T>* src = fields + mock * nbins * N3 + (long long)qx * N * N + qz;
@@ -2246,7 +2246,7 @@ hipError_t filter_y_t(const FilterArgs& a, hipStream_t st) {
   const dim3 gs((N * (N / ZC) + G - 1) / G, a.batch);
   k_filter_y<N, T><<<gs, threads, 0, st>>>(static_cast<const CT<T>*>(a.src), static_cast<CT<T>*>(a.dst),
                                           static_cast<const T*>(a.jtab), a.nq2, a.nbins, a.nbp, a.l, a.m, a.norm,
-                                          a.scale, static_cast<const CT<T>*>(a.tw));
+                                          a.scale, static_cast<const CT<T>*>(a.tw), a.yr);
   return hipGetLastError();
 }
 
@@ -2258,7 +2258,7 @@ hipError_t adjoint_y_t(const FilterArgs& a, hipStream_t st) {
   const dim3 gs((N * (N / ZC) + G - 1) / G, a.batch);
   k_adjoint_y<N, T><<<gs, threads, 0, st>>>(static_cast<const CT<T>*>(a.src), static_cast<CT<T>*>(a.dst),
                                            static_cast<const T*>(a.jtab), a.nq2, a.nbins, a.nbp, a.l, a.m, a.norm,
-                                           a.scale, static_cast<const CT<T>*>(a.tw));
+                                           a.scale, static_cast<const CT<T>*>(a.tw), a.yr);
   return hipGetLastError();
 }
 
@@ -2355,7 +2355,7 @@ hipError_t zpass_nodal_t(const ZpassArgs& a, hipStream_t st) {
 
 template <int N, typename T, int MAXNB>
 hipError_t zpass_adjoint_nb(const ZpassArgs& a, hipStream_t st) {
-  const int threads = zpass_threads<N, VZA>(a.nbins);
+  const int threads = zpass_threads<N, VZA<T>>(a.nbins);
   const size_t lds = zpass_adjoint_lds<N, T>(a.nbins);
   hipError_t e = allow_lds(k_zpass_adjoint<N, T, MAXNB>, lds);
   if (e != hipSuccess) return e;

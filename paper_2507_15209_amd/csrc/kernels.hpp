@@ -5,6 +5,15 @@
 
 namespace mp3 {
 
+// Recurrence of the reduced associated Legendre functions Q_k^m for one
+// (l, m), set on the host: Q_m^m = pmm, Q_{m+1}^m = (2m + 1) x pmm and
+// Q_k^m = c1[k] x Q_{k-1}^m - c2[k] Q_{k-2}^m for k = m + 2 .. l, with
+// c1[k] = (2k - 1) / (k - m), c2[k] = (k + m - 1) / (k - m).
+struct YlmRec {
+  double pmm;
+  double c1[21], c2[21];
+};
+
 struct FilterArgs {
   const void* src;   // k_filter_y: dhat [batch][N^3]; k_adjoint_y: sources [batch][nbins][N^3]
   void* dst;         // k_filter_y: fields [batch][nbins][N^3]; k_adjoint_y: accumulator G [batch][N^3]
@@ -13,6 +22,7 @@ struct FilterArgs {
   int nq2, nbins, nbp, l, m, batch;
   double norm;       // Y_lm normalisation
   double scale;      // extra real factor (1/N^3, times the m weight in the adjoint)
+  YlmRec yr;         // Legendre recurrence of (l, m)
 };
 
 struct ZpassArgs {

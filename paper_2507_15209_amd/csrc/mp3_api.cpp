@@ -245,6 +245,12 @@ mp3::FilterArgs filter_args(const mp3_plan_s* p, const void* src, void* dst, int
   a.batch = p->batch;
   a.norm = mp3::ylm_norm(l, m);
   a.scale = scale;
+  a.yr.pmm = 1.0;
+  for (int k = 1; k <= m; ++k) a.yr.pmm *= -(2.0 * k - 1.0);
+  for (int k = 0; k < 21; ++k) {
+    a.yr.c1[k] = k >= m + 2 ? (2.0 * k - 1.0) / (double)(k - m) : 0.0;
+    a.yr.c2[k] = k >= m + 2 ? (k + m - 1.0) / (double)(k - m) : 0.0;
+  }
   return a;
 }
 
