@@ -182,6 +182,24 @@ int mp3_zeta_backward(mp3_plan_t plan, const void* delta, const double* dzeta,
                       void* ddelta, const float* pos, const float* w, const int64_t* np_off,
                       void* dw, void* workspace, size_t workspace_bytes, void* stream);
 
+/* Value and gradient of J = sum_{j,l,b1,b2} dzeta[j][l][b1][b2] zeta_l^{(j)}[b1][b2]
+ * in one sweep over (l, m): J is linear in zeta, so its cotangent dzeta is
+ * known before the forward (the paper gives no gradient; this is the chain
+ * rule of mp3_zeta, as for mp3_zeta_backward).
+ *   zeta   : as mp3_zeta, overwritten;
+ *   ddelta, dw : as mp3_zeta_backward for the same dzeta.
+ * Arguments, layouts, workspace and error codes are those of the two calls.
+ * Nodal form, float32 or float64, at most 32 bins: each (l, m) computes the
+ * window, y and x passes once, and one z pass both contracts the fields and
+ * forms the adjoint sources, so the fields are neither stored nor computed
+ * twice.  Other forms, BF16-split plans and more bins run mp3_zeta and then
+ * mp3_zeta_backward (same results).  The results agree with the two
+ * separate calls to rounding order (the z transforms use another radix plan). */
+int mp3_zeta_value_and_grad(mp3_plan_t plan, const void* delta, const double* dzeta,
+                            double* zeta, void* ddelta, const float* pos, const float* w,
+                            const int64_t* np_off, void* dw, void* workspace,
+                            size_t workspace_bytes, void* stream);
+
 /* Pass identifiers for per-pass timing. */
 enum mp3_pass {
   MP3_PASS_DFT = 0,        /* forward 3-D DFT of delta; final DFT of the adjoint accumulator */
@@ -195,7 +213,8 @@ enum mp3_pass {
   MP3_PASS_GATHER = 8,     /* B-spline gather at the particles + contraction                   */
   MP3_PASS_GAMMA = 9,      /* grid-Gamma quadrature contraction                                */
   MP3_PASS_SCATTER = 10,   /* adjoint sources scattered from the particles onto the grid      */
-  MP3_NPASS = 11
+  MP3_PASS_Z_FUSED = 11,   /* z-transform + contraction + adjoint sources (value and gradient) */
+  MP3_NPASS = 12
 };
 
 /* Per-pass timing for measurement: with enable != 0 every pass launch of

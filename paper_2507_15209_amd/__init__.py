@@ -9,6 +9,7 @@ library or without a GPU the calls raise.
     delta = plan.deposit(pos, w)                # [batch, n, n, n]
     zeta = plan.zeta(delta)                     # [batch, lmax+1, nbins, nbins] float64
     ddelta, dw = plan.zeta_backward(delta, dzeta, pos, w)
+    zeta, ddelta, dw = plan.zeta_value_and_grad(delta, dzeta, pos, w)   # both in one sweep
 """
 from __future__ import annotations
 
@@ -205,6 +206,34 @@ class Plan:
                                         _ptr(dw), _ptr(ws), ws.numel(), _stream(self.device))
         _lib.check(st, "mp3_zeta_backward")
         return ddelta, dw
+
+    def zeta_value_and_grad(self, delta, dzeta, pos=None, w=None, np_off=None):
+        """Returns (zeta, dJ/ddelta, dJ/dw or None) for J = sum dzeta * zeta in one sweep.
+
+        Same results as zeta() followed by zeta_backward(); the nodal form
+        (float32 / float64, <= 32 bins) computes each (l, m)'s fields once for both."""
+        self._real(delta, "delta")
+        dzeta = dzeta.to(device=self.device, dtype=torch.float64).contiguous()
+        if dzeta.numel() != self.batch * (self.lmax + 1) * self.nbins ** 2:
+            raise ValueError("dzeta must have shape [batch, lmax+1, nbins, nbins]")
+        if self.summation == "particle" and pos is None:
+            raise ValueError("the particle form needs pos (and w, np_off)")
+        z = torch.empty((self.batch, self.lmax + 1, self.nbins, self.nbins), dtype=torch.float64, device=self.device)
+        ddelta = torch.empty_like(delta)
+        dw = None
+        offp = None
+        np_total = 0
+        if pos is not None:
+            self._catalogue(pos, w)
+            np_total = pos.shape[0]
+            off = self._offsets(np_off, np_total)
+            offp = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+            dw = torch.empty(np_total, dtype=self.real_dtype, device=self.device)
+        ws = self._workspace(np_total)
+        st = self.lib.mp3_zeta_value_and_grad(self._h, _ptr(delta), _ptr(dzeta), _ptr(z), _ptr(ddelta), _ptr(pos),
+                                              _ptr(w), offp, _ptr(dw), _ptr(ws), ws.numel(), _stream(self.device))
+        _lib.check(st, "mp3_zeta_value_and_grad")
+        return z, ddelta, dw
 
 
 class Zeta3PCF(torch.autograd.Function):

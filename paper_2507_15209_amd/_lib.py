@@ -27,10 +27,10 @@ EXPORTS = (
     "mp3_plan_create", "mp3_plan_destroy", "mp3_workspace_size", "mp3_deposit",
     "mp3_multipole_fields", "mp3_zeta", "mp3_zeta_backward", "mp3_plan_info",
     "mp3_status_string", "mp3_last_error", "mp3_profile", "mp3_profile_read",
-    "mp3_tune_set", "mp3_tune_get",
+    "mp3_tune_set", "mp3_tune_get", "mp3_zeta_value_and_grad",
 )
 PASSES = ("dft", "filter", "x", "z_nodal", "z_adjoint", "adjoint", "deposit", "z_store", "gather", "gamma",
-          "scatter")
+          "scatter", "z_fused")
 
 
 class PlanDesc(ctypes.Structure):
@@ -80,6 +80,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.mp3_multipole_fields.argtypes = [vp, vp, i32, i32, vp, vp, sz, vp]
     lib.mp3_zeta.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i64), vp, vp, sz, vp]
     lib.mp3_zeta_backward.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(i64), vp, vp, sz, vp]
+    lib.mp3_zeta_value_and_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i64), vp, vp, sz, vp]
     lib.mp3_plan_info.argtypes = [vp] + [ctypes.POINTER(i32)] * 5
     lib.mp3_profile.argtypes = [vp, ctypes.c_int]
     lib.mp3_profile_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]

@@ -131,6 +131,19 @@ __device__ __forceinline__ c2<T> window_angular(int ix, int iy, int iz, int n, i
   return mk<T>((T)f.x, (T)f.y);
 }
 
+// streaming accesses: bulk data that is read or written once per pass goes
+// through the caches with the non-temporal hint, so that the radial-window
+// table (3.9 MB per l at 256^3, 20 bins) stays in L2
+typedef double mp3_nt_d2 __attribute__((ext_vector_type(2)));
+template <typename V> __device__ __forceinline__ void nt_store(V* p, V v) {
+  if constexpr (sizeof(V) == 8) __builtin_nontemporal_store(__builtin_bit_cast(double, v), reinterpret_cast<double*>(p));
+  else __builtin_nontemporal_store(__builtin_bit_cast(mp3_nt_d2, v), reinterpret_cast<mp3_nt_d2*>(p));
+}
+template <typename V> __device__ __forceinline__ V nt_load(const V* p) {
+  if constexpr (sizeof(V) == 8) return __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const double*>(p)));
+  else return __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const mp3_nt_d2*>(p)));
+}
+
 // four consecutive radial-window values (the table's bin axis is padded to a
 // multiple of four and 16-byte aligned per |q|^2 row)
 template <typename T> __device__ __forceinline__ void load_quad(const T* p, T* o);
@@ -387,7 +400,7 @@ __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_filter_y(cons
 #pragma unroll
   for (int r = 0; r < RMAX; ++r) {
     const int qy = F::in_index(j, r);
-    const c2<T> d = active ? dhat[mock * N3 + ((long long)qx * N + qy) * N + qz] : mk<T>(0, 0);
+    const c2<T> d = active ? nt_load(&dhat[mock * N3 + ((long long)qx * N + qy) * N + qz]) : mk<T>(0, 0);
     const c2<T> f = window_angular<T>(qx, qy, qz, N, l, m, norm, scale, yr, q2[r]);
     v0[r] = cmul<T>(d, f);
   }
@@ -415,7 +428,7 @@ __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_filter_y(cons
         if (active) {
           c2<T>* out = fbase + (bq + k) * N3;
 #pragma unroll
-          for (int e = 0; e < RMAX; ++e) out[F::out_index(jj, e) * N] = v[e];
+          for (int e = 0; e < RMAX; ++e) nt_store(&out[F::out_index(jj, e) * N], v[e]);
         }
       }
     }
@@ -1296,10 +1309,14 @@ __global__ void k_reduce_partials(const double* partials, int nwg, int nb2, doub
 //   c_b = delta u_b,
 // and z-transform every c_b (the adjoint's first axis), written over the field.
 // lam_s is read with wave-uniform indices (scalar loads).
+// FUSED: the same sweep also contracts the pencil for zeta (the partials of
+// k_zpass_nodal), so that value and gradient share one computation of the
+// fields when dJ/dzeta is fixed before the forward (J linear in zeta).
 // ---------------------------------------------------------------------------
-template <int N, typename T, int MAXNB>
+template <int N, typename T, int MAXNB, bool FUSED = false, bool MF = false, bool QUAD = false>
 __global__ void __launch_bounds__(512) k_zpass_adjoint(c2<T>* fields, const T* delta, const T* __restrict__ lam_s,
-                                                        T* direct, int nbins, T wm, int ppw, const c2<T>* tw) {
+                                                        T* direct, int nbins, T wm, int ppw, const c2<T>* tw,
+                                                        double* partials) {
   using F = Fft<N, VZA<T>>;
   constexpr int RS = zrow<N>();
   constexpr int NBP = (MAXNB + 3) / 4 * 4;
@@ -1308,6 +1325,7 @@ __global__ void __launch_bounds__(512) k_zpass_adjoint(c2<T>* fields, const T* d
   c2<T>* A = reinterpret_cast<c2<T>*>(smem);
   c2<T>* tws = A + nbins * RS;
   T* lam = reinterpret_cast<T*>(tws + N);             // [nbins][NBP], zero padded
+  T* dl = lam + nbins * NBP;                          // FUSED: delta of the pencil
   const int tid = threadIdx.x;
   const long long mock = blockIdx.y;
   stage_twiddles<N, T>(tw, tws);
@@ -1316,6 +1334,8 @@ __global__ void __launch_bounds__(512) k_zpass_adjoint(c2<T>* fields, const T* d
     lam[t] = b < nbins ? lam_s[mock * nbins * nbins + bp * nbins + b] : (T)0;
   }
   __syncthreads();
+  Contractor<T, MF, false, QUAD> ctr;
+  if constexpr (FUSED) ctr.init(nbins);
   const int nbc = blockDim.x / F::TPC;
   const int p0 = blockIdx.x * ppw;
   const int p1 = min(p0 + ppw, N * N);
@@ -1349,8 +1369,20 @@ __global__ void __launch_bounds__(512) k_zpass_adjoint(c2<T>* fields, const T* d
       prefetch_delta<N, T>(dmock + (long long)(p + 1) * N, dpre);
       prefetch_delta<N, T>(rmock + (long long)(p + 1) * N, rpre);
     }
+    if constexpr (FUSED) {
+#pragma unroll
+      for (int k = 0; k < DPRE; ++k) {
+        const int z = tid + k * blockDim.x;
+        if (z < N) dl[z] = dcur[k];
+      }
+    }
     transform_pencil_bins<N, T, VZA<T>>(fbase, N3, nbins, A, tws, vcur);
     __syncthreads();
+    if constexpr (FUSED) {
+      // contraction of the fields before the sources overwrite them
+      ctr.add(A, dl, nbins, RS, N);
+      __syncthreads();
+    }
 #pragma unroll
     for (int k = 0; k < DPRE; ++k) {
       const int z = tid + k * blockDim.x;
@@ -1409,6 +1441,9 @@ __global__ void __launch_bounds__(512) k_zpass_adjoint(c2<T>* fields, const T* d
     }
     __syncthreads();
   }
+  if constexpr (FUSED)
+    ctr.finish(reinterpret_cast<double*>(smem), partials + ((long long)mock * gridDim.x + blockIdx.x) * nbins * nbins,
+               nbins);
 }
 
 // lam_s[j][b][b'] = (dzeta[j][l][b][b'] + dzeta[j][l][b'][b]) / 2 for one l
@@ -1463,7 +1498,7 @@ __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_adjoint_y(con
   c2<T> vn[RMAX];
   if (active) {
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r) vn[r] = src[F::in_index(j, r) * N];
+    for (int r = 0; r < RMAX; ++r) vn[r] = nt_load(&src[F::in_index(j, r) * N]);
   }
   for (int bq = 0; bq < nbins; bq += 4) {
     T jq[RMAX][4];
@@ -1478,7 +1513,7 @@ __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_adjoint_y(con
         for (int r = 0; r < RMAX; ++r) v[r] = vn[r];
         if (b + 1 < nbins && active) {
 #pragma unroll
-          for (int r = 0; r < RMAX; ++r) vn[r] = src[(b + 1) * N3 + F::in_index(j, r) * N];
+          for (int r = 0; r < RMAX; ++r) vn[r] = nt_load(&src[(b + 1) * N3 + F::in_index(j, r) * N]);
         }
         int jj = j;
         asm volatile("" : "+v"(jj));
@@ -1493,7 +1528,7 @@ __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_adjoint_y(con
 #pragma unroll
     for (int e = 0; e < RMAX; ++e) {
       c2<T>* p = dst + F::out_index(j, e) * N;
-      *p = cadd<T>(*p, acc[e]);
+      nt_store(p, cadd<T>(nt_load(p), acc[e]));
     }
   }
 }
@@ -2353,18 +2388,45 @@ hipError_t zpass_nodal_t(const ZpassArgs& a, hipStream_t st) {
   return zpass_nodal_mf<N, T, false>(a, st);
 }
 
-template <int N, typename T, int MAXNB>
+// fused sweeps round the workgroup up to whole waves (the matrix-core
+// contractions split the work by wave); the extra threads hold no column
+template <int N, typename T> inline int zpass_fused_threads(int nbins) {
+  return (zpass_threads<N, VZA<T>>(nbins) + 63) / 64 * 64;
+}
+
+template <int N, typename T> inline size_t zpass_fused_lds(int nbins, int threads, size_t scratch) {
+  const size_t a = zpass_adjoint_lds<N, T>(nbins) + (size_t)N * sizeof(T);
+  (void)threads;
+  return a > scratch ? a : scratch;
+}
+
+template <int N, typename T, int MAXNB, bool FUSED = false, bool MF = false, bool QUAD = false>
 hipError_t zpass_adjoint_nb(const ZpassArgs& a, hipStream_t st) {
-  const int threads = zpass_threads<N, VZA<T>>(a.nbins);
-  const size_t lds = zpass_adjoint_lds<N, T>(a.nbins);
-  hipError_t e = allow_lds(k_zpass_adjoint<N, T, MAXNB>, lds);
+  const int threads = FUSED ? zpass_fused_threads<N, T>(a.nbins) : zpass_threads<N, VZA<T>>(a.nbins);
+  const size_t lds = FUSED ? zpass_fused_lds<N, T>(a.nbins, threads,
+                                                    Contractor<T, MF, false, QUAD>::scratch_bytes(threads))
+                           : zpass_adjoint_lds<N, T>(a.nbins);
+  hipError_t e = allow_lds(k_zpass_adjoint<N, T, MAXNB, FUSED, MF, QUAD>, lds);
   if (e != hipSuccess) return e;
   const dim3 gs(a.nwg, a.batch);
-  k_zpass_adjoint<N, T, MAXNB><<<gs, threads, lds, st>>>(static_cast<CT<T>*>(const_cast<void*>(a.fields)),
-                                                        static_cast<const T*>(a.delta), static_cast<const T*>(a.lam),
-                                                        static_cast<T*>(a.direct), a.nbins, (T)a.wm, a.ppw,
-                                                        static_cast<const CT<T>*>(a.tw));
+  k_zpass_adjoint<N, T, MAXNB, FUSED, MF, QUAD><<<gs, threads, lds, st>>>(
+      static_cast<CT<T>*>(const_cast<void*>(a.fields)), static_cast<const T*>(a.delta), static_cast<const T*>(a.lam),
+      static_cast<T*>(a.direct), a.nbins, (T)a.wm, a.ppw, static_cast<const CT<T>*>(a.tw), a.partials);
   return hipGetLastError();
+}
+
+// value-and-gradient sweep, <= 32 bins: float32 contracts on the matrix cores
+// (4x4 blocks at 17..20 bins), float64 on the vector ALUs
+template <int N, typename T>
+hipError_t zpass_fused_t(const ZpassArgs& a, hipStream_t st) {
+  if (a.nbins > 32) return hipErrorInvalidValue;
+  constexpr bool MF = std::is_same<T, float>::value;
+  if (a.nbins <= 8) return zpass_adjoint_nb<N, T, 8, true, MF, false>(a, st);
+  if (a.nbins <= 12) return zpass_adjoint_nb<N, T, 12, true, MF, false>(a, st);
+  if (a.nbins <= 16) return zpass_adjoint_nb<N, T, 16, true, MF, false>(a, st);
+  if (a.nbins <= 20) return zpass_adjoint_nb<N, T, 20, true, MF, MF>(a, st);
+  if (a.nbins <= 24) return zpass_adjoint_nb<N, T, 24, true, MF, false>(a, st);
+  return zpass_adjoint_nb<N, T, 32, true, MF, false>(a, st);
 }
 
 template <int N, typename T>
@@ -2425,6 +2487,28 @@ hipError_t launch_zpass_store(int n, int prec, const ZpassArgs& a, void* out, hi
   MP3_DISPATCH(zpass_store_t, n, prec, a, out, st);
 }
 hipError_t launch_zpass_adjoint(int n, int prec, const ZpassArgs& a, hipStream_t st) { MP3_DISPATCH(zpass_adjoint_t, n, prec, a, st); }
+hipError_t launch_zpass_fused(int n, int prec, const ZpassArgs& a, hipStream_t st) { MP3_DISPATCH(zpass_fused_t, n, prec, a, st); }
+
+template <int N, typename T> size_t zpass_fused_lds_need_t(int nbins) {
+  if (nbins > 32) return (size_t)1 << 40;
+  const int threads = zpass_fused_threads<N, T>(nbins);
+  constexpr bool MF = std::is_same<T, float>::value;
+  const size_t red = nbins > 16 && nbins <= 20 ? Contractor<T, MF, false, MF>::scratch_bytes(threads)
+                                                : Contractor<T, MF, false, false>::scratch_bytes(threads);
+  return zpass_fused_lds<N, T>(nbins, threads, red);
+}
+
+size_t zpass_fused_lds_need(int n, int prec, int nbins) {
+  switch (n) {
+    case 16: return prec ? zpass_fused_lds_need_t<16, double>(nbins) : zpass_fused_lds_need_t<16, float>(nbins);
+    case 32: return prec ? zpass_fused_lds_need_t<32, double>(nbins) : zpass_fused_lds_need_t<32, float>(nbins);
+    case 64: return prec ? zpass_fused_lds_need_t<64, double>(nbins) : zpass_fused_lds_need_t<64, float>(nbins);
+    case 128: return prec ? zpass_fused_lds_need_t<128, double>(nbins) : zpass_fused_lds_need_t<128, float>(nbins);
+    case 256: return prec ? zpass_fused_lds_need_t<256, double>(nbins) : zpass_fused_lds_need_t<256, float>(nbins);
+    case 512: return prec ? zpass_fused_lds_need_t<512, double>(nbins) : zpass_fused_lds_need_t<512, float>(nbins);
+    default: return (size_t)-1;
+  }
+}
 
 size_t zpass_lds_need(int n, int prec, int nbins) {
   switch (n) {

@@ -81,7 +81,11 @@ hipError_t launch_filter_y(int n, int prec, const FilterArgs& a, hipStream_t st)
 hipError_t launch_adjoint_y(int n, int prec, const FilterArgs& a, hipStream_t st);
 hipError_t launch_zpass_nodal(int n, int prec, const ZpassArgs& a, hipStream_t st);
 hipError_t launch_zpass_adjoint(int n, int prec, const ZpassArgs& a, hipStream_t st);
+// adjoint z pass that also writes the forward partials (value and gradient in one sweep), <= 32 bins
+hipError_t launch_zpass_fused(int n, int prec, const ZpassArgs& a, hipStream_t st);
 size_t zpass_lds_need(int n, int prec, int nbins);
+// LDS bytes of the value-and-gradient z pass ((size_t)1 << 40 beyond 32 bins)
+size_t zpass_fused_lds_need(int n, int prec, int nbins);
 hipError_t launch_fill(int prec, void* p, long long count, double value, hipStream_t st);
 hipError_t launch_fill_f64(double* p, long long count, double value, hipStream_t st);
 hipError_t launch_lam_sym(int prec, const double* dzeta, void* lam_s, int nbins, int l, int lmax, int batch,

@@ -646,6 +646,31 @@ int mp3_zeta(mp3_plan_t p, const void* delta, const float* pos, const float* w, 
 
 namespace {
 
+// end of the nodal adjoint: final transform of the accumulator G, ddelta, and
+// dJ/dw through the deposit when dw is requested
+int nodal_gradient_tail(mp3_plan_t p, const void* delta, void* ddelta, const float* pos, const float* w,
+                        const int64_t* np_off, void* dw, void* ws, const Layout& L, long long np_total,
+                        long long np_max, hipStream_t st) {
+  const long long n3 = (long long)p->n * p->n * p->n;
+  void* G = at(ws, L.G);
+  void* direct = at(ws, L.direct);
+  MP3_HIP(timed(p, MP3_PASS_DFT, st, [&] { return mp3::launch_fft3d(p->n, p->prec, -1, false, G, G, p->batch, p->tw, st); }), "adjoint final FFT");
+  MP3_HIP(mp3::launch_grad_combine(p->prec, direct, G, ddelta, n3 * p->batch, kFourPi / (double)n3, st), "combine");
+  if (dw) {
+    if (int s = upload_offsets(p, np_off, ws, L, st)) return s;
+    const long long* off = reinterpret_cast<const long long*>(at(ws, L.off));
+    double* W = reinterpret_cast<double*>(at(ws, L.W));
+    double* S = reinterpret_cast<double*>(at(ws, L.S));
+    MP3_HIP(mp3::launch_fill_f64(W, p->batch, 0.0, st), "zero W");
+    MP3_HIP(mp3::launch_fill_f64(S, p->batch, 0.0, st), "zero S");
+    MP3_HIP(mp3::launch_weight_sum(w, off, p->batch, np_max, W, st), "weight sum");
+    MP3_HIP(mp3::launch_dot_rho_g(p->prec, delta, ddelta, n3, S, p->batch, st), "dot");
+    MP3_HIP(mp3::launch_gather_dw(p->prec, pos, off, p->batch, np_total, p->n, (double)p->n / p->box, ddelta, W, S, dw, st),
+            "gather dw");
+  }
+  return MP3_OK;
+}
+
 // Adjoint of the particle summation (chain rule of zeta_particle):
 //   dJ/ddelta = (4 pi / N^3) 2 Re fftn( sum_{l,m,b} wm K_b ifftn(c_b) - H conj(dhat) / (4 pi N^3) ),
 //   c_b = N^3 scatter_i[ (w_i / W) sum_b' lam_s[b][b'] conj(atilde_b'(u_i)) ],
@@ -856,21 +881,70 @@ int mp3_zeta_backward(mp3_plan_t p, const void* delta, const double* dzeta, void
       MP3_HIP(timed(p, MP3_PASS_ADJOINT, st, [&] { return mp3::launch_adjoint_y(p->n, p->prec, a, st); }), "adjoint window pass");
     }
   }
-  MP3_HIP(timed(p, MP3_PASS_DFT, st, [&] { return mp3::launch_fft3d(p->n, p->prec, -1, false, G, G, p->batch, p->tw, st); }), "adjoint final FFT");
-  MP3_HIP(mp3::launch_grad_combine(p->prec, direct, G, ddelta, n3 * p->batch, kFourPi / (double)n3, st), "combine");
-  if (dw) {
-    if (int s = upload_offsets(p, np_off, ws, L, st)) return s;
-    const long long* off = reinterpret_cast<const long long*>(at(ws, L.off));
-    double* W = reinterpret_cast<double*>(at(ws, L.W));
-    double* S = reinterpret_cast<double*>(at(ws, L.S));
-    MP3_HIP(mp3::launch_fill_f64(W, p->batch, 0.0, st), "zero W");
-    MP3_HIP(mp3::launch_fill_f64(S, p->batch, 0.0, st), "zero S");
-    MP3_HIP(mp3::launch_weight_sum(w, off, p->batch, np_max, W, st), "weight sum");
-    MP3_HIP(mp3::launch_dot_rho_g(p->prec, delta, ddelta, n3, S, p->batch, st), "dot");
-    MP3_HIP(mp3::launch_gather_dw(p->prec, pos, off, p->batch, np_total, p->n, (double)p->n / p->box, ddelta, W, S, dw, st),
-            "gather dw");
+  return nodal_gradient_tail(p, delta, ddelta, pos, w, np_off, dw, ws, L, np_total, np_max, st);
+}
+
+int mp3_zeta_value_and_grad(mp3_plan_t p, const void* delta, const double* dzeta, double* zeta, void* ddelta,
+                            const float* pos, const float* w, const int64_t* np_off, void* dw, void* ws, size_t wsb,
+                            void* stream) {
+  if (int s = check_plan(p)) return s;
+  if (!delta || !dzeta || !zeta || !ddelta) return fail(MP3_EINVAL, "delta, dzeta, zeta and ddelta must not be NULL");
+  const int storage = p->prec;
+  const bool one_sweep = p->summation == MP3_SUM_NODAL && !p->split && p->nbins <= 32 &&
+                         mp3::zpass_fused_lds_need(p->n, storage, p->nbins) <= kLdsLimit;
+  if (!one_sweep) {
+    if (int s = mp3_zeta(p, delta, pos, w, np_off, zeta, ws, wsb, stream)) return s;
+    return mp3_zeta_backward(p, delta, dzeta, ddelta, pos, w, np_off, dw, ws, wsb, stream);
   }
-  return MP3_OK;
+  long long np_total = 0, np_max = 0;
+  if (dw) {
+    if (int s = check_offsets(p, np_off, &np_total, &np_max)) return s;
+    if (!pos) return fail(MP3_EINVAL, "pos is NULL while dw is requested");
+  }
+  const Layout L = layout(p, np_total);
+  if (int s = check_ws(p, ws, wsb, L.total)) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const long long n3 = (long long)p->n * p->n * p->n;
+  const int nb2 = p->nbins * p->nbins;
+  if (int s = forward_dft(p, delta, ws, L, st)) return s;
+  void* F = at(ws, L.fields);
+  void* G = at(ws, L.G);
+  void* direct = at(ws, L.direct);
+  double* partials = reinterpret_cast<double*>(at(ws, L.partials));
+  MP3_HIP(mp3::launch_fill_f64(zeta, (long long)p->batch * (p->lmax + 1) * nb2, 0.0, st), "zero zeta");
+  MP3_HIP(mp3::launch_fill(p->prec, G, 2 * n3 * p->batch, 0.0, st), "zero G");
+  MP3_HIP(mp3::launch_fill(p->prec, direct, n3 * p->batch, 0.0, st), "zero direct");
+  for (int l = 0; l <= p->lmax; ++l) {
+    for (int m = 0; m <= l; ++m) {
+      const double wm = m == 0 ? 1.0 : 2.0;
+      if (m == 0)
+        MP3_HIP(mp3::launch_lam_sym(p->prec, dzeta, at(ws, L.lam), p->nbins, l, p->lmax, p->batch, st), "lambda");
+      if (int s = fields_xy(p, ws, L, F, l, m, st)) return s;
+      mp3::ZpassArgs z{};
+      z.fields = F;
+      z.delta = delta;
+      z.partials = partials;
+      z.dzeta = dzeta;
+      z.lam = at(ws, L.lam);
+      z.direct = direct;
+      z.tw = p->tw;
+      z.nbins = p->nbins;
+      z.nwg = L.nwg;
+      z.ppw = L.ppw;
+      z.batch = p->batch;
+      z.l = l;
+      z.lmax = p->lmax;
+      z.wm = wm;
+      MP3_HIP(timed(p, MP3_PASS_Z_FUSED, st, [&] { return mp3::launch_zpass_fused(p->n, p->prec, z, st); }),
+              "z pass (contraction and adjoint)");
+      MP3_HIP(mp3::launch_reduce_partials(partials, L.nwg, nb2, zeta, l, p->lmax, wm * kFourPi / (double)n3, p->batch, st),
+              "reduce");
+      MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, F, p->batch * p->nbins, p->tw, p->tune[MP3_TUNE_FFT_X_PLAN], st); }), "adjoint x pass");
+      mp3::FilterArgs a = filter_args(p, F, G, l, m, wm / (double)n3);
+      MP3_HIP(timed(p, MP3_PASS_ADJOINT, st, [&] { return mp3::launch_adjoint_y(p->n, p->prec, a, st); }), "adjoint window pass");
+    }
+  }
+  return nodal_gradient_tail(p, delta, ddelta, pos, w, np_off, dw, ws, L, np_total, np_max, st);
 }
 
 }  // extern "C"

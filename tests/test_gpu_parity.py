@@ -503,3 +503,84 @@ def test_degenerate_inputs(mp3, summation):
     assert np.all(z == 0.0)
     g, _ = plan.zeta_backward(zero, lam)
     assert torch.count_nonzero(g).item() == 0
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n,lmax,nb", [(16, 2, 3), (32, 3, 5), (32, 3, 20), (32, 2, 24), (16, 2, 32)])
+def test_value_and_grad_nodal(mp3, prec, n, lmax, nb):
+    """One-sweep value and gradient: zeta, dJ/ddelta and dJ/dw against the oracle and the two separate calls."""
+    _say("value and grad", prec, n, lmax, nb)
+    box = 10.0 * n
+    edges = np.linspace(0.08 * box, 0.35 * box, nb + 1)
+    pos, w = lognormal_catalogue(n, box, 6000, 0.05 * box, 81 + nb, 82 + nb, 83 + nb, (0.5, 1.5))
+    lam = np.random.default_rng(84 + nb).standard_normal((lmax + 1, nb, nb))
+    plan = mp3.Plan(n, box, lmax, edges, precision=prec)
+    pt, wt = _dev(pos, torch.float32), _dev(w, torch.float32)
+    delta = plan.deposit(pt, wt)
+    lt = _dev(lam[None], torch.float64)
+    z, dd, dw = plan.zeta_value_and_grad(delta, lt, pt, wt)
+    z2 = plan.zeta(delta)
+    dd2, dw2 = plan.zeta_backward(delta, lt, pt, wt)
+    dref = basis.density_contrast(basis.deposit(pos, w, n, box), float(np.sum(w.astype(np.float64))))
+    op = E.Plan(n, box, lmax, edges)
+    zref = E.zeta_nodal(op, dref)
+    gref = A.zeta_nodal_grad(op, dref, lam)
+    wref = A.deposit_weight_grad(pos, w, n, box, gref)
+    tol = TOL[prec]
+    assert_zeta_close(z.cpu().numpy()[0], zref, tol)
+    eg = np.linalg.norm(dd.cpu().numpy()[0] - gref) / np.linalg.norm(gref)
+    ew = np.linalg.norm(dw.cpu().numpy() - wref) / np.linalg.norm(wref)
+    print("grad errors", eg, ew)
+    assert eg < tol and ew < tol
+    # against the separate calls: rounding-order differences only
+    agree = 1e-12 if prec == "f64" else 2e-5
+    assert_zeta_close(z.cpu().numpy()[0], z2.cpu().numpy()[0], agree)
+    g1, g2 = dd.cpu().numpy(), dd2.cpu().numpy()
+    assert np.abs(g1 - g2).max() <= agree * np.abs(g2).max()
+    zz = z.cpu().numpy()[0]
+    assert np.abs(zz - zz.transpose(0, 2, 1)).max() <= 1e-12 * np.abs(zz).max()
+
+
+def test_value_and_grad_batch_and_other_forms(mp3):
+    """A batch of uneven mocks (float32, 12 bins), and the forms that run the two calls in turn (identical results)."""
+    _say("value and grad batch")
+    n, box, lmax, batch = 32, 250.0, 3, 3
+    edges = np.linspace(20.0, 90.0, 13)
+    sizes = [int(s) for s in batch_sizes(batch, 91, 2000, 8000)]
+    cats = [lognormal_catalogue(n, box, s, 12.0, 92 + j, 95 + j, 98 + j, (0.5, 1.5)) for j, s in enumerate(sizes)]
+    pos = np.concatenate([c[0] for c in cats])
+    w = np.concatenate([c[1] for c in cats])
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    lam = np.random.default_rng(101).standard_normal((batch, lmax + 1, 12, 12))
+    pt, wt, lt = _dev(pos, torch.float32), _dev(w, torch.float32), _dev(lam, torch.float64)
+    plan = mp3.Plan(n, box, lmax, edges, precision="f32", batch=batch)
+    delta = plan.deposit(pt, wt, off)
+    z, dd, dw = plan.zeta_value_and_grad(delta, lt, pt, wt, off)
+    op = E.Plan(n, box, lmax, edges)
+    for j, (p, ww) in enumerate(cats):
+        dref = basis.density_contrast(basis.deposit(p, ww, n, box), float(np.sum(ww.astype(np.float64))))
+        assert_zeta_close(z.cpu().numpy()[j], E.zeta_nodal(op, dref), 1e-4)
+        gref = A.zeta_nodal_grad(op, dref, lam[j])
+        wref = A.deposit_weight_grad(p, ww, n, box, gref)
+        assert np.linalg.norm(dd.cpu().numpy()[j] - gref) < 1e-4 * np.linalg.norm(gref)
+        got = dw.cpu().numpy()[off[j]:off[j + 1]]
+        assert np.linalg.norm(got - wref) < 1e-4 * np.linalg.norm(wref)
+    for summation, prec in (("particle", "f64"), ("gamma", "f64"), ("nodal", "bf16x3")):
+        _say("value and grad, two calls:", summation, prec)
+        n2, box2, lmax2 = 16, 160.0, 2
+        edges2 = np.linspace(15.0, 55.0, 4)
+        p2, w2 = lognormal_catalogue(n2, box2, 3000, 8.0, 111, 112, 113, (0.5, 1.5))
+        pt2, wt2 = _dev(p2, torch.float32), _dev(w2, torch.float32)
+        lam2 = _dev(np.random.default_rng(114).standard_normal((1, lmax2 + 1, 3, 3)), torch.float64)
+        plan2 = mp3.Plan(n2, box2, lmax2, edges2, precision=prec, summation=summation)
+        d2 = plan2.deposit(pt2, wt2)
+        cat = (pt2, wt2) if summation == "particle" else ()
+        z1, g1, w1 = plan2.zeta_value_and_grad(d2, lam2, pt2, wt2)
+        z0 = plan2.zeta(d2, *cat)
+        g0, w0 = plan2.zeta_backward(d2, lam2, pt2, wt2)
+        # the same two calls run; the grid-Gamma adjoint folds tiles with atomics (summation order varies)
+        agree = 1e-12 if prec == "f64" else 2e-5
+        assert_zeta_close(z1.cpu().numpy()[0], z0.cpu().numpy()[0], agree)
+        for a1, a0 in ((g1, g0), (w1, w0)):
+            a1, a0 = a1.cpu().numpy(), a0.cpu().numpy()
+            assert np.abs(a1 - a0).max() <= agree * np.abs(a0).max()
