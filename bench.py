@@ -44,6 +44,7 @@ def pass_bytes(name, n, nb, batch, real_bytes):
         "x": 2.0 * nb * n3 * c,                                            # nb fields in and out
         "z_nodal": nb * n3 * c + n3 * real_bytes,                          # nb fields + delta in
         "z_adjoint": 2.0 * nb * n3 * c + n3 * real_bytes + 2 * n3 * real_bytes,  # fields in/out, delta, direct rmw
+        "z_fused": 2.0 * nb * n3 * c + n3 * real_bytes + 2 * n3 * real_bytes,    # as z_adjoint (partials are KB)
         "adjoint": nb * n3 * c + 2.0 * n3 * c,                             # nb sources in, G rmw
     }.get(name)
 
@@ -84,6 +85,9 @@ def pmc_probe(wl, precision):
     lam = torch.as_tensor(np.random.default_rng(11).standard_normal((1, wl.lmax + 1, wl.nbins, wl.nbins)), device=dev)
     plan = mp3.Plan(wl.n, wl.box, wl.lmax, wl.edges, precision=precision, device=dev)
     delta = plan.deposit(pt, wt)
+    plan.zeta_value_and_grad(delta, lam, pt, wt)
+    torch.cuda.synchronize()
+    log("one-sweep value and gradient done")
     plan.zeta(delta)
     torch.cuda.synchronize()
     log("forward done")
@@ -109,9 +113,12 @@ def _source_digest():
     return hashlib.sha256(src).hexdigest()[:16]
 
 
-# kernels whose traffic is summarised: pass name -> (kernel-name prefix, grid filter on fields per launch)
-PMC_KERNELS = {"x": "k_fft_strided", "filter": "k_filter_y", "z_nodal": "k_zpass_nodal",
-               "z_adjoint": "k_zpass_adjoint", "adjoint": "k_adjoint_y"}
+# kernels whose traffic is summarised: pass name -> kernel-name test
+PMC_KERNELS = {"x": lambda k: "k_fft_strided" in k, "filter": lambda k: "k_filter_y" in k,
+               "z_nodal": lambda k: "k_zpass_nodal" in k,
+               "z_adjoint": lambda k: "k_zpass_adjoint" in k and "false, false, false>" in k,
+               "z_fused": lambda k: "k_zpass_adjoint" in k and ", true," in k.split(">")[0],
+               "adjoint": lambda k: "k_adjoint_y" in k}
 
 
 def pmc_summarize(fetch_dir, write_dir, wl, precision):
@@ -135,8 +142,8 @@ def pmc_summarize(fetch_dir, write_dir, wl, precision):
         factor = kib * 1024.0 / COPY_BYTES
         out.append(f"# {cname}: plain 1 GiB device copy counts {kib:.0f} KiB -> factor {factor:.4f} "
                    f"(counter bytes per true byte)")
-        for tag, prefix in PMC_KERNELS.items():
-            sel = [r for r in rows if prefix in r["Kernel_Name"]]
+        for tag, match in PMC_KERNELS.items():
+            sel = [r for r in rows if match(r["Kernel_Name"])]
             if tag == "x" and sel:
                 # the x pass transforms all bins in one launch: the largest grid of the strided kernel
                 gmax = max(int(r.get("Grid_Size") or 0) for r in sel)
@@ -236,9 +243,10 @@ def measure_form(name, steps=1, warmup=1):
 
     def step():
         delta = plan.deposit(pt, wt, off)
-        plan.zeta(delta, *cat)
         if backward:
-            plan.zeta_backward(delta, lam, pt, wt, off)
+            plan.zeta_value_and_grad(delta, lam, pt, wt, off)
+        else:
+            plan.zeta(delta, *cat)
 
     for _ in range(warmup):
         step()
@@ -285,6 +293,8 @@ def main():
     ap.add_argument("--workload", default="box2000_n256_l10")
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--two-call-steps", type=int, default=3,
+                    help="also time the step as zeta() then zeta_backward() (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default=",".join(DEFAULT_FORMS),
                     help="secondary measurements after the headline (comma list of %s, all, or none)" % ", ".join(FORMS))
@@ -330,15 +340,19 @@ def main():
                           device=dev)
     units = float(wl.n) ** 3 * (wl.lmax + 1) ** 2 * wl.nbins
 
-    def run(precision, steps, warmup, profile):
+    def run(precision, steps, warmup, profile, one_sweep=True):
         t0 = time.perf_counter()
         plan = mp3.Plan(wl.n, wl.box, wl.lmax, wl.edges, precision=precision, device=dev)
         log(f"{precision} plan built in {time.perf_counter() - t0:.1f} s")
 
         def step():
             delta = plan.deposit(pt, wt)
-            plan.zeta(delta)
-            plan.zeta_backward(delta, lam, pt, wt)
+            if one_sweep:
+                # zeta and the gradient of J = <lam, zeta> (lam fixed before the forward)
+                plan.zeta_value_and_grad(delta, lam, pt, wt)
+            else:
+                plan.zeta(delta)
+                plan.zeta_backward(delta, lam, pt, wt)
 
         for i in range(warmup):
             step()
@@ -373,6 +387,14 @@ def main():
     log("per-pass totals (ms, launches):", {k: (round(v[0], 2), v[1]) for k, v in passes.items()})
     traffic = read_pmc(dom)
 
+    two_calls = None
+    if args.two_call_steps > 0:
+        t2, prof2 = run(args.precision, args.two_call_steps, 1, True, one_sweep=False)
+        two_calls = {"value": units / t2, "ms_per_step": t2 * 1e3, "steps": args.two_call_steps,
+                     "pass": "zeta then zeta_backward (the fields of each (l, m) computed twice)",
+                     "passes_ms": {k: {"total_ms": v[0] / args.two_call_steps, "launches": v[1] // args.two_call_steps}
+                                   for k, v in prof2.items() if v[1] > 0}}
+
     fp64 = None
     if args.precision == "f32" and args.fp64_steps > 0:
         t64, _ = run("f64", args.fp64_steps, 1, False)
@@ -401,13 +423,15 @@ def main():
         "vs_baseline": None,
         "dtype": args.precision,
         "data": "synthetic seeded log-normal mock (stand-in for the N-body snapshot)",
-        "config": {"workload": wl.name, "form": "nodal grid summation, forward + adjoint incl. deposit and dJ/dw",
+        "config": {"workload": wl.name, "form": "nodal grid summation, forward + adjoint incl. deposit and dJ/dw "
+                   "(one sweep: zeta_value_and_grad)",
                    "grid": wl.n, "box": wl.box, "lmax": wl.lmax, "nbins": wl.nbins,
                    "n_particles": wl.n_particles, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": abytes},
         "passes_ms": {k: {"total_ms": v[0] / args.steps, "launches": v[1] // args.steps} for k, v in passes.items()},
+        "two_calls": two_calls,
         "fp64_form": fp64,
         "forms": forms,
         "cpu_baseline": cpu,
