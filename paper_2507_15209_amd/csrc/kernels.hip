@@ -581,6 +581,31 @@ __device__ __forceinline__ void mfma_contract_pencil(const float2* A, const floa
   }
 }
 
+// the same for z in [z0, z1) (even bounds), all by the calling wave
+__device__ __forceinline__ void mfma_contract_pencil_range(const float2* A, const float* dl, int nbins, int RS, int z0,
+                                                           int z1, MfmaAcc& acc) {
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 15, kq = lane >> 4;
+  const int zz = kq >> 1, comp = kq & 1;
+  const bool two = nbins > 16;
+  const bool ok0 = col < nbins, ok1 = 16 + col < nbins;
+  const float* r0 = reinterpret_cast<const float*>(A + col * RS) + comp;
+  const float* r1 = reinterpret_cast<const float*>(A + (16 + col) * RS) + comp;
+#pragma unroll 8
+  for (int zp = z0 / 2; zp < z1 / 2; ++zp) {
+    const int z = 2 * zp + zz;
+    const int off = 2 * lds_pos<true>(z);
+    const float d = dl[z];
+    const float v0 = ok0 ? r0[off] : 0.f;
+    acc.c00 = __builtin_amdgcn_mfma_f32_16x16x4f32(d * v0, v0, acc.c00, 0, 0, 0);
+    if (two) {
+      const float v1 = ok1 ? r1[off] : 0.f;
+      acc.c01 = __builtin_amdgcn_mfma_f32_16x16x4f32(d * v0, v1, acc.c01, 0, 0, 0);
+      acc.c11 = __builtin_amdgcn_mfma_f32_16x16x4f32(d * v1, v1, acc.c11, 0, 0, 0);
+    }
+  }
+}
+
 // 17..20 bins: the 15 upper-triangle 4x4 blocks (g1 <= g2 of 5 bin groups)
 // of P on v_mfma_f32_4x4x1f32, 16 independent 4x4 outer products per
 // instruction, one instruction per k = (z, re/im): a third of the matrix-core
@@ -609,6 +634,32 @@ __device__ __forceinline__ void mfma_contract_4x4(const float2* A, const float* 
   const float2* rb = A + (okb ? bb : 0) * RS;
   // three accumulators in rotation keep dependent matrix-core issues apart
   for (int z = 2 * w; z < K; z += 2 * nw) {
+    const int zp0 = lds_pos<true>(z), zp1 = lds_pos<true>(z + 1);
+    const float d0 = dl[z], d1 = dl[z + 1];
+    const float2 u0 = oka ? ra[zp0] : make_float2(0.f, 0.f);
+    const float2 v0 = okb ? rb[zp0] : make_float2(0.f, 0.f);
+    const float2 u1 = oka ? ra[zp1] : make_float2(0.f, 0.f);
+    const float2 v1 = okb ? rb[zp1] : make_float2(0.f, 0.f);
+    acc.c00 = __builtin_amdgcn_mfma_f32_4x4x1f32(d0 * u0.x, v0.x, acc.c00, 0, 0, 0);
+    acc.c01 = __builtin_amdgcn_mfma_f32_4x4x1f32(d0 * u0.y, v0.y, acc.c01, 0, 0, 0);
+    acc.c11 = __builtin_amdgcn_mfma_f32_4x4x1f32(d1 * u1.x, v1.x, acc.c11, 0, 0, 0);
+    acc.c00 = __builtin_amdgcn_mfma_f32_4x4x1f32(d1 * u1.y, v1.y, acc.c00, 0, 0, 0);
+  }
+}
+
+// the same for z in [z0, z1) (even bounds), all by the calling wave
+__device__ __forceinline__ void mfma_contract_4x4_range(const float2* A, const float* dl, int nbins, int RS, int z0,
+                                                        int z1, MfmaAcc& acc) {
+  const int lane = threadIdx.x & 63;
+  const int beta = lane >> 2, i = lane & 3;
+  int g1 = 0, g2 = 0;
+  if (beta < 15) pair_group(beta, g1, g2);
+  const int ba = 4 * g1 + i, bb = 4 * g2 + i;
+  const bool oka = beta < 15 && ba < nbins, okb = beta < 15 && bb < nbins;
+  const float2* ra = A + (oka ? ba : 0) * RS;
+  const float2* rb = A + (okb ? bb : 0) * RS;
+#pragma unroll 8
+  for (int z = z0; z < z1; z += 2) {
     const int zp0 = lds_pos<true>(z), zp1 = lds_pos<true>(z + 1);
     const float d0 = dl[z], d1 = dl[z + 1];
     const float2 u0 = oka ? ra[zp0] : make_float2(0.f, 0.f);
@@ -744,6 +795,17 @@ struct Contractor {
           for (int k = 0; k < 4; ++k) acc[i * 4 + k] += x1[i].x * x2[k].x + x1[i].y * x2[k].y;
       }
     }
+  }
+
+  // matrix-core forms only: z in [z0, z1) by the calling wave alone
+  __device__ void add_range(const c2<T>* A, const T* w, int nbins, int RS, int z0, int z1) {
+    static_assert(MF && !SPLIT, "range contraction: matrix-core float32 forms");
+    if constexpr (QUAD)
+      mfma_contract_4x4_range(reinterpret_cast<const float2*>(A), reinterpret_cast<const float*>(w), nbins, RS, z0, z1,
+                              macc);
+    else
+      mfma_contract_pencil_range(reinterpret_cast<const float2*>(A), reinterpret_cast<const float*>(w), nbins, RS, z0,
+                                 z1, macc);
   }
 
   // LDS bytes finish() needs as scratch
@@ -1379,9 +1441,16 @@ __global__ void __launch_bounds__(512) k_zpass_adjoint(c2<T>* fields, const T* d
     transform_pencil_bins<N, T, VZA<T>>(fbase, N3, nbins, A, tws, vcur);
     __syncthreads();
     if constexpr (FUSED) {
-      // contraction of the fields before the sources overwrite them
-      ctr.add(A, dl, nbins, RS, N);
-      __syncthreads();
+      // contraction of the fields before the sources overwrite them.  On the
+      // matrix cores each wave contracts the 64 z columns whose sources its
+      // own threads form next, so no barrier separates the two steps.
+      if constexpr (MF) {
+        const int z0 = 64 * (tid >> 6);
+        if (z0 < N) ctr.add_range(A, dl, nbins, RS, z0, z0 + 64 < N ? z0 + 64 : N);
+      } else {
+        ctr.add(A, dl, nbins, RS, N);
+        __syncthreads();
+      }
     }
 #pragma unroll
     for (int k = 0; k < DPRE; ++k) {
