@@ -191,10 +191,13 @@ int mp3_zeta_backward(mp3_plan_t plan, const void* delta, const double* dzeta,
  * Arguments, layouts, workspace and error codes are those of the two calls.
  * Nodal form, float32 or float64, at most 32 bins: each (l, m) computes the
  * window, y and x passes once, and one z pass both contracts the fields and
- * forms the adjoint sources, so the fields are neither stored nor computed
- * twice.  Other forms, BF16-split plans and more bins run mp3_zeta and then
- * mp3_zeta_backward (same results).  The results agree with the two
- * separate calls to rounding order (the z transforms use another radix plan). */
+ * forms the adjoint sources, so the fields are neither stored across (l, m)
+ * nor computed twice.  Particle form: the per-call steps (tile sort, stencil
+ * records, power histogram) run once and each (l, m)'s stored fields feed
+ * both the gather contraction and the adjoint sources.  The grid-Gamma form,
+ * BF16-split nodal plans and nodal plans above 32 bins run mp3_zeta and then
+ * mp3_zeta_backward.  The results agree with the two separate calls to
+ * rounding order (the nodal z transforms use another radix plan). */
 int mp3_zeta_value_and_grad(mp3_plan_t plan, const void* delta, const double* dzeta,
                             double* zeta, void* ddelta, const float* pos, const float* w,
                             const int64_t* np_off, void* dw, void* workspace,

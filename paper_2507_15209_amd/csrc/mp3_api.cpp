@@ -765,6 +765,120 @@ int backward_particle(mp3_plan_t p, const void* delta, const double* dzeta, void
 // replaced by the quadrature of the B-spline reconstructions (k_gamma_adjoint
 // produces c_b and the direct term per (l, m)); the same adjoint transforms
 // and deposit chain rule follow.
+// One sweep of the particle form: the forward's and the adjoint's per-call
+// steps run once, and per (l, m) the stored fields feed both the contraction
+// (gather_contract) and the adjoint sources (gather_source).
+int value_and_grad_particle(mp3_plan_t p, const void* delta, const double* dzeta, double* zeta, void* ddelta,
+                            const float* pos, const float* w, const int64_t* np_off, void* dw, void* ws, size_t wsb,
+                            hipStream_t st) {
+  long long np_total = 0, np_max = 0;
+  if (int s = check_offsets(p, np_off, &np_total, &np_max)) return s;
+  if (!pos) return fail(MP3_EINVAL, "pos is NULL (particle summation needs the catalogue)");
+  if (np_total >= (1LL << 31)) return fail(MP3_EUNSUPPORTED, "more than 2^31 - 1 particles");
+  const Layout L = layout(p, np_total);
+  if (int s = check_ws(p, ws, wsb, L.total)) return s;
+  const int nb2 = p->nbins * p->nbins;
+  const long long n3 = (long long)p->n * p->n * p->n;
+  const double n3d = (double)n3;
+  const double sc = (double)p->n / p->box;
+  if (int s = forward_dft(p, delta, ws, L, st)) return s;
+  MP3_HIP(mp3::launch_fill_f64(zeta, (long long)p->batch * (p->lmax + 1) * nb2, 0.0, st), "zero zeta");
+  if (int s = upload_offsets(p, np_off, ws, L, st)) return s;
+  const long long* off = reinterpret_cast<const long long*>(at(ws, L.off));
+  double* W = reinterpret_cast<double*>(at(ws, L.W));
+  MP3_HIP(mp3::launch_fill_f64(W, p->batch, 0.0, st), "zero W");
+  MP3_HIP(mp3::launch_weight_sum(w, off, p->batch, np_max, W, st), "weight sum");
+  int* perm = reinterpret_cast<int*>(at(ws, L.perm));
+  const int* toff = reinterpret_cast<const int*>(at(ws, L.offs));
+  MP3_HIP(mp3::launch_tile_sort(pos, off, p->batch, np_total, p->n, sc, 2, reinterpret_cast<int*>(at(ws, L.counts)),
+                                reinterpret_cast<int*>(at(ws, L.offs)), reinterpret_cast<int*>(at(ws, L.cursor)), perm, st),
+          "tile sort");
+  int* tcell = reinterpret_cast<int*>(at(ws, L.tcell));
+  void* twt = at(ws, L.twt);
+  MP3_HIP(mp3::launch_tap_records(p->prec, pos, perm, np_total, p->n, sc, tcell, twt, st), "stencil records");
+  double* P = reinterpret_cast<double*>(at(ws, L.power));
+  const int nq2 = mp3::nq2_count(p->n);
+  MP3_HIP(mp3::launch_fill_f64(P, (long long)p->batch * nq2, 0.0, st), "zero power");
+  MP3_HIP(mp3::launch_power_hist(p->prec, at(ws, L.dhat), p->n, nq2, P, p->batch, st), "power histogram");
+  void* F = at(ws, L.fields);
+  void* Fi = at(ws, L.fields_i);
+  void* G = at(ws, L.G);
+  void* direct = at(ws, L.direct);
+  void* src = at(ws, L.src);
+  double* FJ = reinterpret_cast<double*>(at(ws, L.fj));
+  double* partials = reinterpret_cast<double*>(at(ws, L.partials));
+  MP3_HIP(mp3::launch_fill(p->prec, G, 2 * n3 * p->batch, 0.0, st), "zero G");
+  MP3_HIP(mp3::launch_fill(p->prec, direct, n3 * p->batch, 0.0, st), "zero direct");
+  MP3_HIP(mp3::launch_fill_f64(FJ, np_total, 0.0, st), "zero F_J");
+  const int gwg = gather_wgs(p, np_max);
+  for (int l = 0; l <= p->lmax; ++l) {
+    MP3_HIP(mp3::launch_lam_sym(p->prec, dzeta, at(ws, L.lam), p->nbins, l, p->lmax, p->batch, st), "lambda");
+    for (int m = 0; m <= l; ++m) {
+      const double wm = m == 0 ? 1.0 : 2.0;
+      if (int s = fields_xy(p, ws, L, F, l, m, st)) return s;
+      mp3::ZpassArgs z{};
+      z.fields = F;
+      z.tw = p->tw;
+      z.nbins = p->nbins;
+      z.nwg = L.nwg;
+      z.ppw = L.ppw;
+      z.batch = p->batch;
+      MP3_HIP(timed(p, MP3_PASS_Z_STORE, st, [&] { return mp3::launch_zpass_store(p->n, p->prec, z, Fi, st); }), "z pass (store)");
+      mp3::GatherArgs g{};
+      g.fields = Fi;
+      g.tcell = tcell;
+      g.twt = twt;
+      g.pos = pos;
+      g.w = w;
+      g.perm = perm;
+      g.off = off;
+      g.W = W;
+      g.partials = partials;
+      g.n = p->n;
+      g.nbins = p->nbins;
+      g.nwg = gwg;
+      g.batch = p->batch;
+      g.sc = sc;
+      g.split = p->split;
+      MP3_HIP(timed(p, MP3_PASS_GATHER, st, [&] { return mp3::launch_gather_contract(p->prec, g, st); }), "gather");
+      MP3_HIP(mp3::launch_reduce_partials(partials, gwg, nb2, zeta, l, p->lmax, wm * kFourPi, p->batch, st), "reduce");
+      MP3_HIP(timed(p, MP3_PASS_GATHER, st, [&] {
+                return mp3::launch_gather_source(p->prec, Fi, tcell, twt, w, perm, off, W, at(ws, L.lam), p->n, p->nbins,
+                                                 wm, gwg, p->batch, FJ, src, st);
+              }),
+              "gather (adjoint sources)");
+      MP3_HIP(timed(p, MP3_PASS_SCATTER, st, [&] {
+                return mp3::launch_scatter_source(p->prec, tcell, twt, toff, src, p->n, p->nbins, p->batch, F, st);
+              }),
+              "scatter (adjoint sources)");
+      MP3_HIP(timed(p, MP3_PASS_Z_ADJOINT, st, [&] { return mp3::launch_fft_z(p->n, p->prec, +1, F, F, p->batch * p->nbins, p->tw, st); }),
+              "adjoint z pass");
+      MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, F, p->batch * p->nbins, p->tw, p->tune[MP3_TUNE_FFT_X_PLAN], st); }),
+              "adjoint x pass");
+      mp3::FilterArgs a = filter_args(p, F, G, l, m, wm / n3d);
+      MP3_HIP(timed(p, MP3_PASS_ADJOINT, st, [&] { return mp3::launch_adjoint_y(p->n, p->prec, a, st); }), "adjoint window pass");
+    }
+    MP3_HIP(mp3::launch_fbar_subtract(p->prec, P, p->jtab, nq2, p->nbp, p->nbins, l, p->lmax, n3d * n3d, zeta, p->batch, st),
+            "volume mean");
+  }
+  MP3_HIP(mp3::launch_fbar_adjoint(p->prec, dzeta, p->jtab, p->nq2, p->nbp, p->nbins, p->lmax, at(ws, L.dhat), p->n,
+                                   -1.0 / (kFourPi * n3d), reinterpret_cast<double*>(at(ws, L.hq)), G, p->batch, st),
+          "volume-mean adjoint");
+  MP3_HIP(timed(p, MP3_PASS_DFT, st, [&] { return mp3::launch_fft3d(p->n, p->prec, -1, false, G, G, p->batch, p->tw, st); }), "adjoint final FFT");
+  MP3_HIP(mp3::launch_grad_combine(p->prec, direct, G, ddelta, n3 * p->batch, kFourPi / n3d, st), "combine");
+  if (dw) {
+    double* S = reinterpret_cast<double*>(at(ws, L.S));
+    double* SF = reinterpret_cast<double*>(at(ws, L.SF));
+    MP3_HIP(mp3::launch_fill_f64(S, p->batch, 0.0, st), "zero S");
+    MP3_HIP(mp3::launch_fill_f64(SF, p->batch, 0.0, st), "zero SF");
+    MP3_HIP(mp3::launch_dot_rho_g(p->prec, delta, ddelta, n3, S, p->batch, st), "dot");
+    MP3_HIP(mp3::launch_gather_dw(p->prec, pos, off, p->batch, np_total, p->n, sc, ddelta, W, S, dw, st), "gather dw");
+    MP3_HIP(mp3::launch_weighted_sum(w, FJ, off, p->batch, np_max, SF, st), "sum w F_J");
+    MP3_HIP(mp3::launch_primary_dw(p->prec, off, p->batch, np_total, FJ, W, SF, dw, st), "primary dw");
+  }
+  return MP3_OK;
+}
+
 int backward_gamma(mp3_plan_t p, const void* delta, const double* dzeta, void* ddelta, const float* pos,
                    const float* w, const int64_t* np_off, void* dw, void* ws, size_t wsb, void* stream) {
   if (mp3::gamma_adjoint_lds_need(p->prec, p->nbins) > kLdsLimit)
@@ -889,6 +1003,9 @@ int mp3_zeta_value_and_grad(mp3_plan_t p, const void* delta, const double* dzeta
                             void* stream) {
   if (int s = check_plan(p)) return s;
   if (!delta || !dzeta || !zeta || !ddelta) return fail(MP3_EINVAL, "delta, dzeta, zeta and ddelta must not be NULL");
+  if (p->summation == MP3_SUM_PARTICLE)
+    return value_and_grad_particle(p, delta, dzeta, zeta, ddelta, pos, w, np_off, dw, ws, wsb,
+                                   static_cast<hipStream_t>(stream));
   const int storage = p->prec;
   const bool one_sweep = p->summation == MP3_SUM_NODAL && !p->split && p->nbins <= 32 &&
                          mp3::zpass_fused_lds_need(p->n, storage, p->nbins) <= kLdsLimit;

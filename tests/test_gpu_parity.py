@@ -584,3 +584,25 @@ def test_value_and_grad_batch_and_other_forms(mp3):
         for a1, a0 in ((g1, g0), (w1, w0)):
             a1, a0 = a1.cpu().numpy(), a0.cpu().numpy()
             assert np.abs(a1 - a0).max() <= agree * np.abs(a0).max()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_value_and_grad_particle(mp3, prec):
+    """Particle form in one sweep: zeta, dJ/ddelta and dJ/dw against the oracle."""
+    _say("value and grad particle", prec)
+    n, lmax, nb, npart = 32, 3, 5, 20000
+    box = 8.0 * n
+    edges = np.linspace(0.06 * box, 0.35 * box, nb + 1)
+    pos, w = lognormal_catalogue(n, box, npart, 0.04 * box, 121, 122, 123, (0.5, 1.5))
+    lam = np.random.default_rng(124).standard_normal((1, lmax + 1, nb, nb))
+    plan = mp3.Plan(n, box, lmax, edges, precision=prec, summation="particle")
+    pt, wt = _dev(pos, torch.float32), _dev(w, torch.float32)
+    delta = plan.deposit(pt, wt)
+    z, g, dw = plan.zeta_value_and_grad(delta, _dev(lam, torch.float64), pt, wt)
+    op = E.Plan(n, box, lmax, edges)
+    assert_zeta_close(z.cpu().numpy()[0], E.zeta_particle(op, pos, w), TOL[prec])
+    gref, dwref = A.zeta_particle_grad(op, pos, w, lam[0])
+    eg = np.linalg.norm(g.cpu().numpy()[0] - gref) / np.linalg.norm(gref)
+    ew = np.linalg.norm(dw.cpu().numpy() - dwref) / np.linalg.norm(dwref)
+    print("grad errors", eg, ew)
+    assert eg <= TOL[prec] and ew <= TOL[prec], (eg, ew)
