@@ -1093,16 +1093,27 @@ __device__ __forceinline__ c2<T> gather_record(const c2<T>* fm, int cell, const 
 // Gather the B-spline interpolants of the (bin-interleaved) fields at the
 // particles, one lane per (particle, bin), into LDS rows, then contract with
 // the weights w_i / W.  Particles are visited in tile order (perm).
-template <typename T, bool MF, bool SPLIT = false, bool QUAD = false>
+// SRC: the same gathered values also give the adjoint sources of
+// k_gather_source (value and gradient in one sweep): per particle
+// v_b = sum_b' lam_s[b][b'] conj(atilde_b'), src = N^3 (w_i / W) v, and
+// wm Re(sum_b atilde_b v_b) added to F_J(u_i); the contraction and the sources
+// only read the slice's rows, so they share one phase.
+template <typename T, bool MF, bool SPLIT = false, bool QUAD = false, bool SRC = false>
 __global__ void __launch_bounds__(256) k_gather_contract(const c2<T>* fields, const int* tcell, const T* twt,
                                                           const float* w, const int* perm, const long long* off,
-                                                          const double* W, int n, int nbins, double* partials) {
+                                                          const double* W, int n, int nbins, double* partials,
+                                                          const T* lam_s, T wm, double* FJ, c2<T>* src) {
   constexpr int K = 256;                                // particles per contraction slice
   constexpr int RS = K + K / 16 + 1;
   extern __shared__ __align__(16) char smem[];
   c2<T>* A = reinterpret_cast<c2<T>*>(smem);
   T* wk = reinterpret_cast<T*>(A + nbins * RS);
+  int* pk = reinterpret_cast<int*>(wk + K);             // SRC: particle index of slot k
+  T* lam = reinterpret_cast<T*>(pk + K);                // SRC: [nbins][nbins]
   const long long mock = blockIdx.y;
+  if constexpr (SRC) {
+    for (int t = threadIdx.x; t < nbins * nbins; t += blockDim.x) lam[t] = lam_s[mock * nbins * nbins + t];
+  }
   const long long n3 = (long long)n * n * n;
   const long long a0 = off[mock], a1 = off[mock + 1];
   const long long per = (a1 - a0 + gridDim.x - 1) / gridDim.x;
@@ -1112,6 +1123,7 @@ __global__ void __launch_bounds__(256) k_gather_contract(const c2<T>* fields, co
   const int ppp = blockDim.x / lpp;                     // particles per pass
   const int b = threadIdx.x % lpp;
   const c2<T>* fm = fields + mock * n3 * nbins;
+  const double fw = (double)n3 / W[mock];
   Contractor<T, MF, SPLIT, QUAD> ctr;
   ctr.init(nbins);
   for (long long c0 = s0; c0 < s1; c0 += K) {
@@ -1120,17 +1132,45 @@ __global__ void __launch_bounds__(256) k_gather_contract(const c2<T>* fields, co
       const long long si = c0 + k;
       c2<T> acc = mk<T>(0, 0);
       T wgt = 0;
+      int i = -1;
       if (si < s1) {
-        const int i = perm[si];
+        i = perm[si];
         const int cell = tcell[si];
         if (cell >= 0 && b < nbins) acc = gather_record<T>(fm, cell, twt + si * 12, n, nbins, b);
         wgt = (T)((w ? (double)w[i] : 1.0) * invW);
       }
       if (b < nbins) A[b * RS + lds_pos<true>(k)] = acc;
-      if (b == 0) wk[k] = wgt;
+      if (b == 0) {
+        wk[k] = wgt;
+        if constexpr (SRC) pk[k] = i;
+      }
     }
     __syncthreads();
     ctr.add(A, wk, nbins, RS, K);
+    if constexpr (SRC) {
+      for (int k0 = 0; k0 < K; k0 += ppp) {
+        const int k = k0 + threadIdx.x / lpp;
+        const long long si = c0 + k;
+        const bool has = si < s1;
+        T fj = 0;
+        if (has && b < nbins) {
+          const int kp = lds_pos<true>(k);
+          c2<T> v = mk<T>(0, 0);
+          for (int bp = 0; bp < nbins; ++bp) {
+            const c2<T> a = A[bp * RS + kp];
+            const T lv = lam[b * nbins + bp];
+            v.x += lv * a.x;
+            v.y -= lv * a.y;
+          }
+          const c2<T> a = A[b * RS + kp];
+          fj = a.x * v.x - a.y * v.y;
+          const T f = (T)(fw * (w ? (double)w[pk[k]] : 1.0));
+          src[si * nbins + b] = mk<T>(f * v.x, f * v.y);
+        }
+        for (int o = lpp / 2; o > 0; o >>= 1) fj += __shfl_xor(fj, o, lpp);
+        if (has && b == 0) FJ[pk[k]] += (double)wm * (double)fj;
+      }
+    }
     __syncthreads();
   }
   ctr.finish(reinterpret_cast<double*>(smem), partials + ((long long)mock * gridDim.x + blockIdx.x) * nbins * nbins,
@@ -2766,20 +2806,31 @@ hipError_t launch_deposit_tiled(int prec, int tside, const float* pos, const flo
   return deposit_tiled_t<float>(tside, pos, w, perm, toff, ntiles_total, g, counter, n, sc, static_cast<float*>(eps), st);
 }
 
-template <typename T, bool MF, bool SPLIT = false, bool QUAD = false>
-hipError_t gather_contract_t(const GatherArgs& a, hipStream_t st) {
+template <typename T, bool MF, bool SPLIT, bool QUAD, bool SRC>
+hipError_t gather_contract_v(const GatherArgs& a, hipStream_t st) {
   constexpr int K = 256;
   const size_t rs = K + K / 16 + 1;
   size_t lds = (size_t)a.nbins * rs * sizeof(CT<T>) + K * sizeof(T);
+  if (SRC) lds += K * sizeof(int) + (size_t)a.nbins * a.nbins * sizeof(T);
   const size_t red = Contractor<T, MF, SPLIT, QUAD>::scratch_bytes(256);
   if (lds < red) lds = red;
-  hipError_t e = allow_lds(k_gather_contract<T, MF, SPLIT, QUAD>, lds);
+  hipError_t e = allow_lds(k_gather_contract<T, MF, SPLIT, QUAD, SRC>, lds);
   if (e != hipSuccess) return e;
   const dim3 gs(a.nwg, a.batch);
-  k_gather_contract<T, MF, SPLIT, QUAD><<<gs, 256, lds, st>>>(static_cast<const CT<T>*>(a.fields), a.tcell,
-                                                             static_cast<const T*>(a.twt), a.w, a.perm, a.off, a.W,
-                                                             a.n, a.nbins, a.partials);
+  k_gather_contract<T, MF, SPLIT, QUAD, SRC><<<gs, 256, lds, st>>>(
+      static_cast<const CT<T>*>(a.fields), a.tcell, static_cast<const T*>(a.twt), a.w, a.perm, a.off, a.W, a.n, a.nbins,
+      a.partials, static_cast<const T*>(a.lam), (T)a.wm, a.FJ, static_cast<CT<T>*>(a.src));
   return hipGetLastError();
+}
+
+template <typename T, bool MF, bool SPLIT = false, bool QUAD = false>
+hipError_t gather_contract_t(const GatherArgs& a, hipStream_t st) {
+  if constexpr (std::is_same<T, double>::value) {
+    if (a.src) return gather_contract_v<T, MF, SPLIT, QUAD, true>(a, st);
+  } else {
+    if (a.src) return hipErrorInvalidValue;      // float32 runs the source gather separately
+  }
+  return gather_contract_v<T, MF, SPLIT, QUAD, false>(a, st);
 }
 
 hipError_t launch_gather_contract(int prec, const GatherArgs& a, hipStream_t st) {

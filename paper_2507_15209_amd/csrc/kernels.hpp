@@ -51,6 +51,12 @@ struct GatherArgs {
   int n, nbins, nwg, batch;
   double sc;              // N / box
   bool split;             // float32 contraction with BF16-split inputs on the matrix cores
+  // adjoint sources from the same gather (value and gradient in one sweep) when src != NULL;
+  // float64 plans only (float32 returns hipErrorInvalidValue and runs launch_gather_source)
+  const void* lam;        // lam_s [batch][nbins][nbins]
+  double wm;              // m weight
+  double* FJ;             // [np_total] F_J accumulator
+  void* src;              // [np_total][nbins] sources in sorted order
 };
 
 // grid summation with connection coefficients (5-point Gauss-Legendre per cell);
