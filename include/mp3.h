@@ -194,10 +194,12 @@ int mp3_zeta_backward(mp3_plan_t plan, const void* delta, const double* dzeta,
  * forms the adjoint sources, so the fields are neither stored across (l, m)
  * nor computed twice.  Particle form: the per-call steps (tile sort, stencil
  * records, power histogram) run once and each (l, m)'s stored fields feed
- * both the gather contraction and the adjoint sources.  The grid-Gamma form,
- * BF16-split nodal plans and nodal plans above 32 bins run mp3_zeta and then
+ * both the gather contraction and the adjoint sources.  Grid-Gamma form:
+ * the adjoint's node values of each (l, m) are also contracted for zeta.
+ * BF16-split plans and nodal plans above 32 bins run mp3_zeta and then
  * mp3_zeta_backward.  The results agree with the two separate calls to
- * rounding order (the nodal z transforms use another radix plan). */
+ * rounding order (the nodal z transforms use another radix plan, the
+ * grid-Gamma contraction visits the nodes in another order). */
 int mp3_zeta_value_and_grad(mp3_plan_t plan, const void* delta, const double* dzeta,
                             double* zeta, void* ddelta, const float* pos, const float* w,
                             const int64_t* np_off, void* dw, void* workspace,

@@ -210,9 +210,9 @@ class Plan:
     def zeta_value_and_grad(self, delta, dzeta, pos=None, w=None, np_off=None):
         """Returns (zeta, dJ/ddelta, dJ/dw or None) for J = sum dzeta * zeta in one sweep.
 
-        Same results as zeta() followed by zeta_backward(); the nodal form
-        (float32 / float64, <= 32 bins) and the particle form compute each
-        (l, m)'s fields once for both."""
+        Same results as zeta() followed by zeta_backward(); every form except
+        BF16-split plans (and nodal plans above 32 bins) computes each (l, m)'s
+        fields once for both."""
         self._real(delta, "delta")
         dzeta = dzeta.to(device=self.device, dtype=torch.float64).contiguous()
         if dzeta.numel() != self.batch * (self.lmax + 1) * self.nbins ** 2:

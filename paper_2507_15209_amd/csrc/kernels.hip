@@ -1961,10 +1961,14 @@ struct GammaAdjLds {
 };
 
 // float: 1024 threads, for the same reason as k_gamma_contract; double needs
-// more than the 128 registers a 1024-thread workgroup leaves each lane
-template <typename T>
+// more than the 128 registers a 1024-thread workgroup leaves each lane.
+// FUSED: the node values and weights of each slice are also contracted for
+// zeta (the partials of k_gamma_contract), so value and gradient share one
+// interpolation of the fields.
+template <typename T, bool FUSED = false, bool MF = false, bool QUAD = false>
 __global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) k_gamma_adjoint(const c2<T>* fields, const T* delta, const T* lam_s, int n,
-                                                        int nbins, GammaQuad gq, T wm, c2<T>* cout, T* direct) {
+                                                        int nbins, GammaQuad gq, T wm, c2<T>* cout, T* direct,
+                                                        double* partials) {
   extern __shared__ __align__(16) char smem[];
   const GammaAdjLds<T> L(nbins);
   c2<T>* C = reinterpret_cast<c2<T>*>(smem + L.C);
@@ -1993,6 +1997,8 @@ __global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) k_gamma_adjoint(c
   T* rm = direct + mock * n3;
   const int nb2 = nbins * nbins;
   for (int t = tid; t < nb2; t += nt) lam[t] = lam_s[mock * nb2 + t];
+  Contractor<T, MF, false, QUAD> ctr;
+  if constexpr (FUSED) ctr.init(nbins);
   const int td = n / GT;
   const long long ntiles = (long long)td * td * td;
   constexpr int NC = GC * GC * GC;
@@ -2084,6 +2090,8 @@ __global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) k_gamma_adjoint(c
           Wq[node] = wq;
         }
         __syncthreads();
+        // FUSED: contraction of the node values (read only in this phase)
+        if constexpr (FUSED) ctr.add(A, W, nbins, AGRS, AGK);
         // per node and AGH bins: v_b = sum_b' lam_s[b][b'] conj(a_b'), F; the
         // node's field values are read from LDS once into registers
         c2<T> vh[AGH];
@@ -2221,6 +2229,11 @@ __global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) k_gamma_adjoint(c
       const int i = c / (GC * GC), j = (c / GC) % GC, k = c % GC;
       atomicAdd(&rm[((long long)wrapi(x0 + i, n) * n + wrapi(y0 + j, n)) * n + wrapi(z0 + k, n)], wm * Dt[c]);
     }
+  }
+  if constexpr (FUSED) {
+    __syncthreads();
+    ctr.finish(reinterpret_cast<double*>(smem), partials + ((long long)mock * gridDim.x + blockIdx.x) * nbins * nbins,
+               nbins);
   }
 }
 
@@ -2986,9 +2999,28 @@ hipError_t launch_primary_dw(int prec, const long long* off, int batch, long lon
   return hipGetLastError();
 }
 
+template <typename T, bool FUSED, bool MF, bool QUAD>
+hipError_t gamma_adjoint_v(const void* fields, const void* delta, const void* lam_s, int n, int nbins,
+                           const GammaQuad& gq, double wm, int nwg, int batch, void* cout, void* direct,
+                           double* partials, hipStream_t st) {
+  const int threads = sizeof(T) == 4 ? 1024 : 512;
+  size_t lds = GammaAdjLds<T>(nbins).total;
+  if (FUSED) {
+    const size_t red = Contractor<T, MF, false, QUAD>::scratch_bytes(threads);
+    if (lds < red) lds = red;
+  }
+  hipError_t e = allow_lds(k_gamma_adjoint<T, FUSED, MF, QUAD>, lds);
+  if (e != hipSuccess) return e;
+  const dim3 gs(nwg, batch);
+  k_gamma_adjoint<T, FUSED, MF, QUAD><<<gs, threads, lds, st>>>(
+      static_cast<const CT<T>*>(fields), static_cast<const T*>(delta), static_cast<const T*>(lam_s), n, nbins, gq, (T)wm,
+      static_cast<CT<T>*>(cout), static_cast<T*>(direct), partials);
+  return hipGetLastError();
+}
+
 hipError_t launch_gamma_adjoint(int prec, const void* fields, const void* delta, const void* lam_s, int n, int nbins,
                                 const double (*m)[4], const double* wq, double wm, int nwg, int batch, void* cout,
-                                void* direct, hipStream_t st) {
+                                void* direct, double* partials, hipStream_t st) {
   GammaQuad gq;
   for (int s = 0; s < 5; ++s) {
     for (int t = 0; t < 4; ++t) {
@@ -2998,24 +3030,14 @@ hipError_t launch_gamma_adjoint(int prec, const void* fields, const void* delta,
     gq.wq[s] = (float)wq[s];
     gq.wqd[s] = wq[s];
   }
-  const dim3 gs(nwg, batch);
   if (nbins > AGP * AGH) return hipErrorInvalidValue;
-  if (prec) {
-    const size_t lds = GammaAdjLds<double>(nbins).total;
-    hipError_t e = allow_lds(k_gamma_adjoint<double>, lds);
-    if (e != hipSuccess) return e;
-    k_gamma_adjoint<double><<<gs, 512, lds, st>>>(static_cast<const double2*>(fields), static_cast<const double*>(delta),
-                                                  static_cast<const double*>(lam_s), n, nbins, gq, wm,
-                                                  static_cast<double2*>(cout), static_cast<double*>(direct));
-  } else {
-    const size_t lds = GammaAdjLds<float>(nbins).total;
-    hipError_t e = allow_lds(k_gamma_adjoint<float>, lds);
-    if (e != hipSuccess) return e;
-    k_gamma_adjoint<float><<<gs, 1024, lds, st>>>(static_cast<const float2*>(fields), static_cast<const float*>(delta),
-                                                 static_cast<const float*>(lam_s), n, nbins, gq, (float)wm,
-                                                 static_cast<float2*>(cout), static_cast<float*>(direct));
-  }
-  return hipGetLastError();
+#define MP3_GAMMA_ADJ(T, F, M, Q) \
+  gamma_adjoint_v<T, F, M, Q>(fields, delta, lam_s, n, nbins, gq, wm, nwg, batch, cout, direct, partials, st)
+  // partials != NULL: also contract for zeta (float32 on the matrix cores)
+  if (prec) return partials ? MP3_GAMMA_ADJ(double, true, false, false) : MP3_GAMMA_ADJ(double, false, false, false);
+  if (!partials) return MP3_GAMMA_ADJ(float, false, false, false);
+  return nbins > 16 ? MP3_GAMMA_ADJ(float, true, true, true) : MP3_GAMMA_ADJ(float, true, true, false);
+#undef MP3_GAMMA_ADJ
 }
 
 size_t gamma_adjoint_lds_need(int prec, int nbins) {

@@ -118,10 +118,12 @@ hipError_t launch_fbar_adjoint(int prec, const double* dzeta, const void* jtab, 
                                const void* dhat, int n, double scale, double* h, void* G, int batch, hipStream_t st);
 // grid-Gamma adjoint for one (l, m): adds the transposed-quadrature sources
 // into cout ([batch][nbins][N^3], zeroed by the caller) and wm times the
-// primary's share into direct; fields bin-interleaved, at most 20 bins
+// primary's share into direct; fields bin-interleaved, at most 20 bins.
+// partials != NULL: also writes the forward contraction's partials
+// ([batch][nwg][nbins^2], as launch_gamma_contract) from the same node values
 hipError_t launch_gamma_adjoint(int prec, const void* fields, const void* delta, const void* lam_s, int n, int nbins,
                                 const double (*m)[4], const double* wq, double wm, int nwg, int batch, void* cout,
-                                void* direct, hipStream_t st);
+                                void* direct, double* partials, hipStream_t st);
 size_t gamma_adjoint_lds_need(int prec, int nbins);
 hipError_t launch_primary_dw(int prec, const long long* off, int batch, long long np_total, const double* FJ,
                              const double* W, const double* SF, void* dw, hipStream_t st);

@@ -889,8 +889,11 @@ int value_and_grad_particle(mp3_plan_t p, const void* delta, const double* dzeta
   return MP3_OK;
 }
 
+// zeta != NULL: one sweep, the adjoint kernel also contracts the node values
+// for zeta (float32 or float64 inputs, not the BF16-split option)
 int backward_gamma(mp3_plan_t p, const void* delta, const double* dzeta, void* ddelta, const float* pos,
-                   const float* w, const int64_t* np_off, void* dw, void* ws, size_t wsb, void* stream) {
+                   const float* w, const int64_t* np_off, void* dw, void* ws, size_t wsb, void* stream,
+                   double* zeta = nullptr) {
   if (mp3::gamma_adjoint_lds_need(p->prec, p->nbins) > kLdsLimit)
     return fail(MP3_EUNSUPPORTED, "nbins too large for the grid-Gamma adjoint tile's LDS at this precision");
   long long np_total = 0, np_max = 0;
@@ -907,10 +910,14 @@ int backward_gamma(mp3_plan_t p, const void* delta, const double* dzeta, void* d
   void* Fi = at(ws, L.fields_i);
   void* G = at(ws, L.G);
   void* direct = at(ws, L.direct);
+  double* partials = zeta ? reinterpret_cast<double*>(at(ws, L.partials)) : nullptr;
+  const int nb2 = p->nbins * p->nbins;
+  if (zeta) MP3_HIP(mp3::launch_fill_f64(zeta, (long long)p->batch * (p->lmax + 1) * nb2, 0.0, st), "zero zeta");
   MP3_HIP(mp3::launch_fill(p->prec, G, 2 * n3 * p->batch, 0.0, st), "zero G");
   MP3_HIP(mp3::launch_fill(p->prec, direct, n3 * p->batch, 0.0, st), "zero direct");
   const long long tiles = (long long)(p->n / 4) * (p->n / 4) * (p->n / 4);
   long long gwg = (long long)contract_wgs(p);
+  if (gwg < 1) gwg = 1;
   if (gwg > tiles) gwg = tiles;
   for (int l = 0; l <= p->lmax; ++l) {
     MP3_HIP(mp3::launch_lam_sym(p->prec, dzeta, at(ws, L.lam), p->nbins, l, p->lmax, p->batch, st), "lambda");
@@ -928,9 +935,13 @@ int backward_gamma(mp3_plan_t p, const void* delta, const double* dzeta, void* d
       MP3_HIP(mp3::launch_fill(p->prec, F, 2 * n3 * p->batch * p->nbins, 0.0, st), "zero sources");
       MP3_HIP(timed(p, MP3_PASS_GAMMA, st, [&] {
                 return mp3::launch_gamma_adjoint(p->prec, Fi, delta, at(ws, L.lam), p->n, p->nbins, p->gm, p->gw, wm,
-                                                 (int)gwg, p->batch, F, direct, st);
+                                                 (int)gwg, p->batch, F, direct, partials, st);
               }),
               "grid-Gamma adjoint");
+      if (zeta)
+        MP3_HIP(mp3::launch_reduce_partials(partials, (int)gwg, nb2, zeta, l, p->lmax, wm * kFourPi / (double)n3,
+                                            p->batch, st),
+                "reduce");
       MP3_HIP(timed(p, MP3_PASS_Z_ADJOINT, st, [&] { return mp3::launch_fft_z(p->n, p->prec, +1, F, F, p->batch * p->nbins, p->tw, st); }),
               "adjoint z pass");
       MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, F, p->batch * p->nbins, p->tw, p->tune[MP3_TUNE_FFT_X_PLAN], st); }),
@@ -1016,6 +1027,8 @@ int mp3_zeta_value_and_grad(mp3_plan_t p, const void* delta, const double* dzeta
   if (p->summation == MP3_SUM_PARTICLE)
     return value_and_grad_particle(p, delta, dzeta, zeta, ddelta, pos, w, np_off, dw, ws, wsb,
                                    static_cast<hipStream_t>(stream));
+  if (p->summation == MP3_SUM_GRID_GAMMA && !p->split)
+    return backward_gamma(p, delta, dzeta, ddelta, pos, w, np_off, dw, ws, wsb, stream, zeta);
   const int storage = p->prec;
   const bool one_sweep = p->summation == MP3_SUM_NODAL && !p->split && p->nbins <= 32 &&
                          mp3::zpass_fused_lds_need(p->n, storage, p->nbins) <= kLdsLimit;

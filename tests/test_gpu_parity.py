@@ -606,3 +606,27 @@ def test_value_and_grad_particle(mp3, prec):
     ew = np.linalg.norm(dw.cpu().numpy() - dwref) / np.linalg.norm(dwref)
     print("grad errors", eg, ew)
     assert eg <= TOL[prec] and ew <= TOL[prec], (eg, ew)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("nb", [3, 18])
+def test_value_and_grad_gamma(mp3, prec, nb):
+    """Grid-Gamma form in one sweep (the adjoint kernel also contracts): zeta and dJ/ddelta against the oracle."""
+    if prec == "f64" and nb > 9:
+        pytest.skip("the float64 grid-Gamma adjoint tile holds at most 9 bins")
+    _say("value and grad gamma", prec, nb)
+    n, box, lmax = 16, 160.0, 2
+    edges = np.linspace(15.0, 55.0, nb + 1)
+    delta = random_field(n, 131 + nb)
+    lam = np.random.default_rng(132 + nb).standard_normal((lmax + 1, nb, nb))
+    plan = mp3.Plan(n, box, lmax, edges, precision=prec, summation="gamma")
+    dd = _dev(delta[None], torch.float64 if prec == "f64" else torch.float32)
+    z, g, _ = plan.zeta_value_and_grad(dd, _dev(lam[None], torch.float64))
+    op = E.Plan(n, box, lmax, edges)
+    assert_zeta_close(z.cpu().numpy()[0], E.zeta_gamma(op, delta), TOL[prec])
+    gref = A.zeta_gamma_grad(op, delta, lam)
+    eg = np.linalg.norm(g.cpu().numpy()[0] - gref) / np.linalg.norm(gref)
+    print("grad error", eg)
+    assert eg <= TOL[prec], eg
+    zz = z.cpu().numpy()[0]
+    assert np.abs(zz - zz.transpose(0, 2, 1)).max() <= 1e-12 * np.abs(zz).max()
