@@ -156,10 +156,24 @@ template <int N, int V = 0> struct Fft {
 // LDS addressing of a column: element i at base[(i + pad(i)) * ld]
 template <bool PAD> __device__ __forceinline__ int lds_pos(int i) { return PAD ? i + (i >> 4) : i; }
 
+// Synchronisation of a column's exchange: the workgroup, or, when all
+// threads of the column are lanes of one wave (WAVE), that wave alone:
+// workgroup-scope fences order the LDS accesses and the wave barrier keeps
+// the compiler from moving them across.
+template <bool WAVE> __device__ __forceinline__ void col_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  } else {
+    __syncthreads();
+  }
+}
+
 // One radix stage (compile-time stage index S_IDX, Ns = product of earlier
 // radices): twiddle, butterflies, and -- unless it is the last stage -- the
 // LDS exchange that gathers the next stage's inputs.
-template <int N, int S_IDX, int DIR, typename T, bool PAD, int V>
+template <int N, int S_IDX, int DIR, typename T, bool PAD, int V, bool WAVE = false>
 __device__ __forceinline__ void fft_stage(c2<T>* v, c2<T>* col, int ld, int j, const c2<T>* tw, bool active, int Ns) {
   using F = Fft<N, V>;
   constexpr int RMAX = F::RMAX;
@@ -189,7 +203,7 @@ __device__ __forceinline__ void fft_stage(c2<T>* v, c2<T>* col, int ld, int j, c
         for (int r = 0; r < R; ++r) col[lds_pos<PAD>(base + r * Ns) * ld] = v[t * R + r];
       }
     }
-    __syncthreads();
+    col_sync<WAVE>();
     constexpr int Rn = FftPlan<N, V>::R[S_IDX + 1];
     constexpr int BPTn = RMAX / Rn;
     if (active) {
@@ -200,8 +214,8 @@ __device__ __forceinline__ void fft_stage(c2<T>* v, c2<T>* col, int ld, int j, c
         for (int r = 0; r < Rn; ++r) v[t * Rn + r] = col[lds_pos<PAD>(jj + r * (N / Rn)) * ld];
       }
     }
-    __syncthreads();
-    fft_stage<N, S_IDX + 1, DIR, T, PAD, V>(v, col, ld, j, tw, active, Ns * R);
+    col_sync<WAVE>();
+    fft_stage<N, S_IDX + 1, DIR, T, PAD, V, WAVE>(v, col, ld, j, tw, active, Ns * R);
   }
 }
 
@@ -210,10 +224,12 @@ __device__ __forceinline__ void fft_stage(c2<T>* v, c2<T>* col, int ld, int j, c
 // (element i at col[lds_pos<PAD>(i) * ld]); it is used as exchange space.
 // Every thread of the workgroup must call this the same number of times
 // (it contains __syncthreads when N has more than one stage); threads without
-// a column pass active = false.
-template <int N, int DIR, typename T, bool PAD, int V = 0>
+// a column pass active = false.  WAVE: the caller guarantees that the TPC
+// threads of every column are lanes of one wave (consecutive thread indices,
+// TPC dividing 64); the exchanges then synchronise that wave only.
+template <int N, int DIR, typename T, bool PAD, int V = 0, bool WAVE = false>
 __device__ __forceinline__ void fft_column(c2<T>* v, c2<T>* col, int ld, int j, const c2<T>* tw, bool active) {
-  fft_stage<N, 0, DIR, T, PAD, V>(v, col, ld, j, tw, active, 1);
+  fft_stage<N, 0, DIR, T, PAD, V, WAVE>(v, col, ld, j, tw, active, 1);
 }
 
 }  // namespace mp3

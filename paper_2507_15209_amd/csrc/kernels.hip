@@ -360,7 +360,7 @@ __global__ void __launch_bounds__((contig_pencils<N, T>() * Fft<N>::TPC)) k_fft_
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) v[r] = in[pen * N + F::in_index(j, r)];
   }
-  fft_column<N, DIR, T, true>(v, lds + p * RS, 1, j, tw, active);
+  fft_column<N, DIR, T, true, 0, 64 % Fft<N>::TPC == 0>(v, lds + p * RS, 1, j, tw, active);
   if (active) {
 #pragma unroll
     for (int e = 0; e < RMAX; ++e) out[pen * N + F::out_index(j, e)] = v[e];
@@ -520,7 +520,7 @@ __device__ __forceinline__ void transform_round(int nbins, int rr, c2<T>* v, c2<
   asm volatile("" : "+v"(j));
   const int b = rr * nbc + threadIdx.x / F::TPC;
   const bool active = b < nbins;
-  fft_column<N, +1, T, true, V>(v, A + (active ? b : 0) * RS, 1, j, tw, active);
+  fft_column<N, +1, T, true, V, 64 % Fft<N, V>::TPC == 0>(v, A + (active ? b : 0) * RS, 1, j, tw, active);
   if (active) {
 #pragma unroll
     for (int e = 0; e < F::RMAX; ++e) A[b * RS + lds_pos<true>(F::out_index(j, e))] = v[e];
@@ -1542,7 +1542,7 @@ __global__ void __launch_bounds__(512) k_zpass_adjoint(c2<T>* fields, const T* d
         for (int r = 0; r < F::RMAX; ++r) v[r] = A[b * RS + lds_pos<true>(F::in_index(j, r))];
       }
       __syncthreads();
-      fft_column<N, +1, T, true, VZA<T>>(v, A + (active ? b : 0) * RS, 1, j, tws, active);
+      fft_column<N, +1, T, true, VZA<T>, 64 % F::TPC == 0>(v, A + (active ? b : 0) * RS, 1, j, tws, active);
       if (active) {
 #pragma unroll
         for (int e = 0; e < F::RMAX; ++e) fbase[b * N3 + F::out_index(j, e)] = v[e];
