@@ -304,7 +304,8 @@ __global__ void k_gather_dw(const float* pos, const long long* off, int batch, l
 }
 
 // ---------------------------------------------------------------------------
-// FFT along a strided axis (x: astride = N^2, outer = N; y: astride = N, outer = N^2)
+// FFT along a strided axis (x: astride = N^2, outer = N; y: astride = N, outer = N^2);
+// the twiddles are staged in LDS while the column loads are in flight
 // ---------------------------------------------------------------------------
 template <int N, typename T, int DIR, bool REAL_IN, int V = 0>
 __global__ void __launch_bounds__((strided_threads_x<N, T, V>())) k_fft_strided(const void* in, c2<T>* out, long long fstride_in,
@@ -313,7 +314,9 @@ __global__ void __launch_bounds__((strided_threads_x<N, T, V>())) k_fft_strided(
   constexpr int ZC = zcx_of<N, T, V>();
   constexpr int G = tiles_x<N, T, V>();
   constexpr int RMAX = F::RMAX;
-  __shared__ c2<T> lds[G * N * ZC];
+  extern __shared__ __align__(16) char smem_x[];
+  c2<T>* lds = reinterpret_cast<c2<T>*>(smem_x);
+  c2<T>* tws = lds + G * N * ZC;
   const int tid = threadIdx.x;
   const int cc = tid % ZC;
   const int j = (tid / ZC) % F::TPC;
@@ -334,7 +337,9 @@ __global__ void __launch_bounds__((strided_threads_x<N, T, V>())) k_fft_strided(
       else v[r] = static_cast<const c2<T>*>(in)[idx];
     }
   }
-  fft_column<N, DIR, T, false, V>(v, lds + g * N * ZC + cc, ZC, j, tw, active);
+  stage_twiddles<N, T>(tw, tws);
+  __syncthreads();
+  fft_column<N, DIR, T, false, V>(v, lds + g * N * ZC + cc, ZC, j, tws, active);
   if (active) {
 #pragma unroll
     for (int e = 0; e < RMAX; ++e)
@@ -2322,8 +2327,28 @@ inline unsigned grid_for(long long count, int threads, unsigned cap = 65535u * 4
 
 template <typename T> using CT = c2<T>;
 
+// dynamic LDS of the strided transform: the column tiles plus the twiddles
+template <int N, typename T, int V> inline size_t xlds() {
+  return ((size_t)tiles_x<N, T, V>() * N * zcx_of<N, T, V>() + N) * sizeof(CT<T>);
+}
+// above 64 KB the kernels must be allowed the larger dynamic LDS
+template <int N, typename T, int V> inline hipError_t allow_x() {
+  const size_t b = xlds<N, T, V>();
+  if (b <= 65536) return hipSuccess;
+  const void* ks[4] = {reinterpret_cast<const void*>(k_fft_strided<N, T, -1, false, V>),
+                       reinterpret_cast<const void*>(k_fft_strided<N, T, +1, false, V>),
+                       reinterpret_cast<const void*>(k_fft_strided<N, T, -1, true, V>),
+                       reinterpret_cast<const void*>(k_fft_strided<N, T, +1, true, V>)};
+  for (const void* k : ks) {
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 template <int N, typename T>
 hipError_t fft3d_t(int dir, bool real_in, const void* in, void* out, int nfields, const void* tw, hipStream_t st) {
+  if (const hipError_t e = allow_x<N, T, 0>(); e != hipSuccess) return e;
   constexpr int ZC = zcx_of<N, T>();
   constexpr int G = tiles_x<N, T>();
   constexpr int threads = Fft<N>::TPC * ZC * G;
@@ -2333,13 +2358,13 @@ hipError_t fft3d_t(int dir, bool real_in, const void* in, void* out, int nfields
   const CT<T>* t = static_cast<const CT<T>*>(tw);
   // x axis (stride N^2), tiles over (y, z-chunk)
   if (dir < 0) {
-    if (real_in) k_fft_strided<N, T, -1, true><<<gs, threads, 0, st>>>(in, o, N3, N3, N * N, N, t);
-    else k_fft_strided<N, T, -1, false><<<gs, threads, 0, st>>>(in, o, N3, N3, N * N, N, t);
-    k_fft_strided<N, T, -1, false><<<gs, threads, 0, st>>>(o, o, N3, N3, N, N * N, t);
+    if (real_in) k_fft_strided<N, T, -1, true><<<gs, threads, xlds<N, T, 0>(), st>>>(in, o, N3, N3, N * N, N, t);
+    else k_fft_strided<N, T, -1, false><<<gs, threads, xlds<N, T, 0>(), st>>>(in, o, N3, N3, N * N, N, t);
+    k_fft_strided<N, T, -1, false><<<gs, threads, xlds<N, T, 0>(), st>>>(o, o, N3, N3, N, N * N, t);
   } else {
-    if (real_in) k_fft_strided<N, T, +1, true><<<gs, threads, 0, st>>>(in, o, N3, N3, N * N, N, t);
-    else k_fft_strided<N, T, +1, false><<<gs, threads, 0, st>>>(in, o, N3, N3, N * N, N, t);
-    k_fft_strided<N, T, +1, false><<<gs, threads, 0, st>>>(o, o, N3, N3, N, N * N, t);
+    if (real_in) k_fft_strided<N, T, +1, true><<<gs, threads, xlds<N, T, 0>(), st>>>(in, o, N3, N3, N * N, N, t);
+    else k_fft_strided<N, T, +1, false><<<gs, threads, xlds<N, T, 0>(), st>>>(in, o, N3, N3, N * N, N, t);
+    k_fft_strided<N, T, +1, false><<<gs, threads, xlds<N, T, 0>(), st>>>(o, o, N3, N3, N, N * N, t);
   }
   constexpr int P = contig_pencils<N, T>();
   const long long npen = (long long)nfields * N * N;
@@ -2351,6 +2376,7 @@ hipError_t fft3d_t(int dir, bool real_in, const void* in, void* out, int nfields
 
 template <int N, typename T, int V>
 hipError_t fft_x_v(int dir, void* buf, int nfields, const void* tw, hipStream_t st) {
+  if (const hipError_t e = allow_x<N, T, V>(); e != hipSuccess) return e;
   constexpr int ZC = zcx_of<N, T, V>();
   constexpr int G = tiles_x<N, T, V>();
   constexpr int threads = Fft<N, V>::TPC * ZC * G;
@@ -2358,8 +2384,8 @@ hipError_t fft_x_v(int dir, void* buf, int nfields, const void* tw, hipStream_t 
   const dim3 gs((N * (N / ZC) + G - 1) / G, nfields);
   CT<T>* o = static_cast<CT<T>*>(buf);
   const CT<T>* t = static_cast<const CT<T>*>(tw);
-  if (dir < 0) k_fft_strided<N, T, -1, false, V><<<gs, threads, 0, st>>>(o, o, N3, N3, N * N, N, t);
-  else k_fft_strided<N, T, +1, false, V><<<gs, threads, 0, st>>>(o, o, N3, N3, N * N, N, t);
+  if (dir < 0) k_fft_strided<N, T, -1, false, V><<<gs, threads, xlds<N, T, V>(), st>>>(o, o, N3, N3, N * N, N, t);
+  else k_fft_strided<N, T, +1, false, V><<<gs, threads, xlds<N, T, V>(), st>>>(o, o, N3, N3, N * N, N, t);
   return hipGetLastError();
 }
 
@@ -2370,6 +2396,7 @@ hipError_t fft_x_t(int dir, void* buf, int nfields, const void* tw, int variant,
 
 template <int N, typename T>
 hipError_t fft_y_t(int dir, void* buf, int nfields, const void* tw, hipStream_t st) {
+  if (const hipError_t e = allow_x<N, T, 0>(); e != hipSuccess) return e;
   constexpr int ZC = zcx_of<N, T>();
   constexpr int G = tiles_x<N, T>();
   constexpr int threads = Fft<N>::TPC * ZC * G;
@@ -2377,8 +2404,8 @@ hipError_t fft_y_t(int dir, void* buf, int nfields, const void* tw, hipStream_t 
   const dim3 gs((N * (N / ZC) + G - 1) / G, nfields);
   CT<T>* o = static_cast<CT<T>*>(buf);
   const CT<T>* t = static_cast<const CT<T>*>(tw);
-  if (dir < 0) k_fft_strided<N, T, -1, false><<<gs, threads, 0, st>>>(o, o, N3, N3, N, N * N, t);
-  else k_fft_strided<N, T, +1, false><<<gs, threads, 0, st>>>(o, o, N3, N3, N, N * N, t);
+  if (dir < 0) k_fft_strided<N, T, -1, false><<<gs, threads, xlds<N, T, 0>(), st>>>(o, o, N3, N3, N, N * N, t);
+  else k_fft_strided<N, T, +1, false><<<gs, threads, xlds<N, T, 0>(), st>>>(o, o, N3, N3, N, N * N, t);
   return hipGetLastError();
 }
 
