@@ -1730,16 +1730,18 @@ __device__ __forceinline__ int tap_offset(int base, int o, int n) {
 
 constexpr int SCT = 8;                    // owner tile side (nodes)
 constexpr int SCB = (SCT + 3) * (SCT + 3) * (SCT + 3);   // first-tap buckets
-// bins per owner workgroup: 10 in float32 (20 bins in two passes over the
-// candidates instead of three; measured 23 % faster than 8 at 512^3), 4 in float64
-template <typename T> constexpr int scatter_bc() { return sizeof(T) == 4 ? 10 : 4; }
+// bins per owner workgroup: float32 8, or 10 where that saves a pass over the
+// candidates (17..20 bins: two passes instead of three, 23 % faster at 512^3);
+// float64 4
+template <typename T> constexpr int scatter_bc() { return sizeof(T) == 4 ? 8 : 4; }
+inline int scatter_bc_f32(int nbins) { return (nbins + 9) / 10 < (nbins + 7) / 8 ? 10 : 8; }
 template <typename T> constexpr int scatter_q() { return sizeof(T) == 4 ? 256 : 256; }
 
-template <typename T>
+template <typename T, int BC>
 struct ScatterLds {
   size_t key, wt, sv, cnt, ord, total;
   __host__ __device__ ScatterLds() {
-    constexpr int Q = scatter_q<T>(), BC = scatter_bc<T>();
+    constexpr int Q = scatter_q<T>();
     size_t o = 0;
     auto take = [&](size_t b) { size_t r = o; o = (o + b + 15) & ~(size_t)15; return r; };
     key = take((size_t)Q * sizeof(int));
@@ -1751,14 +1753,14 @@ struct ScatterLds {
   }
 };
 
-template <typename T>
+template <typename T, int BC>
 __global__ void __launch_bounds__(256) k_scatter_source(const int* tcell, const T* twt, const int* toff,
                                                          const c2<T>* src, int n, int nbins, int nchunk, c2<T>* out) {
   constexpr int TO = SCT, TB = SCT + 3;
   constexpr int NODES = TO * TO * TO;
-  constexpr int BC = scatter_bc<T>(), Q = scatter_q<T>();
+  constexpr int Q = scatter_q<T>();
   extern __shared__ __align__(16) char smem[];
-  const ScatterLds<T> L;
+  const ScatterLds<T, BC> L;
   int* qkey = reinterpret_cast<int*>(smem + L.key);          // bucket of each staged particle
   T* qwt = reinterpret_cast<T*>(smem + L.wt);                // [q][3][4] tap weights
   c2<T>* qsv = reinterpret_cast<c2<T>*>(smem + L.sv);        // [q][BC] sources
@@ -2970,29 +2972,25 @@ hipError_t launch_gather_source(int prec, const void* fields, const int* tcell, 
   return hipGetLastError();
 }
 
+template <typename T, int BC>
+hipError_t scatter_source_t(const int* tcell, const void* twt, const int* toff, const void* src, int n, int nbins,
+                            int batch, void* out, hipStream_t st) {
+  const int no = n / SCT;
+  const int nchunk = (nbins + BC - 1) / BC;
+  const size_t lds = ScatterLds<T, BC>().total;
+  hipError_t e = allow_lds(k_scatter_source<T, BC>, lds);
+  if (e != hipSuccess) return e;
+  const dim3 gs(no * no * no, batch * nchunk);
+  k_scatter_source<T, BC><<<gs, 256, lds, st>>>(tcell, static_cast<const T*>(twt), toff, static_cast<const CT<T>*>(src),
+                                                n, nbins, nchunk, static_cast<CT<T>*>(out));
+  return hipGetLastError();
+}
+
 hipError_t launch_scatter_source(int prec, const int* tcell, const void* twt, const int* toff, const void* src, int n,
                                  int nbins, int batch, void* out, hipStream_t st) {
-  const int no = n / SCT;
-  if (prec) {
-    const int nchunk = (nbins + scatter_bc<double>() - 1) / scatter_bc<double>();
-    const size_t lds = ScatterLds<double>().total;
-    hipError_t e = allow_lds(k_scatter_source<double>, lds);
-    if (e != hipSuccess) return e;
-    const dim3 gs(no * no * no, batch * nchunk);
-    k_scatter_source<double><<<gs, 256, lds, st>>>(tcell, static_cast<const double*>(twt), toff,
-                                                   static_cast<const double2*>(src), n, nbins, nchunk,
-                                                   static_cast<double2*>(out));
-  } else {
-    const int nchunk = (nbins + scatter_bc<float>() - 1) / scatter_bc<float>();
-    const size_t lds = ScatterLds<float>().total;
-    hipError_t e = allow_lds(k_scatter_source<float>, lds);
-    if (e != hipSuccess) return e;
-    const dim3 gs(no * no * no, batch * nchunk);
-    k_scatter_source<float><<<gs, 256, lds, st>>>(tcell, static_cast<const float*>(twt), toff,
-                                                  static_cast<const float2*>(src), n, nbins, nchunk,
-                                                  static_cast<float2*>(out));
-  }
-  return hipGetLastError();
+  if (prec) return scatter_source_t<double, scatter_bc<double>()>(tcell, twt, toff, src, n, nbins, batch, out, st);
+  if (scatter_bc_f32(nbins) == 10) return scatter_source_t<float, 10>(tcell, twt, toff, src, n, nbins, batch, out, st);
+  return scatter_source_t<float, 8>(tcell, twt, toff, src, n, nbins, batch, out, st);
 }
 
 hipError_t launch_tap_records(int prec, const float* pos, const int* perm, long long np_total, int n, double sc,
