@@ -61,7 +61,9 @@ enum mp3_status {
   MP3_ENOMEM = -2,        /* device or host allocation failed in mp3_plan_create   */
   MP3_EHIP = -3,          /* a HIP runtime call or kernel launch failed            */
   MP3_EUNSUPPORTED = -4,  /* valid request the library does not implement          */
-  MP3_EWORKSPACE = -5     /* workspace pointer NULL or smaller than required       */
+  MP3_EWORKSPACE = -5,    /* workspace pointer NULL or smaller than required       */
+  MP3_ENONFINITE = -6     /* a NaN or infinity in the description, or (with
+                             MP3_KF_CHECK_FINITE) in the catalogue or delta       */
 };
 
 /* MP3_F32_BF16X3 is MP3_F32 whose contractions on the matrix cores (nodal,
@@ -79,6 +81,34 @@ enum mp3_summation {
   MP3_SUM_PARTICLE = 2    /* particle summation: primary vertex on the catalogue    */
 };
 
+/* Basis of the density reconstruction (Sec. 2.1, the scaling functions of the
+ * multiresolution analysis).  Only the centred cubic B-spline (support 4
+ * cells per axis) is implemented; other values return MP3_EUNSUPPORTED. */
+enum mp3_basis { MP3_BASIS_BSPLINE3 = 0 };
+
+/* Radial window of the two secondary vertices (Sec. 2.2, the paragraph after
+ * Eq. nL-2fold: a binning window multiplies the multipole window of
+ * Eq. 3PCF-multipole-window at each vertex):
+ *   MP3_BIN_SHELL_AVERAGE  jbar_{l,b}(k) = 3/(r_{b+1}^3 - r_b^3) int r^2 j_l(kr) dr
+ *                          over the shell [edges[b], edges[b+1])
+ *   MP3_BIN_THIN_SHELL     j_l(k r_b) at the shell's mid radius
+ *                          r_b = (edges[b] + edges[b+1]) / 2 (the infinitely
+ *                          thin shell of Eq. 3PCF-multipole-window) */
+enum mp3_binning { MP3_BIN_SHELL_AVERAGE = 0, MP3_BIN_THIN_SHELL = 1 };
+
+/* Option bits of mp3_plan_desc.kflags. */
+enum mp3_kflags {
+  /* multiply the secondary vertices' window by the power spectrum of the
+   * father scaling function, Phi-hat(q) = prod_d sinc^8(pi q_d / N) for the
+   * cubic B-spline, as in Eq. SFC-3PCF-vertex (default: no such factor) */
+  MP3_KF_PHI_HAT = 1u << 0,
+  /* validate inputs on the device before using them: mp3_deposit checks the
+   * positions and weights, the zeta / backward / value-and-grad calls check
+   * delta, and a NaN or infinity returns MP3_ENONFINITE before any other
+   * launch.  The check synchronises the stream (the call then blocks). */
+  MP3_KF_CHECK_FINITE = 1u << 1
+};
+
 typedef struct {
   int32_t n;              /* grid points per side: 16, 32, 64, 128, 256 or 512       */
   double box;             /* periodic box side (length units of the catalogue), > 0  */
@@ -89,6 +119,17 @@ typedef struct {
   int32_t precision;      /* enum mp3_precision                                     */
   int32_t summation;      /* enum mp3_summation                                     */
   int32_t batch;          /* mocks per call, >= 1                                   */
+  int32_t basis;          /* enum mp3_basis (0)                                     */
+  uint32_t kflags;        /* OR of enum mp3_kflags (0 = none)                       */
+  int32_t binning;        /* enum mp3_binning                                       */
+  double smoothing;       /* radius R >= 0 of the spherical top-hat window assigned
+                             to every vertex (Sec. 3, the triple-sphere binning):
+                             W_TH(kR) = 3 j_1(kR) / (kR) multiplies both
+                             secondaries' radial window, and the grid forms
+                             (nodal, grid-Gamma) take the primary as delta
+                             filtered by the same window.  The particle form's
+                             primary is the catalogue itself (no window, the
+                             paragraph before Eq. DDD-sum-privertex).  0 = none */
 } mp3_plan_desc;
 
 /* Build a plan: validates the description, generates the float64 tables (bin-
@@ -115,7 +156,9 @@ int mp3_workspace_size(mp3_plan_t plan, int64_t np_total, size_t* bytes);
  * w       device float32 [np_total] weights, or NULL for unit weights;
  * np_off  HOST int64 [batch+1], strictly increasing prefix offsets with
  *         np_off[0] = 0: mock j owns particles np_off[j] .. np_off[j+1]-1;
- *         an empty mock (W = 0, contrast undefined) returns MP3_EINVAL;
+ *         an empty mock (W = 0, contrast undefined) returns MP3_EINVAL.
+ *         pos, w (and dw of the gradient calls) must hold np_off[batch]
+ *         entries: the library reads and writes exactly that many;
  * delta   device real [batch][N^3], written. */
 int mp3_deposit(mp3_plan_t plan, const float* pos, const float* w, const int64_t* np_off,
                 void* delta, void* workspace, size_t workspace_bytes, void* stream);
@@ -205,6 +248,37 @@ int mp3_zeta_value_and_grad(mp3_plan_t plan, const void* delta, const double* dz
                             const int64_t* np_off, void* dw, void* workspace,
                             size_t workspace_bytes, void* stream);
 
+/* Two-point correlation function of delta by the same window machinery
+ * (Sec. 2.1, Eqs. pair-counting and window-sphshell): with the plan's
+ * top-hat radius R on both vertices (the grid forms' primary filtered as in
+ * mp3_zeta; the particle form's plan leaves the primary unfiltered),
+ *   xi(r) = N^-6 sum_q |dhat(q)|^2 Wp(|k|) W_TH(|k| R) Phi(q) j_0(|k| r)
+ *         = N^-3 sum_x delta_p(x) (W_r o delta)(x),
+ * Wp = W_TH(|k| R) for the grid forms with R > 0, else 1; Phi = phi-hat with
+ * MP3_KF_PHI_HAT, else 1; W_r the infinitely thin shell of radius r; the
+ * Nyquist planes excluded (as for the secondary vertices of mp3_zeta).
+ * radii  HOST double [nr], >= 0, 1 <= nr <= 4096;
+ * xi     device float64 [batch][nr], overwritten. */
+int mp3_xi(mp3_plan_t plan, const void* delta, const double* radii, int32_t nr, double* xi, void* workspace,
+           size_t workspace_bytes, void* stream);
+
+/* The 3PCF at the bin radii reconstructed from its multipoles, truncated at
+ * lt (Sec. 2.2, Eq. triplet-counting; Sec. 3, Eq. Q-factor):
+ *   zeta(r_b1, r_b2, theta) = sum_{l=0}^{lt} zeta_l[b1][b2] P_l(cos theta),
+ *   Q = zeta / (xi(r1) xi(r2) + xi(r2) xi(r3) + xi(r3) xi(r1)),
+ *   r3^2 = r1^2 + r2^2 - 2 r1 r2 cos theta,
+ * with r_b the bins' mid radii (edges[b] + edges[b+1]) / 2 and xi as mp3_xi
+ * of the same delta.
+ * zeta  device float64 [batch][lmax+1][nbins][nbins] (as written by mp3_zeta);
+ * lt    0 <= lt <= lmax;
+ * mu    HOST double [nth] values of cos theta in [-1, 1], 1 <= nth <= 4096;
+ * zeta_theta  device float64 [batch][nbins][nbins][nth], overwritten;
+ * q     device float64, same shape, overwritten, or NULL to skip Q (delta
+ *       may then be NULL too). */
+int mp3_reduced_3pcf(mp3_plan_t plan, const void* delta, const double* zeta, int32_t lt, const double* mu,
+                     int32_t nth, double* zeta_theta, double* q, void* workspace, size_t workspace_bytes,
+                     void* stream);
+
 /* Pass identifiers for per-pass timing. */
 enum mp3_pass {
   MP3_PASS_DFT = 0,        /* forward 3-D DFT of delta; final DFT of the adjoint accumulator */
@@ -266,6 +340,24 @@ int mp3_tune_get(mp3_plan_t plan, int knob, int32_t* value);
 /* Read back the plan's parameters (any out pointer may be NULL). */
 int mp3_plan_info(mp3_plan_t plan, int32_t* n, int32_t* lmax, int32_t* nbins,
                   int32_t* precision, int32_t* batch);
+
+/* Host-side float64 routines of plan creation, exported so that they can be
+ * checked without a GPU (no device work, no plan needed). */
+
+/* Spherical Bessel functions j_0(x) .. j_lmax(x) into out[0 .. lmax]
+ * (the radial functions of the plane-wave expansion, Sec. 2.1,
+ * Eq. plane-sph-harmonics): upward recurrence for x > lmax, Miller's downward
+ * recurrence below, exact at x = 0.  lmax in [0, 64], x >= 0 and finite. */
+int mp3_sph_bessel(int32_t lmax, double x, double* out);
+
+/* The radial window table a plan built from desc uses (Sec. 2.2, the radial
+ * part of Eq. 3PCF-multipole-window times the binning window):
+ *   out[(l * nq2 + s) * nbins + b] = R_{l,b}(k_s) W_TH(k_s R),
+ *   k_s = (2 pi / box) sqrt(s), s = 0 .. nq2 - 1, nq2 = 3 (n/2)^2 + 1,
+ * with R_{l,b} the bin-average or thin-shell window of desc->binning and
+ * W_TH = 1 when desc->smoothing = 0.  count must be (lmax+1) nq2 nbins.
+ * Validates desc as mp3_plan_create does. */
+int mp3_window_table(const mp3_plan_desc* desc, double* out, size_t count);
 
 /* Human-readable name of a status code (static storage). */
 const char* mp3_status_string(int status);

@@ -75,6 +75,7 @@ def zeta_nodal_grad(plan: Plan, delta, lam, ls=None, bins=None) -> np.ndarray:
     lam = np.asarray(lam, dtype=np.float64)
     n = plan.n
     dhat = np.fft.fftn(delta)
+    prim = plan.primary(delta)
     direct = np.zeros_like(delta)
     acc = np.zeros(delta.shape, dtype=np.complex128)
     bl = plan.bins(bins)
@@ -84,11 +85,12 @@ def zeta_nodal_grad(plan: Plan, delta, lam, ls=None, bins=None) -> np.ndarray:
         for m in range(-l, l + 1):
             A = fields(plan, dhat, l, m, bl)                      # [nb, n, n, n]
             direct += np.einsum("ij,ixyz,jxyz->xyz", lam_l, A, A.conj()).real
-            C = delta[None] * np.einsum("ij,jxyz->ixyz", lam_s, A.conj())
+            C = prim[None] * np.einsum("ij,jxyz->ixyz", lam_s, A.conj())
             yc = plan.ylm_conj_grid(l, m)
             for bi, b in enumerate(bl):
                 acc += plan.kernel(l, m, b, yc) * np.fft.ifftn(C[bi])
-    grad = direct + 2.0 * np.fft.fftn(acc).real
+    # the primary is delta filtered by a real, even window: its transpose is the same filter
+    grad = plan.primary(direct) + 2.0 * np.fft.fftn(acc).real
     return grad * (FOUR_PI / n ** 3)
 
 
@@ -146,7 +148,7 @@ def zeta_particle_grad(plan: Plan, pos, w, lam, ls=None, bins=None):
             for bi, b in enumerate(bl):
                 c = float(n) ** 3 * _scatter(S[bi], pos, n, box)
                 acc += plan.kernel(l, m, b, yc) * np.fft.ifftn(c)
-    H *= b7[:, None, None] * b7[None, :, None] * b7[None, None, :]
+    H *= b7[:, None, None] * b7[None, :, None] * b7[None, None, :] * plan.phi_hat_grid() ** 2
     H[plan.nyquist] = 0.0
     g = (FOUR_PI / n ** 3) * 2.0 * np.fft.fftn(acc).real - (2.0 / n ** 3) * np.fft.ifftn(H * dhat).real
     dw = deposit_weight_grad(pos, w, n, box, g) + FOUR_PI * (FJ / W - float(np.dot(w, FJ)) / W ** 2)
@@ -172,7 +174,7 @@ def zeta_gamma_grad(plan: Plan, delta, lam, ls=None, bins=None) -> np.ndarray:
     dhat = np.fft.fftn(delta)
     gmat = basis.gamma_matrix()
     shifts = [(dx, dy, dz) for dx in range(-3, 4) for dy in range(-3, 4) for dz in range(-3, 4)]
-    gfields = {sh: _gamma_stencil_field(delta, gmat, sh) for sh in shifts}
+    gfields = {sh: _gamma_stencil_field(plan.primary(delta), gmat, sh) for sh in shifts}
     direct = np.zeros(delta.shape, dtype=np.complex128)
     acc = np.zeros(delta.shape, dtype=np.complex128)
     bl = plan.bins(bins)
@@ -192,5 +194,5 @@ def zeta_gamma_grad(plan: Plan, delta, lam, ls=None, bins=None) -> np.ndarray:
             yc = plan.ylm_conj_grid(l, m)
             for bi, b in enumerate(bl):
                 acc += plan.kernel(l, m, b, yc) * np.fft.ifftn(C[bi])
-    grad = direct.real + 2.0 * np.fft.fftn(acc).real
+    grad = plan.primary(direct.real) + 2.0 * np.fft.fftn(acc).real
     return grad * (FOUR_PI / n ** 3)

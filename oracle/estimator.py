@@ -37,20 +37,35 @@ import numpy as np
 from . import special, basis
 
 __all__ = ["Plan", "zeta_nodal", "zeta_gamma", "zeta_gamma_quadrature",
-           "zeta_particle", "fields", "volume_mean_pair"]
+           "zeta_particle", "fields", "volume_mean_pair", "xi", "zeta_theta", "reduced_3pcf"]
 
 FOUR_PI = 4.0 * np.pi
 
 
 class Plan:
-    """Grid, bins and the tabulated window functions for one configuration."""
+    """Grid, bins and the tabulated window functions for one configuration.
 
-    def __init__(self, n: int, box: float, lmax: int, edges):
+    binning "shell": r^2-weighted average of j_l over [edges[b], edges[b+1]);
+    "thin": j_l(k r_b) at the mid radius (Eq. 3PCF-multipole-window).
+    smoothing R > 0: the spherical top-hat window W_TH(kR) on every vertex
+    (Sec. 3): both secondaries' radial window, and the grid forms' primary
+    delta_p = ifftn(fftn(delta) W_TH).  phi_hat: the secondaries' window
+    also carries the power spectrum of the B-spline scaling function,
+    prod_d sinc^8(pi q_d / n) (Eq. SFC-3PCF-vertex).
+    """
+
+    def __init__(self, n: int, box: float, lmax: int, edges, binning: str = "shell", smoothing: float = 0.0,
+                 phi_hat: bool = False):
         self.n = int(n)
         self.box = float(box)
         self.lmax = int(lmax)
         self.edges = np.asarray(edges, dtype=np.float64)
         self.nbins = self.edges.size - 1
+        if binning not in ("shell", "thin"):
+            raise ValueError("binning must be 'shell' or 'thin'")
+        self.binning = binning
+        self.smoothing = float(smoothing)
+        self.phi_hat = bool(phi_hat)
         q = np.fft.fftfreq(self.n, d=1.0 / self.n)                     # integers
         self.q1 = q
         qx, qy, qz = q[:, None, None], q[None, :, None], q[None, None, :]
@@ -67,14 +82,40 @@ class Plan:
             ct = np.where(qn > 0, qz / np.where(qn > 0, qn, 1.0), 1.0)
         self.theta = np.arccos(np.clip(ct, -1.0, 1.0))
         self.phi = np.arctan2(np.broadcast_to(qy, q2.shape), np.broadcast_to(qx, q2.shape))
+        self.kgrid = self.kf * qn
         self._jbar = {}
 
     # -- window tables ---------------------------------------------------
     def jbar_uniq(self, l: int) -> np.ndarray:
-        """jbar_{l,b} on the distinct |k| of the grid: [nbins, n_unique]."""
+        """Radial window of a secondary vertex on the distinct |k| of the grid: [nbins, n_unique]
+        (bin average or thin shell, times the top-hat window when smoothing)."""
         if l not in self._jbar:
-            self._jbar[l] = special.jbar(l, self.edges, self.kmag_uniq)
+            if self.binning == "shell":
+                r = special.jbar(l, self.edges, self.kmag_uniq)
+            else:
+                r = special.thin_shell(l, self.edges, self.kmag_uniq)
+            if self.smoothing > 0.0:
+                r = r * special.tophat_window(self.kmag_uniq * self.smoothing)[None, :]
+            self._jbar[l] = r
         return self._jbar[l]
+
+    def phi_hat_grid(self) -> np.ndarray:
+        """prod_d sinc^8(pi q_d / n) on the k-grid (ones without the phi_hat option)."""
+        if not self.phi_hat:
+            return np.ones((self.n,) * 3)
+        h = np.pi * self.q1 / self.n
+        s = np.ones_like(h)
+        nz = h != 0
+        s[nz] = np.sin(h[nz]) / h[nz]
+        s = s ** 8
+        return s[:, None, None] * s[None, :, None] * s[None, None, :]
+
+    def primary(self, delta) -> np.ndarray:
+        """The grid forms' primary vertex: delta, or delta filtered by the top-hat window."""
+        delta = np.asarray(delta, dtype=np.float64)
+        if self.smoothing <= 0.0:
+            return delta
+        return np.fft.ifftn(np.fft.fftn(delta) * special.tophat_window(self.kgrid * self.smoothing)).real
 
     def jbar_grid(self, l: int, b: int) -> np.ndarray:
         return self.jbar_uniq(l)[b][self._q2_inv]
@@ -86,6 +127,8 @@ class Plan:
         """K_{lm,b}(q) on the full k-grid (complex128 [n, n, n])."""
         yc = self.ylm_conj_grid(l, m) if ylm_conj is None else ylm_conj
         k = (1j ** l) * self.jbar_grid(l, b) * yc
+        if self.phi_hat:
+            k = k * self.phi_hat_grid()
         k[self.nyquist] = 0.0
         return k
 
@@ -118,11 +161,12 @@ def zeta_nodal(plan: Plan, delta: np.ndarray, ls=None, bins=None) -> np.ndarray:
     """
     delta = np.asarray(delta, dtype=np.float64)
     dhat = np.fft.fftn(delta)
+    prim = plan.primary(delta)
     out = []
     for l in plan.ls(ls):
         z = 0.0
         for m in range(-l, l + 1):
-            z = z + _pair_sum(fields(plan, dhat, l, m, bins), delta)
+            z = z + _pair_sum(fields(plan, dhat, l, m, bins), prim)
         z = z * (FOUR_PI / plan.n ** 3)
         _check_real(z)
         out.append(z.real)
@@ -169,7 +213,8 @@ def zeta_gamma(plan: Plan, delta: np.ndarray, ls=None, bins=None) -> np.ndarray:
     dhat = np.fft.fftn(delta)
     gmat = basis.gamma_matrix()
     shifts = [(dx, dy, dz) for dx in range(-3, 4) for dy in range(-3, 4) for dz in range(-3, 4)]
-    gfields = {sh: _gamma_stencil_field(delta, gmat, sh) for sh in shifts}
+    prim = plan.primary(delta)
+    gfields = {sh: _gamma_stencil_field(prim, gmat, sh) for sh in shifts}
     out = []
     for l in plan.ls(ls):
         z = 0.0
@@ -220,7 +265,7 @@ def zeta_gamma_quadrature(plan: Plan, delta: np.ndarray, ls=None, bins=None) -> 
     delta = np.asarray(delta, dtype=np.float64)
     dhat = np.fft.fftn(delta)
     W = wq[:, None, None] * wq[None, :, None] * wq[None, None, :]
-    wd = W * interp(delta)
+    wd = W * interp(plan.primary(delta))
     out = []
     for l in plan.ls(ls):
         z = 0.0
@@ -251,7 +296,7 @@ def volume_mean_pair(plan: Plan, dhat: np.ndarray, l: int, bins=None) -> np.ndar
     th = 2.0 * np.pi * plan.q1 / n
     b7 = basis.b7_hat(th)
     b7g = b7[:, None, None] * b7[None, :, None] * b7[None, None, :]
-    p = np.abs(dhat) ** 2 * b7g
+    p = np.abs(dhat) ** 2 * b7g * plan.phi_hat_grid() ** 2
     p[plan.nyquist] = 0.0
     bl = plan.bins(bins)
     J = np.stack([plan.jbar_grid(l, b).ravel() for b in bl])
@@ -295,3 +340,55 @@ def zeta_particle(plan: Plan, pos, w, ls=None, bins=None, mode: str = "delta", d
             z = z - volume_mean_pair(plan, dhat, l, bins)
         out.append(FOUR_PI * z)
     return np.array(out)
+
+
+# ---------------------------------------------------------------------------
+# two-point function and the reconstructed 3PCF
+# ---------------------------------------------------------------------------
+
+def xi(plan: Plan, delta, radii) -> np.ndarray:
+    """xi(r) = n^-3 sum_x delta_p(x) (W_r o delta)(x) for each radius [Sec. 2.1, Eqs. pair-counting and
+    window-sphshell]: the secondary filtered by the thin shell j_0(k r) (times the top-hat and phi-hat
+    windows of the plan, Nyquist planes zeroed as for the 3PCF's secondaries), the primary delta_p the
+    grid forms' primary (plan.primary)."""
+    delta = np.asarray(delta, dtype=np.float64)
+    dhat = np.fft.fftn(delta)
+    prim = plan.primary(delta)
+    w = plan.phi_hat_grid()
+    if plan.smoothing > 0.0:
+        w = w * special.tophat_window(plan.kgrid * plan.smoothing)
+    out = []
+    for r in np.asarray(radii, dtype=np.float64).ravel():
+        k = w * special.sph_jn(0, plan.kgrid * r)
+        k[plan.nyquist] = 0.0
+        sec = np.fft.ifftn(dhat * k)
+        out.append(float(np.mean(prim * sec.real)))
+    return np.array(out)
+
+
+def zeta_theta(zeta, mu, lt: int) -> np.ndarray:
+    """zeta(r1, r2, theta) = sum_{l=0}^{lt} zeta_l(r1, r2) P_l(cos theta) [Eq. triplet-counting],
+    the multipole sum truncated at lt.  zeta [L+1, nb, nb] -> [nb, nb, len(mu)]."""
+    zeta = np.asarray(zeta, dtype=np.float64)
+    mu = np.asarray(mu, dtype=np.float64).ravel()
+    out = np.zeros(zeta.shape[1:] + mu.shape)
+    for l in range(lt + 1):
+        out += zeta[l][:, :, None] * special.legendre(l, mu)[None, None, :]
+    return out
+
+
+def reduced_3pcf(plan: Plan, delta, zeta, mu, lt: int) -> np.ndarray:
+    """Q = zeta(theta) / [xi(r1) xi(r2) + xi(r2) xi(r3) + xi(r3) xi(r1)] [Eq. Q-factor], with the
+    triangle's third side r3^2 = r1^2 + r2^2 - 2 r1 r2 cos theta and r_b the bins' mid radii."""
+    mu = np.asarray(mu, dtype=np.float64).ravel()
+    rb = 0.5 * (plan.edges[:-1] + plan.edges[1:])
+    zt = zeta_theta(zeta, mu, lt)
+    xb = xi(plan, delta, rb)
+    nb = plan.nbins
+    q = np.zeros_like(zt)
+    for i in range(nb):
+        for j in range(nb):
+            r3 = np.sqrt(np.maximum(rb[i] ** 2 + rb[j] ** 2 - 2.0 * rb[i] * rb[j] * mu, 0.0))
+            x3 = xi(plan, delta, r3)
+            q[i, j] = zt[i, j] / (xb[i] * xb[j] + xb[j] * x3 + x3 * xb[i])
+    return q

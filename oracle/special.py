@@ -16,7 +16,8 @@ import numpy as np
 from numpy.polynomial.legendre import leggauss
 from scipy.special import spherical_jn, sph_harm_y, eval_legendre
 
-__all__ = ["sph_jn", "legendre", "ylm", "jbar", "jbar_l0_closed", "gauss_legendre"]
+__all__ = ["sph_jn", "legendre", "ylm", "jbar", "jbar_l0_closed", "gauss_legendre", "tophat_window",
+           "thin_shell"]
 
 # Gauss-Legendre order for the bin average.  A bin spans at most a few
 # oscillations of j_l(k r) at the grid's largest k, where 64 nodes converge to
@@ -76,3 +77,21 @@ def jbar_l0_closed(edges, k) -> np.ndarray:
             v = (prim(r2) - prim(r1)) * 3.0 / (r2 ** 3 - r1 ** 3)
         out[b] = np.where(k == 0, 1.0, v)
     return out
+
+
+def thin_shell(l: int, edges, k) -> np.ndarray:
+    """Infinitely thin shell at each bin's mid radius: j_l(k r_b), r_b = (edges[b] + edges[b+1]) / 2
+    (the radial factor of Eq. 3PCF-multipole-window).  Returns [nbins, k.size]."""
+    k = np.asarray(k, dtype=np.float64).ravel()
+    edges = np.asarray(edges, dtype=np.float64)
+    mid = 0.5 * (edges[:-1] + edges[1:])
+    return spherical_jn(l, np.multiply.outer(mid, k))
+
+
+def tophat_window(x):
+    """Fourier transform of the unit-volume sphere at x = k R: 3 j_1(x) / x
+    (the spherical top-hat binning window of Sec. 3), 1 at x = 0."""
+    x = np.asarray(x, dtype=np.float64)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        v = 3.0 * spherical_jn(1, x) / x
+    return np.where(x == 0.0, 1.0, v)

@@ -42,13 +42,21 @@ class Plan:
     summation "nodal": grid summation on the nodes; "gamma": grid summation
     with the B-spline connection coefficients; "particle": primary vertex on
     the catalogue (zeta() then needs pos, w, np_off).
+    binning "shell": r^2-weighted average of j_l over each bin; "thin": the
+    thin shell at each bin's mid radius.  smoothing: radius of the spherical
+    top-hat window on every vertex (0 = none).  phi_hat: multiply the
+    secondary windows by the scaling function's power spectrum.
+    check_finite: validate inputs on the device (calls then block).
     """
 
     PRECISIONS = {"f32": _lib.MP3_F32, "f64": _lib.MP3_F64, "bf16x3": _lib.MP3_F32_BF16X3}
     SUMMATIONS = {"nodal": _lib.MP3_SUM_NODAL, "gamma": _lib.MP3_SUM_GRID_GAMMA, "particle": _lib.MP3_SUM_PARTICLE}
 
+    BINNINGS = {"shell": _lib.MP3_BIN_SHELL_AVERAGE, "thin": _lib.MP3_BIN_THIN_SHELL}
+
     def __init__(self, n: int, box: float, lmax: int, edges, precision: str = "f32", batch: int = 1,
-                 device=None, summation: str = "nodal"):
+                 device=None, summation: str = "nodal", binning: str = "shell", smoothing: float = 0.0,
+                 phi_hat: bool = False, check_finite: bool = False):
         self.lib = _lib.load()
         self.n, self.box, self.lmax, self.batch = int(n), float(box), int(lmax), int(batch)
         self.edges = np.ascontiguousarray(edges, dtype=np.float64)
@@ -59,13 +67,18 @@ class Plan:
         if summation not in self.SUMMATIONS:
             raise ValueError(f"summation must be one of {sorted(self.SUMMATIONS)}")
         self.summation = summation
+        if binning not in self.BINNINGS:
+            raise ValueError(f"binning must be one of {sorted(self.BINNINGS)}")
+        self.binning, self.smoothing = binning, float(smoothing)
+        kflags = (_lib.MP3_KF_PHI_HAT if phi_hat else 0) | (_lib.MP3_KF_CHECK_FINITE if check_finite else 0)
         self.real_dtype = torch.float64 if precision == "f64" else torch.float32
         self.complex_dtype = torch.complex128 if precision == "f64" else torch.complex64
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         desc = _lib.PlanDesc(self.n, self.box, self.lmax, self.nbins,
                              self.edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                              self.PRECISIONS[precision],
-                             self.SUMMATIONS[summation], self.batch)
+                             self.SUMMATIONS[summation], self.batch, _lib.MP3_BASIS_BSPLINE3, kflags,
+                             self.BINNINGS[binning], self.smoothing)
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _lib.check(self.lib.mp3_plan_create(ctypes.byref(desc), ctypes.byref(handle)), "mp3_plan_create")
@@ -97,8 +110,12 @@ class Plan:
                 raise ValueError("np_off is required when batch > 1")
             np_off = [0, np_total]
         off = np.ascontiguousarray(np_off, dtype=np.int64)
-        if off.size != self.batch + 1:
+        if off.ndim != 1 or off.size != self.batch + 1:
             raise ValueError("np_off must have batch + 1 entries")
+        # the library reads np_off[batch] particles from pos / w and writes as many dw
+        if off[0] != 0 or off[-1] != np_total or np.any(np.diff(off) <= 0):
+            raise ValueError(f"np_off must start at 0, increase strictly and end at the number of particles "
+                             f"({np_total}); got {off.tolist()}")
         return off
 
     def _real(self, x, name):
@@ -235,6 +252,39 @@ class Plan:
                                               _ptr(w), offp, _ptr(dw), _ptr(ws), ws.numel(), _stream(self.device))
         _lib.check(st, "mp3_zeta_value_and_grad")
         return z, ddelta, dw
+
+
+    def xi(self, delta, radii):
+        """Two-point function xi(r) [batch, len(radii)] float64 of delta by the same windows."""
+        self._real(delta, "delta")
+        r = np.ascontiguousarray(radii, dtype=np.float64).ravel()
+        out = torch.empty((self.batch, r.size), dtype=torch.float64, device=self.device)
+        ws = self._workspace()
+        st = self.lib.mp3_xi(self._h, _ptr(delta), r.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(r.size),
+                             _ptr(out), _ptr(ws), ws.numel(), _stream(self.device))
+        _lib.check(st, "mp3_xi")
+        return out
+
+    def reduced_3pcf(self, zeta, mu, lt=None, delta=None):
+        """(zeta(r_b1, r_b2, theta), Q or None), each [batch, nbins, nbins, len(mu)] float64.
+
+        zeta(theta) = sum_{l <= lt} zeta_l P_l(mu); Q needs delta (for xi)."""
+        zeta = zeta.to(device=self.device, dtype=torch.float64).contiguous()
+        if zeta.numel() != self.batch * (self.lmax + 1) * self.nbins ** 2:
+            raise ValueError("zeta must have shape [batch, lmax+1, nbins, nbins]")
+        mu = np.ascontiguousarray(mu, dtype=np.float64).ravel()
+        lt = self.lmax if lt is None else int(lt)
+        zt = torch.empty((self.batch, self.nbins, self.nbins, mu.size), dtype=torch.float64, device=self.device)
+        q = None
+        if delta is not None:
+            self._real(delta, "delta")
+            q = torch.empty_like(zt)
+        ws = self._workspace()
+        st = self.lib.mp3_reduced_3pcf(self._h, _ptr(delta), _ptr(zeta), lt,
+                                       mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(mu.size), _ptr(zt),
+                                       _ptr(q), _ptr(ws), ws.numel(), _stream(self.device))
+        _lib.check(st, "mp3_reduced_3pcf")
+        return zt, q
 
 
 class Zeta3PCF(torch.autograd.Function):

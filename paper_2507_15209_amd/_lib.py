@@ -13,12 +13,18 @@ MP3_ENOMEM = -2
 MP3_EHIP = -3
 MP3_EUNSUPPORTED = -4
 MP3_EWORKSPACE = -5
+MP3_ENONFINITE = -6
 MP3_F32 = 0
 MP3_F64 = 1
 MP3_F32_BF16X3 = 2
 MP3_SUM_NODAL = 0
 MP3_SUM_PARTICLE = 2
 MP3_SUM_GRID_GAMMA = 1
+MP3_BASIS_BSPLINE3 = 0
+MP3_BIN_SHELL_AVERAGE = 0
+MP3_BIN_THIN_SHELL = 1
+MP3_KF_PHI_HAT = 1
+MP3_KF_CHECK_FINITE = 2
 # launch-shape knobs (enum mp3_tune_knob)
 TUNE_KNOBS = ("zpass_wgs", "contract_wgs", "fft_x_plan", "deposit_tile", "deposit_wgs")
 
@@ -27,7 +33,8 @@ EXPORTS = (
     "mp3_plan_create", "mp3_plan_destroy", "mp3_workspace_size", "mp3_deposit",
     "mp3_multipole_fields", "mp3_zeta", "mp3_zeta_backward", "mp3_plan_info",
     "mp3_status_string", "mp3_last_error", "mp3_profile", "mp3_profile_read",
-    "mp3_tune_set", "mp3_tune_get", "mp3_zeta_value_and_grad",
+    "mp3_tune_set", "mp3_tune_get", "mp3_zeta_value_and_grad", "mp3_xi", "mp3_reduced_3pcf",
+    "mp3_sph_bessel", "mp3_window_table",
 )
 PASSES = ("dft", "filter", "x", "z_nodal", "z_adjoint", "adjoint", "deposit", "z_store", "gather", "gamma",
           "scatter", "z_fused")
@@ -43,6 +50,10 @@ class PlanDesc(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("summation", ctypes.c_int32),
         ("batch", ctypes.c_int32),
+        ("basis", ctypes.c_int32),
+        ("kflags", ctypes.c_uint32),
+        ("binning", ctypes.c_int32),
+        ("smoothing", ctypes.c_double),
     ]
 
 
@@ -86,6 +97,10 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.mp3_profile_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     lib.mp3_tune_set.argtypes = [vp, ctypes.c_int, i32]
     lib.mp3_tune_get.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i32)]
+    lib.mp3_xi.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), i32, vp, vp, sz, vp]
+    lib.mp3_reduced_3pcf.argtypes = [vp, vp, vp, i32, ctypes.POINTER(ctypes.c_double), i32, vp, vp, vp, sz, vp]
+    lib.mp3_sph_bessel.argtypes = [i32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+    lib.mp3_window_table.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(ctypes.c_double), sz]
     lib.mp3_status_string.argtypes = [ctypes.c_int]
     lib.mp3_status_string.restype = ctypes.c_char_p
     lib.mp3_last_error.argtypes = []

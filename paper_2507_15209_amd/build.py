@@ -27,7 +27,7 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 def commands() -> list[list[str]]:
     objs = []
     cmds = []
-    for src, dev in (("kernels.hip", True), ("mp3_api.cpp", False), ("tables.cpp", False)):
+    for src, dev in (("kernels.hip", True), ("stats.hip", True), ("mp3_api.cpp", False), ("tables.cpp", False)):
         obj = os.path.join(BUILD, src + ".o")
         flags = COMMON + (DEVICE + ["-x", "hip"] if dev else HOST + ["-x", "c++"])
         cmds.append([HIPCC] + flags + ["-c", os.path.join(CSRC, src), "-o", obj])
@@ -37,14 +37,28 @@ def commands() -> list[list[str]]:
 
 
 def build(verbose: bool = False) -> str:
+    """Compile every source (in parallel), then link."""
     os.makedirs(BUILD, exist_ok=True)
-    for cmd in commands():
+    cmds = commands()
+    procs = []
+    for cmd in cmds[:-1]:
         if verbose:
             print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            sys.stderr.write(r.stdout + r.stderr)
-            raise RuntimeError("hipcc failed: " + " ".join(cmd[-3:]))
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+    failed = None
+    for cmd, pr in procs:
+        out, _ = pr.communicate()
+        if pr.returncode != 0:
+            sys.stderr.write(out)
+            failed = failed or cmd
+    if failed:
+        raise RuntimeError("hipcc failed: " + " ".join(failed[-3:]))
+    if verbose:
+        print(" ".join(cmds[-1]), flush=True)
+    r = subprocess.run(cmds[-1], capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("link failed")
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

@@ -120,14 +120,18 @@ __device__ double2 ylm_conj_il(int qx, int qy, int qz, int l, int m, double norm
 
 // window factor at grid index (ix, iy, iz): i^l conj(Y) * scale with the
 // Nyquist planes set to zero; also returns |q|^2 for the radial table
+// phi != NULL: times the scaling function's power spectrum, a product of
+// per-axis factors phi[ix] phi[iy] phi[iz] (Eq. SFC-3PCF-vertex)
 template <typename T>
 __device__ __forceinline__ c2<T> window_angular(int ix, int iy, int iz, int n, int l, int m, double norm,
-                                                double scale, const YlmRec& yr, int& q2) {
+                                                double scale, const YlmRec& yr, int& q2, const T* phi = nullptr) {
   const int qx = sfreq(ix, n), qy = sfreq(iy, n), qz = sfreq(iz, n);
   q2 = qx * qx + qy * qy + qz * qz;
   const int h = -n / 2;
   if (qx == h || qy == h || qz == h) return mk<T>((T)0, (T)0);
-  const double2 f = ylm_conj_il(qx, qy, qz, l, m, norm, scale, yr);
+  double sc = scale;
+  if (phi) sc *= (double)phi[ix] * (double)phi[iy] * (double)phi[iz];
+  const double2 f = ylm_conj_il(qx, qy, qz, l, m, norm, sc, yr);
   return mk<T>((T)f.x, (T)f.y);
 }
 
@@ -380,7 +384,7 @@ template <int N, typename T>
 __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_filter_y(const c2<T>* dhat, c2<T>* fields,
                                                                          const T* jtab, int nq2, int nbins, int nbp,
                                                                          int l, int m, double norm, double scale,
-                                                                         const c2<T>* tw, YlmRec yr) {
+                                                                         const c2<T>* tw, YlmRec yr, const T* phi) {
   using F = Fft<N, VB>;
   constexpr int ZC = zc_of<T>();
   constexpr int G = tiles_per_wg<N, T, VB>();
@@ -406,7 +410,7 @@ __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_filter_y(cons
   for (int r = 0; r < RMAX; ++r) {
     const int qy = F::in_index(j, r);
     const c2<T> d = active ? nt_load(&dhat[mock * N3 + ((long long)qx * N + qy) * N + qz]) : mk<T>(0, 0);
-    const c2<T> f = window_angular<T>(qx, qy, qz, N, l, m, norm, scale, yr, q2[r]);
+    const c2<T> f = window_angular<T>(qx, qy, qz, N, l, m, norm, scale, yr, q2[r], phi);
     v0[r] = cmul<T>(d, f);
   }
   // radial window of this thread's elements, four bins per load, one quad ahead
@@ -1355,8 +1359,10 @@ __global__ void __launch_bounds__(1024) k_gamma_contract(const c2<T>* fields, co
 // B7hat(theta) = sum_s B7(s) e^{-i theta s} with the cubic B-spline
 // autocorrelation samples B7(0) = 2416/5040, B7(1) = 1191/5040, B7(2) = 120/5040,
 // B7(3) = 1/5040.
+// phi != NULL: each term also carries phi-hat(q)^2 (both secondary vertices
+// of the volume mean carry the scaling function's power spectrum)
 template <typename T>
-__global__ void k_power_hist(const c2<T>* dhat, int n, int nq2, double* P) {
+__global__ void k_power_hist(const c2<T>* dhat, int n, int nq2, double* P, const T* phi) {
   const long long n3 = (long long)n * n * n;
   const int mock = blockIdx.y;
   const c2<T>* d = dhat + mock * n3;
@@ -1373,6 +1379,10 @@ __global__ void k_power_hist(const c2<T>* dhat, int n, int nq2, double* P) {
     for (int a = 0; a < 3; ++a) {
       const double th = tp * qs[a];
       b7 *= (2416.0 + 2382.0 * cos(th) + 240.0 * cos(2.0 * th) + 2.0 * cos(3.0 * th)) / 5040.0;
+    }
+    if (phi) {
+      const double ph = (double)phi[ix] * (double)phi[iy] * (double)phi[iz];
+      b7 *= ph * ph;
     }
     const c2<T> v = d[i];
     const double p2 = (double)v.x * v.x + (double)v.y * v.y;
@@ -1579,7 +1589,7 @@ template <int N, typename T>
 __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_adjoint_y(const c2<T>* fields, c2<T>* G,
                                                                           const T* jtab, int nq2, int nbins, int nbp,
                                                                           int l, int m, double norm, double scale,
-                                                                          const c2<T>* tw, YlmRec yr) {
+                                                                          const c2<T>* tw, YlmRec yr, const T* phi) {
   using F = Fft<N, VB>;
   constexpr int ZC = zc_of<T>();
   constexpr int GT = tiles_per_wg<N, T, VB>();
@@ -1604,7 +1614,7 @@ __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_adjoint_y(con
 #pragma unroll
   for (int e = 0; e < RMAX; ++e) {
     acc[e] = mk<T>(0, 0);
-    fac[e] = window_angular<T>(qx, F::out_index(j, e), qz, N, l, m, norm, scale, yr, q2[e]);
+    fac[e] = window_angular<T>(qx, F::out_index(j, e), qz, N, l, m, norm, scale, yr, q2[e], phi);
   }
   const T* jl = jtab + (long long)l * nq2 * nbp;
   const c2<T>* src = fields + mock * nbins * N3 + (long long)qx * N * N + qz;
@@ -2273,7 +2283,8 @@ __global__ void k_fbar_weight(const double* dzeta, const T* jtab, int nq2, int n
 // volume-mean term of the particle form's gradient, added in k-space before
 // the final transform
 template <typename T>
-__global__ void k_fbar_adjoint(const c2<T>* dhat, const double* h, int n, int nq2, double scale, c2<T>* G) {
+__global__ void k_fbar_adjoint(const c2<T>* dhat, const double* h, int n, int nq2, double scale, c2<T>* G,
+                               const T* phi) {
   const long long n3 = (long long)n * n * n;
   const int mock = blockIdx.y;
   const c2<T>* d = dhat + mock * n3;
@@ -2291,6 +2302,10 @@ __global__ void k_fbar_adjoint(const c2<T>* dhat, const double* h, int n, int nq
     for (int a = 0; a < 3; ++a) {
       const double th = tp * qs[a];
       b7 *= (2416.0 + 2382.0 * cos(th) + 240.0 * cos(2.0 * th) + 2.0 * cos(3.0 * th)) / 5040.0;
+    }
+    if (phi) {
+      const double ph = (double)phi[ix] * (double)phi[iy] * (double)phi[iz];
+      b7 *= ph * ph;
     }
     const double f = scale * b7 * hm[qx * qx + qy * qy + qz * qz];
     const c2<T> v = d[i];
@@ -2434,7 +2449,8 @@ hipError_t filter_y_t(const FilterArgs& a, hipStream_t st) {
   const dim3 gs((N * (N / ZC) + G - 1) / G, a.batch);
   k_filter_y<N, T><<<gs, threads, 0, st>>>(static_cast<const CT<T>*>(a.src), static_cast<CT<T>*>(a.dst),
                                           static_cast<const T*>(a.jtab), a.nq2, a.nbins, a.nbp, a.l, a.m, a.norm,
-                                          a.scale, static_cast<const CT<T>*>(a.tw), a.yr);
+                                          a.scale, static_cast<const CT<T>*>(a.tw), a.yr,
+                                          static_cast<const T*>(a.phi));
   return hipGetLastError();
 }
 
@@ -2446,7 +2462,8 @@ hipError_t adjoint_y_t(const FilterArgs& a, hipStream_t st) {
   const dim3 gs((N * (N / ZC) + G - 1) / G, a.batch);
   k_adjoint_y<N, T><<<gs, threads, 0, st>>>(static_cast<const CT<T>*>(a.src), static_cast<CT<T>*>(a.dst),
                                            static_cast<const T*>(a.jtab), a.nq2, a.nbins, a.nbp, a.l, a.m, a.norm,
-                                           a.scale, static_cast<const CT<T>*>(a.tw), a.yr);
+                                           a.scale, static_cast<const CT<T>*>(a.tw), a.yr,
+                                           static_cast<const T*>(a.phi));
   return hipGetLastError();
 }
 
@@ -2682,6 +2699,12 @@ hipError_t launch_fill(int prec, void* p, long long count, double value, hipStre
   return hipGetLastError();
 }
 
+hipError_t launch_fill_i32(int* p, long long count, int value, hipStream_t st) {
+  const unsigned g = grid_for(count, 256, 8192);
+  k_fill<int><<<g, 256, 0, st>>>(p, count, value);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_f64(double* p, long long count, double value, hipStream_t st) {
   const unsigned g = grid_for(count, 256, 8192);
   k_fill<double><<<g, 256, 0, st>>>(p, count, value);
@@ -2887,11 +2910,14 @@ hipError_t launch_gather_contract(int prec, const GatherArgs& a, hipStream_t st)
   return gather_contract_t<float, false>(a, st);
 }
 
-hipError_t launch_power_hist(int prec, const void* dhat, int n, int nq2, double* P, int batch, hipStream_t st) {
+hipError_t launch_power_hist(int prec, const void* dhat, int n, int nq2, double* P, int batch, const void* phi,
+                             hipStream_t st) {
   const long long n3 = (long long)n * n * n;
   const dim3 gs(grid_for(n3, 256, 8192), batch);
-  if (prec) k_power_hist<double><<<gs, 256, 0, st>>>(static_cast<const double2*>(dhat), n, nq2, P);
-  else k_power_hist<float><<<gs, 256, 0, st>>>(static_cast<const float2*>(dhat), n, nq2, P);
+  if (prec) k_power_hist<double><<<gs, 256, 0, st>>>(static_cast<const double2*>(dhat), n, nq2, P,
+                                                    static_cast<const double*>(phi));
+  else k_power_hist<float><<<gs, 256, 0, st>>>(static_cast<const float2*>(dhat), n, nq2, P,
+                                                  static_cast<const float*>(phi));
   return hipGetLastError();
 }
 
@@ -3002,18 +3028,19 @@ hipError_t launch_tap_records(int prec, const float* pos, const int* perm, long 
 }
 
 hipError_t launch_fbar_adjoint(int prec, const double* dzeta, const void* jtab, int nq2, int nbp, int nbins, int lmax,
-                               const void* dhat, int n, double scale, double* h, void* G, int batch, hipStream_t st) {
+                               const void* dhat, int n, double scale, double* h, void* G, int batch, const void* phi,
+                               hipStream_t st) {
   const dim3 gh(grid_for(nq2, 256, 1024), batch);
   const long long n3 = (long long)n * n * n;
   const dim3 gs(grid_for(n3, 256, 8192), batch);
   if (prec) {
     k_fbar_weight<double><<<gh, 256, 0, st>>>(dzeta, static_cast<const double*>(jtab), nq2, nbp, nbins, lmax, h);
     k_fbar_adjoint<double><<<gs, 256, 0, st>>>(static_cast<const double2*>(dhat), h, n, nq2, scale,
-                                               static_cast<double2*>(G));
+                                               static_cast<double2*>(G), static_cast<const double*>(phi));
   } else {
     k_fbar_weight<float><<<gh, 256, 0, st>>>(dzeta, static_cast<const float*>(jtab), nq2, nbp, nbins, lmax, h);
     k_fbar_adjoint<float><<<gs, 256, 0, st>>>(static_cast<const float2*>(dhat), h, n, nq2, scale,
-                                              static_cast<float2*>(G));
+                                              static_cast<float2*>(G), static_cast<const float*>(phi));
   }
   return hipGetLastError();
 }

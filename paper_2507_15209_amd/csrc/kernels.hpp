@@ -23,6 +23,7 @@ struct FilterArgs {
   double norm;       // Y_lm normalisation
   double scale;      // extra real factor (1/N^3, times the m weight in the adjoint)
   YlmRec yr;         // Legendre recurrence of (l, m)
+  const void* phi = nullptr;   // [N] per-axis phi-hat factors (real), or NULL for none
 };
 
 struct ZpassArgs {
@@ -75,7 +76,9 @@ hipError_t launch_tile_sort(const float* pos, const long long* off, int batch, l
 hipError_t launch_deposit_tiled(int prec, int tside, const float* pos, const float* w, const int* perm, const int* toff,
                                 int ntiles_total, int wgs, int* counter, int n, double sc, void* eps, hipStream_t st);
 hipError_t launch_gather_contract(int prec, const GatherArgs& a, hipStream_t st);
-hipError_t launch_power_hist(int prec, const void* dhat, int n, int nq2, double* P, int batch, hipStream_t st);
+// per-|q|^2 histogram of |dhat|^2 B7hat (times phi-hat^2 when phi != NULL), Nyquist planes excluded
+hipError_t launch_power_hist(int prec, const void* dhat, int n, int nq2, double* P, int batch, const void* phi,
+                             hipStream_t st);
 hipError_t launch_fbar_subtract(int prec, const double* P, const void* jtab, int nq2, int nbp, int nbins, int l, int lmax,
                                 double n6, double* zeta, int batch, hipStream_t st);
 hipError_t launch_fft3d(int n, int prec, int dir, bool real_in, const void* in, void* out, int nfields, const void* tw,
@@ -94,6 +97,7 @@ size_t zpass_lds_need(int n, int prec, int nbins);
 size_t zpass_fused_lds_need(int n, int prec, int nbins);
 hipError_t launch_fill(int prec, void* p, long long count, double value, hipStream_t st);
 hipError_t launch_fill_f64(double* p, long long count, double value, hipStream_t st);
+hipError_t launch_fill_i32(int* p, long long count, int value, hipStream_t st);
 hipError_t launch_lam_sym(int prec, const double* dzeta, void* lam_s, int nbins, int l, int lmax, int batch,
                           hipStream_t st);
 hipError_t launch_reduce_partials(const double* partials, int nwg, int nb2, double* zeta, int l, int lmax, double scale,
@@ -115,7 +119,8 @@ hipError_t launch_scatter_source(int prec, const int* tcell, const void* twt, co
 hipError_t launch_tap_records(int prec, const float* pos, const int* perm, long long np_total, int n, double sc,
                               int* tcell, void* twt, hipStream_t st);
 hipError_t launch_fbar_adjoint(int prec, const double* dzeta, const void* jtab, int nq2, int nbp, int nbins, int lmax,
-                               const void* dhat, int n, double scale, double* h, void* G, int batch, hipStream_t st);
+                               const void* dhat, int n, double scale, double* h, void* G, int batch, const void* phi,
+                               hipStream_t st);
 // grid-Gamma adjoint for one (l, m): adds the transposed-quadrature sources
 // into cout ([batch][nbins][N^3], zeroed by the caller) and wm times the
 // primary's share into direct; fields bin-interleaved, at most 20 bins.
@@ -133,5 +138,22 @@ hipError_t launch_grad_combine(int prec, const void* direct, const void* ghat, v
 hipError_t launch_dot_rho_g(int prec, const void* delta, const void* g, long long n3, double* S, int batch, hipStream_t st);
 hipError_t launch_gather_dw(int prec, const float* pos, const long long* off, int batch, long long np_total, int n,
                             double sc, const void* g, const double* W, const double* S, void* dw, hipStream_t st);
+
+// stats.hip: input validation, the top-hat filter of the primary vertex, xi and Q
+// flag[0] += 1 when any of count values (float or double by prec) is NaN or infinite
+hipError_t launch_count_nonfinite(int prec, const void* p, long long count, int* flag, hipStream_t st);
+// X *= scale * W_TH(|k| R) in place over [batch][N^3] complex spectra, k = kf q
+hipError_t launch_tophat_filter(int prec, void* X, int n, double kf, double R, double scale, int batch, hipStream_t st);
+hipError_t launch_real_part(int prec, const void* in, void* out, long long count, hipStream_t st);
+// per-|q|^2 histogram of |dhat|^2 (times phi-hat when phi != NULL), Nyquist planes excluded
+hipError_t launch_power_plain(int prec, const void* dhat, int n, int nq2, double* P, int batch, const void* phi,
+                              hipStream_t st);
+// xi[batch][nr] at device radii from the histogram of launch_power_plain
+hipError_t launch_xi(const double* P, int nq2, double kf, double R, bool prim_smooth, const double* radii, int nr,
+                     double n6, double* xi, int batch, hipStream_t st);
+// zt[batch][nbins][nbins][nth] = sum_{l <= lt} zeta_l P_l(mu) and, when q != NULL, the reduced 3PCF
+hipError_t launch_reduced_3pcf(const double* zeta, int lmax, int lt, int nbins, const double* mu, int nth,
+                               const double* rb, const double* xib, const double* P, int nq2, double kf, double R,
+                               bool prim_smooth, double n6, double* zt, double* q, int batch, hipStream_t st);
 
 }  // namespace mp3

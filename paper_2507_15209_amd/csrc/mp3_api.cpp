@@ -25,6 +25,10 @@ struct mp3_plan_s {
   double gm[5][4] = {{0}};   // grid-Gamma quadrature: B3 tap weights at the nodes
   double gw[5] = {0};        // and node weights
   int tune[MP3_NTUNE] = {4096, 4096, 0, 8, 2048};   // launch-shape knobs (mp3_tune_knob)
+  int basis = 0, binning = 0;
+  unsigned kflags = 0;
+  double smoothing = 0.0;   // top-hat radius of every vertex (0 = none)
+  void* phi = nullptr;      // [n] real per-axis phi-hat factors when MP3_KF_PHI_HAT
   // optional per-pass HIP event timing
   bool profile = false;
   std::vector<hipEvent_t> pool;
@@ -60,6 +64,7 @@ constexpr size_t kLdsLimit = 160 * 1024;
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
+  size_t dprim, flag, pplain, aux, xib;
   size_t off, W, S, dhat, fields, partials, G, direct, lam, fields_i, perm, counts, offs, cursor, power;
   size_t src, fj, hq, SF, tcell, twt;
   size_t dperm, dcounts, doffs, dcursor, dcounter, total;
@@ -67,6 +72,7 @@ struct Layout {
 };
 
 constexpr int kGatherSlice = 256;
+constexpr int kMaxAux = 4096;   // radii of mp3_xi, angles of mp3_reduced_3pcf
 
 // workgroups per mock of the particle gather: at least four slices each
 int gather_wgs(const mp3_plan_s* p, long long np_max) {
@@ -121,6 +127,13 @@ Layout layout(const mp3_plan_s* p, long long np_total = 0) {
   L.G = take(B * n3 * p->celt);
   L.direct = take(B * n3 * p->elt);
   L.lam = take(B * nb2 * p->elt);
+  // primary vertex filtered by the top-hat window (grid forms with smoothing)
+  if (p->smoothing > 0.0 && p->summation != MP3_SUM_PARTICLE) L.dprim = take(B * n3 * p->elt);
+  L.flag = take(sizeof(int));
+  // plain power histogram, radii / cosines of mp3_xi and mp3_reduced_3pcf, xi at the bins
+  L.pplain = take(B * (size_t)mp3::nq2_count(p->n) * sizeof(double));
+  L.aux = take((size_t)2 * kMaxAux * sizeof(double));
+  L.xib = take(B * (size_t)p->nbins * sizeof(double));
   if (p->summation != MP3_SUM_NODAL) L.fields_i = take(B * (size_t)p->nbins * n3 * p->celt);
   if (p->summation == MP3_SUM_PARTICLE) {
     const size_t nt = (size_t)(p->n / 4) * (p->n / 4) * (p->n / 4) * B + 1;
@@ -152,6 +165,51 @@ Layout layout(const mp3_plan_s* p, long long np_total = 0) {
 }
 
 bool pow2_supported(int n) { return n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512; }
+
+constexpr unsigned kKnownFlags = MP3_KF_PHI_HAT | MP3_KF_CHECK_FINITE;
+
+// checks shared by mp3_plan_create and mp3_window_table
+int validate_desc(const mp3_plan_desc* d) {
+  if (!pow2_supported(d->n)) return fail(MP3_EUNSUPPORTED, "n must be one of 16, 32, 64, 128, 256, 512");
+  if (!std::isfinite(d->box)) return fail(MP3_ENONFINITE, "box is not finite");
+  if (!(d->box > 0.0)) return fail(MP3_EINVAL, "box must be positive");
+  if (d->lmax < 0 || d->lmax > 20) return fail(MP3_EINVAL, "lmax must be in [0, 20]");
+  if (d->nbins < 1 || d->nbins > 64) return fail(MP3_EINVAL, "nbins must be in [1, 64]");
+  if (!d->edges) return fail(MP3_EINVAL, "edges is NULL");
+  for (int b = 0; b <= d->nbins; ++b) {
+    if (!std::isfinite(d->edges[b])) return fail(MP3_ENONFINITE, "edges must be finite");
+    if (d->edges[b] < 0.0) return fail(MP3_EINVAL, "edges must be >= 0");
+    if (b > 0 && !(d->edges[b] > d->edges[b - 1])) return fail(MP3_EINVAL, "edges must increase strictly");
+  }
+  if (d->precision != MP3_F32 && d->precision != MP3_F64 && d->precision != MP3_F32_BF16X3)
+    return fail(MP3_EINVAL, "precision must be MP3_F32, MP3_F64 or MP3_F32_BF16X3");
+  if (d->summation != MP3_SUM_NODAL && d->summation != MP3_SUM_PARTICLE && d->summation != MP3_SUM_GRID_GAMMA)
+    return fail(MP3_EUNSUPPORTED, "summation form not supported");
+  if (d->batch < 1) return fail(MP3_EINVAL, "batch must be >= 1");
+  if (d->basis != MP3_BASIS_BSPLINE3) return fail(MP3_EUNSUPPORTED, "only the cubic B-spline basis is implemented");
+  if (d->kflags & ~kKnownFlags) return fail(MP3_EINVAL, "unknown kflags bits");
+  if (d->binning != MP3_BIN_SHELL_AVERAGE && d->binning != MP3_BIN_THIN_SHELL)
+    return fail(MP3_EINVAL, "binning must be MP3_BIN_SHELL_AVERAGE or MP3_BIN_THIN_SHELL");
+  if (!std::isfinite(d->smoothing)) return fail(MP3_ENONFINITE, "smoothing is not finite");
+  if (d->smoothing < 0.0) return fail(MP3_EINVAL, "smoothing must be >= 0");
+  return MP3_OK;
+}
+
+// with MP3_KF_CHECK_FINITE: count non-finite values on the device and wait
+// for the answer (the call blocks); ptrs/counts/precisions of up to 3 arrays
+int check_finite(const mp3_plan_s* p, void* ws, size_t flag_off, hipStream_t st, const void* a, long long na, int pa,
+                 const void* b = nullptr, long long nb = 0, int pb = 0) {
+  if (!(p->kflags & MP3_KF_CHECK_FINITE)) return MP3_OK;
+  int* flag = reinterpret_cast<int*>(static_cast<char*>(ws) + flag_off);
+  MP3_HIP(mp3::launch_fill_i32(flag, 1, 0, st), "zero flag");
+  if (a) MP3_HIP(mp3::launch_count_nonfinite(pa, a, na, flag, st), "finite check");
+  if (b) MP3_HIP(mp3::launch_count_nonfinite(pb, b, nb, flag, st), "finite check");
+  int h = 0;
+  MP3_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st), "read flag");
+  MP3_HIP(hipStreamSynchronize(st), "wait for the finite check");
+  if (h) return fail(MP3_ENONFINITE, "a NaN or infinity in the input");
+  return MP3_OK;
+}
 
 int check_plan(const mp3_plan_s* p) {
   if (!p) return fail(MP3_EINVAL, "plan is NULL");
@@ -245,6 +303,7 @@ mp3::FilterArgs filter_args(const mp3_plan_s* p, const void* src, void* dst, int
   a.batch = p->batch;
   a.norm = mp3::ylm_norm(l, m);
   a.scale = scale;
+  a.phi = p->phi;
   a.yr.pmm = 1.0;
   for (int k = 1; k <= m; ++k) a.yr.pmm *= -(2.0 * k - 1.0);
   for (int k = 0; k < 21; ++k) {
@@ -263,6 +322,42 @@ int fields_xy(const mp3_plan_s* p, void* ws, const Layout& L, void* dst, int l, 
   return MP3_OK;
 }
 
+// The grid forms' primary vertex: delta itself, or with a smoothing radius
+// delta_p = IFFT[ W_TH(kR) FFT(delta) ] (dhat must be current), stored in the
+// workspace; the fields buffer serves as scratch.
+const void* primary_field(const mp3_plan_s* p, const void* delta, void* ws, const Layout& L, hipStream_t st,
+                          int* status) {
+  *status = MP3_OK;
+  if (!(p->smoothing > 0.0) || p->summation == MP3_SUM_PARTICLE) return delta;
+  const long long n3 = (long long)p->n * p->n * p->n;
+  void* tmp = at(ws, L.fields);
+  hipError_t e = hipMemcpyAsync(tmp, at(ws, L.dhat), (size_t)p->batch * n3 * p->celt, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess)
+    e = mp3::launch_tophat_filter(p->prec, tmp, p->n, 2.0 * M_PI / p->box, p->smoothing, 1.0 / (double)n3, p->batch, st);
+  if (e == hipSuccess) e = mp3::launch_fft3d(p->n, p->prec, +1, false, tmp, tmp, p->batch, p->tw, st);
+  if (e == hipSuccess) e = mp3::launch_real_part(p->prec, tmp, at(ws, L.dprim), n3 * p->batch, st);
+  if (e != hipSuccess) {
+    *status = hip_fail(e, "primary top-hat filter");
+    return nullptr;
+  }
+  return at(ws, L.dprim);
+}
+
+// the transpose of primary_field applied to the primary's gradient share
+// (the filter is real and even, so it is its own transpose), in place
+int filter_direct(const mp3_plan_s* p, void* direct, void* ws, const Layout& L, hipStream_t st) {
+  if (!(p->smoothing > 0.0) || p->summation == MP3_SUM_PARTICLE) return MP3_OK;
+  const long long n3 = (long long)p->n * p->n * p->n;
+  void* tmp = at(ws, L.fields);
+  MP3_HIP(mp3::launch_fft3d(p->n, p->prec, -1, true, direct, tmp, p->batch, p->tw, st), "transpose filter: DFT");
+  MP3_HIP(mp3::launch_tophat_filter(p->prec, tmp, p->n, 2.0 * M_PI / p->box, p->smoothing, 1.0 / (double)n3, p->batch,
+                                    st),
+          "transpose filter");
+  MP3_HIP(mp3::launch_fft3d(p->n, p->prec, +1, false, tmp, tmp, p->batch, p->tw, st), "transpose filter: inverse DFT");
+  MP3_HIP(mp3::launch_real_part(p->prec, tmp, direct, n3 * p->batch, st), "transpose filter: real part");
+  return MP3_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -275,6 +370,7 @@ const char* mp3_status_string(int s) {
     case MP3_EHIP: return "MP3_EHIP";
     case MP3_EUNSUPPORTED: return "MP3_EUNSUPPORTED";
     case MP3_EWORKSPACE: return "MP3_EWORKSPACE";
+    case MP3_ENONFINITE: return "MP3_ENONFINITE";
     default: return "MP3_UNKNOWN";
   }
 }
@@ -283,23 +379,10 @@ const char* mp3_last_error(void) { return g_last_error.c_str(); }
 
 int mp3_plan_create(const mp3_plan_desc* d, mp3_plan_t* out) {
   if (!d || !out) return fail(MP3_EINVAL, "desc and out must not be NULL");
-  if (!pow2_supported(d->n)) return fail(MP3_EUNSUPPORTED, "n must be one of 16, 32, 64, 128, 256, 512");
-  if (!(d->box > 0.0) || !std::isfinite(d->box)) return fail(MP3_EINVAL, "box must be positive and finite");
-  if (d->lmax < 0 || d->lmax > 20) return fail(MP3_EINVAL, "lmax must be in [0, 20]");
-  if (d->nbins < 1 || d->nbins > 64) return fail(MP3_EINVAL, "nbins must be in [1, 64]");
-  if (!d->edges) return fail(MP3_EINVAL, "edges is NULL");
-  for (int b = 0; b <= d->nbins; ++b) {
-    if (!std::isfinite(d->edges[b]) || d->edges[b] < 0.0) return fail(MP3_EINVAL, "edges must be finite and >= 0");
-    if (b > 0 && !(d->edges[b] > d->edges[b - 1])) return fail(MP3_EINVAL, "edges must increase strictly");
-  }
-  if (d->precision != MP3_F32 && d->precision != MP3_F64 && d->precision != MP3_F32_BF16X3)
-    return fail(MP3_EINVAL, "precision must be MP3_F32, MP3_F64 or MP3_F32_BF16X3");
+  if (int s = validate_desc(d)) return s;
   const int storage = d->precision == MP3_F64 ? 1 : 0;
-  if (d->summation != MP3_SUM_NODAL && d->summation != MP3_SUM_PARTICLE && d->summation != MP3_SUM_GRID_GAMMA)
-    return fail(MP3_EUNSUPPORTED, "summation form not supported");
   if (d->summation == MP3_SUM_GRID_GAMMA && mp3::gamma_lds_need(storage, d->nbins) > kLdsLimit)
     return fail(MP3_EUNSUPPORTED, "nbins too large for the grid-Gamma tile's LDS at this precision");
-  if (d->batch < 1) return fail(MP3_EINVAL, "batch must be >= 1");
   // the nodal z passes hold every bin of a pencil in LDS (the other forms'
   // store pass takes the bins in chunks)
   if (d->summation == MP3_SUM_NODAL && mp3::zpass_lds_need(d->n, storage, d->nbins) > kLdsLimit)
@@ -315,6 +398,10 @@ int mp3_plan_create(const mp3_plan_desc* d, mp3_plan_t* out) {
   p->split = d->precision == MP3_F32_BF16X3;
   p->summation = d->summation;
   p->batch = d->batch;
+  p->basis = d->basis;
+  p->binning = d->binning;
+  p->kflags = d->kflags;
+  p->smoothing = d->smoothing;
   p->edges.assign(d->edges, d->edges + d->nbins + 1);
   p->nq2 = mp3::nq2_count(p->n);
   p->nbp = (p->nbins + 3) / 4 * 4;
@@ -324,7 +411,7 @@ int mp3_plan_create(const mp3_plan_desc* d, mp3_plan_t* out) {
   hipGetDevice(&p->device);
 
   std::vector<double> jt;
-  mp3::jbar_table(p->n, p->box, p->lmax, p->edges, jt);
+  mp3::jbar_table(p->n, p->box, p->lmax, p->edges, jt, p->binning, p->smoothing);
   std::vector<double> twr, twi;
   mp3::twiddles(p->n, twr, twi);
   const size_t rows = (size_t)(p->lmax + 1) * p->nq2;
@@ -355,11 +442,24 @@ int mp3_plan_create(const mp3_plan_desc* d, mp3_plan_t* out) {
   }
   hipError_t e1 = hipMemcpy(p->jtab, hj.data(), hj.size(), hipMemcpyHostToDevice);
   hipError_t e2 = hipMemcpy(p->tw, ht.data(), ht.size(), hipMemcpyHostToDevice);
-  if (e1 != hipSuccess || e2 != hipSuccess) {
+  hipError_t e3 = hipSuccess;
+  if (p->kflags & MP3_KF_PHI_HAT) {
+    std::vector<double> ph;
+    mp3::phi_hat_axis(p->n, ph);
+    std::vector<char> hp((size_t)p->n * p->elt);
+    for (int i = 0; i < p->n; ++i) {
+      if (p->prec) reinterpret_cast<double*>(hp.data())[i] = ph[i];
+      else reinterpret_cast<float*>(hp.data())[i] = (float)ph[i];
+    }
+    e3 = hipMalloc(&p->phi, hp.size());
+    if (e3 == hipSuccess) e3 = hipMemcpy(p->phi, hp.data(), hp.size(), hipMemcpyHostToDevice);
+  }
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
     hipFree(p->jtab);
     hipFree(p->tw);
+    if (p->phi) hipFree(p->phi);
     delete p;
-    return hip_fail(e1 != hipSuccess ? e1 : e2, "upload plan tables");
+    return hip_fail(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3), "upload plan tables");
   }
   *out = p;
   return MP3_OK;
@@ -391,6 +491,7 @@ int mp3_plan_destroy(mp3_plan_t p) {
   for (hipEvent_t e : p->pool) hipEventDestroy(e);
   if (p->jtab) hipFree(p->jtab);
   if (p->tw) hipFree(p->tw);
+  if (p->phi) hipFree(p->phi);
   delete p;
   return MP3_OK;
 }
@@ -453,13 +554,14 @@ int mp3_deposit(mp3_plan_t p, const float* pos, const float* w, const int64_t* n
   if (int s = check_ws(p, ws, wsb, L.total)) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const long long n3 = (long long)p->n * p->n * p->n;
+  if (np_total >= (1LL << 31)) return fail(MP3_EUNSUPPORTED, "more than 2^31 - 1 particles");
+  if (int s = check_finite(p, ws, L.flag, st, pos, 3 * np_total, 0, w, w ? np_total : 0, 0)) return s;
   if (int s = upload_offsets(p, np_off, ws, L, st)) return s;
   const long long* off = reinterpret_cast<const long long*>(at(ws, L.off));
   double* W = reinterpret_cast<double*>(at(ws, L.W));
   MP3_HIP(mp3::launch_fill_f64(W, p->batch, 0.0, st), "zero W");
   MP3_HIP(mp3::launch_weight_sum(w, off, p->batch, np_max, W, st), "weight sum");
   MP3_HIP(mp3::launch_fill(p->prec, delta, n3 * p->batch, 0.0, st), "zero grid");
-  if (np_total >= (1LL << 31)) return fail(MP3_EUNSUPPORTED, "more than 2^31 - 1 particles");
   const double sc = (double)p->n / p->box;
   int* dperm = reinterpret_cast<int*>(at(ws, L.dperm));
   int* doffs = reinterpret_cast<int*>(at(ws, L.doffs));
@@ -544,7 +646,7 @@ int zeta_particle(mp3_plan_t p, const float* pos, const float* w, const int64_t*
   double* P = reinterpret_cast<double*>(at(ws, L.power));
   const int nq2 = mp3::nq2_count(p->n);
   MP3_HIP(mp3::launch_fill_f64(P, (long long)p->batch * nq2, 0.0, st), "zero power");
-  MP3_HIP(mp3::launch_power_hist(p->prec, at(ws, L.dhat), p->n, nq2, P, p->batch, st), "power histogram");
+  MP3_HIP(mp3::launch_power_hist(p->prec, at(ws, L.dhat), p->n, nq2, P, p->batch, p->phi, st), "power histogram");
   void* F = at(ws, L.fields);
   void* Fi = at(ws, L.fields_i);
   double* partials = reinterpret_cast<double*>(at(ws, L.partials));
@@ -637,11 +739,16 @@ int mp3_zeta(mp3_plan_t p, const void* delta, const float* pos, const float* w, 
   const Layout L = layout(p, np_total);
   if (int s = check_ws(p, ws, wsb, L.total)) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  const long long n3 = (long long)p->n * p->n * p->n;
+  if (int s = check_finite(p, ws, L.flag, st, delta, n3 * p->batch, p->prec)) return s;
   if (int s = forward_dft(p, delta, ws, L, st)) return s;
   MP3_HIP(mp3::launch_fill_f64(zeta, (long long)p->batch * (p->lmax + 1) * p->nbins * p->nbins, 0.0, st), "zero zeta");
   if (p->summation == MP3_SUM_PARTICLE) return zeta_particle(p, pos, w, np_off, np_total, np_max, zeta, ws, L, st);
-  if (p->summation == MP3_SUM_GRID_GAMMA) return zeta_gamma(p, delta, zeta, ws, L, st);
-  return zeta_nodal(p, delta, zeta, ws, L, st);
+  int ps = MP3_OK;
+  const void* prim = primary_field(p, delta, ws, L, st, &ps);
+  if (ps) return ps;
+  if (p->summation == MP3_SUM_GRID_GAMMA) return zeta_gamma(p, prim, zeta, ws, L, st);
+  return zeta_nodal(p, prim, zeta, ws, L, st);
 }
 
 namespace {
@@ -655,6 +762,7 @@ int nodal_gradient_tail(mp3_plan_t p, const void* delta, void* ddelta, const flo
   void* G = at(ws, L.G);
   void* direct = at(ws, L.direct);
   MP3_HIP(timed(p, MP3_PASS_DFT, st, [&] { return mp3::launch_fft3d(p->n, p->prec, -1, false, G, G, p->batch, p->tw, st); }), "adjoint final FFT");
+  if (int s = filter_direct(p, direct, ws, L, st)) return s;
   MP3_HIP(mp3::launch_grad_combine(p->prec, direct, G, ddelta, n3 * p->batch, kFourPi / (double)n3, st), "combine");
   if (dw) {
     if (int s = upload_offsets(p, np_off, ws, L, st)) return s;
@@ -688,6 +796,7 @@ int backward_particle(mp3_plan_t p, const void* delta, const double* dzeta, void
   hipStream_t st = static_cast<hipStream_t>(stream);
   const long long n3 = (long long)p->n * p->n * p->n;
   const double sc = (double)p->n / p->box;
+  if (int s = check_finite(p, ws, L.flag, st, delta, n3 * p->batch, p->prec)) return s;
   if (int s = forward_dft(p, delta, ws, L, st)) return s;
   if (int s = upload_offsets(p, np_off, ws, L, st)) return s;
   const long long* off = reinterpret_cast<const long long*>(at(ws, L.off));
@@ -743,7 +852,8 @@ int backward_particle(mp3_plan_t p, const void* delta, const double* dzeta, void
     }
   }
   MP3_HIP(mp3::launch_fbar_adjoint(p->prec, dzeta, p->jtab, p->nq2, p->nbp, p->nbins, p->lmax, at(ws, L.dhat), p->n,
-                                   -1.0 / (kFourPi * (double)n3), reinterpret_cast<double*>(at(ws, L.hq)), G, p->batch, st),
+                                   -1.0 / (kFourPi * (double)n3), reinterpret_cast<double*>(at(ws, L.hq)), G, p->batch,
+                                   p->phi, st),
           "volume-mean adjoint");
   MP3_HIP(timed(p, MP3_PASS_DFT, st, [&] { return mp3::launch_fft3d(p->n, p->prec, -1, false, G, G, p->batch, p->tw, st); }), "adjoint final FFT");
   MP3_HIP(mp3::launch_grad_combine(p->prec, direct, G, ddelta, n3 * p->batch, kFourPi / (double)n3, st), "combine");
@@ -781,6 +891,7 @@ int value_and_grad_particle(mp3_plan_t p, const void* delta, const double* dzeta
   const long long n3 = (long long)p->n * p->n * p->n;
   const double n3d = (double)n3;
   const double sc = (double)p->n / p->box;
+  if (int s = check_finite(p, ws, L.flag, st, delta, n3 * p->batch, p->prec)) return s;
   if (int s = forward_dft(p, delta, ws, L, st)) return s;
   MP3_HIP(mp3::launch_fill_f64(zeta, (long long)p->batch * (p->lmax + 1) * nb2, 0.0, st), "zero zeta");
   if (int s = upload_offsets(p, np_off, ws, L, st)) return s;
@@ -799,7 +910,7 @@ int value_and_grad_particle(mp3_plan_t p, const void* delta, const double* dzeta
   double* P = reinterpret_cast<double*>(at(ws, L.power));
   const int nq2 = mp3::nq2_count(p->n);
   MP3_HIP(mp3::launch_fill_f64(P, (long long)p->batch * nq2, 0.0, st), "zero power");
-  MP3_HIP(mp3::launch_power_hist(p->prec, at(ws, L.dhat), p->n, nq2, P, p->batch, st), "power histogram");
+  MP3_HIP(mp3::launch_power_hist(p->prec, at(ws, L.dhat), p->n, nq2, P, p->batch, p->phi, st), "power histogram");
   void* F = at(ws, L.fields);
   void* Fi = at(ws, L.fields_i);
   void* G = at(ws, L.G);
@@ -872,7 +983,8 @@ int value_and_grad_particle(mp3_plan_t p, const void* delta, const double* dzeta
             "volume mean");
   }
   MP3_HIP(mp3::launch_fbar_adjoint(p->prec, dzeta, p->jtab, p->nq2, p->nbp, p->nbins, p->lmax, at(ws, L.dhat), p->n,
-                                   -1.0 / (kFourPi * n3d), reinterpret_cast<double*>(at(ws, L.hq)), G, p->batch, st),
+                                   -1.0 / (kFourPi * n3d), reinterpret_cast<double*>(at(ws, L.hq)), G, p->batch,
+                                   p->phi, st),
           "volume-mean adjoint");
   MP3_HIP(timed(p, MP3_PASS_DFT, st, [&] { return mp3::launch_fft3d(p->n, p->prec, -1, false, G, G, p->batch, p->tw, st); }), "adjoint final FFT");
   MP3_HIP(mp3::launch_grad_combine(p->prec, direct, G, ddelta, n3 * p->batch, kFourPi / n3d, st), "combine");
@@ -905,7 +1017,11 @@ int backward_gamma(mp3_plan_t p, const void* delta, const double* dzeta, void* d
   if (int s = check_ws(p, ws, wsb, L.total)) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const long long n3 = (long long)p->n * p->n * p->n;
+  if (int s = check_finite(p, ws, L.flag, st, delta, n3 * p->batch, p->prec)) return s;
   if (int s = forward_dft(p, delta, ws, L, st)) return s;
+  int ps = MP3_OK;
+  const void* prim = primary_field(p, delta, ws, L, st, &ps);
+  if (ps) return ps;
   void* F = at(ws, L.fields);
   void* Fi = at(ws, L.fields_i);
   void* G = at(ws, L.G);
@@ -934,7 +1050,7 @@ int backward_gamma(mp3_plan_t p, const void* delta, const double* dzeta, void* d
       MP3_HIP(timed(p, MP3_PASS_Z_STORE, st, [&] { return mp3::launch_zpass_store(p->n, p->prec, z, Fi, st); }), "z pass (store)");
       MP3_HIP(mp3::launch_fill(p->prec, F, 2 * n3 * p->batch * p->nbins, 0.0, st), "zero sources");
       MP3_HIP(timed(p, MP3_PASS_GAMMA, st, [&] {
-                return mp3::launch_gamma_adjoint(p->prec, Fi, delta, at(ws, L.lam), p->n, p->nbins, p->gm, p->gw, wm,
+                return mp3::launch_gamma_adjoint(p->prec, Fi, prim, at(ws, L.lam), p->n, p->nbins, p->gm, p->gw, wm,
                                                  (int)gwg, p->batch, F, direct, partials, st);
               }),
               "grid-Gamma adjoint");
@@ -951,6 +1067,7 @@ int backward_gamma(mp3_plan_t p, const void* delta, const double* dzeta, void* d
     }
   }
   MP3_HIP(timed(p, MP3_PASS_DFT, st, [&] { return mp3::launch_fft3d(p->n, p->prec, -1, false, G, G, p->batch, p->tw, st); }), "adjoint final FFT");
+  if (int s = filter_direct(p, direct, ws, L, st)) return s;
   MP3_HIP(mp3::launch_grad_combine(p->prec, direct, G, ddelta, n3 * p->batch, kFourPi / (double)n3, st), "combine");
   if (dw) {
     if (int s = upload_offsets(p, np_off, ws, L, st)) return s;
@@ -984,7 +1101,11 @@ int mp3_zeta_backward(mp3_plan_t p, const void* delta, const double* dzeta, void
   if (int s = check_ws(p, ws, wsb, L.total)) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const long long n3 = (long long)p->n * p->n * p->n;
+  if (int s = check_finite(p, ws, L.flag, st, delta, n3 * p->batch, p->prec)) return s;
   if (int s = forward_dft(p, delta, ws, L, st)) return s;
+  int ps = MP3_OK;
+  const void* prim = primary_field(p, delta, ws, L, st, &ps);
+  if (ps) return ps;
   void* F = at(ws, L.fields);
   void* G = at(ws, L.G);
   void* direct = at(ws, L.direct);
@@ -998,7 +1119,7 @@ int mp3_zeta_backward(mp3_plan_t p, const void* delta, const double* dzeta, void
       if (int s = fields_xy(p, ws, L, F, l, m, st)) return s;
       mp3::ZpassArgs z{};
       z.fields = F;
-      z.delta = delta;
+      z.delta = prim;
       z.dzeta = dzeta;
       z.lam = at(ws, L.lam);
       z.direct = direct;
@@ -1046,7 +1167,11 @@ int mp3_zeta_value_and_grad(mp3_plan_t p, const void* delta, const double* dzeta
   hipStream_t st = static_cast<hipStream_t>(stream);
   const long long n3 = (long long)p->n * p->n * p->n;
   const int nb2 = p->nbins * p->nbins;
+  if (int s = check_finite(p, ws, L.flag, st, delta, n3 * p->batch, p->prec)) return s;
   if (int s = forward_dft(p, delta, ws, L, st)) return s;
+  int ps = MP3_OK;
+  const void* prim = primary_field(p, delta, ws, L, st, &ps);
+  if (ps) return ps;
   void* F = at(ws, L.fields);
   void* G = at(ws, L.G);
   void* direct = at(ws, L.direct);
@@ -1062,7 +1187,7 @@ int mp3_zeta_value_and_grad(mp3_plan_t p, const void* delta, const double* dzeta
       if (int s = fields_xy(p, ws, L, F, l, m, st)) return s;
       mp3::ZpassArgs z{};
       z.fields = F;
-      z.delta = delta;
+      z.delta = prim;
       z.partials = partials;
       z.dzeta = dzeta;
       z.lam = at(ws, L.lam);
@@ -1085,6 +1210,104 @@ int mp3_zeta_value_and_grad(mp3_plan_t p, const void* delta, const double* dzeta
     }
   }
   return nodal_gradient_tail(p, delta, ddelta, pos, w, np_off, dw, ws, L, np_total, np_max, st);
+}
+
+namespace {
+
+// plain |dhat|^2 histogram of delta (forward transform included) into L.pplain
+int power_plain(mp3_plan_t p, const void* delta, void* ws, const Layout& L, hipStream_t st) {
+  if (int s = forward_dft(p, delta, ws, L, st)) return s;
+  double* P = reinterpret_cast<double*>(at(ws, L.pplain));
+  const int nq2 = mp3::nq2_count(p->n);
+  MP3_HIP(mp3::launch_fill_f64(P, (long long)p->batch * nq2, 0.0, st), "zero histogram");
+  MP3_HIP(mp3::launch_power_plain(p->prec, at(ws, L.dhat), p->n, nq2, P, p->batch, p->phi, st), "power histogram");
+  return MP3_OK;
+}
+
+bool primary_smoothed(const mp3_plan_s* p) { return p->smoothing > 0.0 && p->summation != MP3_SUM_PARTICLE; }
+
+}  // namespace
+
+int mp3_xi(mp3_plan_t p, const void* delta, const double* radii, int32_t nr, double* xi, void* ws, size_t wsb,
+           void* stream) {
+  if (int s = check_plan(p)) return s;
+  if (!delta || !radii || !xi) return fail(MP3_EINVAL, "delta, radii and xi must not be NULL");
+  if (nr < 1 || nr > kMaxAux) return fail(MP3_EINVAL, "nr must be in [1, 4096]");
+  for (int i = 0; i < nr; ++i) {
+    if (!std::isfinite(radii[i])) return fail(MP3_ENONFINITE, "radii must be finite");
+    if (radii[i] < 0.0) return fail(MP3_EINVAL, "radii must be >= 0");
+  }
+  const Layout L = layout(p);
+  if (int s = check_ws(p, ws, wsb, L.total)) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const long long n3 = (long long)p->n * p->n * p->n;
+  if (int s = check_finite(p, ws, L.flag, st, delta, n3 * p->batch, p->prec)) return s;
+  if (int s = power_plain(p, delta, ws, L, st)) return s;
+  double* dr = reinterpret_cast<double*>(at(ws, L.aux));
+  MP3_HIP(hipMemcpyAsync(dr, radii, (size_t)nr * sizeof(double), hipMemcpyHostToDevice, st), "copy radii");
+  const double n6 = (double)n3 * (double)n3;
+  MP3_HIP(mp3::launch_xi(reinterpret_cast<const double*>(at(ws, L.pplain)), mp3::nq2_count(p->n), 2.0 * M_PI / p->box,
+                         p->smoothing, primary_smoothed(p), dr, nr, n6, xi, p->batch, st),
+          "xi");
+  return MP3_OK;
+}
+
+int mp3_reduced_3pcf(mp3_plan_t p, const void* delta, const double* zeta, int32_t lt, const double* mu, int32_t nth,
+                     double* zeta_theta, double* q, void* ws, size_t wsb, void* stream) {
+  if (int s = check_plan(p)) return s;
+  if (!zeta || !mu || !zeta_theta) return fail(MP3_EINVAL, "zeta, mu and zeta_theta must not be NULL");
+  if (q && !delta) return fail(MP3_EINVAL, "Q needs delta (for xi)");
+  if (lt < 0 || lt > p->lmax) return fail(MP3_EINVAL, "need 0 <= lt <= lmax");
+  if (nth < 1 || nth > kMaxAux) return fail(MP3_EINVAL, "nth must be in [1, 4096]");
+  for (int i = 0; i < nth; ++i) {
+    if (!std::isfinite(mu[i])) return fail(MP3_ENONFINITE, "mu must be finite");
+    if (mu[i] < -1.0 || mu[i] > 1.0) return fail(MP3_EINVAL, "mu must lie in [-1, 1]");
+  }
+  const Layout L = layout(p);
+  if (int s = check_ws(p, ws, wsb, L.total)) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const long long n3 = (long long)p->n * p->n * p->n;
+  double* dmu = reinterpret_cast<double*>(at(ws, L.aux));
+  double* drb = dmu + kMaxAux;
+  std::vector<double> rb(p->nbins);
+  for (int b = 0; b < p->nbins; ++b) rb[b] = 0.5 * (p->edges[b] + p->edges[b + 1]);
+  MP3_HIP(hipMemcpyAsync(dmu, mu, (size_t)nth * sizeof(double), hipMemcpyHostToDevice, st), "copy mu");
+  MP3_HIP(hipMemcpyAsync(drb, rb.data(), (size_t)p->nbins * sizeof(double), hipMemcpyHostToDevice, st), "copy radii");
+  const double n6 = (double)n3 * (double)n3;
+  const int nq2 = mp3::nq2_count(p->n);
+  const double kf = 2.0 * M_PI / p->box;
+  const double* P = reinterpret_cast<const double*>(at(ws, L.pplain));
+  double* xib = reinterpret_cast<double*>(at(ws, L.xib));
+  if (q) {
+    if (int s = check_finite(p, ws, L.flag, st, delta, n3 * p->batch, p->prec)) return s;
+    if (int s = power_plain(p, delta, ws, L, st)) return s;
+    MP3_HIP(mp3::launch_xi(P, nq2, kf, p->smoothing, primary_smoothed(p), drb, p->nbins, n6, xib, p->batch, st),
+            "xi at the bins");
+  }
+  MP3_HIP(mp3::launch_reduced_3pcf(zeta, p->lmax, lt, p->nbins, dmu, nth, drb, xib, P, nq2, kf, p->smoothing,
+                                   primary_smoothed(p), n6, zeta_theta, q, p->batch, st),
+          "reduced 3PCF");
+  return MP3_OK;
+}
+
+int mp3_sph_bessel(int32_t lmax, double x, double* out) {
+  if (!out) return fail(MP3_EINVAL, "out is NULL");
+  if (lmax < 0 || lmax > 64) return fail(MP3_EINVAL, "lmax must be in [0, 64]");
+  if (!std::isfinite(x)) return fail(MP3_ENONFINITE, "x is not finite");
+  if (x < 0.0) return fail(MP3_EINVAL, "x must be >= 0");
+  mp3::sph_bessel_all(lmax, x, out);
+  return MP3_OK;
+}
+
+int mp3_window_table(const mp3_plan_desc* d, double* out, size_t count) {
+  if (!d || !out) return fail(MP3_EINVAL, "desc and out must not be NULL");
+  if (int s = validate_desc(d)) return s;
+  const size_t need = (size_t)(d->lmax + 1) * mp3::nq2_count(d->n) * d->nbins;
+  if (count != need) return fail(MP3_EINVAL, "count must be (lmax+1) * nq2 * nbins = " + std::to_string(need));
+  std::vector<double> edges(d->edges, d->edges + d->nbins + 1), jt;
+  mp3::jbar_table(d->n, d->box, d->lmax, edges, jt, d->binning, d->smoothing);
+  std::memcpy(out, jt.data(), need * sizeof(double));
+  return MP3_OK;
 }
 
 }  // extern "C"

@@ -2,13 +2,18 @@
 //
 // * Gauss-Legendre nodes by Newton iteration on P_n (three-term recurrence).
 // * Spherical Bessel functions j_0..j_L: upward recurrence from j_0, j_1 when
-//   x > L (stable there), Miller's downward recurrence normalised to j_0 when
-//   x <= L, exact values at x = 0.
-// * Bin-averaged j_l (the radial binning window applied to the secondary
-//   vertices of the multipole window, Sec. 2.2 around Eq. 3PCF-multipole-window):
-//     jbar_{l,b}(k) = 3 / (r_{b+1}^3 - r_b^3) int_{r_b}^{r_{b+1}} r^2 j_l(k r) dr,
-//   64-point Gauss-Legendre per bin, tabulated for every integer |q|^2 of the
-//   grid, k = (2 pi / box) sqrt(|q|^2).
+//   x > L (stable there), Miller's downward recurrence normalised to the larger
+//   of the closed forms j_0, j_1 when x <= L, exact values at x = 0.
+// * Radial window of the secondary vertices (Sec. 2.2 around Eq.
+//   3PCF-multipole-window, times the binning window of each vertex), tabulated
+//   for every integer |q|^2 of the grid, k = (2 pi / box) sqrt(|q|^2):
+//   the bin average
+//     jbar_{l,b}(k) = 3 / (r_{b+1}^3 - r_b^3) int_{r_b}^{r_{b+1}} r^2 j_l(k r) dr
+//   (64-point Gauss-Legendre per bin) or the thin shell j_l(k r_b) at the
+//   bin's mid radius, optionally times the spherical top-hat window
+//   3 j_1(kR) / (kR) of the triple-sphere binning (Sec. 3).
+// * Phi-hat per axis: the power spectrum of the cubic B-spline scaling
+//   function, sinc^8(pi q / N) (Eq. SFC-3PCF-vertex).
 // * FFT twiddles exp(-2 pi i t / N).
 // * Normalisation of Y_lm: sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!).
 #include "tables.hpp"
@@ -87,11 +92,26 @@ void sph_bessel_all(int L, double x, double* out) {
     }
   }
   (void)scale_acc;
-  const double norm = j0 / tmp[0];
+  // normalise by whichever of the closed forms j_0, j_1 is larger in
+  // magnitude: they never vanish together, so the ratio stays accurate near
+  // the zeros of j_0 (x close to n pi)
+  const double j1 = s / (x * x) - c / x;
+  const double norm = std::fabs(j0) >= std::fabs(j1) ? j0 / tmp[0] : j1 / tmp[1];
   for (int l = 0; l <= L; ++l) out[l] = tmp[l] * norm;
 }
 
-void jbar_table(int n, double box, int lmax, const std::vector<double>& edges, std::vector<double>& out) {
+double tophat_window(double x) {
+  // 3 j_1(x) / x = 3 (sin x - x cos x) / x^3; its series below x = 1e-2
+  // (the closed form cancels there)
+  if (x < 1e-2) {
+    const double x2 = x * x;
+    return 1.0 - x2 / 10.0 + x2 * x2 / 280.0 - x2 * x2 * x2 / 15120.0;
+  }
+  return 3.0 * (std::sin(x) - x * std::cos(x)) / (x * x * x);
+}
+
+void jbar_table(int n, double box, int lmax, const std::vector<double>& edges, std::vector<double>& out,
+                int binning, double smoothing) {
   const int nbins = (int)edges.size() - 1;
   const int nq2 = nq2_count(n);
   out.assign((size_t)(lmax + 1) * nq2 * nbins, 0.0);
@@ -104,9 +124,16 @@ void jbar_table(int n, double box, int lmax, const std::vector<double>& edges, s
     std::vector<double> acc((size_t)(lmax + 1));
     for (int s = tid; s < nq2; s += (int)nthreads) {
       const double k = kf * std::sqrt((double)s);
+      const double wth = smoothing > 0.0 ? tophat_window(k * smoothing) : 1.0;
       for (int b = 0; b < nbins; ++b) {
         const double r1 = edges[b], r2 = edges[b + 1];
         const double half = 0.5 * (r2 - r1), mid = 0.5 * (r2 + r1);
+        if (binning == 1) {
+          // thin shell at the mid radius
+          sph_bessel_all(lmax, k * mid, jl.data());
+          for (int l = 0; l <= lmax; ++l) out[((size_t)l * nq2 + s) * nbins + b] = jl[l] * wth;
+          continue;
+        }
         std::fill(acc.begin(), acc.end(), 0.0);
         for (size_t g = 0; g < xg.size(); ++g) {
           const double r = mid + half * xg[g];
@@ -115,7 +142,7 @@ void jbar_table(int n, double box, int lmax, const std::vector<double>& edges, s
           for (int l = 0; l <= lmax; ++l) acc[l] += wr * jl[l];
         }
         const double vol = 3.0 / (r2 * r2 * r2 - r1 * r1 * r1);
-        for (int l = 0; l <= lmax; ++l) out[((size_t)l * nq2 + s) * nbins + b] = acc[l] * vol;
+        for (int l = 0; l <= lmax; ++l) out[((size_t)l * nq2 + s) * nbins + b] = acc[l] * vol * wth;
       }
     }
   };
@@ -135,6 +162,19 @@ void twiddles(int n, std::vector<double>& re, std::vector<double>& im) {
     if (4 * t == n) { re[t] = 0.0; im[t] = -1.0; }
     if (2 * t == n) { re[t] = -1.0; im[t] = 0.0; }
     if (4 * t == 3 * n) { re[t] = 0.0; im[t] = 1.0; }
+  }
+}
+
+void phi_hat_axis(int n, std::vector<double>& out) {
+  // |B3hat|^2 per axis: B3 is the fourfold self-convolution of the unit box,
+  // whose transform at theta = 2 pi q / n is sinc(theta / 2)
+  out.resize(n);
+  for (int i = 0; i < n; ++i) {
+    const int q = i < n / 2 ? i : i - n;
+    const double h = M_PI * (double)q / (double)n;
+    const double sc = q == 0 ? 1.0 : std::sin(h) / h;
+    const double s2 = sc * sc, s4 = s2 * s2;
+    out[i] = s4 * s4;
   }
 }
 

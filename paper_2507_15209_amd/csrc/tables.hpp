@@ -9,8 +9,14 @@ inline int nq2_count(int n) { return 3 * (n / 2) * (n / 2) + 1; }
 
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 void sph_bessel_all(int L, double x, double* out);
-// [lmax+1][nq2][nbins]
-void jbar_table(int n, double box, int lmax, const std::vector<double>& edges, std::vector<double>& out);
+// [lmax+1][nq2][nbins]; binning 0 = shell average, 1 = thin shell at the mid
+// radius; smoothing > 0 multiplies by the top-hat window 3 j_1(kR) / (kR)
+void jbar_table(int n, double box, int lmax, const std::vector<double>& edges, std::vector<double>& out,
+                int binning = 0, double smoothing = 0.0);
+// spherical top-hat window 3 j_1(x) / x
+double tophat_window(double x);
+// sinc^8(pi q / n) at every index of an axis (q = index mod n in [-n/2, n/2))
+void phi_hat_axis(int n, std::vector<double>& out);
 void twiddles(int n, std::vector<double>& re, std::vector<double>& im);
 double ylm_norm(int l, int m);
 // centred cubic B-spline

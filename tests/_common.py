@@ -37,3 +37,19 @@ def assert_zeta_close(got, ref, tol):
     e = per_l_errors(got, ref)
     assert np.all(e <= tol), f"per-l errors {e} exceed {tol}"
     return e
+
+
+def grad_errors(got, ref):
+    """(relative L2 error, max |got - ref| / max |ref|) of a gradient array."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    l2 = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    mx = np.abs(got - ref).max() / np.abs(ref).max()
+    return l2, mx
+
+
+def assert_grad_close(got, ref, tol, what="gradient"):
+    """Both the relative L2 error and the element-wise error (relative to max |ref|) within tol."""
+    l2, mx = grad_errors(got, ref)
+    assert l2 <= tol and mx <= tol, f"{what}: relative L2 {l2:.3e}, max element {mx:.3e} (tol {tol:g})"
+    return l2, mx

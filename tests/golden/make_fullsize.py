@@ -23,7 +23,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-from mockgen import WORKLOADS, workload_catalogue, batch_sizes  # noqa: E402
+from mockgen import WORKLOADS, workload_catalogue, batch_sizes, lognormal_catalogue  # noqa: E402
 from oracle import basis  # noqa: E402
 from oracle import estimator as E  # noqa: E402
 from oracle import adjoint as A  # noqa: E402
@@ -51,7 +51,7 @@ def nodal_lam(nl, nb, seed):
 
 def case_nodal_256():
     wl = WORKLOADS["box2000_n256_l10"]
-    ls, bins = [0, 3], [0, 9, 19]
+    ls, bins = [0, 3, 10], [0, 9, 19]
     pos, w = workload_catalogue(wl)
     say("nodal_256 deposit")
     delta = contrast(pos, w, wl.n, wl.box)
@@ -62,9 +62,13 @@ def case_nodal_256():
     say("nodal_256 gradient")
     lam = nodal_lam(len(ls), len(bins), 8101)
     g = A.zeta_nodal_grad(op, delta, lam, ls=ls, bins=bins)
+    say("nodal_256 weight gradient")
+    dw = A.deposit_weight_grad(pos, w, wl.n, wl.box, g)
+    pidx = np.random.default_rng(8109).integers(0, len(w), NODE_SAMPLES)
     return dict(workload=wl.name, ls=ls, bins=bins, zeta=z.tolist(), lam=lam.tolist(), nodes=idx.tolist(),
                 delta=delta.ravel()[idx].tolist(), delta_max=float(np.abs(delta).max()),
-                grad=g.ravel()[idx].tolist(), grad_max=float(np.abs(g).max()))
+                grad=g.ravel()[idx].tolist(), grad_max=float(np.abs(g).max()),
+                particles=pidx.tolist(), dw=dw[pidx].tolist(), dw_max=float(np.abs(dw).max()))
 
 
 def case_particle(name, ls, bins):
@@ -77,6 +81,45 @@ def case_particle(name, ls, bins):
     z = E.zeta_particle(E.Plan(wl.n, wl.box, wl.lmax, wl.edges), pos, w, ls=ls, bins=bins)
     return dict(workload=wl.name, ls=ls, bins=bins, zeta=z.tolist(), nodes=idx.tolist(),
                 delta=delta.ravel()[idx].tolist(), delta_max=float(np.abs(delta).max()))
+
+
+def case_particle_grad(name, ls, bins):
+    """Gradient samples of the particle form: dJ/ddelta at seeded nodes, dJ/dw at seeded particles."""
+    wl = WORKLOADS[name]
+    pos, w = workload_catalogue(wl)
+    idx = node_sample(wl.n, 8106)
+    pidx = np.random.default_rng(8107).integers(0, len(w), NODE_SAMPLES)
+    lam = nodal_lam(len(ls), len(bins), 8108)
+    say(name, "particle gradient")
+    g, dw = A.zeta_particle_grad(E.Plan(wl.n, wl.box, wl.lmax, wl.edges), pos, w, lam, ls=ls, bins=bins)
+    return dict(workload=wl.name, ls=ls, bins=bins, lam=lam.tolist(), nodes=idx.tolist(),
+                grad=g.ravel()[idx].tolist(), grad_max=float(np.abs(g).max()),
+                particles=pidx.tolist(), dw=dw[pidx].tolist(), dw_max=float(np.abs(dw).max()))
+
+
+def case_onesweep_128():
+    """128^3, L = 1, 20 bins, nodal form: every zeta entry, the gradient at seeded nodes and particles.
+
+    The one-sweep z pass contracts 64 z columns per wave, so 128 points per
+    pencil spread the contraction over several waves."""
+    n, box, lmax = 128, 1280.0, 1
+    edges = np.linspace(0.08 * box, 0.35 * box, 21)
+    pos, w = lognormal_catalogue(n, box, 60000, 0.05 * box, 901, 902, 903, (0.5, 1.5))
+    say("onesweep_128 deposit")
+    delta = contrast(pos, w, n, box)
+    op = E.Plan(n, box, lmax, edges)
+    say("onesweep_128 zeta")
+    z = E.zeta_nodal(op, delta)
+    lam = np.random.default_rng(904).standard_normal((lmax + 1, 20, 20))
+    say("onesweep_128 gradient")
+    g = A.zeta_nodal_grad(op, delta, lam)
+    dw = A.deposit_weight_grad(pos, w, n, box, g)
+    idx = np.random.default_rng(905).integers(0, n ** 3, 4096)
+    pidx = np.random.default_rng(906).integers(0, len(w), 4096)
+    return dict(n=n, box=box, lmax=lmax, edges=edges.tolist(), mock=[60000, 0.05 * box, 901, 902, 903],
+                zeta=z.tolist(), lam=lam.tolist(), nodes=idx.tolist(), grad=g.ravel()[idx].tolist(),
+                grad_max=float(np.abs(g).max()), particles=pidx.tolist(), dw=dw[pidx].tolist(),
+                dw_max=float(np.abs(dw).max()))
 
 
 def case_gamma_256():
@@ -128,6 +171,8 @@ CASES = {
     "nodal_256": case_nodal_256,
     "particle_512": lambda: case_particle("box3000_n512_l10", [0], [0, 19]),
     "particle_128": lambda: case_particle("box1000_n128_l10", [0, 2, 10], [0, 7, 14]),
+    "particle_128_grad": lambda: case_particle_grad("box1000_n128_l10", [0, 2, 10], [0, 7, 14]),
+    "onesweep_128": case_onesweep_128,
     "gamma_256": case_gamma_256,
     "gamma_256_grad": case_gamma_256_grad,
     "batch64": case_batch64,

@@ -11,7 +11,8 @@ from tests._common import ROOT, ensure_library
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "mp3.h")).read()
-    return sorted(set(re.findall(r"\b(mp3_[a-z_]+)\s*\(", src)))
+    # function declarations: a return type at the start of the line, then the name
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(mp3_\w+)\s*\(", src, re.M)))
 
 
 def test_header_declares_expected_entry_points():
@@ -32,19 +33,22 @@ def test_library_exports_every_declared_symbol():
 def _desc(**kw):
     from paper_2507_15209_amd import _lib
     edges = np.asarray(kw.pop("edges", np.linspace(10.0, 60.0, 7)), dtype=np.float64)
-    d = dict(n=32, box=250.0, lmax=4, nbins=edges.size - 1, precision=0, summation=0, batch=1)
+    d = dict(n=32, box=250.0, lmax=4, nbins=edges.size - 1, precision=0, summation=0, batch=1, basis=0, kflags=0,
+             binning=0, smoothing=0.0)
     d.update(kw)
     desc = _lib.PlanDesc(d["n"], d["box"], d["lmax"], d["nbins"],
                          edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), d["precision"], d["summation"],
-                         d["batch"])
+                         d["batch"], d["basis"], d["kflags"], d["binning"], d["smoothing"])
     return desc, edges
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(n=48), -4), (dict(n=1024), -4), (dict(box=0.0), -1), (dict(box=float("nan")), -1),
-    (dict(lmax=-1), -1), (dict(lmax=21), -1), (dict(nbins=0), -1), (dict(nbins=65), -1),
-    (dict(edges=[10.0, 5.0, 20.0]), -1), (dict(edges=[-1.0, 5.0]), -1), (dict(precision=3), -1),
-    (dict(summation=3), -4), (dict(batch=0), -1),
+    (dict(n=48), -4), (dict(n=1024), -4), (dict(box=0.0), -1), (dict(box=float("nan")), -6),
+    (dict(box=float("inf")), -6), (dict(lmax=-1), -1), (dict(lmax=21), -1), (dict(nbins=0), -1),
+    (dict(nbins=65), -1), (dict(edges=[10.0, 5.0, 20.0]), -1), (dict(edges=[-1.0, 5.0]), -1),
+    (dict(edges=[1.0, float("nan")]), -6), (dict(precision=3), -1), (dict(summation=3), -4), (dict(batch=0), -1),
+    (dict(basis=1), -4), (dict(kflags=4), -1), (dict(binning=2), -1), (dict(smoothing=-1.0), -1),
+    (dict(smoothing=float("nan")), -6),
 ])
 def test_plan_create_rejects_bad_descriptions(kw, code):
     ensure_library()

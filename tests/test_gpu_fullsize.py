@@ -71,33 +71,106 @@ def _embed_lam(g, wl, batch=1, per_mock=None):
 
 
 def test_nodal_256_forward_and_gradient(mp3):
-    """box 2000, 256^3, L = 10, 20 bins, 8e6 particles: the bench's workload and launch shapes."""
+    """box 2000, 256^3, L = 10, 20 bins, 8e6 particles: the bench's workload and launch shapes.
+
+    Per precision: the separate calls (zeta, then zeta_backward) and the
+    one-sweep value and gradient with dJ/dw (the bench's timed step, whose z
+    pass contracts 64 z columns per wave) against the oracle's sample, and the
+    one sweep against the two calls on every entry and every node."""
     g = _golden("nodal_256")
     wl = WORKLOADS[g["workload"]]
     ls, bins, nodes = g["ls"], g["bins"], np.asarray(g["nodes"])
+    parts = np.asarray(g["particles"]) if "particles" in g else None
     _say("nodal 256: mock")
     pos, w = workload_catalogue(wl)
     pt, wt = _dev(pos, torch.float32), _dev(w, torch.float32)
     lam = _dev(_embed_lam(g, wl), torch.float64)
     res = {}
     for prec in ("f32", "f64"):
-        _say("nodal 256: GPU", prec)
+        _say("nodal 256: GPU two calls", prec)
         plan = mp3.Plan(wl.n, wl.box, wl.lmax, wl.edges, precision=prec)
         d = plan.deposit(pt, wt)
         z = plan.zeta(d).cpu().numpy()[0]
         gr, _ = plan.zeta_backward(d, lam)
-        res[prec] = (d.cpu().numpy()[0].ravel()[nodes], z, gr.cpu().numpy()[0].ravel()[nodes])
-        del plan, d, gr
+        gr = gr.cpu().numpy()[0].ravel()
+        _say("nodal 256: GPU one sweep", prec)
+        z1, g1, dw1 = plan.zeta_value_and_grad(d, lam, pt, wt)
+        z1, g1, dw1 = z1.cpu().numpy()[0], g1.cpu().numpy()[0].ravel(), dw1.cpu().numpy()
+        agree = 1e-12 if prec == "f64" else 2e-5
+        e = assert_zeta_close(z1, z, agree)
+        _say("one sweep vs two calls, zeta per l", np.array2string(e, precision=2))
+        eg = np.abs(g1 - gr).max() / np.abs(gr).max()
+        _say("one sweep vs two calls, max |d grad| / max |grad|", eg)
+        assert eg <= agree, eg
+        res[prec] = dict(delta=d.cpu().numpy()[0].ravel()[nodes], z=z, g=gr[nodes], z1=z1, g1=g1[nodes],
+                         dw1=dw1[parts] if parts is not None else None)
+        del plan, d
         torch.cuda.empty_cache()
-    e = assert_zeta_close(res["f32"][1], res["f64"][1], 1e-4)
-    _say("f32 vs f64 per l", np.array2string(e, precision=2))
-    z64 = res["f64"][1]
+    for key in ("z", "z1"):
+        e = assert_zeta_close(res["f32"][key], res["f64"][key], 1e-4)
+        _say("f32 vs f64 per l", key, np.array2string(e, precision=2))
+    z64 = res["f64"]["z1"]
     assert np.abs(z64 - z64.transpose(0, 2, 1)).max() <= 1e-12 * np.abs(z64).max()
     for prec, tol in (("f64", 1e-10), ("f32", 1e-4)):
-        dsm, z, gsm = res[prec]
-        _samples_close(dsm, g["delta"], g["delta_max"], 1e-12 if prec == "f64" else 1e-6)
-        assert_zeta_close(_sub(z, ls, bins), g["zeta"], tol)
-        _samples_close(gsm, g["grad"], g["grad_max"], tol)
+        r = res[prec]
+        _samples_close(r["delta"], g["delta"], g["delta_max"], 1e-12 if prec == "f64" else 1e-6)
+        for zk, gk in (("z", "g"), ("z1", "g1")):
+            e = assert_zeta_close(_sub(r[zk], ls, bins), g["zeta"], tol)
+            eg = _samples_close(r[gk], g["grad"], g["grad_max"], tol)
+            _say(prec, zk, "vs oracle sample: zeta per l", np.array2string(e, precision=2), "grad", eg)
+        if parts is not None:
+            ew = _samples_close(r["dw1"], g["dw"], g["dw_max"], tol)
+            _say(prec, "one sweep dJ/dw vs oracle sample", ew)
+
+
+def test_nodal_onesweep_128(mp3):
+    """128^3, L = 1, 20 bins: the one-sweep z pass with its contraction spread over two waves per
+    pencil, float32 and float64, against every oracle zeta entry and the gradients at 4096 nodes
+    and particles."""
+    g = _golden("onesweep_128")
+    n, box, lmax, edges = g["n"], g["box"], g["lmax"], np.asarray(g["edges"])
+    npart, smooth, s1, s2, s3 = g["mock"]
+    from mockgen import lognormal_catalogue
+    pos, w = lognormal_catalogue(n, box, int(npart), smooth, int(s1), int(s2), int(s3), (0.5, 1.5))
+    pt, wt = _dev(pos, torch.float32), _dev(w, torch.float32)
+    lam = _dev(np.asarray(g["lam"])[None], torch.float64)
+    nodes, parts = np.asarray(g["nodes"]), np.asarray(g["particles"])
+    for prec, tol in (("f64", 1e-10), ("f32", 1e-4)):
+        _say("one sweep 128: GPU", prec)
+        plan = mp3.Plan(n, box, lmax, edges, precision=prec)
+        d = plan.deposit(pt, wt)
+        z, gr, dw = plan.zeta_value_and_grad(d, lam, pt, wt)
+        e = assert_zeta_close(z.cpu().numpy()[0], g["zeta"], tol)
+        eg = _samples_close(gr.cpu().numpy()[0].ravel()[nodes], g["grad"], g["grad_max"], tol)
+        ew = _samples_close(dw.cpu().numpy()[parts], g["dw"], g["dw_max"], tol)
+        _say(prec, "zeta per l", np.array2string(e, precision=2), "grad", eg, "dw", ew)
+
+
+def test_particle_128_gradient(mp3):
+    """box 1000, 128^3, L = 10, 15 bins, 1e6 particles, particle form: dJ/ddelta at the oracle's
+    sampled nodes and dJ/dw at its sampled particles, for the backward and the one sweep
+    (float32: two-chunk scatter at 15 bins; float64: one gather for both)."""
+    g = _golden("particle_128_grad")
+    wl = WORKLOADS[g["workload"]]
+    nodes, parts = np.asarray(g["nodes"]), np.asarray(g["particles"])
+    _say("particle 128 gradient: mock")
+    pos, w = workload_catalogue(wl)
+    pt, wt = _dev(pos, torch.float32), _dev(w, torch.float32)
+    lam = _dev(_embed_lam(g, wl), torch.float64)
+    for prec, tol in (("f64", 1e-10), ("f32", 1e-4)):
+        plan = mp3.Plan(wl.n, wl.box, wl.lmax, wl.edges, precision=prec, summation="particle")
+        d = plan.deposit(pt, wt)
+        calls = [("value_and_grad", lambda: plan.zeta_value_and_grad(d, lam, pt, wt)[1:])]
+        if prec == "f32":
+            calls.append(("backward", lambda: plan.zeta_backward(d, lam, pt, wt)))
+        for call, fn in calls:
+            _say("particle 128 gradient: GPU", prec, call)
+            gr, dw = fn()
+            eg = _samples_close(gr.cpu().numpy()[0].ravel()[nodes], g["grad"], g["grad_max"], tol)
+            ew = _samples_close(dw.cpu().numpy()[parts], g["dw"], g["dw_max"], tol)
+            _say(prec, call, "grad", eg, "dw", ew)
+        del plan, d
+        torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("name", ["particle_512", "particle_128"])

@@ -11,7 +11,7 @@ from mockgen import random_field, lognormal_catalogue, WORKLOADS, workload_catal
 from oracle import basis
 from oracle import estimator as E
 from oracle import adjoint as A
-from tests._common import assert_zeta_close, per_l_errors
+from tests._common import assert_zeta_close, per_l_errors, assert_grad_close
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -144,10 +144,9 @@ def test_backward_delta_and_weights(mp3, prec, n, lmax, nb):
     gref = A.zeta_nodal_grad(op, dref, lam)
     wref = A.deposit_weight_grad(pos, w, n, box, gref)
     tol = 1e-10 if prec == "f64" else 1e-4
-    eg = np.linalg.norm(dd.cpu().numpy()[0] - gref) / np.linalg.norm(gref)
-    ew = np.linalg.norm(dw.cpu().numpy() - wref) / np.linalg.norm(wref)
-    print("grad errors", eg, ew)
-    assert eg < tol and ew < tol
+    eg = assert_grad_close(dd.cpu().numpy()[0], gref, tol, "dJ/ddelta")
+    ew = assert_grad_close(dw.cpu().numpy(), wref, tol, "dJ/dw")
+    print("grad errors (L2, max)", eg, ew)
 
 
 def test_backward_batch_autograd(mp3):
@@ -164,7 +163,7 @@ def test_backward_batch_autograd(mp3):
     op = E.Plan(n, box, lmax, edges)
     for j in range(2):
         ref = A.zeta_nodal_grad(op, d[j], lam[j])
-        assert np.linalg.norm(x.grad[j].cpu().numpy() - ref) < 1e-10 * np.linalg.norm(ref)
+        assert_grad_close(x.grad[j].cpu().numpy(), ref, 1e-10, f"dJ/ddelta mock {j}")
 
 
 def test_weight_gradient_finite_difference_f64(mp3):
@@ -323,11 +322,9 @@ def test_backward_particle(mp3, prec, n, lmax, nb, npart):
     g, dw = plan.zeta_backward(delta, _dev(lam, torch.float64), pt, wt)
     g, dw = g.cpu().numpy()[0], dw.cpu().numpy()
     gref, dwref = A.zeta_particle_grad(E.Plan(n, box, lmax, edges), pos, w, lam[0])
-    eg = np.linalg.norm(g - gref) / np.linalg.norm(gref)
-    ew = np.linalg.norm(dw - dwref) / np.linalg.norm(dwref)
-    print("grad errors", eg, ew)
-    tol = TOL[prec]
-    assert eg <= tol and ew <= tol, (eg, ew)
+    eg = assert_grad_close(g, gref, TOL[prec], "dJ/ddelta")
+    ew = assert_grad_close(dw, dwref, TOL[prec], "dJ/dw")
+    print("grad errors (L2, max)", eg, ew)
 
 
 def test_backward_particle_batch_autograd(mp3):
@@ -350,8 +347,7 @@ def test_backward_particle_batch_autograd(mp3):
     op = E.Plan(n, box, lmax, edges)
     for j, (p_, w_) in enumerate(cats):
         _, dwref = A.zeta_particle_grad(op, p_, w_, lam[j])
-        got = dw[off[j]:off[j + 1]]
-        assert np.linalg.norm(got - dwref) <= 1e-4 * np.linalg.norm(dwref), j
+        assert_grad_close(dw[off[j]:off[j + 1]], dwref, 1e-4, f"dJ/dw mock {j}")
 
 
 # BF16-split contraction inputs: each product carries a relative error of about
@@ -430,10 +426,9 @@ def test_backward_gamma(mp3, prec, n, lmax, nb):
     dref = basis.density_contrast(basis.deposit(pos, w, n, box), float(np.sum(w.astype(np.float64))))
     gref = A.zeta_gamma_grad(E.Plan(n, box, lmax, edges), dref, lam[0])
     dwref = A.deposit_weight_grad(pos, w, n, box, gref)
-    eg = np.linalg.norm(g - gref) / np.linalg.norm(gref)
-    ew = np.linalg.norm(dw - dwref) / np.linalg.norm(dwref)
-    print("grad errors", eg, ew)
-    assert eg <= TOL[prec] and ew <= TOL[prec], (eg, ew)
+    eg = assert_grad_close(g, gref, TOL[prec], "dJ/ddelta")
+    ew = assert_grad_close(dw, dwref, TOL[prec], "dJ/dw")
+    print("grad errors (L2, max)", eg, ew)
 
 
 def test_backward_gamma_20_bins_autograd(mp3):
@@ -451,8 +446,7 @@ def test_backward_gamma_20_bins_autograd(mp3):
     dref = basis.density_contrast(basis.deposit(pos, w, n, box), float(np.sum(w.astype(np.float64))))
     gref = A.zeta_gamma_grad(E.Plan(n, box, lmax, edges), dref, lam[0])
     dwref = A.deposit_weight_grad(pos, w, n, box, gref)
-    got = wt.grad.cpu().numpy()
-    assert np.linalg.norm(got - dwref) <= 1e-4 * np.linalg.norm(dwref)
+    assert_grad_close(wt.grad.cpu().numpy(), dwref, 1e-4, "dJ/dw")
 
 
 def test_extreme_orders_and_bins(mp3):
@@ -475,7 +469,7 @@ def test_extreme_orders_and_bins(mp3):
     lam = np.random.default_rng(801).standard_normal((1, 2, 64, 64))
     g, _ = plan.zeta_backward(d, _dev(lam, torch.float64))
     gref = A.zeta_nodal_grad(op, delta, lam[0])
-    assert np.linalg.norm(g.cpu().numpy()[0] - gref) <= 1e-4 * np.linalg.norm(gref)
+    assert_grad_close(g.cpu().numpy()[0], gref, 1e-4, "dJ/ddelta, 64 bins")
 
 
 @pytest.mark.parametrize("summation", ["nodal", "gamma", "particle"])
@@ -528,10 +522,9 @@ def test_value_and_grad_nodal(mp3, prec, n, lmax, nb):
     wref = A.deposit_weight_grad(pos, w, n, box, gref)
     tol = TOL[prec]
     assert_zeta_close(z.cpu().numpy()[0], zref, tol)
-    eg = np.linalg.norm(dd.cpu().numpy()[0] - gref) / np.linalg.norm(gref)
-    ew = np.linalg.norm(dw.cpu().numpy() - wref) / np.linalg.norm(wref)
-    print("grad errors", eg, ew)
-    assert eg < tol and ew < tol
+    eg = assert_grad_close(dd.cpu().numpy()[0], gref, tol, "dJ/ddelta")
+    ew = assert_grad_close(dw.cpu().numpy(), wref, tol, "dJ/dw")
+    print("grad errors (L2, max)", eg, ew)
     # against the separate calls: rounding-order differences only
     agree = 1e-12 if prec == "f64" else 2e-5
     assert_zeta_close(z.cpu().numpy()[0], z2.cpu().numpy()[0], agree)
@@ -562,9 +555,8 @@ def test_value_and_grad_batch_and_other_forms(mp3):
         assert_zeta_close(z.cpu().numpy()[j], E.zeta_nodal(op, dref), 1e-4)
         gref = A.zeta_nodal_grad(op, dref, lam[j])
         wref = A.deposit_weight_grad(p, ww, n, box, gref)
-        assert np.linalg.norm(dd.cpu().numpy()[j] - gref) < 1e-4 * np.linalg.norm(gref)
-        got = dw.cpu().numpy()[off[j]:off[j + 1]]
-        assert np.linalg.norm(got - wref) < 1e-4 * np.linalg.norm(wref)
+        assert_grad_close(dd.cpu().numpy()[j], gref, 1e-4, f"dJ/ddelta mock {j}")
+        assert_grad_close(dw.cpu().numpy()[off[j]:off[j + 1]], wref, 1e-4, f"dJ/dw mock {j}")
     for summation, prec in (("particle", "f64"), ("gamma", "f64"), ("nodal", "bf16x3")):
         _say("value and grad, two calls:", summation, prec)
         n2, box2, lmax2 = 16, 160.0, 2
@@ -602,10 +594,9 @@ def test_value_and_grad_particle(mp3, prec):
     op = E.Plan(n, box, lmax, edges)
     assert_zeta_close(z.cpu().numpy()[0], E.zeta_particle(op, pos, w), TOL[prec])
     gref, dwref = A.zeta_particle_grad(op, pos, w, lam[0])
-    eg = np.linalg.norm(g.cpu().numpy()[0] - gref) / np.linalg.norm(gref)
-    ew = np.linalg.norm(dw.cpu().numpy() - dwref) / np.linalg.norm(dwref)
-    print("grad errors", eg, ew)
-    assert eg <= TOL[prec] and ew <= TOL[prec], (eg, ew)
+    eg = assert_grad_close(g.cpu().numpy()[0], gref, TOL[prec], "dJ/ddelta")
+    ew = assert_grad_close(dw.cpu().numpy(), dwref, TOL[prec], "dJ/dw")
+    print("grad errors (L2, max)", eg, ew)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -625,8 +616,39 @@ def test_value_and_grad_gamma(mp3, prec, nb):
     op = E.Plan(n, box, lmax, edges)
     assert_zeta_close(z.cpu().numpy()[0], E.zeta_gamma(op, delta), TOL[prec])
     gref = A.zeta_gamma_grad(op, delta, lam)
-    eg = np.linalg.norm(g.cpu().numpy()[0] - gref) / np.linalg.norm(gref)
-    print("grad error", eg)
-    assert eg <= TOL[prec], eg
+    eg = assert_grad_close(g.cpu().numpy()[0], gref, TOL[prec], "dJ/ddelta")
+    print("grad error (L2, max)", eg)
     zz = z.cpu().numpy()[0]
     assert np.abs(zz - zz.transpose(0, 2, 1)).max() <= 1e-12 * np.abs(zz).max()
+
+
+@pytest.mark.parametrize("nb", [10, 15, 20])
+def test_particle_gradient_bin_chunks(mp3, nb):
+    """Particle-form gradients where the adjoint scatter takes its bins in chunks.
+
+    float32: 10 bins in one 10-bin workgroup chunk, 15 bins in two 8-bin
+    chunks, 20 bins in two 10-bin chunks; float64: 4-bin chunks (3, 4, 5 of
+    them).  Both the separate backward and the one-sweep value and gradient,
+    for dJ/ddelta and dJ/dw, against the oracle (L2 and element-wise)."""
+    n, lmax, npart = 32, 1, 20000
+    box = 8.0 * n
+    edges = np.linspace(0.06 * box, 0.35 * box, nb + 1)
+    pos, w = lognormal_catalogue(n, box, npart, 0.04 * box, 1300 + nb, 1301 + nb, 1302 + nb, (0.5, 1.5))
+    lam = np.random.default_rng(1303 + nb).standard_normal((1, lmax + 1, nb, nb))
+    op = E.Plan(n, box, lmax, edges)
+    _say("particle gradient chunks: oracle", nb)
+    zref = E.zeta_particle(op, pos, w)
+    gref, dwref = A.zeta_particle_grad(op, pos, w, lam[0])
+    pt, wt = _dev(pos, torch.float32), _dev(w, torch.float32)
+    for prec in ("f32", "f64"):
+        _say("particle gradient chunks: GPU", prec, nb)
+        plan = mp3.Plan(n, box, lmax, edges, precision=prec, summation="particle")
+        delta = plan.deposit(pt, wt)
+        lt = _dev(lam, torch.float64)
+        g0, dw0 = plan.zeta_backward(delta, lt, pt, wt)
+        z1, g1, dw1 = plan.zeta_value_and_grad(delta, lt, pt, wt)
+        assert_zeta_close(z1.cpu().numpy()[0], zref, TOL[prec])
+        for call, g, dw in (("backward", g0, dw0), ("value_and_grad", g1, dw1)):
+            eg = assert_grad_close(g.cpu().numpy()[0], gref, TOL[prec], f"{prec} {call} dJ/ddelta")
+            ew = assert_grad_close(dw.cpu().numpy(), dwref, TOL[prec], f"{prec} {call} dJ/dw")
+            print(prec, call, "grad errors (L2, max)", eg, ew)

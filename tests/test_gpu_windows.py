@@ -1,0 +1,179 @@
+"""GPU parity of the vertex-window options and the statistics built on the multipoles.
+
+Thin-shell binning, the spherical top-hat on every vertex (triple-sphere
+binning), the scaling function's power spectrum, the two-point function and
+the reconstructed 3PCF / reduced 3PCF, each through the C ABI against the
+float64 oracle: float64 within 1e-10, float32 within 1e-4 (per multipole for
+zeta; relative L2 and element-wise for gradients and xi).
+"""
+import numpy as np
+import pytest
+
+from mockgen import random_field, lognormal_catalogue
+from oracle import basis
+from oracle import estimator as E
+from oracle import adjoint as A
+from tests._common import assert_zeta_close, assert_grad_close
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-10, "f32": 1e-4}
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def mp3():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_15209_amd as m
+    return m
+
+
+def _dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+OPTS = [dict(binning="thin"), dict(binning="thin", smoothing=9.0), dict(binning="shell", smoothing=6.0),
+        dict(phi_hat=True), dict(binning="thin", smoothing=5.0, phi_hat=True)]
+
+
+def _ids(o):
+    return "-".join(f"{k}={v}" for k, v in o.items())
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("opts", OPTS, ids=_ids)
+def test_nodal_windows_value_and_gradient(mp3, prec, opts):
+    """Nodal form with each window option: zeta, dJ/ddelta (through the filtered primary) and dJ/dw,
+    the separate calls and the one sweep."""
+    _say("nodal windows", prec, opts)
+    n, box, lmax, nb = 32, 320.0, 3, 5
+    edges = np.linspace(20.0, 110.0, nb + 1)
+    pos, w = lognormal_catalogue(n, box, 8000, 12.0, 1401, 1402, 1403, (0.5, 1.5))
+    lam = np.random.default_rng(1404).standard_normal((lmax + 1, nb, nb))
+    plan = mp3.Plan(n, box, lmax, edges, precision=prec, **opts)
+    pt, wt = _dev(pos, torch.float32), _dev(w, torch.float32)
+    delta = plan.deposit(pt, wt)
+    lt = _dev(lam[None], torch.float64)
+    z0 = plan.zeta(delta).cpu().numpy()[0]
+    g0, dw0 = plan.zeta_backward(delta, lt, pt, wt)
+    z1, g1, dw1 = plan.zeta_value_and_grad(delta, lt, pt, wt)
+    dref = basis.density_contrast(basis.deposit(pos, w, n, box), float(np.sum(w.astype(np.float64))))
+    op = E.Plan(n, box, lmax, edges, **opts)
+    zref = E.zeta_nodal(op, dref)
+    gref = A.zeta_nodal_grad(op, dref, lam)
+    wref = A.deposit_weight_grad(pos, w, n, box, gref)
+    for z, g, dw in ((z0, g0, dw0), (z1.cpu().numpy()[0], g1, dw1)):
+        e = assert_zeta_close(z, zref, TOL[prec])
+        eg = assert_grad_close(g.cpu().numpy()[0], gref, TOL[prec], "dJ/ddelta")
+        ew = assert_grad_close(dw.cpu().numpy(), wref, TOL[prec], "dJ/dw")
+        print("per-l", e, "grad", eg, ew)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("opts", [dict(binning="thin", smoothing=7.0), dict(phi_hat=True)], ids=_ids)
+def test_gamma_windows(mp3, prec, opts):
+    """Grid summation with connection coefficients under the window options (forward and gradient)."""
+    _say("gamma windows", prec, opts)
+    n, box, lmax, nb = 16, 160.0, 2, 3
+    edges = np.linspace(15.0, 55.0, nb + 1)
+    delta = random_field(n, 1411)
+    lam = np.random.default_rng(1412).standard_normal((lmax + 1, nb, nb))
+    plan = mp3.Plan(n, box, lmax, edges, precision=prec, summation="gamma", **opts)
+    dd = _dev(delta[None], torch.float64 if prec == "f64" else torch.float32)
+    z, g, _ = plan.zeta_value_and_grad(dd, _dev(lam[None], torch.float64))
+    op = E.Plan(n, box, lmax, edges, **opts)
+    assert_zeta_close(z.cpu().numpy()[0], E.zeta_gamma(op, delta), TOL[prec])
+    assert_grad_close(g.cpu().numpy()[0], A.zeta_gamma_grad(op, delta, lam), TOL[prec], "dJ/ddelta")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("opts", [dict(binning="thin", smoothing=8.0), dict(phi_hat=True)], ids=_ids)
+def test_particle_windows(mp3, prec, opts):
+    """Particle form: the secondaries carry the windows (and the volume mean phi-hat^2), the primary is
+    the catalogue; zeta, dJ/ddelta and dJ/dw in one sweep against the oracle."""
+    _say("particle windows", prec, opts)
+    n, lmax, nb = 32, 2, 4
+    box = 8.0 * n
+    edges = np.linspace(0.06 * box, 0.35 * box, nb + 1)
+    pos, w = lognormal_catalogue(n, box, 15000, 0.04 * box, 1421, 1422, 1423, (0.5, 1.5))
+    lam = np.random.default_rng(1424).standard_normal((1, lmax + 1, nb, nb))
+    plan = mp3.Plan(n, box, lmax, edges, precision=prec, summation="particle", **opts)
+    pt, wt = _dev(pos, torch.float32), _dev(w, torch.float32)
+    delta = plan.deposit(pt, wt)
+    z, g, dw = plan.zeta_value_and_grad(delta, _dev(lam, torch.float64), pt, wt)
+    op = E.Plan(n, box, lmax, edges, **opts)
+    assert_zeta_close(z.cpu().numpy()[0], E.zeta_particle(op, pos, w), TOL[prec])
+    gref, dwref = A.zeta_particle_grad(op, pos, w, lam[0])
+    assert_grad_close(g.cpu().numpy()[0], gref, TOL[prec], "dJ/ddelta")
+    assert_grad_close(dw.cpu().numpy(), dwref, TOL[prec], "dJ/dw")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("opts", [dict(), dict(smoothing=6.0), dict(smoothing=4.0, phi_hat=True)], ids=_ids)
+def test_xi(mp3, prec, opts):
+    """Two-point function at bin radii and at arbitrary radii (0 included) against the oracle."""
+    _say("xi", prec, opts)
+    n, box = 32, 320.0
+    delta = random_field(n, 1431)
+    radii = np.array([0.0, 4.0, 17.3, 30.0, 55.5, 90.0])
+    plan = mp3.Plan(n, box, 1, [10.0, 20.0], precision=prec, **opts)
+    rd = torch.float64 if prec == "f64" else torch.float32
+    x = plan.xi(_dev(delta[None], rd), radii).cpu().numpy()[0]
+    ref = E.xi(E.Plan(n, box, 1, [10.0, 20.0], **opts), delta, radii)
+    err = np.abs(x - ref).max() / np.abs(ref).max()
+    print("xi error", err)
+    assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_reduced_3pcf(mp3, prec):
+    """zeta(r1, r2, theta) truncated at lt and Q = zeta / zeta_H with thin shells and top-hat windows,
+    from the GPU's multipoles, against the oracle's reconstruction from its own multipoles."""
+    _say("reduced 3pcf", prec)
+    n, box, lmax, nb = 32, 320.0, 6, 4
+    edges = np.array([25.0, 35.0, 45.0, 55.0, 65.0])
+    pos, w = lognormal_catalogue(n, box, 20000, 12.0, 1441, 1442)
+    plan = mp3.Plan(n, box, lmax, edges, precision=prec, binning="thin", smoothing=6.0)
+    delta = plan.deposit(_dev(pos, torch.float32), _dev(w, torch.float32))
+    z = plan.zeta(delta)
+    mu = np.linspace(-1.0, 1.0, 9)
+    lt = 4
+    zt, q = plan.reduced_3pcf(z, mu, lt, delta)
+    dref = basis.density_contrast(basis.deposit(pos, w, n, box), float(np.sum(w.astype(np.float64))))
+    op = E.Plan(n, box, lmax, edges, binning="thin", smoothing=6.0)
+    zref = E.zeta_nodal(op, dref)
+    ztr = E.zeta_theta(zref, mu, lt)
+    qr = E.reduced_3pcf(op, dref, zref, mu, lt)
+    ez = np.abs(zt.cpu().numpy()[0] - ztr).max() / np.abs(ztr).max()
+    eq = np.abs(q.cpu().numpy()[0] - qr).max() / np.abs(qr).max()
+    print("zeta(theta) error", ez, "Q error", eq)
+    assert ez <= TOL[prec] and eq <= TOL[prec]
+    # without delta only zeta(theta) is formed
+    zt2, q2 = plan.reduced_3pcf(z, mu, lt)
+    assert q2 is None and torch.equal(zt2, zt)
+
+
+def test_check_finite_rejects_nan(mp3):
+    """MP3_KF_CHECK_FINITE: a NaN position or delta value returns MP3_ENONFINITE before any work."""
+    _say("check finite")
+    from paper_2507_15209_amd import _lib
+    n, box = 16, 160.0
+    plan = mp3.Plan(n, box, 1, [10.0, 20.0], check_finite=True)
+    pos = np.random.default_rng(1).uniform(0, box, (100, 3)).astype(np.float32)
+    pos[7, 1] = np.nan
+    with pytest.raises(mp3.Mp3Error) as ei:
+        plan.deposit(_dev(pos, torch.float32))
+    assert ei.value.status == _lib.MP3_ENONFINITE
+    d = torch.zeros((1, n, n, n), dtype=torch.float32, device="cuda")
+    d[0, 3, 4, 5] = float("inf")
+    with pytest.raises(mp3.Mp3Error) as ei:
+        plan.zeta(d)
+    assert ei.value.status == _lib.MP3_ENONFINITE
+    pos[7, 1] = 1.0
+    good = plan.deposit(_dev(pos, torch.float32))
+    assert torch.isfinite(plan.zeta(good)).all()
