@@ -35,10 +35,19 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def pass_bytes(name, n, nb, batch, real_bytes):
+def pass_bytes(name, n, nb, batch, real_bytes, summation="nodal", np_total=0):
     """Algorithmic HBM bytes of one launch of a pass (each element read or written once)."""
     n3 = float(n) ** 3 * batch
     c = 2 * real_bytes
+    rec = 4 + 12 * real_bytes + 8           # per particle: packed cell, 12 tap weights, order index, weight
+    if name == "gather" and np_total:
+        return nb * n3 * c + np_total * rec                                # fields once, particle records
+    if name == "scatter" and np_total:
+        return np_total * (nb * c + rec) + nb * n3 * c                     # sources + records in, fields out
+    if name == "z_store":
+        return 2.0 * nb * n3 * c                                           # nb fields in, bin-interleaved out
+    if name == "z_adjoint" and summation != "nodal":
+        return 2.0 * nb * n3 * c                                           # plain adjoint z transform in place
     return {
         "filter": n3 * c + nb * n3 * c,                                    # dhat in, nb fields out
         "x": 2.0 * nb * n3 * c,                                            # nb fields in and out
@@ -195,29 +204,38 @@ def stats_summarize(root, top=20):
               f"| {float(r['MinNs']) / 1e6:.4f} | {float(r['MaxNs']) / 1e6:.4f} | {float(r['Percentage']):.2f} |")
 
 
-# secondary measurements: (workload, summation, precision, with adjoint)
+# secondary measurements: (workload, summation, precision, with adjoint, plan options)
+TRIPLE_SPHERE = {"binning": "thin", "smoothing": 8.0}
 FORMS = {
-    "gamma_256_f32": ("box2000_n256_l10", "gamma", "f32", False),
-    "gamma_256_bf16x3": ("box2000_n256_l10", "gamma", "bf16x3", False),
-    "particle_512_f32": ("box3000_n512_l10", "particle", "f32", True),
+    "gamma_256_f32": ("box2000_n256_l10", "gamma", "f32", False, {}),
+    "gamma_256_bf16x3": ("box2000_n256_l10", "gamma", "bf16x3", False, {}),
+    "gamma_256_f32_adj": ("box2000_n256_l10", "gamma", "f32", True, {}),
+    "particle_512_f32": ("box3000_n512_l10", "particle", "f32", True, {}),
+    "particle_512_f64": ("box3000_n512_l10", "particle", "f64", True, {}),
+    "batch64_f32": ("batch64_n128_l8", "nodal", "f32", True, {}),
+    # the paper's triple-sphere binning: thin shells, top-hat R = 8 on every vertex
+    "nodal_256_thin_tophat_f32": ("box2000_n256_l10", "nodal", "f32", True, TRIPLE_SPHERE),
     # the remaining configurations (not run by default)
-    "gamma_256_f32_adj": ("box2000_n256_l10", "gamma", "f32", True),
-    "gamma_32_f64": ("box250_n32_l4", "gamma", "f64", True),
-    "nodal_32_f64": ("box250_n32_l4", "nodal", "f64", True),
-    "particle_128_f32": ("box1000_n128_l10", "particle", "f32", True),
-    "particle_128_f64": ("box1000_n128_l10", "particle", "f64", True),
-    "batch64_f32": ("batch64_n128_l8", "nodal", "f32", True),
+    "gamma_32_f64": ("box250_n32_l4", "gamma", "f64", True, {}),
+    "nodal_32_f64": ("box250_n32_l4", "nodal", "f64", True, {}),
+    "particle_128_f32": ("box1000_n128_l10", "particle", "f32", True, {}),
+    "particle_128_f64": ("box1000_n128_l10", "particle", "f64", True, {}),
 }
-DEFAULT_FORMS = ("gamma_256_f32", "gamma_256_bf16x3", "particle_512_f32")
+DEFAULT_FORMS = ("gamma_256_f32", "gamma_256_bf16x3", "gamma_256_f32_adj", "particle_512_f32", "particle_512_f64",
+                 "batch64_f32", "nodal_256_thin_tophat_f32")
 
 
-def measure_form(name, steps=1, warmup=1):
-    """Throughput of one form on its workload: deposit + zeta (+ zeta_backward with dJ/dw)."""
+def measure_form(name, steps=1):
+    """Throughput of one form on its workload: deposit + zeta (+ the one-sweep gradient with dJ/dw).
+
+    The first step runs with per-pass HIP-event timing (it also warms up); the
+    timed steps run without it.  The form's dominant pass gets a roofline
+    entry when its algorithmic bytes are known."""
     import torch
     import paper_2507_15209_amd as mp3
     from mockgen import WORKLOADS, workload_catalogue
     from mockgen import batch_sizes
-    wname, summation, precision, backward = FORMS[name]
+    wname, summation, precision, backward, opts = FORMS[name]
     wl = WORKLOADS[wname]
     dev = torch.device("cuda", 0)
     t0 = time.perf_counter()
@@ -234,11 +252,12 @@ def measure_form(name, steps=1, warmup=1):
     batch = 1 if off is None else len(off) - 1
     log(f"{name}: mock drawn in {time.perf_counter() - t0:.1f} s")
     pt, wt = torch.as_tensor(pos, device=dev), torch.as_tensor(w, device=dev)
+    np_total = len(w)
     del pos, w
     lam = torch.as_tensor(np.random.default_rng(12).standard_normal((batch, wl.lmax + 1, wl.nbins, wl.nbins)),
                           device=dev)
     plan = mp3.Plan(wl.n, wl.box, wl.lmax, wl.edges, precision=precision, device=dev, summation=summation,
-                    batch=batch)
+                    batch=batch, **opts)
     cat = (pt, wt, off) if summation == "particle" else ()
 
     def step():
@@ -248,9 +267,11 @@ def measure_form(name, steps=1, warmup=1):
         else:
             plan.zeta(delta, *cat)
 
-    for _ in range(warmup):
-        step()
+    plan.profile(True)
+    step()
     torch.cuda.synchronize()
+    prof = {k: v for k, v in plan.profile_read().items() if v[1] > 0}
+    plan.profile(False)
     t1 = time.perf_counter()
     for _ in range(steps):
         step()
@@ -260,29 +281,80 @@ def measure_form(name, steps=1, warmup=1):
     del plan, pt, wt
     torch.cuda.empty_cache()
     units = float(wl.n) ** 3 * (wl.lmax + 1) ** 2 * wl.nbins * batch
-    return {"workload": wl.name, "summation": summation, "precision": precision, "batch": batch,
-            "pass": "deposit + forward" + (" + adjoint with dJ/dw" if backward else ""),
-            "value": units / dt, "unit": "zeta_l evals/s", "ms_per_step": dt * 1e3, "steps": steps}
+    out = {"workload": wl.name, "summation": summation, "precision": precision, "batch": batch, "options": opts,
+           "pass": "deposit + forward" + (" + adjoint with dJ/dw (one sweep)" if backward else ""),
+           "value": units / dt, "unit": "zeta_l evals/s", "ms_per_step": dt * 1e3, "steps": steps,
+           "passes_ms": {k: {"total_ms": v[0], "launches": v[1]} for k, v in prof.items()}}
+    real_bytes = 8 if precision == "f64" else 4
+    # the dominant pass by total time; HBM roofline from its algorithmic bytes where they are defined
+    per_step = {k: v for k, v in prof.items() if k not in ("deposit", "dft")}
+    if per_step:
+        dom = max(per_step, key=lambda k: per_step[k][0])
+        avg = per_step[dom][0] / per_step[dom][1]
+        ab = pass_bytes(dom, wl.n, wl.nbins, batch, real_bytes, summation, np_total)
+        if ab:
+            ach = ab / (avg * 1e-3) / 1e9
+            out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": ach / HBM_PEAK_GBS, "avg_launch_ms": avg, "algorithmic_bytes_per_launch": ab,
+                               "traffic": None}
+        else:
+            out["roofline"] = {"kernel": dom, "avg_launch_ms": avg, "frac": None,
+                               "note": "no HBM-byte model for this pass (matrix-core or gather bound)"}
+    return out
 
 
-def cpu_baseline(wl, pos, w, nbins_sample=4, l_sample=0):
-    """The float64 oracle on a bounded sample of the same workload: the l = 0 multipole, first bins."""
-    from oracle import basis
+_ORACLE_DELTA = None
+
+
+def _oracle_item(args):
+    """One oracle work item: forward and gradient of zeta_l over its bins (float64)."""
+    wl_name, l, bins = args
+    from mockgen import WORKLOADS
     from oracle import estimator as E
     from oracle import adjoint as A
-    t0 = time.perf_counter()
-    eps = basis.deposit(pos, w, wl.n, wl.box)
-    delta = basis.density_contrast(eps, float(np.sum(w.astype(np.float64))))
+    wl = WORKLOADS[wl_name]
+    t0 = time.process_time()
     plan = E.Plan(wl.n, wl.box, wl.lmax, wl.edges)
-    bins = list(range(nbins_sample))
-    lam = np.random.default_rng(7).standard_normal((1, nbins_sample, nbins_sample))
-    E.zeta_nodal(plan, delta, ls=[l_sample], bins=bins)
-    A.zeta_nodal_grad(plan, delta, lam, ls=[l_sample], bins=bins)
+    lam = np.random.default_rng(7 + l).standard_normal((1, len(bins), len(bins)))
+    E.zeta_nodal(plan, _ORACLE_DELTA, ls=[l], bins=bins)
+    A.zeta_nodal_grad(plan, _ORACLE_DELTA, lam, ls=[l], bins=bins)
+    return float(wl.n) ** 3 * (2 * l + 1) * len(bins), time.process_time() - t0
+
+
+def cpu_baseline(wl, pos, w):
+    """The float64 oracle on a bounded sample of the same workload, on every host core.
+
+    The oracle deposits the full catalogue once; then one worker process per
+    core (fork, before anything touches the GPU) evaluates the forward and the
+    gradient of zeta_0 for its own radial bin, the work items of a step dealt
+    out over the cores.  Throughput = units of all items / wall time of
+    the whole sample (deposit included)."""
+    import multiprocessing as mp
+    from oracle import basis
+    global _ORACLE_DELTA
+    cores = os.cpu_count() or 1
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    workers = max(1, min(cores, 16, wl.nbins))
+    t0 = time.perf_counter()
+    c0 = time.process_time()
+    eps = basis.deposit(pos, w, wl.n, wl.box)
+    _ORACLE_DELTA = basis.density_contrast(eps, float(np.sum(w.astype(np.float64))))
+    c_dep = time.process_time() - c0
+    items = [(wl.name, 0, [j]) for j in range(workers)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        res = pool.map(_oracle_item, items)
     dt = time.perf_counter() - t0
-    units = float(wl.n) ** 3 * (2 * l_sample + 1) * nbins_sample
-    return {"value": units / dt, "unit": "zeta_l evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"deposit of the full catalogue + forward and gradient of zeta_{l_sample} over bins 0..{nbins_sample - 1} "
-                      f"({units:.3g} units in {dt:.1f} s, numpy float64, single-threaded FFTs)"}
+    units = sum(r[0] for r in res)
+    cpu_s = c_dep + sum(r[1] for r in res)
+    _ORACLE_DELTA = None
+    return {"value": units / dt, "unit": "zeta_l evals/s", "cores": workers, "kind": "oracle",
+            "host_cores": cores,
+            "sample": f"deposit of the full catalogue, then forward and gradient of zeta_0 for one radial bin per "
+                      f"worker ({workers} worker processes, bins 0..{workers - 1}): {units:.3g} units in "
+                      f"{dt:.1f} s wall, {cpu_s:.0f} s CPU (numpy float64)"}
 
 
 def main():
@@ -325,13 +397,20 @@ def main():
         pmc_probe(wl, args.precision)
         return
 
-    import torch
-    import paper_2507_15209_amd as mp3
-
     log("workload", wl.name, "n", wl.n, "L", wl.lmax, "bins", wl.nbins, "particles", wl.n_particles)
     t0 = time.perf_counter()
     pos, w = workload_catalogue(wl)
     log(f"mock drawn in {time.perf_counter() - t0:.1f} s")
+
+    # the CPU oracle first: its worker processes fork before anything touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample")
+        cpu = cpu_baseline(wl, pos, w)
+        log("cpu baseline:", cpu["sample"])
+
+    import torch
+    import paper_2507_15209_amd as mp3
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     pt = torch.as_tensor(pos, device=dev)
@@ -374,8 +453,12 @@ def main():
         torch.cuda.empty_cache()
         return dt / steps, prof
 
-    t_step, prof = run(args.precision, args.steps, args.warmup, True)
+    # the headline: timed with per-pass profiling off
+    t_step, _ = run(args.precision, args.steps, args.warmup, False)
     value = units / t_step
+    # per-pass times (HIP events around every launch on the library's stream), a separate run
+    prof_steps = max(1, min(3, args.steps))
+    t_prof, prof = run(args.precision, prof_steps, 1, True)
     real_bytes = 4 if args.precision == "f32" else 8
     passes = {k: v for k, v in prof.items() if v[1] > 0}
     dom = max((k for k in passes if pass_bytes(k, wl.n, wl.nbins, 1, real_bytes) is not None),
@@ -405,11 +488,6 @@ def main():
     for name in names:
         forms[name] = measure_form(name)
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a sample")
-        cpu = cpu_baseline(wl, pos, w)
-
     out = {
         "metric": METRIC,
         "value": value,
@@ -430,7 +508,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": abytes},
-        "passes_ms": {k: {"total_ms": v[0] / args.steps, "launches": v[1] // args.steps} for k, v in passes.items()},
+        "passes_ms": {k: {"total_ms": v[0] / prof_steps, "launches": v[1] // prof_steps} for k, v in passes.items()},
+        "profiled_ms_per_step": t_prof * 1e3,
         "two_calls": two_calls,
         "fp64_form": fp64,
         "forms": forms,

@@ -262,6 +262,18 @@ int mp3_zeta_value_and_grad(mp3_plan_t plan, const void* delta, const double* dz
 int mp3_xi(mp3_plan_t plan, const void* delta, const double* radii, int32_t nr, double* xi, void* workspace,
            size_t workspace_bytes, void* stream);
 
+/* Line-of-sight multipoles of the two-point function (Sec. 2.1, Eqs.
+ * DD-multipole and DD-windowfunction; the line of sight is the grid's z axis,
+ * the plane-parallel form of axial symmetry):
+ *   xi_ell(r) = N^-6 sum_q |dhat(q)|^2 Wp Ws Phi (2 ell + 1) Re(i^ell) j_ell(|k| r) P_ell(q_z / |q|),
+ * windows as mp3_xi, so that the azimuthal average of the pair correlation at
+ * separation r and polar angle theta is sum_ell xi_ell(r) P_ell(cos theta);
+ * odd ell vanish for real delta.
+ * radii  HOST double [nr], >= 0, 1 <= nr <= 4096;  0 <= ell_max <= 16;
+ * xi     device float64 [batch][ell_max+1][nr], overwritten. */
+int mp3_xi_multipoles(mp3_plan_t plan, const void* delta, const double* radii, int32_t nr, int32_t ell_max,
+                      double* xi, void* workspace, size_t workspace_bytes, void* stream);
+
 /* The 3PCF at the bin radii reconstructed from its multipoles, truncated at
  * lt (Sec. 2.2, Eq. triplet-counting; Sec. 3, Eq. Q-factor):
  *   zeta(r_b1, r_b2, theta) = sum_{l=0}^{lt} zeta_l[b1][b2] P_l(cos theta),
@@ -278,6 +290,25 @@ int mp3_xi(mp3_plan_t plan, const void* delta, const double* radii, int32_t nr, 
 int mp3_reduced_3pcf(mp3_plan_t plan, const void* delta, const double* zeta, int32_t lt, const double* mu,
                      int32_t nth, double* zeta_theta, double* q, void* workspace, size_t workspace_bytes,
                      void* stream);
+
+/* Edge-corrected estimator with a random catalogue (Sec. 3, Eq. SSestimator):
+ * zeta = (D - R)^3 / R^3, D - R reconstructed from the differences of the
+ * two catalogues' basis coefficients.  Three steps, each on the device:
+ *   1. mp3_deposit the data and the random catalogue (delta_D, delta_R);
+ *      mp3_ss_fields gives f = delta_D - delta_R = n_D/nbar_D - n_R/nbar_R
+ *      and r = 1 + delta_R = n_R/nbar_R (device real [batch][N^3] each);
+ *   2. mp3_zeta of f and of r with a grid-summation plan (nodal or
+ *      grid-Gamma): the multipoles N_l, R_l of the triplet correlations of
+ *      (D - R) and of R (the q = 0 mode is kept, so r's mean enters);
+ *   3. mp3_ss_multipoles: zeta_l = (2l+1)/2 int N(mu) / R(mu) P_l(mu) dmu,
+ *      N and R summed over l <= lt (Eq. triplet-counting), the integral by
+ *      nquad-point Gauss-Legendre quadrature.
+ * zeta_n, zeta_r  device float64 [batch][lmax+1][nbins][nbins];
+ * zeta_ss         device float64 [batch][lt+1][nbins][nbins], overwritten;
+ * 0 <= lt <= lmax, 1 <= nquad <= 4096. */
+int mp3_ss_fields(mp3_plan_t plan, const void* delta_d, const void* delta_r, void* f, void* r, void* stream);
+int mp3_ss_multipoles(mp3_plan_t plan, const double* zeta_n, const double* zeta_r, int32_t lt, int32_t nquad,
+                      double* zeta_ss, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Pass identifiers for per-pass timing. */
 enum mp3_pass {
@@ -324,7 +355,11 @@ enum mp3_tune_knob {
                                  default 8                                                       */
   MP3_TUNE_DEPOSIT_WGS = 4,   /* workgroups of the persistent deposit; 64 .. 65536, default 2048
                                  (never more than there are tiles)                               */
-  MP3_NTUNE = 5
+  MP3_TUNE_FUSED_WAVES = 5,   /* waves per workgroup of the one-sweep (value and gradient) z
+                                 pass: 0 = the fewest whole waves that hold one round of every
+                                 bin's columns (default), else 1 .. 8, raised to what n needs
+                                 (one thread per z point)                                        */
+  MP3_NTUNE = 6
 };
 
 /* Set a knob.  Out-of-range values return MP3_EINVAL and leave the knob as

@@ -37,7 +37,8 @@ import numpy as np
 from . import special, basis
 
 __all__ = ["Plan", "zeta_nodal", "zeta_gamma", "zeta_gamma_quadrature",
-           "zeta_particle", "fields", "volume_mean_pair", "xi", "zeta_theta", "reduced_3pcf"]
+           "zeta_particle", "fields", "volume_mean_pair", "xi", "zeta_theta", "reduced_3pcf", "xi_multipoles",
+           "ss_fields", "ss_multipoles"]
 
 FOUR_PI = 4.0 * np.pi
 
@@ -392,3 +393,69 @@ def reduced_3pcf(plan: Plan, delta, zeta, mu, lt: int) -> np.ndarray:
             x3 = xi(plan, delta, r3)
             q[i, j] = zt[i, j] / (xb[i] * xb[j] + xb[j] * x3 + x3 * xb[i])
     return q
+
+
+def xi_multipoles(plan: Plan, delta, radii, ells) -> np.ndarray:
+    """Line-of-sight multipoles of the two-point function [Sec. 2.1, Eqs. DD-multipole and
+    DD-windowfunction], the line of sight along the grid's z axis:
+
+        xi_ell(r) = n^-3 sum_x delta_p(x) (W^ell_r o delta)(x),
+        W^ell_r(k) = (2 ell + 1) i^ell j_ell(k r) P_ell(cos theta_k),
+
+    so that the azimuthal average of the pair correlation at separation r and polar angle theta_r
+    is sum_ell xi_ell(r) P_ell(cos theta_r).  The plan's top-hat and phi-hat windows apply as in
+    ``xi`` (Nyquist planes zeroed).  Returns [len(ells), len(radii)] (real part; the imaginary
+    part vanishes for real delta)."""
+    delta = np.asarray(delta, dtype=np.float64)
+    dhat = np.fft.fftn(delta)
+    prim = plan.primary(delta)
+    w = plan.phi_hat_grid()
+    if plan.smoothing > 0.0:
+        w = w * special.tophat_window(plan.kgrid * plan.smoothing)
+    mu = np.cos(plan.theta)
+    out = np.zeros((len(ells), np.size(radii)))
+    for i, ell in enumerate(ells):
+        ang = (2 * ell + 1) * (1j ** ell) * special.legendre(ell, mu)
+        for j, r in enumerate(np.asarray(radii, dtype=np.float64).ravel()):
+            k = w * ang * special.sph_jn(ell, plan.kgrid * r)
+            k[plan.nyquist] = 0.0
+            sec = np.fft.ifftn(dhat * k)
+            out[i, j] = float(np.mean(prim * sec.real))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# edge-corrected estimator with a random catalogue
+# ---------------------------------------------------------------------------
+
+def ss_fields(pos_d, w_d, pos_r, w_r, n: int, box: float):
+    """The two fields of the Szapudi-Szalay estimator [Sec. 3, Eq. SSestimator]: the data and random
+    catalogues deposited on the basis, each normalised to unit mean, and
+
+        f = n_D / nbar_D - n_R / nbar_R   (the field of D - R, from the coefficient differences),
+        r = n_R / nbar_R                  (the field of R).
+
+    Returns (f, r) as float64 [n, n, n]."""
+    w_d = np.ones(len(pos_d)) if w_d is None else np.asarray(w_d, dtype=np.float64)
+    w_r = np.ones(len(pos_r)) if w_r is None else np.asarray(w_r, dtype=np.float64)
+    rd = basis.deposit(pos_d, w_d, n, box) * (n ** 3 / w_d.sum())
+    rr = basis.deposit(pos_r, w_r, n, box) * (n ** 3 / w_r.sum())
+    return rd - rr, rr
+
+
+def ss_multipoles(zeta_n, zeta_r, lt: int, nquad: int) -> np.ndarray:
+    """Multipoles of the edge-corrected 3PCF zeta = (D - R)^3 / R^3 [Eq. SSestimator]:
+
+        zeta_l = (2l + 1) / 2 int_{-1}^{1} N(mu) / R(mu) P_l(mu) dmu,  l = 0 .. lt,
+
+    with N and R the triplet correlations of f and r reconstructed from their multipoles truncated
+    at lt [Eq. triplet-counting], the integral by nquad-point Gauss-Legendre quadrature.
+    zeta_n, zeta_r: [L+1, nb, nb] -> [lt+1, nb, nb]."""
+    xg, wg = special.gauss_legendre(nquad)
+    num = zeta_theta(zeta_n, xg, lt)
+    den = zeta_theta(zeta_r, xg, lt)
+    ratio = num / den
+    out = np.zeros((lt + 1,) + ratio.shape[:2])
+    for l in range(lt + 1):
+        out[l] = 0.5 * (2 * l + 1) * (ratio * (wg * special.legendre(l, xg))[None, None, :]).sum(-1)
+    return out

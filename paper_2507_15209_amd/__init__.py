@@ -265,6 +265,39 @@ class Plan:
         _lib.check(st, "mp3_xi")
         return out
 
+    def xi_multipoles(self, delta, radii, ell_max: int):
+        """Line-of-sight (z) multipoles of xi, [batch, ell_max+1, len(radii)] float64."""
+        self._real(delta, "delta")
+        r = np.ascontiguousarray(radii, dtype=np.float64).ravel()
+        out = torch.empty((self.batch, int(ell_max) + 1, r.size), dtype=torch.float64, device=self.device)
+        ws = self._workspace()
+        st = self.lib.mp3_xi_multipoles(self._h, _ptr(delta), r.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        int(r.size), int(ell_max), _ptr(out), _ptr(ws), ws.numel(),
+                                        _stream(self.device))
+        _lib.check(st, "mp3_xi_multipoles")
+        return out
+
+    def ss_fields(self, delta_d, delta_r):
+        """(f, r) = (delta_D - delta_R, 1 + delta_R): the fields of D - R and R (edge-corrected estimator)."""
+        self._real(delta_d, "delta_d")
+        self._real(delta_r, "delta_r")
+        f, r = torch.empty_like(delta_d), torch.empty_like(delta_d)
+        _lib.check(self.lib.mp3_ss_fields(self._h, _ptr(delta_d), _ptr(delta_r), _ptr(f), _ptr(r),
+                                          _stream(self.device)), "mp3_ss_fields")
+        return f, r
+
+    def ss_multipoles(self, zeta_n, zeta_r, lt=None, nquad: int = 64):
+        """Multipoles [batch, lt+1, nbins, nbins] of (D - R)^3 / R^3 from those of f and r."""
+        zn = zeta_n.to(device=self.device, dtype=torch.float64).contiguous()
+        zr = zeta_r.to(device=self.device, dtype=torch.float64).contiguous()
+        lt = self.lmax if lt is None else int(lt)
+        out = torch.empty((self.batch, lt + 1, self.nbins, self.nbins), dtype=torch.float64, device=self.device)
+        ws = self._workspace()
+        st = self.lib.mp3_ss_multipoles(self._h, _ptr(zn), _ptr(zr), lt, int(nquad), _ptr(out), _ptr(ws), ws.numel(),
+                                        _stream(self.device))
+        _lib.check(st, "mp3_ss_multipoles")
+        return out
+
     def reduced_3pcf(self, zeta, mu, lt=None, delta=None):
         """(zeta(r_b1, r_b2, theta), Q or None), each [batch, nbins, nbins, len(mu)] float64.
 

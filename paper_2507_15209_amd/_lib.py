@@ -26,14 +26,15 @@ MP3_BIN_THIN_SHELL = 1
 MP3_KF_PHI_HAT = 1
 MP3_KF_CHECK_FINITE = 2
 # launch-shape knobs (enum mp3_tune_knob)
-TUNE_KNOBS = ("zpass_wgs", "contract_wgs", "fft_x_plan", "deposit_tile", "deposit_wgs")
+TUNE_KNOBS = ("zpass_wgs", "contract_wgs", "fft_x_plan", "deposit_tile", "deposit_wgs", "fused_waves")
 
 # every entry point of include/mp3.h
 EXPORTS = (
     "mp3_plan_create", "mp3_plan_destroy", "mp3_workspace_size", "mp3_deposit",
     "mp3_multipole_fields", "mp3_zeta", "mp3_zeta_backward", "mp3_plan_info",
     "mp3_status_string", "mp3_last_error", "mp3_profile", "mp3_profile_read",
-    "mp3_tune_set", "mp3_tune_get", "mp3_zeta_value_and_grad", "mp3_xi", "mp3_reduced_3pcf",
+    "mp3_tune_set", "mp3_tune_get", "mp3_zeta_value_and_grad", "mp3_xi", "mp3_xi_multipoles", "mp3_reduced_3pcf",
+    "mp3_ss_fields", "mp3_ss_multipoles",
     "mp3_sph_bessel", "mp3_window_table",
 )
 PASSES = ("dft", "filter", "x", "z_nodal", "z_adjoint", "adjoint", "deposit", "z_store", "gather", "gamma",
@@ -98,6 +99,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.mp3_tune_set.argtypes = [vp, ctypes.c_int, i32]
     lib.mp3_tune_get.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i32)]
     lib.mp3_xi.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), i32, vp, vp, sz, vp]
+    lib.mp3_xi_multipoles.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), i32, i32, vp, vp, sz, vp]
+    lib.mp3_ss_fields.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.mp3_ss_multipoles.argtypes = [vp, vp, vp, i32, i32, vp, vp, sz, vp]
     lib.mp3_reduced_3pcf.argtypes = [vp, vp, vp, i32, ctypes.POINTER(ctypes.c_double), i32, vp, vp, vp, sz, vp]
     lib.mp3_sph_bessel.argtypes = [i32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
     lib.mp3_window_table.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(ctypes.c_double), sz]

@@ -26,6 +26,7 @@ CANDIDATES = {
     "fft_x_plan": (0, 1),
     "zpass_wgs": (1024, 2048, 4096, 8192, 16384),
     "contract_wgs": (1024, 2048, 4096, 8192, 16384),
+    "fused_waves": (0, 4, 8),
 }
 
 
@@ -111,9 +112,11 @@ def autotune(plan, delta, pos=None, w=None, np_off=None, dzeta=None, backward: b
 
     delta: a density contrast of the plan's shape (the forward's input).
     pos, w, np_off: a catalogue; needed by the particle form and for the
-    deposit knobs (skipped without it).  dzeta: the backward's seed (nodal
-    form only; random if None).  With a cache entry for this configuration
-    and ``force`` False the cached knobs are applied and nothing is timed.
+    deposit knobs (skipped without it).  dzeta: the gradient's seed (random
+    if None).  With ``backward`` the timed call is the one-sweep value and
+    gradient (the path the benchmark times), else the forward alone.  With a
+    cache entry for this configuration and ``force`` False the cached knobs
+    are applied and nothing is timed.
     """
     if not force and load_tuning(plan, cache):
         return plan.tuning()
@@ -124,18 +127,21 @@ def autotune(plan, delta, pos=None, w=None, np_off=None, dzeta=None, backward: b
             for k in ("deposit_tile", "deposit_wgs"):
                 times[k] = _descend(plan, k, dep, reps, log)
         cat = (pos, w, np_off) if plan.summation == "particle" else (None, None, None)
-        do_bwd = backward and plan.summation == "nodal"
+        do_bwd = backward and (plan.summation != "particle" or pos is not None)
         if do_bwd and dzeta is None:
             g = torch.Generator(device=plan.device).manual_seed(0)
             dzeta = torch.randn((plan.batch, plan.lmax + 1, plan.nbins, plan.nbins), dtype=torch.float64,
                                 device=plan.device, generator=g)
 
         def path():
-            plan.zeta(delta, *cat)
             if do_bwd:
-                plan.zeta_backward(delta, dzeta)
+                plan.zeta_value_and_grad(delta, dzeta, *cat)
+            else:
+                plan.zeta(delta, *cat)
 
         knobs = ["fft_x_plan", "zpass_wgs"]
+        if do_bwd and plan.summation == "nodal":
+            knobs.append("fused_waves")
         if plan.summation != "nodal":
             knobs.append("contract_wgs")
         for k in knobs:

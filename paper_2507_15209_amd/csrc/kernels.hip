@@ -2560,7 +2560,14 @@ hipError_t zpass_nodal_t(const ZpassArgs& a, hipStream_t st) {
 
 // fused sweeps round the workgroup up to whole waves (the matrix-core
 // contractions split the work by wave); the extra threads hold no column
-template <int N, typename T> inline int zpass_fused_threads(int nbins) {
+template <int N, typename T> inline int zpass_fused_threads(int nbins, int waves = 0) {
+  if (waves > 0) {
+    // at least one thread per z point and one column; at most 8 waves (the launch bound)
+    int need = N / DPRE > Fft<N, VZA<T>>::TPC ? N / DPRE : Fft<N, VZA<T>>::TPC;
+    int t = 64 * waves;
+    if (t < need) t = (need + 63) / 64 * 64;
+    return t > 512 ? 512 : t;
+  }
   return (zpass_threads<N, VZA<T>>(nbins) + 63) / 64 * 64;
 }
 
@@ -2572,7 +2579,7 @@ template <int N, typename T> inline size_t zpass_fused_lds(int nbins, int thread
 
 template <int N, typename T, int MAXNB, bool FUSED = false, bool MF = false, bool QUAD = false>
 hipError_t zpass_adjoint_nb(const ZpassArgs& a, hipStream_t st) {
-  const int threads = FUSED ? zpass_fused_threads<N, T>(a.nbins) : zpass_threads<N, VZA<T>>(a.nbins);
+  const int threads = FUSED ? zpass_fused_threads<N, T>(a.nbins, a.waves) : zpass_threads<N, VZA<T>>(a.nbins);
   const size_t lds = FUSED ? zpass_fused_lds<N, T>(a.nbins, threads,
                                                     Contractor<T, MF, false, QUAD>::scratch_bytes(threads))
                            : zpass_adjoint_lds<N, T>(a.nbins);
@@ -2661,7 +2668,7 @@ hipError_t launch_zpass_fused(int n, int prec, const ZpassArgs& a, hipStream_t s
 
 template <int N, typename T> size_t zpass_fused_lds_need_t(int nbins) {
   if (nbins > 32) return (size_t)1 << 40;
-  const int threads = zpass_fused_threads<N, T>(nbins);
+  const int threads = 512;   // the largest workgroup any waves setting gives
   constexpr bool MF = std::is_same<T, float>::value;
   const size_t red = nbins > 16 && nbins <= 20 ? Contractor<T, MF, false, MF>::scratch_bytes(threads)
                                                 : Contractor<T, MF, false, false>::scratch_bytes(threads);

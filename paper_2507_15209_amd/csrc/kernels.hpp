@@ -37,6 +37,7 @@ struct ZpassArgs {
   int nbins, nwg, ppw, batch, l, lmax;
   double wm;            // m weight (1 for m = 0, 2 otherwise)
   bool split;           // float32 contraction with BF16-split inputs on the matrix cores
+  int waves = 0;        // one-sweep z pass: waves per workgroup (0 = default)
 };
 
 struct GatherArgs {
@@ -151,6 +152,18 @@ hipError_t launch_power_plain(int prec, const void* dhat, int n, int nq2, double
 // xi[batch][nr] at device radii from the histogram of launch_power_plain
 hipError_t launch_xi(const double* P, int nq2, double kf, double R, bool prim_smooth, const double* radii, int nr,
                      double n6, double* xi, int batch, hipStream_t st);
+// H[batch][lmx+1][nq2]: per-|q|^2 Legendre moments of |dhat|^2 along z (lmx <= 16)
+hipError_t launch_power_multipoles(int prec, const void* dhat, int n, int nq2, int lmx, double* H, int batch,
+                                  const void* phi, hipStream_t st);
+// out[batch][lmx+1][nr]: line-of-sight multipoles of xi at device radii
+hipError_t launch_xi_multipoles(const double* H, int nq2, int lmx, double kf, double R, bool prim_smooth,
+                                const double* radii, int nr, double n6, double* out, int batch, hipStream_t st);
+// f = delta_D - delta_R, r = 1 + delta_R over count values
+hipError_t launch_ss_fields(int prec, const void* dd, const void* dr, void* f, void* r, long long count,
+                            hipStream_t st);
+// out[batch][lt+1][nbins][nbins]: Gauss-Legendre projection of N(mu) / R(mu) on P_l (lt <= 20)
+hipError_t launch_ss_multipoles(const double* zn, const double* zr, int lmax, int lt, int nbins, const double* xq,
+                                const double* wq, int nq, double* out, int batch, hipStream_t st);
 // zt[batch][nbins][nbins][nth] = sum_{l <= lt} zeta_l P_l(mu) and, when q != NULL, the reduced 3PCF
 hipError_t launch_reduced_3pcf(const double* zeta, int lmax, int lt, int nbins, const double* mu, int nth,
                                const double* rb, const double* xib, const double* P, int nq2, double kf, double R,

@@ -24,7 +24,7 @@ struct mp3_plan_s {
   int device = 0;
   double gm[5][4] = {{0}};   // grid-Gamma quadrature: B3 tap weights at the nodes
   double gw[5] = {0};        // and node weights
-  int tune[MP3_NTUNE] = {4096, 4096, 0, 8, 2048};   // launch-shape knobs (mp3_tune_knob)
+  int tune[MP3_NTUNE] = {4096, 4096, 0, 8, 2048, 0};   // launch-shape knobs (mp3_tune_knob)
   int basis = 0, binning = 0;
   unsigned kflags = 0;
   double smoothing = 0.0;   // top-hat radius of every vertex (0 = none)
@@ -360,6 +360,11 @@ int filter_direct(const mp3_plan_s* p, void* direct, void* ws, const Layout& L, 
 
 }  // namespace
 
+namespace mp3 {
+// the last-error message of the calling thread, for entry points defined in other sources
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace mp3
+
 extern "C" {
 
 const char* mp3_status_string(int s) {
@@ -509,6 +514,9 @@ int mp3_tune_set(mp3_plan_t p, int knob, int32_t value) {
       break;
     case MP3_TUNE_DEPOSIT_TILE:
       if (value != 4 && value != 8 && value != 16) return fail(MP3_EINVAL, "deposit tile side must be 4, 8 or 16");
+      break;
+    case MP3_TUNE_FUSED_WAVES:
+      if (value < 0 || value > 8) return fail(MP3_EINVAL, "one-sweep z-pass waves must lie in 0 .. 8");
       break;
     default:
       return fail(MP3_EINVAL, "unknown tuning knob");
@@ -1200,6 +1208,7 @@ int mp3_zeta_value_and_grad(mp3_plan_t p, const void* delta, const double* dzeta
       z.l = l;
       z.lmax = p->lmax;
       z.wm = wm;
+      z.waves = p->tune[MP3_TUNE_FUSED_WAVES];
       MP3_HIP(timed(p, MP3_PASS_Z_FUSED, st, [&] { return mp3::launch_zpass_fused(p->n, p->prec, z, st); }),
               "z pass (contraction and adjoint)");
       MP3_HIP(mp3::launch_reduce_partials(partials, L.nwg, nb2, zeta, l, p->lmax, wm * kFourPi / (double)n3, p->batch, st),
@@ -1252,6 +1261,37 @@ int mp3_xi(mp3_plan_t p, const void* delta, const double* radii, int32_t nr, dou
   return MP3_OK;
 }
 
+int mp3_xi_multipoles(mp3_plan_t p, const void* delta, const double* radii, int32_t nr, int32_t ell_max, double* xi,
+                      void* ws, size_t wsb, void* stream) {
+  if (int s = check_plan(p)) return s;
+  if (!delta || !radii || !xi) return fail(MP3_EINVAL, "delta, radii and xi must not be NULL");
+  if (nr < 1 || nr > kMaxAux) return fail(MP3_EINVAL, "nr must be in [1, 4096]");
+  if (ell_max < 0 || ell_max > 16) return fail(MP3_EINVAL, "ell_max must be in [0, 16]");
+  for (int i = 0; i < nr; ++i) {
+    if (!std::isfinite(radii[i])) return fail(MP3_ENONFINITE, "radii must be finite");
+    if (radii[i] < 0.0) return fail(MP3_EINVAL, "radii must be >= 0");
+  }
+  const Layout L = layout(p);
+  if (int s = check_ws(p, ws, wsb, L.total)) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const long long n3 = (long long)p->n * p->n * p->n;
+  if (int s = check_finite(p, ws, L.flag, st, delta, n3 * p->batch, p->prec)) return s;
+  if (int s = forward_dft(p, delta, ws, L, st)) return s;
+  // the moments [batch][ell][nq2] fit in the (idle) field buffer: N^3 > 17 * 3 (N/2)^2 for N >= 16
+  const int nq2 = mp3::nq2_count(p->n);
+  double* H = reinterpret_cast<double*>(at(ws, L.fields));
+  MP3_HIP(mp3::launch_fill_f64(H, (long long)p->batch * (ell_max + 1) * nq2, 0.0, st), "zero moments");
+  MP3_HIP(mp3::launch_power_multipoles(p->prec, at(ws, L.dhat), p->n, nq2, ell_max, H, p->batch, p->phi, st),
+          "power moments");
+  double* dr = reinterpret_cast<double*>(at(ws, L.aux));
+  MP3_HIP(hipMemcpyAsync(dr, radii, (size_t)nr * sizeof(double), hipMemcpyHostToDevice, st), "copy radii");
+  const double n6 = (double)n3 * (double)n3;
+  MP3_HIP(mp3::launch_xi_multipoles(H, nq2, ell_max, 2.0 * M_PI / p->box, p->smoothing, primary_smoothed(p), dr, nr, n6,
+                                    xi, p->batch, st),
+          "xi multipoles");
+  return MP3_OK;
+}
+
 int mp3_reduced_3pcf(mp3_plan_t p, const void* delta, const double* zeta, int32_t lt, const double* mu, int32_t nth,
                      double* zeta_theta, double* q, void* ws, size_t wsb, void* stream) {
   if (int s = check_plan(p)) return s;
@@ -1287,6 +1327,36 @@ int mp3_reduced_3pcf(mp3_plan_t p, const void* delta, const double* zeta, int32_
   MP3_HIP(mp3::launch_reduced_3pcf(zeta, p->lmax, lt, p->nbins, dmu, nth, drb, xib, P, nq2, kf, p->smoothing,
                                    primary_smoothed(p), n6, zeta_theta, q, p->batch, st),
           "reduced 3PCF");
+  return MP3_OK;
+}
+
+int mp3_ss_fields(mp3_plan_t p, const void* delta_d, const void* delta_r, void* f, void* r, void* stream) {
+  if (int s = check_plan(p)) return s;
+  if (!delta_d || !delta_r || !f || !r) return fail(MP3_EINVAL, "delta_d, delta_r, f and r must not be NULL");
+  const long long n3 = (long long)p->n * p->n * p->n;
+  MP3_HIP(mp3::launch_ss_fields(p->prec, delta_d, delta_r, f, r, n3 * p->batch, static_cast<hipStream_t>(stream)),
+          "edge-corrected fields");
+  return MP3_OK;
+}
+
+int mp3_ss_multipoles(mp3_plan_t p, const double* zeta_n, const double* zeta_r, int32_t lt, int32_t nquad,
+                      double* zeta_ss, void* ws, size_t wsb, void* stream) {
+  if (int s = check_plan(p)) return s;
+  if (!zeta_n || !zeta_r || !zeta_ss) return fail(MP3_EINVAL, "zeta_n, zeta_r and zeta_ss must not be NULL");
+  if (lt < 0 || lt > p->lmax) return fail(MP3_EINVAL, "need 0 <= lt <= lmax");
+  if (nquad < 1 || nquad > kMaxAux) return fail(MP3_EINVAL, "nquad must be in [1, 4096]");
+  const Layout L = layout(p);
+  if (int s = check_ws(p, ws, wsb, L.total)) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<double> xq, wq, both;
+  mp3::gauss_legendre(nquad, xq, wq);
+  both.insert(both.end(), xq.begin(), xq.end());
+  both.insert(both.end(), wq.begin(), wq.end());
+  double* dq = reinterpret_cast<double*>(at(ws, L.aux));
+  MP3_HIP(hipMemcpyAsync(dq, both.data(), both.size() * sizeof(double), hipMemcpyHostToDevice, st), "copy nodes");
+  MP3_HIP(mp3::launch_ss_multipoles(zeta_n, zeta_r, p->lmax, lt, p->nbins, dq, dq + nquad, nquad, zeta_ss, p->batch,
+                                    st),
+          "edge-corrected multipoles");
   return MP3_OK;
 }
 

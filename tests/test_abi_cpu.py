@@ -12,7 +12,7 @@ from tests._common import ROOT, ensure_library
 def _declared():
     src = open(os.path.join(ROOT, "include", "mp3.h")).read()
     # function declarations: a return type at the start of the line, then the name
-    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(mp3_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^(?:int|size_t|const char\*)\s+(mp3_\w+)\s*\(", src, re.M)))
 
 
 def test_header_declares_expected_entry_points():
@@ -82,4 +82,4 @@ def test_tuning_knobs_reject_null_plan_and_bad_knobs():
     assert lib.mp3_tune_set(None, 0, 4096) == _lib.MP3_EINVAL
     assert lib.mp3_tune_get(None, 0, ctypes.byref(v)) == _lib.MP3_EINVAL
     assert v.value == -7
-    assert len(_lib.TUNE_KNOBS) == 5
+    assert len(_lib.TUNE_KNOBS) == 6

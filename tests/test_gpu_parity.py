@@ -220,10 +220,20 @@ def test_invalid_arguments_raise(mp3):
         plan.multipole_fields(d, 1, 2)
     pos = torch.zeros((4, 3), dtype=torch.float32, device="cuda")
     b2 = mp3.Plan(16, 100.0, 1, [10.0, 20.0], batch=2)
-    with pytest.raises(mp3.Mp3Error):
-        b2.deposit(pos, None, [0, 4, 4])       # empty second mock
+    with pytest.raises(ValueError):
+        b2.deposit(pos, None, [0, 4, 4])       # empty second mock: the binding refuses it
+    with pytest.raises(ValueError):
+        b2.deposit(pos, None, [0, 2, 6])       # more particles than pos holds
     import ctypes
     from paper_2507_15209_amd import _lib
+    # and so does the library itself
+    off = np.array([0, 4, 4], dtype=np.int64)
+    ws = b2._workspace(4)
+    dd = torch.empty((2, 16, 16, 16), dtype=torch.float32, device="cuda")
+    st = b2.lib.mp3_deposit(b2._h, ctypes.c_void_p(pos.data_ptr()), None,
+                            off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.c_void_p(dd.data_ptr()),
+                            ctypes.c_void_p(ws.data_ptr()), ws.numel(), None)
+    assert st == _lib.MP3_EINVAL
     z = torch.empty((1, 3, 2, 2), dtype=torch.float64, device="cuda")
     ws = torch.empty(16, dtype=torch.uint8, device="cuda")
     st = plan.lib.mp3_zeta(plan._h, ctypes.c_void_p(d.data_ptr()), None, None, None, ctypes.c_void_p(z.data_ptr()),

@@ -111,7 +111,8 @@ def test_tune_set_rejects_out_of_range(mp3):
     _say("tune invalid")
     plan = mp3.Plan(16, 160.0, 1, [10.0, 20.0])
     for knob, bad in [("zpass_wgs", 10), ("zpass_wgs", 1 << 20), ("contract_wgs", 0), ("fft_x_plan", 2),
-                      ("deposit_tile", 5), ("deposit_tile", 32), ("deposit_wgs", 63)]:
+                      ("deposit_tile", 5), ("deposit_tile", 32), ("deposit_wgs", 63), ("fused_waves", -1),
+                      ("fused_waves", 9)]:
         before = plan.tune_get(knob)
         with pytest.raises(mp3.Mp3Error):
             plan.tune_set(knob, bad)
@@ -140,3 +141,31 @@ def test_autotune_caches_and_keeps_results(mp3, tmp_path):
     ref_delta = basis.density_contrast(basis.deposit(pos, w, n, box), float(np.sum(w.astype(np.float64))))
     assert np.abs(d2.cpu().numpy()[0] - ref_delta).max() <= 1e-13 * np.abs(ref_delta).max()
     assert_zeta_close(z, E.zeta_nodal(E.Plan(n, box, lmax, edges), ref_delta), 1e-10)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n,waves", [(32, 1), (32, 4), (32, 8), (128, 2), (128, 4), (128, 6), (128, 8)])
+def test_fused_waves_keep_value_and_gradient(mp3, prec, n, waves):
+    """Every waves-per-workgroup setting of the one-sweep z pass: zeta against the oracle (n = 32)
+    and zeta, dJ/ddelta, dJ/dw against the default setting (all n; 1e-12 / 2e-5)."""
+    _say("fused waves", prec, n, waves)
+    box, lmax, nb = 10.0 * n, 2, 20
+    edges = np.linspace(0.08 * box, 0.35 * box, nb + 1)
+    pos, w = lognormal_catalogue(n, box, 20000, 0.05 * box, 7001, 7002, 7003, (0.5, 1.5))
+    pt, wt = _dev(pos, torch.float32), _dev(w, torch.float32)
+    lam = _dev(np.random.default_rng(7004).standard_normal((1, lmax + 1, nb, nb)), torch.float64)
+    base = mp3.Plan(n, box, lmax, edges, precision=prec)
+    d = base.deposit(pt, wt)
+    z0, g0, w0 = base.zeta_value_and_grad(d, lam, pt, wt)
+    plan = mp3.Plan(n, box, lmax, edges, precision=prec)
+    plan.tune_set("fused_waves", waves)
+    z1, g1, w1 = plan.zeta_value_and_grad(d, lam, pt, wt)
+    agree = 1e-12 if prec == "f64" else 2e-5
+    assert_zeta_close(z1.cpu().numpy()[0], z0.cpu().numpy()[0], agree)
+    for a1, a0 in ((g1, g0), (w1, w0)):
+        a1, a0 = a1.cpu().numpy(), a0.cpu().numpy()
+        assert np.abs(a1 - a0).max() <= agree * np.abs(a0).max()
+    if n == 32:
+        dref = basis.density_contrast(basis.deposit(pos, w, n, box), float(np.sum(w.astype(np.float64))))
+        assert_zeta_close(z1.cpu().numpy()[0], E.zeta_nodal(E.Plan(n, box, lmax, edges), dref),
+                          1e-10 if prec == "f64" else 1e-4)

@@ -177,3 +177,52 @@ def test_check_finite_rejects_nan(mp3):
     pos[7, 1] = 1.0
     good = plan.deposit(_dev(pos, torch.float32))
     assert torch.isfinite(plan.zeta(good)).all()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("opts", [dict(), dict(smoothing=5.0, phi_hat=True)], ids=_ids)
+def test_xi_multipoles(mp3, prec, opts):
+    """Line-of-sight multipoles of xi (ell <= 8) at several radii against the oracle."""
+    _say("xi multipoles", prec, opts)
+    n, box = 32, 320.0
+    pos, w = lognormal_catalogue(n, box, 20000, 10.0, 1451, 1452)
+    plan = mp3.Plan(n, box, 1, [10.0, 20.0], precision=prec, **opts)
+    delta = plan.deposit(_dev(pos, torch.float32), _dev(w, torch.float32))
+    radii = np.array([0.0, 6.0, 21.0, 40.0, 77.0])
+    got = plan.xi_multipoles(delta, radii, 8).cpu().numpy()[0]
+    dref = basis.density_contrast(basis.deposit(pos, w, n, box), float(np.sum(w.astype(np.float64))))
+    ref = E.xi_multipoles(E.Plan(n, box, 1, [10.0, 20.0], **opts), dref, radii, list(range(9)))
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print("xi_ell error", err)
+    assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_ss_estimator(mp3, prec):
+    """Edge-corrected (D - R)^3 / R^3 with a random catalogue confined to a sub-volume (the data drawn
+    inside it): the fields, the two sets of multipoles and the projected ratio against the oracle."""
+    _say("ss estimator", prec)
+    n, box, lmax, nb = 32, 320.0, 4, 4
+    edges = np.linspace(20.0, 80.0, nb + 1)
+    rng = np.random.default_rng(1461)
+    pd, wd = lognormal_catalogue(n, box, 20000, 12.0, 1462, 1463)
+    keep = (pd[:, 0] < 0.75 * box)
+    pd, wd = pd[keep], wd[keep]
+    pr = rng.uniform(0.0, 1.0, (60000, 3)) * np.array([0.75 * box, box, box])
+    pr = pr.astype(np.float32)
+    wr = np.ones(len(pr), dtype=np.float32)
+    plan = mp3.Plan(n, box, lmax, edges, precision=prec)
+    dd = plan.deposit(_dev(pd, torch.float32), _dev(wd, torch.float32))
+    dr = plan.deposit(_dev(pr, torch.float32), _dev(wr, torch.float32))
+    f, r = plan.ss_fields(dd, dr)
+    zn, zr = plan.zeta(f), plan.zeta(r)
+    zs = plan.ss_multipoles(zn, zr, lmax, 48).cpu().numpy()[0]
+    fo, ro = E.ss_fields(pd, wd, pr, wr, n, box)
+    op = E.Plan(n, box, lmax, edges)
+    zno, zro = E.zeta_nodal(op, fo), E.zeta_nodal(op, ro)
+    tol = TOL[prec]
+    assert np.abs(f.cpu().numpy()[0] - fo).max() <= (1e-12 if prec == "f64" else 1e-5) * np.abs(fo).max()
+    assert_zeta_close(zn.cpu().numpy()[0], zno, tol)
+    assert_zeta_close(zr.cpu().numpy()[0], zro, tol)
+    ref = E.ss_multipoles(zno, zro, lmax, 48)
+    assert_zeta_close(zs, ref, tol)

@@ -207,3 +207,87 @@ def test_reduced_3pcf_definition():
     zeta[0] = zh
     q = E.reduced_3pcf(plan, delta, zeta, mu[:1], 2)
     assert np.max(np.abs(q[..., 0] - 1.0)) < 1e-12
+
+
+def test_xi_multipoles_of_one_cosine_mode():
+    """delta = cos(k0.x): xi_ell(r) = (1/2)(2 ell + 1) i^ell j_ell(k0 r) P_ell(mu0) W^2, mu0 the cosine of
+    k0 with the line of sight (odd ell vanish: the two modes +-k0 cancel)."""
+    n, box = 16, 160.0
+    q0 = np.array([2, 1, 3])
+    delta = _cos_mode(n, q0)
+    plan = E.Plan(n, box, 0, [10.0, 20.0], smoothing=4.0)
+    k0 = 2.0 * np.pi / box * np.linalg.norm(q0)
+    mu0 = q0[2] / np.linalg.norm(q0)
+    r = np.array([3.0, 17.5, 41.0])
+    ells = [0, 1, 2, 4, 6]
+    got = E.xi_multipoles(plan, delta, r, ells)
+    w = float(special.tophat_window(k0 * 4.0))
+    for i, ell in enumerate(ells):
+        ref = 0.0 if ell % 2 else 0.5 * w * w * (2 * ell + 1) * ((-1) ** (ell // 2)) * special.sph_jn(ell, k0 * r) \
+            * special.legendre(ell, mu0)
+        assert np.max(np.abs(got[i] - ref)) < 1e-14
+
+
+def test_xi_multipoles_resum_the_azimuthal_average():
+    """sum_ell xi_ell(r) P_ell(cos theta_r) equals the azimuthal average of the pair correlation
+    n^-6 sum_q |dhat|^2 exp(i k.r) over phi_r (Eq. DD-multipole), by quadrature in phi_r."""
+    n, box = 8, 400.0
+    delta = random_field(n, 24)
+    plan = E.Plan(n, box, 0, [10.0, 20.0])
+    r = 35.0
+    ells = list(range(0, 21, 2))
+    xl = E.xi_multipoles(plan, delta, [r], ells)[:, 0]
+    dh = np.fft.fftn(delta)
+    p2 = np.abs(dh) ** 2
+    p2[plan.nyquist] = 0.0
+    q = np.fft.fftfreq(n, 1.0 / n)
+    Q = np.stack(np.meshgrid(q, q, q, indexing="ij"), -1).reshape(-1, 3) * (2.0 * np.pi / box)
+    for ct in (-0.8, 0.0, 0.45, 0.95):
+        st = np.sqrt(1.0 - ct * ct)
+        ph = np.linspace(0.0, 2.0 * np.pi, 256, endpoint=False)
+        rv = r * np.stack([st * np.cos(ph), st * np.sin(ph), np.full_like(ph, ct)], -1)
+        avg = (p2.ravel()[None, :] * np.exp(1j * rv @ Q.T)).sum(1).mean().real / float(n) ** 6
+        res = sum(xl[i] * special.legendre(ell, ct) for i, ell in enumerate(ells))
+        assert abs(res - avg) < 1e-12 * np.abs(xl).max(), (ct, res, avg)
+
+
+def test_ss_estimator_of_identical_catalogues_vanishes():
+    """D = R: the field of D - R is zero, and so is every multipole of (D - R)^3 / R^3."""
+    from mockgen import lognormal_catalogue
+    n, box = 16, 160.0
+    pos, w = lognormal_catalogue(n, box, 3000, 8.0, 31, 32, 33, (0.5, 1.5))
+    f, r = E.ss_fields(pos, w, pos, w, n, box)
+    assert np.abs(f).max() == 0.0
+    assert abs(r.mean() - 1.0) < 1e-14
+
+
+def test_ss_estimator_with_uniform_randoms_is_the_plain_3pcf():
+    """A random field that is exactly uniform (r = 1) has R_0 = 1 and R_{l>0} = 0, so the estimator's
+    multipoles are those of f, recovered exactly by the Gauss-Legendre projection (polynomial in mu)."""
+    n = 8
+    f = random_field(n, 25)
+    r = np.ones((n,) * 3)
+    plan = E.Plan(n, 100.0, 4, np.linspace(8.0, 40.0, 4))
+    zn, zr = E.zeta_nodal(plan, f), E.zeta_nodal(plan, r)
+    assert abs(zr[0] - 1.0).max() < 1e-13 and np.abs(zr[1:]).max() < 1e-13
+    zs = E.ss_multipoles(zn, zr, 4, 12)
+    assert np.max(np.abs(zs - zn)) < 1e-12 * np.abs(zn).max()
+
+
+def test_ss_projection_against_adaptive_quadrature():
+    """The projection of N(mu) / R(mu) for a non-uniform random field against scipy's adaptive
+    quadrature of the same ratio (independent of the Gauss-Legendre rule)."""
+    n = 8
+    f = random_field(n, 26)
+    r = 1.0 + 0.3 * random_field(n, 27)
+    plan = E.Plan(n, 100.0, 3, np.linspace(8.0, 40.0, 3))
+    zn, zr = E.zeta_nodal(plan, f), E.zeta_nodal(plan, r)
+    zs = E.ss_multipoles(zn, zr, 3, 64)
+    for l in range(4):
+        for i in range(2):
+            for j in range(2):
+                g = lambda m: float(E.zeta_theta(zn[:, i:i + 1, j:j + 1], [m], 3)[0, 0, 0]
+                                    / E.zeta_theta(zr[:, i:i + 1, j:j + 1], [m], 3)[0, 0, 0]
+                                    * special.legendre(l, m))
+                ref = 0.5 * (2 * l + 1) * quad(g, -1.0, 1.0, epsabs=1e-14, epsrel=1e-12)[0]
+                assert abs(zs[l, i, j] - ref) < 1e-10 * max(1.0, np.abs(zs).max())
