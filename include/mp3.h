@@ -291,6 +291,24 @@ int mp3_reduced_3pcf(mp3_plan_t plan, const void* delta, const double* zeta, int
                      int32_t nth, double* zeta_theta, double* q, void* workspace, size_t workspace_bytes,
                      void* stream);
 
+/* mp3_zeta_value_and_grad for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation, arguments and results, with the scratch
+ * memory taken from a fixed device array inside the library instead of a
+ * caller's workspace.  Each GPU the library runs on holds its own copy of
+ * that array (mp3_static_scratch_bytes() bytes, 64 MiB) until the process
+ * ends.  A call whose mp3_workspace_size exceeds it returns MP3_EWORKSPACE
+ * (nothing launched).  The call itself allocates nothing.  Every call on one
+ * GPU uses that GPU's one copy, which keeps the last call's contents: calls
+ * that overlap on one GPU (two streams, two threads) race and must be
+ * serialised by the caller.  The plan's device must be current. */
+int mp3_zeta_value_and_grad_static(mp3_plan_t plan, const void* delta, const double* dzeta, double* zeta,
+                                   void* ddelta, const float* pos, const float* w, const int64_t* np_off, void* dw,
+                                   void* stream);
+
+/* Bytes of the static scratch array of mp3_zeta_value_and_grad_static. */
+size_t mp3_static_scratch_bytes(void);
+
 /* Edge-corrected estimator with a random catalogue (Sec. 3, Eq. SSestimator):
  * zeta = (D - R)^3 / R^3, D - R reconstructed from the differences of the
  * two catalogues' basis coefficients.  Three steps, each on the device:

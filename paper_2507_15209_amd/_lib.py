@@ -35,7 +35,7 @@ EXPORTS = (
     "mp3_status_string", "mp3_last_error", "mp3_profile", "mp3_profile_read",
     "mp3_tune_set", "mp3_tune_get", "mp3_zeta_value_and_grad", "mp3_xi", "mp3_xi_multipoles", "mp3_reduced_3pcf",
     "mp3_ss_fields", "mp3_ss_multipoles",
-    "mp3_sph_bessel", "mp3_window_table",
+    "mp3_sph_bessel", "mp3_window_table", "mp3_zeta_value_and_grad_static", "mp3_static_scratch_bytes",
 )
 PASSES = ("dft", "filter", "x", "z_nodal", "z_adjoint", "adjoint", "deposit", "z_store", "gather", "gamma",
           "scatter", "z_fused")
@@ -105,13 +105,16 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.mp3_reduced_3pcf.argtypes = [vp, vp, vp, i32, ctypes.POINTER(ctypes.c_double), i32, vp, vp, vp, sz, vp]
     lib.mp3_sph_bessel.argtypes = [i32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
     lib.mp3_window_table.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(ctypes.c_double), sz]
+    lib.mp3_zeta_value_and_grad_static.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i64), vp, vp]
+    lib.mp3_static_scratch_bytes.argtypes = []
     lib.mp3_status_string.argtypes = [ctypes.c_int]
     lib.mp3_status_string.restype = ctypes.c_char_p
     lib.mp3_last_error.argtypes = []
     lib.mp3_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("mp3_status_string", "mp3_last_error"):
+        if name not in ("mp3_status_string", "mp3_last_error", "mp3_static_scratch_bytes"):
             getattr(lib, name).restype = ctypes.c_int
+    lib.mp3_static_scratch_bytes.restype = sz
     _lib = lib
     return lib
 
