@@ -375,14 +375,19 @@ enum mp3_tune_knob {
                                  (never more than there are tiles)                               */
   MP3_TUNE_FUSED_WAVES = 5,   /* waves per workgroup of the one-sweep (value and gradient) z
                                  pass: 0 = the fewest whole waves that hold one round of every
-                                 bin's columns (default), else 1 .. 8, raised to what n needs
-                                 (one thread per z point)                                        */
-  MP3_NTUNE = 6
+                                 bin's columns, else 1 .. 8 (default 4), raised to what n
+                                 needs (one thread per z point)                                  */
+  MP3_TUNE_ITEM_GROUP = 6,    /* (l, m) items per launch of the nodal adjoint passes (window,
+                                 x and z passes of mp3_zeta_backward and the one sweep of
+                                 mp3_zeta_value_and_grad): 0 = as many as fit 1 GiB of fields
+                                 (default), else 1 .. 1024, capped at (lmax+1)(lmax+2)/2     */
+  MP3_NTUNE = 7
 };
 
 /* Set a knob.  Out-of-range values return MP3_EINVAL and leave the knob as
  * it was.  The workspace size depends on MP3_TUNE_ZPASS_WGS,
- * MP3_TUNE_CONTRACT_WGS and MP3_TUNE_DEPOSIT_TILE: query mp3_workspace_size
+ * MP3_TUNE_CONTRACT_WGS, MP3_TUNE_DEPOSIT_TILE and MP3_TUNE_ITEM_GROUP (the
+ * fields of every item of a group are held at once): query mp3_workspace_size
  * again after changing them.  Not to be called while work of the plan is in
  * flight on another thread. */
 int mp3_tune_set(mp3_plan_t plan, int knob, int32_t value);

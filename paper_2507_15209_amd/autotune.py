@@ -27,6 +27,7 @@ CANDIDATES = {
     "zpass_wgs": (1024, 2048, 4096, 8192, 16384),
     "contract_wgs": (1024, 2048, 4096, 8192, 16384),
     "fused_waves": (0, 4, 8),
+    "item_group": (0, 1, 2, 4, 8, 16),
 }
 
 
@@ -141,7 +142,7 @@ def autotune(plan, delta, pos=None, w=None, np_off=None, dzeta=None, backward: b
 
         knobs = ["fft_x_plan", "zpass_wgs"]
         if do_bwd and plan.summation == "nodal":
-            knobs.append("fused_waves")
+            knobs += ["fused_waves", "item_group"]
         if plan.summation != "nodal":
             knobs.append("contract_wgs")
         for k in knobs:

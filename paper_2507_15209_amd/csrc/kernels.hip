@@ -383,8 +383,8 @@ __global__ void __launch_bounds__((contig_pencils<N, T>() * Fft<N>::TPC)) k_fft_
 template <int N, typename T>
 __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_filter_y(const c2<T>* dhat, c2<T>* fields,
                                                                          const T* jtab, int nq2, int nbins, int nbp,
-                                                                         int l, int m, double norm, double scale,
-                                                                         const c2<T>* tw, YlmRec yr, const T* phi) {
+                                                                         const ItemRec* items, int item0, int batch,
+                                                                         double scale, const c2<T>* tw, const T* phi) {
   using F = Fft<N, VB>;
   constexpr int ZC = zc_of<T>();
   constexpr int G = tiles_per_wg<N, T, VB>();
@@ -401,7 +401,10 @@ __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_filter_y(cons
   const bool active = tile < N * chunks;
   const int qx = active ? tile / chunks : 0;
   const int qz = (active ? tile % chunks : 0) * ZC + cc;
-  const long long mock = blockIdx.y;
+  // grid.y runs over (item of the group, mock)
+  const long long mock = blockIdx.y % batch;
+  const int gi = blockIdx.y / batch;
+  const ItemRec& it = items[item0 + gi];
   stage_twiddles<N, T>(tw, tws);
   __syncthreads();
   c2<T> v0[RMAX];
@@ -410,15 +413,15 @@ __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_filter_y(cons
   for (int r = 0; r < RMAX; ++r) {
     const int qy = F::in_index(j, r);
     const c2<T> d = active ? nt_load(&dhat[mock * N3 + ((long long)qx * N + qy) * N + qz]) : mk<T>(0, 0);
-    const c2<T> f = window_angular<T>(qx, qy, qz, N, l, m, norm, scale, yr, q2[r], phi);
+    const c2<T> f = window_angular<T>(qx, qy, qz, N, it.l, it.m, it.norm, scale, it.yr, q2[r], phi);
     v0[r] = cmul<T>(d, f);
   }
   // radial window of this thread's elements, four bins per load, one quad ahead
-  const T* jl = jtab + (long long)l * nq2 * nbp;
+  const T* jl = jtab + (long long)it.l * nq2 * nbp;
   T jq[RMAX][4];
 #pragma unroll
   for (int r = 0; r < RMAX; ++r) load_quad<T>(jl + (long long)q2[r] * nbp, jq[r]);
-  c2<T>* fbase = fields + mock * nbins * N3 + (long long)qx * N * N + qz;
+  c2<T>* fbase = fields + ((long long)gi * batch + mock) * nbins * N3 + (long long)qx * N * N + qz;
   for (int bq = 0; bq < nbins; bq += 4) {
     T jn[RMAX][4];
     if (bq + 4 < nbins) {
@@ -1239,9 +1242,14 @@ struct GammaLds {
 
 // 1024 threads: the per-node phases are short, and one workgroup fills the
 // CU's LDS, so the waves of that one workgroup are what hides LDS latency
+// Bins: the workgroup contracts nbins local bins, local bin b < na being
+// field bin a0 + b and the rest field bins c0 + (b - na) of the nbt stored
+// bins (all of them with a0 = 0, na = nbins = nbt), so that plans with more
+// bins than the tile's LDS holds take them in pairs of chunks.
 template <typename T, bool MF, bool SPLIT = false, bool QUAD = false>
 __global__ void __launch_bounds__(1024) k_gamma_contract(const c2<T>* fields, const T* delta, int n, int nbins,
-                                                         GammaQuad gq, double* partials) {
+                                                         GammaQuad gq, double* partials, int nbt, int a0, int na,
+                                                         int c0) {
   extern __shared__ __align__(16) char smem[];
   const GammaLds<T> L(nbins);
   c2<T>* C = reinterpret_cast<c2<T>*>(smem + L.C);
@@ -1255,7 +1263,7 @@ __global__ void __launch_bounds__(1024) k_gamma_contract(const c2<T>* fields, co
   const int tid = threadIdx.x, nt = blockDim.x;
   const long long mock = blockIdx.y;
   const long long n3 = (long long)n * n * n;
-  const c2<T>* fm = fields + mock * n3 * nbins;
+  const c2<T>* fm = fields + mock * n3 * nbt;
   const T* dm = delta + mock * n3;
   const int td = n / GT;
   const long long ntiles = (long long)td * td * td;
@@ -1269,7 +1277,7 @@ __global__ void __launch_bounds__(1024) k_gamma_contract(const c2<T>* fields, co
       const int b = e % nbins, c = e / nbins;
       const int i = c / (GC * GC), j = (c / GC) % GC, k = c % GC;
       const long long cell = ((long long)wrapi(x0 + i, n) * n + wrapi(y0 + j, n)) * n + wrapi(z0 + k, n);
-      C[e] = fm[cell * nbins + b];
+      C[e] = fm[cell * nbt + (b < na ? a0 + b : c0 + b - na)];
     }
     for (int c = tid; c < GC * GC * GC; c += nt) {
       const int i = c / (GC * GC), j = (c / GC) % GC, k = c % GC;
@@ -1407,6 +1415,23 @@ __global__ void k_fbar_subtract(const double* P, const T* jtab, int nq2, int nbp
 }
 
 // zeta[j][l][e] += scale * sum_w partials[j][w][e]; one block per (e, j),
+// the partials of a group of items ([item][mock][wg][nb2]) into zeta at each item's l, times its m weight
+__global__ void k_reduce_items(const double* partials, int nwg, int nb2, double* zeta, int lmax, double scale,
+                               const ItemRec* items, int item0, int nitems, int batch) {
+  // one block per (entry, mock) walks the group's items in order: items that
+  // share an l add into the same entry, so no two blocks write one entry
+  __shared__ double sh[32];
+  const int e = blockIdx.x, j = blockIdx.y;
+  for (int g = 0; g < nitems; ++g) {
+    const ItemRec& it = items[item0 + g];
+    const double* p = partials + ((long long)g * batch + j) * nwg * nb2 + e;
+    double s = 0.0;
+    for (int w = threadIdx.x; w < nwg; w += blockDim.x) s += p[(long long)w * nb2];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) zeta[((long long)j * (lmax + 1) + it.l) * nb2 + e] += scale * it.wm * s;
+  }
+}
+
 // fixed summation order (deterministic)
 __global__ void k_reduce_partials(const double* partials, int nwg, int nb2, double* zeta, int l, int lmax, double scale) {
   __shared__ double sh[32];
@@ -1431,153 +1456,190 @@ __global__ void k_reduce_partials(const double* partials, int nwg, int nb2, doub
 // fields when dJ/dzeta is fixed before the forward (J linear in zeta).
 // ---------------------------------------------------------------------------
 template <int N, typename T, int MAXNB, bool FUSED = false, bool MF = false, bool QUAD = false>
-__global__ void __launch_bounds__(512) k_zpass_adjoint(c2<T>* fields, const T* delta, const T* __restrict__ lam_s,
-                                                        T* direct, int nbins, T wm, int ppw, const c2<T>* tw,
-                                                        double* partials) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FUSED && MF ? 3 : 1)))
+k_zpass_adjoint(c2<T>* fields, const T* delta, const T* __restrict__ lam_s, T* direct, int nbins, int ppw,
+                const c2<T>* tw, double* partials, const ItemRec* items, int item0, int nitems, int batch, int nwg,
+                int* counter) {
   using F = Fft<N, VZA<T>>;
   constexpr int RS = zrow<N>();
   constexpr int NBP = (MAXNB + 3) / 4 * 4;
   constexpr long long N3 = (long long)N * N * N;
   extern __shared__ __align__(16) char smem[];
+  __shared__ int s_unit;
   c2<T>* A = reinterpret_cast<c2<T>*>(smem);
   c2<T>* tws = A + nbins * RS;
   T* lam = reinterpret_cast<T*>(tws + N);             // [nbins][NBP], zero padded
   T* dl = lam + nbins * NBP;                          // FUSED: delta of the pencil
   const int tid = threadIdx.x;
-  const long long mock = blockIdx.y;
-  stage_twiddles<N, T>(tw, tws);
-  for (int t = tid; t < nbins * NBP; t += blockDim.x) {
-    const int bp = t / NBP, b = t % NBP;
-    lam[t] = b < nbins ? lam_s[mock * nbins * nbins + bp * nbins + b] : (T)0;
-  }
-  __syncthreads();
-  Contractor<T, MF, false, QUAD> ctr;
-  if constexpr (FUSED) ctr.init(nbins);
   const int nbc = blockDim.x / F::TPC;
-  const int p0 = blockIdx.x * ppw;
-  const int p1 = min(p0 + ppw, N * N);
-  c2<T>* fmock = fields + mock * nbins * N3;
-  const T* dmock = delta + mock * N3;
-  T* rmock = direct + mock * N3;
-  c2<T> vpre[prefetch_rounds<N, VZA<T>>()][F::RMAX];
-  T dpre[DPRE], rpre[DPRE];
-  if (p0 < p1) {
-    prefetch_pencil<N, T, VZA<T>>(fmock + (long long)p0 * N, N3, nbins, vpre);
-    prefetch_delta<N, T>(dmock + (long long)p0 * N, dpre);
-    prefetch_delta<N, T>(rmock + (long long)p0 * N, rpre);
-  }
-  for (int p = p0; p < p1; ++p) {
-    c2<T>* fbase = fmock + (long long)p * N;
-    // this pencil's data moves to vcur; the next pencil's loads are issued
-    // before the transform so they stay in flight for the whole iteration
-    c2<T> vcur[prefetch_rounds<N, VZA<T>>()][F::RMAX];
-#pragma unroll
-    for (int q = 0; q < prefetch_rounds<N, VZA<T>>(); ++q)
-#pragma unroll
-      for (int r = 0; r < F::RMAX; ++r) vcur[q][r] = vpre[q][r];
-    T dcur[DPRE], rcur[DPRE];
-#pragma unroll
-    for (int k = 0; k < DPRE; ++k) {
-      dcur[k] = dpre[k];
-      rcur[k] = rpre[k];
+  const int nb2 = nbins * nbins;
+  // several items of a group update the same direct term: atomically then
+  const bool shared_direct = nitems > 1;
+  // the next pencil's loads are issued at the top of each iteration, so they
+  // stay in flight for the whole of it; the matrix-core one sweep instead
+  // loads each pencil when it starts (no registers held across the
+  // iteration: three workgroups per CU hide the latency instead)
+  constexpr bool NO_PREFETCH = FUSED && MF;
+  // persistent: work units (item of the group, mock, chunk of ppw pencils) from an atomic counter
+  const int total = nitems * batch * nwg;
+  for (;;) {
+    __syncthreads();                          // the previous unit is done with the LDS
+    if (tid == 0) s_unit = atomicAdd(counter, 1);
+    __syncthreads();
+    const int unit = s_unit;
+    if (unit >= total) break;
+    const int g = unit / (batch * nwg);
+    const int mock = (unit / nwg) % batch;
+    const int chunk = unit % nwg;
+    const ItemRec& it = items[item0 + g];
+    const T wm = (T)it.wm;
+    stage_twiddles<N, T>(tw, tws);
+    const T* ls = lam_s + ((long long)it.l * batch + mock) * nb2;
+    for (int t = tid; t < nbins * NBP; t += blockDim.x) {
+      const int bp = t / NBP, b = t % NBP;
+      lam[t] = b < nbins ? ls[bp * nbins + b] : (T)0;
     }
-    if (p + 1 < p1) {
-      prefetch_pencil<N, T, VZA<T>>(fbase + N, N3, nbins, vpre);
-      prefetch_delta<N, T>(dmock + (long long)(p + 1) * N, dpre);
-      prefetch_delta<N, T>(rmock + (long long)(p + 1) * N, rpre);
+    __syncthreads();
+    Contractor<T, MF, false, QUAD> ctr;
+    if constexpr (FUSED) ctr.init(nbins);
+    const int p0 = chunk * ppw;
+    const int p1 = min(p0 + ppw, N * N);
+    c2<T>* fmock = fields + ((long long)g * batch + mock) * nbins * N3;
+    const T* dmock = delta + (long long)mock * N3;
+    T* rmock = direct + (long long)mock * N3;
+    c2<T> vpre[prefetch_rounds<N, VZA<T>>()][F::RMAX];
+    T dpre[DPRE], rpre[DPRE];
+    if (!NO_PREFETCH && p0 < p1) {
+      prefetch_pencil<N, T, VZA<T>>(fmock + (long long)p0 * N, N3, nbins, vpre);
+      prefetch_delta<N, T>(dmock + (long long)p0 * N, dpre);
+      prefetch_delta<N, T>(rmock + (long long)p0 * N, rpre);
     }
-    if constexpr (FUSED) {
+    for (int p = p0; p < p1; ++p) {
+      c2<T>* fbase = fmock + (long long)p * N;
+      c2<T> vcur[prefetch_rounds<N, VZA<T>>()][F::RMAX];
+      T dcur[DPRE], rcur[DPRE];
+      if constexpr (NO_PREFETCH) {
+        prefetch_delta<N, T>(dmock + (long long)p * N, dcur);
+        prefetch_delta<N, T>(rmock + (long long)p * N, rcur);
+      } else {
+#pragma unroll
+        for (int q = 0; q < prefetch_rounds<N, VZA<T>>(); ++q)
+#pragma unroll
+          for (int r = 0; r < F::RMAX; ++r) vcur[q][r] = vpre[q][r];
+#pragma unroll
+        for (int k = 0; k < DPRE; ++k) {
+          dcur[k] = dpre[k];
+          rcur[k] = rpre[k];
+        }
+      }
+      if (!NO_PREFETCH && p + 1 < p1) {
+        prefetch_pencil<N, T, VZA<T>>(fbase + N, N3, nbins, vpre);
+        prefetch_delta<N, T>(dmock + (long long)(p + 1) * N, dpre);
+        prefetch_delta<N, T>(rmock + (long long)(p + 1) * N, rpre);
+      }
+      if constexpr (FUSED) {
+#pragma unroll
+        for (int k = 0; k < DPRE; ++k) {
+          const int z = tid + k * blockDim.x;
+          if (z < N) dl[z] = dcur[k];
+        }
+      }
+      if constexpr (NO_PREFETCH) {
+        const int rounds = pencil_rounds<N, VZA<T>>(nbins);
+        for (int rr = 0; rr < rounds; ++rr) {
+          c2<T> v[F::RMAX];
+          load_pencil_round<N, T, VZA<T>>(fbase, N3, nbins, rr, v);
+          transform_round<N, T, VZA<T>>(nbins, rr, v, A, tws);
+        }
+      } else {
+        transform_pencil_bins<N, T, VZA<T>>(fbase, N3, nbins, A, tws, vcur);
+      }
+      __syncthreads();
+      if constexpr (FUSED) {
+        // contraction of the fields before the sources overwrite them.  On the
+        // matrix cores each wave contracts the 64 z columns whose sources its
+        // own threads form next, so no barrier separates the two steps.
+        if constexpr (MF) {
+          const int z0 = 64 * (tid >> 6);
+          if (z0 < N) ctr.add_range(A, dl, nbins, RS, z0, z0 + 64 < N ? z0 + 64 : N);
+        } else {
+          ctr.add(A, dl, nbins, RS, N);
+          __syncthreads();
+        }
+      }
 #pragma unroll
       for (int k = 0; k < DPRE; ++k) {
         const int z = tid + k * blockDim.x;
-        if (z < N) dl[z] = dcur[k];
-      }
-    }
-    transform_pencil_bins<N, T, VZA<T>>(fbase, N3, nbins, A, tws, vcur);
-    __syncthreads();
-    if constexpr (FUSED) {
-      // contraction of the fields before the sources overwrite them.  On the
-      // matrix cores each wave contracts the 64 z columns whose sources its
-      // own threads form next, so no barrier separates the two steps.
-      if constexpr (MF) {
-        const int z0 = 64 * (tid >> 6);
-        if (z0 < N) ctr.add_range(A, dl, nbins, RS, z0, z0 + 64 < N ? z0 + 64 : N);
-      } else {
-        ctr.add(A, dl, nbins, RS, N);
-        __syncthreads();
-      }
-    }
+        if (z >= N) continue;
+        const int zp = lds_pos<true>(z);
+        c2<T> u[MAXNB];
 #pragma unroll
-    for (int k = 0; k < DPRE; ++k) {
-      const int z = tid + k * blockDim.x;
-      if (z >= N) continue;
-      const int zp = lds_pos<true>(z);
-      c2<T> u[MAXNB];
+        for (int b = 0; b < MAXNB; ++b) u[b] = mk<T>(0, 0);
+        for (int bp = 0; bp < nbins; ++bp) {
+          const c2<T> a = A[bp * RS + zp];
+          const T* lrow = lam + bp * NBP;            // lam_s is symmetric: row bp = column bp
 #pragma unroll
-      for (int b = 0; b < MAXNB; ++b) u[b] = mk<T>(0, 0);
-      for (int bp = 0; bp < nbins; ++bp) {
-        const c2<T> a = A[bp * RS + zp];
-        const T* lrow = lam + bp * NBP;            // lam_s is symmetric: row bp = column bp
+          for (int bq = 0; bq < NBP; bq += 4) {
+            T lq[4];
+            load_quad<T>(lrow + bq, lq);             // LDS broadcast
 #pragma unroll
-        for (int bq = 0; bq < NBP; bq += 4) {
-          T lq[4];
-          load_quad<T>(lrow + bq, lq);             // LDS broadcast
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            if (bq + k < MAXNB) {
-              u[bq + k].x += lq[k] * a.x;
-              u[bq + k].y -= lq[k] * a.y;
+            for (int k = 0; k < 4; ++k) {
+              if (bq + k < MAXNB) {
+                u[bq + k].x += lq[k] * a.x;
+                u[bq + k].y -= lq[k] * a.y;
+              }
             }
           }
         }
-      }
-      const T d = dcur[k];
-      T dir = 0;
+        const T d = dcur[k];
+        T dir = 0;
 #pragma unroll
-      for (int b = 0; b < MAXNB; ++b) {
-        if (b < nbins) {
-          const c2<T> a = A[b * RS + zp];
-          dir += a.x * u[b].x - a.y * u[b].y;
-          A[b * RS + zp] = mk<T>(d * u[b].x, d * u[b].y);
+        for (int b = 0; b < MAXNB; ++b) {
+          if (b < nbins) {
+            const c2<T> a = A[b * RS + zp];
+            dir += a.x * u[b].x - a.y * u[b].y;
+            A[b * RS + zp] = mk<T>(d * u[b].x, d * u[b].y);
+          }
         }
-      }
-      rmock[(long long)p * N + z] = rcur[k] + wm * dir;
-    }
-    __syncthreads();
-    // adjoint z-transform of every c_b, read from LDS, written over the field
-    const int rounds = (nbins + nbc - 1) / nbc;
-    for (int rr = 0; rr < rounds; ++rr) {
-      int j = tid % F::TPC;
-      asm volatile("" : "+v"(j));
-      const int b = rr * nbc + tid / F::TPC;
-      const bool active = b < nbins;
-      c2<T> v[F::RMAX];
-      if (active) {
-#pragma unroll
-        for (int r = 0; r < F::RMAX; ++r) v[r] = A[b * RS + lds_pos<true>(F::in_index(j, r))];
+        if (shared_direct) atomicAdd(&rmock[(long long)p * N + z], wm * dir);
+        else rmock[(long long)p * N + z] = rcur[k] + wm * dir;
       }
       __syncthreads();
-      fft_column<N, +1, T, true, VZA<T>, 64 % F::TPC == 0>(v, A + (active ? b : 0) * RS, 1, j, tws, active);
-      if (active) {
+      // adjoint z-transform of every c_b, read from LDS, written over the field
+      const int rounds = (nbins + nbc - 1) / nbc;
+      for (int rr = 0; rr < rounds; ++rr) {
+        int j = tid % F::TPC;
+        asm volatile("" : "+v"(j));
+        const int b = rr * nbc + tid / F::TPC;
+        const bool active = b < nbins;
+        c2<T> v[F::RMAX];
+        if (active) {
 #pragma unroll
-        for (int e = 0; e < F::RMAX; ++e) fbase[b * N3 + F::out_index(j, e)] = v[e];
+          for (int r = 0; r < F::RMAX; ++r) v[r] = A[b * RS + lds_pos<true>(F::in_index(j, r))];
+        }
+        __syncthreads();
+        fft_column<N, +1, T, true, VZA<T>, 64 % F::TPC == 0>(v, A + (active ? b : 0) * RS, 1, j, tws, active);
+        if (active) {
+#pragma unroll
+          for (int e = 0; e < F::RMAX; ++e) fbase[b * N3 + F::out_index(j, e)] = v[e];
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
+    if constexpr (FUSED)
+      ctr.finish(reinterpret_cast<double*>(smem), partials + (((long long)g * batch + mock) * nwg + chunk) * nb2,
+                 nbins);
   }
-  if constexpr (FUSED)
-    ctr.finish(reinterpret_cast<double*>(smem), partials + ((long long)mock * gridDim.x + blockIdx.x) * nbins * nbins,
-               nbins);
 }
 
-// lam_s[j][b][b'] = (dzeta[j][l][b][b'] + dzeta[j][l][b'][b]) / 2 for one l
+// lam_s[l][j][b][b'] = (dzeta[j][l][b][b'] + dzeta[j][l][b'][b]) / 2 for every l (blockIdx.x = l)
 template <typename T>
-__global__ void k_lam_sym(const double* dzeta, T* lam_s, int nbins, int l, int lmax) {
-  const int j = blockIdx.y;
+__global__ void k_lam_sym(const double* dzeta, T* lam_s, int nbins, int lmax, int batch) {
+  const int j = blockIdx.y, l = blockIdx.x;
   const double* dz = dzeta + ((long long)j * (lmax + 1) + l) * nbins * nbins;
   for (int t = threadIdx.x; t < nbins * nbins; t += blockDim.x) {
     const int b = t / nbins, bp = t % nbins;
-    lam_s[(long long)j * nbins * nbins + t] = (T)(0.5 * (dz[b * nbins + bp] + dz[bp * nbins + b]));
+    lam_s[((long long)l * batch + j) * nbins * nbins + t] = (T)(0.5 * (dz[b * nbins + bp] + dz[bp * nbins + b]));
   }
 }
 
@@ -1588,8 +1650,9 @@ __global__ void k_lam_sym(const double* dzeta, T* lam_s, int nbins, int l, int l
 template <int N, typename T>
 __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_adjoint_y(const c2<T>* fields, c2<T>* G,
                                                                           const T* jtab, int nq2, int nbins, int nbp,
-                                                                          int l, int m, double norm, double scale,
-                                                                          const c2<T>* tw, YlmRec yr, const T* phi) {
+                                                                          const ItemRec* items, int item0, int nitems,
+                                                                          int batch, double scale, const c2<T>* tw,
+                                                                          const T* phi) {
   using F = Fft<N, VB>;
   constexpr int ZC = zc_of<T>();
   constexpr int GT = tiles_per_wg<N, T, VB>();
@@ -1612,38 +1675,42 @@ __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_adjoint_y(con
   c2<T> fac[RMAX], acc[RMAX];
   int q2[RMAX];
 #pragma unroll
-  for (int e = 0; e < RMAX; ++e) {
-    acc[e] = mk<T>(0, 0);
-    fac[e] = window_angular<T>(qx, F::out_index(j, e), qz, N, l, m, norm, scale, yr, q2[e], phi);
-  }
-  const T* jl = jtab + (long long)l * nq2 * nbp;
-  const c2<T>* src = fields + mock * nbins * N3 + (long long)qx * N * N + qz;
-  // next bin's column, one bin ahead
-  c2<T> vn[RMAX];
-  if (active) {
+  for (int e = 0; e < RMAX; ++e) acc[e] = mk<T>(0, 0);
+  // every item of the group adds into the same accumulator: one read-modify-write of G
+  for (int gi = 0; gi < nitems; ++gi) {
+    const ItemRec& it = items[item0 + gi];
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r) vn[r] = nt_load(&src[F::in_index(j, r) * N]);
-  }
-  for (int bq = 0; bq < nbins; bq += 4) {
-    T jq[RMAX][4];
+    for (int e = 0; e < RMAX; ++e)
+      fac[e] = window_angular<T>(qx, F::out_index(j, e), qz, N, it.l, it.m, it.norm, scale * it.wm, it.yr, q2[e], phi);
+    const T* jl = jtab + (long long)it.l * nq2 * nbp;
+    const c2<T>* src = fields + ((long long)gi * batch + mock) * nbins * N3 + (long long)qx * N * N + qz;
+    // next bin's column, one bin ahead
+    c2<T> vn[RMAX];
+    if (active) {
 #pragma unroll
-    for (int e = 0; e < RMAX; ++e) load_quad<T>(jl + (long long)q2[e] * nbp + bq, jq[e]);
+      for (int r = 0; r < RMAX; ++r) vn[r] = nt_load(&src[F::in_index(j, r) * N]);
+    }
+    for (int bq = 0; bq < nbins; bq += 4) {
+      T jq[RMAX][4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int b = bq + k;
-      if (b < nbins) {
-        c2<T> v[RMAX];
+      for (int e = 0; e < RMAX; ++e) load_quad<T>(jl + (long long)q2[e] * nbp + bq, jq[e]);
 #pragma unroll
-        for (int r = 0; r < RMAX; ++r) v[r] = vn[r];
-        if (b + 1 < nbins && active) {
+      for (int k = 0; k < 4; ++k) {
+        const int b = bq + k;
+        if (b < nbins) {
+          c2<T> v[RMAX];
 #pragma unroll
-          for (int r = 0; r < RMAX; ++r) vn[r] = nt_load(&src[(b + 1) * N3 + F::in_index(j, r) * N]);
+          for (int r = 0; r < RMAX; ++r) v[r] = vn[r];
+          if (b + 1 < nbins && active) {
+#pragma unroll
+            for (int r = 0; r < RMAX; ++r) vn[r] = nt_load(&src[(b + 1) * N3 + F::in_index(j, r) * N]);
+          }
+          int jj = j;
+          asm volatile("" : "+v"(jj));
+          fft_column<N, +1, T, false, VB>(v, lds + g * N * ZC + cc, ZC, jj, tws, active);
+#pragma unroll
+          for (int e = 0; e < RMAX; ++e) acc[e] = cadd<T>(acc[e], cmul<T>(v[e], cscale<T>(fac[e], jq[e][k])));
         }
-        int jj = j;
-        asm volatile("" : "+v"(jj));
-        fft_column<N, +1, T, false, VB>(v, lds + g * N * ZC + cc, ZC, jj, tws, active);
-#pragma unroll
-        for (int e = 0; e < RMAX; ++e) acc[e] = cadd<T>(acc[e], cmul<T>(v[e], cscale<T>(fac[e], jq[e][k])));
       }
     }
   }
@@ -2256,6 +2323,338 @@ __global__ void __launch_bounds__(sizeof(T) == 4 ? 1024 : 512) k_gamma_adjoint(c
   }
 }
 
+// ---------------------------------------------------------------------------
+// grid-Gamma adjoint by bin chunks (plans whose tiles of every bin do not fit
+// the LDS): v_b = sum_b' lam_s[b][b'] conj(atilde_b') is the conjugate of the
+// interpolant of U_b = sum_b' lam_s[b][b'] a_b' (the interpolation is real
+// and linear), so with U mixed on the grid first, each bin's sources
+//   c_b(x) = sum_q B3(u_q - x) w_q delta_B(u_q) conj(U~_b(u_q))
+// and each bin's share of the primary term
+//   F = sum_b Re(atilde_b conj(U~_b))
+// need only that bin's a and U: a tile takes the bins in chunks.
+// ---------------------------------------------------------------------------
+// U[mock][x][b] = sum_b' lam_s[mock][b][b'] F[mock][x][b'] (bin-interleaved)
+template <typename T>
+__global__ void k_bin_mix(const c2<T>* F, const T* lam_s, c2<T>* U, long long n3, int nbins) {
+  extern __shared__ __align__(16) char smem_mix[];
+  T* lam = reinterpret_cast<T*>(smem_mix);
+  const long long mock = blockIdx.y;
+  const int nb2 = nbins * nbins;
+  for (int t = threadIdx.x; t < nb2; t += blockDim.x) lam[t] = lam_s[mock * nb2 + t];
+  __syncthreads();
+  const c2<T>* fm = F + mock * n3 * nbins;
+  c2<T>* um = U + mock * n3 * nbins;
+  const long long total = n3 * nbins;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    const long long x = e / nbins;
+    const int b = (int)(e - x * nbins);
+    const c2<T>* row = fm + x * nbins;
+    const T* lrow = lam + b * nbins;
+    T re = 0, im = 0;
+    for (int bp = 0; bp < nbins; ++bp) {
+      const c2<T> a = row[bp];
+      re += lrow[bp] * a.x;
+      im += lrow[bp] * a.y;
+    }
+    um[e] = mk<T>(re, im);
+  }
+}
+
+template <typename T>
+struct GammaBinsLds {
+  size_t C, Cu, Ct, D, Dt, P, Pu, Pt, Pd, Pdt, Q, Qu, Qt, Qd, Qdt, A, Au, W, Wq, Fn, total;
+  __host__ __device__ GammaBinsLds(int nbc) {
+    size_t o = 0;
+    auto take = [&](size_t b) { size_t r = o; o = (o + b + 15) & ~(size_t)15; return r; };
+    const size_t c = sizeof(c2<T>), r = sizeof(T);
+    const size_t nc = (size_t)GC * GC * GC;
+    C = take(nc * nbc * c);
+    Cu = take(nc * nbc * c);
+    Ct = take(nc * nbc * c);
+    D = take(nc * r);
+    Dt = take(nc * r);
+    P = take((size_t)GC * GC * nbc * c);
+    Pu = take((size_t)GC * GC * nbc * c);
+    Pt = take((size_t)GC * GC * nbc * c);
+    Pd = take((size_t)GC * GC * r);
+    Pdt = take((size_t)GC * GC * r);
+    Q = take((size_t)AGY * GC * nbc * c);
+    Qu = take((size_t)AGY * GC * nbc * c);
+    Qt = take((size_t)AGY * GC * nbc * c);
+    Qd = take((size_t)AGY * GC * r);
+    Qdt = take((size_t)AGY * GC * r);
+    A = take((size_t)nbc * AGRS * c);
+    Au = take((size_t)nbc * AGRS * c);
+    W = take((size_t)AGK * r);
+    Wq = take((size_t)AGK * r);
+    Fn = take((size_t)AGK * r);
+    total = o;
+  }
+};
+
+// bins b0 .. b0 + nbc - 1 of nbt; adds the sources into cout (zeroed by the
+// caller) and wm times this chunk's share of the primary term into direct
+template <typename T>
+__global__ void __launch_bounds__(512) k_gamma_adjoint_bins(const c2<T>* fields, const c2<T>* U, const T* delta,
+                                                            int n, int nbt, int b0, int nbc, GammaQuad gq, T wm,
+                                                            c2<T>* cout, T* direct) {
+  extern __shared__ __align__(16) char smem[];
+  const GammaBinsLds<T> L(nbc);
+  c2<T>* C = reinterpret_cast<c2<T>*>(smem + L.C);
+  c2<T>* Cu = reinterpret_cast<c2<T>*>(smem + L.Cu);
+  c2<T>* Ct = reinterpret_cast<c2<T>*>(smem + L.Ct);
+  T* D = reinterpret_cast<T*>(smem + L.D);
+  T* Dt = reinterpret_cast<T*>(smem + L.Dt);
+  c2<T>* P = reinterpret_cast<c2<T>*>(smem + L.P);
+  c2<T>* Pu = reinterpret_cast<c2<T>*>(smem + L.Pu);
+  c2<T>* Pt = reinterpret_cast<c2<T>*>(smem + L.Pt);
+  T* Pd = reinterpret_cast<T*>(smem + L.Pd);
+  T* Pdt = reinterpret_cast<T*>(smem + L.Pdt);
+  c2<T>* Q = reinterpret_cast<c2<T>*>(smem + L.Q);
+  c2<T>* Qu = reinterpret_cast<c2<T>*>(smem + L.Qu);
+  c2<T>* Qt = reinterpret_cast<c2<T>*>(smem + L.Qt);
+  T* Qd = reinterpret_cast<T*>(smem + L.Qd);
+  T* Qdt = reinterpret_cast<T*>(smem + L.Qdt);
+  c2<T>* A = reinterpret_cast<c2<T>*>(smem + L.A);
+  c2<T>* Au = reinterpret_cast<c2<T>*>(smem + L.Au);
+  T* W = reinterpret_cast<T*>(smem + L.W);
+  T* Wq = reinterpret_cast<T*>(smem + L.Wq);
+  T* Fn = reinterpret_cast<T*>(smem + L.Fn);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const long long mock = blockIdx.y;
+  const long long n3 = (long long)n * n * n;
+  const c2<T>* fm = fields + mock * n3 * nbt;
+  const c2<T>* um = U + mock * n3 * nbt;
+  const T* dm = delta + mock * n3;
+  c2<T>* cm = cout + mock * nbt * n3;
+  T* rm = direct + mock * n3;
+  const int td = n / GT;
+  const long long ntiles = (long long)td * td * td;
+  constexpr int NC = GC * GC * GC;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int tx = (int)(tile / ((long long)td * td)), ty = (int)((tile / td) % td), tz = (int)(tile % td);
+    const int x0 = tx * GT - 1, y0 = ty * GT - 1, z0 = tz * GT - 1;
+    __syncthreads();
+    for (int e = tid; e < NC * nbc; e += nt) {
+      const int b = e % nbc, c = e / nbc;
+      const int i = c / (GC * GC), j = (c / GC) % GC, k = c % GC;
+      const long long cell = ((long long)wrapi(x0 + i, n) * n + wrapi(y0 + j, n)) * n + wrapi(z0 + k, n);
+      C[e] = fm[cell * nbt + b0 + b];
+      Cu[e] = um[cell * nbt + b0 + b];
+      Ct[e] = mk<T>(0, 0);
+    }
+    for (int c = tid; c < NC; c += nt) {
+      const int i = c / (GC * GC), j = (c / GC) % GC, k = c % GC;
+      D[c] = dm[((long long)wrapi(x0 + i, n) * n + wrapi(y0 + j, n)) * n + wrapi(z0 + k, n)];
+      Dt[c] = (T)0;
+    }
+    for (int xn = 0; xn < GN; ++xn) {
+      const int cx = xn / 5, sx = xn % 5;
+      __syncthreads();
+      // x interpolation of a, U and delta; clear the transposed accumulators
+      for (int e = tid; e < GC * GC * nbc; e += nt) {
+        const int b = e % nbc, jk = e / nbc;
+        c2<T> acc = mk<T>(0, 0), accu = mk<T>(0, 0);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int src = ((cx + t) * GC * GC + jk) * nbc + b;
+          const T m = gq_m<T>(gq, sx, t);
+          const c2<T> v = C[src], u = Cu[src];
+          acc.x += m * v.x;
+          acc.y += m * v.y;
+          accu.x += m * u.x;
+          accu.y += m * u.y;
+        }
+        P[e] = acc;
+        Pu[e] = accu;
+        Pt[e] = mk<T>(0, 0);
+      }
+      for (int jk = tid; jk < GC * GC; jk += nt) {
+        T acc = 0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc += gq_m<T>(gq, sx, t) * D[(cx + t) * GC * GC + jk];
+        Pd[jk] = acc;
+        Pdt[jk] = (T)0;
+      }
+      for (int cy = 0; cy < GT; ++cy) {
+        __syncthreads();
+        // y interpolation for the 5 y nodes of cell cy
+        for (int e = tid; e < AGY * GC * nbc; e += nt) {
+          const int b = e % nbc, yk = e / nbc;
+          const int yh = yk / GC, k = yk % GC;
+          c2<T> acc = mk<T>(0, 0), accu = mk<T>(0, 0);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int src = ((cy + t) * GC + k) * nbc + b;
+            const T m = gq_m<T>(gq, yh, t);
+            const c2<T> v = P[src], u = Pu[src];
+            acc.x += m * v.x;
+            acc.y += m * v.y;
+            accu.x += m * u.x;
+            accu.y += m * u.y;
+          }
+          Q[e] = acc;
+          Qu[e] = accu;
+        }
+        for (int yk = tid; yk < AGY * GC; yk += nt) {
+          const int yh = yk / GC, k = yk % GC;
+          T acc = 0;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc += gq_m<T>(gq, yh, t) * Pd[(cy + t) * GC + k];
+          Qd[yk] = acc;
+        }
+        __syncthreads();
+        // z interpolation to the 100 nodes of this (x node, y cell) slice
+        for (int e = tid; e < AGK * nbc; e += nt) {
+          const int b = e % nbc, node = e / nbc;
+          const int yh = node / GN, zn = node % GN, cz = zn / 5, sz = zn % 5;
+          c2<T> acc = mk<T>(0, 0), accu = mk<T>(0, 0);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int src = (yh * GC + cz + t) * nbc + b;
+            const T m = gq_m<T>(gq, sz, t);
+            const c2<T> v = Q[src], u = Qu[src];
+            acc.x += m * v.x;
+            acc.y += m * v.y;
+            accu.x += m * u.x;
+            accu.y += m * u.y;
+          }
+          A[b * AGRS + lds_pos<true>(node)] = acc;
+          Au[b * AGRS + lds_pos<true>(node)] = accu;
+        }
+        for (int node = tid; node < AGK; node += nt) {
+          const int yh = node / GN, zn = node % GN, cz = zn / 5, sz = zn % 5;
+          T acc = 0;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc += gq_m<T>(gq, sz, t) * Qd[yh * GC + cz + t];
+          const T wq = gq_w<T>(gq, sx) * gq_w<T>(gq, yh) * gq_w<T>(gq, sz);
+          W[node] = acc * wq;
+          Wq[node] = wq;
+        }
+        __syncthreads();
+        // per node: F (this chunk's bins) and the sources S_b = w delta_B conj(U~_b), over A
+        for (int node = tid; node < AGK; node += nt) {
+          const int zp = lds_pos<true>(node);
+          const T wv = W[node];
+          T f = 0;
+          for (int b = 0; b < nbc; ++b) {
+            const c2<T> a = A[b * AGRS + zp], u = Au[b * AGRS + zp];
+            f += a.x * u.x + a.y * u.y;
+            A[b * AGRS + zp] = mk<T>(wv * u.x, -wv * u.y);
+          }
+          Fn[node] = Wq[node] * f;
+        }
+        __syncthreads();
+        // transposed z
+        for (int e = tid; e < AGY * GC * nbc; e += nt) {
+          const int b = e % nbc, yk = e / nbc;
+          const int yh = yk / GC, kz = yk % GC;
+          c2<T> acc = mk<T>(0, 0);
+#pragma unroll
+          for (int tz = 0; tz < 4; ++tz) {
+            const int cz = kz - tz;
+            if (cz < 0 || cz >= GT) continue;
+#pragma unroll
+            for (int sz = 0; sz < 5; ++sz) {
+              const c2<T> v = A[b * AGRS + lds_pos<true>(yh * GN + 5 * cz + sz)];
+              const T m = gq_m<T>(gq, sz, tz);
+              acc.x += m * v.x;
+              acc.y += m * v.y;
+            }
+          }
+          Qt[e] = acc;
+        }
+        for (int yk = tid; yk < AGY * GC; yk += nt) {
+          const int yh = yk / GC, kz = yk % GC;
+          T acc = 0;
+#pragma unroll
+          for (int tz = 0; tz < 4; ++tz) {
+            const int cz = kz - tz;
+            if (cz < 0 || cz >= GT) continue;
+#pragma unroll
+            for (int sz = 0; sz < 5; ++sz) acc += gq_m<T>(gq, sz, tz) * Fn[yh * GN + 5 * cz + sz];
+          }
+          Qdt[yk] = acc;
+        }
+        __syncthreads();
+        // transposed y
+        for (int e = tid; e < 4 * GC * nbc; e += nt) {
+          const int b = e % nbc, tk = e / nbc;
+          const int tyy = tk / GC, kz = tk % GC;
+          c2<T> acc = mk<T>(0, 0);
+#pragma unroll
+          for (int yh = 0; yh < AGY; ++yh) {
+            const c2<T> v = Qt[(yh * GC + kz) * nbc + b];
+            const T m = gq_m<T>(gq, yh, tyy);
+            acc.x += m * v.x;
+            acc.y += m * v.y;
+          }
+          c2<T>& o = Pt[((cy + tyy) * GC + kz) * nbc + b];
+          o.x += acc.x;
+          o.y += acc.y;
+        }
+        for (int tk = tid; tk < 4 * GC; tk += nt) {
+          const int tyy = tk / GC, kz = tk % GC;
+          T acc = 0;
+#pragma unroll
+          for (int yh = 0; yh < AGY; ++yh) acc += gq_m<T>(gq, yh, tyy) * Qdt[yh * GC + kz];
+          Pdt[(cy + tyy) * GC + kz] += acc;
+        }
+      }
+      __syncthreads();
+      // transposed x
+      for (int e = tid; e < 4 * GC * GC * nbc; e += nt) {
+        const int b = e % nbc, r = e / nbc;
+        const int txx = r / (GC * GC), jk = r % (GC * GC);
+        const c2<T> v = Pt[jk * nbc + b];
+        const T m = gq_m<T>(gq, sx, txx);
+        c2<T>& o = Ct[((cx + txx) * GC * GC + jk) * nbc + b];
+        o.x += m * v.x;
+        o.y += m * v.y;
+      }
+      for (int r = tid; r < 4 * GC * GC; r += nt) {
+        const int txx = r / (GC * GC), jk = r % (GC * GC);
+        Dt[(cx + txx) * GC * GC + jk] += gq_m<T>(gq, sx, txx) * Pdt[jk];
+      }
+    }
+    __syncthreads();
+    // fold the tile into the grid (neighbouring tiles share coefficients)
+    for (int e = tid; e < NC * nbc; e += nt) {
+      const int b = e % nbc, c = e / nbc;
+      const int i = c / (GC * GC), j = (c / GC) % GC, k = c % GC;
+      const long long cell = ((long long)wrapi(x0 + i, n) * n + wrapi(y0 + j, n)) * n + wrapi(z0 + k, n);
+      c2<T>* o = cm + (long long)(b0 + b) * n3 + cell;
+      atomicAdd(&o->x, Ct[e].x);
+      atomicAdd(&o->y, Ct[e].y);
+    }
+    for (int c = tid; c < NC; c += nt) {
+      const int i = c / (GC * GC), j = (c / GC) % GC, k = c % GC;
+      atomicAdd(&rm[((long long)wrapi(x0 + i, n) * n + wrapi(y0 + j, n)) * n + wrapi(z0 + k, n)], wm * Dt[c]);
+    }
+  }
+}
+
+// zeta[mock][l][g(i)][g(j)] += scale sum_w partials[mock][w][i][j] for the local
+// pairs (i, j) of a chunk-pair contraction that this pass owns: the cross
+// block always, the diagonal block of the first chunk when own_a, of the
+// second when own_c (local i < na is field bin a0 + i, else c0 + i - na)
+__global__ void k_reduce_partials_map(const double* partials, int nwg, int nl, double* zeta, int l, int lmax,
+                                      double scale, int nbt, int a0, int na, int c0, int own_a, int own_c) {
+  __shared__ double sh[32];
+  const int e = blockIdx.x, mock = blockIdx.y;
+  const int i = e / nl, j = e % nl;
+  const bool ia = i < na, ja = j < na;
+  if (ia && ja && !own_a) return;
+  if (!ia && !ja && !own_c) return;
+  const int nl2 = nl * nl;
+  const double* p = partials + (long long)mock * nwg * nl2 + e;
+  double s = 0.0;
+  for (int w = threadIdx.x; w < nwg; w += blockDim.x) s += p[(long long)w * nl2];
+  s = block_sum(s, sh);
+  const int gi = ia ? a0 + i : c0 + i - na, gj = ja ? a0 + j : c0 + j - na;
+  if (threadIdx.x == 0) zeta[((long long)mock * (lmax + 1) + l) * nbt * nbt + (long long)gi * nbt + gj] += scale * s;
+}
+
 // h[mock][s] = sum_l (2l+1) sum_{b1,b2} dzeta[mock][l][b1][b2] jbar_{l,b1}(s) jbar_{l,b2}(s):
 // the weight of |dhat(q)|^2 B7hat(q) in sum_l <dzeta_l, 4 pi Fbar_l>
 template <typename T>
@@ -2446,10 +2845,10 @@ hipError_t filter_y_t(const FilterArgs& a, hipStream_t st) {
   constexpr int ZC = zc_of<T>();
   constexpr int G = tiles_per_wg<N, T, VB>();
   constexpr int threads = Fft<N, VB>::TPC * ZC * G;
-  const dim3 gs((N * (N / ZC) + G - 1) / G, a.batch);
+  const dim3 gs((N * (N / ZC) + G - 1) / G, a.batch * a.nitems);
   k_filter_y<N, T><<<gs, threads, 0, st>>>(static_cast<const CT<T>*>(a.src), static_cast<CT<T>*>(a.dst),
-                                          static_cast<const T*>(a.jtab), a.nq2, a.nbins, a.nbp, a.l, a.m, a.norm,
-                                          a.scale, static_cast<const CT<T>*>(a.tw), a.yr,
+                                          static_cast<const T*>(a.jtab), a.nq2, a.nbins, a.nbp, a.items, a.item0,
+                                          a.batch, a.scale, static_cast<const CT<T>*>(a.tw),
                                           static_cast<const T*>(a.phi));
   return hipGetLastError();
 }
@@ -2461,8 +2860,8 @@ hipError_t adjoint_y_t(const FilterArgs& a, hipStream_t st) {
   constexpr int threads = Fft<N, VB>::TPC * ZC * G;
   const dim3 gs((N * (N / ZC) + G - 1) / G, a.batch);
   k_adjoint_y<N, T><<<gs, threads, 0, st>>>(static_cast<const CT<T>*>(a.src), static_cast<CT<T>*>(a.dst),
-                                           static_cast<const T*>(a.jtab), a.nq2, a.nbins, a.nbp, a.l, a.m, a.norm,
-                                           a.scale, static_cast<const CT<T>*>(a.tw), a.yr,
+                                           static_cast<const T*>(a.jtab), a.nq2, a.nbins, a.nbp, a.items, a.item0,
+                                           a.nitems, a.batch, a.scale, static_cast<const CT<T>*>(a.tw),
                                            static_cast<const T*>(a.phi));
   return hipGetLastError();
 }
@@ -2577,6 +2976,10 @@ template <int N, typename T> inline size_t zpass_fused_lds(int nbins, int thread
   return a > scratch ? a : scratch;
 }
 
+// persistent launch over the group's (item, mock, chunk) units: at most
+// kZpassResident workgroups take units from the counter (zeroed here first)
+constexpr int kZpassResident = 2048;
+
 template <int N, typename T, int MAXNB, bool FUSED = false, bool MF = false, bool QUAD = false>
 hipError_t zpass_adjoint_nb(const ZpassArgs& a, hipStream_t st) {
   const int threads = FUSED ? zpass_fused_threads<N, T>(a.nbins, a.waves) : zpass_threads<N, VZA<T>>(a.nbins);
@@ -2585,10 +2988,13 @@ hipError_t zpass_adjoint_nb(const ZpassArgs& a, hipStream_t st) {
                            : zpass_adjoint_lds<N, T>(a.nbins);
   hipError_t e = allow_lds(k_zpass_adjoint<N, T, MAXNB, FUSED, MF, QUAD>, lds);
   if (e != hipSuccess) return e;
-  const dim3 gs(a.nwg, a.batch);
-  k_zpass_adjoint<N, T, MAXNB, FUSED, MF, QUAD><<<gs, threads, lds, st>>>(
+  k_fill<int><<<1, 64, 0, st>>>(a.counter, 1, 0);
+  const long long units = (long long)a.nitems * a.batch * a.nwg;
+  const unsigned grid = (unsigned)(units < kZpassResident ? units : kZpassResident);
+  k_zpass_adjoint<N, T, MAXNB, FUSED, MF, QUAD><<<grid, threads, lds, st>>>(
       static_cast<CT<T>*>(const_cast<void*>(a.fields)), static_cast<const T*>(a.delta), static_cast<const T*>(a.lam),
-      static_cast<T*>(a.direct), a.nbins, (T)a.wm, a.ppw, static_cast<const CT<T>*>(a.tw), a.partials);
+      static_cast<T*>(a.direct), a.nbins, a.ppw, static_cast<const CT<T>*>(a.tw), a.partials, a.items, a.item0,
+      a.nitems, a.batch, a.nwg, a.counter);
   return hipGetLastError();
 }
 
@@ -2718,11 +3124,10 @@ hipError_t launch_fill_f64(double* p, long long count, double value, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_lam_sym(int prec, const double* dzeta, void* lam_s, int nbins, int l, int lmax, int batch,
-                          hipStream_t st) {
-  const dim3 gs(1, batch);
-  if (prec) k_lam_sym<double><<<gs, 256, 0, st>>>(dzeta, static_cast<double*>(lam_s), nbins, l, lmax);
-  else k_lam_sym<float><<<gs, 256, 0, st>>>(dzeta, static_cast<float*>(lam_s), nbins, l, lmax);
+hipError_t launch_lam_sym(int prec, const double* dzeta, void* lam_s, int nbins, int lmax, int batch, hipStream_t st) {
+  const dim3 gs(lmax + 1, batch);
+  if (prec) k_lam_sym<double><<<gs, 256, 0, st>>>(dzeta, static_cast<double*>(lam_s), nbins, lmax, batch);
+  else k_lam_sym<float><<<gs, 256, 0, st>>>(dzeta, static_cast<float*>(lam_s), nbins, lmax, batch);
   return hipGetLastError();
 }
 
@@ -2730,6 +3135,13 @@ hipError_t launch_reduce_partials(const double* partials, int nwg, int nb2, doub
                                   int batch, hipStream_t st) {
   const dim3 gs(nb2, batch);
   k_reduce_partials<<<gs, 256, 0, st>>>(partials, nwg, nb2, zeta, l, lmax, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_items(const double* partials, int nwg, int nb2, double* zeta, int lmax, double scale,
+                               const ItemRec* items, int item0, int nitems, int batch, hipStream_t st) {
+  const dim3 gs(nb2, batch);
+  k_reduce_items<<<gs, 256, 0, st>>>(partials, nwg, nb2, zeta, lmax, scale, items, item0, nitems, batch);
   return hipGetLastError();
 }
 
@@ -2939,9 +3351,10 @@ hipError_t launch_fbar_subtract(int prec, const double* P, const void* jtab, int
 }
 
 template <typename T, bool MF, bool SPLIT = false, bool QUAD = false>
-hipError_t gamma_contract_t(const void* fields, const void* delta, int n, int nbins, const GammaQuad& gq,
+hipError_t gamma_contract_t(const void* fields, const void* delta, int n, const BinPair& bp, const GammaQuad& gq,
                             double* partials, int nwg, int batch, hipStream_t st) {
   const int threads = 1024;
+  const int nbins = bp.na + bp.nc;
   size_t lds = GammaLds<T>(nbins).total;
   const size_t red = Contractor<T, MF, SPLIT, QUAD>::scratch_bytes(threads);
   if (lds < red) lds = red;
@@ -2949,13 +3362,12 @@ hipError_t gamma_contract_t(const void* fields, const void* delta, int n, int nb
   if (e != hipSuccess) return e;
   const dim3 gs(nwg, batch);
   k_gamma_contract<T, MF, SPLIT, QUAD><<<gs, threads, lds, st>>>(static_cast<const CT<T>*>(fields),
-                                                                static_cast<const T*>(delta), n, nbins, gq, partials);
+                                                                static_cast<const T*>(delta), n, nbins, gq, partials,
+                                                                bp.nbt, bp.a0, bp.na, bp.c0);
   return hipGetLastError();
 }
 
-hipError_t launch_gamma_contract(int prec, bool split, const void* fields, const void* delta, int n, int nbins,
-                                 const double (*m)[4], const double* wq, double* partials, int nwg, int batch,
-                                 hipStream_t st) {
+GammaQuad make_gamma_quad(const double (*m)[4], const double* wq) {
   GammaQuad gq;
   for (int s = 0; s < 5; ++s) {
     for (int t = 0; t < 4; ++t) {
@@ -2965,18 +3377,80 @@ hipError_t launch_gamma_contract(int prec, bool split, const void* fields, const
     gq.wq[s] = (float)wq[s];
     gq.wqd[s] = wq[s];
   }
-  if (prec) return gamma_contract_t<double, false>(fields, delta, n, nbins, gq, partials, nwg, batch, st);
+  return gq;
+}
+
+hipError_t launch_gamma_contract(int prec, bool split, const void* fields, const void* delta, int n,
+                                 const BinPair& bp, const double (*m)[4], const double* wq, double* partials, int nwg,
+                                 int batch, hipStream_t st) {
+  const GammaQuad gq = make_gamma_quad(m, wq);
+  const int nbins = bp.na + bp.nc;
+  if (prec) return gamma_contract_t<double, false>(fields, delta, n, bp, gq, partials, nwg, batch, st);
   if (nbins <= 32) {
-    if (split) return gamma_contract_t<float, true, true>(fields, delta, n, nbins, gq, partials, nwg, batch, st);
+    if (split) return gamma_contract_t<float, true, true>(fields, delta, n, bp, gq, partials, nwg, batch, st);
     if (nbins > 16 && nbins <= 20)
-      return gamma_contract_t<float, true, false, true>(fields, delta, n, nbins, gq, partials, nwg, batch, st);
-    return gamma_contract_t<float, true>(fields, delta, n, nbins, gq, partials, nwg, batch, st);
+      return gamma_contract_t<float, true, false, true>(fields, delta, n, bp, gq, partials, nwg, batch, st);
+    return gamma_contract_t<float, true>(fields, delta, n, bp, gq, partials, nwg, batch, st);
   }
-  return gamma_contract_t<float, false>(fields, delta, n, nbins, gq, partials, nwg, batch, st);
+  return gamma_contract_t<float, false>(fields, delta, n, bp, gq, partials, nwg, batch, st);
 }
 
 size_t gamma_lds_need(int prec, int nbins) {
-  return prec ? GammaLds<double>(nbins).total : GammaLds<float>(nbins).total;
+  // the tile plus the contraction's reduction scratch (1024 threads)
+  const size_t a = prec ? GammaLds<double>(nbins).total : GammaLds<float>(nbins).total;
+  const size_t r = prec ? Contractor<double, false>::scratch_bytes(1024)
+                        : (nbins <= 32 ? Contractor<float, true>::scratch_bytes(1024)
+                                       : Contractor<float, false>::scratch_bytes(1024));
+  return a > r ? a : r;
+}
+
+hipError_t launch_reduce_partials_map(const double* partials, int nwg, const BinPair& bp, double* zeta, int l,
+                                      int lmax, double scale, bool own_a, bool own_c, int batch, hipStream_t st) {
+  const int nl = bp.na + bp.nc;
+  const dim3 gs(nl * nl, batch);
+  k_reduce_partials_map<<<gs, 256, 0, st>>>(partials, nwg, nl, zeta, l, lmax, scale, bp.nbt, bp.a0, bp.na, bp.c0,
+                                            own_a ? 1 : 0, own_c ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_mix(int prec, const void* F, const void* lam_s, void* U, long long n3, int nbins, int batch,
+                          hipStream_t st) {
+  const size_t lds = (size_t)nbins * nbins * (prec ? 8 : 4);
+  const dim3 gs(grid_for(n3 * nbins, 256, 16384), batch);
+  if (prec)
+    k_bin_mix<double><<<gs, 256, lds, st>>>(static_cast<const double2*>(F), static_cast<const double*>(lam_s),
+                                            static_cast<double2*>(U), n3, nbins);
+  else
+    k_bin_mix<float><<<gs, 256, lds, st>>>(static_cast<const float2*>(F), static_cast<const float*>(lam_s),
+                                           static_cast<float2*>(U), n3, nbins);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t gamma_adjoint_bins_t(const void* fields, const void* U, const void* delta, int n, int nbt, int b0, int nbc,
+                                const GammaQuad& gq, double wm, int nwg, int batch, void* cout, void* direct,
+                                hipStream_t st) {
+  const size_t lds = GammaBinsLds<T>(nbc).total;
+  hipError_t e = allow_lds(k_gamma_adjoint_bins<T>, lds);
+  if (e != hipSuccess) return e;
+  const dim3 gs(nwg, batch);
+  k_gamma_adjoint_bins<T><<<gs, 512, lds, st>>>(static_cast<const CT<T>*>(fields), static_cast<const CT<T>*>(U),
+                                                static_cast<const T*>(delta), n, nbt, b0, nbc, gq, (T)wm,
+                                                static_cast<CT<T>*>(cout), static_cast<T*>(direct));
+  return hipGetLastError();
+}
+
+hipError_t launch_gamma_adjoint_bins(int prec, const void* fields, const void* U, const void* delta, int n, int nbt,
+                                     int b0, int nbc, const double (*m)[4], const double* wq, double wm, int nwg,
+                                     int batch, void* cout, void* direct, hipStream_t st) {
+  const GammaQuad gq = make_gamma_quad(m, wq);
+  if (prec)
+    return gamma_adjoint_bins_t<double>(fields, U, delta, n, nbt, b0, nbc, gq, wm, nwg, batch, cout, direct, st);
+  return gamma_adjoint_bins_t<float>(fields, U, delta, n, nbt, b0, nbc, gq, wm, nwg, batch, cout, direct, st);
+}
+
+size_t gamma_adjoint_bins_lds_need(int prec, int nbc) {
+  return prec ? GammaBinsLds<double>(nbc).total : GammaBinsLds<float>(nbc).total;
 }
 
 hipError_t launch_gather_source(int prec, const void* fields, const int* tcell, const void* twt, const float* w,

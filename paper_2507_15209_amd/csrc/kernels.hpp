@@ -14,30 +14,46 @@ struct YlmRec {
   double c1[21], c2[21];
 };
 
+// One (l, m) work item of a call: everything the window passes need, kept in
+// a device table (the workspace) for every item of the call.
+struct ItemRec {
+  int l, m;
+  double norm;       // Y_lm normalisation
+  double wm;         // m weight of the contraction: 1 for m = 0, 2 otherwise
+  YlmRec yr;         // Legendre recurrence of (l, m)
+};
+
+// Window passes over a group of nitems consecutive items of the table,
+// starting at item0: the forward pass writes fields [item][batch][nbins][N^3],
+// the adjoint pass sums every item of the group into G.
 struct FilterArgs {
-  const void* src;   // k_filter_y: dhat [batch][N^3]; k_adjoint_y: sources [batch][nbins][N^3]
-  void* dst;         // k_filter_y: fields [batch][nbins][N^3]; k_adjoint_y: accumulator G [batch][N^3]
+  const void* src;   // k_filter_y: dhat [batch][N^3]; k_adjoint_y: sources [item][batch][nbins][N^3]
+  void* dst;         // k_filter_y: fields [item][batch][nbins][N^3]; k_adjoint_y: accumulator G [batch][N^3]
   const void* jtab;  // [lmax+1][nq2][nbp] radial window, bin axis padded to nbp = 4 ceil(nbins / 4)
   const void* tw;    // twiddles exp(-2 pi i t / N)
-  int nq2, nbins, nbp, l, m, batch;
-  double norm;       // Y_lm normalisation
-  double scale;      // extra real factor (1/N^3, times the m weight in the adjoint)
-  YlmRec yr;         // Legendre recurrence of (l, m)
+  int nq2, nbins, nbp, batch;
+  const ItemRec* items;   // device item table
+  int item0, nitems;
+  double scale;      // real factor (1/N^3); the adjoint pass also takes each item's m weight
   const void* phi = nullptr;   // [N] per-axis phi-hat factors (real), or NULL for none
 };
 
 struct ZpassArgs {
-  const void* fields;   // [batch][nbins][N^3], layout [x][y][qz]
+  const void* fields;   // [batch][nbins][N^3], layout [x][y][qz] (adjoint passes: [item][batch][nbins][N^3])
   const void* delta;    // [batch][N^3]
-  double* partials;     // forward: [batch][nwg][nbins^2]
+  double* partials;     // forward: [batch][nwg][nbins^2]; one sweep: [item][batch][nwg][nbins^2]
   const double* dzeta;  // backward: [batch][lmax+1][nbins^2]
   void* direct;         // backward: [batch][N^3] explicit-primary gradient accumulator
-  const void* lam;      // backward: symmetrised dzeta of this l, [batch][nbins^2] real
+  const void* lam;      // backward: symmetrised dzeta, [lmax+1][batch][nbins^2] real
   const void* tw;
   int nbins, nwg, ppw, batch, l, lmax;
-  double wm;            // m weight (1 for m = 0, 2 otherwise)
   bool split;           // float32 contraction with BF16-split inputs on the matrix cores
   int waves = 0;        // one-sweep z pass: waves per workgroup (0 = default)
+  // adjoint passes: the group of items (table, first item, count) and the
+  // persistent launch's work counter (device int, zeroed by the launch)
+  const ItemRec* items = nullptr;
+  int item0 = 0, nitems = 1;
+  int* counter = nullptr;
 };
 
 struct GatherArgs {
@@ -61,12 +77,34 @@ struct GatherArgs {
   void* src;              // [np_total][nbins] sources in sorted order
 };
 
+// The bins a grid-Gamma contraction takes: local bin i < na is stored bin
+// a0 + i, the others stored bins c0 + (i - na), of nbt stored bins
+// (all bins: {nbt, 0, nbt, 0, 0}).
+struct BinPair {
+  int nbt, a0, na, c0, nc;
+};
+
 // grid summation with connection coefficients (5-point Gauss-Legendre per cell);
-// m[s][t] = B3(xi_s + 1 - t), wq[s] node weights on [0, 1]
-hipError_t launch_gamma_contract(int prec, bool split, const void* fields, const void* delta, int n, int nbins,
-                                 const double (*m)[4], const double* wq, double* partials, int nwg, int batch,
-                                 hipStream_t st);
+// m[s][t] = B3(xi_s + 1 - t), wq[s] node weights on [0, 1]; partials over the
+// pair's (na + nc)^2 local bin pairs
+hipError_t launch_gamma_contract(int prec, bool split, const void* fields, const void* delta, int n,
+                                 const BinPair& bp, const double (*m)[4], const double* wq, double* partials, int nwg,
+                                 int batch, hipStream_t st);
+// LDS bytes of a contraction tile holding nbins bins
 size_t gamma_lds_need(int prec, int nbins);
+// zeta += the pair's partials at their stored-bin positions (cross block always,
+// diagonal blocks when owned)
+hipError_t launch_reduce_partials_map(const double* partials, int nwg, const BinPair& bp, double* zeta, int l,
+                                      int lmax, double scale, bool own_a, bool own_c, int batch, hipStream_t st);
+// U[x][b] = sum_b' lam_s[b][b'] F[x][b'] over bin-interleaved fields
+hipError_t launch_bin_mix(int prec, const void* F, const void* lam_s, void* U, long long n3, int nbins, int batch,
+                          hipStream_t st);
+// grid-Gamma adjoint of stored bins b0 .. b0 + nbc - 1 from the fields and
+// their mix U: sources into cout, wm times the chunk's primary share into direct
+hipError_t launch_gamma_adjoint_bins(int prec, const void* fields, const void* U, const void* delta, int n, int nbt,
+                                     int b0, int nbc, const double (*m)[4], const double* wq, double wm, int nwg,
+                                     int batch, void* cout, void* direct, hipStream_t st);
+size_t gamma_adjoint_bins_lds_need(int prec, int nbc);
 hipError_t launch_zpass_store(int n, int prec, const ZpassArgs& a, void* out, hipStream_t st);
 // counting sort of the particles by (2^shift)^3-cell tile of their mock; offs
 // gets batch * (n >> shift)^3 + 1 exclusive tile offsets
@@ -99,8 +137,11 @@ size_t zpass_fused_lds_need(int n, int prec, int nbins);
 hipError_t launch_fill(int prec, void* p, long long count, double value, hipStream_t st);
 hipError_t launch_fill_f64(double* p, long long count, double value, hipStream_t st);
 hipError_t launch_fill_i32(int* p, long long count, int value, hipStream_t st);
-hipError_t launch_lam_sym(int prec, const double* dzeta, void* lam_s, int nbins, int l, int lmax, int batch,
-                          hipStream_t st);
+// lam_s[l][batch][nbins^2] for every l <= lmax
+hipError_t launch_lam_sym(int prec, const double* dzeta, void* lam_s, int nbins, int lmax, int batch, hipStream_t st);
+// partials of a group of items [item][batch][nwg][nb2] into zeta at each item's l (times scale and the item's m weight)
+hipError_t launch_reduce_items(const double* partials, int nwg, int nb2, double* zeta, int lmax, double scale,
+                               const ItemRec* items, int item0, int nitems, int batch, hipStream_t st);
 hipError_t launch_reduce_partials(const double* partials, int nwg, int nb2, double* zeta, int l, int lmax, double scale,
                                   int batch, hipStream_t st);
 hipError_t launch_weight_sum(const float* w, const long long* off, int batch, long long np_max, double* W, hipStream_t st);

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -24,11 +25,13 @@ struct mp3_plan_s {
   int device = 0;
   double gm[5][4] = {{0}};   // grid-Gamma quadrature: B3 tap weights at the nodes
   double gw[5] = {0};        // and node weights
-  int tune[MP3_NTUNE] = {4096, 4096, 0, 8, 2048, 0};   // launch-shape knobs (mp3_tune_knob)
+  int tune[MP3_NTUNE] = {4096, 4096, 0, 8, 2048, 4, 0};   // launch-shape knobs (mp3_tune_knob)
   int basis = 0, binning = 0;
   unsigned kflags = 0;
   double smoothing = 0.0;   // top-hat radius of every vertex (0 = none)
   void* phi = nullptr;      // [n] real per-axis phi-hat factors when MP3_KF_PHI_HAT
+  std::vector<mp3::ItemRec> items;   // every (l, m >= 0) of the plan, index l (l + 1) / 2 + m
+  mp3::ItemRec* items_dev = nullptr; // the same table on the device
   // optional per-pass HIP event timing
   bool profile = false;
   std::vector<hipEvent_t> pool;
@@ -64,7 +67,8 @@ constexpr size_t kLdsLimit = 160 * 1024;
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t dprim, flag, pplain, aux, xib;
+  size_t dprim, flag, pplain, aux, xib, fields_u, counter;
+  int group;   // (l, m) items per launch of the one-sweep nodal passes
   size_t off, W, S, dhat, fields, partials, G, direct, lam, fields_i, perm, counts, offs, cursor, power;
   size_t src, fj, hq, SF, tcell, twt;
   size_t dperm, dcounts, doffs, dcursor, dcounter, total;
@@ -97,8 +101,25 @@ size_t deposit_tiles(const mp3_plan_s* p) {
 
 int tile_shift(int side) { return side == 4 ? 2 : (side == 8 ? 3 : 4); }
 
+// (l, m) items per launch of the one-sweep nodal passes: the knob, or (0)
+// as many as fit a 1 GiB field budget, at least one
+constexpr double kGroupBudget = 1073741824.0;
+
+int item_group(const mp3_plan_s* p) {
+  const int total = (int)p->items.size();
+  if (p->summation != MP3_SUM_NODAL) return 1;
+  int g = p->tune[MP3_TUNE_ITEM_GROUP];
+  if (g <= 0) {
+    const double set = (double)p->batch * p->nbins * p->n * (double)p->n * p->n * (double)p->celt;
+    g = (int)(kGroupBudget / set);
+  }
+  if (g < 1) g = 1;
+  return g < total ? g : total;
+}
+
 Layout layout(const mp3_plan_s* p, long long np_total = 0) {
   Layout L{};
+  L.group = item_group(p);
   const size_t n3 = (size_t)p->n * p->n * p->n;
   const size_t B = (size_t)p->batch;
   const size_t nb2 = (size_t)p->nbins * p->nbins;
@@ -122,11 +143,12 @@ Layout layout(const mp3_plan_s* p, long long np_total = 0) {
   L.W = take(B * sizeof(double));
   L.S = take(B * sizeof(double));
   L.dhat = take(B * n3 * p->celt);
-  L.fields = take(B * (size_t)p->nbins * n3 * p->celt);
-  L.partials = take(B * pw * nb2 * sizeof(double));
+  L.fields = take((size_t)L.group * B * (size_t)p->nbins * n3 * p->celt);
+  L.partials = take((size_t)L.group * B * pw * nb2 * sizeof(double));
   L.G = take(B * n3 * p->celt);
   L.direct = take(B * n3 * p->elt);
-  L.lam = take(B * nb2 * p->elt);
+  L.lam = take((size_t)(p->lmax + 1) * B * nb2 * p->elt);
+  L.counter = take(sizeof(int));
   // primary vertex filtered by the top-hat window (grid forms with smoothing)
   if (p->smoothing > 0.0 && p->summation != MP3_SUM_PARTICLE) L.dprim = take(B * n3 * p->elt);
   L.flag = take(sizeof(int));
@@ -135,6 +157,9 @@ Layout layout(const mp3_plan_s* p, long long np_total = 0) {
   L.aux = take((size_t)2 * kMaxAux * sizeof(double));
   L.xib = take(B * (size_t)p->nbins * sizeof(double));
   if (p->summation != MP3_SUM_NODAL) L.fields_i = take(B * (size_t)p->nbins * n3 * p->celt);
+  // grid-Gamma adjoint by bin chunks: the bin mix U of the fields
+  if (p->summation == MP3_SUM_GRID_GAMMA && mp3::gamma_adjoint_lds_need(p->prec, p->nbins) > kLdsLimit)
+    L.fields_u = take(B * (size_t)p->nbins * n3 * p->celt);
   if (p->summation == MP3_SUM_PARTICLE) {
     const size_t nt = (size_t)(p->n / 4) * (p->n / 4) * (p->n / 4) * B + 1;
     L.perm = take((size_t)(np_total > 0 ? np_total : 1) * sizeof(int));
@@ -289,7 +314,21 @@ int forward_dft(const mp3_plan_s* p, const void* delta, void* ws, const Layout& 
   return MP3_OK;
 }
 
-mp3::FilterArgs filter_args(const mp3_plan_s* p, const void* src, void* dst, int l, int m, double scale) {
+int item_index(int l, int m) { return l * (l + 1) / 2 + m; }
+
+// the symmetrised cotangent of multipole l: [batch][nbins^2] real
+void* lam_at(const mp3_plan_s* p, void* ws, const Layout& L, int l) {
+  return at(ws, L.lam + (size_t)l * p->batch * p->nbins * p->nbins * p->elt);
+}
+
+// symmetrised cotangents of every l into the workspace (one launch)
+int lam_all(const mp3_plan_s* p, const double* dzeta, void* ws, const Layout& L, hipStream_t st) {
+  MP3_HIP(mp3::launch_lam_sym(p->prec, dzeta, at(ws, L.lam), p->nbins, p->lmax, p->batch, st), "lambda");
+  return MP3_OK;
+}
+
+mp3::FilterArgs filter_args(const mp3_plan_s* p, void* ws, const Layout& L, const void* src, void* dst, int item0,
+                            int nitems) {
   mp3::FilterArgs a;
   a.src = src;
   a.dst = dst;
@@ -298,27 +337,42 @@ mp3::FilterArgs filter_args(const mp3_plan_s* p, const void* src, void* dst, int
   a.nq2 = p->nq2;
   a.nbp = p->nbp;
   a.nbins = p->nbins;
-  a.l = l;
-  a.m = m;
   a.batch = p->batch;
-  a.norm = mp3::ylm_norm(l, m);
-  a.scale = scale;
+  a.items = p->items_dev;
+  a.item0 = item0;
+  a.nitems = nitems;
+  a.scale = 1.0 / ((double)p->n * p->n * p->n);
   a.phi = p->phi;
-  a.yr.pmm = 1.0;
-  for (int k = 1; k <= m; ++k) a.yr.pmm *= -(2.0 * k - 1.0);
-  for (int k = 0; k < 21; ++k) {
-    a.yr.c1[k] = k >= m + 2 ? (2.0 * k - 1.0) / (double)(k - m) : 0.0;
-    a.yr.c2[k] = k >= m + 2 ? (k + m - 1.0) / (double)(k - m) : 0.0;
-  }
   return a;
 }
 
-// fields of (l, m) after the y and x passes: layout [batch][nbins][x][y][qz]
-int fields_xy(const mp3_plan_s* p, void* ws, const Layout& L, void* dst, int l, int m, hipStream_t st) {
-  const double n3 = (double)p->n * p->n * p->n;
-  mp3::FilterArgs a = filter_args(p, at(ws, L.dhat), dst, l, m, 1.0 / n3);
+// arguments of the adjoint z passes over a group of items
+mp3::ZpassArgs adjoint_zargs(const mp3_plan_s* p, void* ws, const Layout& L, void* F, const void* prim,
+                             const double* dzeta, void* direct, int item0, int nitems) {
+  mp3::ZpassArgs z{};
+  z.fields = F;
+  z.delta = prim;
+  z.dzeta = dzeta;
+  z.lam = at(ws, L.lam);
+  z.direct = direct;
+  z.tw = p->tw;
+  z.nbins = p->nbins;
+  z.nwg = L.nwg;
+  z.ppw = L.ppw;
+  z.batch = p->batch;
+  z.lmax = p->lmax;
+  z.items = p->items_dev;
+  z.item0 = item0;
+  z.nitems = nitems;
+  z.counter = reinterpret_cast<int*>(at(ws, L.counter));
+  return z;
+}
+
+// fields of a group of items after the y and x passes: layout [item][batch][nbins][x][y][qz]
+int fields_xy(const mp3_plan_s* p, void* ws, const Layout& L, void* dst, int item0, int nitems, hipStream_t st) {
+  mp3::FilterArgs a = filter_args(p, ws, L, at(ws, L.dhat), dst, item0, nitems);
   MP3_HIP(timed(p, MP3_PASS_FILTER, st, [&] { return mp3::launch_filter_y(p->n, p->prec, a, st); }), "window pass");
-  MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, dst, p->batch * p->nbins, p->tw, p->tune[MP3_TUNE_FFT_X_PLAN], st); }), "x pass");
+  MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, dst, nitems * p->batch * p->nbins, p->tw, p->tune[MP3_TUNE_FFT_X_PLAN], st); }), "x pass");
   return MP3_OK;
 }
 
@@ -386,8 +440,7 @@ int mp3_plan_create(const mp3_plan_desc* d, mp3_plan_t* out) {
   if (!d || !out) return fail(MP3_EINVAL, "desc and out must not be NULL");
   if (int s = validate_desc(d)) return s;
   const int storage = d->precision == MP3_F64 ? 1 : 0;
-  if (d->summation == MP3_SUM_GRID_GAMMA && mp3::gamma_lds_need(storage, d->nbins) > kLdsLimit)
-    return fail(MP3_EUNSUPPORTED, "nbins too large for the grid-Gamma tile's LDS at this precision");
+  (void)storage;
   // the nodal z passes hold every bin of a pencil in LDS (the other forms'
   // store pass takes the bins in chunks)
   if (d->summation == MP3_SUM_NODAL && mp3::zpass_lds_need(d->n, storage, d->nbins) > kLdsLimit)
@@ -448,6 +501,25 @@ int mp3_plan_create(const mp3_plan_desc* d, mp3_plan_t* out) {
   hipError_t e1 = hipMemcpy(p->jtab, hj.data(), hj.size(), hipMemcpyHostToDevice);
   hipError_t e2 = hipMemcpy(p->tw, ht.data(), ht.size(), hipMemcpyHostToDevice);
   hipError_t e3 = hipSuccess;
+  for (int l = 0; l <= p->lmax; ++l) {
+    for (int m = 0; m <= l; ++m) {
+      mp3::ItemRec it{};
+      it.l = l;
+      it.m = m;
+      it.norm = mp3::ylm_norm(l, m);
+      it.wm = m == 0 ? 1.0 : 2.0;
+      it.yr.pmm = 1.0;
+      for (int k = 1; k <= m; ++k) it.yr.pmm *= -(2.0 * k - 1.0);
+      for (int k = 0; k < 21; ++k) {
+        it.yr.c1[k] = k >= m + 2 ? (2.0 * k - 1.0) / (double)(k - m) : 0.0;
+        it.yr.c2[k] = k >= m + 2 ? (k + m - 1.0) / (double)(k - m) : 0.0;
+      }
+      p->items.push_back(it);
+    }
+  }
+  const size_t ib = p->items.size() * sizeof(mp3::ItemRec);
+  hipError_t e4 = hipMalloc(&p->items_dev, ib);
+  if (e4 == hipSuccess) e4 = hipMemcpy(p->items_dev, p->items.data(), ib, hipMemcpyHostToDevice);
   if (p->kflags & MP3_KF_PHI_HAT) {
     std::vector<double> ph;
     mp3::phi_hat_axis(p->n, ph);
@@ -459,12 +531,14 @@ int mp3_plan_create(const mp3_plan_desc* d, mp3_plan_t* out) {
     e3 = hipMalloc(&p->phi, hp.size());
     if (e3 == hipSuccess) e3 = hipMemcpy(p->phi, hp.data(), hp.size(), hipMemcpyHostToDevice);
   }
-  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
     hipFree(p->jtab);
     hipFree(p->tw);
     if (p->phi) hipFree(p->phi);
+    if (p->items_dev) hipFree(p->items_dev);
     delete p;
-    return hip_fail(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3), "upload plan tables");
+    const hipError_t e = e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : (e3 != hipSuccess ? e3 : e4));
+    return hip_fail(e, "upload plan tables");
   }
   *out = p;
   return MP3_OK;
@@ -497,6 +571,7 @@ int mp3_plan_destroy(mp3_plan_t p) {
   if (p->jtab) hipFree(p->jtab);
   if (p->tw) hipFree(p->tw);
   if (p->phi) hipFree(p->phi);
+  if (p->items_dev) hipFree(p->items_dev);
   delete p;
   return MP3_OK;
 }
@@ -517,6 +592,9 @@ int mp3_tune_set(mp3_plan_t p, int knob, int32_t value) {
       break;
     case MP3_TUNE_FUSED_WAVES:
       if (value < 0 || value > 8) return fail(MP3_EINVAL, "one-sweep z-pass waves must lie in 0 .. 8");
+      break;
+    case MP3_TUNE_ITEM_GROUP:
+      if (value < 0 || value > 1024) return fail(MP3_EINVAL, "items per nodal adjoint launch must lie in 0 .. 1024");
       break;
     default:
       return fail(MP3_EINVAL, "unknown tuning knob");
@@ -597,12 +675,62 @@ int mp3_multipole_fields(mp3_plan_t p, const void* delta, int32_t l, int32_t m, 
   if (int s = check_ws(p, ws, wsb, L.total)) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (int s = forward_dft(p, delta, ws, L, st)) return s;
-  if (int s = fields_xy(p, ws, L, a_out, l, m, st)) return s;
+  if (int s = fields_xy(p, ws, L, a_out, item_index(l, m), 1, st)) return s;
   MP3_HIP(mp3::launch_fft_z(p->n, p->prec, +1, a_out, a_out, p->batch * p->nbins, p->tw, st), "z pass");
   return MP3_OK;
 }
 
 namespace {
+
+// The grid-Gamma contraction's bin pairs: every bin in one tile when the LDS
+// holds them, else the bins in chunks and one contraction per pair of
+// chunks, each diagonal block owned by exactly one pair.
+struct GammaPass {
+  mp3::BinPair bp;
+  bool own_a, own_c;
+};
+
+std::vector<GammaPass> gamma_passes(const mp3_plan_s* p) {
+  const int nb = p->nbins;
+  std::vector<GammaPass> out;
+  if (mp3::gamma_lds_need(p->prec, nb) <= kLdsLimit) {
+    out.push_back({{nb, 0, nb, 0, 0}, true, true});
+    return out;
+  }
+  int cs = nb / 2;
+  while (cs > 1 && mp3::gamma_lds_need(p->prec, 2 * cs) > kLdsLimit) --cs;
+  const int k = (nb + cs - 1) / cs;
+  for (int i = 0; i < k; ++i) {
+    for (int j = i + 1; j < k; ++j) {
+      const int a0 = i * cs, na = std::min(cs, nb - a0), c0 = j * cs, nc = std::min(cs, nb - c0);
+      out.push_back({{nb, a0, na, c0, nc}, j == i + 1, i == k - 2 && j == k - 1});
+    }
+  }
+  return out;
+}
+
+// bins per chunk of the chunked grid-Gamma adjoint
+int gamma_adjoint_chunk(const mp3_plan_s* p) {
+  int c = p->nbins;
+  while (c > 1 && mp3::gamma_adjoint_bins_lds_need(p->prec, c) > kLdsLimit) --c;
+  return c;
+}
+
+// the contraction of the stored bin-interleaved fields of one (l, m), all passes, into zeta
+int gamma_contract_all(const mp3_plan_s* p, const void* Fi, const void* prim, double* partials, int gwg, double* zeta,
+                       int l, double scale, hipStream_t st) {
+  for (const GammaPass& g : gamma_passes(p)) {
+    MP3_HIP(timed(p, MP3_PASS_GAMMA, st, [&] {
+              return mp3::launch_gamma_contract(p->prec, p->split, Fi, prim, p->n, g.bp, p->gm, p->gw, partials, gwg,
+                                                p->batch, st);
+            }),
+            "grid-Gamma contraction");
+    MP3_HIP(mp3::launch_reduce_partials_map(partials, gwg, g.bp, zeta, l, p->lmax, scale, g.own_a, g.own_c, p->batch,
+                                            st),
+            "reduce");
+  }
+  return MP3_OK;
+}
 
 int zeta_nodal(mp3_plan_t p, const void* delta, double* zeta, void* ws, const Layout& L, hipStream_t st) {
   const int nb2 = p->nbins * p->nbins;
@@ -611,7 +739,7 @@ int zeta_nodal(mp3_plan_t p, const void* delta, double* zeta, void* ws, const La
   double* partials = reinterpret_cast<double*>(at(ws, L.partials));
   for (int l = 0; l <= p->lmax; ++l) {
     for (int m = 0; m <= l; ++m) {
-      if (int s = fields_xy(p, ws, L, F, l, m, st)) return s;
+      if (int s = fields_xy(p, ws, L, F, item_index(l, m), 1, st)) return s;
       mp3::ZpassArgs z{};
       z.fields = F;
       z.delta = delta;
@@ -661,7 +789,7 @@ int zeta_particle(mp3_plan_t p, const float* pos, const float* w, const int64_t*
   const int gwg = gather_wgs(p, np_max);
   for (int l = 0; l <= p->lmax; ++l) {
     for (int m = 0; m <= l; ++m) {
-      if (int s = fields_xy(p, ws, L, F, l, m, st)) return s;
+      if (int s = fields_xy(p, ws, L, F, item_index(l, m), 1, st)) return s;
       mp3::ZpassArgs z{};
       z.fields = F;
       z.tw = p->tw;
@@ -710,7 +838,7 @@ int zeta_gamma(mp3_plan_t p, const void* delta, double* zeta, void* ws, const La
   if (gwg > tiles) gwg = tiles;
   for (int l = 0; l <= p->lmax; ++l) {
     for (int m = 0; m <= l; ++m) {
-      if (int s = fields_xy(p, ws, L, F, l, m, st)) return s;
+      if (int s = fields_xy(p, ws, L, F, item_index(l, m), 1, st)) return s;
       mp3::ZpassArgs z{};
       z.fields = F;
       z.tw = p->tw;
@@ -719,14 +847,8 @@ int zeta_gamma(mp3_plan_t p, const void* delta, double* zeta, void* ws, const La
       z.ppw = L.ppw;
       z.batch = p->batch;
       MP3_HIP(timed(p, MP3_PASS_Z_STORE, st, [&] { return mp3::launch_zpass_store(p->n, p->prec, z, Fi, st); }), "z pass (store)");
-      MP3_HIP(timed(p, MP3_PASS_GAMMA, st, [&] {
-                return mp3::launch_gamma_contract(p->prec, p->split, Fi, delta, p->n, p->nbins, p->gm, p->gw, partials, (int)gwg,
-                                                  p->batch, st);
-              }),
-              "grid-Gamma contraction");
       const double wm = m == 0 ? 1.0 : 2.0;
-      MP3_HIP(mp3::launch_reduce_partials(partials, (int)gwg, nb2, zeta, l, p->lmax, wm * kFourPi / n3, p->batch, st),
-              "reduce");
+      if (int s = gamma_contract_all(p, Fi, delta, partials, (int)gwg, zeta, l, wm * kFourPi / n3, st)) return s;
     }
   }
   return MP3_OK;
@@ -806,6 +928,7 @@ int backward_particle(mp3_plan_t p, const void* delta, const double* dzeta, void
   const double sc = (double)p->n / p->box;
   if (int s = check_finite(p, ws, L.flag, st, delta, n3 * p->batch, p->prec)) return s;
   if (int s = forward_dft(p, delta, ws, L, st)) return s;
+  if (int s = lam_all(p, dzeta, ws, L, st)) return s;
   if (int s = upload_offsets(p, np_off, ws, L, st)) return s;
   const long long* off = reinterpret_cast<const long long*>(at(ws, L.off));
   double* W = reinterpret_cast<double*>(at(ws, L.W));
@@ -830,10 +953,9 @@ int backward_particle(mp3_plan_t p, const void* delta, const double* dzeta, void
   MP3_HIP(mp3::launch_fill_f64(FJ, np_total, 0.0, st), "zero F_J");
   const int gwg = gather_wgs(p, np_max);
   for (int l = 0; l <= p->lmax; ++l) {
-    MP3_HIP(mp3::launch_lam_sym(p->prec, dzeta, at(ws, L.lam), p->nbins, l, p->lmax, p->batch, st), "lambda");
     for (int m = 0; m <= l; ++m) {
       const double wm = m == 0 ? 1.0 : 2.0;
-      if (int s = fields_xy(p, ws, L, F, l, m, st)) return s;
+      if (int s = fields_xy(p, ws, L, F, item_index(l, m), 1, st)) return s;
       mp3::ZpassArgs z{};
       z.fields = F;
       z.tw = p->tw;
@@ -843,7 +965,7 @@ int backward_particle(mp3_plan_t p, const void* delta, const double* dzeta, void
       z.batch = p->batch;
       MP3_HIP(timed(p, MP3_PASS_Z_STORE, st, [&] { return mp3::launch_zpass_store(p->n, p->prec, z, Fi, st); }), "z pass (store)");
       MP3_HIP(timed(p, MP3_PASS_GATHER, st, [&] {
-                return mp3::launch_gather_source(p->prec, Fi, tcell, twt, w, perm, off, W, at(ws, L.lam), p->n, p->nbins,
+                return mp3::launch_gather_source(p->prec, Fi, tcell, twt, w, perm, off, W, lam_at(p, ws, L, l), p->n, p->nbins,
                                                  wm, gwg, p->batch, FJ, src, st);
               }),
               "gather (adjoint sources)");
@@ -855,7 +977,7 @@ int backward_particle(mp3_plan_t p, const void* delta, const double* dzeta, void
               "adjoint z pass");
       MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, F, p->batch * p->nbins, p->tw, p->tune[MP3_TUNE_FFT_X_PLAN], st); }),
               "adjoint x pass");
-      mp3::FilterArgs a = filter_args(p, F, G, l, m, wm / (double)n3);
+      mp3::FilterArgs a = filter_args(p, ws, L, F, G, item_index(l, m), 1);
       MP3_HIP(timed(p, MP3_PASS_ADJOINT, st, [&] { return mp3::launch_adjoint_y(p->n, p->prec, a, st); }), "adjoint window pass");
     }
   }
@@ -901,6 +1023,7 @@ int value_and_grad_particle(mp3_plan_t p, const void* delta, const double* dzeta
   const double sc = (double)p->n / p->box;
   if (int s = check_finite(p, ws, L.flag, st, delta, n3 * p->batch, p->prec)) return s;
   if (int s = forward_dft(p, delta, ws, L, st)) return s;
+  if (int s = lam_all(p, dzeta, ws, L, st)) return s;
   MP3_HIP(mp3::launch_fill_f64(zeta, (long long)p->batch * (p->lmax + 1) * nb2, 0.0, st), "zero zeta");
   if (int s = upload_offsets(p, np_off, ws, L, st)) return s;
   const long long* off = reinterpret_cast<const long long*>(at(ws, L.off));
@@ -931,10 +1054,9 @@ int value_and_grad_particle(mp3_plan_t p, const void* delta, const double* dzeta
   MP3_HIP(mp3::launch_fill_f64(FJ, np_total, 0.0, st), "zero F_J");
   const int gwg = gather_wgs(p, np_max);
   for (int l = 0; l <= p->lmax; ++l) {
-    MP3_HIP(mp3::launch_lam_sym(p->prec, dzeta, at(ws, L.lam), p->nbins, l, p->lmax, p->batch, st), "lambda");
     for (int m = 0; m <= l; ++m) {
       const double wm = m == 0 ? 1.0 : 2.0;
-      if (int s = fields_xy(p, ws, L, F, l, m, st)) return s;
+      if (int s = fields_xy(p, ws, L, F, item_index(l, m), 1, st)) return s;
       mp3::ZpassArgs z{};
       z.fields = F;
       z.tw = p->tw;
@@ -963,7 +1085,7 @@ int value_and_grad_particle(mp3_plan_t p, const void* delta, const double* dzeta
       // float32: two gathers (measured faster: the separate source kernel
       // overlaps its loads and arithmetic across waves)
       if (p->prec) {
-        g.lam = at(ws, L.lam);
+        g.lam = lam_at(p, ws, L, l);
         g.wm = wm;
         g.FJ = FJ;
         g.src = src;
@@ -972,7 +1094,7 @@ int value_and_grad_particle(mp3_plan_t p, const void* delta, const double* dzeta
       MP3_HIP(mp3::launch_reduce_partials(partials, gwg, nb2, zeta, l, p->lmax, wm * kFourPi, p->batch, st), "reduce");
       if (!p->prec)
         MP3_HIP(timed(p, MP3_PASS_GATHER, st, [&] {
-                  return mp3::launch_gather_source(p->prec, Fi, tcell, twt, w, perm, off, W, at(ws, L.lam), p->n,
+                  return mp3::launch_gather_source(p->prec, Fi, tcell, twt, w, perm, off, W, lam_at(p, ws, L, l), p->n,
                                                    p->nbins, wm, gwg, p->batch, FJ, src, st);
                 }),
                 "gather (adjoint sources)");
@@ -984,7 +1106,7 @@ int value_and_grad_particle(mp3_plan_t p, const void* delta, const double* dzeta
               "adjoint z pass");
       MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, F, p->batch * p->nbins, p->tw, p->tune[MP3_TUNE_FFT_X_PLAN], st); }),
               "adjoint x pass");
-      mp3::FilterArgs a = filter_args(p, F, G, l, m, wm / n3d);
+      mp3::FilterArgs a = filter_args(p, ws, L, F, G, item_index(l, m), 1);
       MP3_HIP(timed(p, MP3_PASS_ADJOINT, st, [&] { return mp3::launch_adjoint_y(p->n, p->prec, a, st); }), "adjoint window pass");
     }
     MP3_HIP(mp3::launch_fbar_subtract(p->prec, P, p->jtab, nq2, p->nbp, p->nbins, l, p->lmax, n3d * n3d, zeta, p->batch, st),
@@ -1014,8 +1136,9 @@ int value_and_grad_particle(mp3_plan_t p, const void* delta, const double* dzeta
 int backward_gamma(mp3_plan_t p, const void* delta, const double* dzeta, void* ddelta, const float* pos,
                    const float* w, const int64_t* np_off, void* dw, void* ws, size_t wsb, void* stream,
                    double* zeta = nullptr) {
-  if (mp3::gamma_adjoint_lds_need(p->prec, p->nbins) > kLdsLimit)
-    return fail(MP3_EUNSUPPORTED, "nbins too large for the grid-Gamma adjoint tile's LDS at this precision");
+  // tiles that do not hold every bin: the adjoint by bin chunks (and, for
+  // zeta, the contraction by pairs of chunks)
+  const bool chunked = mp3::gamma_adjoint_lds_need(p->prec, p->nbins) > kLdsLimit;
   long long np_total = 0, np_max = 0;
   if (dw) {
     if (int s = check_offsets(p, np_off, &np_total, &np_max)) return s;
@@ -1027,6 +1150,7 @@ int backward_gamma(mp3_plan_t p, const void* delta, const double* dzeta, void* d
   const long long n3 = (long long)p->n * p->n * p->n;
   if (int s = check_finite(p, ws, L.flag, st, delta, n3 * p->batch, p->prec)) return s;
   if (int s = forward_dft(p, delta, ws, L, st)) return s;
+  if (int s = lam_all(p, dzeta, ws, L, st)) return s;
   int ps = MP3_OK;
   const void* prim = primary_field(p, delta, ws, L, st, &ps);
   if (ps) return ps;
@@ -1044,10 +1168,9 @@ int backward_gamma(mp3_plan_t p, const void* delta, const double* dzeta, void* d
   if (gwg < 1) gwg = 1;
   if (gwg > tiles) gwg = tiles;
   for (int l = 0; l <= p->lmax; ++l) {
-    MP3_HIP(mp3::launch_lam_sym(p->prec, dzeta, at(ws, L.lam), p->nbins, l, p->lmax, p->batch, st), "lambda");
     for (int m = 0; m <= l; ++m) {
       const double wm = m == 0 ? 1.0 : 2.0;
-      if (int s = fields_xy(p, ws, L, F, l, m, st)) return s;
+      if (int s = fields_xy(p, ws, L, F, item_index(l, m), 1, st)) return s;
       mp3::ZpassArgs z{};
       z.fields = F;
       z.tw = p->tw;
@@ -1057,20 +1180,37 @@ int backward_gamma(mp3_plan_t p, const void* delta, const double* dzeta, void* d
       z.batch = p->batch;
       MP3_HIP(timed(p, MP3_PASS_Z_STORE, st, [&] { return mp3::launch_zpass_store(p->n, p->prec, z, Fi, st); }), "z pass (store)");
       MP3_HIP(mp3::launch_fill(p->prec, F, 2 * n3 * p->batch * p->nbins, 0.0, st), "zero sources");
-      MP3_HIP(timed(p, MP3_PASS_GAMMA, st, [&] {
-                return mp3::launch_gamma_adjoint(p->prec, Fi, prim, at(ws, L.lam), p->n, p->nbins, p->gm, p->gw, wm,
-                                                 (int)gwg, p->batch, F, direct, partials, st);
-              }),
-              "grid-Gamma adjoint");
-      if (zeta)
-        MP3_HIP(mp3::launch_reduce_partials(partials, (int)gwg, nb2, zeta, l, p->lmax, wm * kFourPi / (double)n3,
-                                            p->batch, st),
-                "reduce");
+      if (chunked) {
+        if (zeta)
+          if (int s = gamma_contract_all(p, Fi, prim, partials, (int)gwg, zeta, l, wm * kFourPi / (double)n3, st))
+            return s;
+        void* U = at(ws, L.fields_u);
+        MP3_HIP(mp3::launch_bin_mix(p->prec, Fi, lam_at(p, ws, L, l), U, n3, p->nbins, p->batch, st), "bin mix");
+        const int cb = gamma_adjoint_chunk(p);
+        for (int b0 = 0; b0 < p->nbins; b0 += cb) {
+          const int nbc = std::min(cb, p->nbins - b0);
+          MP3_HIP(timed(p, MP3_PASS_GAMMA, st, [&] {
+                    return mp3::launch_gamma_adjoint_bins(p->prec, Fi, U, prim, p->n, p->nbins, b0, nbc, p->gm, p->gw,
+                                                          wm, (int)gwg, p->batch, F, direct, st);
+                  }),
+                  "grid-Gamma adjoint (bin chunk)");
+        }
+      } else {
+        MP3_HIP(timed(p, MP3_PASS_GAMMA, st, [&] {
+                  return mp3::launch_gamma_adjoint(p->prec, Fi, prim, lam_at(p, ws, L, l), p->n, p->nbins, p->gm, p->gw, wm,
+                                                   (int)gwg, p->batch, F, direct, partials, st);
+                }),
+                "grid-Gamma adjoint");
+        if (zeta)
+          MP3_HIP(mp3::launch_reduce_partials(partials, (int)gwg, nb2, zeta, l, p->lmax, wm * kFourPi / (double)n3,
+                                              p->batch, st),
+                  "reduce");
+      }
       MP3_HIP(timed(p, MP3_PASS_Z_ADJOINT, st, [&] { return mp3::launch_fft_z(p->n, p->prec, +1, F, F, p->batch * p->nbins, p->tw, st); }),
               "adjoint z pass");
       MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, F, p->batch * p->nbins, p->tw, p->tune[MP3_TUNE_FFT_X_PLAN], st); }),
               "adjoint x pass");
-      mp3::FilterArgs a = filter_args(p, F, G, l, m, wm / (double)n3);
+      mp3::FilterArgs a = filter_args(p, ws, L, F, G, item_index(l, m), 1);
       MP3_HIP(timed(p, MP3_PASS_ADJOINT, st, [&] { return mp3::launch_adjoint_y(p->n, p->prec, a, st); }), "adjoint window pass");
     }
   }
@@ -1111,6 +1251,7 @@ int mp3_zeta_backward(mp3_plan_t p, const void* delta, const double* dzeta, void
   const long long n3 = (long long)p->n * p->n * p->n;
   if (int s = check_finite(p, ws, L.flag, st, delta, n3 * p->batch, p->prec)) return s;
   if (int s = forward_dft(p, delta, ws, L, st)) return s;
+  if (int s = lam_all(p, dzeta, ws, L, st)) return s;
   int ps = MP3_OK;
   const void* prim = primary_field(p, delta, ws, L, st, &ps);
   if (ps) return ps;
@@ -1119,31 +1260,15 @@ int mp3_zeta_backward(mp3_plan_t p, const void* delta, const double* dzeta, void
   void* direct = at(ws, L.direct);
   MP3_HIP(mp3::launch_fill(p->prec, G, 2 * n3 * p->batch, 0.0, st), "zero G");
   MP3_HIP(mp3::launch_fill(p->prec, direct, n3 * p->batch, 0.0, st), "zero direct");
-  for (int l = 0; l <= p->lmax; ++l) {
-    for (int m = 0; m <= l; ++m) {
-      const double wm = m == 0 ? 1.0 : 2.0;
-      if (m == 0)
-        MP3_HIP(mp3::launch_lam_sym(p->prec, dzeta, at(ws, L.lam), p->nbins, l, p->lmax, p->batch, st), "lambda");
-      if (int s = fields_xy(p, ws, L, F, l, m, st)) return s;
-      mp3::ZpassArgs z{};
-      z.fields = F;
-      z.delta = prim;
-      z.dzeta = dzeta;
-      z.lam = at(ws, L.lam);
-      z.direct = direct;
-      z.tw = p->tw;
-      z.nbins = p->nbins;
-      z.nwg = L.nwg;
-      z.ppw = L.ppw;
-      z.batch = p->batch;
-      z.l = l;
-      z.lmax = p->lmax;
-      z.wm = wm;
-      MP3_HIP(timed(p, MP3_PASS_Z_ADJOINT, st, [&] { return mp3::launch_zpass_adjoint(p->n, p->prec, z, st); }), "z pass (adjoint)");
-      MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, F, p->batch * p->nbins, p->tw, p->tune[MP3_TUNE_FFT_X_PLAN], st); }), "adjoint x pass");
-      mp3::FilterArgs a = filter_args(p, F, G, l, m, wm / (double)n3);
-      MP3_HIP(timed(p, MP3_PASS_ADJOINT, st, [&] { return mp3::launch_adjoint_y(p->n, p->prec, a, st); }), "adjoint window pass");
-    }
+  const int nitems_all = (int)p->items.size();
+  for (int item0 = 0; item0 < nitems_all; item0 += L.group) {
+    const int ni = std::min(L.group, nitems_all - item0);
+    if (int s = fields_xy(p, ws, L, F, item0, ni, st)) return s;
+    mp3::ZpassArgs z = adjoint_zargs(p, ws, L, F, prim, dzeta, direct, item0, ni);
+    MP3_HIP(timed(p, MP3_PASS_Z_ADJOINT, st, [&] { return mp3::launch_zpass_adjoint(p->n, p->prec, z, st); }), "z pass (adjoint)");
+    MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, F, ni * p->batch * p->nbins, p->tw, p->tune[MP3_TUNE_FFT_X_PLAN], st); }), "adjoint x pass");
+    mp3::FilterArgs a = filter_args(p, ws, L, F, G, item0, ni);
+    MP3_HIP(timed(p, MP3_PASS_ADJOINT, st, [&] { return mp3::launch_adjoint_y(p->n, p->prec, a, st); }), "adjoint window pass");
   }
   return nodal_gradient_tail(p, delta, ddelta, pos, w, np_off, dw, ws, L, np_total, np_max, st);
 }
@@ -1177,6 +1302,7 @@ int mp3_zeta_value_and_grad(mp3_plan_t p, const void* delta, const double* dzeta
   const int nb2 = p->nbins * p->nbins;
   if (int s = check_finite(p, ws, L.flag, st, delta, n3 * p->batch, p->prec)) return s;
   if (int s = forward_dft(p, delta, ws, L, st)) return s;
+  if (int s = lam_all(p, dzeta, ws, L, st)) return s;
   int ps = MP3_OK;
   const void* prim = primary_field(p, delta, ws, L, st, &ps);
   if (ps) return ps;
@@ -1187,36 +1313,21 @@ int mp3_zeta_value_and_grad(mp3_plan_t p, const void* delta, const double* dzeta
   MP3_HIP(mp3::launch_fill_f64(zeta, (long long)p->batch * (p->lmax + 1) * nb2, 0.0, st), "zero zeta");
   MP3_HIP(mp3::launch_fill(p->prec, G, 2 * n3 * p->batch, 0.0, st), "zero G");
   MP3_HIP(mp3::launch_fill(p->prec, direct, n3 * p->batch, 0.0, st), "zero direct");
-  for (int l = 0; l <= p->lmax; ++l) {
-    for (int m = 0; m <= l; ++m) {
-      const double wm = m == 0 ? 1.0 : 2.0;
-      if (m == 0)
-        MP3_HIP(mp3::launch_lam_sym(p->prec, dzeta, at(ws, L.lam), p->nbins, l, p->lmax, p->batch, st), "lambda");
-      if (int s = fields_xy(p, ws, L, F, l, m, st)) return s;
-      mp3::ZpassArgs z{};
-      z.fields = F;
-      z.delta = prim;
-      z.partials = partials;
-      z.dzeta = dzeta;
-      z.lam = at(ws, L.lam);
-      z.direct = direct;
-      z.tw = p->tw;
-      z.nbins = p->nbins;
-      z.nwg = L.nwg;
-      z.ppw = L.ppw;
-      z.batch = p->batch;
-      z.l = l;
-      z.lmax = p->lmax;
-      z.wm = wm;
-      z.waves = p->tune[MP3_TUNE_FUSED_WAVES];
-      MP3_HIP(timed(p, MP3_PASS_Z_FUSED, st, [&] { return mp3::launch_zpass_fused(p->n, p->prec, z, st); }),
-              "z pass (contraction and adjoint)");
-      MP3_HIP(mp3::launch_reduce_partials(partials, L.nwg, nb2, zeta, l, p->lmax, wm * kFourPi / (double)n3, p->batch, st),
-              "reduce");
-      MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, F, p->batch * p->nbins, p->tw, p->tune[MP3_TUNE_FFT_X_PLAN], st); }), "adjoint x pass");
-      mp3::FilterArgs a = filter_args(p, F, G, l, m, wm / (double)n3);
-      MP3_HIP(timed(p, MP3_PASS_ADJOINT, st, [&] { return mp3::launch_adjoint_y(p->n, p->prec, a, st); }), "adjoint window pass");
-    }
+  const int nitems_all = (int)p->items.size();
+  for (int item0 = 0; item0 < nitems_all; item0 += L.group) {
+    const int ni = std::min(L.group, nitems_all - item0);
+    if (int s = fields_xy(p, ws, L, F, item0, ni, st)) return s;
+    mp3::ZpassArgs z = adjoint_zargs(p, ws, L, F, prim, dzeta, direct, item0, ni);
+    z.partials = partials;
+    z.waves = p->tune[MP3_TUNE_FUSED_WAVES];
+    MP3_HIP(timed(p, MP3_PASS_Z_FUSED, st, [&] { return mp3::launch_zpass_fused(p->n, p->prec, z, st); }),
+            "z pass (contraction and adjoint)");
+    MP3_HIP(mp3::launch_reduce_items(partials, L.nwg, nb2, zeta, p->lmax, kFourPi / (double)n3, p->items_dev, item0, ni,
+                                     p->batch, st),
+            "reduce");
+    MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, F, ni * p->batch * p->nbins, p->tw, p->tune[MP3_TUNE_FFT_X_PLAN], st); }), "adjoint x pass");
+    mp3::FilterArgs a = filter_args(p, ws, L, F, G, item0, ni);
+    MP3_HIP(timed(p, MP3_PASS_ADJOINT, st, [&] { return mp3::launch_adjoint_y(p->n, p->prec, a, st); }), "adjoint window pass");
   }
   return nodal_gradient_tail(p, delta, ddelta, pos, w, np_off, dw, ws, L, np_total, np_max, st);
 }

@@ -68,5 +68,9 @@ def test_candidates_are_within_the_abi_ranges():
                 assert 64 <= v <= 65536
             elif k == "fft_x_plan":
                 assert v in (0, 1)
+            elif k == "fused_waves":
+                assert 0 <= v <= 8
+            elif k == "item_group":
+                assert 0 <= v <= 1024
             else:
                 assert v in (4, 8, 16)

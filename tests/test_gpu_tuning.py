@@ -10,7 +10,7 @@ import pytest
 from mockgen import random_field, lognormal_catalogue, batch_sizes
 from oracle import basis
 from oracle import estimator as E
-from tests._common import assert_zeta_close
+from tests._common import assert_zeta_close, assert_grad_close
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -112,7 +112,7 @@ def test_tune_set_rejects_out_of_range(mp3):
     plan = mp3.Plan(16, 160.0, 1, [10.0, 20.0])
     for knob, bad in [("zpass_wgs", 10), ("zpass_wgs", 1 << 20), ("contract_wgs", 0), ("fft_x_plan", 2),
                       ("deposit_tile", 5), ("deposit_tile", 32), ("deposit_wgs", 63), ("fused_waves", -1),
-                      ("fused_waves", 9)]:
+                      ("fused_waves", 9), ("item_group", -1), ("item_group", 1025)]:
         before = plan.tune_get(knob)
         with pytest.raises(mp3.Mp3Error):
             plan.tune_set(knob, bad)
@@ -169,3 +169,45 @@ def test_fused_waves_keep_value_and_gradient(mp3, prec, n, waves):
         dref = basis.density_contrast(basis.deposit(pos, w, n, box), float(np.sum(w.astype(np.float64))))
         assert_zeta_close(z1.cpu().numpy()[0], E.zeta_nodal(E.Plan(n, box, lmax, edges), dref),
                           1e-10 if prec == "f64" else 1e-4)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("group", [1, 2, 5, 7, 1024])
+def test_item_group_keeps_value_and_gradient(mp3, prec, group):
+    """Items per launch of the nodal adjoint passes on a batch of two uneven catalogues (L = 4, 15
+    items, so groups of 2, 5, 7 leave a ragged last group): the one sweep and the backward alone
+    against the oracle's zeta and dJ/ddelta per mock, and against one item per launch (1e-12 / 2e-5)."""
+    from oracle import adjoint as A
+    _say("item group", prec, group)
+    n, box, lmax, nb = 32, 320.0, 4, 6
+    edges = np.linspace(30.0, 110.0, nb + 1)
+    cats = [lognormal_catalogue(n, box, npart, 16.0, 7101 + j, 7111 + j, 7121 + j, (0.5, 1.5))
+            for j, npart in enumerate((9000, 4000))]
+    pos = np.concatenate([c[0] for c in cats])
+    w = np.concatenate([c[1] for c in cats])
+    off = np.array([0, 9000, 13000], dtype=np.int64)
+    pt, wt = _dev(pos, torch.float32), _dev(w, torch.float32)
+    lam = np.random.default_rng(7131).standard_normal((2, lmax + 1, nb, nb))
+    lt = _dev(lam, torch.float64)
+
+    def run(g):
+        plan = mp3.Plan(n, box, lmax, edges, precision=prec, batch=2)
+        plan.tune_set("item_group", g)
+        d = plan.deposit(pt, wt, off)
+        z, dd, dw = plan.zeta_value_and_grad(d, lt, pt, wt, off)
+        dd2, dw2 = plan.zeta_backward(d, lt, pt, wt, off)
+        return d, [t.cpu().numpy() for t in (z, dd, dw, dd2, dw2)]
+
+    d, got = run(group)
+    _, one = run(1)
+    agree = 1e-12 if prec == "f64" else 2e-5
+    assert_zeta_close(got[0], one[0], agree)
+    for a1, a0 in zip(got[1:], one[1:]):
+        assert np.abs(a1 - a0).max() <= agree * np.abs(a0).max()
+    op = E.Plan(n, box, lmax, edges)
+    dn = d.cpu().numpy()
+    for j in range(2):
+        assert_zeta_close(got[0][j], E.zeta_nodal(op, dn[j]), 1e-10 if prec == "f64" else 1e-4)
+        ref = A.zeta_nodal_grad(op, dn[j], lam[j])
+        for k in (1, 3):
+            assert_grad_close(got[k][j], ref, 1e-10 if prec == "f64" else 1e-4, f"dJ/ddelta mock {j}")
