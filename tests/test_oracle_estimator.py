@@ -288,6 +288,48 @@ def test_uniform_randoms_consistent_with_shot_noise():
     assert np.all(np.abs(expect) < 10 * np.abs(zs).max())
 
 
+def test_uniform_randoms_particle_form_consistent_with_shot_noise():
+    """The particle summation in its default mode (primary on the weighted particles, secondaries from
+    the deposited contrast, volume mean subtracted) on uniform randoms equals its Poisson expectation
+    within the scatter of 16 seeds.
+
+    With delta = sum_j f_j, f_j = (n^3/N_R)(B(u_j - x) - n^-3), the primary's average over particles i
+    of F(u_i) - Fbar keeps in expectation only the terms whose two secondaries both come from particle
+    i: a secondary from another particle j has zero mean over u_j, and for i outside {j, k} the mean
+    over u_i is the volume mean that Fbar removes.  Hence
+        E[zeta_l] = (n^3/N_R)^2 E_u[zeta1_l(u)],
+    zeta1(u) the same form for one unit-weight particle at u with secondaries g_u = B(u - x) - n^-3,
+    averaged over sub-cell offsets (the form is invariant under whole-cell shifts).  Dropping the
+    volume mean, or scaling it or the primary's weights wrongly, moves the mean by O(N_R) times this."""
+    n, box, nr = 16, 125.0, 4000
+    edges = np.linspace(15.0, 55.0, 4)
+    plan = E.Plan(n, box, 2, edges)
+    zs, fbar = [], []
+    for seed in range(16):
+        pos, w = uniform_catalogue(nr, box, 7100 + seed)
+        zs.append(E.zeta_particle(plan, pos, w))
+        dh = np.fft.fftn(basis.density_contrast(basis.deposit(pos, w, n, box), float(w.astype(np.float64).sum())))
+        fbar.append([4 * np.pi * E.volume_mean_pair(plan, dh, l) for l in range(3)])
+    zs, fbar = np.array(zs), np.array(fbar)
+    a = box / n
+    acc = 0.0
+    t = (np.arange(4) + 0.5) / 4
+    for ux in t:
+        for uy in t:
+            for uz in t:
+                p = (np.array([[ux, uy, uz]]) * a + 40.0).astype(np.float32)
+                g = basis.deposit(p, None, n, box) - 1.0 / n ** 3
+                acc = acc + E.zeta_particle(plan, p, None, delta=g)
+    expect = acc / 64 * (float(n) ** 3 / nr) ** 2
+    mean = zs.mean(0)
+    sig = zs.std(0, ddof=1) / np.sqrt(len(zs))
+    zscore = np.abs(mean - expect) / sig
+    assert np.mean(zscore < 3.0) >= 0.9
+    assert np.all(zscore < 5.0)
+    # power: without the volume mean the same means would sit many sigma away
+    assert np.min(np.abs(mean + fbar.mean(0) - expect) / sig) > 10.0
+
+
 def test_lognormal_skewness_positive():
     """A log-normal field has positive three-point amplitude on small bins; its Gaussian parent is odd."""
     n, box = 32, 250.0
