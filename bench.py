@@ -368,6 +368,8 @@ def main():
     ap.add_argument("--two-call-steps", type=int, default=3,
                     help="also time the step as zeta() then zeta_backward() (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default knobs (else: cached knobs, or a tuning run on a cache miss)")
     ap.add_argument("--forms", default=",".join(DEFAULT_FORMS),
                     help="secondary measurements after the headline (comma list of %s, all, or none)" % ", ".join(FORMS))
     ap.add_argument("--pmc-probe", action="store_true", help="one step plus a 1 GiB copy, for counter runs")
@@ -418,11 +420,27 @@ def main():
     lam = torch.as_tensor(np.random.default_rng(11).standard_normal((1, wl.lmax + 1, wl.nbins, wl.nbins)),
                           device=dev)
     units = float(wl.n) ** 3 * (wl.lmax + 1) ** 2 * wl.nbins
+    tunings = {}
+
+    def tune(plan, precision):
+        """Cached knobs for this configuration, or a descent over the knobs on the one-sweep call."""
+        if args.no_autotune:
+            return
+        from paper_2507_15209_amd import autotune as at
+        t0 = time.perf_counter()
+        d0 = plan.deposit(pt, wt)
+        try:
+            at.autotune(plan, d0, pt, wt, dzeta=lam, backward=True, reps=1, log=log)
+        except OSError as e:                      # tuning cache not writable: keep the tuned knobs anyway
+            log("tuning cache not written:", e)
+        tunings[precision] = plan.tuning()
+        log(f"{precision} knobs {tunings[precision]} ({time.perf_counter() - t0:.1f} s)")
 
     def run(precision, steps, warmup, profile, one_sweep=True):
         t0 = time.perf_counter()
         plan = mp3.Plan(wl.n, wl.box, wl.lmax, wl.edges, precision=precision, device=dev)
         log(f"{precision} plan built in {time.perf_counter() - t0:.1f} s")
+        tune(plan, precision)
 
         def step():
             delta = plan.deposit(pt, wt)
@@ -514,6 +532,7 @@ def main():
         "fp64_form": fp64,
         "forms": forms,
         "cpu_baseline": cpu,
+        "tuning": tunings,
     }
     print(json.dumps(out), flush=True)
 

@@ -27,7 +27,7 @@ CANDIDATES = {
     "zpass_wgs": (1024, 2048, 4096, 8192, 16384),
     "contract_wgs": (1024, 2048, 4096, 8192, 16384),
     "fused_waves": (0, 4, 8),
-    "item_group": (0, 1, 2, 4, 8, 16),
+    "item_group": (0, 1, 2, 4),
 }
 
 
