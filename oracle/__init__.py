@@ -18,6 +18,9 @@ fusion or reordering beyond what the definitions state.
 Modules
   special    spherical Bessel functions, bin-averaged j_l, Y_lm, Legendre P_l
   basis      cubic B-spline basis, deposit / gather, connection coefficients
+  basis_d4   Daubechies-4 scaling function (cascade table, deposit / gather,
+             autocorrelation, |phi_hat|^2 by the infinite product, connection
+             coefficients from the two-scale relation)
   estimator  multipole kernel, a_lm fields, zeta_l by nodal, grid-Gamma and
              particle summation
   adjoint    gradients of sum_l lambda_l . zeta_l w.r.t. the density grid and
@@ -27,5 +30,5 @@ Parity status: every function is pinned by the CPU tests (``-m "not gpu"``)
 against closed forms, brute force or finite differences; none is "parity
 unpinned".
 """
-from . import special, basis, estimator, adjoint  # noqa: F401
+from . import special, basis, basis_d4, estimator, adjoint  # noqa: F401
 from .estimator import Plan  # noqa: F401

@@ -53,7 +53,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import basis
-from .estimator import Plan, fields, FOUR_PI
+from .estimator import Plan, fields, FOUR_PI, BASES
 
 __all__ = ["zeta_nodal_grad", "deposit_weight_grad", "zeta_nodal_objective",
            "zeta_particle_objective", "zeta_particle_grad", "zeta_gamma_objective", "zeta_gamma_grad"]
@@ -94,13 +94,14 @@ def zeta_nodal_grad(plan: Plan, delta, lam, ls=None, bins=None) -> np.ndarray:
     return grad * (FOUR_PI / n ** 3)
 
 
-def deposit_weight_grad(pos, w, n: int, box: float, g) -> np.ndarray:
+def deposit_weight_grad(pos, w, n: int, box: float, g, basis_name: str = "b3") -> np.ndarray:
     """dJ/dw_i given g = dJ/ddelta on the grid (delta from the deposit of (pos, w))."""
     w = np.ones(len(pos)) if w is None else np.asarray(w, dtype=np.float64)
     W = w.sum()
-    eps = basis.deposit(pos, w, n, box)
+    B = BASES[basis_name]
+    eps = B.deposit(pos, w, n, box)
     g = np.asarray(g, dtype=np.float64)
-    interp = basis.gather(g, pos, n, box)
+    interp = B.gather(g, pos, n, box)
     return (n ** 3 / W) * interp - (n ** 3 / W ** 2) * float(np.sum(eps * g))
 
 
@@ -110,9 +111,9 @@ def zeta_particle_objective(plan: Plan, pos, w, lam) -> float:
     return float(np.sum(np.asarray(lam) * zeta_particle(plan, pos, w)))
 
 
-def _scatter(vals, pos, n: int, box: float) -> np.ndarray:
-    """Transpose of basis.gather for complex per-particle values: sum_i v_i B(u_i - l)."""
-    return (basis.deposit(pos, vals.real, n, box) + 1j * basis.deposit(pos, vals.imag, n, box))
+def _scatter(vals, pos, n: int, box: float, B=basis) -> np.ndarray:
+    """Transpose of the basis' gather for complex per-particle values: sum_i v_i B(u_i - l)."""
+    return (B.deposit(pos, vals.real, n, box) + 1j * B.deposit(pos, vals.imag, n, box))
 
 
 def zeta_particle_grad(plan: Plan, pos, w, lam, ls=None, bins=None):
@@ -126,13 +127,12 @@ def zeta_particle_grad(plan: Plan, pos, w, lam, ls=None, bins=None):
     w = np.ones(len(pos)) if w is None else np.asarray(w, dtype=np.float64)
     W = w.sum()
     lam = np.asarray(lam, dtype=np.float64)
-    delta = basis.density_contrast(basis.deposit(pos, w, n, box), W)
+    delta = basis.density_contrast(plan.B.deposit(pos, w, n, box), W)
     dhat = np.fft.fftn(delta)
     acc = np.zeros(delta.shape, dtype=np.complex128)
     FJ = np.zeros(len(pos))
     bl = plan.bins(bins)
-    th = 2.0 * np.pi * plan.q1 / n
-    b7 = basis.b7_hat(th)
+    b7 = plan.autocorr_hat_axis()
     H = np.zeros(delta.shape)
     for li, l in enumerate(plan.ls(ls)):
         lam_l = lam[li]
@@ -141,17 +141,17 @@ def zeta_particle_grad(plan: Plan, pos, w, lam, ls=None, bins=None):
         H += (2 * l + 1) * np.einsum("ij,ixyz,jxyz->xyz", lam_l, J, J)
         for m in range(-l, l + 1):
             A = fields(plan, dhat, l, m, bl)
-            At = basis.gather(A, pos, n, box)                          # [nb, P]
+            At = plan.B.gather(A, pos, n, box)                         # [nb, P]
             FJ += np.einsum("ij,ip,jp->p", lam_l, At, At.conj()).real
             S = (w / W)[None, :] * (lam_s @ At.conj())
             yc = plan.ylm_conj_grid(l, m)
             for bi, b in enumerate(bl):
-                c = float(n) ** 3 * _scatter(S[bi], pos, n, box)
+                c = float(n) ** 3 * _scatter(S[bi], pos, n, box, plan.B)
                 acc += plan.kernel(l, m, b, yc) * np.fft.ifftn(c)
     H *= b7[:, None, None] * b7[None, :, None] * b7[None, None, :] * plan.phi_hat_grid() ** 2
     H[plan.nyquist] = 0.0
     g = (FOUR_PI / n ** 3) * 2.0 * np.fft.fftn(acc).real - (2.0 / n ** 3) * np.fft.ifftn(H * dhat).real
-    dw = deposit_weight_grad(pos, w, n, box, g) + FOUR_PI * (FJ / W - float(np.dot(w, FJ)) / W ** 2)
+    dw = deposit_weight_grad(pos, w, n, box, g, plan.basis) + FOUR_PI * (FJ / W - float(np.dot(w, FJ)) / W ** 2)
     return g, dw
 
 
@@ -159,6 +159,24 @@ def zeta_gamma_objective(plan: Plan, delta, lam) -> float:
     """J = sum_l <lam_l, zeta_l> for the grid-Gamma form (used by finite differences)."""
     from .estimator import zeta_gamma
     return float(np.sum(np.asarray(lam) * zeta_gamma(plan, delta)))
+
+
+def _gamma_stencil_field_t(q, gmat, shift):
+    """Transpose in delta of G_Delta(y) = sum_s delta(y - s) Gamma(s, s + Delta):
+    sum_s q(x + s) Gamma(s, s + Delta), per axis (Gamma separable).  No reflection symmetry of
+    Gamma is assumed (the Daubechies-4 scaling function is not symmetric)."""
+    g = q
+    for axis in range(3):
+        d = shift[axis]
+        acc = np.zeros_like(g)
+        for s in range(-3, 4):
+            t = s + d
+            if -3 <= t <= 3:
+                c = gmat[s + 3, t + 3]
+                if c != 0.0:
+                    acc = acc + c * np.roll(g, -s, axis=axis)       # g(x + s)
+        g = acc
+    return g
 
 
 def zeta_gamma_grad(plan: Plan, delta, lam, ls=None, bins=None) -> np.ndarray:
@@ -172,7 +190,7 @@ def zeta_gamma_grad(plan: Plan, delta, lam, ls=None, bins=None) -> np.ndarray:
     lam = np.asarray(lam, dtype=np.float64)
     n = plan.n
     dhat = np.fft.fftn(delta)
-    gmat = basis.gamma_matrix()
+    gmat = plan.B.gamma_matrix()
     shifts = [(dx, dy, dz) for dx in range(-3, 4) for dy in range(-3, 4) for dz in range(-3, 4)]
     gfields = {sh: _gamma_stencil_field(plan.primary(delta), gmat, sh) for sh in shifts}
     direct = np.zeros(delta.shape, dtype=np.complex128)
@@ -189,7 +207,7 @@ def zeta_gamma_grad(plan: Plan, delta, lam, ls=None, bins=None) -> np.ndarray:
                 rolled = (-sh[0], -sh[1], -sh[2])
                 Ash = np.roll(A, shift=rolled, axis=(1, 2, 3))              # a(x + Delta)
                 Q = np.einsum("ij,ixyz,jxyz->xyz", lam_l, A, Ash.conj())     # sum lam a_b1(y) conj(a_b2(y + Delta))
-                direct += _gamma_stencil_field(Q, gmat, (-sh[0], -sh[1], -sh[2]))
+                direct += _gamma_stencil_field_t(Q, gmat, sh)
                 C += G[None] * np.roll(V, shift=rolled, axis=(1, 2, 3))      # G_Delta(x) V_b(x + Delta)
             yc = plan.ylm_conj_grid(l, m)
             for bi, b in enumerate(bl):

@@ -34,7 +34,9 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import special, basis
+from . import special, basis, basis_d4
+
+BASES = {"b3": basis, "d4": basis_d4}
 
 __all__ = ["Plan", "zeta_nodal", "zeta_gamma", "zeta_gamma_quadrature",
            "zeta_particle", "fields", "volume_mean_pair", "xi", "zeta_theta", "reduced_3pcf", "xi_multipoles",
@@ -51,12 +53,19 @@ class Plan:
     smoothing R > 0: the spherical top-hat window W_TH(kR) on every vertex
     (Sec. 3): both secondaries' radial window, and the grid forms' primary
     delta_p = ifftn(fftn(delta) W_TH).  phi_hat: the secondaries' window
-    also carries the power spectrum of the B-spline scaling function,
-    prod_d sinc^8(pi q_d / n) (Eq. SFC-3PCF-vertex).
+    also carries the power spectrum of the scaling function (Eq. SFC-3PCF-vertex):
+    prod_d sinc^8(pi q_d / n) for the cubic B-spline, prod_d |phi_hat(2 pi q_d / n)|^2 by the
+    infinite product for Daubechies-4.  basis "b3" (cubic B-spline, module ``basis``) or "d4"
+    (Daubechies-4, module ``basis_d4``): the deposit, the interpolation at particles, the volume
+    mean's autocorrelation and the connection coefficients follow it.
     """
 
     def __init__(self, n: int, box: float, lmax: int, edges, binning: str = "shell", smoothing: float = 0.0,
-                 phi_hat: bool = False):
+                 phi_hat: bool = False, basis: str = "b3"):
+        if basis not in BASES:
+            raise ValueError("basis must be 'b3' or 'd4'")
+        self.basis = basis
+        self.B = BASES[basis]
         self.n = int(n)
         self.box = float(box)
         self.lmax = int(lmax)
@@ -101,15 +110,24 @@ class Plan:
         return self._jbar[l]
 
     def phi_hat_grid(self) -> np.ndarray:
-        """prod_d sinc^8(pi q_d / n) on the k-grid (ones without the phi_hat option)."""
+        """The basis power spectrum on the k-grid (ones without the phi_hat option):
+        prod_d sinc^8(pi q_d / n) (B3), prod_d |phi_hat(2 pi q_d / n)|^2 (D4)."""
         if not self.phi_hat:
             return np.ones((self.n,) * 3)
-        h = np.pi * self.q1 / self.n
-        s = np.ones_like(h)
-        nz = h != 0
-        s[nz] = np.sin(h[nz]) / h[nz]
-        s = s ** 8
+        if self.basis == "d4":
+            s = basis_d4.phi_hat_axis(self.n)
+        else:
+            h = np.pi * self.q1 / self.n
+            s = np.ones_like(h)
+            nz = h != 0
+            s[nz] = np.sin(h[nz]) / h[nz]
+            s = s ** 8
         return s[:, None, None] * s[None, :, None] * s[None, None, :]
+
+    def autocorr_hat_axis(self) -> np.ndarray:
+        """sum_s A(s) e^{-i theta s} of the basis autocorrelation samples A(s), theta = 2 pi q / n."""
+        th = 2.0 * np.pi * self.q1 / self.n
+        return basis.b7_hat(th) if self.basis == "b3" else basis_d4.autocorr_hat(th)
 
     def primary(self, delta) -> np.ndarray:
         """The grid forms' primary vertex: delta, or delta filtered by the top-hat window."""
@@ -212,7 +230,7 @@ def zeta_gamma(plan: Plan, delta: np.ndarray, ls=None, bins=None) -> np.ndarray:
     """
     delta = np.asarray(delta, dtype=np.float64)
     dhat = np.fft.fftn(delta)
-    gmat = basis.gamma_matrix()
+    gmat = plan.B.gamma_matrix()
     shifts = [(dx, dy, dz) for dx in range(-3, 4) for dy in range(-3, 4) for dz in range(-3, 4)]
     prim = plan.primary(delta)
     gfields = {sh: _gamma_stencil_field(prim, gmat, sh) for sh in shifts}
@@ -253,7 +271,10 @@ def zeta_gamma_quadrature(plan: Plan, delta: np.ndarray, ls=None, bins=None) -> 
     sum_{x,s,t} delta_x Gamma(s,t) a(x+s) b*(x+t) = int delta_B(u) a_B(u) b_B*(u) d^3u,
     with f_B(u) = sum_l f_l B3(u - l); the integrand is a degree-9 polynomial
     per axis on each cell, which 5-point Gauss-Legendre integrates exactly.
+    Cubic B-spline only (the Daubechies-4 products are not piecewise polynomial).
     """
+    if plan.basis != "b3":
+        raise ValueError("the quadrature form needs the cubic B-spline basis")
     n = plan.n
     M, wq = _node_interp_matrix(n)
 
@@ -288,14 +309,14 @@ def volume_mean_pair(plan: Plan, dhat: np.ndarray, l: int, bins=None) -> np.ndar
     """Fbar_l[b1,b2] = (1/n^3) int sum_m atilde_{b1} conj(atilde_{b2}) d^3u.
 
     By Parseval on the periodic interpolants (aliases folded into the
-    autocorrelation of B3) and the addition theorem
+    autocorrelation of the basis) and the addition theorem
     sum_m conj(Y_lm) Y_lm = (2l+1)/(4 pi):
-        Fbar_l = (2l+1) / (4 pi n^6) sum_q |dhat|^2 B7hat(q) jbar_{b1} jbar_{b2},
+        Fbar_l = (2l+1) / (4 pi n^6) sum_q |dhat|^2 Ahat(q) jbar_{b1} jbar_{b2},
+    Ahat = prod_d sum_s A(s) e^{-i theta_d s} (B7hat for the cubic B-spline),
     Nyquist planes excluded (the window vanishes there).
     """
     n = plan.n
-    th = 2.0 * np.pi * plan.q1 / n
-    b7 = basis.b7_hat(th)
+    b7 = plan.autocorr_hat_axis()
     b7g = b7[:, None, None] * b7[None, :, None] * b7[None, None, :]
     p = np.abs(dhat) ** 2 * b7g * plan.phi_hat_grid() ** 2
     p[plan.nyquist] = 0.0
@@ -322,7 +343,7 @@ def zeta_particle(plan: Plan, pos, w, ls=None, bins=None, mode: str = "delta", d
             raise ValueError("an explicit delta needs mode 'delta'")
         src = np.asarray(delta, dtype=np.float64)
     else:
-        eps = basis.deposit(pos, w, n, box)
+        eps = plan.B.deposit(pos, w, n, box)
         rho = eps * (n ** 3 / W)
         src = rho - 1.0 if mode == "delta" else rho
     dhat = np.fft.fftn(src)
@@ -332,7 +353,7 @@ def zeta_particle(plan: Plan, pos, w, ls=None, bins=None, mode: str = "delta", d
         floor = 0.0
         for m in range(-l, l + 1):
             A = fields(plan, dhat, l, m, bins)
-            At = basis.gather(A, pos, n, box)                 # [nb, P]
+            At = plan.B.gather(A, pos, n, box)                # [nb, P]
             z = z + (At * (w / W)) @ At.conj().T
             floor += float(np.abs(A).max()) ** 2
         _check_real(z, floor)
@@ -428,7 +449,7 @@ def xi_multipoles(plan: Plan, delta, radii, ells) -> np.ndarray:
 # edge-corrected estimator with a random catalogue
 # ---------------------------------------------------------------------------
 
-def ss_fields(pos_d, w_d, pos_r, w_r, n: int, box: float):
+def ss_fields(pos_d, w_d, pos_r, w_r, n: int, box: float, basis_name: str = "b3"):
     """The two fields of the Szapudi-Szalay estimator [Sec. 3, Eq. SSestimator]: the data and random
     catalogues deposited on the basis, each normalised to unit mean, and
 
@@ -438,8 +459,9 @@ def ss_fields(pos_d, w_d, pos_r, w_r, n: int, box: float):
     Returns (f, r) as float64 [n, n, n]."""
     w_d = np.ones(len(pos_d)) if w_d is None else np.asarray(w_d, dtype=np.float64)
     w_r = np.ones(len(pos_r)) if w_r is None else np.asarray(w_r, dtype=np.float64)
-    rd = basis.deposit(pos_d, w_d, n, box) * (n ** 3 / w_d.sum())
-    rr = basis.deposit(pos_r, w_r, n, box) * (n ** 3 / w_r.sum())
+    B = BASES[basis_name]
+    rd = B.deposit(pos_d, w_d, n, box) * (n ** 3 / w_d.sum())
+    rr = B.deposit(pos_r, w_r, n, box) * (n ** 3 / w_r.sum())
     return rd - rr, rr
 
 

@@ -1,5 +1,6 @@
 """Pins of the oracle's gradients: central finite differences and dot-product tests."""
 import numpy as np
+import pytest
 
 from mockgen import random_field, lognormal_catalogue
 from oracle import basis
@@ -78,19 +79,20 @@ def test_fft_filter_dot_products():
     assert abs(lhs - rhs) < 1e-13 * abs(lhs)
 
 
-def _particle_case():
+def _particle_case(basis_name="b3"):
     n, box = 8, 80.0
     pos, w = lognormal_catalogue(n, box, 1500, 12.0, 31, 32, 33, (0.5, 1.5))
-    plan = E.Plan(n, box, 2, np.array([8.0, 16.0, 24.0, 32.0]))
+    plan = E.Plan(n, box, 2, np.array([8.0, 16.0, 24.0, 32.0]), basis=basis_name)
     lam = np.random.default_rng(34).standard_normal((plan.lmax + 1, plan.nbins, plan.nbins))
     return plan, pos, w.astype(np.float64), lam
 
 
-def test_particle_grad_delta_matches_finite_differences():
+@pytest.mark.parametrize("basis_name", ["b3", "d4"])
+def test_particle_grad_delta_matches_finite_differences(basis_name):
     """dJ/ddelta of the particle form (primary weights fixed) against central differences."""
-    plan, pos, w, lam = _particle_case()
+    plan, pos, w, lam = _particle_case(basis_name)
     g, _ = A.zeta_particle_grad(plan, pos, w, lam)
-    delta = basis.density_contrast(basis.deposit(pos, w, plan.n, plan.box), w.sum())
+    delta = basis.density_contrast(plan.B.deposit(pos, w, plan.n, plan.box), w.sum())
     rng = np.random.default_rng(35)
     for _ in range(3):
         v = rng.standard_normal(delta.shape)
@@ -102,9 +104,10 @@ def test_particle_grad_delta_matches_finite_differences():
         assert abs(fd - np.sum(g * v)) < 1e-7 * abs(fd)
 
 
-def test_particle_grad_weights_matches_finite_differences():
+@pytest.mark.parametrize("basis_name", ["b3", "d4"])
+def test_particle_grad_weights_matches_finite_differences(basis_name):
     """dJ/dw of the particle form (through the deposit and the primary) against central differences."""
-    plan, pos, w, lam = _particle_case()
+    plan, pos, w, lam = _particle_case(basis_name)
     _, dw = A.zeta_particle_grad(plan, pos, w, lam)
     rng = np.random.default_rng(36)
     for _ in range(3):
@@ -128,11 +131,12 @@ def test_particle_grad_subset_equals_masked_full():
     assert np.abs(dw_full - dw_sub).max() <= 1e-12 * np.abs(dw_full).max()
 
 
-def test_gamma_grad_matches_finite_differences():
+@pytest.mark.parametrize("basis_name", ["b3", "d4"])
+def test_gamma_grad_matches_finite_differences(basis_name):
     """dJ/ddelta of the grid summation with connection coefficients against central differences."""
     n = 8
     delta = random_field(n, 41)
-    plan = E.Plan(n, 100.0, 2, np.linspace(5.0, 40.0, 4))
+    plan = E.Plan(n, 100.0, 2, np.linspace(5.0, 40.0, 4), basis=basis_name)
     lam = np.random.default_rng(42).standard_normal((plan.lmax + 1, plan.nbins, plan.nbins))
     g = A.zeta_gamma_grad(plan, delta, lam)
     rng = np.random.default_rng(43)

@@ -133,9 +133,9 @@ def test_real_harmonics_give_same_zeta():
         assert np.max(np.abs(zr.real - z[l])) < 1e-13 * np.max(np.abs(z))
 
 
-def _gamma_literal(delta, A, B):
+def _gamma_literal(delta, A, B, g=None):
     """sum_x delta_x sum_{s,t in [-3,3]^3} Gamma(s,t) A(x+s) conj(B(x+t)), literally over all (s, t)."""
-    g = basis.gamma_matrix()
+    g = basis.gamma_matrix() if g is None else g
     offs = [(i, j, k) for i in range(-3, 4) for j in range(-3, 4) for k in range(-3, 4)]
     As = np.stack([np.roll(A, (-o[0], -o[1], -o[2]), axis=(0, 1, 2)).ravel() for o in offs])
     Bs = np.stack([np.roll(B, (-o[0], -o[1], -o[2]), axis=(0, 1, 2)).ravel() for o in offs])
@@ -158,6 +158,25 @@ def test_gamma_forms_agree_with_literal_sum():
     for m in range(-l, l + 1):
         A = E.fields(plan, dh, l, m)
         tot = tot + _gamma_literal(delta, A[0], A[1])
+    tot *= 4 * np.pi / n ** 3
+    assert abs(tot.imag) < 1e-13 * abs(tot)
+    assert abs(tot.real - zg[l, 0, 1]) < 1e-13 * np.max(np.abs(zg[l]))
+
+
+def test_gamma_d4_agrees_with_literal_sum():
+    """The Delta-stencil oracle with the Daubechies-4 connection coefficients (not reflection
+    symmetric) equals Eq. SFC-3PCF summed literally over (s, t)."""
+    from oracle import basis_d4
+    n = 8
+    delta = random_field(n, 19)
+    plan = E.Plan(n, 100.0, 1, np.linspace(10.0, 40.0, 3), basis="d4")
+    zg = E.zeta_gamma(plan, delta)
+    dh = np.fft.fftn(delta)
+    l = 1
+    tot = 0.0
+    for m in range(-l, l + 1):
+        A = E.fields(plan, dh, l, m)
+        tot = tot + _gamma_literal(delta, A[0], A[1], basis_d4.gamma_matrix())
     tot *= 4 * np.pi / n ** 3
     assert abs(tot.imag) < 1e-13 * abs(tot)
     assert abs(tot.real - zg[l, 0, 1]) < 1e-13 * np.max(np.abs(zg[l]))
