@@ -483,7 +483,11 @@ def main():
               key=lambda k: passes[k][0])
     ms_tot, cnt = passes[dom]
     avg_ms = ms_tot / cnt
-    abytes = pass_bytes(dom, wl.n, wl.nbins, 1, real_bytes)
+    # (l, m) items per launch of the pass on average (1 unless the plan groups items)
+    per_item = {"filter": 1, "x": 2, "z_fused": 1, "adjoint": 1}.get(dom, 1)
+    items = (wl.lmax + 1) * (wl.lmax + 2) // 2
+    ipl = per_item * items * prof_steps / cnt
+    abytes = pass_bytes(dom, wl.n, wl.nbins, 1, real_bytes) * ipl
     achieved = abytes / (avg_ms * 1e-3) / 1e9
     log("per-pass totals (ms, launches):", {k: (round(v[0], 2), v[1]) for k, v in passes.items()})
     traffic = read_pmc(dom)
@@ -525,7 +529,7 @@ def main():
                    "n_particles": wl.n_particles, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": abytes},
+                     "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": abytes, "items_per_launch": ipl},
         "passes_ms": {k: {"total_ms": v[0] / prof_steps, "launches": v[1] // prof_steps} for k, v in passes.items()},
         "profiled_ms_per_step": t_prof * 1e3,
         "two_calls": two_calls,

@@ -82,9 +82,21 @@ enum mp3_summation {
 };
 
 /* Basis of the density reconstruction (Sec. 2.1, the scaling functions of the
- * multiresolution analysis).  Only the centred cubic B-spline (support 4
- * cells per axis) is implemented; other values return MP3_EUNSUPPORTED. */
-enum mp3_basis { MP3_BASIS_BSPLINE3 = 0 };
+ * multiresolution analysis; Sec. 3, the basis paragraph), in cell units u:
+ *   MP3_BASIS_BSPLINE3     the centred cubic B-spline B3(u - l), support 4
+ *                          cells per axis (not orthogonal; the deposit is the
+ *                          projection coefficient sum_i w_i B3(u_i - l))
+ *   MP3_BASIS_DAUBECHIES4  the Daubechies scaling function of genus 4 (four
+ *                          orthonormal filter taps, support 3 cells): node l
+ *                          carries phi(u - l + 1), phi taken as the linear
+ *                          interpolant of its values at the points i / 1024
+ *                          of [0, 3] from the cascade algorithm.  Nodal and
+ *                          particle summation; with MP3_SUM_GRID_GAMMA
+ *                          mp3_plan_create returns MP3_EUNSUPPORTED.
+ * The basis sets the deposit, the interpolation at particles (the particle
+ * form), the autocorrelation in the particle form's volume mean and the
+ * Phi-hat factor of MP3_KF_PHI_HAT. */
+enum mp3_basis { MP3_BASIS_BSPLINE3 = 0, MP3_BASIS_DAUBECHIES4 = 1 };
 
 /* Radial window of the two secondary vertices (Sec. 2.2, the paragraph after
  * Eq. nL-2fold: a binning window multiplies the multipole window of
@@ -99,8 +111,10 @@ enum mp3_binning { MP3_BIN_SHELL_AVERAGE = 0, MP3_BIN_THIN_SHELL = 1 };
 /* Option bits of mp3_plan_desc.kflags. */
 enum mp3_kflags {
   /* multiply the secondary vertices' window by the power spectrum of the
-   * father scaling function, Phi-hat(q) = prod_d sinc^8(pi q_d / N) for the
-   * cubic B-spline, as in Eq. SFC-3PCF-vertex (default: no such factor) */
+   * father scaling function, Phi-hat(q) = prod_d |phi-hat(2 pi q_d / N)|^2
+   * (sinc^8(pi q_d / N) for the cubic B-spline; the infinite product of the
+   * filter's |m0|^2 for Daubechies-4), as in Eq. SFC-3PCF-vertex (default: no
+   * such factor) */
   MP3_KF_PHI_HAT = 1u << 0,
   /* validate inputs on the device before using them: mp3_deposit checks the
    * positions and weights, the zeta / backward / value-and-grad calls check
@@ -119,7 +133,7 @@ typedef struct {
   int32_t precision;      /* enum mp3_precision                                     */
   int32_t summation;      /* enum mp3_summation                                     */
   int32_t batch;          /* mocks per call, >= 1                                   */
-  int32_t basis;          /* enum mp3_basis (0)                                     */
+  int32_t basis;          /* enum mp3_basis                                         */
   uint32_t kflags;        /* OR of enum mp3_kflags (0 = none)                       */
   int32_t binning;        /* enum mp3_binning                                       */
   double smoothing;       /* radius R >= 0 of the spherical top-hat window assigned
@@ -416,6 +430,18 @@ int mp3_sph_bessel(int32_t lmax, double x, double* out);
  * W_TH = 1 when desc->smoothing = 0.  count must be (lmax+1) nq2 nbins.
  * Validates desc as mp3_plan_create does. */
 int mp3_window_table(const mp3_plan_desc* desc, double* out, size_t count);
+
+/* Host tables of a basis (Sec. 3, the basis paragraph; Eq. SFC-3PCF-vertex),
+ * computed without a GPU as mp3_plan_create does; any output may be NULL:
+ *   table[i] = phi(i / 1024), i = 0 .. 3072 (table_count must be 3073),
+ *              Daubechies-4 only (NULL for the B-spline);
+ *   acf[s]   = int phi(x) phi(x - s) dx, s = 0 .. 3, of the basis as the
+ *              deposit uses it (the autocorrelation of the particle form's
+ *              volume mean);
+ *   phi_hat[i] = |phi-hat(2 pi q / n)|^2, q = i for i < n/2 else i - n
+ *              (n a supported grid size).
+ * Returns MP3_EINVAL for an unknown basis or a wrong count. */
+int mp3_basis_tables(int32_t basis, int32_t n, double* table, size_t table_count, double* acf, double* phi_hat);
 
 /* Human-readable name of a status code (static storage). */
 const char* mp3_status_string(int status);

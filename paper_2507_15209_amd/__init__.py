@@ -47,16 +47,19 @@ class Plan:
     top-hat window on every vertex (0 = none).  phi_hat: multiply the
     secondary windows by the scaling function's power spectrum.
     check_finite: validate inputs on the device (calls then block).
+    basis "b3": centred cubic B-spline; "d4": Daubechies-4 scaling function
+    (nodal and particle summation).
     """
 
     PRECISIONS = {"f32": _lib.MP3_F32, "f64": _lib.MP3_F64, "bf16x3": _lib.MP3_F32_BF16X3}
     SUMMATIONS = {"nodal": _lib.MP3_SUM_NODAL, "gamma": _lib.MP3_SUM_GRID_GAMMA, "particle": _lib.MP3_SUM_PARTICLE}
 
     BINNINGS = {"shell": _lib.MP3_BIN_SHELL_AVERAGE, "thin": _lib.MP3_BIN_THIN_SHELL}
+    BASES = {"b3": _lib.MP3_BASIS_BSPLINE3, "d4": _lib.MP3_BASIS_DAUBECHIES4}
 
     def __init__(self, n: int, box: float, lmax: int, edges, precision: str = "f32", batch: int = 1,
                  device=None, summation: str = "nodal", binning: str = "shell", smoothing: float = 0.0,
-                 phi_hat: bool = False, check_finite: bool = False):
+                 phi_hat: bool = False, check_finite: bool = False, basis: str = "b3"):
         self.lib = _lib.load()
         self.n, self.box, self.lmax, self.batch = int(n), float(box), int(lmax), int(batch)
         self.edges = np.ascontiguousarray(edges, dtype=np.float64)
@@ -70,6 +73,9 @@ class Plan:
         if binning not in self.BINNINGS:
             raise ValueError(f"binning must be one of {sorted(self.BINNINGS)}")
         self.binning, self.smoothing = binning, float(smoothing)
+        if basis not in self.BASES:
+            raise ValueError(f"basis must be one of {sorted(self.BASES)}")
+        self.basis = basis
         kflags = (_lib.MP3_KF_PHI_HAT if phi_hat else 0) | (_lib.MP3_KF_CHECK_FINITE if check_finite else 0)
         self.real_dtype = torch.float64 if precision == "f64" else torch.float32
         self.complex_dtype = torch.complex128 if precision == "f64" else torch.complex64
@@ -77,7 +83,7 @@ class Plan:
         desc = _lib.PlanDesc(self.n, self.box, self.lmax, self.nbins,
                              self.edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                              self.PRECISIONS[precision],
-                             self.SUMMATIONS[summation], self.batch, _lib.MP3_BASIS_BSPLINE3, kflags,
+                             self.SUMMATIONS[summation], self.batch, self.BASES[basis], kflags,
                              self.BINNINGS[binning], self.smoothing)
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):

@@ -21,6 +21,7 @@ MP3_SUM_NODAL = 0
 MP3_SUM_PARTICLE = 2
 MP3_SUM_GRID_GAMMA = 1
 MP3_BASIS_BSPLINE3 = 0
+MP3_BASIS_DAUBECHIES4 = 1
 MP3_BIN_SHELL_AVERAGE = 0
 MP3_BIN_THIN_SHELL = 1
 MP3_KF_PHI_HAT = 1
@@ -37,6 +38,7 @@ EXPORTS = (
     "mp3_tune_set", "mp3_tune_get", "mp3_zeta_value_and_grad", "mp3_xi", "mp3_xi_multipoles", "mp3_reduced_3pcf",
     "mp3_ss_fields", "mp3_ss_multipoles",
     "mp3_sph_bessel", "mp3_window_table", "mp3_zeta_value_and_grad_static", "mp3_static_scratch_bytes",
+    "mp3_basis_tables",
 )
 PASSES = ("dft", "filter", "x", "z_nodal", "z_adjoint", "adjoint", "deposit", "z_store", "gather", "gamma",
           "scatter", "z_fused")
@@ -106,6 +108,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.mp3_reduced_3pcf.argtypes = [vp, vp, vp, i32, ctypes.POINTER(ctypes.c_double), i32, vp, vp, vp, sz, vp]
     lib.mp3_sph_bessel.argtypes = [i32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
     lib.mp3_window_table.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(ctypes.c_double), sz]
+    lib.mp3_basis_tables.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_double), sz, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
     lib.mp3_zeta_value_and_grad_static.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i64), vp, vp]
     lib.mp3_static_scratch_bytes.argtypes = []
     lib.mp3_status_string.argtypes = [ctypes.c_int]

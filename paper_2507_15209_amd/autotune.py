@@ -43,7 +43,7 @@ def cache_path(path: str | None = None) -> str:
 def cache_key(plan) -> str:
     name = torch.cuda.get_device_name(plan.device) if torch.cuda.is_available() else "nodevice"
     return (f"{name}|n={plan.n}|nbins={plan.nbins}|lmax={plan.lmax}|{plan.summation}|{plan.precision}"
-            f"|batch={plan.batch}")
+            f"|batch={plan.batch}|basis={getattr(plan, 'basis', 'b3')}")
 
 
 def _read(path: str) -> dict:
@@ -142,7 +142,9 @@ def autotune(plan, delta, pos=None, w=None, np_off=None, dzeta=None, backward: b
 
         knobs = ["fft_x_plan", "zpass_wgs"]
         if do_bwd and plan.summation == "nodal":
-            knobs += ["fused_waves", "item_group"]
+            # item_group is left at its default (as many items per launch as fit 1 GiB of fields),
+            # the best or within noise of it wherever it was measured
+            knobs.append("fused_waves")
         if plan.summation != "nodal":
             knobs.append("contract_wgs")
         for k in knobs:

@@ -235,17 +235,21 @@ struct Taps {
   bool ok;
 };
 
-// weight of tap a (0..3) at fractional position f: the same expressions as make_taps
-__device__ __forceinline__ double b3_tap(double f, int a) {
-  const double g = 1.0 - f;
-  const double w0 = g * g * g / 6.0;
-  const double w1 = (4.0 - 6.0 * f * f + 3.0 * f * f * f) / 6.0;
-  const double w2 = (4.0 - 6.0 * g * g + 3.0 * g * g * g) / 6.0;
-  const double w3 = f * f * f / 6.0;
-  return a == 0 ? w0 : (a == 1 ? w1 : (a == 2 ? w2 : w3));
+// Daubechies-4: phi at x by linear interpolation of its values at the dyadic
+// points i / 2^kD4Level of [0, 3] (tab), zero outside [0, 3)
+__device__ __forceinline__ double d4_phi(const double* tab, double x) {
+  if (!(x >= 0.0) || x >= 3.0) return 0.0;
+  const double s = x * (double)(1 << kD4Level);
+  const double fl = floor(s);
+  const int i = (int)fl;
+  const double fr = s - fl;
+  return (1.0 - fr) * tab[i] + fr * tab[i + 1];
 }
 
-__device__ __forceinline__ Taps make_taps(const float* p, int n, double sc) {
+// Stencil of a particle: nodes base .. base + 3 per axis (base = floor(u) - 1)
+// with the cubic B-spline weights B3(u - node), or with btab (Daubechies-4,
+// node l carrying phi(u - l + 1)) the weights phi(f + 2 - a), the last zero.
+__device__ __forceinline__ Taps make_taps(const float* p, int n, double sc, const double* btab) {
   Taps t;
   t.ok = true;
 #pragma unroll
@@ -259,11 +263,16 @@ __device__ __forceinline__ Taps make_taps(const float* p, int n, double sc) {
     if (ib >= n) { ib -= n; }
     t.base[d] = ib - 1;
     t.f[d] = f;
-    const double g = 1.0 - f;
-    t.wt[d][0] = g * g * g / 6.0;
-    t.wt[d][1] = (4.0 - 6.0 * f * f + 3.0 * f * f * f) / 6.0;
-    t.wt[d][2] = (4.0 - 6.0 * g * g + 3.0 * g * g * g) / 6.0;
-    t.wt[d][3] = f * f * f / 6.0;
+    if (btab) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) t.wt[d][a] = d4_phi(btab, f + 2.0 - (double)a);
+    } else {
+      const double g = 1.0 - f;
+      t.wt[d][0] = g * g * g / 6.0;
+      t.wt[d][1] = (4.0 - 6.0 * f * f + 3.0 * f * f * f) / 6.0;
+      t.wt[d][2] = (4.0 - 6.0 * g * g + 3.0 * g * g * g) / 6.0;
+      t.wt[d][3] = f * f * f / 6.0;
+    }
   }
   return t;
 }
@@ -282,11 +291,11 @@ __global__ void k_normalise(T* eps, const double* W, long long n3) {
 // dw_i = (N^3 / W) sum_taps B g - S / W
 template <typename T>
 __global__ void k_gather_dw(const float* pos, const long long* off, int batch, long long np_total, int n, double sc,
-                            const T* g, const double* W, const double* S, T* dw) {
+                            const T* g, const double* W, const double* S, T* dw, const double* btab) {
   const long long n3 = (long long)n * n * n;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < np_total; i += (long long)gridDim.x * blockDim.x) {
     const int mock = find_mock(off, batch, i);
-    Taps t = make_taps(pos + 3 * i, n, sc);
+    Taps t = make_taps(pos + 3 * i, n, sc, btab);
     double acc = 0.0;
     if (t.ok) {
       const T* gg = g + mock * n3;
@@ -1062,9 +1071,9 @@ __device__ __forceinline__ int pack_cell(const Taps& t) {
 
 template <typename T>
 __global__ void k_tap_records(const float* pos, const int* perm, long long np_total, int n, double sc, int* tcell,
-                              T* twt) {
+                              T* twt, const double* btab) {
   for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < np_total; k += (long long)gridDim.x * blockDim.x) {
-    const Taps t = make_taps(pos + 3 * (long long)perm[k], n, sc);
+    const Taps t = make_taps(pos + 3 * (long long)perm[k], n, sc, btab);
     tcell[k] = pack_cell(t);
 #pragma unroll
     for (int d = 0; d < 3; ++d)
@@ -1363,14 +1372,18 @@ __global__ void __launch_bounds__(1024) k_gamma_contract(const c2<T>* fields, co
              nbins);
 }
 
-// P[mock][s] += |dhat(q)|^2 B7hat(q) over q with |q|^2 = s, Nyquist planes excluded.
-// B7hat(theta) = sum_s B7(s) e^{-i theta s} with the cubic B-spline
-// autocorrelation samples B7(0) = 2416/5040, B7(1) = 1191/5040, B7(2) = 120/5040,
-// B7(3) = 1/5040.
+// sum_s A(s) e^{-i theta s} over the autocorrelation samples of the basis
+__device__ __forceinline__ double acf_hat(const Acf& c, double th) {
+  return c.a[0] + 2.0 * (c.a[1] * cos(th) + c.a[2] * cos(2.0 * th) + c.a[3] * cos(3.0 * th));
+}
+
+// P[mock][s] += |dhat(q)|^2 Ahat(q) over q with |q|^2 = s, Nyquist planes excluded,
+// Ahat = prod_d acf_hat(theta_d) (for the cubic B-spline the samples are
+// A(0..3) = (2416, 1191, 120, 1) / 5040).
 // phi != NULL: each term also carries phi-hat(q)^2 (both secondary vertices
 // of the volume mean carry the scaling function's power spectrum)
 template <typename T>
-__global__ void k_power_hist(const c2<T>* dhat, int n, int nq2, double* P, const T* phi) {
+__global__ void k_power_hist(const c2<T>* dhat, int n, int nq2, double* P, const T* phi, Acf acf) {
   const long long n3 = (long long)n * n * n;
   const int mock = blockIdx.y;
   const c2<T>* d = dhat + mock * n3;
@@ -1384,10 +1397,7 @@ __global__ void k_power_hist(const c2<T>* dhat, int n, int nq2, double* P, const
     double b7 = 1.0;
     const int qs[3] = {qx, qy, qz};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double th = tp * qs[a];
-      b7 *= (2416.0 + 2382.0 * cos(th) + 240.0 * cos(2.0 * th) + 2.0 * cos(3.0 * th)) / 5040.0;
-    }
+    for (int a = 0; a < 3; ++a) b7 *= acf_hat(acf, tp * qs[a]);
     if (phi) {
       const double ph = (double)phi[ix] * (double)phi[iy] * (double)phi[iz];
       b7 *= ph * ph;
@@ -2683,7 +2693,7 @@ __global__ void k_fbar_weight(const double* dzeta, const T* jtab, int nq2, int n
 // the final transform
 template <typename T>
 __global__ void k_fbar_adjoint(const c2<T>* dhat, const double* h, int n, int nq2, double scale, c2<T>* G,
-                               const T* phi) {
+                               const T* phi, Acf acf) {
   const long long n3 = (long long)n * n * n;
   const int mock = blockIdx.y;
   const c2<T>* d = dhat + mock * n3;
@@ -2698,10 +2708,7 @@ __global__ void k_fbar_adjoint(const c2<T>* dhat, const double* h, int n, int nq
     double b7 = 1.0;
     const int qs[3] = {qx, qy, qz};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double th = tp * qs[a];
-      b7 *= (2416.0 + 2382.0 * cos(th) + 240.0 * cos(2.0 * th) + 2.0 * cos(3.0 * th)) / 5040.0;
-    }
+    for (int a = 0; a < 3; ++a) b7 *= acf_hat(acf, tp * qs[a]);
     if (phi) {
       const double ph = (double)phi[ix] * (double)phi[iy] * (double)phi[iz];
       b7 *= ph * ph;
@@ -3187,14 +3194,15 @@ hipError_t launch_dot_rho_g(int prec, const void* delta, const void* g, long lon
 }
 
 hipError_t launch_gather_dw(int prec, const float* pos, const long long* off, int batch, long long np_total, int n,
-                            double sc, const void* g, const double* W, const double* S, void* dw, hipStream_t st) {
+                            double sc, const void* g, const double* W, const double* S, void* dw, const double* btab,
+                            hipStream_t st) {
   const unsigned gr = grid_for(np_total, 256, 16384);
   if (prec)
     k_gather_dw<double><<<gr, 256, 0, st>>>(pos, off, batch, np_total, n, sc, static_cast<const double*>(g), W, S,
-                                            static_cast<double*>(dw));
+                                            static_cast<double*>(dw), btab);
   else
     k_gather_dw<float><<<gr, 256, 0, st>>>(pos, off, batch, np_total, n, sc, static_cast<const float*>(g), W, S,
-                                           static_cast<float*>(dw));
+                                           static_cast<float*>(dw), btab);
   return hipGetLastError();
 }
 
@@ -3220,7 +3228,7 @@ hipError_t launch_tile_sort(const float* pos, const long long* off, int batch, l
 template <typename T, int TS>
 __global__ void __launch_bounds__(256) k_deposit_tiled(const float* pos, const float* w, const int* perm,
                                                        const int* toff, int ntiles_total, int* counter, int n,
-                                                       double sc, T* eps) {
+                                                       double sc, T* eps, const double* btab) {
   constexpr int TB = TS + 3;
   __shared__ T acc[TB * TB * TB];
   __shared__ int item_sh;
@@ -3242,7 +3250,7 @@ __global__ void __launch_bounds__(256) k_deposit_tiled(const float* pos, const f
     __syncthreads();
     for (int k = a + threadIdx.x; k < b; k += blockDim.x) {
       const int i = perm[k];
-      Taps tp = make_taps(pos + 3 * (long long)i, n, sc);
+      Taps tp = make_taps(pos + 3 * (long long)i, n, sc, btab);
       if (!tp.ok) continue;
       const double wi = w ? (double)w[i] : 1.0;
       const int lx = tp.base[0] - ox, ly = tp.base[1] - oy, lz = tp.base[2] - oz;   // in [0, TS)
@@ -3273,23 +3281,28 @@ __global__ void __launch_bounds__(256) k_deposit_tiled(const float* pos, const f
 
 template <typename T>
 hipError_t deposit_tiled_t(int tside, const float* pos, const float* w, const int* perm, const int* toff,
-                           int ntiles_total, unsigned g, int* counter, int n, double sc, T* eps, hipStream_t st) {
+                           int ntiles_total, unsigned g, int* counter, int n, double sc, T* eps, const double* btab,
+                           hipStream_t st) {
   switch (tside) {
-    case 4: k_deposit_tiled<T, 4><<<g, 256, 0, st>>>(pos, w, perm, toff, ntiles_total, counter, n, sc, eps); break;
-    case 8: k_deposit_tiled<T, 8><<<g, 256, 0, st>>>(pos, w, perm, toff, ntiles_total, counter, n, sc, eps); break;
-    case 16: k_deposit_tiled<T, 16><<<g, 256, 0, st>>>(pos, w, perm, toff, ntiles_total, counter, n, sc, eps); break;
+    case 4: k_deposit_tiled<T, 4><<<g, 256, 0, st>>>(pos, w, perm, toff, ntiles_total, counter, n, sc, eps, btab); break;
+    case 8: k_deposit_tiled<T, 8><<<g, 256, 0, st>>>(pos, w, perm, toff, ntiles_total, counter, n, sc, eps, btab); break;
+    case 16: k_deposit_tiled<T, 16><<<g, 256, 0, st>>>(pos, w, perm, toff, ntiles_total, counter, n, sc, eps, btab); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_deposit_tiled(int prec, int tside, const float* pos, const float* w, const int* perm, const int* toff,
-                                int ntiles_total, int wgs, int* counter, int n, double sc, void* eps, hipStream_t st) {
+                                int ntiles_total, int wgs, int* counter, int n, double sc, void* eps, const double* btab,
+                                hipStream_t st) {
   if (ntiles_total <= 0 || wgs <= 0 || tside <= 0 || n % tside != 0) return hipErrorInvalidValue;
   k_fill<int><<<1, 64, 0, st>>>(counter, 1, 0);
   const unsigned g = (unsigned)(ntiles_total < wgs ? ntiles_total : wgs);
-  if (prec) return deposit_tiled_t<double>(tside, pos, w, perm, toff, ntiles_total, g, counter, n, sc, static_cast<double*>(eps), st);
-  return deposit_tiled_t<float>(tside, pos, w, perm, toff, ntiles_total, g, counter, n, sc, static_cast<float*>(eps), st);
+  if (prec)
+    return deposit_tiled_t<double>(tside, pos, w, perm, toff, ntiles_total, g, counter, n, sc,
+                                   static_cast<double*>(eps), btab, st);
+  return deposit_tiled_t<float>(tside, pos, w, perm, toff, ntiles_total, g, counter, n, sc, static_cast<float*>(eps),
+                                btab, st);
 }
 
 template <typename T, bool MF, bool SPLIT, bool QUAD, bool SRC>
@@ -3330,13 +3343,13 @@ hipError_t launch_gather_contract(int prec, const GatherArgs& a, hipStream_t st)
 }
 
 hipError_t launch_power_hist(int prec, const void* dhat, int n, int nq2, double* P, int batch, const void* phi,
-                             hipStream_t st) {
+                             const Acf& acf, hipStream_t st) {
   const long long n3 = (long long)n * n * n;
   const dim3 gs(grid_for(n3, 256, 8192), batch);
   if (prec) k_power_hist<double><<<gs, 256, 0, st>>>(static_cast<const double2*>(dhat), n, nq2, P,
-                                                    static_cast<const double*>(phi));
+                                                    static_cast<const double*>(phi), acf);
   else k_power_hist<float><<<gs, 256, 0, st>>>(static_cast<const float2*>(dhat), n, nq2, P,
-                                                  static_cast<const float*>(phi));
+                                                  static_cast<const float*>(phi), acf);
   return hipGetLastError();
 }
 
@@ -3501,27 +3514,28 @@ hipError_t launch_scatter_source(int prec, const int* tcell, const void* twt, co
 }
 
 hipError_t launch_tap_records(int prec, const float* pos, const int* perm, long long np_total, int n, double sc,
-                              int* tcell, void* twt, hipStream_t st) {
+                              int* tcell, void* twt, const double* btab, hipStream_t st) {
   const unsigned g = grid_for(np_total, 256, 16384);
-  if (prec) k_tap_records<double><<<g, 256, 0, st>>>(pos, perm, np_total, n, sc, tcell, static_cast<double*>(twt));
-  else k_tap_records<float><<<g, 256, 0, st>>>(pos, perm, np_total, n, sc, tcell, static_cast<float*>(twt));
+  if (prec)
+    k_tap_records<double><<<g, 256, 0, st>>>(pos, perm, np_total, n, sc, tcell, static_cast<double*>(twt), btab);
+  else k_tap_records<float><<<g, 256, 0, st>>>(pos, perm, np_total, n, sc, tcell, static_cast<float*>(twt), btab);
   return hipGetLastError();
 }
 
 hipError_t launch_fbar_adjoint(int prec, const double* dzeta, const void* jtab, int nq2, int nbp, int nbins, int lmax,
                                const void* dhat, int n, double scale, double* h, void* G, int batch, const void* phi,
-                               hipStream_t st) {
+                               const Acf& acf, hipStream_t st) {
   const dim3 gh(grid_for(nq2, 256, 1024), batch);
   const long long n3 = (long long)n * n * n;
   const dim3 gs(grid_for(n3, 256, 8192), batch);
   if (prec) {
     k_fbar_weight<double><<<gh, 256, 0, st>>>(dzeta, static_cast<const double*>(jtab), nq2, nbp, nbins, lmax, h);
     k_fbar_adjoint<double><<<gs, 256, 0, st>>>(static_cast<const double2*>(dhat), h, n, nq2, scale,
-                                               static_cast<double2*>(G), static_cast<const double*>(phi));
+                                               static_cast<double2*>(G), static_cast<const double*>(phi), acf);
   } else {
     k_fbar_weight<float><<<gh, 256, 0, st>>>(dzeta, static_cast<const float*>(jtab), nq2, nbp, nbins, lmax, h);
     k_fbar_adjoint<float><<<gs, 256, 0, st>>>(static_cast<const float2*>(dhat), h, n, nq2, scale,
-                                              static_cast<float2*>(G), static_cast<const float*>(phi));
+                                              static_cast<float2*>(G), static_cast<const float*>(phi), acf);
   }
   return hipGetLastError();
 }

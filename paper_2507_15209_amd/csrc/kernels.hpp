@@ -16,6 +16,15 @@ struct YlmRec {
 
 // One (l, m) work item of a call: everything the window passes need, kept in
 // a device table (the workspace) for every item of the call.
+// Daubechies-4 table: phi at i / 2^kD4Level, i = 0 .. 3 2^kD4Level
+constexpr int kD4Level = 10;
+constexpr int kD4TableSize = 3 * (1 << kD4Level) + 1;
+
+// autocorrelation samples A(s) = int phi(x) phi(x - s) dx, s = 0 .. 3, of the basis
+struct Acf {
+  double a[4];
+};
+
 struct ItemRec {
   int l, m;
   double norm;       // Y_lm normalisation
@@ -112,12 +121,15 @@ hipError_t launch_tile_sort(const float* pos, const long long* off, int batch, l
                             int shift, int* counts, int* offs, int* cursor, int* perm, hipStream_t st);
 // persistent tiled deposit over tiles of side tside (4, 8, 16) with at most
 // wgs workgroups; toff from launch_tile_sort with shift log2(tside)
+// btab: NULL for the cubic B-spline, else the Daubechies-4 table (kD4TableSize doubles)
 hipError_t launch_deposit_tiled(int prec, int tside, const float* pos, const float* w, const int* perm, const int* toff,
-                                int ntiles_total, int wgs, int* counter, int n, double sc, void* eps, hipStream_t st);
+                                int ntiles_total, int wgs, int* counter, int n, double sc, void* eps, const double* btab,
+                                hipStream_t st);
 hipError_t launch_gather_contract(int prec, const GatherArgs& a, hipStream_t st);
-// per-|q|^2 histogram of |dhat|^2 B7hat (times phi-hat^2 when phi != NULL), Nyquist planes excluded
+// per-|q|^2 histogram of |dhat|^2 Ahat (the basis autocorrelation's transform; times phi-hat^2
+// when phi != NULL), Nyquist planes excluded
 hipError_t launch_power_hist(int prec, const void* dhat, int n, int nq2, double* P, int batch, const void* phi,
-                             hipStream_t st);
+                             const Acf& acf, hipStream_t st);
 hipError_t launch_fbar_subtract(int prec, const double* P, const void* jtab, int nq2, int nbp, int nbins, int l, int lmax,
                                 double n6, double* zeta, int batch, hipStream_t st);
 hipError_t launch_fft3d(int n, int prec, int dir, bool real_in, const void* in, void* out, int nfields, const void* tw,
@@ -159,10 +171,10 @@ hipError_t launch_scatter_source(int prec, const int* tcell, const void* twt, co
 // per-particle stencil records in sorted order: packed cell (-1 if not
 // finite) and 12 tap weights in the working precision
 hipError_t launch_tap_records(int prec, const float* pos, const int* perm, long long np_total, int n, double sc,
-                              int* tcell, void* twt, hipStream_t st);
+                              int* tcell, void* twt, const double* btab, hipStream_t st);
 hipError_t launch_fbar_adjoint(int prec, const double* dzeta, const void* jtab, int nq2, int nbp, int nbins, int lmax,
                                const void* dhat, int n, double scale, double* h, void* G, int batch, const void* phi,
-                               hipStream_t st);
+                               const Acf& acf, hipStream_t st);
 // grid-Gamma adjoint for one (l, m): adds the transposed-quadrature sources
 // into cout ([batch][nbins][N^3], zeroed by the caller) and wm times the
 // primary's share into direct; fields bin-interleaved, at most 20 bins.
@@ -179,7 +191,8 @@ hipError_t launch_grad_combine(int prec, const void* direct, const void* ghat, v
                                hipStream_t st);
 hipError_t launch_dot_rho_g(int prec, const void* delta, const void* g, long long n3, double* S, int batch, hipStream_t st);
 hipError_t launch_gather_dw(int prec, const float* pos, const long long* off, int batch, long long np_total, int n,
-                            double sc, const void* g, const double* W, const double* S, void* dw, hipStream_t st);
+                            double sc, const void* g, const double* W, const double* S, void* dw, const double* btab,
+                            hipStream_t st);
 
 // stats.hip: input validation, the top-hat filter of the primary vertex, xi and Q
 // flag[0] += 1 when any of count values (float or double by prec) is NaN or infinite

@@ -30,6 +30,8 @@ struct mp3_plan_s {
   unsigned kflags = 0;
   double smoothing = 0.0;   // top-hat radius of every vertex (0 = none)
   void* phi = nullptr;      // [n] real per-axis phi-hat factors when MP3_KF_PHI_HAT
+  double* btab = nullptr;   // Daubechies-4 basis: phi at the dyadic points (NULL for the B-spline)
+  mp3::Acf acf{{2416.0 / 5040.0, 1191.0 / 5040.0, 120.0 / 5040.0, 1.0 / 5040.0}};   // basis autocorrelation
   std::vector<mp3::ItemRec> items;   // every (l, m >= 0) of the plan, index l (l + 1) / 2 + m
   mp3::ItemRec* items_dev = nullptr; // the same table on the device
   // optional per-pass HIP event timing
@@ -211,7 +213,10 @@ int validate_desc(const mp3_plan_desc* d) {
   if (d->summation != MP3_SUM_NODAL && d->summation != MP3_SUM_PARTICLE && d->summation != MP3_SUM_GRID_GAMMA)
     return fail(MP3_EUNSUPPORTED, "summation form not supported");
   if (d->batch < 1) return fail(MP3_EINVAL, "batch must be >= 1");
-  if (d->basis != MP3_BASIS_BSPLINE3) return fail(MP3_EUNSUPPORTED, "only the cubic B-spline basis is implemented");
+  if (d->basis != MP3_BASIS_BSPLINE3 && d->basis != MP3_BASIS_DAUBECHIES4)
+    return fail(MP3_EINVAL, "basis must be MP3_BASIS_BSPLINE3 or MP3_BASIS_DAUBECHIES4");
+  if (d->basis == MP3_BASIS_DAUBECHIES4 && d->summation == MP3_SUM_GRID_GAMMA)
+    return fail(MP3_EUNSUPPORTED, "the grid-Gamma form is built for the cubic B-spline basis only");
   if (d->kflags & ~kKnownFlags) return fail(MP3_EINVAL, "unknown kflags bits");
   if (d->binning != MP3_BIN_SHELL_AVERAGE && d->binning != MP3_BIN_THIN_SHELL)
     return fail(MP3_EINVAL, "binning must be MP3_BIN_SHELL_AVERAGE or MP3_BIN_THIN_SHELL");
@@ -520,9 +525,17 @@ int mp3_plan_create(const mp3_plan_desc* d, mp3_plan_t* out) {
   const size_t ib = p->items.size() * sizeof(mp3::ItemRec);
   hipError_t e4 = hipMalloc(&p->items_dev, ib);
   if (e4 == hipSuccess) e4 = hipMemcpy(p->items_dev, p->items.data(), ib, hipMemcpyHostToDevice);
+  if (p->basis == MP3_BASIS_DAUBECHIES4 && e4 == hipSuccess) {
+    std::vector<double> tab;
+    mp3::d4_table(mp3::kD4Level, tab);
+    mp3::d4_autocorr(tab, mp3::kD4Level, p->acf.a);
+    e4 = hipMalloc(&p->btab, tab.size() * sizeof(double));
+    if (e4 == hipSuccess) e4 = hipMemcpy(p->btab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
+  }
   if (p->kflags & MP3_KF_PHI_HAT) {
     std::vector<double> ph;
-    mp3::phi_hat_axis(p->n, ph);
+    if (p->basis == MP3_BASIS_DAUBECHIES4) mp3::d4_phi_hat_axis(p->n, ph);
+    else mp3::phi_hat_axis(p->n, ph);
     std::vector<char> hp((size_t)p->n * p->elt);
     for (int i = 0; i < p->n; ++i) {
       if (p->prec) reinterpret_cast<double*>(hp.data())[i] = ph[i];
@@ -536,6 +549,7 @@ int mp3_plan_create(const mp3_plan_desc* d, mp3_plan_t* out) {
     hipFree(p->tw);
     if (p->phi) hipFree(p->phi);
     if (p->items_dev) hipFree(p->items_dev);
+    if (p->btab) hipFree(p->btab);
     delete p;
     const hipError_t e = e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : (e3 != hipSuccess ? e3 : e4));
     return hip_fail(e, "upload plan tables");
@@ -572,6 +586,7 @@ int mp3_plan_destroy(mp3_plan_t p) {
   if (p->tw) hipFree(p->tw);
   if (p->phi) hipFree(p->phi);
   if (p->items_dev) hipFree(p->items_dev);
+  if (p->btab) hipFree(p->btab);
   delete p;
   return MP3_OK;
 }
@@ -659,7 +674,7 @@ int mp3_deposit(mp3_plan_t p, const float* pos, const float* w, const int64_t* n
                                                  reinterpret_cast<int*>(at(ws, L.dcursor)), dperm, st);
             if (e != hipSuccess) return e;
             return mp3::launch_deposit_tiled(p->prec, tside, pos, w, dperm, doffs, ntiles, p->tune[MP3_TUNE_DEPOSIT_WGS],
-                                             reinterpret_cast<int*>(at(ws, L.dcounter)), p->n, sc, delta, st);
+                                             reinterpret_cast<int*>(at(ws, L.dcounter)), p->n, sc, delta, p->btab, st);
           }),
           "deposit");
   MP3_HIP(mp3::launch_normalise(p->prec, delta, W, n3, p->batch, st), "normalise");
@@ -778,11 +793,11 @@ int zeta_particle(mp3_plan_t p, const float* pos, const float* w, const int64_t*
           "tile sort");
   int* tcell = reinterpret_cast<int*>(at(ws, L.tcell));
   void* twt = at(ws, L.twt);
-  MP3_HIP(mp3::launch_tap_records(p->prec, pos, perm, np_total, p->n, sc, tcell, twt, st), "stencil records");
+  MP3_HIP(mp3::launch_tap_records(p->prec, pos, perm, np_total, p->n, sc, tcell, twt, p->btab, st), "stencil records");
   double* P = reinterpret_cast<double*>(at(ws, L.power));
   const int nq2 = mp3::nq2_count(p->n);
   MP3_HIP(mp3::launch_fill_f64(P, (long long)p->batch * nq2, 0.0, st), "zero power");
-  MP3_HIP(mp3::launch_power_hist(p->prec, at(ws, L.dhat), p->n, nq2, P, p->batch, p->phi, st), "power histogram");
+  MP3_HIP(mp3::launch_power_hist(p->prec, at(ws, L.dhat), p->n, nq2, P, p->batch, p->phi, p->acf, st), "power histogram");
   void* F = at(ws, L.fields);
   void* Fi = at(ws, L.fields_i);
   double* partials = reinterpret_cast<double*>(at(ws, L.partials));
@@ -903,7 +918,7 @@ int nodal_gradient_tail(mp3_plan_t p, const void* delta, void* ddelta, const flo
     MP3_HIP(mp3::launch_fill_f64(S, p->batch, 0.0, st), "zero S");
     MP3_HIP(mp3::launch_weight_sum(w, off, p->batch, np_max, W, st), "weight sum");
     MP3_HIP(mp3::launch_dot_rho_g(p->prec, delta, ddelta, n3, S, p->batch, st), "dot");
-    MP3_HIP(mp3::launch_gather_dw(p->prec, pos, off, p->batch, np_total, p->n, (double)p->n / p->box, ddelta, W, S, dw, st),
+    MP3_HIP(mp3::launch_gather_dw(p->prec, pos, off, p->batch, np_total, p->n, (double)p->n / p->box, ddelta, W, S, dw, p->btab, st),
             "gather dw");
   }
   return MP3_OK;
@@ -941,7 +956,7 @@ int backward_particle(mp3_plan_t p, const void* delta, const double* dzeta, void
           "tile sort");
   int* tcell = reinterpret_cast<int*>(at(ws, L.tcell));
   void* twt = at(ws, L.twt);
-  MP3_HIP(mp3::launch_tap_records(p->prec, pos, perm, np_total, p->n, sc, tcell, twt, st), "stencil records");
+  MP3_HIP(mp3::launch_tap_records(p->prec, pos, perm, np_total, p->n, sc, tcell, twt, p->btab, st), "stencil records");
   void* F = at(ws, L.fields);
   void* Fi = at(ws, L.fields_i);
   void* G = at(ws, L.G);
@@ -983,7 +998,7 @@ int backward_particle(mp3_plan_t p, const void* delta, const double* dzeta, void
   }
   MP3_HIP(mp3::launch_fbar_adjoint(p->prec, dzeta, p->jtab, p->nq2, p->nbp, p->nbins, p->lmax, at(ws, L.dhat), p->n,
                                    -1.0 / (kFourPi * (double)n3), reinterpret_cast<double*>(at(ws, L.hq)), G, p->batch,
-                                   p->phi, st),
+                                   p->phi, p->acf, st),
           "volume-mean adjoint");
   MP3_HIP(timed(p, MP3_PASS_DFT, st, [&] { return mp3::launch_fft3d(p->n, p->prec, -1, false, G, G, p->batch, p->tw, st); }), "adjoint final FFT");
   MP3_HIP(mp3::launch_grad_combine(p->prec, direct, G, ddelta, n3 * p->batch, kFourPi / (double)n3, st), "combine");
@@ -993,7 +1008,7 @@ int backward_particle(mp3_plan_t p, const void* delta, const double* dzeta, void
     MP3_HIP(mp3::launch_fill_f64(S, p->batch, 0.0, st), "zero S");
     MP3_HIP(mp3::launch_fill_f64(SF, p->batch, 0.0, st), "zero SF");
     MP3_HIP(mp3::launch_dot_rho_g(p->prec, delta, ddelta, n3, S, p->batch, st), "dot");
-    MP3_HIP(mp3::launch_gather_dw(p->prec, pos, off, p->batch, np_total, p->n, sc, ddelta, W, S, dw, st), "gather dw");
+    MP3_HIP(mp3::launch_gather_dw(p->prec, pos, off, p->batch, np_total, p->n, sc, ddelta, W, S, dw, p->btab, st), "gather dw");
     MP3_HIP(mp3::launch_weighted_sum(w, FJ, off, p->batch, np_max, SF, st), "sum w F_J");
     MP3_HIP(mp3::launch_primary_dw(p->prec, off, p->batch, np_total, FJ, W, SF, dw, st), "primary dw");
   }
@@ -1037,11 +1052,11 @@ int value_and_grad_particle(mp3_plan_t p, const void* delta, const double* dzeta
           "tile sort");
   int* tcell = reinterpret_cast<int*>(at(ws, L.tcell));
   void* twt = at(ws, L.twt);
-  MP3_HIP(mp3::launch_tap_records(p->prec, pos, perm, np_total, p->n, sc, tcell, twt, st), "stencil records");
+  MP3_HIP(mp3::launch_tap_records(p->prec, pos, perm, np_total, p->n, sc, tcell, twt, p->btab, st), "stencil records");
   double* P = reinterpret_cast<double*>(at(ws, L.power));
   const int nq2 = mp3::nq2_count(p->n);
   MP3_HIP(mp3::launch_fill_f64(P, (long long)p->batch * nq2, 0.0, st), "zero power");
-  MP3_HIP(mp3::launch_power_hist(p->prec, at(ws, L.dhat), p->n, nq2, P, p->batch, p->phi, st), "power histogram");
+  MP3_HIP(mp3::launch_power_hist(p->prec, at(ws, L.dhat), p->n, nq2, P, p->batch, p->phi, p->acf, st), "power histogram");
   void* F = at(ws, L.fields);
   void* Fi = at(ws, L.fields_i);
   void* G = at(ws, L.G);
@@ -1114,7 +1129,7 @@ int value_and_grad_particle(mp3_plan_t p, const void* delta, const double* dzeta
   }
   MP3_HIP(mp3::launch_fbar_adjoint(p->prec, dzeta, p->jtab, p->nq2, p->nbp, p->nbins, p->lmax, at(ws, L.dhat), p->n,
                                    -1.0 / (kFourPi * n3d), reinterpret_cast<double*>(at(ws, L.hq)), G, p->batch,
-                                   p->phi, st),
+                                   p->phi, p->acf, st),
           "volume-mean adjoint");
   MP3_HIP(timed(p, MP3_PASS_DFT, st, [&] { return mp3::launch_fft3d(p->n, p->prec, -1, false, G, G, p->batch, p->tw, st); }), "adjoint final FFT");
   MP3_HIP(mp3::launch_grad_combine(p->prec, direct, G, ddelta, n3 * p->batch, kFourPi / n3d, st), "combine");
@@ -1124,7 +1139,7 @@ int value_and_grad_particle(mp3_plan_t p, const void* delta, const double* dzeta
     MP3_HIP(mp3::launch_fill_f64(S, p->batch, 0.0, st), "zero S");
     MP3_HIP(mp3::launch_fill_f64(SF, p->batch, 0.0, st), "zero SF");
     MP3_HIP(mp3::launch_dot_rho_g(p->prec, delta, ddelta, n3, S, p->batch, st), "dot");
-    MP3_HIP(mp3::launch_gather_dw(p->prec, pos, off, p->batch, np_total, p->n, sc, ddelta, W, S, dw, st), "gather dw");
+    MP3_HIP(mp3::launch_gather_dw(p->prec, pos, off, p->batch, np_total, p->n, sc, ddelta, W, S, dw, p->btab, st), "gather dw");
     MP3_HIP(mp3::launch_weighted_sum(w, FJ, off, p->batch, np_max, SF, st), "sum w F_J");
     MP3_HIP(mp3::launch_primary_dw(p->prec, off, p->batch, np_total, FJ, W, SF, dw, st), "primary dw");
   }
@@ -1226,7 +1241,7 @@ int backward_gamma(mp3_plan_t p, const void* delta, const double* dzeta, void* d
     MP3_HIP(mp3::launch_fill_f64(S, p->batch, 0.0, st), "zero S");
     MP3_HIP(mp3::launch_weight_sum(w, off, p->batch, np_max, W, st), "weight sum");
     MP3_HIP(mp3::launch_dot_rho_g(p->prec, delta, ddelta, n3, S, p->batch, st), "dot");
-    MP3_HIP(mp3::launch_gather_dw(p->prec, pos, off, p->batch, np_total, p->n, (double)p->n / p->box, ddelta, W, S, dw, st),
+    MP3_HIP(mp3::launch_gather_dw(p->prec, pos, off, p->batch, np_total, p->n, (double)p->n / p->box, ddelta, W, S, dw, p->btab, st),
             "gather dw");
   }
   return MP3_OK;
@@ -1477,6 +1492,37 @@ int mp3_sph_bessel(int32_t lmax, double x, double* out) {
   if (!std::isfinite(x)) return fail(MP3_ENONFINITE, "x is not finite");
   if (x < 0.0) return fail(MP3_EINVAL, "x must be >= 0");
   mp3::sph_bessel_all(lmax, x, out);
+  return MP3_OK;
+}
+
+int mp3_basis_tables(int32_t basis, int32_t n, double* table, size_t table_count, double* acf, double* phi_hat) {
+  if (basis != MP3_BASIS_BSPLINE3 && basis != MP3_BASIS_DAUBECHIES4) return fail(MP3_EINVAL, "unknown basis");
+  if (phi_hat && !pow2_supported(n)) return fail(MP3_EUNSUPPORTED, "n must be one of 16, 32, 64, 128, 256, 512");
+  if (basis == MP3_BASIS_BSPLINE3) {
+    if (table) return fail(MP3_EINVAL, "the cubic B-spline has no tabulated values");
+    if (acf) {
+      const double b7[4] = {2416.0 / 5040.0, 1191.0 / 5040.0, 120.0 / 5040.0, 1.0 / 5040.0};
+      for (int s = 0; s < 4; ++s) acf[s] = b7[s];
+    }
+    if (phi_hat) {
+      std::vector<double> ph;
+      mp3::phi_hat_axis(n, ph);
+      std::copy(ph.begin(), ph.end(), phi_hat);
+    }
+    return MP3_OK;
+  }
+  if (table && table_count != (size_t)mp3::kD4TableSize) return fail(MP3_EINVAL, "table_count must be 3073");
+  if (table || acf) {
+    std::vector<double> tab;
+    mp3::d4_table(mp3::kD4Level, tab);
+    if (table) std::copy(tab.begin(), tab.end(), table);
+    if (acf) mp3::d4_autocorr(tab, mp3::kD4Level, acf);
+  }
+  if (phi_hat) {
+    std::vector<double> ph;
+    mp3::d4_phi_hat_axis(n, ph);
+    std::copy(ph.begin(), ph.end(), phi_hat);
+  }
   return MP3_OK;
 }
 

@@ -178,6 +178,85 @@ void phi_hat_axis(int n, std::vector<double>& out) {
   }
 }
 
+// Daubechies-4 scaling function: four orthonormal filter taps, support [0, 3]
+namespace {
+void d4_filter(double h[4]) {
+  const double s = std::sqrt(3.0), d = 4.0 * std::sqrt(2.0);
+  h[0] = (1.0 + s) / d;
+  h[1] = (3.0 + s) / d;
+  h[2] = (3.0 - s) / d;
+  h[3] = (1.0 - s) / d;
+}
+}  // namespace
+
+void d4_table(int level, std::vector<double>& out) {
+  double h[4];
+  d4_filter(h);
+  const double r2 = std::sqrt(2.0);
+  // at the integers (phi(0) = phi(3) = 0) the two-scale relation
+  // phi(x) = sqrt2 sum_j h_j phi(2x - j) reads phi(1) = sqrt2 (h1 phi(1) + h0 phi(2)),
+  // which fixes phi(2) / phi(1); partition of unity fixes phi(1) + phi(2) = 1
+  const double ratio = (1.0 - r2 * h[1]) / (r2 * h[0]);
+  const double p1 = 1.0 / (1.0 + ratio);
+  std::vector<double> cur = {0.0, p1, ratio * p1, 0.0};
+  // each level doubles the resolution: even points are known, odd points
+  // follow from the relation at the previous level
+  for (int r = 1; r <= level; ++r) {
+    const int half = 1 << (r - 1);
+    std::vector<double> nxt(3 * (1 << r) + 1, 0.0);
+    for (size_t i = 0; i < cur.size(); ++i) nxt[2 * i] = cur[i];
+    for (int i = 1; i < (int)nxt.size(); i += 2) {
+      double acc = 0.0;
+      for (int j = 0; j < 4; ++j) {
+        const int idx = i - j * half;
+        if (idx >= 0 && idx < (int)cur.size()) acc += h[j] * cur[idx];
+      }
+      nxt[i] = r2 * acc;
+    }
+    cur.swap(nxt);
+  }
+  out.swap(cur);
+}
+
+void d4_autocorr(const std::vector<double>& t, int level, double a[4]) {
+  // int phi_R(x) phi_R(x - s) dx of the piecewise-linear interpolant: on each
+  // interval of width h both factors are linear, integrated exactly
+  const double h = std::ldexp(1.0, -level);
+  const int per = 1 << level;
+  for (int s = 0; s < 4; ++s) {
+    const int sh = s * per;
+    double acc = 0.0;
+    for (int i = sh; i + 1 < (int)t.size(); ++i) {
+      const double a0 = t[i], a1 = t[i + 1], b0 = t[i - sh], b1 = t[i + 1 - sh];
+      acc += 2.0 * a0 * b0 + a0 * b1 + a1 * b0 + 2.0 * a1 * b1;
+    }
+    a[s] = acc * h / 6.0;
+  }
+}
+
+void d4_phi_hat_axis(int n, std::vector<double>& out) {
+  // |phi_hat(w)|^2 = prod_{j >= 1} |m0(w / 2^j)|^2 with m0(w) = 2^-1/2 sum_k h_k e^{-i k w},
+  // at w = 2 pi q / n; 64 factors (the last ones are 1 to double precision)
+  double h[4];
+  d4_filter(h);
+  out.resize(n);
+  for (int i = 0; i < n; ++i) {
+    const int q = i < n / 2 ? i : i - n;
+    const double w = 2.0 * M_PI * (double)q / (double)n;
+    double prod = 1.0;
+    for (int j = 1; j <= 64; ++j) {
+      const double xi = std::ldexp(w, -j);
+      double re = 0.0, im = 0.0;
+      for (int k = 0; k < 4; ++k) {
+        re += h[k] * std::cos(k * xi);
+        im -= h[k] * std::sin(k * xi);
+      }
+      prod *= 0.5 * (re * re + im * im);
+    }
+    out[i] = prod;
+  }
+}
+
 double bspline3(double u) {
   const double a = std::fabs(u);
   if (a < 1.0) return (4.0 - 6.0 * a * a + 3.0 * a * a * a) / 6.0;

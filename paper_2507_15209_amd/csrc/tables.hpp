@@ -18,6 +18,12 @@ double tophat_window(double x);
 // sinc^8(pi q / n) at every index of an axis (q = index mod n in [-n/2, n/2))
 void phi_hat_axis(int n, std::vector<double>& out);
 void twiddles(int n, std::vector<double>& re, std::vector<double>& im);
+// Daubechies-4 scaling function phi at x = i / 2^level, i = 0 .. 3 2^level (cascade algorithm)
+void d4_table(int level, std::vector<double>& out);
+// int phi_R(x) phi_R(x - s) dx, s = 0 .. 3, of the table's linear interpolant
+void d4_autocorr(const std::vector<double>& table, int level, double a[4]);
+// |phi_hat(2 pi q / n)|^2 of the Daubechies-4 scaling function per axis index (infinite product)
+void d4_phi_hat_axis(int n, std::vector<double>& out);
 double ylm_norm(int l, int m);
 // centred cubic B-spline
 double bspline3(double u);

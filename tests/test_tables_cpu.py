@@ -87,3 +87,37 @@ def test_window_table_rejects_bad_arguments(lib):
     assert lib.mp3_window_table(ctypes.byref(bad), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 8) == -6
     assert lib.mp3_sph_bessel(3, float("nan"), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == -6
     assert lib.mp3_sph_bessel(3, -1.0, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == -1
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+@pytest.mark.parametrize("n", [16, 64, 256])
+def test_basis_tables_match_oracle(lib, n):
+    """Daubechies-4 table (cascade), autocorrelation of its interpolant and |phi_hat|^2 (infinite
+    product) from the library's host code against the oracle's independent computation; the cubic
+    B-spline's autocorrelation and sinc^8 likewise."""
+    from oracle import basis as B3
+    from oracle import basis_d4 as D4
+    tab = np.zeros(3 * 1024 + 1)
+    acf = np.zeros(4)
+    ph = np.zeros(n)
+    assert lib.mp3_basis_tables(1, n, _dp(tab), tab.size, _dp(acf), _dp(ph)) == 0
+    assert np.abs(tab - D4.table(10)).max() < 1e-14
+    assert np.abs(acf[:3] - D4.autocorr_samples()).max() < 1e-14 and acf[3] == 0.0
+    assert np.abs(ph - D4.phi_hat_axis(n)).max() < 1e-13
+    assert lib.mp3_basis_tables(0, n, None, 0, _dp(acf), _dp(ph)) == 0
+    b7 = B3.b7_samples()
+    assert np.abs(acf - np.array([float(b7[s]) for s in range(4)])).max() < 1e-16
+    plan = E.Plan(n, 100.0, 0, [1.0, 2.0], phi_hat=True)
+    assert np.abs(ph - plan.phi_hat_grid()[:, 0, 0]).max() < 1e-14
+
+
+def test_basis_tables_reject_bad_arguments(lib):
+    tab = np.zeros(10)
+    assert lib.mp3_basis_tables(2, 16, None, 0, None, None) == -1
+    assert lib.mp3_basis_tables(1, 16, _dp(tab), tab.size, None, None) == -1       # wrong count
+    assert lib.mp3_basis_tables(0, 16, _dp(tab), tab.size, None, None) == -1       # no table for B3
+    ph = np.zeros(24)
+    assert lib.mp3_basis_tables(1, 24, None, 0, None, _dp(ph)) == -4               # unsupported n
