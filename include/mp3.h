@@ -431,17 +431,23 @@ int mp3_sph_bessel(int32_t lmax, double x, double* out);
  * Validates desc as mp3_plan_create does. */
 int mp3_window_table(const mp3_plan_desc* desc, double* out, size_t count);
 
-/* Host tables of a basis (Sec. 3, the basis paragraph; Eq. SFC-3PCF-vertex),
- * computed without a GPU as mp3_plan_create does; any output may be NULL:
+/* Host tables of a basis (Sec. 3, the basis paragraph; Eqs. SFC-3PCF-vertex
+ * and con-coeff), computed without a GPU as mp3_plan_create does; any output
+ * may be NULL:
  *   table[i] = phi(i / 1024), i = 0 .. 3072 (table_count must be 3073),
  *              Daubechies-4 only (NULL for the B-spline);
  *   acf[s]   = int phi(x) phi(x - s) dx, s = 0 .. 3, of the basis as the
  *              deposit uses it (the autocorrelation of the particle form's
  *              volume mean);
  *   phi_hat[i] = |phi-hat(2 pi q / n)|^2, q = i for i < n/2 else i - n
- *              (n a supported grid size).
- * Returns MP3_EINVAL for an unknown basis or a wrong count. */
-int mp3_basis_tables(int32_t basis, int32_t n, double* table, size_t table_count, double* acf, double* phi_hat);
+ *              (n a supported grid size);
+ *   gamma[(s + 2) * 5 + t + 2] = int phi phi(. - s) phi(. - t), s, t in
+ *              -2 .. 2, of the exact scaling function (the connection
+ *              coefficients of one axis), Daubechies-4 only.
+ * Returns MP3_EINVAL for an unknown basis, a wrong count or a table the basis
+ * does not have. */
+int mp3_basis_tables(int32_t basis, int32_t n, double* table, size_t table_count, double* acf, double* phi_hat,
+                     double* gamma);
 
 /* Human-readable name of a status code (static storage). */
 const char* mp3_status_string(int status);

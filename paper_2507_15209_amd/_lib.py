@@ -109,7 +109,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.mp3_sph_bessel.argtypes = [i32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
     lib.mp3_window_table.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(ctypes.c_double), sz]
     lib.mp3_basis_tables.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_double), sz, ctypes.POINTER(ctypes.c_double),
-                                     ctypes.POINTER(ctypes.c_double)]
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.mp3_zeta_value_and_grad_static.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i64), vp, vp]
     lib.mp3_static_scratch_bytes.argtypes = []
     lib.mp3_status_string.argtypes = [ctypes.c_int]

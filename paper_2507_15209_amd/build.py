@@ -27,7 +27,8 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 def commands() -> list[list[str]]:
     objs = []
     cmds = []
-    for src, dev in (("kernels.hip", True), ("stats.hip", True), ("static_scratch.hip", True), ("mp3_api.cpp", False),
+    for src, dev in (("kernels.hip", True), ("stats.hip", True), ("stencil.hip", True), ("static_scratch.hip", True),
+                     ("mp3_api.cpp", False),
                      ("tables.cpp", False)):
         obj = os.path.join(BUILD, src + ".o")
         flags = COMMON + (DEVICE + ["-x", "hip"] if dev else HOST + ["-x", "c++"])

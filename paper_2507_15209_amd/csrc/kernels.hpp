@@ -114,6 +114,22 @@ hipError_t launch_gamma_adjoint_bins(int prec, const void* fields, const void* U
                                      int b0, int nbc, const double (*m)[4], const double* wq, double wm, int nwg,
                                      int batch, void* cout, void* direct, hipStream_t st);
 size_t gamma_adjoint_bins_lds_need(int prec, int nbc);
+
+// grid summation with connection coefficients as a stencil over the 125
+// shifts of a support-3 basis (stencil.hip): gamma(s, t) at g[s + 2][t + 2]
+struct StencilGamma {
+  double g[5][5];
+};
+// partials over the pair's local bins, as launch_gamma_contract
+hipError_t launch_stencil_contract(int prec, const void* fields, const void* delta, int n, const BinPair& bp,
+                                   const StencilGamma& sg, double* partials, int nwg, int batch, hipStream_t st);
+size_t stencil_lds_need(int prec, int nl);
+// adjoint of stored bins b0 .. b0 + nbc - 1 from the fields and their mix U: sources
+// into cout (per-bin layout), wm times the primary's share into direct
+hipError_t launch_stencil_adjoint(int prec, const void* fields, const void* U, const void* delta, int n, int nbt,
+                                  int b0, int nbc, const StencilGamma& sg, double wm, int nwg, int batch, void* cout,
+                                  void* direct, hipStream_t st);
+size_t stencil_adjoint_lds_need(int prec, int nbc);
 hipError_t launch_zpass_store(int n, int prec, const ZpassArgs& a, void* out, hipStream_t st);
 // counting sort of the particles by (2^shift)^3-cell tile of their mock; offs
 // gets batch * (n >> shift)^3 + 1 exclusive tile offsets

@@ -32,6 +32,7 @@ struct mp3_plan_s {
   void* phi = nullptr;      // [n] real per-axis phi-hat factors when MP3_KF_PHI_HAT
   double* btab = nullptr;   // Daubechies-4 basis: phi at the dyadic points (NULL for the B-spline)
   mp3::Acf acf{{2416.0 / 5040.0, 1191.0 / 5040.0, 120.0 / 5040.0, 1.0 / 5040.0}};   // basis autocorrelation
+  mp3::StencilGamma sgam{};  // Daubechies-4 connection coefficients (grid summation as a stencil)
   std::vector<mp3::ItemRec> items;   // every (l, m >= 0) of the plan, index l (l + 1) / 2 + m
   mp3::ItemRec* items_dev = nullptr; // the same table on the device
   // optional per-pass HIP event timing
@@ -160,7 +161,8 @@ Layout layout(const mp3_plan_s* p, long long np_total = 0) {
   L.xib = take(B * (size_t)p->nbins * sizeof(double));
   if (p->summation != MP3_SUM_NODAL) L.fields_i = take(B * (size_t)p->nbins * n3 * p->celt);
   // grid-Gamma adjoint by bin chunks: the bin mix U of the fields
-  if (p->summation == MP3_SUM_GRID_GAMMA && mp3::gamma_adjoint_lds_need(p->prec, p->nbins) > kLdsLimit)
+  if (p->summation == MP3_SUM_GRID_GAMMA &&
+      (p->basis == MP3_BASIS_DAUBECHIES4 || mp3::gamma_adjoint_lds_need(p->prec, p->nbins) > kLdsLimit))
     L.fields_u = take(B * (size_t)p->nbins * n3 * p->celt);
   if (p->summation == MP3_SUM_PARTICLE) {
     const size_t nt = (size_t)(p->n / 4) * (p->n / 4) * (p->n / 4) * B + 1;
@@ -215,8 +217,8 @@ int validate_desc(const mp3_plan_desc* d) {
   if (d->batch < 1) return fail(MP3_EINVAL, "batch must be >= 1");
   if (d->basis != MP3_BASIS_BSPLINE3 && d->basis != MP3_BASIS_DAUBECHIES4)
     return fail(MP3_EINVAL, "basis must be MP3_BASIS_BSPLINE3 or MP3_BASIS_DAUBECHIES4");
-  if (d->basis == MP3_BASIS_DAUBECHIES4 && d->summation == MP3_SUM_GRID_GAMMA)
-    return fail(MP3_EUNSUPPORTED, "the grid-Gamma form is built for the cubic B-spline basis only");
+  if (d->basis == MP3_BASIS_DAUBECHIES4 && d->summation == MP3_SUM_GRID_GAMMA && d->precision == MP3_F32_BF16X3)
+    return fail(MP3_EUNSUPPORTED, "BF16-split inputs: cubic B-spline grid summation only");
   if (d->kflags & ~kKnownFlags) return fail(MP3_EINVAL, "unknown kflags bits");
   if (d->binning != MP3_BIN_SHELL_AVERAGE && d->binning != MP3_BIN_THIN_SHELL)
     return fail(MP3_EINVAL, "binning must be MP3_BIN_SHELL_AVERAGE or MP3_BIN_THIN_SHELL");
@@ -529,6 +531,7 @@ int mp3_plan_create(const mp3_plan_desc* d, mp3_plan_t* out) {
     std::vector<double> tab;
     mp3::d4_table(mp3::kD4Level, tab);
     mp3::d4_autocorr(tab, mp3::kD4Level, p->acf.a);
+    mp3::d4_gamma(p->sgam.g);
     e4 = hipMalloc(&p->btab, tab.size() * sizeof(double));
     if (e4 == hipSuccess) e4 = hipMemcpy(p->btab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
   }
@@ -705,15 +708,20 @@ struct GammaPass {
   bool own_a, own_c;
 };
 
+// LDS bytes of the forward contraction tile holding nl local bins (the basis' kernel)
+size_t contract_lds_need(const mp3_plan_s* p, int nl) {
+  return p->basis == MP3_BASIS_DAUBECHIES4 ? mp3::stencil_lds_need(p->prec, nl) : mp3::gamma_lds_need(p->prec, nl);
+}
+
 std::vector<GammaPass> gamma_passes(const mp3_plan_s* p) {
   const int nb = p->nbins;
   std::vector<GammaPass> out;
-  if (mp3::gamma_lds_need(p->prec, nb) <= kLdsLimit) {
+  if (contract_lds_need(p, nb) <= kLdsLimit) {
     out.push_back({{nb, 0, nb, 0, 0}, true, true});
     return out;
   }
   int cs = nb / 2;
-  while (cs > 1 && mp3::gamma_lds_need(p->prec, 2 * cs) > kLdsLimit) --cs;
+  while (cs > 1 && contract_lds_need(p, 2 * cs) > kLdsLimit) --cs;
   const int k = (nb + cs - 1) / cs;
   for (int i = 0; i < k; ++i) {
     for (int j = i + 1; j < k; ++j) {
@@ -727,6 +735,10 @@ std::vector<GammaPass> gamma_passes(const mp3_plan_s* p) {
 // bins per chunk of the chunked grid-Gamma adjoint
 int gamma_adjoint_chunk(const mp3_plan_s* p) {
   int c = p->nbins;
+  if (p->basis == MP3_BASIS_DAUBECHIES4) {
+    while (c > 1 && mp3::stencil_adjoint_lds_need(p->prec, c) > kLdsLimit) --c;
+    return c;
+  }
   while (c > 1 && mp3::gamma_adjoint_bins_lds_need(p->prec, c) > kLdsLimit) --c;
   return c;
 }
@@ -736,6 +748,9 @@ int gamma_contract_all(const mp3_plan_s* p, const void* Fi, const void* prim, do
                        int l, double scale, hipStream_t st) {
   for (const GammaPass& g : gamma_passes(p)) {
     MP3_HIP(timed(p, MP3_PASS_GAMMA, st, [&] {
+              if (p->basis == MP3_BASIS_DAUBECHIES4)
+                return mp3::launch_stencil_contract(p->prec, Fi, prim, p->n, g.bp, p->sgam, partials, gwg, p->batch,
+                                                    st);
               return mp3::launch_gamma_contract(p->prec, p->split, Fi, prim, p->n, g.bp, p->gm, p->gw, partials, gwg,
                                                 p->batch, st);
             }),
@@ -1153,7 +1168,7 @@ int backward_gamma(mp3_plan_t p, const void* delta, const double* dzeta, void* d
                    double* zeta = nullptr) {
   // tiles that do not hold every bin: the adjoint by bin chunks (and, for
   // zeta, the contraction by pairs of chunks)
-  const bool chunked = mp3::gamma_adjoint_lds_need(p->prec, p->nbins) > kLdsLimit;
+  const bool chunked = p->basis == MP3_BASIS_DAUBECHIES4 || mp3::gamma_adjoint_lds_need(p->prec, p->nbins) > kLdsLimit;
   long long np_total = 0, np_max = 0;
   if (dw) {
     if (int s = check_offsets(p, np_off, &np_total, &np_max)) return s;
@@ -1205,6 +1220,9 @@ int backward_gamma(mp3_plan_t p, const void* delta, const double* dzeta, void* d
         for (int b0 = 0; b0 < p->nbins; b0 += cb) {
           const int nbc = std::min(cb, p->nbins - b0);
           MP3_HIP(timed(p, MP3_PASS_GAMMA, st, [&] {
+                    if (p->basis == MP3_BASIS_DAUBECHIES4)
+                      return mp3::launch_stencil_adjoint(p->prec, Fi, U, prim, p->n, p->nbins, b0, nbc, p->sgam, wm,
+                                                         (int)gwg, p->batch, F, direct, st);
                     return mp3::launch_gamma_adjoint_bins(p->prec, Fi, U, prim, p->n, p->nbins, b0, nbc, p->gm, p->gw,
                                                           wm, (int)gwg, p->batch, F, direct, st);
                   }),
@@ -1495,11 +1513,13 @@ int mp3_sph_bessel(int32_t lmax, double x, double* out) {
   return MP3_OK;
 }
 
-int mp3_basis_tables(int32_t basis, int32_t n, double* table, size_t table_count, double* acf, double* phi_hat) {
+int mp3_basis_tables(int32_t basis, int32_t n, double* table, size_t table_count, double* acf, double* phi_hat,
+                     double* gamma) {
   if (basis != MP3_BASIS_BSPLINE3 && basis != MP3_BASIS_DAUBECHIES4) return fail(MP3_EINVAL, "unknown basis");
   if (phi_hat && !pow2_supported(n)) return fail(MP3_EUNSUPPORTED, "n must be one of 16, 32, 64, 128, 256, 512");
   if (basis == MP3_BASIS_BSPLINE3) {
     if (table) return fail(MP3_EINVAL, "the cubic B-spline has no tabulated values");
+    if (gamma) return fail(MP3_EINVAL, "the cubic B-spline's grid summation uses node quadrature, not a table");
     if (acf) {
       const double b7[4] = {2416.0 / 5040.0, 1191.0 / 5040.0, 120.0 / 5040.0, 1.0 / 5040.0};
       for (int s = 0; s < 4; ++s) acf[s] = b7[s];
@@ -1522,6 +1542,12 @@ int mp3_basis_tables(int32_t basis, int32_t n, double* table, size_t table_count
     std::vector<double> ph;
     mp3::d4_phi_hat_axis(n, ph);
     std::copy(ph.begin(), ph.end(), phi_hat);
+  }
+  if (gamma) {
+    double g[5][5];
+    mp3::d4_gamma(g);
+    for (int s = 0; s < 5; ++s)
+      for (int t = 0; t < 5; ++t) gamma[s * 5 + t] = g[s][t];
   }
   return MP3_OK;
 }

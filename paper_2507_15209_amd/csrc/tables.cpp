@@ -257,6 +257,55 @@ void d4_phi_hat_axis(int n, std::vector<double>& out) {
   }
 }
 
+void d4_gamma(double g[5][5]) {
+  // gamma(s, t) = int phi(x) phi(x - s) phi(x - t) dx over the 19 pairs with
+  // |s|, |t|, |s - t| <= 2.  Inserting the two-scale relation in all three
+  // factors gives gamma(s, t) = sqrt2 sum_{k,l,m} h_k h_l h_m
+  // gamma(2s + l - k, 2t + m - k): a homogeneous system, made unique by
+  // sum_{s,t} gamma(s, t) = int phi = 1 (partition of unity).  Solved by
+  // Gaussian elimination with partial pivoting, the normalisation replacing
+  // the first equation.
+  double h[4];
+  d4_filter(h);
+  const double r2 = std::sqrt(2.0);
+  int idx[5][5];
+  int np = 0;
+  for (int s = -2; s <= 2; ++s)
+    for (int t = -2; t <= 2; ++t) idx[s + 2][t + 2] = std::abs(s - t) <= 2 ? np++ : -1;
+  std::vector<double> A((size_t)np * (np + 1), 0.0);   // augmented [np][np + 1]
+  auto at = [&](int r, int c) -> double& { return A[(size_t)r * (np + 1) + c]; };
+  for (int s = -2; s <= 2; ++s) {
+    for (int t = -2; t <= 2; ++t) {
+      const int r = idx[s + 2][t + 2];
+      if (r < 0) continue;
+      at(r, r) -= 1.0;
+      for (int k = 0; k < 4; ++k)
+        for (int l = 0; l < 4; ++l)
+          for (int m = 0; m < 4; ++m) {
+            const int u = 2 * s + l - k, v = 2 * t + m - k;
+            if (u < -2 || u > 2 || v < -2 || v > 2 || idx[u + 2][v + 2] < 0) continue;
+            at(r, idx[u + 2][v + 2]) += r2 * h[k] * h[l] * h[m];
+          }
+    }
+  }
+  for (int c = 0; c <= np; ++c) at(0, c) = 1.0;   // sum of all unknowns = 1
+  for (int c = 0; c < np; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < np; ++r)
+      if (std::fabs(at(r, c)) > std::fabs(at(piv, c))) piv = r;
+    if (piv != c)
+      for (int k = 0; k <= np; ++k) std::swap(at(c, k), at(piv, k));
+    for (int r = 0; r < np; ++r) {
+      if (r == c) continue;
+      const double f = at(r, c) / at(c, c);
+      if (f != 0.0)
+        for (int k = c; k <= np; ++k) at(r, k) -= f * at(c, k);
+    }
+  }
+  for (int s = 0; s < 5; ++s)
+    for (int t = 0; t < 5; ++t) g[s][t] = idx[s][t] < 0 ? 0.0 : at(idx[s][t], np) / at(idx[s][t], idx[s][t]);
+}
+
 double bspline3(double u) {
   const double a = std::fabs(u);
   if (a < 1.0) return (4.0 - 6.0 * a * a + 3.0 * a * a * a) / 6.0;

@@ -24,6 +24,8 @@ void d4_table(int level, std::vector<double>& out);
 void d4_autocorr(const std::vector<double>& table, int level, double a[4]);
 // |phi_hat(2 pi q / n)|^2 of the Daubechies-4 scaling function per axis index (infinite product)
 void d4_phi_hat_axis(int n, std::vector<double>& out);
+// connection coefficients int phi phi(. - s) phi(. - t) of the Daubechies-4 function, g[s + 2][t + 2]
+void d4_gamma(double g[5][5]);
 double ylm_norm(int l, int m);
 // centred cubic B-spline
 double bspline3(double u);

@@ -47,7 +47,7 @@ def _desc(**kw):
     (dict(box=float("inf")), -6), (dict(lmax=-1), -1), (dict(lmax=21), -1), (dict(nbins=0), -1),
     (dict(nbins=65), -1), (dict(edges=[10.0, 5.0, 20.0]), -1), (dict(edges=[-1.0, 5.0]), -1),
     (dict(edges=[1.0, float("nan")]), -6), (dict(precision=3), -1), (dict(summation=3), -4), (dict(batch=0), -1),
-    (dict(basis=2), -1), (dict(basis=1, summation=1), -4), (dict(kflags=4), -1), (dict(binning=2), -1), (dict(smoothing=-1.0), -1),
+    (dict(basis=2), -1), (dict(basis=1, summation=1, precision=2), -4), (dict(kflags=4), -1), (dict(binning=2), -1), (dict(smoothing=-1.0), -1),
     (dict(smoothing=float("nan")), -6),
 ])
 def test_plan_create_rejects_bad_descriptions(kw, code):
