@@ -215,6 +215,9 @@ FORMS = {
     "batch64_f32": ("batch64_n128_l8", "nodal", "f32", True, {}),
     # the paper's triple-sphere binning: thin shells, top-hat R = 8 on every vertex
     "nodal_256_thin_tophat_f32": ("box2000_n256_l10", "nodal", "f32", True, TRIPLE_SPHERE),
+    # the paper's Daubechies-4 basis: nodal one sweep, and the grid summation with its connection coefficients
+    "nodal_256_d4_f32": ("box2000_n256_l10", "nodal", "f32", True, {"basis": "d4"}),
+    "gamma_256_d4_f32_adj": ("box2000_n256_l10", "gamma", "f32", True, {"basis": "d4"}),
     # the remaining configurations (not run by default)
     "gamma_32_f64": ("box250_n32_l4", "gamma", "f64", True, {}),
     "nodal_32_f64": ("box250_n32_l4", "nodal", "f64", True, {}),
@@ -222,7 +225,7 @@ FORMS = {
     "particle_128_f64": ("box1000_n128_l10", "particle", "f64", True, {}),
 }
 DEFAULT_FORMS = ("gamma_256_f32", "gamma_256_bf16x3", "gamma_256_f32_adj", "particle_512_f32", "particle_512_f64",
-                 "batch64_f32", "nodal_256_thin_tophat_f32")
+                 "batch64_f32", "nodal_256_thin_tophat_f32", "nodal_256_d4_f32", "gamma_256_d4_f32_adj")
 
 
 def measure_form(name, steps=1):
@@ -370,6 +373,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default knobs (else: cached knobs, or a tuning run on a cache miss)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="tuning cache file to read and write (default: the per-user cache, then the packaged one)")
     ap.add_argument("--forms", default=",".join(DEFAULT_FORMS),
                     help="secondary measurements after the headline (comma list of %s, all, or none)" % ", ".join(FORMS))
     ap.add_argument("--pmc-probe", action="store_true", help="one step plus a 1 GiB copy, for counter runs")
@@ -430,7 +435,7 @@ def main():
         t0 = time.perf_counter()
         d0 = plan.deposit(pt, wt)
         try:
-            at.autotune(plan, d0, pt, wt, dzeta=lam, backward=True, reps=1, log=log)
+            at.autotune(plan, d0, pt, wt, dzeta=lam, backward=True, reps=1, log=log, cache=args.tune_cache)
         except OSError as e:                      # tuning cache not writable: keep the tuned knobs anyway
             log("tuning cache not written:", e)
         tunings[precision] = plan.tuning()

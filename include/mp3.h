@@ -395,13 +395,18 @@ enum mp3_tune_knob {
                                  x and z passes of mp3_zeta_backward and the one sweep of
                                  mp3_zeta_value_and_grad): 0 = as many as fit 1 GiB of fields
                                  (default), else 1 .. 1024, capped at (lmax+1)(lmax+2)/2     */
-  MP3_NTUNE = 7
+  MP3_TUNE_GAMMA_ADJOINT = 7, /* kernel of the grid-Gamma adjoint (B-spline plans): 0 = the
+                                 stencil over the shifts of the connection coefficients
+                                 (default), 1 = the transposed node quadrature; Daubechies-4
+                                 plans always take the stencil                               */
+  MP3_NTUNE = 8
 };
 
 /* Set a knob.  Out-of-range values return MP3_EINVAL and leave the knob as
  * it was.  The workspace size depends on MP3_TUNE_ZPASS_WGS,
- * MP3_TUNE_CONTRACT_WGS, MP3_TUNE_DEPOSIT_TILE and MP3_TUNE_ITEM_GROUP (the
- * fields of every item of a group are held at once): query mp3_workspace_size
+ * MP3_TUNE_CONTRACT_WGS, MP3_TUNE_DEPOSIT_TILE, MP3_TUNE_ITEM_GROUP (the
+ * fields of every item of a group are held at once) and MP3_TUNE_GAMMA_ADJOINT:
+ * query mp3_workspace_size
  * again after changing them.  Not to be called while work of the plan is in
  * flight on another thread. */
 int mp3_tune_set(mp3_plan_t plan, int knob, int32_t value);
@@ -441,9 +446,10 @@ int mp3_window_table(const mp3_plan_desc* desc, double* out, size_t count);
  *              volume mean);
  *   phi_hat[i] = |phi-hat(2 pi q / n)|^2, q = i for i < n/2 else i - n
  *              (n a supported grid size);
- *   gamma[(s + 2) * 5 + t + 2] = int phi phi(. - s) phi(. - t), s, t in
- *              -2 .. 2, of the exact scaling function (the connection
- *              coefficients of one axis), Daubechies-4 only.
+ *   gamma[(s + 3) * 7 + t + 3] = int phi phi(. - s) phi(. - t), s, t in
+ *              -3 .. 3 (the connection coefficients of one axis; for
+ *              Daubechies-4 those of the exact scaling function, zero for
+ *              |s| or |t| = 3).
  * Returns MP3_EINVAL for an unknown basis, a wrong count or a table the basis
  * does not have. */
 int mp3_basis_tables(int32_t basis, int32_t n, double* table, size_t table_count, double* acf, double* phi_hat,

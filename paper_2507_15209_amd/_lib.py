@@ -28,7 +28,7 @@ MP3_KF_PHI_HAT = 1
 MP3_KF_CHECK_FINITE = 2
 # launch-shape knobs (enum mp3_tune_knob)
 TUNE_KNOBS = ("zpass_wgs", "contract_wgs", "fft_x_plan", "deposit_tile", "deposit_wgs", "fused_waves",
-              "item_group")
+              "item_group", "gamma_adjoint")
 
 # every entry point of include/mp3.h
 EXPORTS = (

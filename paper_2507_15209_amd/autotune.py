@@ -28,10 +28,17 @@ CANDIDATES = {
     "contract_wgs": (1024, 2048, 4096, 8192, 16384),
     "fused_waves": (0, 4, 8),
     "item_group": (0, 1, 2, 4),
+    "gamma_adjoint": (0, 1),
 }
 
 
+# knobs measured on this package's target device, shipped with it (read when no
+# other cache is named); entries are keyed by device name and configuration
+PACKAGED_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+
+
 def cache_path(path: str | None = None) -> str:
+    """The cache to use: ``path``, else $MP3_TUNE_CACHE, else the per-user cache."""
     if path:
         return path
     env = os.environ.get("MP3_TUNE_CACHE")
@@ -56,8 +63,11 @@ def _read(path: str) -> dict:
 
 
 def load_tuning(plan, path: str | None = None) -> bool:
-    """Apply cached knobs to the plan; False if the cache has none for it."""
+    """Apply cached knobs to the plan (the named or per-user cache, then the packaged one);
+    False if neither has an entry for it."""
     entry = _read(cache_path(path)).get(cache_key(plan))
+    if not isinstance(entry, dict) and not path:
+        entry = _read(PACKAGED_CACHE).get(cache_key(plan))
     if not isinstance(entry, dict):
         return False
     for k, v in entry.get("knobs", {}).items():
@@ -147,6 +157,8 @@ def autotune(plan, delta, pos=None, w=None, np_off=None, dzeta=None, backward: b
             knobs.append("fused_waves")
         if plan.summation != "nodal":
             knobs.append("contract_wgs")
+        if do_bwd and plan.summation == "gamma" and getattr(plan, "basis", "b3") == "b3":
+            knobs.append("gamma_adjoint")
         for k in knobs:
             times[k] = _descend(plan, k, path, reps, log)
     save_tuning(plan, times, cache)

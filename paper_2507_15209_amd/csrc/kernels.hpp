@@ -115,21 +115,23 @@ hipError_t launch_gamma_adjoint_bins(int prec, const void* fields, const void* U
                                      int batch, void* cout, void* direct, hipStream_t st);
 size_t gamma_adjoint_bins_lds_need(int prec, int nbc);
 
-// grid summation with connection coefficients as a stencil over the 125
-// shifts of a support-3 basis (stencil.hip): gamma(s, t) at g[s + 2][t + 2]
+// grid summation with connection coefficients as a stencil over the shifts
+// -halo .. halo per axis (stencil.hip): gamma(s, t) at g[s + 3][t + 3];
+// halo 2 (Daubechies-4, support 3) or 3 (cubic B-spline, support 4)
 struct StencilGamma {
-  double g[5][5];
+  double g[7][7];
+  int halo;
 };
 // partials over the pair's local bins, as launch_gamma_contract
 hipError_t launch_stencil_contract(int prec, const void* fields, const void* delta, int n, const BinPair& bp,
                                    const StencilGamma& sg, double* partials, int nwg, int batch, hipStream_t st);
-size_t stencil_lds_need(int prec, int nl);
+size_t stencil_lds_need(int prec, int halo, int nl);
 // adjoint of stored bins b0 .. b0 + nbc - 1 from the fields and their mix U: sources
 // into cout (per-bin layout), wm times the primary's share into direct
 hipError_t launch_stencil_adjoint(int prec, const void* fields, const void* U, const void* delta, int n, int nbt,
                                   int b0, int nbc, const StencilGamma& sg, double wm, int nwg, int batch, void* cout,
                                   void* direct, hipStream_t st);
-size_t stencil_adjoint_lds_need(int prec, int nbc);
+size_t stencil_adjoint_lds_need(int prec, int halo, int nbc);
 hipError_t launch_zpass_store(int n, int prec, const ZpassArgs& a, void* out, hipStream_t st);
 // counting sort of the particles by (2^shift)^3-cell tile of their mock; offs
 // gets batch * (n >> shift)^3 + 1 exclusive tile offsets

@@ -25,7 +25,7 @@ struct mp3_plan_s {
   int device = 0;
   double gm[5][4] = {{0}};   // grid-Gamma quadrature: B3 tap weights at the nodes
   double gw[5] = {0};        // and node weights
-  int tune[MP3_NTUNE] = {4096, 4096, 0, 8, 2048, 4, 0};   // launch-shape knobs (mp3_tune_knob)
+  int tune[MP3_NTUNE] = {4096, 4096, 0, 8, 2048, 4, 0, 0};   // launch-shape knobs (mp3_tune_knob)
   int basis = 0, binning = 0;
   unsigned kflags = 0;
   double smoothing = 0.0;   // top-hat radius of every vertex (0 = none)
@@ -120,6 +120,12 @@ int item_group(const mp3_plan_s* p) {
   return g < total ? g : total;
 }
 
+// the grid-Gamma adjoint as the shift stencil (Daubechies-4 always; the
+// B-spline unless the node-quadrature kernel is selected)
+bool gamma_stencil_adjoint(const mp3_plan_s* p) {
+  return p->basis == MP3_BASIS_DAUBECHIES4 || p->tune[MP3_TUNE_GAMMA_ADJOINT] == 0;
+}
+
 Layout layout(const mp3_plan_s* p, long long np_total = 0) {
   Layout L{};
   L.group = item_group(p);
@@ -162,7 +168,7 @@ Layout layout(const mp3_plan_s* p, long long np_total = 0) {
   if (p->summation != MP3_SUM_NODAL) L.fields_i = take(B * (size_t)p->nbins * n3 * p->celt);
   // grid-Gamma adjoint by bin chunks: the bin mix U of the fields
   if (p->summation == MP3_SUM_GRID_GAMMA &&
-      (p->basis == MP3_BASIS_DAUBECHIES4 || mp3::gamma_adjoint_lds_need(p->prec, p->nbins) > kLdsLimit))
+      (gamma_stencil_adjoint(p) || mp3::gamma_adjoint_lds_need(p->prec, p->nbins) > kLdsLimit))
     L.fields_u = take(B * (size_t)p->nbins * n3 * p->celt);
   if (p->summation == MP3_SUM_PARTICLE) {
     const size_t nt = (size_t)(p->n / 4) * (p->n / 4) * (p->n / 4) * B + 1;
@@ -525,13 +531,21 @@ int mp3_plan_create(const mp3_plan_desc* d, mp3_plan_t* out) {
     }
   }
   const size_t ib = p->items.size() * sizeof(mp3::ItemRec);
+  if (p->basis == MP3_BASIS_BSPLINE3) {
+    mp3::b3_gamma(p->sgam.g);
+    p->sgam.halo = 3;
+  }
   hipError_t e4 = hipMalloc(&p->items_dev, ib);
   if (e4 == hipSuccess) e4 = hipMemcpy(p->items_dev, p->items.data(), ib, hipMemcpyHostToDevice);
   if (p->basis == MP3_BASIS_DAUBECHIES4 && e4 == hipSuccess) {
     std::vector<double> tab;
     mp3::d4_table(mp3::kD4Level, tab);
     mp3::d4_autocorr(tab, mp3::kD4Level, p->acf.a);
-    mp3::d4_gamma(p->sgam.g);
+    double g5[5][5];
+    mp3::d4_gamma(g5);
+    for (int s = 0; s < 5; ++s)
+      for (int t = 0; t < 5; ++t) p->sgam.g[s + 1][t + 1] = g5[s][t];
+    p->sgam.halo = 2;
     e4 = hipMalloc(&p->btab, tab.size() * sizeof(double));
     if (e4 == hipSuccess) e4 = hipMemcpy(p->btab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
   }
@@ -613,6 +627,9 @@ int mp3_tune_set(mp3_plan_t p, int knob, int32_t value) {
       break;
     case MP3_TUNE_ITEM_GROUP:
       if (value < 0 || value > 1024) return fail(MP3_EINVAL, "items per nodal adjoint launch must lie in 0 .. 1024");
+      break;
+    case MP3_TUNE_GAMMA_ADJOINT:
+      if (value != 0 && value != 1) return fail(MP3_EINVAL, "grid-Gamma adjoint kernel must be 0 or 1");
       break;
     default:
       return fail(MP3_EINVAL, "unknown tuning knob");
@@ -710,7 +727,7 @@ struct GammaPass {
 
 // LDS bytes of the forward contraction tile holding nl local bins (the basis' kernel)
 size_t contract_lds_need(const mp3_plan_s* p, int nl) {
-  return p->basis == MP3_BASIS_DAUBECHIES4 ? mp3::stencil_lds_need(p->prec, nl) : mp3::gamma_lds_need(p->prec, nl);
+  return p->basis == MP3_BASIS_DAUBECHIES4 ? mp3::stencil_lds_need(p->prec, 2, nl) : mp3::gamma_lds_need(p->prec, nl);
 }
 
 std::vector<GammaPass> gamma_passes(const mp3_plan_s* p) {
@@ -735,8 +752,8 @@ std::vector<GammaPass> gamma_passes(const mp3_plan_s* p) {
 // bins per chunk of the chunked grid-Gamma adjoint
 int gamma_adjoint_chunk(const mp3_plan_s* p) {
   int c = p->nbins;
-  if (p->basis == MP3_BASIS_DAUBECHIES4) {
-    while (c > 1 && mp3::stencil_adjoint_lds_need(p->prec, c) > kLdsLimit) --c;
+  if (gamma_stencil_adjoint(p)) {
+    while (c > 1 && mp3::stencil_adjoint_lds_need(p->prec, p->sgam.halo, c) > kLdsLimit) --c;
     return c;
   }
   while (c > 1 && mp3::gamma_adjoint_bins_lds_need(p->prec, c) > kLdsLimit) --c;
@@ -1168,7 +1185,7 @@ int backward_gamma(mp3_plan_t p, const void* delta, const double* dzeta, void* d
                    double* zeta = nullptr) {
   // tiles that do not hold every bin: the adjoint by bin chunks (and, for
   // zeta, the contraction by pairs of chunks)
-  const bool chunked = p->basis == MP3_BASIS_DAUBECHIES4 || mp3::gamma_adjoint_lds_need(p->prec, p->nbins) > kLdsLimit;
+  const bool chunked = gamma_stencil_adjoint(p) || mp3::gamma_adjoint_lds_need(p->prec, p->nbins) > kLdsLimit;
   long long np_total = 0, np_max = 0;
   if (dw) {
     if (int s = check_offsets(p, np_off, &np_total, &np_max)) return s;
@@ -1220,7 +1237,7 @@ int backward_gamma(mp3_plan_t p, const void* delta, const double* dzeta, void* d
         for (int b0 = 0; b0 < p->nbins; b0 += cb) {
           const int nbc = std::min(cb, p->nbins - b0);
           MP3_HIP(timed(p, MP3_PASS_GAMMA, st, [&] {
-                    if (p->basis == MP3_BASIS_DAUBECHIES4)
+                    if (gamma_stencil_adjoint(p))
                       return mp3::launch_stencil_adjoint(p->prec, Fi, U, prim, p->n, p->nbins, b0, nbc, p->sgam, wm,
                                                          (int)gwg, p->batch, F, direct, st);
                     return mp3::launch_gamma_adjoint_bins(p->prec, Fi, U, prim, p->n, p->nbins, b0, nbc, p->gm, p->gw,
@@ -1519,7 +1536,12 @@ int mp3_basis_tables(int32_t basis, int32_t n, double* table, size_t table_count
   if (phi_hat && !pow2_supported(n)) return fail(MP3_EUNSUPPORTED, "n must be one of 16, 32, 64, 128, 256, 512");
   if (basis == MP3_BASIS_BSPLINE3) {
     if (table) return fail(MP3_EINVAL, "the cubic B-spline has no tabulated values");
-    if (gamma) return fail(MP3_EINVAL, "the cubic B-spline's grid summation uses node quadrature, not a table");
+    if (gamma) {
+      double g[7][7];
+      mp3::b3_gamma(g);
+      for (int s = 0; s < 7; ++s)
+        for (int t = 0; t < 7; ++t) gamma[s * 7 + t] = g[s][t];
+    }
     if (acf) {
       const double b7[4] = {2416.0 / 5040.0, 1191.0 / 5040.0, 120.0 / 5040.0, 1.0 / 5040.0};
       for (int s = 0; s < 4; ++s) acf[s] = b7[s];
@@ -1546,8 +1568,9 @@ int mp3_basis_tables(int32_t basis, int32_t n, double* table, size_t table_count
   if (gamma) {
     double g[5][5];
     mp3::d4_gamma(g);
+    for (int e = 0; e < 49; ++e) gamma[e] = 0.0;
     for (int s = 0; s < 5; ++s)
-      for (int t = 0; t < 5; ++t) gamma[s * 5 + t] = g[s][t];
+      for (int t = 0; t < 5; ++t) gamma[(s + 1) * 7 + t + 1] = g[s][t];
   }
   return MP3_OK;
 }

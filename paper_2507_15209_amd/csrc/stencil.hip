@@ -29,43 +29,49 @@ namespace mp3 {
 namespace {
 
 constexpr int ST = 4;             // cells per tile edge
-constexpr int SH = 2;             // halo (support 3: shifts -2 .. 2)
-constexpr int SW = ST + 2 * SH;   // window edge (8)
-constexpr int SW3 = SW * SW * SW;
 constexpr int ST3 = ST * ST * ST;
-constexpr int NS = 2 * SH + 1;    // shifts per axis (5)
-constexpr int SLAB = NS * NS;     // shifts of one x-shift slab (25)
 constexpr int kStencilThreads = 512;
+
+// the geometry of halo H (shifts -H .. H per axis): window edge ST + 2H,
+// NS = 2H + 1 shifts per axis, SLAB = NS^2 shifts per x-shift
+#define STENCIL_GEOMETRY(H)                                                 \
+  constexpr int SH = (H), SW = ST + 2 * (H), SW3 = SW * SW * SW;            \
+  constexpr int NS = 2 * (H) + 1, SLAB = NS * NS;                           \
+  (void)SW3;                                                                \
+  (void)SLAB
 
 __device__ __forceinline__ int wrap_s(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// gamma(s, t) at [s + 2][t + 2], held in LDS (indexed at run time)
-template <typename T>
+// gamma(s, t) for s, t in -H .. H at [(s + H) * (2H + 1) + t + H], held in
+// LDS (indexed at run time)
+template <typename T, int H>
 struct StencilCoef {
   const T* g;
 };
 
-template <typename T>
-__device__ __forceinline__ StencilCoef<T> coef_of(const StencilGamma& sg, T* lds) {
-  for (int e = threadIdx.x; e < NS * NS; e += blockDim.x) lds[e] = (T)sg.g[e / NS][e % NS];
+template <typename T, int H>
+__device__ __forceinline__ StencilCoef<T, H> coef_of(const StencilGamma& sg, T* lds) {
+  constexpr int NS = 2 * H + 1;
+  for (int e = threadIdx.x; e < NS * NS; e += blockDim.x) lds[e] = (T)sg.g[e / NS - H + 3][e % NS - H + 3];
   __syncthreads();
-  return StencilCoef<T>{lds};
+  return StencilCoef<T, H>{lds};
 }
 
-// gamma(s, s + d) for s, d in -2 .. 2 (zero when |s + d| > 2)
-template <typename T>
-__device__ __forceinline__ T gsd(const StencilCoef<T>& c, int s, int d) {
+// gamma(s, s + d) for s, d in -H .. H (zero when |s + d| > H)
+template <typename T, int H>
+__device__ __forceinline__ T gsd(const StencilCoef<T, H>& c, int s, int d) {
   const int t = s + d;
-  return (t < -SH || t > SH) ? (T)0 : c.g[(s + SH) * NS + t + SH];
+  return (t < -H || t > H) ? (T)0 : c.g[(s + H) * (2 * H + 1) + t + H];
 }
 
-template <typename T>
+template <typename T, int H>
 struct StencilLds {
   size_t D, Gx, Gxy, Gs, R, C, total;
   // forward: R = rows on the tile, C = columns on the window, nl local bins;
   // adjoint: R = the chunk's fields on the tile, C = U on the window, plus the
   // Q slab and the transposed-stencil scratch
   __host__ __device__ StencilLds(int nl, bool adjoint) {
+    STENCIL_GEOMETRY(H);
     size_t o = 0;
     auto take = [&](size_t b) { size_t r = o; o = (o + b + 15) & ~(size_t)15; return r; };
     D = take(SW3 * sizeof(T));
@@ -85,14 +91,20 @@ struct StencilLds {
 };
 
 // window index of window coordinates
-__device__ __forceinline__ int widx(int i, int j, int k) { return (i * SW + j) * SW + k; }
+template <int H>
+__device__ __forceinline__ int widx(int i, int j, int k) {
+  constexpr int SW = ST + 2 * H;
+  return (i * SW + j) * SW + k;
+}
 // tile cell index of tile coordinates
 __device__ __forceinline__ int tidx(int i, int j, int k) { return (i * ST + j) * ST + k; }
 
 // primary on the window, and its x-convolutions for every x-shift:
 // Gx[dx][xi][j][k] = sum_sx gamma(sx, sx + dx) delta(x0 + xi - sx, window j, k)
-template <typename T>
-__device__ void stencil_prepare(const T* dm, int n, int x0, int y0, int z0, const StencilCoef<T>& c, T* D, T* Gx) {
+template <typename T, int H>
+__device__ void stencil_prepare(const T* dm, int n, int x0, int y0, int z0, const StencilCoef<T, H>& c, T* D,
+                                T* Gx) {
+  STENCIL_GEOMETRY(H);
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int w = tid; w < SW3; w += nt) {
     const int i = w / (SW * SW), j = (w / SW) % SW, k = w % SW;
@@ -110,8 +122,9 @@ __device__ void stencil_prepare(const T* dm, int n, int x0, int y0, int z0, cons
 }
 
 // G_Delta on the tile for the 25 shifts of x-shift dx: Gs[(dy+2)*5 + dz+2][cell]
-template <typename T>
-__device__ void stencil_slab(int dx, const StencilCoef<T>& c, const T* Gx, T* Gxy, T* Gs) {
+template <typename T, int H>
+__device__ void stencil_slab(int dx, const StencilCoef<T, H>& c, const T* Gx, T* Gxy, T* Gs) {
+  STENCIL_GEOMETRY(H);
   const int tid = threadIdx.x, nt = blockDim.x;
   const T* gx = Gx + (dx + SH) * ST * SW * SW;
   for (int e = tid; e < NS * ST * ST * SW; e += nt) {
@@ -142,12 +155,13 @@ __device__ void stencil_slab(int dx, const StencilCoef<T>& c, const T* Gx, T* Gx
 // Threads own a 4x4 block of a pair (b-block i <= j) and a share of the
 // (shift, cell) terms; both orders of the pair are accumulated so that the
 // partial is symmetric exactly.
-template <typename T>
+template <typename T, int H>
 __global__ void __launch_bounds__(kStencilThreads) k_stencil_contract(const c2<T>* fields, const T* delta, int n,
                                                                      StencilGamma sg, double* partials, int nl,
                                                                      int nbt, int a0, int na, int c0) {
+  STENCIL_GEOMETRY(H);
   extern __shared__ __align__(16) char smem[];
-  const StencilLds<T> L(nl, false);
+  const StencilLds<T, H> L(nl, false);
   T* D = reinterpret_cast<T*>(smem + L.D);
   T* Gx = reinterpret_cast<T*>(smem + L.Gx);
   T* Gxy = reinterpret_cast<T*>(smem + L.Gxy);
@@ -155,7 +169,7 @@ __global__ void __launch_bounds__(kStencilThreads) k_stencil_contract(const c2<T
   c2<T>* Rw = reinterpret_cast<c2<T>*>(smem + L.R);
   c2<T>* Cw = reinterpret_cast<c2<T>*>(smem + L.C);
   __shared__ T gco[NS * NS];
-  const StencilCoef<T> c = coef_of<T>(sg, gco);
+  const StencilCoef<T, H> c = coef_of<T, H>(sg, gco);
   const int tid = threadIdx.x, nt = blockDim.x;
   const long long mock = blockIdx.y;
   const long long n3 = (long long)n * n * n;
@@ -193,10 +207,10 @@ __global__ void __launch_bounds__(kStencilThreads) k_stencil_contract(const c2<T
       if (i >= SH && i < SH + ST && j >= SH && j < SH + ST && k >= SH && k < SH + ST)
         Rw[tidx(i - SH, j - SH, k - SH) * nl + b] = v;
     }
-    stencil_prepare<T>(dm, n, x0, y0, z0, c, D, Gx);
+    stencil_prepare<T, H>(dm, n, x0, y0, z0, c, D, Gx);
     for (int dx = -SH; dx <= SH; ++dx) {
       __syncthreads();                            // Gx ready / the previous slab's Gs consumed
-      stencil_slab<T>(dx, c, Gx, Gxy, Gs);
+      stencil_slab<T, H>(dx, c, Gx, Gxy, Gs);
       __syncthreads();
       if (active) {
         for (int e = part; e < SLAB * ST3; e += parts) {
@@ -204,7 +218,7 @@ __global__ void __launch_bounds__(kStencilThreads) k_stencil_contract(const c2<T
           const int dy = sh / NS - SH, dz = sh % NS - SH;
           const T g = Gs[e];
           const int xi = cell / (ST * ST), yi = (cell / ST) % ST, zi = cell % ST;
-          const int ws = widx(xi + SH + dx, yi + SH + dy, zi + SH + dz);
+          const int ws = widx<H>(xi + SH + dx, yi + SH + dy, zi + SH + dz);
           c2<T> ri[4], rj[4], ci[4], cj[4];
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
@@ -258,13 +272,14 @@ __global__ void __launch_bounds__(kStencilThreads) k_stencil_contract(const c2<T
 // Source items (cell, bin) per thread: at most kSrcItems.
 constexpr int kSrcItems = 5;
 
-template <typename T>
+template <typename T, int H>
 __global__ void __launch_bounds__(kStencilThreads) k_stencil_adjoint(const c2<T>* fields, const c2<T>* U,
                                                                     const T* delta, int n, int nbt, int b0, int nbc,
                                                                     StencilGamma sg, double wm, c2<T>* cout,
                                                                     T* direct) {
+  STENCIL_GEOMETRY(H);
   extern __shared__ __align__(16) char smem[];
-  const StencilLds<T> L(nbc, true);
+  const StencilLds<T, H> L(nbc, true);
   T* D = reinterpret_cast<T*>(smem + L.D);
   T* Gx = reinterpret_cast<T*>(smem + L.Gx);
   T* Gxy = reinterpret_cast<T*>(smem + L.Gxy);
@@ -276,7 +291,7 @@ __global__ void __launch_bounds__(kStencilThreads) k_stencil_adjoint(const c2<T>
   T* Ty = Tz + NS * ST * ST * SW;
   T* Dw = Ty + ST * SW * SW;
   __shared__ T gco[NS * NS];
-  const StencilCoef<T> c = coef_of<T>(sg, gco);
+  const StencilCoef<T, H> c = coef_of<T, H>(sg, gco);
   const int tid = threadIdx.x, nt = blockDim.x;
   const long long mock = blockIdx.y;
   const long long n3 = (long long)n * n * n;
@@ -300,13 +315,13 @@ __global__ void __launch_bounds__(kStencilThreads) k_stencil_adjoint(const c2<T>
         Ar[tidx(i - SH, j - SH, k - SH) * nbc + b] = fm[cell * nbt + b0 + b];
     }
     for (int w = tid; w < SW3; w += nt) Dw[w] = 0;
-    stencil_prepare<T>(dm, n, x0, y0, z0, c, D, Gx);
+    stencil_prepare<T, H>(dm, n, x0, y0, z0, c, D, Gx);
     c2<T> src[kSrcItems];
 #pragma unroll
     for (int q = 0; q < kSrcItems; ++q) src[q] = mk<T>(0, 0);
     for (int dx = -SH; dx <= SH; ++dx) {
       __syncthreads();
-      stencil_slab<T>(dx, c, Gx, Gxy, Gs);
+      stencil_slab<T, H>(dx, c, Gx, Gxy, Gs);
       __syncthreads();
       // sources: every (cell, bin) item of this thread, over the slab's shifts
 #pragma unroll
@@ -319,7 +334,7 @@ __global__ void __launch_bounds__(kStencilThreads) k_stencil_adjoint(const c2<T>
           for (int sh = 0; sh < SLAB; ++sh) {
             const int dy = sh / NS - SH, dz = sh % NS - SH;
             const T g = Gs[sh * ST3 + cell];
-            const c2<T> u = Uw[widx(xi + SH + dx, yi + SH + dy, zi + SH + dz) * nbc + b];
+            const c2<T> u = Uw[widx<H>(xi + SH + dx, yi + SH + dy, zi + SH + dz) * nbc + b];
             s.x += g * u.x;
             s.y -= g * u.y;
           }
@@ -331,7 +346,7 @@ __global__ void __launch_bounds__(kStencilThreads) k_stencil_adjoint(const c2<T>
         const int sh = e / ST3, cell = e % ST3;
         const int dy = sh / NS - SH, dz = sh % NS - SH;
         const int xi = cell / (ST * ST), yi = (cell / ST) % ST, zi = cell % ST;
-        const c2<T>* ua = Uw + widx(xi + SH + dx, yi + SH + dy, zi + SH + dz) * nbc;
+        const c2<T>* ua = Uw + widx<H>(xi + SH + dx, yi + SH + dy, zi + SH + dz) * nbc;
         const c2<T>* aa = Ar + cell * nbc;
         T qv = 0;
         for (int b = 0; b < nbc; ++b) qv += aa[b].x * ua[b].x + aa[b].y * ua[b].y;
@@ -400,9 +415,9 @@ __global__ void __launch_bounds__(kStencilThreads) k_stencil_adjoint(const c2<T>
   }
 }
 
-template <typename T>
+template <typename T, int H>
 size_t stencil_need(int nl, bool adjoint) {
-  StencilLds<T> L(nl, adjoint);
+  StencilLds<T, H> L(nl, adjoint);
   size_t need = L.total;
   if (!adjoint) {
     const int nq = (nl + 3) / 4, npb = nq * (nq + 1) / 2;
@@ -422,58 +437,69 @@ hipError_t allow(K kern, size_t lds) {
 }  // namespace
 
 // dynamic LDS plus the kernels' static coefficient table
-constexpr size_t kStaticLds = 256;
+constexpr size_t kStaticLds = 512;
 
-size_t stencil_lds_need(int prec, int nl) {
-  return kStaticLds + (prec ? stencil_need<double>(nl, false) : stencil_need<float>(nl, false));
+size_t stencil_lds_need(int prec, int halo, int nl) {
+  if (halo == 2) return kStaticLds + (prec ? stencil_need<double, 2>(nl, false) : stencil_need<float, 2>(nl, false));
+  return kStaticLds + (prec ? stencil_need<double, 3>(nl, false) : stencil_need<float, 3>(nl, false));
 }
 
-size_t stencil_adjoint_lds_need(int prec, int nbc) {
+size_t stencil_adjoint_lds_need(int prec, int halo, int nbc) {
   if ((ST3 * nbc + kStencilThreads - 1) / kStencilThreads > kSrcItems) return (size_t)1 << 40;
-  return kStaticLds + (prec ? stencil_need<double>(nbc, true) : stencil_need<float>(nbc, true));
+  if (halo == 2) return kStaticLds + (prec ? stencil_need<double, 2>(nbc, true) : stencil_need<float, 2>(nbc, true));
+  return kStaticLds + (prec ? stencil_need<double, 3>(nbc, true) : stencil_need<float, 3>(nbc, true));
 }
+
+namespace {
+
+template <typename T, int H>
+hipError_t stencil_contract_t(const void* fields, const void* delta, int n, const BinPair& bp, const StencilGamma& sg,
+                              double* partials, int nl, dim3 gs, hipStream_t st) {
+  const size_t lds = stencil_need<T, H>(nl, false);
+  if (hipError_t e = allow(k_stencil_contract<T, H>, lds)) return e;
+  k_stencil_contract<T, H><<<gs, kStencilThreads, lds, st>>>(static_cast<const c2<T>*>(fields),
+                                                             static_cast<const T*>(delta), n, sg, partials, nl, bp.nbt,
+                                                             bp.a0, bp.na, bp.c0);
+  return hipGetLastError();
+}
+
+template <typename T, int H>
+hipError_t stencil_adjoint_t(const void* fields, const void* U, const void* delta, int n, int nbt, int b0, int nbc,
+                             const StencilGamma& sg, double wm, dim3 gs, void* cout, void* direct, hipStream_t st) {
+  const size_t lds = stencil_need<T, H>(nbc, true);
+  if (hipError_t e = allow(k_stencil_adjoint<T, H>, lds)) return e;
+  k_stencil_adjoint<T, H><<<gs, kStencilThreads, lds, st>>>(
+      static_cast<const c2<T>*>(fields), static_cast<const c2<T>*>(U), static_cast<const T*>(delta), n, nbt, b0, nbc,
+      sg, wm, static_cast<c2<T>*>(cout), static_cast<T*>(direct));
+  return hipGetLastError();
+}
+
+}  // namespace
 
 hipError_t launch_stencil_contract(int prec, const void* fields, const void* delta, int n, const BinPair& bp,
                                    const StencilGamma& sg, double* partials, int nwg, int batch, hipStream_t st) {
   const int nl = (bp.a0 == 0 && bp.na == bp.nbt) ? bp.nbt : bp.na + bp.nc;
-  if (n % ST != 0 || nwg < 1 || nl < 1) return hipErrorInvalidValue;
+  if (n % ST != 0 || nwg < 1 || nl < 1 || (sg.halo != 2 && sg.halo != 3)) return hipErrorInvalidValue;
   const dim3 gs((unsigned)nwg, (unsigned)batch);
-  if (prec) {
-    const size_t lds = stencil_need<double>(nl, false);
-    if (hipError_t e = allow(k_stencil_contract<double>, lds)) return e;
-    k_stencil_contract<double><<<gs, kStencilThreads, lds, st>>>(static_cast<const double2*>(fields),
-                                                                 static_cast<const double*>(delta), n, sg, partials,
-                                                                 nl, bp.nbt, bp.a0, bp.na, bp.c0);
-  } else {
-    const size_t lds = stencil_need<float>(nl, false);
-    if (hipError_t e = allow(k_stencil_contract<float>, lds)) return e;
-    k_stencil_contract<float><<<gs, kStencilThreads, lds, st>>>(static_cast<const float2*>(fields),
-                                                                static_cast<const float*>(delta), n, sg, partials,
-                                                                nl, bp.nbt, bp.a0, bp.na, bp.c0);
-  }
-  return hipGetLastError();
+  if (sg.halo == 2)
+    return prec ? stencil_contract_t<double, 2>(fields, delta, n, bp, sg, partials, nl, gs, st)
+                : stencil_contract_t<float, 2>(fields, delta, n, bp, sg, partials, nl, gs, st);
+  return prec ? stencil_contract_t<double, 3>(fields, delta, n, bp, sg, partials, nl, gs, st)
+              : stencil_contract_t<float, 3>(fields, delta, n, bp, sg, partials, nl, gs, st);
 }
 
 hipError_t launch_stencil_adjoint(int prec, const void* fields, const void* U, const void* delta, int n, int nbt,
                                   int b0, int nbc, const StencilGamma& sg, double wm, int nwg, int batch, void* cout,
                                   void* direct, hipStream_t st) {
-  if (n % ST != 0 || nwg < 1 || nbc < 1 || (ST3 * nbc + kStencilThreads - 1) / kStencilThreads > kSrcItems)
+  if (n % ST != 0 || nwg < 1 || nbc < 1 || (ST3 * nbc + kStencilThreads - 1) / kStencilThreads > kSrcItems ||
+      (sg.halo != 2 && sg.halo != 3))
     return hipErrorInvalidValue;
   const dim3 gs((unsigned)nwg, (unsigned)batch);
-  if (prec) {
-    const size_t lds = stencil_need<double>(nbc, true);
-    if (hipError_t e = allow(k_stencil_adjoint<double>, lds)) return e;
-    k_stencil_adjoint<double><<<gs, kStencilThreads, lds, st>>>(
-        static_cast<const double2*>(fields), static_cast<const double2*>(U), static_cast<const double*>(delta), n, nbt,
-        b0, nbc, sg, wm, static_cast<double2*>(cout), static_cast<double*>(direct));
-  } else {
-    const size_t lds = stencil_need<float>(nbc, true);
-    if (hipError_t e = allow(k_stencil_adjoint<float>, lds)) return e;
-    k_stencil_adjoint<float><<<gs, kStencilThreads, lds, st>>>(
-        static_cast<const float2*>(fields), static_cast<const float2*>(U), static_cast<const float*>(delta), n, nbt, b0,
-        nbc, sg, wm, static_cast<float2*>(cout), static_cast<float*>(direct));
-  }
-  return hipGetLastError();
+  if (sg.halo == 2)
+    return prec ? stencil_adjoint_t<double, 2>(fields, U, delta, n, nbt, b0, nbc, sg, wm, gs, cout, direct, st)
+                : stencil_adjoint_t<float, 2>(fields, U, delta, n, nbt, b0, nbc, sg, wm, gs, cout, direct, st);
+  return prec ? stencil_adjoint_t<double, 3>(fields, U, delta, n, nbt, b0, nbc, sg, wm, gs, cout, direct, st)
+              : stencil_adjoint_t<float, 3>(fields, U, delta, n, nbt, b0, nbc, sg, wm, gs, cout, direct, st);
 }
 
 }  // namespace mp3

@@ -306,6 +306,26 @@ void d4_gamma(double g[5][5]) {
     for (int t = 0; t < 5; ++t) g[s][t] = idx[s][t] < 0 ? 0.0 : at(idx[s][t], np) / at(idx[s][t], idx[s][t]);
 }
 
+void b3_gamma(double g[7][7]) {
+  // gamma(s, t) = int B3(u) B3(u - s) B3(u - t) du: on each unit interval of
+  // B3's support the integrand is a polynomial of degree 9, integrated exactly
+  // by 5-point Gauss-Legendre
+  std::vector<double> x, w;
+  gauss_legendre(5, x, w);
+  for (int s = -3; s <= 3; ++s) {
+    for (int t = -3; t <= 3; ++t) {
+      double acc = 0.0;
+      for (int j = -2; j < 2; ++j) {
+        for (int q = 0; q < 5; ++q) {
+          const double u = j + 0.5 * (x[q] + 1.0);
+          acc += 0.5 * w[q] * bspline3(u) * bspline3(u - s) * bspline3(u - t);
+        }
+      }
+      g[s + 3][t + 3] = acc;
+    }
+  }
+}
+
 double bspline3(double u) {
   const double a = std::fabs(u);
   if (a < 1.0) return (4.0 - 6.0 * a * a + 3.0 * a * a * a) / 6.0;

@@ -26,6 +26,8 @@ void d4_autocorr(const std::vector<double>& table, int level, double a[4]);
 void d4_phi_hat_axis(int n, std::vector<double>& out);
 // connection coefficients int phi phi(. - s) phi(. - t) of the Daubechies-4 function, g[s + 2][t + 2]
 void d4_gamma(double g[5][5]);
+// connection coefficients int B3 B3(. - s) B3(. - t) of the cubic B-spline, g[s + 3][t + 3]
+void b3_gamma(double g[7][7]);
 double ylm_norm(int l, int m);
 // centred cubic B-spline
 double bspline3(double u);

@@ -82,4 +82,4 @@ def test_tuning_knobs_reject_null_plan_and_bad_knobs():
     assert lib.mp3_tune_set(None, 0, 4096) == _lib.MP3_EINVAL
     assert lib.mp3_tune_get(None, 0, ctypes.byref(v)) == _lib.MP3_EINVAL
     assert v.value == -7
-    assert len(_lib.TUNE_KNOBS) == 7
+    assert len(_lib.TUNE_KNOBS) == 8

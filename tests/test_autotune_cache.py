@@ -72,5 +72,7 @@ def test_candidates_are_within_the_abi_ranges():
                 assert 0 <= v <= 8
             elif k == "item_group":
                 assert 0 <= v <= 1024
+            elif k == "gamma_adjoint":
+                assert v in (0, 1)
             else:
                 assert v in (4, 8, 16)

@@ -112,7 +112,8 @@ def test_tune_set_rejects_out_of_range(mp3):
     plan = mp3.Plan(16, 160.0, 1, [10.0, 20.0])
     for knob, bad in [("zpass_wgs", 10), ("zpass_wgs", 1 << 20), ("contract_wgs", 0), ("fft_x_plan", 2),
                       ("deposit_tile", 5), ("deposit_tile", 32), ("deposit_wgs", 63), ("fused_waves", -1),
-                      ("fused_waves", 9), ("item_group", -1), ("item_group", 1025)]:
+                      ("fused_waves", 9), ("item_group", -1), ("item_group", 1025),
+                      ("gamma_adjoint", 2), ("gamma_adjoint", -1)]:
         before = plan.tune_get(knob)
         with pytest.raises(mp3.Mp3Error):
             plan.tune_set(knob, bad)
@@ -211,3 +212,30 @@ def test_item_group_keeps_value_and_gradient(mp3, prec, group):
         ref = A.zeta_nodal_grad(op, dn[j], lam[j])
         for k in (1, 3):
             assert_grad_close(got[k][j], ref, 1e-10 if prec == "f64" else 1e-4, f"dJ/ddelta mock {j}")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("nb", [3, 20])
+def test_gamma_adjoint_kernels_agree(mp3, prec, nb):
+    """The B-spline grid-Gamma gradient by the shift stencil (default) and by the transposed node
+    quadrature: the same dJ/ddelta (1e-12 / 2e-5) and the oracle's (1e-10 / 1e-4), forward value too."""
+    from oracle import adjoint as A
+    from tests._common import assert_grad_close
+    _say("gamma adjoint kernels", prec, nb)
+    n, box, lmax = 16, 160.0, 2
+    edges = np.linspace(15.0, 55.0, nb + 1)
+    delta = random_field(n, 261 + nb)
+    lam = np.random.default_rng(262 + nb).standard_normal((lmax + 1, nb, nb))
+    dd = _dev(delta[None], torch.float64 if prec == "f64" else torch.float32)
+    lt = _dev(lam[None], torch.float64)
+    out = []
+    for k in (0, 1):
+        plan = mp3.Plan(n, box, lmax, edges, precision=prec, summation="gamma")
+        plan.tune_set("gamma_adjoint", k)
+        z, g, _ = plan.zeta_value_and_grad(dd, lt)
+        out.append((z.cpu().numpy()[0], g.cpu().numpy()[0]))
+    agree = 1e-12 if prec == "f64" else 2e-5
+    assert_zeta_close(out[0][0], out[1][0], agree)
+    assert np.abs(out[0][1] - out[1][1]).max() <= agree * np.abs(out[1][1]).max()
+    op = E.Plan(n, box, lmax, edges)
+    assert_grad_close(out[0][1], A.zeta_gamma_grad(op, delta, lam), 1e-10 if prec == "f64" else 1e-4, "dJ/ddelta")

@@ -103,13 +103,14 @@ def test_basis_tables_match_oracle(lib, n):
     tab = np.zeros(3 * 1024 + 1)
     acf = np.zeros(4)
     ph = np.zeros(n)
-    gam = np.zeros(25)
+    gam = np.zeros(49)
     assert lib.mp3_basis_tables(1, n, _dp(tab), tab.size, _dp(acf), _dp(ph), _dp(gam)) == 0
     assert np.abs(tab - D4.table(10)).max() < 1e-14
     assert np.abs(acf[:3] - D4.autocorr_samples()).max() < 1e-14 and acf[3] == 0.0
     assert np.abs(ph - D4.phi_hat_axis(n)).max() < 1e-13
-    assert np.abs(gam.reshape(5, 5) - D4.gamma_matrix()[1:6, 1:6]).max() < 1e-13
-    assert lib.mp3_basis_tables(0, n, None, 0, _dp(acf), _dp(ph), None) == 0
+    assert np.abs(gam.reshape(7, 7) - D4.gamma_matrix()).max() < 1e-13
+    assert lib.mp3_basis_tables(0, n, None, 0, _dp(acf), _dp(ph), _dp(gam)) == 0
+    assert np.abs(gam.reshape(7, 7) - B3.gamma_matrix()).max() < 1e-15
     b7 = B3.b7_samples()
     assert np.abs(acf - np.array([float(b7[s]) for s in range(4)])).max() < 1e-16
     plan = E.Plan(n, 100.0, 0, [1.0, 2.0], phi_hat=True)
@@ -121,6 +122,5 @@ def test_basis_tables_reject_bad_arguments(lib):
     assert lib.mp3_basis_tables(2, 16, None, 0, None, None, None) == -1
     assert lib.mp3_basis_tables(1, 16, _dp(tab), tab.size, None, None, None) == -1       # wrong count
     assert lib.mp3_basis_tables(0, 16, _dp(tab), tab.size, None, None, None) == -1       # no table for B3
-    assert lib.mp3_basis_tables(0, 16, None, 0, None, None, _dp(tab)) == -1              # no gamma for B3
     ph = np.zeros(24)
     assert lib.mp3_basis_tables(1, 24, None, 0, None, _dp(ph), None) == -4               # unsupported n
