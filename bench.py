@@ -93,6 +93,8 @@ def pmc_probe(wl, precision):
     pt, wt = torch.as_tensor(pos, device=dev), torch.as_tensor(w, device=dev)
     lam = torch.as_tensor(np.random.default_rng(11).standard_normal((1, wl.lmax + 1, wl.nbins, wl.nbins)), device=dev)
     plan = mp3.Plan(wl.n, wl.box, wl.lmax, wl.edges, precision=precision, device=dev)
+    from paper_2507_15209_amd import autotune as at
+    at.load_tuning(plan)                           # the knobs the bench runs with, when cached
     delta = plan.deposit(pt, wt)
     plan.zeta_value_and_grad(delta, lam, pt, wt)
     torch.cuda.synchronize()
@@ -495,6 +497,15 @@ def main():
     abytes = pass_bytes(dom, wl.n, wl.nbins, 1, real_bytes) * ipl
     achieved = abytes / (avg_ms * 1e-3) / 1e9
     log("per-pass totals (ms, launches):", {k: (round(v[0], 2), v[1]) for k, v in passes.items()})
+    # every pass with a byte model, for comparison with the dominant one
+    per_pass = {}
+    for k, (mt, c) in passes.items():
+        b = pass_bytes(k, wl.n, wl.nbins, 1, real_bytes)
+        if b is None:
+            continue
+        ipk = {"filter": 1, "x": 2, "z_fused": 1, "adjoint": 1}.get(k, 1) * items * prof_steps / c
+        ach_k = b * ipk / (mt / c * 1e-3) / 1e9
+        per_pass[k] = {"avg_launch_ms": mt / c, "achieved": ach_k, "frac": ach_k / HBM_PEAK_GBS}
     traffic = read_pmc(dom)
 
     two_calls = None
@@ -534,7 +545,8 @@ def main():
                    "n_particles": wl.n_particles, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": abytes, "items_per_launch": ipl},
+                     "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": abytes, "items_per_launch": ipl,
+                     "passes": per_pass},
         "passes_ms": {k: {"total_ms": v[0] / prof_steps, "launches": v[1] // prof_steps} for k, v in passes.items()},
         "profiled_ms_per_step": t_prof * 1e3,
         "two_calls": two_calls,
