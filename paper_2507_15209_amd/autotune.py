@@ -47,8 +47,17 @@ def cache_path(path: str | None = None) -> str:
     return os.path.join(os.path.expanduser("~"), ".cache", "mp3", "tuning.json")
 
 
+def _device_tag(device) -> str:
+    """Architecture and compute-unit count (stable across driver name strings)."""
+    if not torch.cuda.is_available():
+        return "nodevice"
+    prop = torch.cuda.get_device_properties(device)
+    arch = str(getattr(prop, "gcnArchName", "") or torch.cuda.get_device_name(device)).split(":")[0]
+    return f"{arch}/cu{prop.multi_processor_count}"
+
+
 def cache_key(plan) -> str:
-    name = torch.cuda.get_device_name(plan.device) if torch.cuda.is_available() else "nodevice"
+    name = _device_tag(plan.device)
     return (f"{name}|n={plan.n}|nbins={plan.nbins}|lmax={plan.lmax}|{plan.summation}|{plan.precision}"
             f"|batch={plan.batch}|basis={getattr(plan, 'basis', 'b3')}")
 
