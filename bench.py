@@ -263,6 +263,8 @@ def measure_form(name, steps=1):
                           device=dev)
     plan = mp3.Plan(wl.n, wl.box, wl.lmax, wl.edges, precision=precision, device=dev, summation=summation,
                     batch=batch, **opts)
+    from paper_2507_15209_amd import autotune as at
+    at.load_tuning(plan)                           # shipped knobs for this configuration, if any
     cat = (pt, wt, off) if summation == "particle" else ()
 
     def step():

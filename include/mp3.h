@@ -372,10 +372,11 @@ int mp3_profile_read(mp3_plan_t plan, int pass, double* total_ms, int64_t* launc
 
 /* Launch-shape knobs of a plan.  They change how the work is cut into
  * workgroups and which FFT radix plan a pass uses, never what is computed
- * (results agree to rounding order).  Defaults are the values measured best
- * for the 256^3, L = 10, 20-bin nodal workload on MI355X; the autotuner of
- * the Python package searches them per (n, nbins, lmax, form, precision,
- * batch, device) and caches the winners. */
+ * (results agree to rounding order).  Defaults are values measured good on
+ * MI355X across the benchmark workloads; the autotuner of the Python package
+ * searches them per (n, nbins, lmax, form, precision, batch, basis, device)
+ * and caches the winners (the package ships those of its benchmark
+ * workloads). */
 enum mp3_tune_knob {
   MP3_TUNE_ZPASS_WGS = 0,     /* workgroups of the z passes per call, split over the batch;
                                  64 .. 65536, default 4096                                       */
@@ -389,8 +390,9 @@ enum mp3_tune_knob {
                                  (never more than there are tiles)                               */
   MP3_TUNE_FUSED_WAVES = 5,   /* waves per workgroup of the one-sweep (value and gradient) z
                                  pass: 0 = the fewest whole waves that hold one round of every
-                                 bin's columns, else 1 .. 8 (default 4), raised to what n
-                                 needs (one thread per z point)                                  */
+                                 bin's columns (default; best measured at 128^3, 12 bins),
+                                 else 1 .. 8, raised to what n needs (one thread per z point;
+                                 4 is best measured at 256^3, 20 bins)                           */
   MP3_TUNE_ITEM_GROUP = 6,    /* (l, m) items per launch of the nodal adjoint passes (window,
                                  x and z passes of mp3_zeta_backward and the one sweep of
                                  mp3_zeta_value_and_grad): 0 = as many as fit 1 GiB of fields

@@ -25,7 +25,7 @@ struct mp3_plan_s {
   int device = 0;
   double gm[5][4] = {{0}};   // grid-Gamma quadrature: B3 tap weights at the nodes
   double gw[5] = {0};        // and node weights
-  int tune[MP3_NTUNE] = {4096, 4096, 0, 8, 2048, 4, 0, 0};   // launch-shape knobs (mp3_tune_knob)
+  int tune[MP3_NTUNE] = {4096, 4096, 0, 8, 2048, 0, 0, 0};   // launch-shape knobs (mp3_tune_knob)
   int basis = 0, binning = 0;
   unsigned kflags = 0;
   double smoothing = 0.0;   // top-hat radius of every vertex (0 = none)
