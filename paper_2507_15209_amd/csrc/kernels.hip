@@ -391,9 +391,10 @@ __global__ void __launch_bounds__((contig_pencils<N, T>() * Fft<N>::TPC)) k_fft_
 // ---------------------------------------------------------------------------
 template <int N, typename T>
 __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_filter_y(const c2<T>* dhat, c2<T>* fields,
-                                                                         const T* jtab, int nq2, int nbins, int nbp,
-                                                                         const ItemRec* items, int item0, int batch,
-                                                                         double scale, const c2<T>* tw, const T* phi) {
+                                                                         const T* jtab, int jmocks, int nq2, int nbins,
+                                                                         int nbp, const ItemRec* items, int item0,
+                                                                         int batch, double scale, const c2<T>* tw,
+                                                                         const T* phi) {
   using F = Fft<N, VB>;
   constexpr int ZC = zc_of<T>();
   constexpr int G = tiles_per_wg<N, T, VB>();
@@ -425,8 +426,9 @@ __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_filter_y(cons
     const c2<T> f = window_angular<T>(qx, qy, qz, N, it.l, it.m, it.norm, scale, it.yr, q2[r], phi);
     v0[r] = cmul<T>(d, f);
   }
-  // radial window of this thread's elements, four bins per load, one quad ahead
-  const T* jl = jtab + (long long)it.l * nq2 * nbp;
+  // radial window of this thread's elements, four bins per load, one quad
+  // ahead (jmocks tables per l: one, or one per mock in the cotangent's eigenbasis)
+  const T* jl = jtab + ((long long)it.l * jmocks + mock % jmocks) * nq2 * nbp;
   T jq[RMAX][4];
 #pragma unroll
   for (int r = 0; r < RMAX; ++r) load_quad<T>(jl + (long long)q2[r] * nbp, jq[r]);
@@ -1467,7 +1469,7 @@ __global__ void k_reduce_partials(const double* partials, int nwg, int nb2, doub
 // ---------------------------------------------------------------------------
 template <int N, typename T, int MAXNB, bool FUSED = false, bool MF = false, bool QUAD = false>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FUSED && MF ? 3 : 1)))
-k_zpass_adjoint(c2<T>* fields, const T* delta, const T* __restrict__ lam_s, T* direct, int nbins, int ppw,
+k_zpass_adjoint(c2<T>* fields, const T* delta, const T* __restrict__ lam_d, T* direct, int nbins, int ppw,
                 const c2<T>* tw, double* partials, const ItemRec* items, int item0, int nitems, int batch, int nwg,
                 int* counter) {
   using F = Fft<N, VZA<T>>;
@@ -1478,8 +1480,8 @@ k_zpass_adjoint(c2<T>* fields, const T* delta, const T* __restrict__ lam_s, T* d
   __shared__ int s_unit;
   c2<T>* A = reinterpret_cast<c2<T>*>(smem);
   c2<T>* tws = A + nbins * RS;
-  T* lam = reinterpret_cast<T*>(tws + N);             // [nbins][NBP], zero padded
-  T* dl = lam + nbins * NBP;                          // FUSED: delta of the pencil
+  T* lam = reinterpret_cast<T*>(tws + N);             // [NBP] eigenvalues of the cotangent, zero padded
+  T* dl = lam + NBP;                                  // FUSED: delta of the pencil
   const int tid = threadIdx.x;
   const int nbc = blockDim.x / F::TPC;
   const int nb2 = nbins * nbins;
@@ -1504,11 +1506,8 @@ k_zpass_adjoint(c2<T>* fields, const T* delta, const T* __restrict__ lam_s, T* d
     const ItemRec& it = items[item0 + g];
     const T wm = (T)it.wm;
     stage_twiddles<N, T>(tw, tws);
-    const T* ls = lam_s + ((long long)it.l * batch + mock) * nb2;
-    for (int t = tid; t < nbins * NBP; t += blockDim.x) {
-      const int bp = t / NBP, b = t % NBP;
-      lam[t] = b < nbins ? ls[bp * nbins + b] : (T)0;
-    }
+    const T* ls = lam_d + ((long long)it.l * batch + mock) * nbins;
+    for (int t = tid; t < NBP; t += blockDim.x) lam[t] = t < nbins ? ls[t] : (T)0;
     __syncthreads();
     Contractor<T, MF, false, QUAD> ctr;
     if constexpr (FUSED) ctr.init(nbins);
@@ -1582,33 +1581,23 @@ k_zpass_adjoint(c2<T>* fields, const T* delta, const T* __restrict__ lam_s, T* d
         const int z = tid + k * blockDim.x;
         if (z >= N) continue;
         const int zp = lds_pos<true>(z);
-        c2<T> u[MAXNB];
-#pragma unroll
-        for (int b = 0; b < MAXNB; ++b) u[b] = mk<T>(0, 0);
-        for (int bp = 0; bp < nbins; ++bp) {
-          const c2<T> a = A[bp * RS + zp];
-          const T* lrow = lam + bp * NBP;            // lam_s is symmetric: row bp = column bp
-#pragma unroll
-          for (int bq = 0; bq < NBP; bq += 4) {
-            T lq[4];
-            load_quad<T>(lrow + bq, lq);             // LDS broadcast
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              if (bq + k < MAXNB) {
-                u[bq + k].x += lq[k] * a.x;
-                u[bq + k].y -= lq[k] * a.y;
-              }
-            }
-          }
-        }
+        // in the eigenbasis of the cotangent the source of field k is
+        // d_k conj(a_k) delta and the direct term sum_k d_k |a_k|^2
         const T d = dcur[k];
         T dir = 0;
 #pragma unroll
-        for (int b = 0; b < MAXNB; ++b) {
-          if (b < nbins) {
-            const c2<T> a = A[b * RS + zp];
-            dir += a.x * u[b].x - a.y * u[b].y;
-            A[b * RS + zp] = mk<T>(d * u[b].x, d * u[b].y);
+        for (int bq = 0; bq < NBP; bq += 4) {
+          T lq[4];
+          load_quad<T>(lam + bq, lq);                // LDS broadcast
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int b = bq + i;
+            if (b < nbins) {
+              const c2<T> a = A[b * RS + zp];
+              const T e = lq[i] * a.x, f = lq[i] * a.y;
+              dir += e * a.x + f * a.y;
+              A[b * RS + zp] = mk<T>(d * e, -(d * f));
+            }
           }
         }
         if (shared_direct) atomicAdd(&rmock[(long long)p * N + z], wm * dir);
@@ -1654,15 +1643,209 @@ __global__ void k_lam_sym(const double* dzeta, T* lam_s, int nbins, int lmax, in
 }
 
 // ---------------------------------------------------------------------------
+// The nodal gradient in the eigenbasis of the cotangent.  The symmetrised
+// cotangent of multipole l and mock j is real symmetric, lam_s = V diag(d) V^T
+// with V orthogonal, so sum_{b,b'} lam_s[b][b'] a_b conj(a_b') equals
+// sum_k d_k |abar_k|^2 for the rotated fields abar_k = sum_b V[b][k] a_b.  The
+// window pass is linear in the radial table, so the rotated fields come from
+// the rotated table jbar_{l,k} = sum_b V[b][k] jbar_{l,b}; the adjoint sources
+// become diagonal, and the value in the rotated basis is turned back by
+// zeta = V zetabar V^T.
+// ---------------------------------------------------------------------------
+constexpr int kEigMaxBins = 64;
+
+// LDS bytes of k_lam_eig for nbins bins
+inline size_t lam_eig_lds(int nbins) {
+  const int half = (nbins + 1) / 2;
+  return (size_t)2 * nbins * (nbins + 1) * sizeof(double) + (size_t)2 * half * sizeof(double) +
+         (size_t)2 * 8 * sizeof(double) + (size_t)2 * half * sizeof(int);
+}
+
+// One workgroup per (l, mock): cyclic Jacobi in float64 with the round-robin
+// pair order (each round rotates nbins / 2 disjoint index pairs at once, which
+// commute), until the off-diagonal norm is below 1e-14 of the matrix norm or
+// after kEigSweeps sweeps.  Writes the eigenvalues d [l][mock][nbins] at the
+// plan precision and the eigenvectors V [l][mock][nbins][nbins] (columns) in
+// float64.
+constexpr int kEigSweeps = 40;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_lam_eig(const double* dzeta, T* lam_d, double* evec, int nbins, int lmax,
+                                                 int batch) {
+  extern __shared__ __align__(16) char smem[];
+  const int l = blockIdx.x, j = blockIdx.y, nb = nbins, ld = nbins + 1;
+  const int m = (nb + 1) & ~1, half = m / 2;   // an even index count: index nb is a dummy when nb is odd
+  double* A = reinterpret_cast<double*>(smem);
+  double* V = A + nb * ld;
+  double* cs = V + nb * ld;
+  double* sn = cs + half;
+  double* red = sn + half;                      // [2][8]: per-wave partial norms
+  int* pp = reinterpret_cast<int*>(red + 16);
+  int* pq = pp + half;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const double* dz = dzeta + ((long long)j * (lmax + 1) + l) * nb * nb;
+  for (int t = tid; t < nb * nb; t += nt) {
+    const int b = t / nb, c = t % nb;
+    A[b * ld + c] = 0.5 * (dz[b * nb + c] + dz[c * nb + b]);
+    V[b * ld + c] = b == c ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < kEigSweeps; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int t = tid; t < nb * nb; t += nt) {
+      const int b = t / nb, c = t % nb;
+      const double a2 = A[b * ld + c] * A[b * ld + c];
+      tot += a2;
+      if (b != c) off += a2;
+    }
+    for (int o = warpSize / 2; o > 0; o >>= 1) {
+      off += __shfl_down(off, o);
+      tot += __shfl_down(tot, o);
+    }
+    if (tid % warpSize == 0) {
+      red[tid / warpSize] = off;
+      red[8 + tid / warpSize] = tot;
+    }
+    __syncthreads();
+    off = 0.0;
+    tot = 0.0;
+    for (int w = 0; w < (nt + warpSize - 1) / warpSize; ++w) {
+      off += red[w];
+      tot += red[8 + w];
+    }
+    __syncthreads();   // every thread has read red before it is written again
+    if (!(off > 1e-28 * tot)) break;   // also ends on an all-zero matrix
+    for (int r = 0; r + 1 < m; ++r) {
+      // round r pairs index m - 1 with r and (r + k) with (r - k) modulo m - 1
+      if (tid < half) {
+        int p = tid == 0 ? r : (r + tid) % (m - 1);
+        int q = tid == 0 ? m - 1 : (r - tid + (m - 1)) % (m - 1);
+        if (p > q) {
+          const int s = p;
+          p = q;
+          q = s;
+        }
+        double c = 1.0, s = 0.0;
+        if (q < nb) {
+          const double apq = A[p * ld + q];
+          if (apq != 0.0) {
+            // the rotation that zeroes the (p, q) entry, the smaller of the two angles
+            const double tau = (A[q * ld + q] - A[p * ld + p]) / (2.0 * apq);
+            const double at = fabs(tau);
+            const double tt = at > 1e150 ? 0.5 / tau : (tau >= 0.0 ? 1.0 : -1.0) / (at + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
+          }
+        } else {
+          q = -1;   // the dummy index: no rotation
+        }
+        pp[tid] = p;
+        pq[tid] = q;
+        cs[tid] = c;
+        sn[tid] = s;
+      }
+      __syncthreads();
+      // columns p, q of A and of V (A J, V J)
+      for (int t = tid; t < nb * half; t += nt) {
+        const int i = t / half, k = t % half;
+        const int p = pp[k], q = pq[k];
+        if (q < 0) continue;
+        const double c = cs[k], s = sn[k];
+        const double ap = A[i * ld + p], aq = A[i * ld + q];
+        A[i * ld + p] = c * ap - s * aq;
+        A[i * ld + q] = s * ap + c * aq;
+        const double vp = V[i * ld + p], vq = V[i * ld + q];
+        V[i * ld + p] = c * vp - s * vq;
+        V[i * ld + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+      // rows p, q of A (J^T A J); the rotated pair's own entries are zero
+      for (int t = tid; t < nb * half; t += nt) {
+        const int k = t / nb, c2i = t % nb;
+        const int p = pp[k], q = pq[k];
+        if (q < 0) continue;
+        const double c = cs[k], s = sn[k];
+        const double ap = A[p * ld + c2i], aq = A[q * ld + c2i];
+        A[p * ld + c2i] = (c2i == q) ? 0.0 : c * ap - s * aq;
+        A[q * ld + c2i] = (c2i == p) ? 0.0 : s * ap + c * aq;
+      }
+      __syncthreads();
+    }
+  }
+  const long long lj = (long long)l * batch + j;
+  for (int b = tid; b < nb; b += nt) lam_d[lj * nb + b] = (T)A[b * ld + b];
+  for (int t = tid; t < nb * nb; t += nt) evec[lj * nb * nb + t] = V[(t / nb) * ld + t % nb];
+}
+
+// jrot[l][mock][q2][k] = sum_b jtab[l][q2][b] V_{l,mock}[b][k], zero for k >= nbins
+// (grid.y = (l, mock)); MB >= nbins bins held in registers
+template <typename T, int MB>
+__global__ void __launch_bounds__(256) k_rotate_jtab(const T* jtab, T* jrot, const double* evec, int nq2, int nbins,
+                                                     int nbp, int batch) {
+  __shared__ double v[MB * MB];
+  const int lj = blockIdx.y, l = lj / batch;
+  const double* V = evec + (long long)lj * nbins * nbins;
+  for (int t = threadIdx.x; t < nbins * nbins; t += blockDim.x) v[(t / nbins) * MB + t % nbins] = V[t];
+  __syncthreads();
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nq2; q += gridDim.x * blockDim.x) {
+    const T* src = jtab + ((long long)l * nq2 + q) * nbp;
+    T* dst = jrot + ((long long)lj * nq2 + q) * nbp;
+    double jb[MB];
+#pragma unroll
+    for (int b = 0; b < MB; ++b) jb[b] = b < nbins ? (double)src[b] : 0.0;
+    for (int k = 0; k < nbp; ++k) {
+      double acc = 0.0;
+      if (k < nbins) {
+#pragma unroll
+        for (int b = 0; b < MB; ++b)
+          if (b < nbins) acc += jb[b] * v[b * MB + k];
+      }
+      dst[k] = (T)acc;
+    }
+  }
+}
+
+// zeta[mock][l] = V zetabar V^T in place, written symmetric (one workgroup per (l, mock))
+__global__ void __launch_bounds__(256) k_rotate_zeta(double* zeta, const double* evec, int nbins, int lmax, int batch) {
+  extern __shared__ __align__(16) char smem[];
+  const int l = blockIdx.x, j = blockIdx.y, nb = nbins, nb2 = nbins * nbins;
+  double* zt = reinterpret_cast<double*>(smem);   // zetabar
+  double* v = zt + nb2;
+  double* w = v + nb2;                             // V zetabar
+  double* z = zeta + ((long long)j * (lmax + 1) + l) * nb2;
+  const double* V = evec + ((long long)l * batch + j) * nb2;
+  for (int t = threadIdx.x; t < nb2; t += blockDim.x) {
+    zt[t] = z[t];
+    v[t] = V[t];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nb2; t += blockDim.x) {
+    const int b = t / nb, kp = t % nb;
+    double s = 0.0;
+    for (int k = 0; k < nb; ++k) s += v[b * nb + k] * zt[k * nb + kp];
+    w[t] = s;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nb2; t += blockDim.x) {
+    const int b = t / nb, bp = t % nb;
+    if (b > bp) continue;
+    double s = 0.0;
+    for (int k = 0; k < nb; ++k) s += w[b * nb + k] * v[bp * nb + k];
+    z[b * nb + bp] = s;
+    z[bp * nb + b] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // last adjoint pass: y-transform of every adjoint source c_b, times the window,
 // summed over bins and accumulated into G(q) (one read-modify-write per (l, m))
 // ---------------------------------------------------------------------------
 template <int N, typename T>
 __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_adjoint_y(const c2<T>* fields, c2<T>* G,
-                                                                          const T* jtab, int nq2, int nbins, int nbp,
-                                                                          const ItemRec* items, int item0, int nitems,
-                                                                          int batch, double scale, const c2<T>* tw,
-                                                                          const T* phi) {
+                                                                          const T* jtab, int jmocks, int nq2, int nbins,
+                                                                          int nbp, const ItemRec* items, int item0,
+                                                                          int nitems, int batch, double scale,
+                                                                          const c2<T>* tw, const T* phi) {
   using F = Fft<N, VB>;
   constexpr int ZC = zc_of<T>();
   constexpr int GT = tiles_per_wg<N, T, VB>();
@@ -1692,7 +1875,7 @@ __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_adjoint_y(con
 #pragma unroll
     for (int e = 0; e < RMAX; ++e)
       fac[e] = window_angular<T>(qx, F::out_index(j, e), qz, N, it.l, it.m, it.norm, scale * it.wm, it.yr, q2[e], phi);
-    const T* jl = jtab + (long long)it.l * nq2 * nbp;
+    const T* jl = jtab + ((long long)it.l * jmocks + mock % jmocks) * nq2 * nbp;
     const c2<T>* src = fields + ((long long)gi * batch + mock) * nbins * N3 + (long long)qx * N * N + qz;
     // next bin's column, one bin ahead
     c2<T> vn[RMAX];
@@ -2854,8 +3037,8 @@ hipError_t filter_y_t(const FilterArgs& a, hipStream_t st) {
   constexpr int threads = Fft<N, VB>::TPC * ZC * G;
   const dim3 gs((N * (N / ZC) + G - 1) / G, a.batch * a.nitems);
   k_filter_y<N, T><<<gs, threads, 0, st>>>(static_cast<const CT<T>*>(a.src), static_cast<CT<T>*>(a.dst),
-                                          static_cast<const T*>(a.jtab), a.nq2, a.nbins, a.nbp, a.items, a.item0,
-                                          a.batch, a.scale, static_cast<const CT<T>*>(a.tw),
+                                          static_cast<const T*>(a.jtab), a.jmocks, a.nq2, a.nbins, a.nbp, a.items,
+                                          a.item0, a.batch, a.scale, static_cast<const CT<T>*>(a.tw),
                                           static_cast<const T*>(a.phi));
   return hipGetLastError();
 }
@@ -2867,8 +3050,8 @@ hipError_t adjoint_y_t(const FilterArgs& a, hipStream_t st) {
   constexpr int threads = Fft<N, VB>::TPC * ZC * G;
   const dim3 gs((N * (N / ZC) + G - 1) / G, a.batch);
   k_adjoint_y<N, T><<<gs, threads, 0, st>>>(static_cast<const CT<T>*>(a.src), static_cast<CT<T>*>(a.dst),
-                                           static_cast<const T*>(a.jtab), a.nq2, a.nbins, a.nbp, a.items, a.item0,
-                                           a.nitems, a.batch, a.scale, static_cast<const CT<T>*>(a.tw),
+                                           static_cast<const T*>(a.jtab), a.jmocks, a.nq2, a.nbins, a.nbp, a.items,
+                                           a.item0, a.nitems, a.batch, a.scale, static_cast<const CT<T>*>(a.tw),
                                            static_cast<const T*>(a.phi));
   return hipGetLastError();
 }
@@ -2896,12 +3079,10 @@ template <int N, typename T> inline size_t zpass_nodal_lds(int nbins, int thread
 
 template <int N, typename T> inline size_t zpass_adjoint_lds(int nbins) {
   constexpr int RS = zrow<N>();
-  const size_t nbp = (size_t)(nbins + 3) / 4 * 4;
-  // nbp here is the padded stride of the largest MAXNB that serves nbins
+  // the cotangent's eigenvalues, padded to the largest MAXNB that serves nbins
   const size_t maxnb = nbins <= 8 ? 8 : nbins <= 12 ? 12 : nbins <= 16 ? 16 : nbins <= 20 ? 20 : nbins <= 24 ? 24
                        : nbins <= 32 ? 32 : nbins <= 48 ? 48 : 64;
-  (void)nbp;
-  return (size_t)nbins * RS * sizeof(CT<T>) + (size_t)N * sizeof(CT<T>) + (size_t)nbins * maxnb * sizeof(T);
+  return (size_t)nbins * RS * sizeof(CT<T>) + (size_t)N * sizeof(CT<T>) + maxnb * sizeof(T);
 }
 
 template <typename K> hipError_t allow_lds(K kernel, size_t bytes) {
@@ -3135,6 +3316,51 @@ hipError_t launch_lam_sym(int prec, const double* dzeta, void* lam_s, int nbins,
   const dim3 gs(lmax + 1, batch);
   if (prec) k_lam_sym<double><<<gs, 256, 0, st>>>(dzeta, static_cast<double*>(lam_s), nbins, lmax, batch);
   else k_lam_sym<float><<<gs, 256, 0, st>>>(dzeta, static_cast<float*>(lam_s), nbins, lmax, batch);
+  return hipGetLastError();
+}
+
+hipError_t launch_lam_eig(int prec, const double* dzeta, void* lam_d, double* evec, int nbins, int lmax, int batch,
+                          hipStream_t st) {
+  if (nbins < 1 || nbins > kEigMaxBins) return hipErrorInvalidValue;
+  const dim3 gs(lmax + 1, batch);
+  const size_t lds = lam_eig_lds(nbins);
+  if (prec) {
+    hipError_t e = allow_lds(k_lam_eig<double>, lds);
+    if (e != hipSuccess) return e;
+    k_lam_eig<double><<<gs, 256, lds, st>>>(dzeta, static_cast<double*>(lam_d), evec, nbins, lmax, batch);
+  } else {
+    hipError_t e = allow_lds(k_lam_eig<float>, lds);
+    if (e != hipSuccess) return e;
+    k_lam_eig<float><<<gs, 256, lds, st>>>(dzeta, static_cast<float*>(lam_d), evec, nbins, lmax, batch);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t rotate_jtab_t(const void* jtab, void* jrot, const double* evec, int nq2, int nbins, int nbp, int lmax,
+                         int batch, hipStream_t st) {
+  const dim3 gs((unsigned)grid_for(nq2, 256, 64), (unsigned)((lmax + 1) * batch));
+  const T* src = static_cast<const T*>(jtab);
+  T* dst = static_cast<T*>(jrot);
+  if (nbins <= 16) k_rotate_jtab<T, 16><<<gs, 256, 0, st>>>(src, dst, evec, nq2, nbins, nbp, batch);
+  else if (nbins <= 32) k_rotate_jtab<T, 32><<<gs, 256, 0, st>>>(src, dst, evec, nq2, nbins, nbp, batch);
+  else k_rotate_jtab<T, 64><<<gs, 256, 0, st>>>(src, dst, evec, nq2, nbins, nbp, batch);
+  return hipGetLastError();
+}
+
+hipError_t launch_rotate_jtab(int prec, const void* jtab, void* jrot, const double* evec, int nq2, int nbins, int nbp,
+                              int lmax, int batch, hipStream_t st) {
+  if (nbins < 1 || nbins > kEigMaxBins || nbp < nbins) return hipErrorInvalidValue;
+  return prec ? rotate_jtab_t<double>(jtab, jrot, evec, nq2, nbins, nbp, lmax, batch, st)
+              : rotate_jtab_t<float>(jtab, jrot, evec, nq2, nbins, nbp, lmax, batch, st);
+}
+
+hipError_t launch_rotate_zeta(double* zeta, const double* evec, int nbins, int lmax, int batch, hipStream_t st) {
+  if (nbins < 1 || nbins > kEigMaxBins) return hipErrorInvalidValue;
+  const size_t lds = (size_t)3 * nbins * nbins * sizeof(double);
+  hipError_t e = allow_lds(k_rotate_zeta, lds);
+  if (e != hipSuccess) return e;
+  k_rotate_zeta<<<dim3(lmax + 1, batch), 256, lds, st>>>(zeta, evec, nbins, lmax, batch);
   return hipGetLastError();
 }
 

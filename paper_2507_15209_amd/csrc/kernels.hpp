@@ -38,7 +38,8 @@ struct ItemRec {
 struct FilterArgs {
   const void* src;   // k_filter_y: dhat [batch][N^3]; k_adjoint_y: sources [item][batch][nbins][N^3]
   void* dst;         // k_filter_y: fields [item][batch][nbins][N^3]; k_adjoint_y: accumulator G [batch][N^3]
-  const void* jtab;  // [lmax+1][nq2][nbp] radial window, bin axis padded to nbp = 4 ceil(nbins / 4)
+  const void* jtab;  // [lmax+1][jmocks][nq2][nbp] radial window, bin axis padded to nbp = 4 ceil(nbins / 4)
+  int jmocks = 1;    // tables per l: 1 (the plan's), or batch (rotated into each mock's cotangent eigenbasis)
   const void* tw;    // twiddles exp(-2 pi i t / N)
   int nq2, nbins, nbp, batch;
   const ItemRec* items;   // device item table
@@ -53,7 +54,7 @@ struct ZpassArgs {
   double* partials;     // forward: [batch][nwg][nbins^2]; one sweep: [item][batch][nwg][nbins^2]
   const double* dzeta;  // backward: [batch][lmax+1][nbins^2]
   void* direct;         // backward: [batch][N^3] explicit-primary gradient accumulator
-  const void* lam;      // backward: symmetrised dzeta, [lmax+1][batch][nbins^2] real
+  const void* lam;      // backward: eigenvalues of the symmetrised dzeta, [lmax+1][batch][nbins] real
   const void* tw;
   int nbins, nwg, ppw, batch, l, lmax;
   bool split;           // float32 contraction with BF16-split inputs on the matrix cores
@@ -169,6 +170,15 @@ hipError_t launch_fill_f64(double* p, long long count, double value, hipStream_t
 hipError_t launch_fill_i32(int* p, long long count, int value, hipStream_t st);
 // lam_s[l][batch][nbins^2] for every l <= lmax
 hipError_t launch_lam_sym(int prec, const double* dzeta, void* lam_s, int nbins, int lmax, int batch, hipStream_t st);
+// eigen-decomposition of every symmetrised cotangent (float64 Jacobi, nbins <= 64): eigenvalues
+// lam_d[l][batch][nbins] at the plan precision, eigenvectors evec[l][batch][nbins][nbins] (columns)
+hipError_t launch_lam_eig(int prec, const double* dzeta, void* lam_d, double* evec, int nbins, int lmax, int batch,
+                          hipStream_t st);
+// jrot[l][batch][nq2][nbp] = jtab[l][nq2][:] rotated by evec[l][batch]
+hipError_t launch_rotate_jtab(int prec, const void* jtab, void* jrot, const double* evec, int nq2, int nbins, int nbp,
+                              int lmax, int batch, hipStream_t st);
+// zeta[batch][l] = evec zeta evec^T for every l (the value of the rotated fields back to the bins)
+hipError_t launch_rotate_zeta(double* zeta, const double* evec, int nbins, int lmax, int batch, hipStream_t st);
 // partials of a group of items [item][batch][nwg][nb2] into zeta at each item's l (times scale and the item's m weight)
 hipError_t launch_reduce_items(const double* partials, int nwg, int nb2, double* zeta, int lmax, double scale,
                                const ItemRec* items, int item0, int nitems, int batch, hipStream_t st);

@@ -71,6 +71,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
   size_t dprim, flag, pplain, aux, xib, fields_u, counter;
+  size_t evec, jrot;   // nodal gradient: the cotangents' eigenvectors and the rotated radial tables
   int group;   // (l, m) items per launch of the one-sweep nodal passes
   size_t off, W, S, dhat, fields, partials, G, direct, lam, fields_i, perm, counts, offs, cursor, power;
   size_t src, fj, hq, SF, tcell, twt;
@@ -158,6 +159,10 @@ Layout layout(const mp3_plan_s* p, long long np_total = 0) {
   L.direct = take(B * n3 * p->elt);
   L.lam = take((size_t)(p->lmax + 1) * B * nb2 * p->elt);
   L.counter = take(sizeof(int));
+  if (p->summation == MP3_SUM_NODAL) {
+    L.evec = take((size_t)(p->lmax + 1) * B * nb2 * sizeof(double));
+    L.jrot = take((size_t)(p->lmax + 1) * B * (size_t)p->nq2 * p->nbp * p->elt);
+  }
   // primary vertex filtered by the top-hat window (grid forms with smoothing)
   if (p->smoothing > 0.0 && p->summation != MP3_SUM_PARTICLE) L.dprim = take(B * n3 * p->elt);
   L.flag = take(sizeof(int));
@@ -340,12 +345,27 @@ int lam_all(const mp3_plan_s* p, const double* dzeta, void* ws, const Layout& L,
   return MP3_OK;
 }
 
+// The nodal gradient runs in the eigenbasis of each symmetrised cotangent
+// lam_s = V diag(d) V^T (per l and mock): the eigenvalues d into the lambda
+// slot, V into L.evec, and the radial tables rotated by V into L.jrot.
+int lam_eig_all(const mp3_plan_s* p, const double* dzeta, void* ws, const Layout& L, hipStream_t st) {
+  double* evec = reinterpret_cast<double*>(at(ws, L.evec));
+  MP3_HIP(mp3::launch_lam_eig(p->prec, dzeta, at(ws, L.lam), evec, p->nbins, p->lmax, p->batch, st),
+          "cotangent eigenbasis");
+  MP3_HIP(mp3::launch_rotate_jtab(p->prec, p->jtab, at(ws, L.jrot), evec, p->nq2, p->nbins, p->nbp, p->lmax,
+                                  p->batch, st),
+          "rotated radial tables");
+  return MP3_OK;
+}
+
+// rotated: the radial tables of the cotangents' eigenbasis (lam_eig_all), one per (l, mock)
 mp3::FilterArgs filter_args(const mp3_plan_s* p, void* ws, const Layout& L, const void* src, void* dst, int item0,
-                            int nitems) {
+                            int nitems, bool rotated = false) {
   mp3::FilterArgs a;
   a.src = src;
   a.dst = dst;
-  a.jtab = p->jtab;
+  a.jtab = rotated ? at(ws, L.jrot) : p->jtab;
+  a.jmocks = rotated ? p->batch : 1;
   a.tw = p->tw;
   a.nq2 = p->nq2;
   a.nbp = p->nbp;
@@ -382,8 +402,9 @@ mp3::ZpassArgs adjoint_zargs(const mp3_plan_s* p, void* ws, const Layout& L, voi
 }
 
 // fields of a group of items after the y and x passes: layout [item][batch][nbins][x][y][qz]
-int fields_xy(const mp3_plan_s* p, void* ws, const Layout& L, void* dst, int item0, int nitems, hipStream_t st) {
-  mp3::FilterArgs a = filter_args(p, ws, L, at(ws, L.dhat), dst, item0, nitems);
+int fields_xy(const mp3_plan_s* p, void* ws, const Layout& L, void* dst, int item0, int nitems, hipStream_t st,
+              bool rotated = false) {
+  mp3::FilterArgs a = filter_args(p, ws, L, at(ws, L.dhat), dst, item0, nitems, rotated);
   MP3_HIP(timed(p, MP3_PASS_FILTER, st, [&] { return mp3::launch_filter_y(p->n, p->prec, a, st); }), "window pass");
   MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, dst, nitems * p->batch * p->nbins, p->tw, p->tune[MP3_TUNE_FFT_X_PLAN], st); }), "x pass");
   return MP3_OK;
@@ -1301,7 +1322,7 @@ int mp3_zeta_backward(mp3_plan_t p, const void* delta, const double* dzeta, void
   const long long n3 = (long long)p->n * p->n * p->n;
   if (int s = check_finite(p, ws, L.flag, st, delta, n3 * p->batch, p->prec)) return s;
   if (int s = forward_dft(p, delta, ws, L, st)) return s;
-  if (int s = lam_all(p, dzeta, ws, L, st)) return s;
+  if (int s = lam_eig_all(p, dzeta, ws, L, st)) return s;
   int ps = MP3_OK;
   const void* prim = primary_field(p, delta, ws, L, st, &ps);
   if (ps) return ps;
@@ -1313,11 +1334,11 @@ int mp3_zeta_backward(mp3_plan_t p, const void* delta, const double* dzeta, void
   const int nitems_all = (int)p->items.size();
   for (int item0 = 0; item0 < nitems_all; item0 += L.group) {
     const int ni = std::min(L.group, nitems_all - item0);
-    if (int s = fields_xy(p, ws, L, F, item0, ni, st)) return s;
+    if (int s = fields_xy(p, ws, L, F, item0, ni, st, true)) return s;
     mp3::ZpassArgs z = adjoint_zargs(p, ws, L, F, prim, dzeta, direct, item0, ni);
     MP3_HIP(timed(p, MP3_PASS_Z_ADJOINT, st, [&] { return mp3::launch_zpass_adjoint(p->n, p->prec, z, st); }), "z pass (adjoint)");
     MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, F, ni * p->batch * p->nbins, p->tw, p->tune[MP3_TUNE_FFT_X_PLAN], st); }), "adjoint x pass");
-    mp3::FilterArgs a = filter_args(p, ws, L, F, G, item0, ni);
+    mp3::FilterArgs a = filter_args(p, ws, L, F, G, item0, ni, true);
     MP3_HIP(timed(p, MP3_PASS_ADJOINT, st, [&] { return mp3::launch_adjoint_y(p->n, p->prec, a, st); }), "adjoint window pass");
   }
   return nodal_gradient_tail(p, delta, ddelta, pos, w, np_off, dw, ws, L, np_total, np_max, st);
@@ -1352,7 +1373,7 @@ int mp3_zeta_value_and_grad(mp3_plan_t p, const void* delta, const double* dzeta
   const int nb2 = p->nbins * p->nbins;
   if (int s = check_finite(p, ws, L.flag, st, delta, n3 * p->batch, p->prec)) return s;
   if (int s = forward_dft(p, delta, ws, L, st)) return s;
-  if (int s = lam_all(p, dzeta, ws, L, st)) return s;
+  if (int s = lam_eig_all(p, dzeta, ws, L, st)) return s;
   int ps = MP3_OK;
   const void* prim = primary_field(p, delta, ws, L, st, &ps);
   if (ps) return ps;
@@ -1366,7 +1387,7 @@ int mp3_zeta_value_and_grad(mp3_plan_t p, const void* delta, const double* dzeta
   const int nitems_all = (int)p->items.size();
   for (int item0 = 0; item0 < nitems_all; item0 += L.group) {
     const int ni = std::min(L.group, nitems_all - item0);
-    if (int s = fields_xy(p, ws, L, F, item0, ni, st)) return s;
+    if (int s = fields_xy(p, ws, L, F, item0, ni, st, true)) return s;
     mp3::ZpassArgs z = adjoint_zargs(p, ws, L, F, prim, dzeta, direct, item0, ni);
     z.partials = partials;
     z.waves = p->tune[MP3_TUNE_FUSED_WAVES];
@@ -1376,9 +1397,13 @@ int mp3_zeta_value_and_grad(mp3_plan_t p, const void* delta, const double* dzeta
                                      p->batch, st),
             "reduce");
     MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, F, ni * p->batch * p->nbins, p->tw, p->tune[MP3_TUNE_FFT_X_PLAN], st); }), "adjoint x pass");
-    mp3::FilterArgs a = filter_args(p, ws, L, F, G, item0, ni);
+    mp3::FilterArgs a = filter_args(p, ws, L, F, G, item0, ni, true);
     MP3_HIP(timed(p, MP3_PASS_ADJOINT, st, [&] { return mp3::launch_adjoint_y(p->n, p->prec, a, st); }), "adjoint window pass");
   }
+  // the value was summed over the rotated fields: back to the bins
+  MP3_HIP(mp3::launch_rotate_zeta(zeta, reinterpret_cast<const double*>(at(ws, L.evec)), p->nbins, p->lmax, p->batch,
+                                  st),
+          "zeta out of the eigenbasis");
   return nodal_gradient_tail(p, delta, ddelta, pos, w, np_off, dw, ws, L, np_total, np_max, st);
 }
 
