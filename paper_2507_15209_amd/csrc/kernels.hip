@@ -1117,26 +1117,21 @@ __device__ __forceinline__ c2<T> gather_record(const c2<T>* fm, int cell, const 
 // particles, one lane per (particle, bin), into LDS rows, then contract with
 // the weights w_i / W.  Particles are visited in tile order (perm).
 // SRC: the same gathered values also give the adjoint sources of
-// k_gather_source (value and gradient in one sweep): per particle
-// v_b = sum_b' lam_s[b][b'] conj(atilde_b'), src = N^3 (w_i / W) v, and
-// wm Re(sum_b atilde_b v_b) added to F_J(u_i); the contraction and the sources
-// only read the slice's rows, so they share one phase.
+// k_gather_source (value and gradient in one sweep, fields in the eigenbasis
+// of the cotangent, lam_d its eigenvalues): per lane v_b = d_b conj(atilde_b),
+// src = N^3 (w_i / W) v_b, and wm sum_b d_b |atilde_b|^2 added to F_J(u_i),
+// all at gather time.
 template <typename T, bool MF, bool SPLIT = false, bool QUAD = false, bool SRC = false>
 __global__ void __launch_bounds__(256) k_gather_contract(const c2<T>* fields, const int* tcell, const T* twt,
                                                           const float* w, const int* perm, const long long* off,
                                                           const double* W, int n, int nbins, double* partials,
-                                                          const T* lam_s, T wm, double* FJ, c2<T>* src) {
+                                                          const T* lam_d, T wm, double* FJ, c2<T>* src) {
   constexpr int K = 256;                                // particles per contraction slice
   constexpr int RS = K + K / 16 + 1;
   extern __shared__ __align__(16) char smem[];
   c2<T>* A = reinterpret_cast<c2<T>*>(smem);
   T* wk = reinterpret_cast<T*>(A + nbins * RS);
-  int* pk = reinterpret_cast<int*>(wk + K);             // SRC: particle index of slot k
-  T* lam = reinterpret_cast<T*>(pk + K);                // SRC: [nbins][nbins]
   const long long mock = blockIdx.y;
-  if constexpr (SRC) {
-    for (int t = threadIdx.x; t < nbins * nbins; t += blockDim.x) lam[t] = lam_s[mock * nbins * nbins + t];
-  }
   const long long n3 = (long long)n * n * n;
   const long long a0 = off[mock], a1 = off[mock + 1];
   const long long per = (a1 - a0 + gridDim.x - 1) / gridDim.x;
@@ -1147,6 +1142,7 @@ __global__ void __launch_bounds__(256) k_gather_contract(const c2<T>* fields, co
   const int b = threadIdx.x % lpp;
   const c2<T>* fm = fields + mock * n3 * nbins;
   const double fw = (double)n3 / W[mock];
+  const T dl = (SRC && b < nbins) ? lam_d[mock * nbins + b] : (T)0;
   Contractor<T, MF, SPLIT, QUAD> ctr;
   ctr.init(nbins);
   for (long long c0 = s0; c0 < s1; c0 += K) {
@@ -1154,46 +1150,32 @@ __global__ void __launch_bounds__(256) k_gather_contract(const c2<T>* fields, co
       const int k = k0 + threadIdx.x / lpp;
       const long long si = c0 + k;
       c2<T> acc = mk<T>(0, 0);
-      T wgt = 0;
+      T wgt = 0, fj = 0;
       int i = -1;
       if (si < s1) {
         i = perm[si];
         const int cell = tcell[si];
         if (cell >= 0 && b < nbins) acc = gather_record<T>(fm, cell, twt + si * 12, n, nbins, b);
-        wgt = (T)((w ? (double)w[i] : 1.0) * invW);
+        const double wi = w ? (double)w[i] : 1.0;
+        wgt = (T)(wi * invW);
+        if constexpr (SRC) {
+          if (b < nbins) {
+            const T e = dl * acc.x, f2 = dl * acc.y;
+            fj = e * acc.x + f2 * acc.y;
+            const T f = (T)(fw * wi);
+            src[si * nbins + b] = mk<T>(f * e, -(f * f2));
+          }
+        }
+      }
+      if constexpr (SRC) {
+        for (int o = lpp / 2; o > 0; o >>= 1) fj += __shfl_xor(fj, o, lpp);
+        if (si < s1 && b == 0) FJ[i] += (double)wm * (double)fj;
       }
       if (b < nbins) A[b * RS + lds_pos<true>(k)] = acc;
-      if (b == 0) {
-        wk[k] = wgt;
-        if constexpr (SRC) pk[k] = i;
-      }
+      if (b == 0) wk[k] = wgt;
     }
     __syncthreads();
     ctr.add(A, wk, nbins, RS, K);
-    if constexpr (SRC) {
-      for (int k0 = 0; k0 < K; k0 += ppp) {
-        const int k = k0 + threadIdx.x / lpp;
-        const long long si = c0 + k;
-        const bool has = si < s1;
-        T fj = 0;
-        if (has && b < nbins) {
-          const int kp = lds_pos<true>(k);
-          c2<T> v = mk<T>(0, 0);
-          for (int bp = 0; bp < nbins; ++bp) {
-            const c2<T> a = A[bp * RS + kp];
-            const T lv = lam[b * nbins + bp];
-            v.x += lv * a.x;
-            v.y -= lv * a.y;
-          }
-          const c2<T> a = A[b * RS + kp];
-          fj = a.x * v.x - a.y * v.y;
-          const T f = (T)(fw * (w ? (double)w[pk[k]] : 1.0));
-          src[si * nbins + b] = mk<T>(f * v.x, f * v.y);
-        }
-        for (int o = lpp / 2; o > 0; o >>= 1) fj += __shfl_xor(fj, o, lpp);
-        if (has && b == 0) FJ[pk[k]] += (double)wm * (double)fj;
-      }
-    }
     __syncthreads();
   }
   ctr.finish(reinterpret_cast<double*>(smem), partials + ((long long)mock * gridDim.x + blockIdx.x) * nbins * nbins,
@@ -1927,55 +1909,41 @@ __global__ void k_grad_combine(const T* direct, const c2<T>* ghat, T* ddelta, lo
 // ---------------------------------------------------------------------------
 // adjoint of the particle summation
 // ---------------------------------------------------------------------------
-// Per particle (tile order): gather atilde_b(u_i) for every bin, form
-//   v_b = sum_b' lam_s[b][b'] conj(atilde_b'),
-// add wm sum_b Re(atilde_b v_b) to F_J(u_i) (the primary vertex's share of J)
-// and store the adjoint source s_b(i) = N^3 (w_i / W) v_b at the particle's
-// sorted slot.  One lane per (particle, bin), 32 or 64 lanes per particle.
+// Per particle (tile order), in the eigenbasis of the cotangent (the fields
+// come from the rotated radial tables, lam_d holds the eigenvalues): gather
+// atilde_b(u_i), form v_b = d_b conj(atilde_b), add wm sum_b d_b |atilde_b|^2
+// to F_J(u_i) (the primary vertex's share of J) and store the adjoint source
+// s_b(i) = N^3 (w_i / W) v_b at the particle's sorted slot.  One lane per
+// (particle, bin), 32 or 64 lanes per particle.
 template <typename T>
 __global__ void __launch_bounds__(256) k_gather_source(const c2<T>* fields, const int* tcell, const T* twt,
                                                         const float* w, const int* perm, const long long* off,
-                                                        const double* W, const T* lam_s, int n, int nbins, T wm,
+                                                        const double* W, const T* lam_d, int n, int nbins, T wm,
                                                         double* FJ, c2<T>* src) {
-  extern __shared__ __align__(16) char smem[];
-  c2<T>* at = reinterpret_cast<c2<T>*>(smem);                     // [particles per pass][nbins]
   const int lpp = nbins <= 32 ? 32 : 64;
   const int ppp = blockDim.x / lpp;
-  T* lam = reinterpret_cast<T*>(at + ppp * nbins);               // [nbins][nbins]
   const long long mock = blockIdx.y;
-  const int nb2 = nbins * nbins;
-  for (int t = threadIdx.x; t < nb2; t += blockDim.x) lam[t] = lam_s[mock * nb2 + t];
   const long long n3 = (long long)n * n * n;
   const long long a0 = off[mock], a1 = off[mock + 1];
   const long long per = (a1 - a0 + gridDim.x - 1) / gridDim.x;
   const long long s0 = a0 + per * blockIdx.x, s1 = min(a1, s0 + per);
   const double fw = (double)n3 / W[mock];
   const int b = threadIdx.x % lpp, g = threadIdx.x / lpp;
+  const T d = b < nbins ? lam_d[mock * nbins + b] : (T)0;
   const c2<T>* fm = fields + mock * n3 * nbins;
   for (long long c0 = s0; c0 < s1; c0 += ppp) {
     const long long si = c0 + g;
     const bool has = si < s1;
     const int i = has ? perm[si] : 0;
-    c2<T> acc = mk<T>(0, 0);
-    if (has && b < nbins) {
-      const int cell = tcell[si];
-      if (cell >= 0) acc = gather_record<T>(fm, cell, twt + si * 12, n, nbins, b);
-    }
-    __syncthreads();                                   // the previous pass's reads of at[] are done
-    if (b < nbins) at[g * nbins + b] = acc;
-    __syncthreads();
     T fj = 0;
     if (has && b < nbins) {
-      c2<T> v = mk<T>(0, 0);
-      for (int bp = 0; bp < nbins; ++bp) {
-        const c2<T> a = at[g * nbins + bp];
-        const T lv = lam[b * nbins + bp];
-        v.x += lv * a.x;
-        v.y -= lv * a.y;
-      }
-      fj = acc.x * v.x - acc.y * v.y;
+      c2<T> acc = mk<T>(0, 0);
+      const int cell = tcell[si];
+      if (cell >= 0) acc = gather_record<T>(fm, cell, twt + si * 12, n, nbins, b);
+      const T e = d * acc.x, f2 = d * acc.y;
+      fj = e * acc.x + f2 * acc.y;
       const T f = (T)(fw * (w ? (double)w[i] : 1.0));
-      src[si * nbins + b] = mk<T>(f * v.x, f * v.y);
+      src[si * nbins + b] = mk<T>(f * e, -(f * f2));
     }
     for (int o = lpp / 2; o > 0; o >>= 1) fj += __shfl_xor(fj, o, lpp);
     if (has && b == 0) FJ[i] += (double)wm * (double)fj;
@@ -3536,7 +3504,6 @@ hipError_t gather_contract_v(const GatherArgs& a, hipStream_t st) {
   constexpr int K = 256;
   const size_t rs = K + K / 16 + 1;
   size_t lds = (size_t)a.nbins * rs * sizeof(CT<T>) + K * sizeof(T);
-  if (SRC) lds += K * sizeof(int) + (size_t)a.nbins * a.nbins * sizeof(T);
   const size_t red = Contractor<T, MF, SPLIT, QUAD>::scratch_bytes(256);
   if (lds < red) lds = red;
   hipError_t e = allow_lds(k_gather_contract<T, MF, SPLIT, QUAD, SRC>, lds);
@@ -3550,11 +3517,7 @@ hipError_t gather_contract_v(const GatherArgs& a, hipStream_t st) {
 
 template <typename T, bool MF, bool SPLIT = false, bool QUAD = false>
 hipError_t gather_contract_t(const GatherArgs& a, hipStream_t st) {
-  if constexpr (std::is_same<T, double>::value) {
-    if (a.src) return gather_contract_v<T, MF, SPLIT, QUAD, true>(a, st);
-  } else {
-    if (a.src) return hipErrorInvalidValue;      // float32 runs the source gather separately
-  }
+  if (a.src) return gather_contract_v<T, MF, SPLIT, QUAD, true>(a, st);
   return gather_contract_v<T, MF, SPLIT, QUAD, false>(a, st);
 }
 
@@ -3693,28 +3656,19 @@ size_t gamma_adjoint_bins_lds_need(int prec, int nbc) {
 }
 
 hipError_t launch_gather_source(int prec, const void* fields, const int* tcell, const void* twt, const float* w,
-                                const int* perm, const long long* off, const double* W, const void* lam_s, int n,
+                                const int* perm, const long long* off, const double* W, const void* lam_d, int n,
                                 int nbins, double wm, int nwg, int batch, double* FJ, void* src, hipStream_t st) {
-  const int lpp = nbins <= 32 ? 32 : 64;
-  const int ppp = 256 / lpp;
-  const size_t elt = prec ? sizeof(double) : sizeof(float);
-  const size_t lds = (size_t)ppp * nbins * 2 * elt + (size_t)nbins * nbins * elt;
   const dim3 gs(nwg, batch);
-  if (prec) {
-    hipError_t e = allow_lds(k_gather_source<double>, lds);
-    if (e != hipSuccess) return e;
-    k_gather_source<double><<<gs, 256, lds, st>>>(static_cast<const double2*>(fields), tcell,
-                                                  static_cast<const double*>(twt), w, perm, off, W,
-                                                  static_cast<const double*>(lam_s), n, nbins, wm, FJ,
-                                                  static_cast<double2*>(src));
-  } else {
-    hipError_t e = allow_lds(k_gather_source<float>, lds);
-    if (e != hipSuccess) return e;
-    k_gather_source<float><<<gs, 256, lds, st>>>(static_cast<const float2*>(fields), tcell,
-                                                 static_cast<const float*>(twt), w, perm, off, W,
-                                                 static_cast<const float*>(lam_s), n, nbins, (float)wm, FJ,
-                                                 static_cast<float2*>(src));
-  }
+  if (prec)
+    k_gather_source<double><<<gs, 256, 0, st>>>(static_cast<const double2*>(fields), tcell,
+                                                static_cast<const double*>(twt), w, perm, off, W,
+                                                static_cast<const double*>(lam_d), n, nbins, wm, FJ,
+                                                static_cast<double2*>(src));
+  else
+    k_gather_source<float><<<gs, 256, 0, st>>>(static_cast<const float2*>(fields), tcell,
+                                               static_cast<const float*>(twt), w, perm, off, W,
+                                               static_cast<const float*>(lam_d), n, nbins, (float)wm, FJ,
+                                               static_cast<float2*>(src));
   return hipGetLastError();
 }
 

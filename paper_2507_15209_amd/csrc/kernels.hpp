@@ -79,9 +79,9 @@ struct GatherArgs {
   int n, nbins, nwg, batch;
   double sc;              // N / box
   bool split;             // float32 contraction with BF16-split inputs on the matrix cores
-  // adjoint sources from the same gather (value and gradient in one sweep) when src != NULL;
-  // float64 plans only (float32 returns hipErrorInvalidValue and runs launch_gather_source)
-  const void* lam;        // lam_s [batch][nbins][nbins]
+  // adjoint sources from the same gather (value and gradient in one sweep) when src != NULL:
+  // the fields are those of the rotated radial tables, lam the cotangent's eigenvalues
+  const void* lam;        // [batch][nbins] eigenvalues of the symmetrised cotangent
   double wm;              // m weight
   double* FJ;             // [np_total] F_J accumulator
   void* src;              // [np_total][nbins] sources in sorted order
@@ -192,7 +192,7 @@ hipError_t launch_weighted_sum(const float* w, const double* f, const long long*
 // grid ([batch][nbins][N^3], every node written), the volume-mean term into G
 // and the primary vertex's share of dJ/dw
 hipError_t launch_gather_source(int prec, const void* fields, const int* tcell, const void* twt, const float* w,
-                                const int* perm, const long long* off, const double* W, const void* lam_s, int n,
+                                const int* perm, const long long* off, const double* W, const void* lam_d, int n,
                                 int nbins, double wm, int nwg, int batch, double* FJ, void* src, hipStream_t st);
 hipError_t launch_scatter_source(int prec, const int* tcell, const void* twt, const int* toff, const void* src, int n,
                                  int nbins, int batch, void* out, hipStream_t st);

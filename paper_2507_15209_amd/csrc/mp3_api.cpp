@@ -159,7 +159,7 @@ Layout layout(const mp3_plan_s* p, long long np_total = 0) {
   L.direct = take(B * n3 * p->elt);
   L.lam = take((size_t)(p->lmax + 1) * B * nb2 * p->elt);
   L.counter = take(sizeof(int));
-  if (p->summation == MP3_SUM_NODAL) {
+  if (p->summation == MP3_SUM_NODAL || p->summation == MP3_SUM_PARTICLE) {
     L.evec = take((size_t)(p->lmax + 1) * B * nb2 * sizeof(double));
     L.jrot = take((size_t)(p->lmax + 1) * B * (size_t)p->nq2 * p->nbp * p->elt);
   }
@@ -337,6 +337,11 @@ int item_index(int l, int m) { return l * (l + 1) / 2 + m; }
 // the symmetrised cotangent of multipole l: [batch][nbins^2] real
 void* lam_at(const mp3_plan_s* p, void* ws, const Layout& L, int l) {
   return at(ws, L.lam + (size_t)l * p->batch * p->nbins * p->nbins * p->elt);
+}
+
+// the cotangent's eigenvalues of multipole l after lam_eig_all: [batch][nbins] real
+void* lam_d_at(const mp3_plan_s* p, void* ws, const Layout& L, int l) {
+  return at(ws, L.lam + (size_t)l * p->batch * p->nbins * p->elt);
 }
 
 // symmetrised cotangents of every l into the workspace (one launch)
@@ -996,7 +1001,7 @@ int backward_particle(mp3_plan_t p, const void* delta, const double* dzeta, void
   const double sc = (double)p->n / p->box;
   if (int s = check_finite(p, ws, L.flag, st, delta, n3 * p->batch, p->prec)) return s;
   if (int s = forward_dft(p, delta, ws, L, st)) return s;
-  if (int s = lam_all(p, dzeta, ws, L, st)) return s;
+  if (int s = lam_eig_all(p, dzeta, ws, L, st)) return s;
   if (int s = upload_offsets(p, np_off, ws, L, st)) return s;
   const long long* off = reinterpret_cast<const long long*>(at(ws, L.off));
   double* W = reinterpret_cast<double*>(at(ws, L.W));
@@ -1023,7 +1028,7 @@ int backward_particle(mp3_plan_t p, const void* delta, const double* dzeta, void
   for (int l = 0; l <= p->lmax; ++l) {
     for (int m = 0; m <= l; ++m) {
       const double wm = m == 0 ? 1.0 : 2.0;
-      if (int s = fields_xy(p, ws, L, F, item_index(l, m), 1, st)) return s;
+      if (int s = fields_xy(p, ws, L, F, item_index(l, m), 1, st, true)) return s;
       mp3::ZpassArgs z{};
       z.fields = F;
       z.tw = p->tw;
@@ -1033,7 +1038,7 @@ int backward_particle(mp3_plan_t p, const void* delta, const double* dzeta, void
       z.batch = p->batch;
       MP3_HIP(timed(p, MP3_PASS_Z_STORE, st, [&] { return mp3::launch_zpass_store(p->n, p->prec, z, Fi, st); }), "z pass (store)");
       MP3_HIP(timed(p, MP3_PASS_GATHER, st, [&] {
-                return mp3::launch_gather_source(p->prec, Fi, tcell, twt, w, perm, off, W, lam_at(p, ws, L, l), p->n, p->nbins,
+                return mp3::launch_gather_source(p->prec, Fi, tcell, twt, w, perm, off, W, lam_d_at(p, ws, L, l), p->n, p->nbins,
                                                  wm, gwg, p->batch, FJ, src, st);
               }),
               "gather (adjoint sources)");
@@ -1045,7 +1050,7 @@ int backward_particle(mp3_plan_t p, const void* delta, const double* dzeta, void
               "adjoint z pass");
       MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, F, p->batch * p->nbins, p->tw, p->tune[MP3_TUNE_FFT_X_PLAN], st); }),
               "adjoint x pass");
-      mp3::FilterArgs a = filter_args(p, ws, L, F, G, item_index(l, m), 1);
+      mp3::FilterArgs a = filter_args(p, ws, L, F, G, item_index(l, m), 1, true);
       MP3_HIP(timed(p, MP3_PASS_ADJOINT, st, [&] { return mp3::launch_adjoint_y(p->n, p->prec, a, st); }), "adjoint window pass");
     }
   }
@@ -1091,7 +1096,7 @@ int value_and_grad_particle(mp3_plan_t p, const void* delta, const double* dzeta
   const double sc = (double)p->n / p->box;
   if (int s = check_finite(p, ws, L.flag, st, delta, n3 * p->batch, p->prec)) return s;
   if (int s = forward_dft(p, delta, ws, L, st)) return s;
-  if (int s = lam_all(p, dzeta, ws, L, st)) return s;
+  if (int s = lam_eig_all(p, dzeta, ws, L, st)) return s;
   MP3_HIP(mp3::launch_fill_f64(zeta, (long long)p->batch * (p->lmax + 1) * nb2, 0.0, st), "zero zeta");
   if (int s = upload_offsets(p, np_off, ws, L, st)) return s;
   const long long* off = reinterpret_cast<const long long*>(at(ws, L.off));
@@ -1124,7 +1129,7 @@ int value_and_grad_particle(mp3_plan_t p, const void* delta, const double* dzeta
   for (int l = 0; l <= p->lmax; ++l) {
     for (int m = 0; m <= l; ++m) {
       const double wm = m == 0 ? 1.0 : 2.0;
-      if (int s = fields_xy(p, ws, L, F, item_index(l, m), 1, st)) return s;
+      if (int s = fields_xy(p, ws, L, F, item_index(l, m), 1, st, true)) return s;
       mp3::ZpassArgs z{};
       z.fields = F;
       z.tw = p->tw;
@@ -1149,23 +1154,13 @@ int value_and_grad_particle(mp3_plan_t p, const void* delta, const double* dzeta
       g.batch = p->batch;
       g.sc = sc;
       g.split = p->split;
-      // float64: one gather gives the contraction and the adjoint sources;
-      // float32: two gathers (measured faster: the separate source kernel
-      // overlaps its loads and arithmetic across waves)
-      if (p->prec) {
-        g.lam = lam_at(p, ws, L, l);
-        g.wm = wm;
-        g.FJ = FJ;
-        g.src = src;
-      }
+      // one gather gives the contraction and the (diagonal) adjoint sources
+      g.lam = lam_d_at(p, ws, L, l);
+      g.wm = wm;
+      g.FJ = FJ;
+      g.src = src;
       MP3_HIP(timed(p, MP3_PASS_GATHER, st, [&] { return mp3::launch_gather_contract(p->prec, g, st); }), "gather");
       MP3_HIP(mp3::launch_reduce_partials(partials, gwg, nb2, zeta, l, p->lmax, wm * kFourPi, p->batch, st), "reduce");
-      if (!p->prec)
-        MP3_HIP(timed(p, MP3_PASS_GATHER, st, [&] {
-                  return mp3::launch_gather_source(p->prec, Fi, tcell, twt, w, perm, off, W, lam_at(p, ws, L, l), p->n,
-                                                   p->nbins, wm, gwg, p->batch, FJ, src, st);
-                }),
-                "gather (adjoint sources)");
       MP3_HIP(timed(p, MP3_PASS_SCATTER, st, [&] {
                 return mp3::launch_scatter_source(p->prec, tcell, twt, toff, src, p->n, p->nbins, p->batch, F, st);
               }),
@@ -1174,12 +1169,17 @@ int value_and_grad_particle(mp3_plan_t p, const void* delta, const double* dzeta
               "adjoint z pass");
       MP3_HIP(timed(p, MP3_PASS_X, st, [&] { return mp3::launch_fft_x(p->n, p->prec, +1, F, p->batch * p->nbins, p->tw, p->tune[MP3_TUNE_FFT_X_PLAN], st); }),
               "adjoint x pass");
-      mp3::FilterArgs a = filter_args(p, ws, L, F, G, item_index(l, m), 1);
+      mp3::FilterArgs a = filter_args(p, ws, L, F, G, item_index(l, m), 1, true);
       MP3_HIP(timed(p, MP3_PASS_ADJOINT, st, [&] { return mp3::launch_adjoint_y(p->n, p->prec, a, st); }), "adjoint window pass");
     }
+  }
+  // the value was summed over the rotated fields: back to the bins, then the volume means
+  MP3_HIP(mp3::launch_rotate_zeta(zeta, reinterpret_cast<const double*>(at(ws, L.evec)), p->nbins, p->lmax, p->batch,
+                                  st),
+          "zeta out of the eigenbasis");
+  for (int l = 0; l <= p->lmax; ++l)
     MP3_HIP(mp3::launch_fbar_subtract(p->prec, P, p->jtab, nq2, p->nbp, p->nbins, l, p->lmax, n3d * n3d, zeta, p->batch, st),
             "volume mean");
-  }
   MP3_HIP(mp3::launch_fbar_adjoint(p->prec, dzeta, p->jtab, p->nq2, p->nbp, p->nbins, p->lmax, at(ws, L.dhat), p->n,
                                    -1.0 / (kFourPi * n3d), reinterpret_cast<double*>(at(ws, L.hq)), G, p->batch,
                                    p->phi, p->acf, st),
