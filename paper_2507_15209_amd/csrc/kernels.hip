@@ -588,16 +588,18 @@ __device__ __forceinline__ void mfma_contract_pencil(const float2* A, const floa
   const int zz = kq >> 1, comp = kq & 1;
   const bool two = nbins > 16;
   const bool ok0 = col < nbins, ok1 = 16 + col < nbins;
-  const float* r0 = reinterpret_cast<const float*>(A + col * RS) + comp;
-  const float* r1 = reinterpret_cast<const float*>(A + (16 + col) * RS) + comp;
+  // lanes of bins beyond nbins read row 0 (finite values): they only feed
+  // entries of P that the reduction drops, and the loads need no mask
+  const float* r0 = reinterpret_cast<const float*>(A + (ok0 ? col : 0) * RS) + comp;
+  const float* r1 = reinterpret_cast<const float*>(A + (ok1 ? 16 + col : 0) * RS) + comp;
   for (int zp = w; zp < N / 2; zp += nw) {
     const int z = 2 * zp + zz;
     const int off = 2 * lds_pos<true>(z);
     const float d = dl[z];
-    const float v0 = ok0 ? r0[off] : 0.f;
+    const float v0 = r0[off];
     acc.c00 = __builtin_amdgcn_mfma_f32_16x16x4f32(d * v0, v0, acc.c00, 0, 0, 0);
     if (two) {
-      const float v1 = ok1 ? r1[off] : 0.f;
+      const float v1 = r1[off];
       acc.c01 = __builtin_amdgcn_mfma_f32_16x16x4f32(d * v0, v1, acc.c01, 0, 0, 0);
       acc.c11 = __builtin_amdgcn_mfma_f32_16x16x4f32(d * v1, v1, acc.c11, 0, 0, 0);
     }
@@ -612,17 +614,19 @@ __device__ __forceinline__ void mfma_contract_pencil_range(const float2* A, cons
   const int zz = kq >> 1, comp = kq & 1;
   const bool two = nbins > 16;
   const bool ok0 = col < nbins, ok1 = 16 + col < nbins;
-  const float* r0 = reinterpret_cast<const float*>(A + col * RS) + comp;
-  const float* r1 = reinterpret_cast<const float*>(A + (16 + col) * RS) + comp;
+  // lanes of bins beyond nbins read row 0 (finite values): they only feed
+  // entries of P that the reduction drops, and the loads need no mask
+  const float* r0 = reinterpret_cast<const float*>(A + (ok0 ? col : 0) * RS) + comp;
+  const float* r1 = reinterpret_cast<const float*>(A + (ok1 ? 16 + col : 0) * RS) + comp;
 #pragma unroll 8
   for (int zp = z0 / 2; zp < z1 / 2; ++zp) {
     const int z = 2 * zp + zz;
     const int off = 2 * lds_pos<true>(z);
     const float d = dl[z];
-    const float v0 = ok0 ? r0[off] : 0.f;
+    const float v0 = r0[off];
     acc.c00 = __builtin_amdgcn_mfma_f32_16x16x4f32(d * v0, v0, acc.c00, 0, 0, 0);
     if (two) {
-      const float v1 = ok1 ? r1[off] : 0.f;
+      const float v1 = r1[off];
       acc.c01 = __builtin_amdgcn_mfma_f32_16x16x4f32(d * v0, v1, acc.c01, 0, 0, 0);
       acc.c11 = __builtin_amdgcn_mfma_f32_16x16x4f32(d * v1, v1, acc.c11, 0, 0, 0);
     }
@@ -653,16 +657,15 @@ __device__ __forceinline__ void mfma_contract_4x4(const float2* A, const float* 
   if (beta < 15) pair_group(beta, g1, g2);
   const int ba = 4 * g1 + i, bb = 4 * g2 + i;
   const bool oka = beta < 15 && ba < nbins, okb = beta < 15 && bb < nbins;
+  // lanes of block 15 and of bins beyond nbins read row 0 (finite values):
+  // they only feed entries of P that the reduction drops, so no load is masked
   const float2* ra = A + (oka ? ba : 0) * RS;
   const float2* rb = A + (okb ? bb : 0) * RS;
   // three accumulators in rotation keep dependent matrix-core issues apart
   for (int z = 2 * w; z < K; z += 2 * nw) {
     const int zp0 = lds_pos<true>(z), zp1 = lds_pos<true>(z + 1);
     const float d0 = dl[z], d1 = dl[z + 1];
-    const float2 u0 = oka ? ra[zp0] : make_float2(0.f, 0.f);
-    const float2 v0 = okb ? rb[zp0] : make_float2(0.f, 0.f);
-    const float2 u1 = oka ? ra[zp1] : make_float2(0.f, 0.f);
-    const float2 v1 = okb ? rb[zp1] : make_float2(0.f, 0.f);
+    const float2 u0 = ra[zp0], v0 = rb[zp0], u1 = ra[zp1], v1 = rb[zp1];
     acc.c00 = __builtin_amdgcn_mfma_f32_4x4x1f32(d0 * u0.x, v0.x, acc.c00, 0, 0, 0);
     acc.c01 = __builtin_amdgcn_mfma_f32_4x4x1f32(d0 * u0.y, v0.y, acc.c01, 0, 0, 0);
     acc.c11 = __builtin_amdgcn_mfma_f32_4x4x1f32(d1 * u1.x, v1.x, acc.c11, 0, 0, 0);
@@ -679,16 +682,15 @@ __device__ __forceinline__ void mfma_contract_4x4_range(const float2* A, const f
   if (beta < 15) pair_group(beta, g1, g2);
   const int ba = 4 * g1 + i, bb = 4 * g2 + i;
   const bool oka = beta < 15 && ba < nbins, okb = beta < 15 && bb < nbins;
+  // lanes of block 15 and of bins beyond nbins read row 0 (finite values):
+  // they only feed entries of P that the reduction drops, so no load is masked
   const float2* ra = A + (oka ? ba : 0) * RS;
   const float2* rb = A + (okb ? bb : 0) * RS;
 #pragma unroll 8
   for (int z = z0; z < z1; z += 2) {
     const int zp0 = lds_pos<true>(z), zp1 = lds_pos<true>(z + 1);
     const float d0 = dl[z], d1 = dl[z + 1];
-    const float2 u0 = oka ? ra[zp0] : make_float2(0.f, 0.f);
-    const float2 v0 = okb ? rb[zp0] : make_float2(0.f, 0.f);
-    const float2 u1 = oka ? ra[zp1] : make_float2(0.f, 0.f);
-    const float2 v1 = okb ? rb[zp1] : make_float2(0.f, 0.f);
+    const float2 u0 = ra[zp0], v0 = rb[zp0], u1 = ra[zp1], v1 = rb[zp1];
     acc.c00 = __builtin_amdgcn_mfma_f32_4x4x1f32(d0 * u0.x, v0.x, acc.c00, 0, 0, 0);
     acc.c01 = __builtin_amdgcn_mfma_f32_4x4x1f32(d0 * u0.y, v0.y, acc.c01, 0, 0, 0);
     acc.c11 = __builtin_amdgcn_mfma_f32_4x4x1f32(d1 * u1.x, v1.x, acc.c11, 0, 0, 0);
