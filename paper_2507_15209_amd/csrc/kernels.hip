@@ -1087,30 +1087,53 @@ __global__ void k_tap_records(const float* pos, const int* perm, long long np_to
 }
 
 // sum over the 64 taps of record k of w_tap * f[node][b] (bin-interleaved
-// fields of one mock, nbins per node)
+// fields of one mock, nbins per node), separably: the four z taps of each
+// (x, y) row with the z weights, the rows with the y weights, then x.  A row
+// whose z taps do not wrap is read at one base address plus multiples of the
+// node stride.
 template <typename T>
 __device__ __forceinline__ c2<T> gather_record(const c2<T>* fm, int cell, const T* wt, int n, int nbins, int b) {
-  c2<T> acc = mk<T>(0, 0);
   const int cx = cell & 1023, cy = (cell >> 10) & 1023, cz = cell >> 20;
-  int iz[4];
+  T w[8];                                               // y and z weights (x weights read per row)
 #pragma unroll
-  for (int az = 0; az < 4; ++az) iz[az] = wrapi(cz - 1 + az, n);
+  for (int e = 0; e < 8; ++e) w[e] = wt[4 + e];
+  const long long rowy = (long long)n * nbins;          // elements per y step
+  const long long rowx = (long long)n * rowy;           // elements per x step
+  const bool zin = cz >= 1 && cz + 2 < n;
+  long long oz[4];
 #pragma unroll
+  for (int az = 0; az < 4; ++az) oz[az] = (long long)(zin ? cz - 1 + az : wrapi(cz - 1 + az, n)) * nbins + b;
+  c2<T> acc = mk<T>(0, 0);
+  // one x row of 16 taps per iteration keeps 16 loads in flight without
+  // holding all 64 in registers
+#pragma unroll 1
   for (int ax = 0; ax < 4; ++ax) {
-    const int ix = wrapi(cx - 1 + ax, n);
+    const c2<T>* px = fm + wrapi(cx - 1 + ax, n) * rowx;
+    c2<T> sy = mk<T>(0, 0);
 #pragma unroll
     for (int ay = 0; ay < 4; ++ay) {
-      const int iy = wrapi(cy - 1 + ay, n);
-      const T wxy = wt[ax] * wt[4 + ay];
-      const int row = (ix * n + iy) * n;
+      const c2<T>* py = px + wrapi(cy - 1 + ay, n) * rowy;
+      c2<T> v[4];
+      if (zin) {
+        const c2<T>* q = py + oz[0];
+#pragma unroll
+        for (int az = 0; az < 4; ++az) v[az] = q[az * nbins];
+      } else {
+#pragma unroll
+        for (int az = 0; az < 4; ++az) v[az] = py[oz[az]];
+      }
+      c2<T> sz = mk<T>(0, 0);
 #pragma unroll
       for (int az = 0; az < 4; ++az) {
-        const c2<T> v = fm[(long long)(row + iz[az]) * nbins + b];
-        const T w = wxy * wt[8 + az];
-        acc.x += w * v.x;
-        acc.y += w * v.y;
+        sz.x += w[4 + az] * v[az].x;
+        sz.y += w[4 + az] * v[az].y;
       }
+      sy.x += w[ay] * sz.x;
+      sy.y += w[ay] * sz.y;
     }
+    const T wx = wt[ax];
+    acc.x += wx * sy.x;
+    acc.y += wx * sy.y;
   }
   return acc;
 }
@@ -1128,56 +1151,79 @@ __global__ void __launch_bounds__(256) k_gather_contract(const c2<T>* fields, co
                                                           const float* w, const int* perm, const long long* off,
                                                           const double* W, int n, int nbins, double* partials,
                                                           const T* lam_d, T wm, double* FJ, c2<T>* src) {
-  constexpr int K = 256;                                // particles per contraction slice
+  constexpr int K = 256;                                // particle slots per contraction slice
   constexpr int RS = K + K / 16 + 1;
   extern __shared__ __align__(16) char smem[];
   c2<T>* A = reinterpret_cast<c2<T>*>(smem);
   T* wk = reinterpret_cast<T*>(A + nbins * RS);
+  int* pk = reinterpret_cast<int*>(wk + K);             // SRC: particle of slot k (-1: none)
+  T* lam = reinterpret_cast<T*>(pk + K);                // SRC: the eigenvalues d_b
   const long long mock = blockIdx.y;
   const long long n3 = (long long)n * n * n;
   const long long a0 = off[mock], a1 = off[mock + 1];
   const long long per = (a1 - a0 + gridDim.x - 1) / gridDim.x;
   const long long s0 = a0 + per * blockIdx.x, s1 = min(a1, s0 + per);
   const double invW = 1.0 / W[mock];
-  const int lpp = nbins <= 32 ? 32 : 64;                // lanes per particle
-  const int ppp = blockDim.x / lpp;                     // particles per pass
-  const int b = threadIdx.x % lpp;
+  // nbins lanes per particle, 64 / nbins particles per wave (the rest idle)
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int ppw = 64 / nbins;
+  const int pw = lane / nbins, b = lane - pw * nbins;
+  const bool lane_ok = pw < ppw;
+  const int ppp = nw * ppw;                             // particles per pass
+  int kcount = ppp * (K / ppp);                         // slots per slice: even, and a multiple of 8
+  while (kcount % 8) kcount -= ppp;
   const c2<T>* fm = fields + mock * n3 * nbins;
   const double fw = (double)n3 / W[mock];
-  const T dl = (SRC && b < nbins) ? lam_d[mock * nbins + b] : (T)0;
+  const T dl = (SRC && lane_ok) ? lam_d[mock * nbins + b] : (T)0;
+  if constexpr (SRC) {
+    for (int t = threadIdx.x; t < nbins; t += blockDim.x) lam[t] = lam_d[mock * nbins + t];
+  }
   Contractor<T, MF, SPLIT, QUAD> ctr;
   ctr.init(nbins);
-  for (long long c0 = s0; c0 < s1; c0 += K) {
-    for (int k0 = 0; k0 < K; k0 += ppp) {
-      const int k = k0 + threadIdx.x / lpp;
+  for (long long c0 = s0; c0 < s1; c0 += kcount) {
+    for (int k0 = 0; k0 < kcount; k0 += ppp) {
+      const int k = k0 + wv * ppw + pw;
       const long long si = c0 + k;
       c2<T> acc = mk<T>(0, 0);
-      T wgt = 0, fj = 0;
+      T wgt = 0;
       int i = -1;
-      if (si < s1) {
+      if (lane_ok && si < s1) {
         i = perm[si];
         const int cell = tcell[si];
-        if (cell >= 0 && b < nbins) acc = gather_record<T>(fm, cell, twt + si * 12, n, nbins, b);
+        if (cell >= 0) acc = gather_record<T>(fm, cell, twt + si * 12, n, nbins, b);
         const double wi = w ? (double)w[i] : 1.0;
         wgt = (T)(wi * invW);
         if constexpr (SRC) {
-          if (b < nbins) {
-            const T e = dl * acc.x, f2 = dl * acc.y;
-            fj = e * acc.x + f2 * acc.y;
-            const T f = (T)(fw * wi);
-            src[si * nbins + b] = mk<T>(f * e, -(f * f2));
-          }
+          const T e = dl * acc.x, f2 = dl * acc.y;
+          const T f = (T)(fw * wi);
+          src[si * nbins + b] = mk<T>(f * e, -(f * f2));
         }
       }
-      if constexpr (SRC) {
-        for (int o = lpp / 2; o > 0; o >>= 1) fj += __shfl_xor(fj, o, lpp);
-        if (si < s1 && b == 0) FJ[i] += (double)wm * (double)fj;
+      if (lane_ok) {
+        A[b * RS + lds_pos<true>(k)] = acc;
+        if (b == 0) {
+          wk[k] = wgt;
+          if constexpr (SRC) pk[k] = i;
+        }
       }
-      if (b < nbins) A[b * RS + lds_pos<true>(k)] = acc;
-      if (b == 0) wk[k] = wgt;
     }
     __syncthreads();
-    ctr.add(A, wk, nbins, RS, K);
+    ctr.add(A, wk, nbins, RS, kcount);
+    if constexpr (SRC) {
+      // the primary vertex's share: F_J(u_i) += wm sum_b d_b |atilde_b|^2, one thread per slot
+      for (int k = threadIdx.x; k < kcount; k += blockDim.x) {
+        const int ip = pk[k];
+        if (ip >= 0) {
+          const int kp = lds_pos<true>(k);
+          T fj = 0;
+          for (int bb = 0; bb < nbins; ++bb) {
+            const c2<T> a = A[bb * RS + kp];
+            fj += lam[bb] * (a.x * a.x + a.y * a.y);
+          }
+          FJ[ip] += (double)wm * (double)fj;
+        }
+      }
+    }
     __syncthreads();
   }
   ctr.finish(reinterpret_cast<double*>(smem), partials + ((long long)mock * gridDim.x + blockIdx.x) * nbins * nbins,
@@ -3506,6 +3552,7 @@ hipError_t gather_contract_v(const GatherArgs& a, hipStream_t st) {
   constexpr int K = 256;
   const size_t rs = K + K / 16 + 1;
   size_t lds = (size_t)a.nbins * rs * sizeof(CT<T>) + K * sizeof(T);
+  if (SRC) lds += K * sizeof(int) + (size_t)a.nbins * sizeof(T);
   const size_t red = Contractor<T, MF, SPLIT, QUAD>::scratch_bytes(256);
   if (lds < red) lds = red;
   hipError_t e = allow_lds(k_gather_contract<T, MF, SPLIT, QUAD, SRC>, lds);
