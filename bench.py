@@ -73,11 +73,13 @@ def read_pmc(kernel_tag):
 COPY_BYTES = 1 << 30
 
 
-def pmc_probe(wl, precision):
+def pmc_probe(wl, precision, lmax=None):
     """One step of the path and a plain 1 GiB device copy, for hardware-counter runs.
 
     The copy reads and writes COPY_BYTES each; what FETCH_SIZE / WRITE_SIZE
-    report for it calibrates the counters against known traffic."""
+    report for it calibrates the counters against known traffic.  The plan
+    takes the workload's summation form; lmax (default the workload's) can be
+    lowered to keep a counter run of a large workload short."""
     import torch
     import paper_2507_15209_amd as mp3
     from mockgen import workload_catalogue
@@ -91,15 +93,16 @@ def pmc_probe(wl, precision):
     log("copy done")
     pos, w = workload_catalogue(wl)
     pt, wt = torch.as_tensor(pos, device=dev), torch.as_tensor(w, device=dev)
-    lam = torch.as_tensor(np.random.default_rng(11).standard_normal((1, wl.lmax + 1, wl.nbins, wl.nbins)), device=dev)
-    plan = mp3.Plan(wl.n, wl.box, wl.lmax, wl.edges, precision=precision, device=dev)
+    lmax = wl.lmax if lmax is None else lmax
+    lam = torch.as_tensor(np.random.default_rng(11).standard_normal((1, lmax + 1, wl.nbins, wl.nbins)), device=dev)
+    plan = mp3.Plan(wl.n, wl.box, lmax, wl.edges, precision=precision, summation=wl.form, device=dev)
     from paper_2507_15209_amd import autotune as at
     at.load_tuning(plan)                           # the knobs the bench runs with, when cached
     delta = plan.deposit(pt, wt)
     plan.zeta_value_and_grad(delta, lam, pt, wt)
     torch.cuda.synchronize()
     log("one-sweep value and gradient done")
-    plan.zeta(delta)
+    plan.zeta(delta, pt, wt)
     torch.cuda.synchronize()
     log("forward done")
     plan.zeta_backward(delta, lam, pt, wt)
@@ -382,6 +385,7 @@ def main():
     ap.add_argument("--forms", default=",".join(DEFAULT_FORMS),
                     help="secondary measurements after the headline (comma list of %s, all, or none)" % ", ".join(FORMS))
     ap.add_argument("--pmc-probe", action="store_true", help="one step plus a 1 GiB copy, for counter runs")
+    ap.add_argument("--probe-lmax", type=int, default=None, help="multipole order of the --pmc-probe plan")
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print the per-launch traffic summary of two rocprofv3 --pmc runs of --pmc-probe")
     ap.add_argument("--stats-summarize", metavar="DIR", help="print a table of a rocprofv3 --stats run")
@@ -405,7 +409,7 @@ def main():
     from mockgen import WORKLOADS, workload_catalogue
     wl = WORKLOADS[args.workload]
     if args.pmc_probe:
-        pmc_probe(wl, args.precision)
+        pmc_probe(wl, args.precision, args.probe_lmax)
         return
 
     log("workload", wl.name, "n", wl.n, "L", wl.lmax, "bins", wl.nbins, "particles", wl.n_particles)
