@@ -1138,6 +1138,9 @@ __device__ __forceinline__ c2<T> gather_record(const c2<T>* fm, int cell, const 
   return acc;
 }
 
+// particle slots of one contraction slice of the gather (LDS rows of nbins x slots)
+constexpr int kGatherSlots = 256;
+
 // Gather the B-spline interpolants of the (bin-interleaved) fields at the
 // particles, one lane per (particle, bin), into LDS rows, then contract with
 // the weights w_i / W.  Particles are visited in tile order (perm).
@@ -1151,7 +1154,7 @@ __global__ void __launch_bounds__(256) k_gather_contract(const c2<T>* fields, co
                                                           const float* w, const int* perm, const long long* off,
                                                           const double* W, int n, int nbins, double* partials,
                                                           const T* lam_d, T wm, double* FJ, c2<T>* src) {
-  constexpr int K = 256;                                // particle slots per contraction slice
+  constexpr int K = kGatherSlots;                       // particle slots per contraction slice
   constexpr int RS = K + K / 16 + 1;
   extern __shared__ __align__(16) char smem[];
   c2<T>* A = reinterpret_cast<c2<T>*>(smem);
@@ -1166,12 +1169,21 @@ __global__ void __launch_bounds__(256) k_gather_contract(const c2<T>* fields, co
   const double invW = 1.0 / W[mock];
   // nbins lanes per particle, 64 / nbins particles per wave (the rest idle)
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int ppw = 64 / nbins;
+  // slots per slice: a multiple of the particles per pass and of 8 (fewer
+  // particles per wave where no multiple fits the slice)
+  int ppw = 64 / nbins;
+  if (ppw * nw > K) ppw = K / nw;
+  int kcount = 0;
+  for (;;) {
+    const int pp = nw * ppw;
+    kcount = pp * (K / pp);
+    while (kcount > 0 && kcount % 8) kcount -= pp;
+    if (kcount > 0 || ppw == 1) break;
+    --ppw;
+  }
   const int pw = lane / nbins, b = lane - pw * nbins;
   const bool lane_ok = pw < ppw;
   const int ppp = nw * ppw;                             // particles per pass
-  int kcount = ppp * (K / ppp);                         // slots per slice: even, and a multiple of 8
-  while (kcount % 8) kcount -= ppp;
   const c2<T>* fm = fields + mock * n3 * nbins;
   const double fw = (double)n3 / W[mock];
   const T dl = (SRC && lane_ok) ? lam_d[mock * nbins + b] : (T)0;
@@ -3549,7 +3561,7 @@ hipError_t launch_deposit_tiled(int prec, int tside, const float* pos, const flo
 
 template <typename T, bool MF, bool SPLIT, bool QUAD, bool SRC>
 hipError_t gather_contract_v(const GatherArgs& a, hipStream_t st) {
-  constexpr int K = 256;
+  constexpr int K = kGatherSlots;
   const size_t rs = K + K / 16 + 1;
   size_t lds = (size_t)a.nbins * rs * sizeof(CT<T>) + K * sizeof(T);
   if (SRC) lds += K * sizeof(int) + (size_t)a.nbins * sizeof(T);
