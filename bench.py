@@ -110,6 +110,27 @@ def pmc_probe(wl, precision, lmax=None):
     log("backward done")
 
 
+def copy_probe(nbytes=2684354560, reps=5):
+    """Best time of a plain device-to-device copy of nbytes (the fields of one (l, m) at
+    256^3, 20 bins, float32): the streaming bandwidth a pass that reads and writes every
+    byte once can reach on this card."""
+    import torch
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    best = None
+    for _ in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    print(json.dumps({"copy_bytes": nbytes, "best_ms": best, "tb_per_s": 2.0 * nbytes / best / 1e9}))
+
+
 def _csv_rows(root, suffix):
     import csv
     import glob
@@ -386,6 +407,7 @@ def main():
                     help="secondary measurements after the headline (comma list of %s, all, or none)" % ", ".join(FORMS))
     ap.add_argument("--pmc-probe", action="store_true", help="one step plus a 1 GiB copy, for counter runs")
     ap.add_argument("--probe-lmax", type=int, default=None, help="multipole order of the --pmc-probe plan")
+    ap.add_argument("--copy-probe", action="store_true", help="time a plain 2.5 GiB device copy (streaming ceiling)")
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print the per-launch traffic summary of two rocprofv3 --pmc runs of --pmc-probe")
     ap.add_argument("--stats-summarize", metavar="DIR", help="print a table of a rocprofv3 --stats run")
@@ -396,6 +418,9 @@ def main():
         return
     if args.pmc_table:
         pmc_table(args.pmc_table)
+        return
+    if args.copy_probe:
+        copy_probe()
         return
     if args.pmc_summarize:
         from mockgen import WORKLOADS

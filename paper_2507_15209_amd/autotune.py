@@ -127,7 +127,7 @@ def _descend(plan, knob: str, fn, reps: int, log) -> float:
 
 
 def autotune(plan, delta, pos=None, w=None, np_off=None, dzeta=None, backward: bool = True,
-             reps: int = 2, cache: str | None = None, force: bool = False, log=None) -> dict:
+             reps: int = 2, cache: str | None = None, force: bool = False, log=None, rounds: int = 2) -> dict:
     """Tune ``plan`` on representative inputs and return its knobs.
 
     delta: a density contrast of the plan's shape (the forward's input).
@@ -136,7 +136,10 @@ def autotune(plan, delta, pos=None, w=None, np_off=None, dzeta=None, backward: b
     if None).  With ``backward`` the timed call is the one-sweep value and
     gradient (the path the benchmark times), else the forward alone.  With a
     cache entry for this configuration and ``force`` False the cached knobs
-    are applied and nothing is timed.
+    are applied and nothing is timed.  The path's knobs are descended one at a
+    time, the one with the largest effect first, over ``rounds`` passes (the
+    knobs interact: the best persistent-grid size depends on the waves per
+    workgroup).
     """
     if not force and load_tuning(plan, cache):
         return plan.tuning()
@@ -159,16 +162,18 @@ def autotune(plan, delta, pos=None, w=None, np_off=None, dzeta=None, backward: b
             else:
                 plan.zeta(delta, *cat)
 
-        knobs = ["fft_x_plan", "zpass_wgs"]
+        knobs = []
         if do_bwd and plan.summation == "nodal":
             # item_group is left at its default (as many items per launch as fit 1 GiB of fields),
             # the best or within noise of it wherever it was measured
             knobs.append("fused_waves")
+        knobs += ["fft_x_plan", "zpass_wgs"]
         if plan.summation != "nodal":
             knobs.append("contract_wgs")
         if do_bwd and plan.summation == "gamma" and getattr(plan, "basis", "b3") == "b3":
             knobs.append("gamma_adjoint")
-        for k in knobs:
-            times[k] = _descend(plan, k, path, reps, log)
+        for _ in range(max(1, rounds)):
+            for k in knobs:
+                times[k] = _descend(plan, k, path, reps, log)
     save_tuning(plan, times, cache)
     return plan.tuning()
