@@ -1104,9 +1104,8 @@ __device__ __forceinline__ c2<T> gather_record(const c2<T>* fm, int cell, const 
 #pragma unroll
   for (int az = 0; az < 4; ++az) oz[az] = (long long)(zin ? cz - 1 + az : wrapi(cz - 1 + az, n)) * nbins + b;
   c2<T> acc = mk<T>(0, 0);
-  // one x row of 16 taps per iteration keeps 16 loads in flight without
-  // holding all 64 in registers
-#pragma unroll 1
+  // all four x rows unrolled: the 64 loads of a record are in flight together
+#pragma unroll
   for (int ax = 0; ax < 4; ++ax) {
     const c2<T>* px = fm + wrapi(cx - 1 + ax, n) * rowx;
     c2<T> sy = mk<T>(0, 0);
