@@ -218,9 +218,13 @@ int mp3_zeta(mp3_plan_t plan, const void* delta, const float* pos, const float* 
 
 /* Gradient of J = sum_{j,l,b1,b2} dzeta[j][l][b1][b2] zeta_l^{(j)}[b1][b2] for
  * every form; the paper gives no gradient, this is the chain rule of mp3_zeta
- * and mp3_deposit.  The grid-Gamma form's adjoint tile holds 7^3 coefficients
- * of every bin twice in LDS: float32 up to 20 bins, float64 up to 9 bins
- * (MP3_EUNSUPPORTED beyond).
+ * and mp3_deposit.  The grid-Gamma form's adjoint takes the bins in chunks
+ * that fit the LDS of its shift stencil.
+ * The nodal and particle forms work in the eigenbasis of each symmetrised
+ * cotangent (dzeta_l + dzeta_l^T) / 2 = V diag(d) V^T, decomposed per (l,
+ * mock) on the device in float64: their fields come from the radial window
+ * rotated by V, so the adjoint sources are diagonal in the bins; the
+ * gradient is the same to rounding.
  * The fields are recomputed per (l, m); nothing is kept from mp3_zeta.
  *   ddelta = dJ/ddelta                                          (device real [batch][N^3])
  *            For the particle form this is the dependence through the
@@ -254,9 +258,13 @@ int mp3_zeta_backward(mp3_plan_t plan, const void* delta, const double* dzeta,
  * both the gather contraction and the adjoint sources.  Grid-Gamma form:
  * the adjoint's node values of each (l, m) are also contracted for zeta.
  * BF16-split plans and nodal plans above 32 bins run mp3_zeta and then
- * mp3_zeta_backward.  The results agree with the two separate calls to
- * rounding order (the nodal z transforms use another radix plan, the
- * grid-Gamma contraction visits the nodes in another order). */
+ * mp3_zeta_backward.  The nodal and particle forms contract zeta over the
+ * fields of the cotangent's eigenbasis (see mp3_zeta_backward) and rotate it
+ * back, zeta = V zetabar V^T (exactly symmetric); the particle form then
+ * subtracts its volume means.  The results agree with the two separate calls
+ * to rounding (per multipole: an entry's rounding follows the largest entry
+ * of its multipole; the grid-Gamma contraction visits the nodes in another
+ * order). */
 int mp3_zeta_value_and_grad(mp3_plan_t plan, const void* delta, const double* dzeta,
                             double* zeta, void* ddelta, const float* pos, const float* w,
                             const int64_t* np_off, void* dw, void* workspace,
