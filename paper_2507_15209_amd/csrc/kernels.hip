@@ -1878,11 +1878,15 @@ __global__ void __launch_bounds__(256) k_rotate_zeta(double* zeta, const double*
 }
 
 // ---------------------------------------------------------------------------
-// last adjoint pass: y-transform of every adjoint source c_b, times the window,
-// summed over bins and accumulated into G(q) (one read-modify-write per (l, m))
+// last adjoint pass: y-transform of every adjoint source c_b, summed over the
+// bins with the radial window, times the angular factor (common to the bins),
+// accumulated into G(q) (one read-modify-write per (l, m))
 // ---------------------------------------------------------------------------
+// float32: four waves per SIMD (128 registers; the angular factors wait in
+// LDS, so the bin loop holds the bin sum, the column and the window values)
 template <int N, typename T>
-__global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_adjoint_y(const c2<T>* fields, c2<T>* G,
+__global__ void __launch_bounds__((strided_threads<N, T, VB>())) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
+k_adjoint_y(const c2<T>* fields, c2<T>* G,
                                                                           const T* jtab, int jmocks, int nq2, int nbins,
                                                                           int nbp, const ItemRec* items, int item0,
                                                                           int nitems, int batch, double scale,
@@ -1894,6 +1898,10 @@ __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_adjoint_y(con
   constexpr long long N3 = (long long)N * N * N;
   __shared__ c2<T> lds[GT * N * ZC];
   __shared__ c2<T> tws[N];
+  // each thread's angular factors, parked in LDS while the bins are summed
+  // (registers hold the bin sum only): [RMAX][threads]
+  extern __shared__ __align__(16) char dyn[];
+  c2<T>* facs = reinterpret_cast<c2<T>*>(dyn);
   stage_twiddles<N, T>(tw, tws);
   __syncthreads();
   const int tid = threadIdx.x;
@@ -1906,16 +1914,26 @@ __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_adjoint_y(con
   const int qx = active ? tile / chunks : 0;
   const int qz = (active ? tile % chunks : 0) * ZC + cc;
   const long long mock = blockIdx.y;
-  c2<T> fac[RMAX], acc[RMAX];
+  c2<T>* dst = G + mock * N3 + (long long)qx * N * N + qz;
   int q2[RMAX];
 #pragma unroll
-  for (int e = 0; e < RMAX; ++e) acc[e] = mk<T>(0, 0);
-  // every item of the group adds into the same accumulator: one read-modify-write of G
+  for (int e = 0; e < RMAX; ++e) {
+    const int qxs = sfreq(qx, N), qys = sfreq(F::out_index(j, e), N), qzs = sfreq(qz, N);
+    q2[e] = qxs * qxs + qys * qys + qzs * qzs;
+  }
   for (int gi = 0; gi < nitems; ++gi) {
     const ItemRec& it = items[item0 + gi];
+    // one element at a time: the float64 recurrences of the elements do not
+    // run side by side (registers)
+#pragma unroll 1
+    for (int e = 0; e < RMAX; ++e) {
+      int q2e;
+      facs[e * blockDim.x + tid] =
+          window_angular<T>(qx, F::out_index(j, e), qz, N, it.l, it.m, it.norm, scale * it.wm, it.yr, q2e, phi);
+    }
+    c2<T> acc[RMAX];
 #pragma unroll
-    for (int e = 0; e < RMAX; ++e)
-      fac[e] = window_angular<T>(qx, F::out_index(j, e), qz, N, it.l, it.m, it.norm, scale * it.wm, it.yr, q2[e], phi);
+    for (int e = 0; e < RMAX; ++e) acc[e] = mk<T>(0, 0);
     const T* jl = jtab + ((long long)it.l * jmocks + mock % jmocks) * nq2 * nbp;
     const c2<T>* src = fields + ((long long)gi * batch + mock) * nbins * N3 + (long long)qx * N * N + qz;
     // next bin's column, one bin ahead
@@ -1943,17 +1961,20 @@ __global__ void __launch_bounds__((strided_threads<N, T, VB>())) k_adjoint_y(con
           asm volatile("" : "+v"(jj));
           fft_column<N, +1, T, false, VB>(v, lds + g * N * ZC + cc, ZC, jj, tws, active);
 #pragma unroll
-          for (int e = 0; e < RMAX; ++e) acc[e] = cadd<T>(acc[e], cmul<T>(v[e], cscale<T>(fac[e], jq[e][k])));
+          for (int e = 0; e < RMAX; ++e) {
+            acc[e].x += jq[e][k] * v[e].x;
+            acc[e].y += jq[e][k] * v[e].y;
+          }
         }
       }
     }
-  }
-  if (active) {
-    c2<T>* dst = G + mock * N3 + (long long)qx * N * N + qz;
+    // the window's angular factor is common to every bin: applied once, into G
+    if (active) {
 #pragma unroll
-    for (int e = 0; e < RMAX; ++e) {
-      c2<T>* p = dst + F::out_index(j, e) * N;
-      nt_store(p, cadd<T>(nt_load(p), acc[e]));
+      for (int e = 0; e < RMAX; ++e) {
+        c2<T>* p = dst + F::out_index(j, e) * N;
+        nt_store(p, cadd<T>(nt_load(p), cmul<T>(acc[e], facs[e * blockDim.x + tid])));
+      }
     }
   }
 }
@@ -3076,7 +3097,11 @@ hipError_t adjoint_y_t(const FilterArgs& a, hipStream_t st) {
   constexpr int G = tiles_per_wg<N, T, VB>();
   constexpr int threads = Fft<N, VB>::TPC * ZC * G;
   const dim3 gs((N * (N / ZC) + G - 1) / G, a.batch);
-  k_adjoint_y<N, T><<<gs, threads, 0, st>>>(static_cast<const CT<T>*>(a.src), static_cast<CT<T>*>(a.dst),
+  const size_t dyn = (size_t)threads * Fft<N, VB>::RMAX * sizeof(CT<T>);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_adjoint_y<N, T>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+  if (e != hipSuccess) return e;
+  k_adjoint_y<N, T><<<gs, threads, dyn, st>>>(static_cast<const CT<T>*>(a.src), static_cast<CT<T>*>(a.dst),
                                            static_cast<const T*>(a.jtab), a.jmocks, a.nq2, a.nbins, a.nbp, a.items,
                                            a.item0, a.nitems, a.batch, a.scale, static_cast<const CT<T>*>(a.tw),
                                            static_cast<const T*>(a.phi));
