@@ -2053,6 +2053,9 @@ constexpr int SCB = (SCT + 3) * (SCT + 3) * (SCT + 3);   // first-tap buckets
 // float64 4
 template <typename T> constexpr int scatter_bc() { return sizeof(T) == 4 ? 8 : 4; }
 inline int scatter_bc_f32(int nbins) { return (nbins + 9) / 10 < (nbins + 7) / 8 ? 10 : 8; }
+// float64 beyond 8 bins: 10 bins per workgroup (two workgroups per CU by LDS)
+// instead of 4, so that 20 bins take two passes over the candidates, not five
+inline int scatter_bc_f64(int nbins) { return nbins > 8 ? 10 : 4; }
 template <typename T> constexpr int scatter_q() { return sizeof(T) == 4 ? 256 : 256; }
 
 template <typename T, int BC>
@@ -3773,7 +3776,10 @@ hipError_t scatter_source_t(const int* tcell, const void* twt, const int* toff, 
 
 hipError_t launch_scatter_source(int prec, const int* tcell, const void* twt, const int* toff, const void* src, int n,
                                  int nbins, int batch, void* out, hipStream_t st) {
-  if (prec) return scatter_source_t<double, scatter_bc<double>()>(tcell, twt, toff, src, n, nbins, batch, out, st);
+  if (prec) {
+    if (scatter_bc_f64(nbins) == 10) return scatter_source_t<double, 10>(tcell, twt, toff, src, n, nbins, batch, out, st);
+    return scatter_source_t<double, scatter_bc<double>()>(tcell, twt, toff, src, n, nbins, batch, out, st);
+  }
   if (scatter_bc_f32(nbins) == 10) return scatter_source_t<float, 10>(tcell, twt, toff, src, n, nbins, batch, out, st);
   return scatter_source_t<float, 8>(tcell, twt, toff, src, n, nbins, batch, out, st);
 }
