@@ -2050,7 +2050,7 @@ constexpr int SCT = 8;                    // owner tile side (nodes)
 constexpr int SCB = (SCT + 3) * (SCT + 3) * (SCT + 3);   // first-tap buckets
 // bins per owner workgroup: float32 8, or 10 where that saves a pass over the
 // candidates (17..20 bins: two passes instead of three, 23 % faster at 512^3);
-// float64 4
+// float64 4 up to 8 bins, 10 beyond (scatter_bc_f64)
 template <typename T> constexpr int scatter_bc() { return sizeof(T) == 4 ? 8 : 4; }
 inline int scatter_bc_f32(int nbins) { return (nbins + 9) / 10 < (nbins + 7) / 8 ? 10 : 8; }
 // float64 beyond 8 bins: 10 bins per workgroup (two workgroups per CU by LDS)
